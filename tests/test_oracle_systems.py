@@ -238,3 +238,17 @@ def test_error_paths(orc):
     with pytest.raises(orc.OracleError) as e:
         orc.respa(x, np.zeros_like(x), box, n_iter=7, k=2)
     assert e.value.code == orc.ERR_NOT_MULTIPLE_OF_K
+
+
+def test_cutoff_is_inclusive(orc):
+    """Pairs and triplets at exactly rc interact: the paper's rule is 'less than or equal to
+    the cutoff' for pairs and for all three triplet edges (Sec. 4.2.2, Fig. 2 caption).
+    2.5 and its square are exact in binary, so the test is exact."""
+    box = np.full(3, 10.0)
+    x = np.array([[1.0, 1.0, 1.0], [3.5, 1.0, 1.0], [2.25, 2.0, 1.0]])
+    assert orc.pair_forces(x, box, rc=2.5).count == 3
+    assert orc.triplet_forces(x, box, rc=2.5).count == 1
+    x2 = x.copy()
+    x2[1, 0] = np.nextafter(3.5, 4.0)
+    assert orc.pair_forces(x2, box, rc=2.5).count == 2
+    assert orc.triplet_forces(x2, box, rc=2.5).count == 0
