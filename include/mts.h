@@ -1,0 +1,175 @@
+/*
+ * mts.h -- C ABI of the MI355X (gfx950) library for two- plus three-body molecular
+ * dynamics with r-RESPA multiple time stepping.
+ *
+ * The method (Martin et al., "The Multiple Time-Stepping Method for 3-Body
+ * Interactions in High Performance Molecular Dynamics Simulations"):
+ *   - pair force F2 = -grad of the Lennard-Jones 12-6 potential (Sec. 2.1), cut off
+ *     at rc_pair, evaluated every step;
+ *   - triplet force F3 = -grad of the Axilrod-Teller-Muto potential (Sec. 2.1) over
+ *     every triplet whose three pairwise distances are all <= rc_triplet
+ *     (Sec. 4.1 and 4.2.2), found through linked cells (Sec. 2.2, 4.1), evaluated
+ *     once per outer step;
+ *   - r-RESPA as the paper implements it (Sec. 4.1, Algorithm 2): F2 every step,
+ *     F3 kicks of dt*s/(2m) every s-th step, s = k here.
+ *
+ * Conventions shared by every call
+ *   - Units: reduced Lennard-Jones units as in the paper's appendix table.
+ *   - Positions, velocities and forces are FP64 device arrays [N][3], row-major
+ *     (x, y, z of particle 0, then particle 1, ...), N = sum of n_particles[].
+ *     Systems are concatenated in order.  Forces come back in this same order.
+ *   - Boxes are orthorhombic and periodic.  Every edge must exceed twice the larger
+ *     cutoff (so that each pair has at most one interacting image).
+ *   - Cutoffs are inclusive: d^2 <= rc^2, with d the minimum-image displacement.
+ *   - Pointers marked "dev" are device pointers (e.g. torch CUDA tensors on ROCm);
+ *     "host" pointers are ordinary CPU memory.  The caller owns every pointer it
+ *     passes and keeps it alive until the work is done; the library never frees
+ *     caller memory.  The library owns cells, work buffers and force caches.
+ *   - Asynchrony: calls validate on the host, enqueue work on the stream given at
+ *     init and return without waiting, unless documented as synchronising.  Device
+ *     side problems (capacity overflow, non-finite values) raise flags that the
+ *     next mts_sync() reports.  A handle must not be used from two threads at once.
+ *   - Return value: MTS_OK or a negative mts_status; mts_last_error() gives text.
+ */
+#ifndef MTS_H
+#define MTS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mts_system mts_system; /* opaque, library-owned */
+
+typedef enum {
+    MTS_OK = 0,
+    MTS_ERR_INVALID_ARG = -1,       /* bad pointer, size or parameter */
+    MTS_ERR_BOX_TOO_SMALL = -2,     /* a box edge is not above 2 * max(rc_pair, rc_triplet) */
+    MTS_ERR_NOT_MULTIPLE_OF_K = -3, /* n_iter is not a multiple of k (Sec. 4.1) */
+    MTS_ERR_CAPACITY = -4,          /* a cell neighbourhood or neighbour list overflowed */
+    MTS_ERR_NONFINITE = -5,         /* a force or energy became NaN or infinite */
+    MTS_ERR_HIP = -6,               /* a HIP runtime call failed */
+    MTS_ERR_OOM = -7,               /* device allocation failed */
+    MTS_ERR_UNSUPPORTED = -8        /* valid input this build does not handle */
+} mts_status;
+
+typedef enum {
+    MTS_FP64 = 0, /* all force arithmetic in FP64 */
+    MTS_FP32 = 1  /* LJ and ATM arithmetic in FP32; cutoff geometry, accumulation,
+                     integration and energy reductions in FP64 */
+} mts_precision;
+
+/* Interaction and integration parameters (Sec. 2.1; appendix table). */
+typedef struct {
+    double epsilon;          /* LJ well depth epsilon_LJ */
+    double sigma;            /* LJ length sigma_LJ */
+    double rc_pair;          /* pair cutoff */
+    double nu;               /* ATM coefficient nu_ATM */
+    double rc_triplet;       /* three-body cutoff: all three edges <= rc_triplet */
+    double mass;             /* particle mass m (uniform) */
+    double dt;               /* inner time step delta t */
+    int32_t k;               /* r-RESPA step-size factor s >= 1 (Sec. 4.1) */
+    int32_t precision;       /* mts_precision */
+    int32_t lj_energy_shift; /* 1: report U2 shifted by -U(rc_pair) per pair (forces unchanged) */
+    int32_t reserved;        /* must be 0 */
+} mts_params;
+
+/* Energy record per system: kinetic K, LJ energy U2, ATM energy U3, pair virial W2,
+ * triplet virial W3 (W = sum over interactions of x . F, so that the pressure is
+ * (2K + W2 + W3) / (3V)). */
+enum { MTS_NE = 5 };
+
+/* Creates a handle for n_systems independent periodic systems.
+ *   params       host, read during the call.
+ *   n_particles  host [n_systems], each >= 0.
+ *   box          host [n_systems][3], edge lengths.
+ *   stream       hipStream_t to enqueue on (NULL = default stream).
+ *   out          host, receives the handle; release it with mts_destroy_system.
+ * Fails with MTS_ERR_BOX_TOO_SMALL, MTS_ERR_INVALID_ARG or MTS_ERR_OOM; on failure
+ * *out is NULL. */
+mts_status mts_init_system(const mts_params *params, int32_t n_systems, const int64_t *n_particles,
+                           const double *box, void *stream, mts_system **out);
+
+/* Waits for queued work, then frees every library-owned buffer.  NULL is ignored. */
+void mts_destroy_system(mts_system *sys);
+
+/* Assigns particles to linked cells (Sec. 2.2, 4.1): wraps positions into the box,
+ * computes each cell index and sorts particles by cell with a stable counting sort
+ * (equal cells keep ascending particle order).  x is dev [N][3]; it is read, not
+ * modified.  The force calls below bin by themselves; this call exists for the cell
+ * inspection exports. */
+mts_status mts_build_cells(mts_system *sys, const double *x);
+
+/* F2(x): Lennard-Jones forces (Sec. 2.1; Algorithm 2, "calculate F2b").
+ *   x   dev [N][3] positions (need not be wrapped).
+ *   f2  dev [N][3] output, overwritten.
+ *   ew  dev [n_systems][2] output {U2, W2}, or NULL. */
+mts_status mts_compute_pair_forces(mts_system *sys, const double *x, double *f2, double *ew);
+
+/* F3(x): Axilrod-Teller-Muto forces over every triplet with all three edges
+ * <= rc_triplet (Sec. 2.1, 4.1; Algorithm 2, "calculate F3b").  Newton's third law is
+ * applied across each triplet: every triplet is evaluated once.
+ *   x   dev [N][3] positions.
+ *   f3  dev [N][3] output, overwritten.
+ *   ew  dev [n_systems][2] output {U3, W3}, or NULL. */
+mts_status mts_compute_triplet_forces(mts_system *sys, const double *x, double *f3, double *ew);
+
+/* Runs n_iter inner steps of r-RESPA (Sec. 4.1, Algorithm 2) in place.
+ *   x       dev [N][3] positions x^0 in, x^n out (wrapped into the box after each drift).
+ *   v       dev [N][3] velocities v^0 in, v^n out.
+ *   n_iter  number of inner steps, a multiple of k (else MTS_ERR_NOT_MULTIPLE_OF_K).
+ *   e_full  dev [n_iter/k + 1][n_systems][MTS_NE] energies at x^0 and after every full
+ *           step (only full steps have synchronised velocities), or NULL.
+ * Both forces are recomputed at x^0 on entry, as Algorithm 2 does, so two calls of
+ * n and m steps equal one call of n + m steps. */
+mts_status mts_respa_step(mts_system *sys, double *x, double *v, int64_t n_iter, double *e_full);
+
+/* Waits for the stream and reports device flags raised since the last mts_sync:
+ * MTS_ERR_CAPACITY (the affected forces are wrong; capacities are enlarged for the
+ * next call) or MTS_ERR_NONFINITE.  Clears the flags. */
+mts_status mts_sync(mts_system *sys);
+
+/* Text of the last error on this handle ("" if none); valid until the next call. */
+const char *mts_last_error(const mts_system *sys);
+
+/* Name of a status code. */
+const char *mts_status_string(int32_t status);
+
+/* ---- inspection exports (used by the parity tests) ---- */
+
+/* Cell grid of one system: n_cells[0..2] along x, y, z (host out). */
+mts_status mts_get_grid(const mts_system *sys, int32_t system, int32_t n_cells[3]);
+
+/* After mts_build_cells: per-particle linear cell index (c_z * n_y + c_y) * n_x + c_x
+ * within its own system's grid.  cell is dev [N] int32, in input particle order. */
+mts_status mts_get_cell_index(mts_system *sys, int32_t *cell);
+
+/* Number of interacting triplets at x, summed over systems.  Synchronising; count is
+ * a host pointer. */
+mts_status mts_count_triplets(mts_system *sys, const double *x, int64_t *count);
+
+/* Lists the interacting triplets at x as particle-index triples (i<j<k, global
+ * indices), in no particular order.  ijk is dev [cap][3] int32; *n (host) receives
+ * the total count, which may exceed cap (then only cap rows are written).
+ * Synchronising. */
+mts_status mts_list_triplets(mts_system *sys, const double *x, int32_t *ijk, int64_t cap,
+                             int64_t *n);
+
+/* ---- profiling hook ---- */
+
+/* Turns per-launch timing of the two force kernels on or off (synchronising).  While on,
+ * every launch of the triplet-force kernel and of the pair-force kernel is bracketed by
+ * HIP events recorded on the handle's stream. */
+mts_status mts_enable_kernel_timing(mts_system *sys, int32_t enable);
+
+/* Synchronising.  For kernel class 0 (triplet forces) and 1 (pair forces): launches[c]
+ * receives the number of timed launches since the last call and ms[c] their summed
+ * duration in milliseconds (host arrays of 2).  Resets the counters. */
+mts_status mts_kernel_times(mts_system *sys, int64_t launches[2], double ms[2]);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MTS_H */

@@ -1,0 +1,169 @@
+// Internal declarations of the MI355X r-RESPA library: device system descriptors,
+// canonical periodic geometry, stencil tables and the kernel launchers.
+//
+// Every source of the library is compiled with -ffp-contract=off: the cutoff
+// geometry (wrap, minimum image, squared distance) must round exactly as written, so
+// that cell assignment and the interacting pair/triplet sets are reproducible
+// bit for bit.  Force arithmetic that wants fused multiply-adds spells them out
+// with fma()/fmaf().
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mts {
+
+constexpr int kWave = 64;        // CDNA wavefront width
+constexpr int kNumHalf = 14;     // self cell + 13 forward cells of the half stencil
+constexpr int kNumFull = 27;     // full 3x3x3 stencil
+constexpr int kNE = 5;           // K, U2, U3, W2, W3
+
+// Per-system description, read by every kernel.
+struct SysDesc {
+    double L[3];    // box edges
+    double q[3];    // n_cells / L, the cell-coordinate scale
+    int nc[3];      // cells per edge (>= 2); cell edge L/nc exceeds the largest cutoff
+    int cell0;      // first global cell id of this system
+    int ncell;      // nc[0] * nc[1] * nc[2]
+    int pad;
+    int64_t p0;     // first particle (global index); particles are concatenated by system
+    int64_t n;      // particles in this system
+};
+
+// Device error flags (bit mask in a single int).
+enum : int {
+    kFlagStageOverflow = 1,  // a triplet neighbourhood did not fit the LDS tile
+    kFlagListOverflow = 2,   // an anchor had more forward neighbours than the list holds
+    kFlagNonFinite = 4,      // a force or energy was NaN/Inf
+    kFlagTripletListFull = 8 // debug triplet listing exceeded its buffer (not an error)
+};
+
+// ---------------------------------------------------------------- geometry
+// Wrap into [0, L]: w = x - L * floor(x / L).  (w may equal L after rounding; the cell
+// coordinate is clamped, so such a particle sits on the top face of the last cell.)
+__device__ __forceinline__ double wrap1(double x, double L) { return x - L * floor(x / L); }
+
+// Cell coordinate min(nc - 1, max(0, floor(w * q))); NaN maps to 0 (the bin kernel flags
+// non-finite positions separately).
+__device__ __forceinline__ int cell_coord(double w, double q, int nc) {
+    const double t = floor(w * q);
+    if (!(t >= 0.0)) return 0;
+    return t < (double)nc ? (int)t : nc - 1;
+}
+
+// Cell coordinate c + o on a periodic grid of nc cells, and the image shift (in box
+// edges: -1, 0, +1) that the particles of that cell carry when seen from cell c.
+// Requires |o| <= 1 and nc >= 2.
+__device__ __forceinline__ int wrap_cell(int c, int o, int nc, int &shift) {
+    int t = c + o;
+    shift = 0;
+    if (t < 0) { t += nc; shift = -1; }
+    else if (t >= nc) { t -= nc; shift = 1; }
+    return t;
+}
+
+// Minimum-image displacement component from p to q.  The caller supplies the image
+// shift S (0 or +-L) of q relative to p; the rounding is fl(fl(x_q - x_p) + S), which
+// equals fl(d - L*rint(d/L)) for every pair within a cutoff below L/2.
+__device__ __forceinline__ double disp1(double xp, double xq, double S) { return (xq - xp) + S; }
+
+__device__ __forceinline__ double norm2(double dx, double dy, double dz) {
+    return (dx * dx + dy * dy) + dz * dz;
+}
+
+// Offsets of the 3x3x3 stencil, full (index 13 is the centre) and forward half (index 0
+// is the centre).  "Forward" is lexicographic in (z, y, x): oz > 0, or oz == 0 and
+// oy > 0, or oz == oy == 0 and ox > 0.
+__device__ __forceinline__ void full_offset(int o, int &ox, int &oy, int &oz) {
+    ox = o % 3 - 1;
+    oy = (o / 3) % 3 - 1;
+    oz = o / 9 - 1;
+}
+
+__device__ __forceinline__ void half_offset(int o, int &ox, int &oy, int &oz) {
+    // o = 0 is (0,0,0); o = 1..13 are full-stencil entries 14..26 (all forward).
+    int f = o == 0 ? 13 : 13 + o;
+    full_offset(f, ox, oy, oz);
+}
+
+// ---------------------------------------------------------------- launchers
+// All launchers enqueue on `st` and return hipGetLastError().
+
+// Binning (counting sort by cell).
+hipError_t launch_bin_count(hipStream_t st, int64_t n, const double *x, const SysDesc *sd,
+                            const int *sys_of, int *cell_of, int *rank, int *count, int *flags);
+hipError_t launch_scan(hipStream_t st, int ncell, const int *count, int *start, int64_t n_total);
+hipError_t launch_bin_scatter(hipStream_t st, int64_t n, const int *cell_of, const int *rank,
+                              const int *start, int *perm);
+hipError_t launch_cell_sort(hipStream_t st, int ncell, const int *start, int *perm, int *count);
+hipError_t launch_gather_sorted(hipStream_t st, int64_t n, const double *x, const int *perm,
+                                const SysDesc *sd, const int *sys_of, double *xs);
+hipError_t launch_local_cell_index(hipStream_t st, int64_t n, const int *cell_of,
+                                   const SysDesc *sd, const int *sys_of, int *out);
+
+// Pair forces: full stencil, each particle sums its own neighbours.
+struct PairArgs {
+    int64_t n;
+    const double *xs;       // sorted wrapped positions, SoA [3][n]
+    const int *perm;        // sorted -> input index
+    const int *start;       // cell starts [ncell_total + 1]
+    const SysDesc *sd;
+    const int *sys_of;      // per particle (same in input and sorted order)
+    double *f;              // out [n][3], input order
+    double *pe;             // out [n][2] per-particle {U2/2-sums, W2/2-sums}, sorted order
+    double eps, sigma2, rc2, ushift;
+    int *flags;
+};
+hipError_t launch_pair(hipStream_t st, const PairArgs &a, bool fp32, int lanes_per_particle);
+
+// Triplet forces: one workgroup per base cell, forward half stencil in LDS.
+struct TripletArgs {
+    int ncell;              // total cells (grid size)
+    const double *xs;
+    const int *start;
+    const SysDesc *sd;
+    const int *sys_of_cell; // [ncell]
+    const int *perm;        // for triplet listing
+    double *pf;             // out partial slots [kNumHalf][3][n]
+    double *ce;             // out per-cell {U3, W3} [ncell][2]
+    long long *cc;          // out per-cell triplet counts [ncell]
+    int64_t n;
+    double nu, rc2;
+    int stage_cap, list_cap;
+    int *flags;
+    int *list_ijk;          // optional triplet listing [list_cap_rows][3]
+    unsigned long long *list_n;  // listing counter
+    long long list_rows;
+};
+hipError_t launch_triplet(hipStream_t st, const TripletArgs &a, bool fp32, bool listing);
+size_t triplet_lds_bytes(int stage_cap, int list_cap);
+hipError_t launch_triplet_gather(hipStream_t st, int64_t n, const double *pf, const int *perm,
+                                 double *f, int *flags);
+
+// Integrator pieces (input particle order, FP64).
+hipError_t launch_kick(hipStream_t st, int64_t n3, double *v, const double *f, double c);
+hipError_t launch_drift(hipStream_t st, int64_t n, double *x, const double *v, const double *f2,
+                        double dt, double cx, const SysDesc *sd, const int *sys_of);
+hipError_t launch_kick2(hipStream_t st, int64_t n3, double *v, const double *fa,
+                        const double *fb, double c);
+
+// Energy reductions: one workgroup per system, fixed summation order.
+struct ReduceArgs {
+    int nsys;
+    const SysDesc *sd;
+    const double *v;        // [n][3] or null (K = 0)
+    double half_mass;
+    const double *pe;       // per-particle pair energies [n][2] or null
+    const double *ce;       // per-cell triplet energies [ncell][2] or null
+    const long long *cc;    // per-cell triplet counts or null
+    double *out;            // [nsys][stride]
+    int stride;             // 5: {K,U2,U3,W2,W3}; 2: {U,W} from whichever source is non-null
+    long long *count_out;   // [nsys] triplet counts or null
+    int *flags;
+    const int *row;         // optional device row index: out += (*row) * nsys * stride
+};
+hipError_t launch_reduce(hipStream_t st, const ReduceArgs &a);
+hipError_t launch_bump_row(hipStream_t st, int *row);
+
+}  // namespace mts

@@ -1,0 +1,147 @@
+// r-RESPA update pieces (Sec. 4.1, Algorithm 2) and the FP64 energy reductions.
+//
+// The updates are elementwise FP64 streams over x, v and the force caches (HBM-bound).
+// Each keeps the exact expression order of Algorithm 2:
+//   kick:   v <- v + c * F                 (c = dt*s/(2m) for F3)
+//   drift:  x <- wrap(x + dt*v + dt^2/(2m) * F2(x^i))
+//   kick2:  v <- v + dt/(2m) * (F2(x^i) + F2(x^{i+1}))
+// Reductions sum in a fixed order (per-thread strided sums, then an LDS tree), one
+// workgroup per system, so energies are bitwise reproducible.
+#include "common.h"
+
+namespace mts {
+
+__global__ void __launch_bounds__(256) k_kick(int64_t n3, double *__restrict__ v,
+                                              const double *__restrict__ f, double c) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n3) v[q] = v[q] + c * f[q];
+}
+
+__global__ void __launch_bounds__(256) k_kick2(int64_t n3, double *__restrict__ v,
+                                               const double *__restrict__ fa,
+                                               const double *__restrict__ fb, double c) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n3) v[q] = v[q] + c * (fa[q] + fb[q]);
+}
+
+__global__ void __launch_bounds__(256) k_drift(int64_t n, double *__restrict__ x,
+                                               const double *__restrict__ v,
+                                               const double *__restrict__ f2, double dt, double cx,
+                                               const SysDesc *__restrict__ sd,
+                                               const int *__restrict__ sys_of) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const SysDesc &d = sd[sys_of[i]];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int64_t q = 3 * i + k;
+        x[q] = wrap1(x[q] + dt * v[q] + cx * f2[q], d.L[k]);
+    }
+}
+
+constexpr int kRed = 256;
+
+__device__ __forceinline__ double block_sum(double v, double *red) {
+    const int t = threadIdx.x;
+    red[t] = v;
+    __syncthreads();
+    for (int s = kRed / 2; s > 0; s >>= 1) {
+        if (t < s) red[t] += red[t + s];
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ void __launch_bounds__(kRed) k_reduce(ReduceArgs a) {
+    __shared__ double red[kRed];
+    const int s = blockIdx.x;
+    const int t = threadIdx.x;
+    const SysDesc &d = a.sd[s];
+    double kin = 0.0, u2 = 0.0, w2 = 0.0, u3 = 0.0, w3 = 0.0;
+    long long cnt = 0;
+    if (a.v) {
+        for (int64_t i = d.p0 + t; i < d.p0 + d.n; i += kRed) {
+            const double vx = a.v[3 * i], vy = a.v[3 * i + 1], vz = a.v[3 * i + 2];
+            kin += (vx * vx + vy * vy) + vz * vz;
+        }
+    }
+    if (a.pe) {
+        for (int64_t p = d.p0 + t; p < d.p0 + d.n; p += kRed) {
+            u2 += a.pe[2 * p];
+            w2 += a.pe[2 * p + 1];
+        }
+    }
+    if (a.ce) {
+        for (int c = d.cell0 + t; c < d.cell0 + d.ncell; c += kRed) {
+            u3 += a.ce[2 * c];
+            w3 += a.ce[2 * c + 1];
+            if (a.cc) cnt += a.cc[c];
+        }
+    }
+    kin = block_sum(kin, red) * a.half_mass;
+    u2 = block_sum(u2, red);
+    w2 = block_sum(w2, red);
+    u3 = block_sum(u3, red);
+    w3 = block_sum(w3, red);
+    __shared__ long long redc[kRed];
+    redc[t] = cnt;
+    __syncthreads();
+    for (int h = kRed / 2; h > 0; h >>= 1) {
+        if (t < h) redc[t] += redc[t + h];
+        __syncthreads();
+    }
+    if (t != 0) return;
+    double *out = a.out;
+    if (out) {
+        if (a.row) out += (int64_t)(*a.row) * a.nsys * a.stride;
+        out += (int64_t)s * a.stride;
+        if (a.stride == kNE) {
+            out[0] = kin;
+            out[1] = u2;
+            out[2] = u3;
+            out[3] = w2;
+            out[4] = w3;
+        } else {
+            out[0] = a.pe ? u2 : u3;
+            out[1] = a.pe ? w2 : w3;
+        }
+    }
+    if (a.count_out) a.count_out[s] = redc[0];
+    if (!isfinite(kin) || !isfinite(u2) || !isfinite(u3) || !isfinite(w2) || !isfinite(w3))
+        atomicOr(a.flags, kFlagNonFinite);
+}
+
+__global__ void k_bump_row(int *row) { *row += 1; }
+
+static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+hipError_t launch_kick(hipStream_t st, int64_t n3, double *v, const double *f, double c) {
+    if (n3 > 0) k_kick<<<blocks_for(n3, 256), 256, 0, st>>>(n3, v, f, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_kick2(hipStream_t st, int64_t n3, double *v, const double *fa,
+                        const double *fb, double c) {
+    if (n3 > 0) k_kick2<<<blocks_for(n3, 256), 256, 0, st>>>(n3, v, fa, fb, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_drift(hipStream_t st, int64_t n, double *x, const double *v, const double *f2,
+                        double dt, double cx, const SysDesc *sd, const int *sys_of) {
+    if (n > 0) k_drift<<<blocks_for(n, 256), 256, 0, st>>>(n, x, v, f2, dt, cx, sd, sys_of);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(hipStream_t st, const ReduceArgs &a) {
+    if (a.nsys > 0) k_reduce<<<a.nsys, kRed, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_bump_row(hipStream_t st, int *row) {
+    k_bump_row<<<1, 1, 0, st>>>(row);
+    return hipGetLastError();
+}
+
+}  // namespace mts

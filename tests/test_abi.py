@@ -1,0 +1,72 @@
+"""The C ABI library loads and exports every entry point include/mts.h declares; host-side
+parameter validation rejects bad input before any device work (no GPU needed)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "mts.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mts_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2507_11172_amd import mts
+    return mts.load_library()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_2507_11172_amd import mts
+    names = _declared()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(mts.EXPORTS)
+
+
+def test_status_strings(lib):
+    assert lib.mts_status_string(0) == b"MTS_OK"
+    assert lib.mts_status_string(-3) == b"MTS_ERR_NOT_MULTIPLE_OF_K"
+
+
+def _init(lib, **over):
+    from paper_2507_11172_amd import mts
+    kw = dict(epsilon=1.0, sigma=1.0, rc_pair=2.5, nu=0.073, rc_triplet=2.5, mass=1.0, dt=0.001,
+              k=10, precision=0, lj_energy_shift=1, reserved=0)
+    n = over.pop("n", [500])
+    box = over.pop("box", [[8.55, 8.55, 8.55]])
+    kw.update(over)
+    p = mts.mts_params(**kw)
+    nn = np.ascontiguousarray(np.asarray(n, dtype=np.int64))
+    bb = np.ascontiguousarray(np.asarray(box, dtype=np.float64))
+    h = C.c_void_p()
+    rc = lib.mts_init_system(C.byref(p), len(n), nn.ctypes.data_as(C.POINTER(C.c_int64)),
+                             bb.ctypes.data_as(C.POINTER(C.c_double)), None, C.byref(h))
+    return rc, h
+
+
+@pytest.mark.parametrize("bad,code", [
+    (dict(k=0), -1), (dict(dt=0.0), -1), (dict(mass=-1.0), -1), (dict(sigma=0.0), -1),
+    (dict(rc_pair=float("nan")), -1), (dict(precision=7), -1), (dict(reserved=1), -1),
+    (dict(epsilon=-1.0), -1), (dict(n=[-5]), -1),
+    (dict(box=[[4.9, 8.5, 8.5]]), -2), (dict(box=[[8.5, 8.5, 5.0]]), -2),
+    (dict(rc_triplet=4.3), -2),
+])
+def test_host_validation(lib, bad, code):
+    rc, h = _init(lib, **bad)
+    assert rc == code
+    assert not h.value
+
+
+def test_null_arguments(lib):
+    assert lib.mts_init_system(None, 1, None, None, None, None) == -1
+    assert lib.mts_sync(None) == -1
+    assert lib.mts_respa_step(None, None, None, 0, None) == -1
+    lib.mts_destroy_system(None)  # ignored

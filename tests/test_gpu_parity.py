@@ -1,0 +1,241 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Bars: bit-exact cell assignment and triplet set; FP64 forces within 1e-12 of the oracle
+(max |dF| over RMS |F|); FP32-arithmetic form within 1e-5 on forces and 1e-7 per particle
+on energy; r-RESPA trajectories within round-off amplification.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2507_11172_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "no GPU visible"
+    return torch
+
+
+def _system(w, **kw):
+    from paper_2507_11172_amd import mts
+    p = mts.Params(epsilon=w.epsilon, sigma=w.sigma, rc_pair=w.rc_pair, nu=w.nu,
+                   rc_triplet=w.rc_triplet, mass=w.mass, dt=w.dt, k=kw.pop("k", w.k),
+                   precision=kw.pop("precision", "fp64"), **kw)
+    return mts.System(p, w.n_particles.tolist(), w.box)
+
+
+def _dev(a):
+    torch = _torch()
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def rel_err(got, ref):
+    return np.abs(got - ref).max() / np.sqrt(np.mean(np.sum(ref * ref, axis=1)))
+
+
+def _small_box(n=150, length=6.2, seed=3):
+    """2 rc < L < 3 rc: two cells per edge, images must close triangles."""
+    rng = W.rng_for(seed)
+    x, box = W.fcc_subset(n, n / length ** 3, 0.05, rng)
+    v = W.maxwell_boltzmann(n, 0.7, rng)
+    return W.Workload("smallbox", x, v, box[None, :], np.array([n]), np.array([0.7]))
+
+
+def _jittered(n_cells=4, jitter=0.15, seed=17):
+    return W.fcc_workload("fcc256", n_cells, seed, jitter=jitter)
+
+
+CASES = {"fcc500": W.plain_fp64, "smallbox": _small_box, "fcc256": _jittered}
+
+
+@pytest.mark.parametrize("case", ["fcc500", "smallbox", "fcc256", "fcc32k"])
+def test_cell_index_bit_exact(case):
+    torch = _torch()
+    w = W.fp64_at_scale() if case == "fcc32k" else CASES[case]()
+    with _system(w) as s:
+        x = _dev(w.x + np.array([0.0, w.box[0, 1], -2 * w.box[0, 2]]))  # unwrapped input
+        s.build_cells(x)
+        out = torch.empty(w.n_total, dtype=torch.int32, device="cuda")
+        s.get_cell_index(out)
+        s.sync()
+        grid = s.get_grid(0)
+        ref = oracle.cell_index(x.cpu().numpy(), w.box[0], grid)
+        assert np.array_equal(out.cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("case", ["fcc500", "smallbox", "fcc256"])
+def test_triplet_set_bit_exact(case):
+    w = CASES[case]()
+    ref = oracle.triplet_list(w.x, w.box[0], rc=w.rc_triplet)
+    with _system(w) as s:
+        x = _dev(w.x)
+        assert s.count_triplets(x) == ref.shape[0]
+        got, total = s.list_triplets(x, ref.shape[0] + 16)
+        s.sync()
+    assert total == ref.shape[0]
+    g = got.cpu().numpy().astype(np.int64)
+    g = g[np.lexsort((g[:, 2], g[:, 1], g[:, 0]))]
+    assert np.array_equal(g, ref.astype(np.int64))
+
+
+@pytest.mark.parametrize("case", ["fcc500", "smallbox", "fcc256"])
+def test_fp64_forces_and_energies(case):
+    torch = _torch()
+    w = CASES[case]()
+    box = w.box[0]
+    r2 = oracle.pair_forces(w.x, box, rc=w.rc_pair)
+    r3 = oracle.triplet_forces(w.x, box, rc=w.rc_triplet)
+    with _system(w) as s:
+        x = _dev(w.x)
+        f2 = torch.empty_like(x)
+        f3 = torch.empty_like(x)
+        e2 = torch.zeros((1, 2), dtype=torch.float64, device="cuda")
+        e3 = torch.zeros((1, 2), dtype=torch.float64, device="cuda")
+        s.compute_pair_forces(x, f2, e2)
+        s.compute_triplet_forces(x, f3, e3)
+        s.sync()
+    assert rel_err(f2.cpu().numpy(), r2.f) <= 1e-12
+    assert rel_err(f3.cpu().numpy(), r3.f) <= 1e-12
+    e2 = e2.cpu().numpy()[0]
+    e3 = e3.cpu().numpy()[0]
+    assert e2[0] == pytest.approx(r2.energy, rel=1e-12)
+    assert e2[1] == pytest.approx(r2.virial, rel=1e-12)
+    assert e3[0] == pytest.approx(r3.energy, rel=1e-12)
+    assert e3[1] == pytest.approx(r3.virial, rel=1e-11)
+
+
+@pytest.mark.parametrize("case", ["fcc500", "fcc256"])
+def test_fp32_form_within_tolerance(case):
+    torch = _torch()
+    w = CASES[case]()
+    box = w.box[0]
+    n = w.n_total
+    r2 = oracle.pair_forces(w.x, box)
+    r3 = oracle.triplet_forces(w.x, box)
+    with _system(w, precision="fp32") as s:
+        x = _dev(w.x)
+        f2 = torch.empty_like(x)
+        f3 = torch.empty_like(x)
+        e2 = torch.zeros((1, 2), dtype=torch.float64, device="cuda")
+        e3 = torch.zeros((1, 2), dtype=torch.float64, device="cuda")
+        s.compute_pair_forces(x, f2, e2)
+        s.compute_triplet_forces(x, f3, e3)
+        assert s.count_triplets(x) == r3.count
+        s.sync()
+    err2 = rel_err(f2.cpu().numpy(), r2.f)
+    err3 = rel_err(f3.cpu().numpy(), r3.f)
+    de = abs(e2.cpu().numpy()[0, 0] + e3.cpu().numpy()[0, 0] - r2.energy - r3.energy) / n
+    print("fp32 %s: F2 %.2e  F3 %.2e  dE/N %.2e" % (case, err2, err3, de))
+    assert err2 <= 1e-5 and err3 <= 1e-5
+    assert de <= 1e-7
+
+
+def test_fp64_at_scale_32k():
+    """32,000 particles: exact triplet count from the oracle's brute force; forces on a
+    seeded sample of 300 particles from the oracle's exact subset mode."""
+    torch = _torch()
+    w = W.fp64_at_scale()
+    box = w.box[0]
+    idx = np.sort(W.rng_for(77).choice(w.n_total, size=300, replace=False))
+    ref2, ref3 = oracle.subset_forces(w.x, box, idx)
+    with _system(w) as s:
+        x = _dev(w.x)
+        f2 = torch.empty_like(x)
+        f3 = torch.empty_like(x)
+        s.compute_pair_forces(x, f2)
+        s.compute_triplet_forces(x, f3)
+        count = s.count_triplets(x)
+        s.sync()
+    f2 = f2.cpu().numpy()
+    f3 = f3.cpu().numpy()
+    rms2 = np.sqrt(np.mean(np.sum(f2 * f2, axis=1)))
+    rms3 = np.sqrt(np.mean(np.sum(f3 * f3, axis=1)))
+    assert np.abs(f2[idx] - ref2).max() <= 1e-12 * rms2
+    assert np.abs(f3[idx] - ref3).max() <= 1e-12 * rms3
+    assert np.abs(f3.sum(axis=0)).max() <= 1e-10 * np.abs(f3).sum()
+    full = oracle.triplet_forces(w.x, box)
+    assert count == full.count
+    assert rel_err(f3, full.f) <= 1e-12
+
+
+@pytest.mark.parametrize("k,n_iter", [(1, 100), (2, 20), (5, 40)])
+def test_respa_matches_oracle(k, n_iter):
+    torch = _torch()
+    w = W.plain_fp64()
+    box = w.box[0]
+    xo, vo, eo = oracle.respa(w.x, w.v, box, n_iter=n_iter, k=k)
+    with _system(w, k=k) as s:
+        x = _dev(w.x)
+        v = _dev(w.v)
+        e = torch.zeros((n_iter // k + 1, 1, 5), dtype=torch.float64, device="cuda")
+        s.respa_step(x, v, n_iter, e)
+        s.sync()
+    dx = x.cpu().numpy() - xo
+    dx -= box * np.rint(dx / box)
+    assert np.abs(dx).max() <= 1e-10
+    assert np.abs(v.cpu().numpy() - vo).max() <= 1e-10 * np.abs(vo).max()
+    assert np.abs(e.cpu().numpy()[:, 0, :] - eo).max() <= 1e-10 * np.abs(eo).max()
+
+
+def test_determinism_and_resume():
+    torch = _torch()
+    w = W.plain_fp64()
+    with _system(w, k=5) as s:
+        x = _dev(w.x)
+        f_a = torch.empty_like(x)
+        f_b = torch.empty_like(x)
+        s.compute_triplet_forces(x, f_a)
+        s.compute_triplet_forces(x, f_b)
+        s.sync()
+        assert torch.equal(f_a, f_b)
+        x1, v1 = _dev(w.x), _dev(w.v)
+        s.respa_step(x1, v1, 20)
+        x2, v2 = _dev(w.x), _dev(w.v)
+        s.respa_step(x2, v2, 10)
+        s.respa_step(x2, v2, 10)
+        s.sync()
+        assert torch.equal(x1, x2) and torch.equal(v1, v2)
+
+
+def test_error_paths():
+    torch = _torch()
+    from paper_2507_11172_amd import mts
+    w = W.plain_fp64()
+    with _system(w, k=4) as s:
+        x, v = _dev(w.x), _dev(w.v)
+        with pytest.raises(mts.MTSError) as e:
+            s.respa_step(x, v, 10)
+        assert e.value.code == mts.MTS_ERR_NOT_MULTIPLE_OF_K
+        bad = w.x.copy()
+        bad[7, 2] = np.nan
+        f = torch.empty_like(x)
+        s.compute_pair_forces(_dev(bad), f)
+        with pytest.raises(mts.MTSError) as e:
+            s.sync()
+        assert e.value.code == mts.MTS_ERR_NONFINITE
+        s.compute_pair_forces(x, f)
+        s.sync()  # flags were cleared
+
+
+def test_capacity_overflow_is_reported_then_recovers():
+    """A dense clump overflows the LDS tile: the kernel clamps, flags, and the next call
+    runs with a doubled tile."""
+    torch = _torch()
+    from paper_2507_11172_amd import mts
+    rng = W.rng_for(9)
+    n = 700
+    x = 1.0 + rng.uniform(0.0, 2.4, size=(n, 3)) * np.array([1.0, 1.0, 1.0])
+    w = W.Workload("clump", x, np.zeros_like(x), np.full((1, 3), 20.0), np.array([n]),
+                   np.array([0.0]), nu=0.0)
+    with _system(w) as s:
+        xd = _dev(x)
+        f = torch.empty_like(xd)
+        s.compute_triplet_forces(xd, f)
+        with pytest.raises(mts.MTSError) as e:
+            s.sync()
+        assert e.value.code == mts.MTS_ERR_CAPACITY
