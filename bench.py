@@ -107,8 +107,8 @@ def cpu_baseline(w, k: int):
     return {"value": steps_per_s, "unit": "MD steps/s", "cores": nthreads, "kind": "oracle",
             "sample": "one LJ pair evaluation (%.2f s) and one ATM triplet evaluation "
                       "(%.2f s, %d triplets) of the full %d-particle system, combined as "
-                      "k=%d pair + 1 triplet evaluations per %d inner steps"
-                      % (t_pair, t_trip, r3.count, w.n_total, k, k, k),
+                      "k=%d pair + 1 triplet evaluations per k inner steps"
+                      % (t_pair, t_trip, r3.count, w.n_total, k),
             "triplets_per_s": r3.count / t_trip}
 
 
