@@ -115,7 +115,10 @@ mts_status mts_compute_pair_forces(mts_system *sys, const double *x, double *f2,
  *   ew  dev [n_systems][2] output {U3, W3}, or NULL. */
 mts_status mts_compute_triplet_forces(mts_system *sys, const double *x, double *f3, double *ew);
 
-/* Runs n_iter inner steps of r-RESPA (Sec. 4.1, Algorithm 2) in place.
+/* Runs n_iter inner steps of r-RESPA (Sec. 4.1, Algorithm 2) in place.  Each outer
+ * cycle (k inner steps, one F3 evaluation, its half kicks and the energy record) is one
+ * captured HIP graph replayed on a library stream that is ordered after, and before, the
+ * handle's stream (see MTS_OPT_CYCLE_GRAPH); the caller's x and v are copied in and out.
  *   x       dev [N][3] positions x^0 in, x^n out (wrapped into the box after each drift).
  *   v       dev [N][3] velocities v^0 in, v^n out.
  *   n_iter  number of inner steps, a multiple of k (else MTS_ERR_NOT_MULTIPLE_OF_K).
@@ -155,6 +158,18 @@ mts_status mts_count_triplets(mts_system *sys, const double *x, int64_t *count);
  * Synchronising. */
 mts_status mts_list_triplets(mts_system *sys, const double *x, int32_t *ijk, int64_t cap,
                              int64_t *n);
+
+/* ---- options ---- */
+
+enum {
+    /* 1 (default): mts_respa_step replays each outer cycle from a captured HIP graph on
+     * an internal stream; 0: launches every kernel one by one (same kernels, same order,
+     * bitwise-identical results). */
+    MTS_OPT_CYCLE_GRAPH = 1
+};
+
+/* Sets an option (see the MTS_OPT_ constants).  MTS_ERR_INVALID_ARG for unknown options. */
+mts_status mts_set_option(mts_system *sys, int32_t option, int64_t value);
 
 /* ---- profiling hook ---- */
 

@@ -13,6 +13,7 @@
 
 using namespace mts;
 
+
 struct mts_system {
     mts_params p{};
     int nsys = 0;
@@ -21,8 +22,8 @@ struct mts_system {
     std::vector<SysDesc> hsd;
     hipStream_t st = nullptr;
     bool fp32 = false;
-    int pair_lanes = 8;
-    int stage_cap = 0, list_cap = 0;
+    int stage_cap = 0, list_cap = 0, pair_cap = 0;
+    size_t max_lds = 64 * 1024;  // per-workgroup LDS limit of the device
     double ushift = 0.0;
     std::string err;
 
@@ -31,6 +32,8 @@ struct mts_system {
     int *sys_of = nullptr;       // [n]
     int *sys_of_cell = nullptr;  // [ncell]
     int *cell_of = nullptr, *rank = nullptr, *count = nullptr, *start = nullptr, *perm = nullptr;
+    int *perm_tmp = nullptr;     // [n] unordered scatter before ranking
+    double *red_part = nullptr;  // [nsys][kRedChunks][6] reduction partials
     double *xs = nullptr;        // [3][n]
     double *f2a = nullptr, *f2b = nullptr, *f3 = nullptr;  // [n][3] force caches
     double *pf = nullptr;        // [14][3][n]
@@ -40,9 +43,16 @@ struct mts_system {
     long long *cnt_sys = nullptr;  // [nsys]
     int *flags = nullptr;
     int *row = nullptr;
-    double *e_buf = nullptr;     // [rows][nsys][5]
+    double *e_buf = nullptr;     // [e_rows][nsys][5] energy records of one respa_step
     int64_t e_rows = 0;
     unsigned long long *list_n = nullptr;
+
+    // r-RESPA cycles run on an internal stream, optionally replayed from captured graphs
+    hipStream_t ist = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    bool use_graph = true;
+    hipGraphExec_t gexec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [energies][F2 parity]
+    double *xi = nullptr, *vi = nullptr;  // internal copies of x and v, [n][3]
 
     // optional per-launch HIP-event timing of the two force kernels (0: triplet, 1: pair)
     bool timing = false;
@@ -92,22 +102,26 @@ mts_status validate_params(const mts_params *p, std::string &msg) {
 
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
-// Tile capacities.  The staged half stencil holds 14 cells; a cell of volume h^3 holds
-// about rho h^3 particles.  Sizing assumes a local density of at least 1.25 (above any
-// LJ liquid or solid at these temperatures) so that slabs and crystals fit; overflow is
-// detected on the device and doubles the capacity for the next call.
+// Tile capacities.  A cell of volume h^3 holds about rho h^3 particles; sizing assumes a
+// local density of max(0.9, 1.2 x the system's mean), which covers LJ liquids and
+// crystals near the densities of the paper's scenarios, including a liquid slab inside
+// a dilute box.  The triplet tile holds the 14 cells of the forward half stencil, the
+// pair tile all 27 cells, and a forward-neighbour list about half a cutoff sphere.
+// Overflow is detected on the device, reported by mts_sync, and doubles the capacity
+// for the next call.
 void size_tiles(mts_system *s) {
     double need = 0.0, nl = 0.0;
     const double rc3 = s->p.rc_triplet;
     for (const SysDesc &d : s->hsd) {
         const double vol = d.L[0] * d.L[1] * d.L[2];
-        const double rho = std::max(1.25, 1.5 * (double)d.n / vol);
+        const double rho = std::max(0.9, 1.2 * (double)d.n / vol);
         const double cellv = (d.L[0] / d.nc[0]) * (d.L[1] / d.nc[1]) * (d.L[2] / d.nc[2]);
-        need = std::max(need, kNumHalf * rho * cellv);
-        nl = std::max(nl, rho * (4.0 / 3.0) * M_PI * rc3 * rc3 * rc3);  // full sphere: 2x the forward half
+        need = std::max(need, rho * cellv);
+        nl = std::max(nl, rho * (2.0 / 3.0) * M_PI * rc3 * rc3 * rc3);
     }
-    s->stage_cap = std::min(2048, round_up((int)std::ceil(need * 1.15) + 32, 64));
-    s->list_cap = std::min(1024, round_up((int)std::ceil(nl) + 16, 32));
+    s->stage_cap = std::min(2048, round_up((int)std::ceil(kNumHalf * need * 1.1) + 16, 32));
+    s->pair_cap = std::min(2048, round_up((int)std::ceil(kNumFull * need * 1.1) + 16, 32));
+    s->list_cap = std::min(1024, round_up((int)std::ceil(1.6 * nl) + 16, 32));
 }
 
 mts_status alloc_all(mts_system *s) {
@@ -120,6 +134,8 @@ mts_status alloc_all(mts_system *s) {
     HIP_TRY(s, dalloc(&s->count, s->ncell));
     HIP_TRY(s, dalloc(&s->start, (size_t)s->ncell + 1));
     HIP_TRY(s, dalloc(&s->perm, n));
+    HIP_TRY(s, dalloc(&s->perm_tmp, n));
+    HIP_TRY(s, dalloc(&s->red_part, (size_t)s->nsys * kRedChunks * 6));
     HIP_TRY(s, dalloc(&s->xs, 3 * n));
     HIP_TRY(s, dalloc(&s->f2a, 3 * n));
     HIP_TRY(s, dalloc(&s->f2b, 3 * n));
@@ -132,6 +148,11 @@ mts_status alloc_all(mts_system *s) {
     HIP_TRY(s, dalloc(&s->flags, 1));
     HIP_TRY(s, dalloc(&s->row, 1));
     HIP_TRY(s, dalloc(&s->list_n, 1));
+    HIP_TRY(s, dalloc(&s->xi, 3 * n));
+    HIP_TRY(s, dalloc(&s->vi, 3 * n));
+    HIP_TRY(s, hipStreamCreateWithFlags(&s->ist, hipStreamNonBlocking));
+    HIP_TRY(s, hipEventCreateWithFlags(&s->ev_in, hipEventDisableTiming));
+    HIP_TRY(s, hipEventCreateWithFlags(&s->ev_out, hipEventDisableTiming));
 
     std::vector<int> so(n > 0 ? n : 1), soc(s->ncell);
     for (int q = 0; q < s->nsys; ++q) {
@@ -168,12 +189,26 @@ void timer_end(mts_system *s, int cls, long slot) {
     if (slot >= 0) (void)hipEventRecord(s->ev_pool[cls][slot + 1], s->st);
 }
 
+void drop_graphs(mts_system *s) {
+    for (auto &g : s->gexec)
+        for (hipGraphExec_t &e : g)
+            if (e) {
+                (void)hipGraphExecDestroy(e);
+                e = nullptr;
+            }
+}
+
 void free_all(mts_system *s) {
+    drop_graphs(s);
+    if (s->ev_in) (void)hipEventDestroy(s->ev_in);
+    if (s->ev_out) (void)hipEventDestroy(s->ev_out);
+    if (s->ist) (void)hipStreamDestroy(s->ist);
     for (int c = 0; c < 2; ++c)
         for (hipEvent_t e : s->ev_pool[c]) (void)hipEventDestroy(e);
     void *ptrs[] = {s->sd, s->sys_of, s->sys_of_cell, s->cell_of, s->rank, s->count, s->start,
                     s->perm, s->xs, s->f2a, s->f2b, s->f3, s->pf, s->pe, s->ce, s->cc,
-                    s->cnt_sys, s->flags, s->row, s->e_buf, s->list_n};
+                    s->cnt_sys, s->flags, s->row, s->e_buf, s->list_n, s->perm_tmp,
+                    s->red_part, s->xi, s->vi};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -183,14 +218,17 @@ mts_status enqueue_bin(mts_system *s, const double *x) {
     HIP_TRY(s, launch_bin_count(s->st, s->n, x, s->sd, s->sys_of, s->cell_of, s->rank, s->count,
                                 s->flags));
     HIP_TRY(s, launch_scan(s->st, s->ncell, s->count, s->start, s->n));
-    HIP_TRY(s, launch_bin_scatter(s->st, s->n, s->cell_of, s->rank, s->start, s->perm));
-    HIP_TRY(s, launch_cell_sort(s->st, s->ncell, s->start, s->perm, s->count));
-    HIP_TRY(s, launch_gather_sorted(s->st, s->n, x, s->perm, s->sd, s->sys_of, s->xs));
+    HIP_TRY(s, launch_bin_scatter(s->st, s->n, s->cell_of, s->rank, s->start, s->perm_tmp));
+    HIP_TRY(s, launch_rank_gather(s->st, s->n, s->perm_tmp, s->cell_of, s->start, x, s->sd,
+                                  s->sys_of, s->perm, s->xs));
     return MTS_OK;
 }
 
 mts_status enqueue_pair(mts_system *s, double *f2) {
     PairArgs a{};
+    a.ncell = s->ncell;
+    a.sys_of_cell = s->sys_of_cell;
+    a.stage_cap = s->pair_cap;
     a.n = s->n;
     a.xs = s->xs;
     a.perm = s->perm;
@@ -205,7 +243,7 @@ mts_status enqueue_pair(mts_system *s, double *f2) {
     a.ushift = s->ushift;
     a.flags = s->flags;
     const long ts = timer_begin(s, 1);
-    HIP_TRY(s, launch_pair(s->st, a, s->fp32, s->pair_lanes));
+    HIP_TRY(s, launch_pair(s->st, a, s->fp32));
     timer_end(s, 1, ts);
     return MTS_OK;
 }
@@ -252,6 +290,7 @@ mts_status enqueue_reduce(mts_system *s, const double *v, bool pair, bool trip, 
     a.count_out = count_out;
     a.flags = s->flags;
     a.row = row;
+    a.part = s->red_part;
     HIP_TRY(s, launch_reduce(s->st, a));
     return MTS_OK;
 }
@@ -332,7 +371,19 @@ mts_status mts_init_system(const mts_params *params, int32_t n_systems, const in
                     ? lj_energy(params->rc_pair * params->rc_pair, params->epsilon, params->sigma)
                     : 0.0;
     size_tiles(s);
-    if (triplet_lds_bytes(s->stage_cap, s->list_cap) > 64 * 1024) {
+    {
+        int dev = 0, lds = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+            lds > 0)
+            s->max_lds = (size_t)lds;
+        // keep room for the kernels' static LDS
+        s->max_lds = s->max_lds > 1024 ? s->max_lds - 1024 : s->max_lds;
+        if (configure_kernel_lds(s->max_lds) != hipSuccess) s->max_lds = 64 * 1024 - 1024;
+        (void)hipGetLastError();  // do not leave a failed attribute call as a sticky error
+    }
+    if (triplet_lds_bytes(s->stage_cap, s->list_cap) > s->max_lds ||
+        pair_lds_bytes(s->pair_cap) > s->max_lds) {
         free_all(s);
         delete s;
         return MTS_ERR_UNSUPPORTED;
@@ -349,6 +400,7 @@ mts_status mts_init_system(const mts_params *params, int32_t n_systems, const in
 
 void mts_destroy_system(mts_system *sys) {
     if (!sys) return;
+    if (sys->ist) (void)hipStreamSynchronize(sys->ist);
     (void)hipStreamSynchronize(sys->st);
     free_all(sys);
     delete sys;
@@ -378,74 +430,154 @@ mts_status mts_compute_triplet_forces(mts_system *sys, const double *x, double *
     return MTS_OK;
 }
 
+// One outer cycle of Algorithm 2 on the internal copies xi, vi: k inner steps (F3 half
+// kick at the first, drift + wrap, binning, F2, F2 kick), then F3 at the full step, its
+// half kick and, if requested, the energy record.  f2a holds F2 of the cycle's first
+// position; after the cycle F2 of the last position is in f2a when k is even, f2b when odd.
+mts_status enqueue_cycle(mts_system *s, double *f2a, double *f2b, bool energies) {
+    const int k = s->p.k;
+    const int64_t n3 = 3 * s->n;
+    const double dt = s->p.dt, m = s->p.mass;
+    const double c3 = (dt * (double)k) / (2.0 * m);
+    const double cx = (dt * dt) / (2.0 * m);
+    const double c2 = dt / (2.0 * m);
+    double *f2cur = f2a, *f2nxt = f2b;
+    for (int i = 0; i < k; ++i) {
+        if (i == 0) HIP_TRY(s, launch_kick(s->st, n3, s->vi, s->f3, c3));
+        HIP_TRY(s, launch_drift(s->st, s->n, s->xi, s->vi, f2cur, dt, cx, s->sd, s->sys_of));
+        MTS_TRY(enqueue_bin(s, s->xi));
+        MTS_TRY(enqueue_pair(s, f2nxt));
+        HIP_TRY(s, launch_kick2(s->st, n3, s->vi, f2cur, f2nxt, c2));
+        std::swap(f2cur, f2nxt);
+    }
+    MTS_TRY(enqueue_triplet(s, s->f3, nullptr, 0));
+    HIP_TRY(s, launch_kick(s->st, n3, s->vi, s->f3, c3));
+    if (energies) {
+        MTS_TRY(enqueue_reduce(s, s->vi, true, true, s->e_buf, kNE, s->row, nullptr));
+        HIP_TRY(s, launch_bump_row(s->st, s->row));
+    }
+    return MTS_OK;
+}
+
+// Captures one cycle into an executable graph (kernels only: no memset or copy nodes).
+mts_status capture_cycle(mts_system *s, bool energies, int parity) {
+    double *fa = parity ? s->f2b : s->f2a, *fb = parity ? s->f2a : s->f2b;
+    HIP_TRY(s, hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal));
+    mts_status r = enqueue_cycle(s, fa, fb, energies);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(s->st, &g);
+    if (r != MTS_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return r;
+    }
+    if (e != hipSuccess) return hip_fail(s, e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&s->gexec[energies][parity], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(s, e, "hipGraphInstantiate");
+    return MTS_OK;
+}
+
+mts_status respa_internal(mts_system *s, double *x, double *v, int64_t n_iter, double *e_full) {
+    const int k = s->p.k;
+    const int64_t cycles = n_iter / k;
+    const bool energies = e_full != nullptr;
+    const int64_t bytes = 3 * s->n * (int64_t)sizeof(double);
+    if (energies && s->e_rows < cycles + 1) {
+        // grow the energy record buffer; graphs holding the old pointer are dropped
+        drop_graphs(s);
+        if (s->e_buf) HIP_TRY(s, hipFree(s->e_buf));
+        s->e_buf = nullptr;
+        s->e_rows = 0;
+        HIP_TRY(s, dalloc(&s->e_buf, (size_t)(cycles + 1) * s->nsys * kNE));
+        s->e_rows = cycles + 1;
+    }
+    if (bytes > 0) {
+        HIP_TRY(s, hipMemcpyAsync(s->xi, x, bytes, hipMemcpyDeviceToDevice, s->st));
+        HIP_TRY(s, hipMemcpyAsync(s->vi, v, bytes, hipMemcpyDeviceToDevice, s->st));
+    }
+    // Algorithm 2, lines 1-2: F2(x^0), F3(x^0); energies of x^0 in row 0
+    MTS_TRY(enqueue_bin(s, s->xi));
+    MTS_TRY(enqueue_pair(s, s->f2a));
+    MTS_TRY(enqueue_triplet(s, s->f3, nullptr, 0));
+    if (energies) {
+        HIP_TRY(s, launch_set_int(s->st, s->row, 0));
+        MTS_TRY(enqueue_reduce(s, s->vi, true, true, s->e_buf, kNE, s->row, nullptr));
+        HIP_TRY(s, launch_bump_row(s->st, s->row));
+    }
+    const bool graph = s->use_graph && !s->timing;
+    for (int64_t c = 0; c < cycles; ++c) {
+        const int parity = (k & 1) ? (int)(c & 1) : 0;
+        if (graph) {
+            if (!s->gexec[energies][parity]) MTS_TRY(capture_cycle(s, energies, parity));
+            HIP_TRY(s, hipGraphLaunch(s->gexec[energies][parity], s->st));
+        } else {
+            MTS_TRY(enqueue_cycle(s, parity ? s->f2b : s->f2a, parity ? s->f2a : s->f2b, energies));
+        }
+    }
+    if (bytes > 0) {
+        HIP_TRY(s, hipMemcpyAsync(x, s->xi, bytes, hipMemcpyDeviceToDevice, s->st));
+        HIP_TRY(s, hipMemcpyAsync(v, s->vi, bytes, hipMemcpyDeviceToDevice, s->st));
+    }
+    if (energies)
+        HIP_TRY(s, hipMemcpyAsync(e_full, s->e_buf, sizeof(double) * (size_t)(cycles + 1) * s->nsys * kNE,
+                                  hipMemcpyDeviceToDevice, s->st));
+    return MTS_OK;
+}
+
 mts_status mts_respa_step(mts_system *sys, double *x, double *v, int64_t n_iter, double *e_full) {
     if (!sys) return MTS_ERR_INVALID_ARG;
     if ((!x || !v) && sys->n > 0) return fail(sys, MTS_ERR_INVALID_ARG, "x or v is NULL");
     if (n_iter < 0) return fail(sys, MTS_ERR_INVALID_ARG, "n_iter < 0");
-    const int k = sys->p.k;
-    if (n_iter % k != 0)
+    if (n_iter % sys->p.k != 0)
         return fail(sys, MTS_ERR_NOT_MULTIPLE_OF_K, "n_iter must be a multiple of k (Sec. 4.1)");
-    const int64_t n3 = 3 * sys->n;
-    const double dt = sys->p.dt, m = sys->p.mass;
-    const double c3 = (dt * (double)k) / (2.0 * m);
-    const double cx = (dt * dt) / (2.0 * m);
-    const double c2 = dt / (2.0 * m);
-    int *row = nullptr;
-    double *eout = nullptr;
-    if (e_full) {
-        HIP_TRY(sys, hipMemsetAsync(sys->row, 0, sizeof(int), sys->st));
-        row = sys->row;
-        eout = e_full;
+    // run on the internal stream, ordered after and before the caller's stream
+    hipStream_t user = sys->st;
+    HIP_TRY(sys, hipEventRecord(sys->ev_in, user));
+    HIP_TRY(sys, hipStreamWaitEvent(sys->ist, sys->ev_in, 0));
+    sys->st = sys->ist;
+    mts_status r = respa_internal(sys, x, v, n_iter, e_full);
+    sys->st = user;
+    HIP_TRY(sys, hipEventRecord(sys->ev_out, sys->ist));
+    HIP_TRY(sys, hipStreamWaitEvent(user, sys->ev_out, 0));
+    return r;
+}
+
+mts_status mts_set_option(mts_system *sys, int32_t option, int64_t value) {
+    if (!sys) return MTS_ERR_INVALID_ARG;
+    switch (option) {
+        case MTS_OPT_CYCLE_GRAPH:
+            sys->use_graph = value != 0;
+            return MTS_OK;
+        default:
+            return fail(sys, MTS_ERR_INVALID_ARG, "unknown option");
     }
-    // Algorithm 2, lines 1-2: F2(x^0), F3(x^0)
-    double *f2cur = sys->f2a, *f2nxt = sys->f2b;
-    MTS_TRY(enqueue_bin(sys, x));
-    MTS_TRY(enqueue_pair(sys, f2cur));
-    MTS_TRY(enqueue_triplet(sys, sys->f3, nullptr, 0));
-    if (eout) {
-        MTS_TRY(enqueue_reduce(sys, v, true, true, eout, kNE, row, nullptr));
-        HIP_TRY(sys, launch_bump_row(sys->st, sys->row));
-    }
-    for (int64_t i = 0; i < n_iter; ++i) {
-        if (i % k == 0) HIP_TRY(sys, launch_kick(sys->st, n3, v, sys->f3, c3));
-        HIP_TRY(sys, launch_drift(sys->st, sys->n, x, v, f2cur, dt, cx, sys->sd, sys->sys_of));
-        MTS_TRY(enqueue_bin(sys, x));
-        MTS_TRY(enqueue_pair(sys, f2nxt));
-        HIP_TRY(sys, launch_kick2(sys->st, n3, v, f2cur, f2nxt, c2));
-        std::swap(f2cur, f2nxt);
-        if ((i + 1) % k == 0) {
-            MTS_TRY(enqueue_triplet(sys, sys->f3, nullptr, 0));
-            HIP_TRY(sys, launch_kick(sys->st, n3, v, sys->f3, c3));
-            if (eout) {
-                MTS_TRY(enqueue_reduce(sys, v, true, true, eout, kNE, row, nullptr));
-                HIP_TRY(sys, launch_bump_row(sys->st, sys->row));
-            }
-        }
-    }
-    // keep the F2 cache that belongs to the final x in f2a for the next call's reuse
-    if (f2cur != sys->f2a) std::swap(sys->f2a, sys->f2b);
-    return MTS_OK;
 }
 
 mts_status mts_sync(mts_system *sys) {
     if (!sys) return MTS_ERR_INVALID_ARG;
+    HIP_TRY(sys, hipStreamSynchronize(sys->ist));
     HIP_TRY(sys, hipStreamSynchronize(sys->st));
     int flags = 0;
     HIP_TRY(sys, hipMemcpy(&flags, sys->flags, sizeof(int), hipMemcpyDeviceToHost));
     HIP_TRY(sys, hipMemset(sys->flags, 0, sizeof(int)));
     if (flags & (kFlagStageOverflow | kFlagListOverflow)) {
-        const int old_s = sys->stage_cap, old_l = sys->list_cap;
-        if (flags & kFlagStageOverflow) sys->stage_cap = std::min(4096, 2 * sys->stage_cap);
+        const int old_s = sys->stage_cap, old_l = sys->list_cap, old_p = sys->pair_cap;
+        if (flags & kFlagStageOverflow) {
+            sys->stage_cap = std::min(4096, 2 * sys->stage_cap);
+            sys->pair_cap = std::min(4096, 2 * sys->pair_cap);
+        }
         if (flags & kFlagListOverflow) sys->list_cap = std::min(2048, 2 * sys->list_cap);
-        if (triplet_lds_bytes(sys->stage_cap, sys->list_cap) > 64 * 1024) {
+        if (triplet_lds_bytes(sys->stage_cap, sys->list_cap) > sys->max_lds) {
             sys->stage_cap = old_s;
             sys->list_cap = old_l;
         }
-        char buf[160];
+        if (pair_lds_bytes(sys->pair_cap) > sys->max_lds) sys->pair_cap = old_p;
+        drop_graphs(sys);  // captured launches carry the old tile sizes
+        char buf[200];
         snprintf(buf, sizeof buf,
-                 "capacity overflow (flags %d): tile %d -> %d, neighbour list %d -> %d; "
-                 "results since the last sync are invalid",
-                 flags, old_s, sys->stage_cap, old_l, sys->list_cap);
+                 "capacity overflow (flags %d): triplet tile %d -> %d, pair tile %d -> %d, "
+                 "neighbour list %d -> %d; results since the last sync are invalid",
+                 flags, old_s, sys->stage_cap, old_p, sys->pair_cap, old_l, sys->list_cap);
         return fail(sys, MTS_ERR_CAPACITY, buf);
     }
     if (flags & kFlagNonFinite) return fail(sys, MTS_ERR_NONFINITE, "non-finite force or energy");
@@ -497,6 +629,7 @@ mts_status mts_list_triplets(mts_system *sys, const double *x, int32_t *ijk, int
 
 mts_status mts_enable_kernel_timing(mts_system *sys, int32_t enable) {
     if (!sys) return MTS_ERR_INVALID_ARG;
+    HIP_TRY(sys, hipStreamSynchronize(sys->ist));
     HIP_TRY(sys, hipStreamSynchronize(sys->st));
     sys->timing = enable != 0;
     sys->ev_used[0] = sys->ev_used[1] = 0;
@@ -505,6 +638,7 @@ mts_status mts_enable_kernel_timing(mts_system *sys, int32_t enable) {
 
 mts_status mts_kernel_times(mts_system *sys, int64_t launches[2], double ms[2]) {
     if (!sys || !launches || !ms) return MTS_ERR_INVALID_ARG;
+    HIP_TRY(sys, hipStreamSynchronize(sys->ist));
     HIP_TRY(sys, hipStreamSynchronize(sys->st));
     for (int c = 0; c < 2; ++c) {
         double tot = 0.0;

@@ -1,8 +1,9 @@
 // Linked-cell binning by counting sort (Sec. 2.2 and 4.1: particles are assigned to
 // cells by position).  Steps: wrap + cell index + histogram (int atomics), exclusive
-// scan, scatter, then a per-cell insertion sort so that particles inside a cell keep
-// ascending input order -- the sort is stable and deterministic, which fixes every
-// later summation order.  All passes are HBM/L2-bound streaming kernels.
+// scan (which also clears the histogram for the next call), atomic scatter, then a rank
+// pass that restores ascending input order inside every cell -- the sort is stable and
+// deterministic, which fixes every later summation order.  All passes are HBM/L2-bound
+// streaming kernels.
 #include "common.h"
 
 namespace mts {
@@ -32,7 +33,7 @@ __global__ void __launch_bounds__(256) k_bin_count(int64_t n, const double *__re
 
 // Exclusive scan of count[0..ncell) into start[0..ncell], start[ncell] = n_total.
 // One workgroup of 1024 threads; each thread owns a contiguous chunk.
-__global__ void __launch_bounds__(1024) k_scan(int ncell, const int *__restrict__ count,
+__global__ void __launch_bounds__(1024) k_scan(int ncell, int *__restrict__ count,
                                                int *__restrict__ start, int64_t n_total) {
     __shared__ int part[1024];
     const int t = threadIdx.x;
@@ -53,6 +54,7 @@ __global__ void __launch_bounds__(1024) k_scan(int ncell, const int *__restrict_
     for (int c = b; c < e; ++c) {
         start[c] = run;
         run += count[c];
+        count[c] = 0;  // ready for the next binning
     }
     if (t == 0) start[ncell] = (int)n_total;
 }
@@ -66,37 +68,30 @@ __global__ void __launch_bounds__(256) k_bin_scatter(int64_t n, const int *__res
     perm[start[cell_of[i]] + rank[i]] = (int)i;
 }
 
-// One thread per cell: insertion-sort the cell's input indices ascending and clear
-// the cell counter for the next binning.
-__global__ void __launch_bounds__(256) k_cell_sort(int ncell, const int *__restrict__ start,
-                                                   int *__restrict__ perm, int *__restrict__ count) {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncell) return;
-    const int b = start[c], e = start[c + 1];
-    for (int i = b + 1; i < e; ++i) {
-        int key = perm[i];
-        int j = i - 1;
-        while (j >= b && perm[j] > key) {
-            perm[j + 1] = perm[j];
-            --j;
-        }
-        perm[j + 1] = key;
-    }
-    count[c] = 0;
-}
-
-// Sorted, wrapped positions in SoA layout: xs[k * n + p] = wrap(x[perm[p]][k]).
-__global__ void __launch_bounds__(256) k_gather_sorted(int64_t n, const double *__restrict__ x,
-                                                       const int *__restrict__ perm,
-                                                       const SysDesc *__restrict__ sd,
-                                                       const int *__restrict__ sys_of,
-                                                       double *__restrict__ xs) {
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Final, deterministic order inside each cell: the particle that the atomic scatter put
+// at slot p finds its rank among the cell's members by counting smaller input indices
+// (cells hold ~10-20 particles), then writes its input index and its wrapped position
+// (SoA) to the ranked slot.  Equal cells therefore keep ascending input order.
+__global__ void __launch_bounds__(256) k_rank_gather(int64_t n, const int *__restrict__ tmp,
+                                                     const int *__restrict__ cell_of,
+                                                     const int *__restrict__ start,
+                                                     const double *__restrict__ x,
+                                                     const SysDesc *__restrict__ sd,
+                                                     const int *__restrict__ sys_of,
+                                                     int *__restrict__ perm,
+                                                     double *__restrict__ xs) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
-    const int64_t i = perm[p];
-    const SysDesc &d = sd[sys_of[p]];
+    const int key = tmp[p];
+    const int c = cell_of[key];
+    const int b = start[c], e = start[c + 1];
+    int r = 0;
+    for (int q = b; q < e; ++q) r += tmp[q] < key;
+    const int64_t dst = b + r;
+    perm[dst] = key;
+    const SysDesc &d = sd[sys_of[key]];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) xs[k * n + p] = wrap1(x[3 * i + k], d.L[k]);
+    for (int k = 0; k < 3; ++k) xs[k * n + dst] = wrap1(x[3 * (int64_t)key + k], d.L[k]);
 }
 
 __global__ void k_local_cell_index(int64_t n, const int *__restrict__ cell_of,
@@ -116,7 +111,7 @@ hipError_t launch_bin_count(hipStream_t st, int64_t n, const double *x, const Sy
     return hipGetLastError();
 }
 
-hipError_t launch_scan(hipStream_t st, int ncell, const int *count, int *start, int64_t n_total) {
+hipError_t launch_scan(hipStream_t st, int ncell, int *count, int *start, int64_t n_total) {
     k_scan<<<1, 1024, 0, st>>>(ncell, count, start, n_total);
     return hipGetLastError();
 }
@@ -127,14 +122,12 @@ hipError_t launch_bin_scatter(hipStream_t st, int64_t n, const int *cell_of, con
     return hipGetLastError();
 }
 
-hipError_t launch_cell_sort(hipStream_t st, int ncell, const int *start, int *perm, int *count) {
-    k_cell_sort<<<blocks_for(ncell, 256), 256, 0, st>>>(ncell, start, perm, count);
-    return hipGetLastError();
-}
-
-hipError_t launch_gather_sorted(hipStream_t st, int64_t n, const double *x, const int *perm,
-                                const SysDesc *sd, const int *sys_of, double *xs) {
-    if (n > 0) k_gather_sorted<<<blocks_for(n, 256), 256, 0, st>>>(n, x, perm, sd, sys_of, xs);
+hipError_t launch_rank_gather(hipStream_t st, int64_t n, const int *tmp, const int *cell_of,
+                              const int *start, const double *x, const SysDesc *sd,
+                              const int *sys_of, int *perm, double *xs) {
+    if (n > 0)
+        k_rank_gather<<<blocks_for(n, 256), 256, 0, st>>>(n, tmp, cell_of, start, x, sd, sys_of,
+                                                          perm, xs);
     return hipGetLastError();
 }
 

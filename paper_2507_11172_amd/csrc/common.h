@@ -87,23 +87,89 @@ __device__ __forceinline__ void half_offset(int o, int &ox, int &oy, int &oz) {
     full_offset(f, ox, oy, oz);
 }
 
+// ---------------------------------------------------------------- tile staging
+// Stencil description of one workgroup's tile: for each stencil cell o (< NC), the
+// first sorted particle, the tile offset and the packed image-shift code.
+template <int NC>
+struct StencilTable {
+    int begin[NC];
+    int off[NC + 1];
+    int code[NC];
+};
+
+// Fills the table for base cell (cx, cy, cz).  Lane o of wave 0 handles stencil cell o
+// (offsets from `offset_of(o)`), reads its bounds from `start`, and a shuffle prefix sum
+// gives the tile offsets, so a tile costs two dependent global loads instead of two per
+// cell.  Call from every thread; contains __syncthreads().  Returns the total count.
+template <int NC, bool HALF>
+__device__ __forceinline__ int stencil_table(StencilTable<NC> &tab, const SysDesc &d, int cx,
+                                             int cy, int cz, const int *start) {
+    static_assert(NC <= 64, "one lane per stencil cell");
+    const int tid = threadIdx.x;
+    if (tid < 64) {
+        int cnt = 0;
+        if (tid < NC) {
+            int ox, oy, oz, sx, sy, sz;
+            if (HALF) {
+                const int f = tid == 0 ? 13 : 13 + tid;
+                ox = f % 3 - 1; oy = (f / 3) % 3 - 1; oz = f / 9 - 1;
+            } else {
+                ox = tid % 3 - 1; oy = (tid / 3) % 3 - 1; oz = tid / 9 - 1;
+            }
+            const int tx = wrap_cell(cx, ox, d.nc[0], sx);
+            const int ty = wrap_cell(cy, oy, d.nc[1], sy);
+            const int tz = wrap_cell(cz, oz, d.nc[2], sz);
+            const int cell = d.cell0 + (tz * d.nc[1] + ty) * d.nc[0] + tx;
+            const int b = start[cell];
+            cnt = start[cell + 1] - b;
+            tab.begin[tid] = b;
+            tab.code[tid] = (sx + 1) | ((sy + 1) << 2) | ((sz + 1) << 4) | (tid << 8);
+        }
+        int incl = cnt;
+#pragma unroll
+        for (int m = 1; m < 64; m <<= 1) {
+            const int y = __shfl_up(incl, m);
+            if (tid >= m) incl += y;
+        }
+        if (tid < NC) tab.off[tid] = incl - cnt;
+        if (tid == NC - 1) tab.off[NC] = incl;
+    }
+    __syncthreads();
+    return tab.off[NC];
+}
+
+// Stencil cell of tile entry t (binary search over the offsets).
+template <int NC>
+__device__ __forceinline__ int stencil_cell_of(const StencilTable<NC> &tab, int t) {
+    int lo = 0, hi = NC - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tab.off[mid] <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 // ---------------------------------------------------------------- launchers
 // All launchers enqueue on `st` and return hipGetLastError().
 
 // Binning (counting sort by cell).
 hipError_t launch_bin_count(hipStream_t st, int64_t n, const double *x, const SysDesc *sd,
                             const int *sys_of, int *cell_of, int *rank, int *count, int *flags);
-hipError_t launch_scan(hipStream_t st, int ncell, const int *count, int *start, int64_t n_total);
+hipError_t launch_scan(hipStream_t st, int ncell, int *count, int *start, int64_t n_total);
 hipError_t launch_bin_scatter(hipStream_t st, int64_t n, const int *cell_of, const int *rank,
-                              const int *start, int *perm);
-hipError_t launch_cell_sort(hipStream_t st, int ncell, const int *start, int *perm, int *count);
-hipError_t launch_gather_sorted(hipStream_t st, int64_t n, const double *x, const int *perm,
-                                const SysDesc *sd, const int *sys_of, double *xs);
+                              const int *start, int *tmp);
+hipError_t launch_rank_gather(hipStream_t st, int64_t n, const int *tmp, const int *cell_of,
+                              const int *start, const double *x, const SysDesc *sd,
+                              const int *sys_of, int *perm, double *xs);
 hipError_t launch_local_cell_index(hipStream_t st, int64_t n, const int *cell_of,
                                    const SysDesc *sd, const int *sys_of, int *out);
 
-// Pair forces: full stencil, each particle sums its own neighbours.
+// Pair forces: one wavefront per base cell over its full stencil tile in LDS.
 struct PairArgs {
+    int ncell;
+    const int *sys_of_cell; // [ncell]
+    int stage_cap;          // LDS tile capacity (particles)
     int64_t n;
     const double *xs;       // sorted wrapped positions, SoA [3][n]
     const int *perm;        // sorted -> input index
@@ -115,7 +181,11 @@ struct PairArgs {
     double eps, sigma2, rc2, ushift;
     int *flags;
 };
-hipError_t launch_pair(hipStream_t st, const PairArgs &a, bool fp32, int lanes_per_particle);
+hipError_t launch_pair(hipStream_t st, const PairArgs &a, bool fp32);
+size_t pair_lds_bytes(int stage_cap);
+
+// Lets every LDS-tiled kernel use up to max_bytes of dynamic LDS per workgroup.
+hipError_t configure_kernel_lds(size_t max_bytes);
 
 // Triplet forces: one workgroup per base cell, forward half stencil in LDS.
 struct TripletArgs {
@@ -162,8 +232,11 @@ struct ReduceArgs {
     long long *count_out;   // [nsys] triplet counts or null
     int *flags;
     const int *row;         // optional device row index: out += (*row) * nsys * stride
+    double *part;           // scratch [nsys][kRedChunks][6]
 };
+constexpr int kRedChunks = 64;
 hipError_t launch_reduce(hipStream_t st, const ReduceArgs &a);
 hipError_t launch_bump_row(hipStream_t st, int *row);
+hipError_t launch_set_int(hipStream_t st, int *p, int v);  // a kernel, so it may be captured
 
 }  // namespace mts

@@ -54,66 +54,74 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
     return r;
 }
 
-__global__ void __launch_bounds__(kRed) k_reduce(ReduceArgs a) {
+// Pass 1: block (system s, chunk c) sums a fixed contiguous chunk of the system's
+// particles (kinetic, pair energy/virial) and cells (triplet energy/virial/count).
+__global__ void __launch_bounds__(kRed) k_reduce_part(ReduceArgs a) {
     __shared__ double red[kRed];
-    const int s = blockIdx.x;
+    const int s = blockIdx.x / kRedChunks, c = blockIdx.x % kRedChunks;
     const int t = threadIdx.x;
     const SysDesc &d = a.sd[s];
-    double kin = 0.0, u2 = 0.0, w2 = 0.0, u3 = 0.0, w3 = 0.0;
-    long long cnt = 0;
-    if (a.v) {
-        for (int64_t i = d.p0 + t; i < d.p0 + d.n; i += kRed) {
+    const int64_t lp = (d.n + kRedChunks - 1) / kRedChunks;
+    const int64_t pb = d.p0 + c * lp, pe = d.p0 + min(d.n, (c + 1) * lp);
+    const int lc = (d.ncell + kRedChunks - 1) / kRedChunks;
+    const int cb = d.cell0 + c * lc, ce = d.cell0 + min(d.ncell, (c + 1) * lc);
+    double kin = 0.0, u2 = 0.0, w2 = 0.0, u3 = 0.0, w3 = 0.0, cnt = 0.0;
+    if (a.v)
+        for (int64_t i = pb + t; i < pe; i += kRed) {
             const double vx = a.v[3 * i], vy = a.v[3 * i + 1], vz = a.v[3 * i + 2];
             kin += (vx * vx + vy * vy) + vz * vz;
         }
-    }
-    if (a.pe) {
-        for (int64_t p = d.p0 + t; p < d.p0 + d.n; p += kRed) {
+    if (a.pe)
+        for (int64_t p = pb + t; p < pe; p += kRed) {
             u2 += a.pe[2 * p];
             w2 += a.pe[2 * p + 1];
         }
-    }
-    if (a.ce) {
-        for (int c = d.cell0 + t; c < d.cell0 + d.ncell; c += kRed) {
-            u3 += a.ce[2 * c];
-            w3 += a.ce[2 * c + 1];
-            if (a.cc) cnt += a.cc[c];
+    if (a.ce)
+        for (int q = cb + t; q < ce; q += kRed) {
+            u3 += a.ce[2 * q];
+            w3 += a.ce[2 * q + 1];
+            if (a.cc) cnt += (double)a.cc[q];
         }
-    }
-    kin = block_sum(kin, red) * a.half_mass;
+    kin = block_sum(kin, red);
     u2 = block_sum(u2, red);
     w2 = block_sum(w2, red);
     u3 = block_sum(u3, red);
     w3 = block_sum(w3, red);
-    __shared__ long long redc[kRed];
-    redc[t] = cnt;
-    __syncthreads();
-    for (int h = kRed / 2; h > 0; h >>= 1) {
-        if (t < h) redc[t] += redc[t + h];
-        __syncthreads();
+    cnt = block_sum(cnt, red);
+    if (t == 0) {
+        double *o = a.part + 6 * (size_t)blockIdx.x;
+        o[0] = kin; o[1] = u2; o[2] = u3; o[3] = w2; o[4] = w3; o[5] = cnt;
     }
-    if (t != 0) return;
+}
+
+// Pass 2: one thread per system sums its kRedChunks partials in chunk order.
+__global__ void k_reduce_final(ReduceArgs a) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= a.nsys) return;
+    double r[6] = {0, 0, 0, 0, 0, 0};
+    for (int c = 0; c < kRedChunks; ++c)
+        for (int q = 0; q < 6; ++q) r[q] += a.part[6 * ((size_t)s * kRedChunks + c) + q];
+    const double kin = r[0] * a.half_mass;
     double *out = a.out;
     if (out) {
         if (a.row) out += (int64_t)(*a.row) * a.nsys * a.stride;
         out += (int64_t)s * a.stride;
         if (a.stride == kNE) {
-            out[0] = kin;
-            out[1] = u2;
-            out[2] = u3;
-            out[3] = w2;
-            out[4] = w3;
+            out[0] = kin; out[1] = r[1]; out[2] = r[2]; out[3] = r[3]; out[4] = r[4];
         } else {
-            out[0] = a.pe ? u2 : u3;
-            out[1] = a.pe ? w2 : w3;
+            out[0] = a.pe ? r[1] : r[2];
+            out[1] = a.pe ? r[3] : r[4];
         }
     }
-    if (a.count_out) a.count_out[s] = redc[0];
-    if (!isfinite(kin) || !isfinite(u2) || !isfinite(u3) || !isfinite(w2) || !isfinite(w3))
-        atomicOr(a.flags, kFlagNonFinite);
+    if (a.count_out) a.count_out[s] = (long long)r[5];
+    bool ok = true;
+    for (int q = 0; q < 5; ++q) ok = ok && isfinite(r[q]);
+    if (!ok) atomicOr(a.flags, kFlagNonFinite);
 }
 
 __global__ void k_bump_row(int *row) { *row += 1; }
+
+__global__ void k_set_int(int *p, int v) { *p = v; }
 
 static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
@@ -135,7 +143,16 @@ hipError_t launch_drift(hipStream_t st, int64_t n, double *x, const double *v, c
 }
 
 hipError_t launch_reduce(hipStream_t st, const ReduceArgs &a) {
-    if (a.nsys > 0) k_reduce<<<a.nsys, kRed, 0, st>>>(a);
+    if (a.nsys <= 0) return hipSuccess;
+    k_reduce_part<<<a.nsys * kRedChunks, kRed, 0, st>>>(a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_reduce_final<<<(a.nsys + 63) / 64, 64, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_int(hipStream_t st, int *p, int v) {
+    k_set_int<<<1, 1, 0, st>>>(p, v);
     return hipGetLastError();
 }
 

@@ -31,7 +31,8 @@ MTS_NE = 5
 EXPORTS = ("mts_init_system", "mts_destroy_system", "mts_build_cells", "mts_compute_pair_forces",
            "mts_compute_triplet_forces", "mts_respa_step", "mts_sync", "mts_last_error",
            "mts_status_string", "mts_get_grid", "mts_get_cell_index", "mts_count_triplets",
-           "mts_list_triplets", "mts_enable_kernel_timing", "mts_kernel_times")
+           "mts_list_triplets", "mts_enable_kernel_timing", "mts_kernel_times", "mts_set_option")
+MTS_OPT_CYCLE_GRAPH = 1
 
 
 class MTSError(RuntimeError):
@@ -79,6 +80,8 @@ def load_library(path: str = LIB_PATH):
     L.mts_count_triplets.argtypes = [vp, vp, C.POINTER(C.c_int64)]
     L.mts_list_triplets.argtypes = [vp, vp, vp, C.c_int64, C.POINTER(C.c_int64)]
     L.mts_enable_kernel_timing.argtypes = [vp, C.c_int32]
+    L.mts_set_option.argtypes = [vp, C.c_int32, C.c_int64]
+    L.mts_set_option.restype = C.c_int32
     L.mts_kernel_times.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
     for name in ("mts_enable_kernel_timing", "mts_kernel_times", "mts_init_system", "mts_build_cells", "mts_compute_pair_forces",
                  "mts_compute_triplet_forces", "mts_respa_step", "mts_sync", "mts_get_grid",
@@ -217,6 +220,9 @@ class System:
                                                 int(cap), C.byref(c)), "mts_list_triplets")
         total = int(c.value)
         return buf[:min(total, cap)], total
+
+    def set_option(self, option: int, value: int):
+        self._check(self._lib.mts_set_option(self._h, int(option), int(value)), "mts_set_option")
 
     def enable_kernel_timing(self, enable: bool = True):
         self._check(self._lib.mts_enable_kernel_timing(self._h, int(bool(enable))),

@@ -239,3 +239,24 @@ def test_capacity_overflow_is_reported_then_recovers():
         with pytest.raises(mts.MTSError) as e:
             s.sync()
         assert e.value.code == mts.MTS_ERR_CAPACITY
+
+
+@pytest.mark.parametrize("k", [3, 10])
+def test_cycle_graph_matches_eager_bitwise(k):
+    """Captured-graph replay runs the same kernels in the same order as eager launches."""
+    torch = _torch()
+    from paper_2507_11172_amd import mts
+    w = W.plain_fp64()
+    out = []
+    for graph in (1, 0):
+        with _system(w, k=k) as s:
+            s.set_option(mts.MTS_OPT_CYCLE_GRAPH, graph)
+            x, v = _dev(w.x), _dev(w.v)
+            e = torch.zeros((5, 1, 5), dtype=torch.float64, device="cuda")
+            s.respa_step(x, v, 4 * k, e)
+            # a second call reuses the captured graphs
+            s.respa_step(x, v, 4 * k, e)
+            s.sync()
+            out.append((x.cpu(), v.cpu(), e.cpu()))
+    for a, b in zip(out[0], out[1]):
+        assert torch.equal(a, b)
