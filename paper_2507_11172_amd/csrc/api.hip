@@ -1,6 +1,15 @@
 // C ABI of the library (declared in include/mts.h): handle life cycle, validation,
 // buffer ownership and the host-side sequencing of the r-RESPA loop of Sec. 4.1,
-// Algorithm 2.  All device work is enqueued on the caller's stream.
+// Algorithm 2.
+//
+// Two linked-cell grids are kept per system:
+//   * the triplet grid, cell edge >= rc_triplet, used by the triplet kernel;
+//   * the pair grid, cell edge >= rc_pair + skin, used to build a Verlet pair list.
+// Between two full steps of r-RESPA the particles move far less than half the skin, so
+// the pair list built at a full step holds every pair within rc_pair for the next k
+// inner steps; each inner step then costs two launches (fused update, list pair forces)
+// instead of a full rebinning.  A particle that moves more than half the skin raises a
+// device flag that mts_sync reports (the list is rebuilt at every full step anyway).
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -13,37 +22,54 @@
 
 using namespace mts;
 
+namespace {
+
+// One linked-cell binning of all systems.
+struct Grid {
+    std::vector<SysDesc> hsd;
+    SysDesc *sd = nullptr;
+    int ncell = 0;
+    int *sys_of_cell = nullptr;   // [ncell]
+    int *cell_of = nullptr;       // [n] input order
+    int *rank = nullptr;          // [n] atomic arrival rank in the cell
+    int *count = nullptr;         // [ncell] histogram (kept zero between binnings)
+    int *start = nullptr;         // [ncell + 1]
+    int *perm_tmp = nullptr;      // [n] unordered scatter
+    int *perm = nullptr;          // [n] sorted -> input
+    int *inv_perm = nullptr;      // [n] input -> sorted
+    double *xs = nullptr;         // [3][n] sorted wrapped positions
+};
+
+}  // namespace
 
 struct mts_system {
     mts_params p{};
     int nsys = 0;
     int64_t n = 0;
-    int ncell = 0;
-    std::vector<SysDesc> hsd;
     hipStream_t st = nullptr;
     bool fp32 = false;
-    int stage_cap = 0, list_cap = 0, pair_cap = 0;
-    size_t max_lds = 64 * 1024;  // per-workgroup LDS limit of the device
+    Grid gt, gp;                  // triplet grid, pair grid
+    double skin = 0.0;            // pair-list skin in use (0: no list, rebin every step)
+    int stage_cap = 0, list_cap = 0, pair_cap = 0, nl_cap = 0;
+    size_t max_lds = 64 * 1024;   // per-workgroup LDS limit of the device
     double ushift = 0.0;
     std::string err;
 
     // device buffers (library-owned)
-    SysDesc *sd = nullptr;
-    int *sys_of = nullptr;       // [n]
-    int *sys_of_cell = nullptr;  // [ncell]
-    int *cell_of = nullptr, *rank = nullptr, *count = nullptr, *start = nullptr, *perm = nullptr;
-    int *perm_tmp = nullptr;     // [n] unordered scatter before ranking
-    double *red_part = nullptr;  // [nsys][kRedChunks][6] reduction partials
-    double *xs = nullptr;        // [3][n]
+    int *sys_of = nullptr;        // [n]
+    double *red_part = nullptr;   // [nsys][kRedChunks][6] reduction partials
     double *f2a = nullptr, *f2b = nullptr, *f3 = nullptr;  // [n][3] force caches
-    double *pf = nullptr;        // [14][3][n]
-    double *pe = nullptr;        // [n][2]
-    double *ce = nullptr;        // [ncell][2]
-    long long *cc = nullptr;     // [ncell]
-    long long *cnt_sys = nullptr;  // [nsys]
+    double *pf = nullptr;         // [14][3][n] triplet partial slots
+    double *pe = nullptr;         // [n][2] per-particle pair energy/virial (pair-grid order)
+    double *ce = nullptr;         // [ncell_t][2] per-cell triplet energy/virial
+    long long *cc = nullptr;      // [ncell_t] per-cell triplet counts
+    long long *cnt_sys = nullptr; // [nsys]
+    int *nbr = nullptr;           // [n][nl_cap] pair list (pair-grid sorted indices)
+    int *nn = nullptr;            // [n]
+    double *x_ref = nullptr;      // [n][3] wrapped positions at the last list build
     int *flags = nullptr;
     int *row = nullptr;
-    double *e_buf = nullptr;     // [e_rows][nsys][5] energy records of one respa_step
+    double *e_buf = nullptr;      // [e_rows][nsys][5] energy records of one respa_step
     int64_t e_rows = 0;
     unsigned long long *list_n = nullptr;
 
@@ -71,10 +97,16 @@ mts_status hip_fail(mts_system *s, hipError_t e, const char *what) {
     return fail(s, MTS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-#define HIP_TRY(sys, expr)                                   \
-    do {                                                     \
-        hipError_t _e = (expr);                              \
+#define HIP_TRY(sys, expr)                                     \
+    do {                                                       \
+        hipError_t _e = (expr);                                \
         if (_e != hipSuccess) return hip_fail(sys, _e, #expr); \
+    } while (0)
+
+#define MTS_TRY(expr)                \
+    do {                             \
+        mts_status _r = (expr);      \
+        if (_r != MTS_OK) return _r; \
     } while (0)
 
 template <typename T>
@@ -94,6 +126,7 @@ mts_status validate_params(const mts_params *p, std::string &msg) {
     if (!std::isfinite(p->nu)) { msg = "nu must be finite"; return MTS_ERR_INVALID_ARG; }
     if (!finite_pos(p->mass)) { msg = "mass must be > 0"; return MTS_ERR_INVALID_ARG; }
     if (!finite_pos(p->dt)) { msg = "dt must be > 0"; return MTS_ERR_INVALID_ARG; }
+    if (!std::isfinite(p->skin) || p->skin < 0.0) { msg = "skin must be finite and >= 0"; return MTS_ERR_INVALID_ARG; }
     if (p->k < 1) { msg = "k (step-size factor) must be >= 1"; return MTS_ERR_INVALID_ARG; }
     if (p->precision != MTS_FP64 && p->precision != MTS_FP32) { msg = "unknown precision"; return MTS_ERR_INVALID_ARG; }
     if (p->reserved != 0) { msg = "reserved must be 0"; return MTS_ERR_INVALID_ARG; }
@@ -102,49 +135,104 @@ mts_status validate_params(const mts_params *p, std::string &msg) {
 
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
-// Tile capacities.  A cell of volume h^3 holds about rho h^3 particles; sizing assumes a
-// local density of max(0.9, 1.2 x the system's mean), which covers LJ liquids and
-// crystals near the densities of the paper's scenarios, including a liquid slab inside
-// a dilute box.  The triplet tile holds the 14 cells of the forward half stencil, the
-// pair tile all 27 cells, and a forward-neighbour list about half a cutoff sphere.
-// Overflow is detected on the device, reported by mts_sync, and doubles the capacity
-// for the next call.
-void size_tiles(mts_system *s) {
-    double need = 0.0, nl = 0.0;
-    const double rc3 = s->p.rc_triplet;
-    for (const SysDesc &d : s->hsd) {
+// Grid with cell edges of at least hmin (margin against rounding so that any pair within
+// the cutoff lies in adjacent cells), at least 2 cells per edge.
+mts_status make_grid(Grid &g, const std::vector<SysDesc> &base, double hmin) {
+    g.hsd = base;
+    int64_t cell0 = 0;
+    for (SysDesc &d : g.hsd) {
+        for (int k = 0; k < 3; ++k) {
+            d.nc[k] = (int)std::floor(d.L[k] / hmin);
+            if (d.nc[k] < 2) return MTS_ERR_BOX_TOO_SMALL;
+            d.q[k] = (double)d.nc[k] / d.L[k];
+        }
+        d.ncell = d.nc[0] * d.nc[1] * d.nc[2];
+        d.cell0 = (int)cell0;
+        cell0 += d.ncell;
+    }
+    if (cell0 >= (int64_t)1 << 30) return MTS_ERR_UNSUPPORTED;
+    g.ncell = (int)cell0;
+    return MTS_OK;
+}
+
+double max_cell_volume(const Grid &g, double &rho_max) {
+    double v = 0.0;
+    rho_max = 0.0;
+    for (const SysDesc &d : g.hsd) {
         const double vol = d.L[0] * d.L[1] * d.L[2];
         const double rho = std::max(0.9, 1.2 * (double)d.n / vol);
-        const double cellv = (d.L[0] / d.nc[0]) * (d.L[1] / d.nc[1]) * (d.L[2] / d.nc[2]);
-        need = std::max(need, rho * cellv);
-        nl = std::max(nl, rho * (2.0 / 3.0) * M_PI * rc3 * rc3 * rc3);
+        rho_max = std::max(rho_max, rho);
+        v = std::max(v, rho * (d.L[0] / d.nc[0]) * (d.L[1] / d.nc[1]) * (d.L[2] / d.nc[2]));
     }
-    s->stage_cap = std::min(2048, round_up((int)std::ceil(kNumHalf * need * 1.1) + 16, 32));
-    s->pair_cap = std::min(2048, round_up((int)std::ceil(kNumFull * need * 1.1) + 16, 32));
-    s->list_cap = std::min(1024, round_up((int)std::ceil(1.6 * nl) + 16, 32));
+    return v;
+}
+
+// Tile and list capacities.  A cell of volume h^3 holds about rho h^3 particles; sizing
+// assumes a local density of max(0.9, 1.2 x the system's mean), which covers LJ liquids
+// and crystals near the densities of the paper's scenarios, including a liquid slab
+// inside a dilute box.  The triplet tile holds the 14 cells of the forward half stencil
+// and the pair tile all 27 cells of the pair grid; a forward-neighbour list holds about
+// half a cutoff sphere and a pair-list row a whole (rc + skin) sphere.  Overflow is
+// detected on the device, reported by mts_sync, and doubles the capacity for the next
+// call.
+void size_tiles(mts_system *s) {
+    double rho_t, rho_p;
+    const double vt = max_cell_volume(s->gt, rho_t);
+    const double vp = max_cell_volume(s->gp, rho_p);
+    const double rc3 = s->p.rc_triplet, rv = s->p.rc_pair + s->skin;
+    s->stage_cap = std::min(2048, round_up((int)std::ceil(kNumHalf * vt * 1.1) + 16, 32));
+    s->pair_cap = std::min(2048, round_up((int)std::ceil(kNumFull * vp * 1.1) + 16, 32));
+    s->list_cap = std::min(1024, round_up((int)std::ceil(1.6 * rho_t * (2.0 / 3.0) * M_PI * rc3 * rc3 * rc3) + 16, 32));
+    s->nl_cap = std::min(2048, round_up((int)std::ceil(1.3 * rho_p * (4.0 / 3.0) * M_PI * rv * rv * rv) + 16, 32));
+}
+
+mts_status alloc_grid(mts_system *s, Grid &g) {
+    const int64_t n = s->n;
+    HIP_TRY(s, dalloc(&g.sd, s->nsys));
+    HIP_TRY(s, dalloc(&g.sys_of_cell, g.ncell));
+    HIP_TRY(s, dalloc(&g.cell_of, n));
+    HIP_TRY(s, dalloc(&g.rank, n));
+    HIP_TRY(s, dalloc(&g.count, g.ncell));
+    HIP_TRY(s, dalloc(&g.start, (size_t)g.ncell + 1));
+    HIP_TRY(s, dalloc(&g.perm_tmp, n));
+    HIP_TRY(s, dalloc(&g.perm, n));
+    HIP_TRY(s, dalloc(&g.inv_perm, n));
+    HIP_TRY(s, dalloc(&g.xs, 3 * n));
+    std::vector<int> soc(g.ncell);
+    for (int q = 0; q < s->nsys; ++q) {
+        const SysDesc &d = g.hsd[q];
+        for (int c = 0; c < d.ncell; ++c) soc[d.cell0 + c] = q;
+    }
+    HIP_TRY(s, hipMemcpy(g.sd, g.hsd.data(), sizeof(SysDesc) * s->nsys, hipMemcpyHostToDevice));
+    HIP_TRY(s, hipMemcpy(g.sys_of_cell, soc.data(), sizeof(int) * g.ncell, hipMemcpyHostToDevice));
+    HIP_TRY(s, hipMemset(g.count, 0, sizeof(int) * g.ncell));
+    return MTS_OK;
+}
+
+void free_grid(Grid &g) {
+    void *ptrs[] = {g.sd, g.sys_of_cell, g.cell_of, g.rank, g.count, g.start, g.perm_tmp,
+                    g.perm, g.inv_perm, g.xs};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
 }
 
 mts_status alloc_all(mts_system *s) {
     const int64_t n = s->n;
-    HIP_TRY(s, dalloc(&s->sd, s->nsys));
+    MTS_TRY(alloc_grid(s, s->gt));
+    MTS_TRY(alloc_grid(s, s->gp));
     HIP_TRY(s, dalloc(&s->sys_of, n));
-    HIP_TRY(s, dalloc(&s->sys_of_cell, s->ncell));
-    HIP_TRY(s, dalloc(&s->cell_of, n));
-    HIP_TRY(s, dalloc(&s->rank, n));
-    HIP_TRY(s, dalloc(&s->count, s->ncell));
-    HIP_TRY(s, dalloc(&s->start, (size_t)s->ncell + 1));
-    HIP_TRY(s, dalloc(&s->perm, n));
-    HIP_TRY(s, dalloc(&s->perm_tmp, n));
     HIP_TRY(s, dalloc(&s->red_part, (size_t)s->nsys * kRedChunks * 6));
-    HIP_TRY(s, dalloc(&s->xs, 3 * n));
     HIP_TRY(s, dalloc(&s->f2a, 3 * n));
     HIP_TRY(s, dalloc(&s->f2b, 3 * n));
     HIP_TRY(s, dalloc(&s->f3, 3 * n));
     HIP_TRY(s, dalloc(&s->pf, (size_t)kNumHalf * 3 * n));
     HIP_TRY(s, dalloc(&s->pe, 2 * n));
-    HIP_TRY(s, dalloc(&s->ce, 2 * (size_t)s->ncell));
-    HIP_TRY(s, dalloc(&s->cc, s->ncell));
+    HIP_TRY(s, dalloc(&s->ce, 2 * (size_t)s->gt.ncell));
+    HIP_TRY(s, dalloc(&s->cc, s->gt.ncell));
     HIP_TRY(s, dalloc(&s->cnt_sys, s->nsys));
+    HIP_TRY(s, dalloc(&s->nbr, (size_t)n * s->nl_cap));
+    HIP_TRY(s, dalloc(&s->nn, n));
+    HIP_TRY(s, dalloc(&s->x_ref, 3 * n));
     HIP_TRY(s, dalloc(&s->flags, 1));
     HIP_TRY(s, dalloc(&s->row, 1));
     HIP_TRY(s, dalloc(&s->list_n, 1));
@@ -154,19 +242,40 @@ mts_status alloc_all(mts_system *s) {
     HIP_TRY(s, hipEventCreateWithFlags(&s->ev_in, hipEventDisableTiming));
     HIP_TRY(s, hipEventCreateWithFlags(&s->ev_out, hipEventDisableTiming));
 
-    std::vector<int> so(n > 0 ? n : 1), soc(s->ncell);
+    std::vector<int> so(n > 0 ? n : 1);
     for (int q = 0; q < s->nsys; ++q) {
-        const SysDesc &d = s->hsd[q];
+        const SysDesc &d = s->gt.hsd[q];
         for (int64_t i = 0; i < d.n; ++i) so[d.p0 + i] = q;
-        for (int c = 0; c < d.ncell; ++c) soc[d.cell0 + c] = q;
     }
-    HIP_TRY(s, hipMemcpy(s->sd, s->hsd.data(), sizeof(SysDesc) * s->nsys, hipMemcpyHostToDevice));
     if (n > 0) HIP_TRY(s, hipMemcpy(s->sys_of, so.data(), sizeof(int) * n, hipMemcpyHostToDevice));
-    HIP_TRY(s, hipMemcpy(s->sys_of_cell, soc.data(), sizeof(int) * s->ncell, hipMemcpyHostToDevice));
-    HIP_TRY(s, hipMemset(s->count, 0, sizeof(int) * s->ncell));
     HIP_TRY(s, hipMemset(s->flags, 0, sizeof(int)));
     HIP_TRY(s, hipMemset(s->pf, 0, sizeof(double) * kNumHalf * 3 * (n > 0 ? n : 1)));
     return MTS_OK;
+}
+
+void drop_graphs(mts_system *s) {
+    for (auto &g : s->gexec)
+        for (hipGraphExec_t &e : g)
+            if (e) {
+                (void)hipGraphExecDestroy(e);
+                e = nullptr;
+            }
+}
+
+void free_all(mts_system *s) {
+    drop_graphs(s);
+    if (s->ev_in) (void)hipEventDestroy(s->ev_in);
+    if (s->ev_out) (void)hipEventDestroy(s->ev_out);
+    if (s->ist) (void)hipStreamDestroy(s->ist);
+    for (int c = 0; c < 2; ++c)
+        for (hipEvent_t e : s->ev_pool[c]) (void)hipEventDestroy(e);
+    free_grid(s->gt);
+    free_grid(s->gp);
+    void *ptrs[] = {s->sys_of, s->red_part, s->f2a, s->f2b, s->f3, s->pf, s->pe, s->ce, s->cc,
+                    s->cnt_sys, s->nbr, s->nn, s->x_ref, s->flags, s->row, s->e_buf, s->list_n,
+                    s->xi, s->vi};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
 }
 
 // Records a start event before a timed kernel launch; returns the slot or -1.
@@ -189,51 +298,62 @@ void timer_end(mts_system *s, int cls, long slot) {
     if (slot >= 0) (void)hipEventRecord(s->ev_pool[cls][slot + 1], s->st);
 }
 
-void drop_graphs(mts_system *s) {
-    for (auto &g : s->gexec)
-        for (hipGraphExec_t &e : g)
-            if (e) {
-                (void)hipGraphExecDestroy(e);
-                e = nullptr;
-            }
-}
+// ---- enqueue helpers (all on s->st)
 
-void free_all(mts_system *s) {
-    drop_graphs(s);
-    if (s->ev_in) (void)hipEventDestroy(s->ev_in);
-    if (s->ev_out) (void)hipEventDestroy(s->ev_out);
-    if (s->ist) (void)hipStreamDestroy(s->ist);
-    for (int c = 0; c < 2; ++c)
-        for (hipEvent_t e : s->ev_pool[c]) (void)hipEventDestroy(e);
-    void *ptrs[] = {s->sd, s->sys_of, s->sys_of_cell, s->cell_of, s->rank, s->count, s->start,
-                    s->perm, s->xs, s->f2a, s->f2b, s->f3, s->pf, s->pe, s->ce, s->cc,
-                    s->cnt_sys, s->flags, s->row, s->e_buf, s->list_n, s->perm_tmp,
-                    s->red_part, s->xi, s->vi};
-    for (void *p : ptrs)
-        if (p) (void)hipFree(p);
-}
-
-// ---- enqueue helpers
-mts_status enqueue_bin(mts_system *s, const double *x) {
-    HIP_TRY(s, launch_bin_count(s->st, s->n, x, s->sd, s->sys_of, s->cell_of, s->rank, s->count,
-                                s->flags));
-    HIP_TRY(s, launch_scan(s->st, s->ncell, s->count, s->start, s->n));
-    HIP_TRY(s, launch_bin_scatter(s->st, s->n, s->cell_of, s->rank, s->start, s->perm_tmp));
-    HIP_TRY(s, launch_rank_gather(s->st, s->n, s->perm_tmp, s->cell_of, s->start, x, s->sd,
-                                  s->sys_of, s->perm, s->xs));
+// Counting sort of x into grid g; with_ref also records the wrapped positions as the
+// reference of the next pair-list build.
+mts_status enqueue_bin(mts_system *s, Grid &g, const double *x, bool with_ref) {
+    HIP_TRY(s, launch_bin_count(s->st, s->n, x, g.sd, s->sys_of, g.cell_of, g.rank, g.count, s->flags));
+    HIP_TRY(s, launch_scan(s->st, g.ncell, g.count, g.start, s->n));
+    HIP_TRY(s, launch_bin_scatter(s->st, s->n, g.cell_of, g.rank, g.start, g.perm_tmp));
+    HIP_TRY(s, launch_rank_gather(s->st, s->n, g.perm_tmp, g.cell_of, g.start, x, g.sd, s->sys_of,
+                                  g.perm, g.inv_perm, g.xs, with_ref ? s->x_ref : nullptr));
     return MTS_OK;
 }
 
-mts_status enqueue_pair(mts_system *s, double *f2) {
+// F2 from the pair grid's cell tiles; with build_list also (re)builds the pair list.
+mts_status enqueue_pair(mts_system *s, double *f2, bool build_list) {
+    const Grid &g = s->gp;
     PairArgs a{};
-    a.ncell = s->ncell;
-    a.sys_of_cell = s->sys_of_cell;
+    a.ncell = g.ncell;
+    a.sys_of_cell = g.sys_of_cell;
     a.stage_cap = s->pair_cap;
     a.n = s->n;
-    a.xs = s->xs;
-    a.perm = s->perm;
-    a.start = s->start;
-    a.sd = s->sd;
+    a.xs = g.xs;
+    a.perm = g.perm;
+    a.start = g.start;
+    a.sd = g.sd;
+    a.sys_of = s->sys_of;
+    a.f = f2;
+    a.pe = s->pe;
+    a.eps = s->p.epsilon;
+    a.sigma2 = s->p.sigma * s->p.sigma;
+    a.rc2 = s->p.rc_pair * s->p.rc_pair;
+    a.ushift = s->ushift;
+    a.flags = s->flags;
+    if (build_list) {
+        const double rv = s->p.rc_pair + s->skin;
+        a.nbr = s->nbr;
+        a.nn = s->nn;
+        a.nl_cap = s->nl_cap;
+        a.rcv2 = rv * rv;
+    }
+    const long ts = timer_begin(s, 1);
+    HIP_TRY(s, launch_pair(s->st, a, s->fp32));
+    timer_end(s, 1, ts);
+    return MTS_OK;
+}
+
+// F2 from the pair list (positions in the pair grid's sorted order, updated by k_int).
+mts_status enqueue_pair_list(mts_system *s, double *f2) {
+    PairListArgs a{};
+    a.n = s->n;
+    a.xs = s->gp.xs;
+    a.perm = s->gp.perm;
+    a.nbr = s->nbr;
+    a.nn = s->nn;
+    a.nl_cap = s->nl_cap;
+    a.sd = s->gp.sd;
     a.sys_of = s->sys_of;
     a.f = f2;
     a.pe = s->pe;
@@ -243,19 +363,20 @@ mts_status enqueue_pair(mts_system *s, double *f2) {
     a.ushift = s->ushift;
     a.flags = s->flags;
     const long ts = timer_begin(s, 1);
-    HIP_TRY(s, launch_pair(s->st, a, s->fp32));
+    HIP_TRY(s, launch_pair_list(s->st, a, s->fp32));
     timer_end(s, 1, ts);
     return MTS_OK;
 }
 
 mts_status enqueue_triplet(mts_system *s, double *f3, int *list_ijk, long long list_rows) {
+    const Grid &g = s->gt;
     TripletArgs a{};
-    a.ncell = s->ncell;
-    a.xs = s->xs;
-    a.start = s->start;
-    a.sd = s->sd;
-    a.sys_of_cell = s->sys_of_cell;
-    a.perm = s->perm;
+    a.ncell = g.ncell;
+    a.xs = g.xs;
+    a.start = g.start;
+    a.sd = g.sd;
+    a.sys_of_cell = g.sys_of_cell;
+    a.perm = g.perm;
     a.pf = s->pf;
     a.ce = s->ce;
     a.cc = s->cc;
@@ -271,7 +392,7 @@ mts_status enqueue_triplet(mts_system *s, double *f3, int *list_ijk, long long l
     const long ts = timer_begin(s, 0);
     HIP_TRY(s, launch_triplet(s->st, a, s->fp32, list_ijk != nullptr));
     timer_end(s, 0, ts);
-    if (f3) HIP_TRY(s, launch_triplet_gather(s->st, s->n, s->pf, s->perm, f3, s->flags));
+    if (f3) HIP_TRY(s, launch_triplet_gather(s->st, s->n, s->pf, g.perm, f3, s->flags));
     return MTS_OK;
 }
 
@@ -279,7 +400,7 @@ mts_status enqueue_reduce(mts_system *s, const double *v, bool pair, bool trip, 
                           int stride, const int *row, long long *count_out) {
     ReduceArgs a{};
     a.nsys = s->nsys;
-    a.sd = s->sd;
+    a.sd = s->gt.sd;
     a.v = v;
     a.half_mass = 0.5 * s->p.mass;
     a.pe = pair ? s->pe : nullptr;
@@ -295,163 +416,76 @@ mts_status enqueue_reduce(mts_system *s, const double *v, bool pair, bool trip, 
     return MTS_OK;
 }
 
-#define MTS_TRY(expr)                 \
-    do {                              \
-        mts_status _r = (expr);       \
-        if (_r != MTS_OK) return _r;  \
-    } while (0)
-
-double lj_energy(double r2, double eps, double sigma) {
-    const double s2 = sigma * sigma / r2, s6 = s2 * s2 * s2;
-    return 4.0 * eps * (s6 * s6 - s6);
-}
-
-}  // namespace
-
-extern "C" {
-
-const char *mts_status_string(int32_t status) {
-    switch (status) {
-        case MTS_OK: return "MTS_OK";
-        case MTS_ERR_INVALID_ARG: return "MTS_ERR_INVALID_ARG";
-        case MTS_ERR_BOX_TOO_SMALL: return "MTS_ERR_BOX_TOO_SMALL";
-        case MTS_ERR_NOT_MULTIPLE_OF_K: return "MTS_ERR_NOT_MULTIPLE_OF_K";
-        case MTS_ERR_CAPACITY: return "MTS_ERR_CAPACITY";
-        case MTS_ERR_NONFINITE: return "MTS_ERR_NONFINITE";
-        case MTS_ERR_HIP: return "MTS_ERR_HIP";
-        case MTS_ERR_OOM: return "MTS_ERR_OOM";
-        case MTS_ERR_UNSUPPORTED: return "MTS_ERR_UNSUPPORTED";
-        default: return "unknown status";
-    }
-}
-
-mts_status mts_init_system(const mts_params *params, int32_t n_systems, const int64_t *n_particles,
-                           const double *box, void *stream, mts_system **out) {
-    if (!out) return MTS_ERR_INVALID_ARG;
-    *out = nullptr;
-    std::string msg;
-    mts_status v = validate_params(params, msg);
-    if (v != MTS_OK) return v;
-    if (n_systems < 1 || !n_particles || !box) return MTS_ERR_INVALID_ARG;
-    mts_system *s = new mts_system();
-    s->p = *params;
-    s->nsys = n_systems;
-    s->st = (hipStream_t)stream;
-    s->fp32 = params->precision == MTS_FP32;
-    const double rc_max = std::max(params->rc_pair, params->rc_triplet);
-    // cells strictly wider than the largest cutoff, with margin for rounding, so that any
-    // interacting pair lies in adjacent cells
-    const double hmin = rc_max * (1.0 + 1e-9);
-    int64_t p0 = 0;
-    int64_t cell0 = 0;
-    for (int q = 0; q < n_systems; ++q) {
-        SysDesc d{};
-        if (n_particles[q] < 0) { delete s; return MTS_ERR_INVALID_ARG; }
-        for (int k = 0; k < 3; ++k) {
-            const double L = box[3 * q + k];
-            if (!finite_pos(L)) { delete s; return MTS_ERR_INVALID_ARG; }
-            if (!(L > 2.0 * hmin)) { delete s; return MTS_ERR_BOX_TOO_SMALL; }
-            d.L[k] = L;
-            d.nc[k] = (int)std::floor(L / hmin);
-            if (d.nc[k] < 2) { delete s; return MTS_ERR_BOX_TOO_SMALL; }
-            d.q[k] = (double)d.nc[k] / L;
-        }
-        d.ncell = d.nc[0] * d.nc[1] * d.nc[2];
-        d.cell0 = (int)cell0;
-        d.p0 = p0;
-        d.n = n_particles[q];
-        p0 += d.n;
-        cell0 += d.ncell;
-        s->hsd.push_back(d);
-    }
-    if (p0 >= (int64_t)1 << 30 || cell0 >= (int64_t)1 << 30) { delete s; return MTS_ERR_UNSUPPORTED; }
-    s->n = p0;
-    s->ncell = (int)cell0;
-    s->ushift = params->lj_energy_shift
-                    ? lj_energy(params->rc_pair * params->rc_pair, params->epsilon, params->sigma)
-                    : 0.0;
-    size_tiles(s);
-    {
-        int dev = 0, lds = 0;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
-            lds > 0)
-            s->max_lds = (size_t)lds;
-        // keep room for the kernels' static LDS
-        s->max_lds = s->max_lds > 1024 ? s->max_lds - 1024 : s->max_lds;
-        if (configure_kernel_lds(s->max_lds) != hipSuccess) s->max_lds = 64 * 1024 - 1024;
-        (void)hipGetLastError();  // do not leave a failed attribute call as a sticky error
-    }
-    if (triplet_lds_bytes(s->stage_cap, s->list_cap) > s->max_lds ||
-        pair_lds_bytes(s->pair_cap) > s->max_lds) {
-        free_all(s);
-        delete s;
-        return MTS_ERR_UNSUPPORTED;
-    }
-    mts_status a = alloc_all(s);
-    if (a != MTS_OK) {
-        free_all(s);
-        delete s;
-        return a == MTS_ERR_HIP ? MTS_ERR_OOM : a;
-    }
-    *out = s;
-    return MTS_OK;
-}
-
-void mts_destroy_system(mts_system *sys) {
-    if (!sys) return;
-    if (sys->ist) (void)hipStreamSynchronize(sys->ist);
-    (void)hipStreamSynchronize(sys->st);
-    free_all(sys);
-    delete sys;
-}
-
-mts_status mts_build_cells(mts_system *sys, const double *x) {
-    if (!sys) return MTS_ERR_INVALID_ARG;
-    if (!x && sys->n > 0) return fail(sys, MTS_ERR_INVALID_ARG, "x is NULL");
-    return enqueue_bin(sys, x);
-}
-
-mts_status mts_compute_pair_forces(mts_system *sys, const double *x, double *f2, double *ew) {
-    if (!sys) return MTS_ERR_INVALID_ARG;
-    if ((!x || !f2) && sys->n > 0) return fail(sys, MTS_ERR_INVALID_ARG, "x or f2 is NULL");
-    MTS_TRY(enqueue_bin(sys, x));
-    MTS_TRY(enqueue_pair(sys, f2));
-    if (ew) MTS_TRY(enqueue_reduce(sys, nullptr, true, false, ew, 2, nullptr, nullptr));
-    return MTS_OK;
-}
-
-mts_status mts_compute_triplet_forces(mts_system *sys, const double *x, double *f3, double *ew) {
-    if (!sys) return MTS_ERR_INVALID_ARG;
-    if ((!x || !f3) && sys->n > 0) return fail(sys, MTS_ERR_INVALID_ARG, "x or f3 is NULL");
-    MTS_TRY(enqueue_bin(sys, x));
-    MTS_TRY(enqueue_triplet(sys, f3, nullptr, 0));
-    if (ew) MTS_TRY(enqueue_reduce(sys, nullptr, false, true, ew, 2, nullptr, nullptr));
-    return MTS_OK;
-}
-
-// One outer cycle of Algorithm 2 on the internal copies xi, vi: k inner steps (F3 half
-// kick at the first, drift + wrap, binning, F2, F2 kick), then F3 at the full step, its
-// half kick and, if requested, the energy record.  f2a holds F2 of the cycle's first
-// position; after the cycle F2 of the last position is in f2a when k is even, f2b when odd.
-mts_status enqueue_cycle(mts_system *s, double *f2a, double *f2b, bool energies) {
-    const int k = s->p.k;
-    const int64_t n3 = 3 * s->n;
+// Fused update: see IntArgs.  drift_mode 0: no drift; 1: drift, update the pair-list
+// positions and check the skin; 2: drift only (a rebinning follows).
+mts_status enqueue_int(mts_system *s, const double *f2prev, const double *f2cur, bool kick2,
+                       bool kick3_end, bool kick3_start, int drift_mode) {
     const double dt = s->p.dt, m = s->p.mass;
-    const double c3 = (dt * (double)k) / (2.0 * m);
-    const double cx = (dt * dt) / (2.0 * m);
-    const double c2 = dt / (2.0 * m);
-    double *f2cur = f2a, *f2nxt = f2b;
-    for (int i = 0; i < k; ++i) {
-        if (i == 0) HIP_TRY(s, launch_kick(s->st, n3, s->vi, s->f3, c3));
-        HIP_TRY(s, launch_drift(s->st, s->n, s->xi, s->vi, f2cur, dt, cx, s->sd, s->sys_of));
-        MTS_TRY(enqueue_bin(s, s->xi));
-        MTS_TRY(enqueue_pair(s, f2nxt));
-        HIP_TRY(s, launch_kick2(s->st, n3, s->vi, f2cur, f2nxt, c2));
-        std::swap(f2cur, f2nxt);
+    IntArgs a{};
+    a.n = s->n;
+    a.x = s->xi;
+    a.v = s->vi;
+    a.f2prev = f2prev;
+    a.f2cur = f2cur;
+    a.f3 = s->f3;
+    a.c2 = dt / (2.0 * m);
+    a.c3 = (dt * (double)s->p.k) / (2.0 * m);
+    a.dt = dt;
+    a.cx = (dt * dt) / (2.0 * m);
+    a.kick2 = kick2;
+    a.kick3_end = kick3_end;
+    a.kick3_start = kick3_start;
+    a.drift = drift_mode != 0;
+    a.sd = s->gt.sd;
+    a.sys_of = s->sys_of;
+    if (drift_mode == 1) {
+        a.inv_perm = s->gp.inv_perm;
+        a.xs = s->gp.xs;
+        a.x_ref = s->x_ref;
+        a.half_skin2 = 0.25 * s->skin * s->skin;
     }
+    a.flags = s->flags;
+    HIP_TRY(s, launch_int(s->st, a));
+    return MTS_OK;
+}
+
+// Forces at the current internal positions, binning both grids: F2 into f2 (and a new
+// pair list), F3 into s->f3.
+mts_status enqueue_full_forces(mts_system *s, double *f2) {
+    MTS_TRY(enqueue_bin(s, s->gp, s->xi, true));
+    MTS_TRY(enqueue_pair(s, f2, s->skin > 0.0));
+    MTS_TRY(enqueue_bin(s, s->gt, s->xi, false));
     MTS_TRY(enqueue_triplet(s, s->f3, nullptr, 0));
-    HIP_TRY(s, launch_kick(s->st, n3, s->vi, s->f3, c3));
+    return MTS_OK;
+}
+
+// One outer cycle of Algorithm 2 on the internal copies xi, vi.  On entry F2 of the
+// cycle's first position is in f2[0] and F3 in s->f3; on exit F2 of the last position is
+// in f2[k % 2] and F3 of it in s->f3, with the closing F3 half kick applied.
+//   inner step i < k-1:  k_int (kick2 of step i-1 | opening F3 kick at i = 0, drift,
+//                         list positions, skin check), F2 from the pair list;
+//   last step i = k-1:   k_int (kick2, drift), rebin both grids, F2 + new pair list,
+//                         F3, then k_int (last kick2 and the closing F3 kick) and the
+//                         energy record of the full step.
+// Without a pair list (skin 0) every step rebins the pair grid instead.
+mts_status enqueue_cycle(mts_system *s, double *f2_0, double *f2_1, bool energies) {
+    const int k = s->p.k;
+    double *f2[2] = {f2_0, f2_1};
+    const bool list = s->skin > 0.0;
+    for (int i = 0; i < k; ++i) {
+        double *prev = f2[(i + 1) & 1], *cur = f2[i & 1], *next = f2[(i + 1) & 1];
+        const bool last = i == k - 1;
+        MTS_TRY(enqueue_int(s, prev, cur, i > 0, false, i == 0, (last || !list) ? 2 : 1));
+        if (last) {
+            MTS_TRY(enqueue_full_forces(s, next));
+        } else if (list) {
+            MTS_TRY(enqueue_pair_list(s, next));
+        } else {
+            MTS_TRY(enqueue_bin(s, s->gp, s->xi, false));
+            MTS_TRY(enqueue_pair(s, next, false));
+        }
+    }
+    MTS_TRY(enqueue_int(s, f2[(k - 1) & 1], f2[k & 1], true, true, false, 0));
     if (energies) {
         MTS_TRY(enqueue_reduce(s, s->vi, true, true, s->e_buf, kNE, s->row, nullptr));
         HIP_TRY(s, launch_bump_row(s->st, s->row));
@@ -496,9 +530,7 @@ mts_status respa_internal(mts_system *s, double *x, double *v, int64_t n_iter, d
         HIP_TRY(s, hipMemcpyAsync(s->vi, v, bytes, hipMemcpyDeviceToDevice, s->st));
     }
     // Algorithm 2, lines 1-2: F2(x^0), F3(x^0); energies of x^0 in row 0
-    MTS_TRY(enqueue_bin(s, s->xi));
-    MTS_TRY(enqueue_pair(s, s->f2a));
-    MTS_TRY(enqueue_triplet(s, s->f3, nullptr, 0));
+    MTS_TRY(enqueue_full_forces(s, s->f2a));
     if (energies) {
         HIP_TRY(s, launch_set_int(s->st, s->row, 0));
         MTS_TRY(enqueue_reduce(s, s->vi, true, true, s->e_buf, kNE, s->row, nullptr));
@@ -521,6 +553,143 @@ mts_status respa_internal(mts_system *s, double *x, double *v, int64_t n_iter, d
     if (energies)
         HIP_TRY(s, hipMemcpyAsync(e_full, s->e_buf, sizeof(double) * (size_t)(cycles + 1) * s->nsys * kNE,
                                   hipMemcpyDeviceToDevice, s->st));
+    return MTS_OK;
+}
+
+double lj_energy(double r2, double eps, double sigma) {
+    const double s2 = sigma * sigma / r2, s6 = s2 * s2 * s2;
+    return 4.0 * eps * (s6 * s6 - s6);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *mts_status_string(int32_t status) {
+    switch (status) {
+        case MTS_OK: return "MTS_OK";
+        case MTS_ERR_INVALID_ARG: return "MTS_ERR_INVALID_ARG";
+        case MTS_ERR_BOX_TOO_SMALL: return "MTS_ERR_BOX_TOO_SMALL";
+        case MTS_ERR_NOT_MULTIPLE_OF_K: return "MTS_ERR_NOT_MULTIPLE_OF_K";
+        case MTS_ERR_CAPACITY: return "MTS_ERR_CAPACITY";
+        case MTS_ERR_NONFINITE: return "MTS_ERR_NONFINITE";
+        case MTS_ERR_HIP: return "MTS_ERR_HIP";
+        case MTS_ERR_OOM: return "MTS_ERR_OOM";
+        case MTS_ERR_UNSUPPORTED: return "MTS_ERR_UNSUPPORTED";
+        default: return "unknown status";
+    }
+}
+
+mts_status mts_init_system(const mts_params *params, int32_t n_systems, const int64_t *n_particles,
+                           const double *box, void *stream, mts_system **out) {
+    if (!out) return MTS_ERR_INVALID_ARG;
+    *out = nullptr;
+    std::string msg;
+    mts_status v = validate_params(params, msg);
+    if (v != MTS_OK) return v;
+    if (n_systems < 1 || !n_particles || !box) return MTS_ERR_INVALID_ARG;
+    const double rc_max = std::max(params->rc_pair, params->rc_triplet);
+    // cells strictly wider than the cutoff, with margin for rounding, so that any
+    // interacting pair lies in adjacent cells
+    const double margin = 1.0 + 1e-9;
+    std::vector<SysDesc> base;
+    int64_t p0 = 0;
+    double lmin = INFINITY;
+    for (int q = 0; q < n_systems; ++q) {
+        SysDesc d{};
+        if (n_particles[q] < 0) return MTS_ERR_INVALID_ARG;
+        for (int k = 0; k < 3; ++k) {
+            const double L = box[3 * q + k];
+            if (!finite_pos(L)) return MTS_ERR_INVALID_ARG;
+            if (!(L > 2.0 * rc_max * margin)) return MTS_ERR_BOX_TOO_SMALL;
+            d.L[k] = L;
+            lmin = std::min(lmin, L);
+        }
+        d.p0 = p0;
+        d.n = n_particles[q];
+        p0 += d.n;
+        base.push_back(d);
+    }
+    if (p0 >= (int64_t)1 << 30) return MTS_ERR_UNSUPPORTED;
+
+    mts_system *s = new mts_system();
+    s->p = *params;
+    s->nsys = n_systems;
+    s->n = p0;
+    s->st = (hipStream_t)stream;
+    s->fp32 = params->precision == MTS_FP32;
+    // Pair-list skin: the requested one (default 0.3 + 0.01 k sigma), shrunk so that
+    // every box edge exceeds 2 (rc + skin) -- a pair then has one image within the list
+    // radius.  Below 0.05 sigma the list is not worth it: every step rebins instead.
+    double skin = params->skin > 0.0 ? params->skin : (0.3 + 0.01 * params->k) * params->sigma;
+    skin = std::min(skin, 0.4999 * lmin / margin - params->rc_pair);
+    s->skin = skin >= 0.05 * params->sigma ? skin : 0.0;
+    mts_status g1 = make_grid(s->gt, base, params->rc_triplet * margin);
+    mts_status g2 = g1 == MTS_OK ? make_grid(s->gp, base, (params->rc_pair + s->skin) * margin) : g1;
+    if (g2 != MTS_OK) {
+        delete s;
+        return g2;
+    }
+    s->ushift = params->lj_energy_shift
+                    ? lj_energy(params->rc_pair * params->rc_pair, params->epsilon, params->sigma)
+                    : 0.0;
+    size_tiles(s);
+    {
+        int dev = 0, lds = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+            lds > 0)
+            s->max_lds = (size_t)lds;
+        // keep room for the kernels' static LDS
+        s->max_lds = s->max_lds > 1024 ? s->max_lds - 1024 : s->max_lds;
+        if (configure_kernel_lds(s->max_lds) != hipSuccess) s->max_lds = 64 * 1024 - 1024;
+        (void)hipGetLastError();  // do not leave a failed attribute call as a sticky error
+    }
+    if (triplet_lds_bytes(s->stage_cap, s->list_cap) > s->max_lds ||
+        pair_lds_bytes(s->pair_cap) > s->max_lds) {
+        delete s;
+        return MTS_ERR_UNSUPPORTED;
+    }
+    mts_status a = alloc_all(s);
+    if (a != MTS_OK) {
+        free_all(s);
+        delete s;
+        return a == MTS_ERR_HIP ? MTS_ERR_OOM : a;
+    }
+    *out = s;
+    return MTS_OK;
+}
+
+void mts_destroy_system(mts_system *sys) {
+    if (!sys) return;
+    if (sys->ist) (void)hipStreamSynchronize(sys->ist);
+    (void)hipStreamSynchronize(sys->st);
+    free_all(sys);
+    delete sys;
+}
+
+mts_status mts_build_cells(mts_system *sys, const double *x) {
+    if (!sys) return MTS_ERR_INVALID_ARG;
+    if (!x && sys->n > 0) return fail(sys, MTS_ERR_INVALID_ARG, "x is NULL");
+    MTS_TRY(enqueue_bin(sys, sys->gp, x, false));
+    return enqueue_bin(sys, sys->gt, x, false);
+}
+
+mts_status mts_compute_pair_forces(mts_system *sys, const double *x, double *f2, double *ew) {
+    if (!sys) return MTS_ERR_INVALID_ARG;
+    if ((!x || !f2) && sys->n > 0) return fail(sys, MTS_ERR_INVALID_ARG, "x or f2 is NULL");
+    MTS_TRY(enqueue_bin(sys, sys->gp, x, false));
+    MTS_TRY(enqueue_pair(sys, f2, false));
+    if (ew) MTS_TRY(enqueue_reduce(sys, nullptr, true, false, ew, 2, nullptr, nullptr));
+    return MTS_OK;
+}
+
+mts_status mts_compute_triplet_forces(mts_system *sys, const double *x, double *f3, double *ew) {
+    if (!sys) return MTS_ERR_INVALID_ARG;
+    if ((!x || !f3) && sys->n > 0) return fail(sys, MTS_ERR_INVALID_ARG, "x or f3 is NULL");
+    MTS_TRY(enqueue_bin(sys, sys->gt, x, false));
+    MTS_TRY(enqueue_triplet(sys, f3, nullptr, 0));
+    if (ew) MTS_TRY(enqueue_reduce(sys, nullptr, false, true, ew, 2, nullptr, nullptr));
     return MTS_OK;
 }
 
@@ -560,8 +729,9 @@ mts_status mts_sync(mts_system *sys) {
     int flags = 0;
     HIP_TRY(sys, hipMemcpy(&flags, sys->flags, sizeof(int), hipMemcpyDeviceToHost));
     HIP_TRY(sys, hipMemset(sys->flags, 0, sizeof(int)));
-    if (flags & (kFlagStageOverflow | kFlagListOverflow)) {
-        const int old_s = sys->stage_cap, old_l = sys->list_cap, old_p = sys->pair_cap;
+    if (flags & (kFlagStageOverflow | kFlagListOverflow | kFlagPairList)) {
+        const int old_s = sys->stage_cap, old_l = sys->list_cap, old_p = sys->pair_cap,
+                  old_n = sys->nl_cap;
         if (flags & kFlagStageOverflow) {
             sys->stage_cap = std::min(4096, 2 * sys->stage_cap);
             sys->pair_cap = std::min(4096, 2 * sys->pair_cap);
@@ -572,12 +742,30 @@ mts_status mts_sync(mts_system *sys) {
             sys->list_cap = old_l;
         }
         if (pair_lds_bytes(sys->pair_cap) > sys->max_lds) sys->pair_cap = old_p;
-        drop_graphs(sys);  // captured launches carry the old tile sizes
-        char buf[200];
+        if (flags & kFlagPairList) {
+            const int cap = std::min(4096, 2 * sys->nl_cap);
+            int *nb = nullptr;
+            if (dalloc(&nb, (size_t)sys->n * cap) == hipSuccess) {
+                (void)hipFree(sys->nbr);
+                sys->nbr = nb;
+                sys->nl_cap = cap;
+            }
+        }
+        drop_graphs(sys);  // captured launches carry the old sizes and pointers
+        char buf[240];
         snprintf(buf, sizeof buf,
                  "capacity overflow (flags %d): triplet tile %d -> %d, pair tile %d -> %d, "
-                 "neighbour list %d -> %d; results since the last sync are invalid",
-                 flags, old_s, sys->stage_cap, old_p, sys->pair_cap, old_l, sys->list_cap);
+                 "neighbour list %d -> %d, pair list %d -> %d; results since the last sync "
+                 "are invalid",
+                 flags, old_s, sys->stage_cap, old_p, sys->pair_cap, old_l, sys->list_cap, old_n,
+                 sys->nl_cap);
+        return fail(sys, MTS_ERR_CAPACITY, buf);
+    }
+    if (flags & kFlagSkin) {
+        char buf[200];
+        snprintf(buf, sizeof buf,
+                 "a particle moved more than half the pair-list skin (%.3g) between full steps; "
+                 "pair forces since the last sync may miss pairs", sys->skin);
         return fail(sys, MTS_ERR_CAPACITY, buf);
     }
     if (flags & kFlagNonFinite) return fail(sys, MTS_ERR_NONFINITE, "non-finite force or energy");
@@ -588,19 +776,19 @@ const char *mts_last_error(const mts_system *sys) { return sys ? sys->err.c_str(
 
 mts_status mts_get_grid(const mts_system *sys, int32_t system, int32_t n_cells[3]) {
     if (!sys || !n_cells || system < 0 || system >= sys->nsys) return MTS_ERR_INVALID_ARG;
-    for (int k = 0; k < 3; ++k) n_cells[k] = sys->hsd[system].nc[k];
+    for (int k = 0; k < 3; ++k) n_cells[k] = sys->gt.hsd[system].nc[k];
     return MTS_OK;
 }
 
 mts_status mts_get_cell_index(mts_system *sys, int32_t *cell) {
     if (!sys || (!cell && sys->n > 0)) return MTS_ERR_INVALID_ARG;
-    HIP_TRY(sys, launch_local_cell_index(sys->st, sys->n, sys->cell_of, sys->sd, sys->sys_of, cell));
+    HIP_TRY(sys, launch_local_cell_index(sys->st, sys->n, sys->gt.cell_of, sys->gt.sd, sys->sys_of, cell));
     return MTS_OK;
 }
 
 mts_status mts_count_triplets(mts_system *sys, const double *x, int64_t *count) {
     if (!sys || !count || (!x && sys->n > 0)) return MTS_ERR_INVALID_ARG;
-    MTS_TRY(enqueue_bin(sys, x));
+    MTS_TRY(enqueue_bin(sys, sys->gt, x, false));
     MTS_TRY(enqueue_triplet(sys, nullptr, nullptr, 0));
     MTS_TRY(enqueue_reduce(sys, nullptr, false, true, nullptr, 2, nullptr, sys->cnt_sys));
     std::vector<long long> c(sys->nsys);
@@ -618,7 +806,7 @@ mts_status mts_list_triplets(mts_system *sys, const double *x, int32_t *ijk, int
     if (!sys || !n || cap < 0 || (!x && sys->n > 0)) return MTS_ERR_INVALID_ARG;
     if (!ijk || cap == 0) return mts_count_triplets(sys, x, n);
     HIP_TRY(sys, hipMemsetAsync(sys->list_n, 0, sizeof(unsigned long long), sys->st));
-    MTS_TRY(enqueue_bin(sys, x));
+    MTS_TRY(enqueue_bin(sys, sys->gt, x, false));
     MTS_TRY(enqueue_triplet(sys, nullptr, ijk, cap));
     unsigned long long total = 0;
     HIP_TRY(sys, hipMemcpyAsync(&total, sys->list_n, sizeof(unsigned long long), hipMemcpyDeviceToHost, sys->st));

@@ -79,7 +79,9 @@ __global__ void __launch_bounds__(256) k_rank_gather(int64_t n, const int *__res
                                                      const SysDesc *__restrict__ sd,
                                                      const int *__restrict__ sys_of,
                                                      int *__restrict__ perm,
-                                                     double *__restrict__ xs) {
+                                                     int *__restrict__ inv_perm,
+                                                     double *__restrict__ xs,
+                                                     double *__restrict__ x_ref) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     const int key = tmp[p];
@@ -89,9 +91,14 @@ __global__ void __launch_bounds__(256) k_rank_gather(int64_t n, const int *__res
     for (int q = b; q < e; ++q) r += tmp[q] < key;
     const int64_t dst = b + r;
     perm[dst] = key;
+    inv_perm[key] = (int)dst;
     const SysDesc &d = sd[sys_of[key]];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) xs[k * n + dst] = wrap1(x[3 * (int64_t)key + k], d.L[k]);
+    for (int k = 0; k < 3; ++k) {
+        const double w = wrap1(x[3 * (int64_t)key + k], d.L[k]);
+        xs[k * n + dst] = w;
+        if (x_ref) x_ref[3 * (int64_t)key + k] = w;
+    }
 }
 
 __global__ void k_local_cell_index(int64_t n, const int *__restrict__ cell_of,
@@ -124,10 +131,11 @@ hipError_t launch_bin_scatter(hipStream_t st, int64_t n, const int *cell_of, con
 
 hipError_t launch_rank_gather(hipStream_t st, int64_t n, const int *tmp, const int *cell_of,
                               const int *start, const double *x, const SysDesc *sd,
-                              const int *sys_of, int *perm, double *xs) {
+                              const int *sys_of, int *perm, int *inv_perm, double *xs,
+                              double *x_ref) {
     if (n > 0)
         k_rank_gather<<<blocks_for(n, 256), 256, 0, st>>>(n, tmp, cell_of, start, x, sd, sys_of,
-                                                          perm, xs);
+                                                          perm, inv_perm, xs, x_ref);
     return hipGetLastError();
 }
 

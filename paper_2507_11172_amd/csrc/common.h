@@ -36,7 +36,9 @@ enum : int {
     kFlagStageOverflow = 1,  // a triplet neighbourhood did not fit the LDS tile
     kFlagListOverflow = 2,   // an anchor had more forward neighbours than the list holds
     kFlagNonFinite = 4,      // a force or energy was NaN/Inf
-    kFlagTripletListFull = 8 // debug triplet listing exceeded its buffer (not an error)
+    kFlagTripletListFull = 8,// debug triplet listing exceeded its buffer (not an error)
+    kFlagSkin = 16,          // a particle moved more than half the pair-list skin
+    kFlagPairList = 32       // a particle had more pair-list neighbours than the list holds
 };
 
 // ---------------------------------------------------------------- geometry
@@ -161,7 +163,8 @@ hipError_t launch_bin_scatter(hipStream_t st, int64_t n, const int *cell_of, con
                               const int *start, int *tmp);
 hipError_t launch_rank_gather(hipStream_t st, int64_t n, const int *tmp, const int *cell_of,
                               const int *start, const double *x, const SysDesc *sd,
-                              const int *sys_of, int *perm, double *xs);
+                              const int *sys_of, int *perm, int *inv_perm, double *xs,
+                              double *x_ref);
 hipError_t launch_local_cell_index(hipStream_t st, int64_t n, const int *cell_of,
                                    const SysDesc *sd, const int *sys_of, int *out);
 
@@ -180,8 +183,33 @@ struct PairArgs {
     double *pe;             // out [n][2] per-particle {U2/2-sums, W2/2-sums}, sorted order
     double eps, sigma2, rc2, ushift;
     int *flags;
+    // optional pair-list build: neighbours within sqrt(rcv2) of sorted particle p go to
+    // nbr[p * nl_cap + s] (sorted indices, tile order), their number to nn[p]
+    int *nbr;
+    int *nn;
+    int nl_cap;
+    double rcv2;
 };
 hipError_t launch_pair(hipStream_t st, const PairArgs &a, bool fp32);
+
+// Pair forces from the pair list, every inner step between rebuilds.  The displacement
+// of each listed pair is re-derived from the current wrapped positions with the minimum
+// image, so particles may wrap across the box between rebuilds.
+struct PairListArgs {
+    int64_t n;
+    const double *xs;       // current wrapped positions in the list's sorted order, SoA
+    const int *perm;        // sorted -> input index
+    const int *nbr;         // [n][nl_cap]
+    const int *nn;          // [n]
+    int nl_cap;
+    const SysDesc *sd;
+    const int *sys_of;
+    double *f;              // out [n][3], input order
+    double *pe;             // out [n][2], sorted order
+    double eps, sigma2, rc2, ushift;
+    int *flags;
+};
+hipError_t launch_pair_list(hipStream_t st, const PairListArgs &a, bool fp32);
 size_t pair_lds_bytes(int stage_cap);
 
 // Lets every LDS-tiled kernel use up to max_bytes of dynamic LDS per workgroup.
@@ -211,12 +239,27 @@ size_t triplet_lds_bytes(int stage_cap, int list_cap);
 hipError_t launch_triplet_gather(hipStream_t st, int64_t n, const double *pf, const int *perm,
                                  double *f, int *flags);
 
-// Integrator pieces (input particle order, FP64).
-hipError_t launch_kick(hipStream_t st, int64_t n3, double *v, const double *f, double c);
-hipError_t launch_drift(hipStream_t st, int64_t n, double *x, const double *v, const double *f2,
-                        double dt, double cx, const SysDesc *sd, const int *sys_of);
-hipError_t launch_kick2(hipStream_t st, int64_t n3, double *v, const double *fa,
-                        const double *fb, double c);
+// Fused r-RESPA update (input particle order, FP64), in Algorithm 2's order:
+//   kick2:  v <- v + dt/(2m) (F2(x^{i-1}) + F2(x^i))     (previous step's F2 kick)
+//   kick3:  v <- v + dt s/(2m) F3, once or twice          (end / start of an outer cycle)
+//   drift:  x <- wrap(x + dt v + dt^2/(2m) F2(x^i))
+// then, when drifting, the new position is scattered to the pair list's sorted order and
+// compared with the position of the last list build (skin check).
+struct IntArgs {
+    int64_t n;
+    double *x, *v;
+    const double *f2prev, *f2cur, *f3;
+    double c2, c3, dt, cx;
+    int kick2, kick3_end, kick3_start, drift;
+    const SysDesc *sd;      // any grid: only the box edges are used
+    const int *sys_of;
+    const int *inv_perm;    // input -> sorted index of the pair grid, or null
+    double *xs;             // sorted positions of the pair grid, or null
+    const double *x_ref;    // positions at the last list build, or null
+    double half_skin2;      // (skin / 2)^2
+    int *flags;
+};
+hipError_t launch_int(hipStream_t st, const IntArgs &a);
 
 // Energy reductions: one workgroup per system, fixed summation order.
 struct ReduceArgs {

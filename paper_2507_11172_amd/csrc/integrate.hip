@@ -1,41 +1,53 @@
-// r-RESPA update pieces (Sec. 4.1, Algorithm 2) and the FP64 energy reductions.
+// r-RESPA update (Sec. 4.1, Algorithm 2) and the FP64 energy reductions.
 //
-// The updates are elementwise FP64 streams over x, v and the force caches (HBM-bound).
-// Each keeps the exact expression order of Algorithm 2:
-//   kick:   v <- v + c * F                 (c = dt*s/(2m) for F3)
-//   drift:  x <- wrap(x + dt*v + dt^2/(2m) * F2(x^i))
+// k_int fuses, per particle, every velocity/position update that falls between two force
+// evaluations -- the previous step's F2 kick, the F3 half kicks that close one outer cycle
+// and open the next, and the drift -- so one launch replaces four.  It is an elementwise
+// FP64 stream over x, v and the force caches (HBM-bound) and keeps the exact expression
+// order of Algorithm 2:
 //   kick2:  v <- v + dt/(2m) * (F2(x^i) + F2(x^{i+1}))
+//   kick3:  v <- v + dt*s/(2m) * F3
+//   drift:  x <- wrap(x + dt*v + dt^2/(2m) * F2(x^i))
 // Reductions sum in a fixed order (per-thread strided sums, then an LDS tree), one
 // workgroup per system, so energies are bitwise reproducible.
 #include "common.h"
 
 namespace mts {
 
-__global__ void __launch_bounds__(256) k_kick(int64_t n3, double *__restrict__ v,
-                                              const double *__restrict__ f, double c) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q < n3) v[q] = v[q] + c * f[q];
-}
-
-__global__ void __launch_bounds__(256) k_kick2(int64_t n3, double *__restrict__ v,
-                                               const double *__restrict__ fa,
-                                               const double *__restrict__ fb, double c) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q < n3) v[q] = v[q] + c * (fa[q] + fb[q]);
-}
-
-__global__ void __launch_bounds__(256) k_drift(int64_t n, double *__restrict__ x,
-                                               const double *__restrict__ v,
-                                               const double *__restrict__ f2, double dt, double cx,
-                                               const SysDesc *__restrict__ sd,
-                                               const int *__restrict__ sys_of) {
+__global__ void __launch_bounds__(256) k_int(IntArgs a) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const SysDesc &d = sd[sys_of[i]];
+    if (i >= a.n) return;
+    const SysDesc &d = a.sd[a.sys_of[i]];
+    double xn[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const int64_t q = 3 * i + k;
-        x[q] = wrap1(x[q] + dt * v[q] + cx * f2[q], d.L[k]);
+        double vq = a.v[q];
+        if (a.kick2) vq = vq + a.c2 * (a.f2prev[q] + a.f2cur[q]);
+        if (a.kick3_end) vq = vq + a.c3 * a.f3[q];
+        if (a.kick3_start) vq = vq + a.c3 * a.f3[q];
+        a.v[q] = vq;
+        if (a.drift) {
+            xn[k] = wrap1(a.x[q] + a.dt * vq + a.cx * a.f2cur[q], d.L[k]);
+            a.x[q] = xn[k];
+        }
+    }
+    if (!a.drift) return;
+    if (a.xs) {
+        const int64_t p = a.inv_perm[i];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) a.xs[k * a.n + p] = xn[k];
+    }
+    if (a.x_ref) {
+        double dd[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            double t = xn[k] - a.x_ref[3 * i + k];
+            const double h = 0.5 * d.L[k];
+            t = t > h ? t - d.L[k] : (t < -h ? t + d.L[k] : t);
+            dd[k] = t;
+        }
+        if (!(norm2(dd[0], dd[1], dd[2]) <= a.half_skin2)) atomicOr(a.flags, kFlagSkin);
     }
 }
 
@@ -125,20 +137,8 @@ __global__ void k_set_int(int *p, int v) { *p = v; }
 
 static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
-hipError_t launch_kick(hipStream_t st, int64_t n3, double *v, const double *f, double c) {
-    if (n3 > 0) k_kick<<<blocks_for(n3, 256), 256, 0, st>>>(n3, v, f, c);
-    return hipGetLastError();
-}
-
-hipError_t launch_kick2(hipStream_t st, int64_t n3, double *v, const double *fa,
-                        const double *fb, double c) {
-    if (n3 > 0) k_kick2<<<blocks_for(n3, 256), 256, 0, st>>>(n3, v, fa, fb, c);
-    return hipGetLastError();
-}
-
-hipError_t launch_drift(hipStream_t st, int64_t n, double *x, const double *v, const double *f2,
-                        double dt, double cx, const SysDesc *sd, const int *sys_of) {
-    if (n > 0) k_drift<<<blocks_for(n, 256), 256, 0, st>>>(n, x, v, f2, dt, cx, sd, sys_of);
+hipError_t launch_int(hipStream_t st, const IntArgs &a) {
+    if (a.n > 0) k_int<<<blocks_for(a.n, 256), 256, 0, st>>>(a);
     return hipGetLastError();
 }
 

@@ -55,13 +55,14 @@ struct alignas(16) PairEnt {
 };
 static_assert(sizeof(PairEnt) == 48, "48-byte LDS entries");
 
-size_t pair_lds_bytes(int cap) { return (size_t)cap * sizeof(PairEnt); }
+size_t pair_lds_bytes(int cap) { return (size_t)cap * (sizeof(PairEnt) + sizeof(int)); }
 
 template <typename T>
 __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     const int CAP = a.stage_cap;
     PairEnt *tile = (PairEnt *)smem_raw;
+    int *tslot = (int *)(tile + CAP);  // sorted index of each tile entry
     const int base = blockIdx.x;
     const int lane = threadIdx.x;  // thread index in the workgroup
     const int64_t n = a.n;
@@ -90,26 +91,33 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
         e.sy = (double)(((code >> 2) & 3) - 1) * d.L[1];
         e.sz = (double)(((code >> 4) & 3) - 1) * d.L[2];
         tile[t] = e;
+        tslot[t] = src;
     }
     __syncthreads();
 
-    const int g = lane / kPairGroup, r = lane % kPairGroup;
+    const int g = lane / kPairGroup, r = lane % kPairGroup;  // group and lane in group
     const T sigma2 = (T)a.sigma2, eps24 = (T)(24.0 * a.eps), eps4 = (T)(4.0 * a.eps);
     const int pbase = a.start[base];
+    const bool build = a.nbr != nullptr;
+    const int gshift = kPairGroup * ((lane % kWave) / kPairGroup);  // group's bits in the ballot
     for (int ib = 0; ib < nself; ib += kPairGroups) {
         const int i = ib + g;
         const bool act = i < nself;
+        const int self = s13 + (act ? i : 0);
+        const PairEnt pi = tile[self];
+        const int64_t p = pbase + i;
         double fx = 0.0, fy = 0.0, fz = 0.0, u = 0.0, w = 0.0;
-        if (act) {
-            const int self = s13 + i;
-            const PairEnt pi = tile[self];
-            for (int t = r; t < nst; t += kPairGroup) {
+        int cnt = 0;  // pair-list entries of this group's particle (uniform in the group)
+        for (int t0 = 0; t0 < nst; t0 += kPairGroup) {
+            const int t = t0 + r;
+            bool near = false;
+            if (act && t < nst && t != self) {
                 const PairEnt e = tile[t];
                 const double dx = disp1(pi.x, e.x, e.sx);
                 const double dy = disp1(pi.y, e.y, e.sy);
                 const double dz = disp1(pi.z, e.z, e.sz);
                 const double r2 = norm2(dx, dy, dz);
-                if (r2 <= a.rc2 && t != self) {
+                if (r2 <= a.rc2) {
                     T fr, e4;
                     lj_terms<T>(r2, sigma2, eps24, eps4, fr, e4);
                     fx -= (double)(fr * (T)dx);
@@ -118,6 +126,14 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
                     u += (double)e4 - a.ushift;
                     w += (double)(fr * (T)r2);
                 }
+                near = r2 <= a.rcv2;
+            }
+            if (build) {
+                const uint64_t mask = __ballot(near);
+                const unsigned gbits = (unsigned)(mask >> gshift) & 0xffffu;
+                const int pos = cnt + __popc(gbits & ((1u << r) - 1u));
+                if (near && pos < a.nl_cap) a.nbr[p * a.nl_cap + pos] = tslot[t];
+                cnt += __popc(gbits);
             }
         }
 #pragma unroll
@@ -129,7 +145,6 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
             w += __shfl_xor(w, m);
         }
         if (act && r == 0) {
-            const int64_t p = pbase + i;
             const int64_t q = a.perm[p];
             a.f[3 * q] = fx;
             a.f[3 * q + 1] = fy;
@@ -139,8 +154,94 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
             a.pe[2 * p + 1] = 0.5 * w;
             if (!isfinite(fx) || !isfinite(fy) || !isfinite(fz) || !isfinite(u))
                 atomicOr(a.flags, kFlagNonFinite);
+            if (build) {
+                a.nn[p] = min(cnt, a.nl_cap);
+                if (cnt > a.nl_cap) atomicOr(a.flags, kFlagPairList);
+            }
         }
     }
+}
+
+// Per-step pair forces from the list: 8 lanes per particle take every 8th list entry,
+// and a DPP butterfly inside each 8-lane row segment combines them in fixed order.
+constexpr int kListGroup = 8;
+
+template <int CTRL>
+__device__ __forceinline__ double dpp8(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ double sum8(double v) {
+    v += dpp8<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp8<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp8<0x141>(v);  // row_half_mirror: lane i <- lane 7-i within 8
+    return v;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_pair_list(PairListArgs a) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t p = gid / kListGroup;
+    const int r = (int)(gid % kListGroup);
+    const bool act = p < a.n;
+    double fx = 0.0, fy = 0.0, fz = 0.0, u = 0.0, w = 0.0;
+    if (act) {
+        const int64_t n = a.n;
+        const SysDesc &d = a.sd[a.sys_of[p]];
+        const double L0 = d.L[0], L1 = d.L[1], L2 = d.L[2];
+        const double h0 = 0.5 * L0, h1 = 0.5 * L1, h2 = 0.5 * L2;
+        const double xp = a.xs[p], yp = a.xs[n + p], zp = a.xs[2 * n + p];
+        const T sigma2 = (T)a.sigma2, eps24 = (T)(24.0 * a.eps), eps4 = (T)(4.0 * a.eps);
+        const int cnt = a.nn[p];
+        const int *row = a.nbr + p * a.nl_cap;
+        for (int s = r; s < cnt; s += kListGroup) {
+            const int64_t q = row[s];
+            // minimum image by comparison: fl(fl(x_q - x_p) + S), S in {-L, 0, +L}
+            double dx = a.xs[q] - xp, dy = a.xs[n + q] - yp, dz = a.xs[2 * n + q] - zp;
+            dx = dx > h0 ? dx - L0 : (dx < -h0 ? dx + L0 : dx);
+            dy = dy > h1 ? dy - L1 : (dy < -h1 ? dy + L1 : dy);
+            dz = dz > h2 ? dz - L2 : (dz < -h2 ? dz + L2 : dz);
+            const double r2 = norm2(dx, dy, dz);
+            if (r2 <= a.rc2) {
+                T fr, e4;
+                lj_terms<T>(r2, sigma2, eps24, eps4, fr, e4);
+                fx -= (double)(fr * (T)dx);
+                fy -= (double)(fr * (T)dy);
+                fz -= (double)(fr * (T)dz);
+                u += (double)e4 - a.ushift;
+                w += (double)(fr * (T)r2);
+            }
+        }
+    }
+    fx = sum8(fx);
+    fy = sum8(fy);
+    fz = sum8(fz);
+    u = sum8(u);
+    w = sum8(w);
+    if (act && r == 0) {
+        const int64_t q = a.perm[p];
+        a.f[3 * q] = fx;
+        a.f[3 * q + 1] = fy;
+        a.f[3 * q + 2] = fz;
+        a.pe[2 * p] = 0.5 * u;
+        a.pe[2 * p + 1] = 0.5 * w;
+        if (!isfinite(fx) || !isfinite(fy) || !isfinite(fz) || !isfinite(u))
+            atomicOr(a.flags, kFlagNonFinite);
+    }
+}
+
+hipError_t launch_pair_list(hipStream_t st, const PairListArgs &a, bool fp32) {
+    const int64_t threads = a.n * kListGroup;
+    const unsigned blocks = (unsigned)((threads + 255) / 256);
+    if (blocks == 0) return hipSuccess;
+    if (fp32)
+        k_pair_list<float><<<blocks, 256, 0, st>>>(a);
+    else
+        k_pair_list<double><<<blocks, 256, 0, st>>>(a);
+    return hipGetLastError();
 }
 
 hipError_t configure_triplet_lds(size_t max_bytes);

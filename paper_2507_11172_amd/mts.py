@@ -45,7 +45,8 @@ class MTSError(RuntimeError):
 class mts_params(C.Structure):
     _fields_ = [("epsilon", C.c_double), ("sigma", C.c_double), ("rc_pair", C.c_double),
                 ("nu", C.c_double), ("rc_triplet", C.c_double), ("mass", C.c_double),
-                ("dt", C.c_double), ("k", C.c_int32), ("precision", C.c_int32),
+                ("dt", C.c_double), ("skin", C.c_double), ("k", C.c_int32),
+                ("precision", C.c_int32),
                 ("lj_energy_shift", C.c_int32), ("reserved", C.c_int32)]
 
 
@@ -110,11 +111,13 @@ class Params:
     k: int = 1
     precision: str = "fp64"   # "fp64" or "fp32"
     lj_energy_shift: bool = True
+    skin: float = 0.0         # pair-list skin; 0 picks the library default
 
     def to_c(self) -> mts_params:
         prec = {"fp64": MTS_FP64, "fp32": MTS_FP32}[self.precision]
         return mts_params(self.epsilon, self.sigma, self.rc_pair, self.nu, self.rc_triplet,
-                          self.mass, self.dt, int(self.k), prec, int(bool(self.lj_energy_shift)), 0)
+                          self.mass, self.dt, float(self.skin), int(self.k), prec,
+                          int(bool(self.lj_energy_shift)), 0)
 
 
 def _ptr(t, what: str, shape: Optional[Tuple[int, ...]] = None, dtype=None):

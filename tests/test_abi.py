@@ -39,7 +39,7 @@ def test_status_strings(lib):
 def _init(lib, **over):
     from paper_2507_11172_amd import mts
     kw = dict(epsilon=1.0, sigma=1.0, rc_pair=2.5, nu=0.073, rc_triplet=2.5, mass=1.0, dt=0.001,
-              k=10, precision=0, lj_energy_shift=1, reserved=0)
+              skin=0.0, k=10, precision=0, lj_energy_shift=1, reserved=0)
     n = over.pop("n", [500])
     box = over.pop("box", [[8.55, 8.55, 8.55]])
     kw.update(over)
@@ -55,7 +55,8 @@ def _init(lib, **over):
 @pytest.mark.parametrize("bad,code", [
     (dict(k=0), -1), (dict(dt=0.0), -1), (dict(mass=-1.0), -1), (dict(sigma=0.0), -1),
     (dict(rc_pair=float("nan")), -1), (dict(precision=7), -1), (dict(reserved=1), -1),
-    (dict(epsilon=-1.0), -1), (dict(n=[-5]), -1),
+    (dict(epsilon=-1.0), -1), (dict(skin=-0.1), -1), (dict(skin=float("inf")), -1),
+    (dict(n=[-5]), -1),
     (dict(box=[[4.9, 8.5, 8.5]]), -2), (dict(box=[[8.5, 8.5, 5.0]]), -2),
     (dict(rc_triplet=4.3), -2),
 ])

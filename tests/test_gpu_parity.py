@@ -24,7 +24,8 @@ def _torch():
 def _system(w, **kw):
     from paper_2507_11172_amd import mts
     p = mts.Params(epsilon=w.epsilon, sigma=w.sigma, rc_pair=w.rc_pair, nu=w.nu,
-                   rc_triplet=w.rc_triplet, mass=w.mass, dt=w.dt, k=kw.pop("k", w.k),
+                   rc_triplet=w.rc_triplet, mass=w.mass, dt=kw.pop("dt", w.dt),
+                   k=kw.pop("k", w.k),
                    precision=kw.pop("precision", "fp64"), **kw)
     return mts.System(p, w.n_particles.tolist(), w.box)
 
@@ -180,6 +181,41 @@ def test_respa_matches_oracle(k, n_iter):
     assert np.abs(dx).max() <= 1e-10
     assert np.abs(v.cpu().numpy() - vo).max() <= 1e-10 * np.abs(vo).max()
     assert np.abs(e.cpu().numpy()[:, 0, :] - eo).max() <= 1e-10 * np.abs(eo).max()
+
+
+@pytest.mark.parametrize("case,skin", [("smallbox", 0.0), ("fcc500", 0.01), ("fcc256", 0.6)])
+def test_respa_pair_list_variants(case, skin):
+    """Pair list on a two-cell pair grid (smallbox), no list (skin below the minimum),
+    and a wide skin: all follow the oracle's trajectory."""
+    torch = _torch()
+    w = CASES[case]()
+    box = w.box[0]
+    k, n_iter = 5, 40
+    xo, vo, eo = oracle.respa(w.x, w.v, box, n_iter=n_iter, k=k)
+    with _system(w, k=k, skin=skin) as s:
+        x, v = _dev(w.x), _dev(w.v)
+        e = torch.zeros((n_iter // k + 1, 1, 5), dtype=torch.float64, device="cuda")
+        s.respa_step(x, v, n_iter, e)
+        s.sync()
+    dx = x.cpu().numpy() - xo
+    dx -= box * np.rint(dx / box)
+    assert np.abs(dx).max() <= 1e-10
+    assert np.abs(v.cpu().numpy() - vo).max() <= 1e-10 * np.abs(vo).max()
+    assert np.abs(e.cpu().numpy()[:, 0, :] - eo).max() <= 1e-10 * np.abs(eo).max()
+
+
+def test_pair_list_skin_violation_is_reported():
+    """Particles that outrun half the skin between full steps raise an error at sync."""
+    torch = _torch()
+    from paper_2507_11172_amd import mts
+    w = W.plain_fp64()
+    with _system(w, k=10, skin=0.05, dt=0.005) as s:
+        x, v = _dev(w.x), _dev(4.0 * w.v)
+        s.respa_step(x, v, 10)
+        with pytest.raises(mts.MTSError) as e:
+            s.sync()
+        assert e.value.code == mts.MTS_ERR_CAPACITY
+        assert "skin" in str(e.value)
 
 
 def test_determinism_and_resume():
