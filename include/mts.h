@@ -69,8 +69,9 @@ typedef struct {
     double rc_triplet;       /* three-body cutoff: all three edges <= rc_triplet */
     double mass;             /* particle mass m (uniform) */
     double dt;               /* inner time step delta t */
-    double skin;             /* Verlet pair-list skin added to rc_pair (0: 0.3 + 0.01 k sigma);
-                                shrunk to fit the box, no list below 0.05 sigma */
+    double skin;             /* Verlet pair-list skin added to rc_pair (0: the default,
+                                max(0.3 sigma, 12 k dt sqrt(epsilon/mass))); shrunk to fit
+                                the box, no list below 0.05 sigma */
     int32_t k;               /* r-RESPA step-size factor s >= 1 (Sec. 4.1) */
     int32_t precision;       /* mts_precision */
     int32_t lj_energy_shift; /* 1: report U2 shifted by -U(rc_pair) per pair (forces unchanged) */

@@ -37,7 +37,8 @@ struct Grid {
     int *perm_tmp = nullptr;      // [n] unordered scatter
     int *perm = nullptr;          // [n] sorted -> input
     int *inv_perm = nullptr;      // [n] input -> sorted
-    double *xs = nullptr;         // [3][n] sorted wrapped positions
+    Pos4 *xs = nullptr;           // [n] sorted wrapped positions
+    Pos4 *xs2 = nullptr;          // [n] second position buffer (pair grid: list steps)
 };
 
 }  // namespace
@@ -197,7 +198,8 @@ mts_status alloc_grid(mts_system *s, Grid &g) {
     HIP_TRY(s, dalloc(&g.perm_tmp, n));
     HIP_TRY(s, dalloc(&g.perm, n));
     HIP_TRY(s, dalloc(&g.inv_perm, n));
-    HIP_TRY(s, dalloc(&g.xs, 3 * n));
+    HIP_TRY(s, dalloc(&g.xs, n));
+    HIP_TRY(s, dalloc(&g.xs2, n));
     std::vector<int> soc(g.ncell);
     for (int q = 0; q < s->nsys; ++q) {
         const SysDesc &d = g.hsd[q];
@@ -211,7 +213,7 @@ mts_status alloc_grid(mts_system *s, Grid &g) {
 
 void free_grid(Grid &g) {
     void *ptrs[] = {g.sd, g.sys_of_cell, g.cell_of, g.rank, g.count, g.start, g.perm_tmp,
-                    g.perm, g.inv_perm, g.xs};
+                    g.perm, g.inv_perm, g.xs, g.xs2};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -300,19 +302,38 @@ void timer_end(mts_system *s, int cls, long slot) {
 
 // ---- enqueue helpers (all on s->st)
 
-// Counting sort of x into grid g; with_ref also records the wrapped positions as the
-// reference of the next pair-list build.
-mts_status enqueue_bin(mts_system *s, Grid &g, const double *x, bool with_ref) {
-    HIP_TRY(s, launch_bin_count(s->st, s->n, x, g.sd, s->sys_of, g.cell_of, g.rank, g.count, s->flags));
-    HIP_TRY(s, launch_scan(s->st, g.ncell, g.count, g.start, s->n));
-    HIP_TRY(s, launch_bin_scatter(s->st, s->n, g.cell_of, g.rank, g.start, g.perm_tmp));
-    HIP_TRY(s, launch_rank_gather(s->st, s->n, g.perm_tmp, g.cell_of, g.start, x, g.sd, s->sys_of,
-                                  g.perm, g.inv_perm, g.xs, with_ref ? s->x_ref : nullptr));
+enum : int { kBinPair = 1, kBinTriplet = 2 };
+
+void fill_bin_grid(BinGrid &b, Grid &g, double *x_ref) {
+    b.sd = g.sd;
+    b.ncell = g.ncell;
+    b.cell_of = g.cell_of;
+    b.rank = g.rank;
+    b.count = g.count;
+    b.start = g.start;
+    b.tmp = g.perm_tmp;
+    b.perm = g.perm;
+    b.inv_perm = g.inv_perm;
+    b.xs = g.xs;
+    b.x_ref = x_ref;
+}
+
+// Counting sort of x into the pair grid and/or the triplet grid (one launch per pass);
+// with_ref also records the wrapped positions as the reference of the next skin check.
+mts_status enqueue_bin(mts_system *s, int which, const double *x, bool with_ref) {
+    BinArgs a{};
+    a.n = s->n;
+    a.x = x;
+    a.sys_of = s->sys_of;
+    a.flags = s->flags;
+    if (which & kBinPair) fill_bin_grid(a.g[a.ng++], s->gp, with_ref ? s->x_ref : nullptr);
+    if (which & kBinTriplet) fill_bin_grid(a.g[a.ng++], s->gt, nullptr);
+    HIP_TRY(s, launch_bin(s->st, a));
     return MTS_OK;
 }
 
-// F2 from the pair grid's cell tiles; with build_list also (re)builds the pair list.
-mts_status enqueue_pair(mts_system *s, double *f2, bool build_list) {
+// F2 from the pair grid's cell tiles (no list).
+mts_status enqueue_pair(mts_system *s, double *f2) {
     const Grid &g = s->gp;
     PairArgs a{};
     a.ncell = g.ncell;
@@ -331,24 +352,48 @@ mts_status enqueue_pair(mts_system *s, double *f2, bool build_list) {
     a.rc2 = s->p.rc_pair * s->p.rc_pair;
     a.ushift = s->ushift;
     a.flags = s->flags;
-    if (build_list) {
-        const double rv = s->p.rc_pair + s->skin;
-        a.nbr = s->nbr;
-        a.nn = s->nn;
-        a.nl_cap = s->nl_cap;
-        a.rcv2 = rv * rv;
-    }
     const long ts = timer_begin(s, 1);
     HIP_TRY(s, launch_pair(s->st, a, s->fp32));
     timer_end(s, 1, ts);
     return MTS_OK;
 }
 
-// F2 from the pair list (positions in the pair grid's sorted order, updated by k_int).
-mts_status enqueue_pair_list(mts_system *s, double *f2) {
+// Verlet list of the pair grid at its current binning.
+mts_status enqueue_list_build(mts_system *s) {
+    const Grid &g = s->gp;
+    ListBuildArgs a{};
+    a.ncell = g.ncell;
+    a.sys_of_cell = g.sys_of_cell;
+    a.stage_cap = s->pair_cap;
+    a.n = s->n;
+    a.xs = g.xs;
+    a.start = g.start;
+    a.sd = g.sd;
+    a.nbr = s->nbr;
+    a.nn = s->nn;
+    a.nl_cap = s->nl_cap;
+    const double rv = s->p.rc_pair + s->skin;
+    a.rv2 = rv * rv;
+    a.flags = s->flags;
+    HIP_TRY(s, launch_list_build(s->st, a));
+    return MTS_OK;
+}
+
+// Update steps fused behind the list forces (see PairListArgs).
+struct Fused {
+    bool kick2 = false, kick3_end = false, kick3_start = false, drift = false;
+    const double *f2prev = nullptr;
+    Pos4 *xs_out = nullptr;
+};
+
+// F2 from the pair list at positions xs_in (pair grid sorted order) into f2, then the
+// fused update u of the internal x, v (u.drift writes the new positions to u.xs_out).
+mts_status enqueue_pair_list(mts_system *s, const Pos4 *xs_in, double *f2, const Fused &u,
+                             bool energy) {
+    const double dt = s->p.dt, m = s->p.mass;
     PairListArgs a{};
     a.n = s->n;
-    a.xs = s->gp.xs;
+    a.xs = xs_in;
     a.perm = s->gp.perm;
     a.nbr = s->nbr;
     a.nn = s->nn;
@@ -356,12 +401,29 @@ mts_status enqueue_pair_list(mts_system *s, double *f2) {
     a.sd = s->gp.sd;
     a.sys_of = s->sys_of;
     a.f = f2;
-    a.pe = s->pe;
+    a.pe = energy ? s->pe : nullptr;
     a.eps = s->p.epsilon;
     a.sigma2 = s->p.sigma * s->p.sigma;
     a.rc2 = s->p.rc_pair * s->p.rc_pair;
     a.ushift = s->ushift;
     a.flags = s->flags;
+    if (u.kick2 || u.kick3_end || u.kick3_start || u.drift) {
+        a.kick2 = u.kick2;
+        a.kick3_end = u.kick3_end;
+        a.kick3_start = u.kick3_start;
+        a.drift = u.drift;
+        a.x = s->xi;
+        a.v = s->vi;
+        a.f2prev = u.f2prev;
+        a.f3 = s->f3;
+        a.c2 = dt / (2.0 * m);
+        a.c3 = (dt * (double)s->p.k) / (2.0 * m);
+        a.dt = dt;
+        a.cx = (dt * dt) / (2.0 * m);
+        a.xs_out = u.xs_out;
+        a.x_ref = u.drift && u.xs_out ? s->x_ref : nullptr;
+        a.half_skin2 = 0.25 * s->skin * s->skin;
+    }
     const long ts = timer_begin(s, 1);
     HIP_TRY(s, launch_pair_list(s->st, a, s->fp32));
     timer_end(s, 1, ts);
@@ -416,10 +478,10 @@ mts_status enqueue_reduce(mts_system *s, const double *v, bool pair, bool trip, 
     return MTS_OK;
 }
 
-// Fused update: see IntArgs.  drift_mode 0: no drift; 1: drift, update the pair-list
-// positions and check the skin; 2: drift only (a rebinning follows).
+// Update kernel (see IntArgs).  xs_out: the drifted positions also go to the pair
+// grid's sorted order (and are checked against the skin); null when a rebinning follows.
 mts_status enqueue_int(mts_system *s, const double *f2prev, const double *f2cur, bool kick2,
-                       bool kick3_end, bool kick3_start, int drift_mode) {
+                       bool kick3_end, bool kick3_start, bool drift, Pos4 *xs_out) {
     const double dt = s->p.dt, m = s->p.mass;
     IntArgs a{};
     a.n = s->n;
@@ -435,12 +497,12 @@ mts_status enqueue_int(mts_system *s, const double *f2prev, const double *f2cur,
     a.kick2 = kick2;
     a.kick3_end = kick3_end;
     a.kick3_start = kick3_start;
-    a.drift = drift_mode != 0;
+    a.drift = drift;
     a.sd = s->gt.sd;
     a.sys_of = s->sys_of;
-    if (drift_mode == 1) {
+    if (drift && xs_out) {
         a.inv_perm = s->gp.inv_perm;
-        a.xs = s->gp.xs;
+        a.xs = xs_out;
         a.x_ref = s->x_ref;
         a.half_skin2 = 0.25 * s->skin * s->skin;
     }
@@ -449,43 +511,73 @@ mts_status enqueue_int(mts_system *s, const double *f2prev, const double *f2cur,
     return MTS_OK;
 }
 
-// Forces at the current internal positions, binning both grids: F2 into f2 (and a new
-// pair list), F3 into s->f3.
-mts_status enqueue_full_forces(mts_system *s, double *f2) {
-    MTS_TRY(enqueue_bin(s, s->gp, s->xi, true));
-    MTS_TRY(enqueue_pair(s, f2, s->skin > 0.0));
-    MTS_TRY(enqueue_bin(s, s->gt, s->xi, false));
+// Rebins both grids at the internal positions, rebuilds the pair list and computes F3
+// into s->f3 (list mode); the caller then computes F2 from the new list.
+mts_status enqueue_full_step_list(mts_system *s) {
+    MTS_TRY(enqueue_bin(s, kBinPair | kBinTriplet, s->xi, true));
+    MTS_TRY(enqueue_list_build(s));
     MTS_TRY(enqueue_triplet(s, s->f3, nullptr, 0));
     return MTS_OK;
 }
 
+// Forces at the internal positions x^0 of a call: F3 into s->f3, F2 into f2.
+mts_status enqueue_entry_forces(mts_system *s, double *f2) {
+    if (s->skin > 0.0) {
+        MTS_TRY(enqueue_full_step_list(s));
+        MTS_TRY(enqueue_pair_list(s, s->gp.xs, f2, Fused{}, true));
+    } else {
+        MTS_TRY(enqueue_bin(s, kBinPair | kBinTriplet, s->xi, false));
+        MTS_TRY(enqueue_pair(s, f2));
+        MTS_TRY(enqueue_triplet(s, s->f3, nullptr, 0));
+    }
+    return MTS_OK;
+}
+
 // One outer cycle of Algorithm 2 on the internal copies xi, vi.  On entry F2 of the
-// cycle's first position is in f2[0] and F3 in s->f3; on exit F2 of the last position is
-// in f2[k % 2] and F3 of it in s->f3, with the closing F3 half kick applied.
-//   inner step i < k-1:  k_int (kick2 of step i-1 | opening F3 kick at i = 0, drift,
-//                         list positions, skin check), F2 from the pair list;
-//   last step i = k-1:   k_int (kick2, drift), rebin both grids, F2 + new pair list,
-//                         F3, then k_int (last kick2 and the closing F3 kick) and the
-//                         energy record of the full step.
-// Without a pair list (skin 0) every step rebins the pair grid instead.
+// cycle's first position x^0 is in f2[0] and F3(x^0) in s->f3; on exit F2(x^k) is in
+// f2[k % 2] and F3(x^k) in s->f3, with the closing F3 half kick applied.
+// With a pair list (launches per cycle: k + 8, plus 3 with energies):
+//   step 0:          k_int: opening F3 kick, drift to x^1 (also into sorted buffer B)
+//   x^i, 0 < i < k:  k_pair_list at x^i: F2(x^i), then kick2 of step i-1 and the drift
+//                    of step i, positions ping-ponging between sorted buffers A and B
+//   x^k:             rebin both grids, rebuild the list, F3(x^k); k_pair_list at x^k:
+//                    F2(x^k), last kick2 and the closing F3 kick
+// Without a list (skin 0) every step rebins the pair grid and runs the tile kernel.
 mts_status enqueue_cycle(mts_system *s, double *f2_0, double *f2_1, bool energies) {
     const int k = s->p.k;
     double *f2[2] = {f2_0, f2_1};
-    const bool list = s->skin > 0.0;
-    for (int i = 0; i < k; ++i) {
-        double *prev = f2[(i + 1) & 1], *cur = f2[i & 1], *next = f2[(i + 1) & 1];
-        const bool last = i == k - 1;
-        MTS_TRY(enqueue_int(s, prev, cur, i > 0, false, i == 0, (last || !list) ? 2 : 1));
-        if (last) {
-            MTS_TRY(enqueue_full_forces(s, next));
-        } else if (list) {
-            MTS_TRY(enqueue_pair_list(s, next));
-        } else {
-            MTS_TRY(enqueue_bin(s, s->gp, s->xi, false));
-            MTS_TRY(enqueue_pair(s, next, false));
+    if (s->skin > 0.0) {
+        Pos4 *buf[2] = {s->gp.xs, s->gp.xs2};  // x^i lives in buf[i & 1] for 0 < i < k
+        MTS_TRY(enqueue_int(s, nullptr, f2[0], false, false, true, true, k > 1 ? buf[1] : nullptr));
+        for (int i = 1; i < k; ++i) {
+            Fused u;
+            u.kick2 = true;
+            u.drift = true;
+            u.f2prev = f2[(i - 1) & 1];
+            u.xs_out = i + 1 < k ? buf[(i + 1) & 1] : nullptr;  // x^k: a rebinning follows
+            MTS_TRY(enqueue_pair_list(s, buf[i & 1], f2[i & 1], u, false));
         }
+        MTS_TRY(enqueue_full_step_list(s));
+        Fused u;
+        u.kick2 = true;
+        u.kick3_end = true;
+        u.f2prev = f2[(k - 1) & 1];
+        MTS_TRY(enqueue_pair_list(s, s->gp.xs, f2[k & 1], u, energies));
+    } else {
+        for (int i = 0; i < k; ++i) {
+            double *prev = f2[(i + 1) & 1], *cur = f2[i & 1], *next = f2[(i + 1) & 1];
+            MTS_TRY(enqueue_int(s, prev, cur, i > 0, false, i == 0, true, nullptr));
+            if (i == k - 1) {
+                MTS_TRY(enqueue_bin(s, kBinPair | kBinTriplet, s->xi, false));
+                MTS_TRY(enqueue_pair(s, next));
+                MTS_TRY(enqueue_triplet(s, s->f3, nullptr, 0));
+            } else {
+                MTS_TRY(enqueue_bin(s, kBinPair, s->xi, false));
+                MTS_TRY(enqueue_pair(s, next));
+            }
+        }
+        MTS_TRY(enqueue_int(s, f2[(k - 1) & 1], f2[k & 1], true, true, false, false, nullptr));
     }
-    MTS_TRY(enqueue_int(s, f2[(k - 1) & 1], f2[k & 1], true, true, false, 0));
     if (energies) {
         MTS_TRY(enqueue_reduce(s, s->vi, true, true, s->e_buf, kNE, s->row, nullptr));
         HIP_TRY(s, launch_bump_row(s->st, s->row));
@@ -530,7 +622,7 @@ mts_status respa_internal(mts_system *s, double *x, double *v, int64_t n_iter, d
         HIP_TRY(s, hipMemcpyAsync(s->vi, v, bytes, hipMemcpyDeviceToDevice, s->st));
     }
     // Algorithm 2, lines 1-2: F2(x^0), F3(x^0); energies of x^0 in row 0
-    MTS_TRY(enqueue_full_forces(s, s->f2a));
+    MTS_TRY(enqueue_entry_forces(s, s->f2a));
     if (energies) {
         HIP_TRY(s, launch_set_int(s->st, s->row, 0));
         MTS_TRY(enqueue_reduce(s, s->vi, true, true, s->e_buf, kNE, s->row, nullptr));
@@ -603,6 +695,7 @@ mts_status mts_init_system(const mts_params *params, int32_t n_systems, const in
             if (!finite_pos(L)) return MTS_ERR_INVALID_ARG;
             if (!(L > 2.0 * rc_max * margin)) return MTS_ERR_BOX_TOO_SMALL;
             d.L[k] = L;
+            d.iL[k] = 1.0 / L;
             lmin = std::min(lmin, L);
         }
         d.p0 = p0;
@@ -618,10 +711,14 @@ mts_status mts_init_system(const mts_params *params, int32_t n_systems, const in
     s->n = p0;
     s->st = (hipStream_t)stream;
     s->fp32 = params->precision == MTS_FP32;
-    // Pair-list skin: the requested one (default 0.3 + 0.01 k sigma), shrunk so that
-    // every box edge exceeds 2 (rc + skin) -- a pair then has one image within the list
-    // radius.  Below 0.05 sigma the list is not worth it: every step rebins instead.
-    double skin = params->skin > 0.0 ? params->skin : (0.3 + 0.01 * params->k) * params->sigma;
+    // Pair-list skin: the requested one, by default max(0.3 sigma, 12 k dt sqrt(eps/m))
+    // (room for particles at four times a typical thermal speed of LJ fluids), shrunk so
+    // that every box edge exceeds 2 (rc + skin) -- a pair then has one image within the
+    // list radius.  Below 0.05 sigma the list is not worth it: every step rebins instead.
+    double skin = params->skin > 0.0
+                      ? params->skin
+                      : std::max(0.3 * params->sigma,
+                                 12.0 * params->k * params->dt * std::sqrt(params->epsilon / params->mass));
     skin = std::min(skin, 0.4999 * lmin / margin - params->rc_pair);
     s->skin = skin >= 0.05 * params->sigma ? skin : 0.0;
     mts_status g1 = make_grid(s->gt, base, params->rc_triplet * margin);
@@ -671,15 +768,14 @@ void mts_destroy_system(mts_system *sys) {
 mts_status mts_build_cells(mts_system *sys, const double *x) {
     if (!sys) return MTS_ERR_INVALID_ARG;
     if (!x && sys->n > 0) return fail(sys, MTS_ERR_INVALID_ARG, "x is NULL");
-    MTS_TRY(enqueue_bin(sys, sys->gp, x, false));
-    return enqueue_bin(sys, sys->gt, x, false);
+    return enqueue_bin(sys, kBinPair | kBinTriplet, x, false);
 }
 
 mts_status mts_compute_pair_forces(mts_system *sys, const double *x, double *f2, double *ew) {
     if (!sys) return MTS_ERR_INVALID_ARG;
     if ((!x || !f2) && sys->n > 0) return fail(sys, MTS_ERR_INVALID_ARG, "x or f2 is NULL");
-    MTS_TRY(enqueue_bin(sys, sys->gp, x, false));
-    MTS_TRY(enqueue_pair(sys, f2, false));
+    MTS_TRY(enqueue_bin(sys, kBinPair, x, false));
+    MTS_TRY(enqueue_pair(sys, f2));
     if (ew) MTS_TRY(enqueue_reduce(sys, nullptr, true, false, ew, 2, nullptr, nullptr));
     return MTS_OK;
 }
@@ -687,7 +783,7 @@ mts_status mts_compute_pair_forces(mts_system *sys, const double *x, double *f2,
 mts_status mts_compute_triplet_forces(mts_system *sys, const double *x, double *f3, double *ew) {
     if (!sys) return MTS_ERR_INVALID_ARG;
     if ((!x || !f3) && sys->n > 0) return fail(sys, MTS_ERR_INVALID_ARG, "x or f3 is NULL");
-    MTS_TRY(enqueue_bin(sys, sys->gt, x, false));
+    MTS_TRY(enqueue_bin(sys, kBinTriplet, x, false));
     MTS_TRY(enqueue_triplet(sys, f3, nullptr, 0));
     if (ew) MTS_TRY(enqueue_reduce(sys, nullptr, false, true, ew, 2, nullptr, nullptr));
     return MTS_OK;
@@ -788,7 +884,7 @@ mts_status mts_get_cell_index(mts_system *sys, int32_t *cell) {
 
 mts_status mts_count_triplets(mts_system *sys, const double *x, int64_t *count) {
     if (!sys || !count || (!x && sys->n > 0)) return MTS_ERR_INVALID_ARG;
-    MTS_TRY(enqueue_bin(sys, sys->gt, x, false));
+    MTS_TRY(enqueue_bin(sys, kBinTriplet, x, false));
     MTS_TRY(enqueue_triplet(sys, nullptr, nullptr, 0));
     MTS_TRY(enqueue_reduce(sys, nullptr, false, true, nullptr, 2, nullptr, sys->cnt_sys));
     std::vector<long long> c(sys->nsys);
@@ -806,7 +902,7 @@ mts_status mts_list_triplets(mts_system *sys, const double *x, int32_t *ijk, int
     if (!sys || !n || cap < 0 || (!x && sys->n > 0)) return MTS_ERR_INVALID_ARG;
     if (!ijk || cap == 0) return mts_count_triplets(sys, x, n);
     HIP_TRY(sys, hipMemsetAsync(sys->list_n, 0, sizeof(unsigned long long), sys->st));
-    MTS_TRY(enqueue_bin(sys, sys->gt, x, false));
+    MTS_TRY(enqueue_bin(sys, kBinTriplet, x, false));
     MTS_TRY(enqueue_triplet(sys, nullptr, ijk, cap));
     unsigned long long total = 0;
     HIP_TRY(sys, hipMemcpyAsync(&total, sys->list_n, sizeof(unsigned long long), hipMemcpyDeviceToHost, sys->st));

@@ -23,12 +23,19 @@ constexpr int kNE = 5;           // K, U2, U3, W2, W3
 struct SysDesc {
     double L[3];    // box edges
     double q[3];    // n_cells / L, the cell-coordinate scale
+    double iL[3];   // 1 / L
     int nc[3];      // cells per edge (>= 2); cell edge L/nc exceeds the largest cutoff
     int cell0;      // first global cell id of this system
     int ncell;      // nc[0] * nc[1] * nc[2]
     int pad;
     int64_t p0;     // first particle (global index); particles are concatenated by system
     int64_t n;      // particles in this system
+};
+
+// Sorted wrapped position, padded to 32 bytes so that a gather of one particle touches
+// a single cache line and a staged copy is two 16-byte loads.
+struct alignas(32) Pos4 {
+    double x, y, z, w;  // w = 0
 };
 
 // Device error flags (bit mask in a single int).
@@ -155,26 +162,40 @@ __device__ __forceinline__ int stencil_cell_of(const StencilTable<NC> &tab, int 
 // ---------------------------------------------------------------- launchers
 // All launchers enqueue on `st` and return hipGetLastError().
 
-// Binning (counting sort by cell).
-hipError_t launch_bin_count(hipStream_t st, int64_t n, const double *x, const SysDesc *sd,
-                            const int *sys_of, int *cell_of, int *rank, int *count, int *flags);
-hipError_t launch_scan(hipStream_t st, int ncell, int *count, int *start, int64_t n_total);
-hipError_t launch_bin_scatter(hipStream_t st, int64_t n, const int *cell_of, const int *rank,
-                              const int *start, int *tmp);
-hipError_t launch_rank_gather(hipStream_t st, int64_t n, const int *tmp, const int *cell_of,
-                              const int *start, const double *x, const SysDesc *sd,
-                              const int *sys_of, int *perm, int *inv_perm, double *xs,
-                              double *x_ref);
+// Binning (counting sort by cell) of one set of positions into one or two cell grids
+// (the pair-list grid and the triplet grid) with one launch per pass.
+struct BinGrid {
+    const SysDesc *sd;
+    int ncell;
+    int *cell_of;           // [n] global cell id, input order
+    int *rank;              // [n] arrival rank inside the cell (scratch)
+    int *count;             // [ncell] histogram; zero on entry, left zero by the scan
+    int *start;             // [ncell + 1] first sorted slot of each cell
+    int *tmp;               // [n] unordered scatter (scratch)
+    int *perm;              // [n] sorted -> input index
+    int *inv_perm;          // [n] input -> sorted index
+    Pos4 *xs;               // [n] sorted wrapped positions
+    double *x_ref;          // [n][3] wrapped positions in input order, or null
+};
+struct BinArgs {
+    int64_t n;
+    const double *x;        // [n][3] positions, any image
+    const int *sys_of;      // [n]
+    int *flags;
+    int ng;                 // 1 or 2 grids
+    BinGrid g[2];
+};
+hipError_t launch_bin(hipStream_t st, const BinArgs &a);
+// Local (per-system) cell index of every particle, input order.
 hipError_t launch_local_cell_index(hipStream_t st, int64_t n, const int *cell_of,
                                    const SysDesc *sd, const int *sys_of, int *out);
 
-// Pair forces: one wavefront per base cell over its full stencil tile in LDS.
 struct PairArgs {
     int ncell;
     const int *sys_of_cell; // [ncell]
     int stage_cap;          // LDS tile capacity (particles)
     int64_t n;
-    const double *xs;       // sorted wrapped positions, SoA [3][n]
+    const Pos4 *xs;         // [n] sorted wrapped positions
     const int *perm;        // sorted -> input index
     const int *start;       // cell starts [ncell_total + 1]
     const SysDesc *sd;
@@ -183,21 +204,45 @@ struct PairArgs {
     double *pe;             // out [n][2] per-particle {U2/2-sums, W2/2-sums}, sorted order
     double eps, sigma2, rc2, ushift;
     int *flags;
-    // optional pair-list build: neighbours within sqrt(rcv2) of sorted particle p go to
-    // nbr[p * nl_cap + s] (sorted indices, tile order), their number to nn[p]
-    int *nbr;
-    int *nn;
-    int nl_cap;
-    double rcv2;
 };
 hipError_t launch_pair(hipStream_t st, const PairArgs &a, bool fp32);
 
-// Pair forces from the pair list, every inner step between rebuilds.  The displacement
-// of each listed pair is re-derived from the current wrapped positions with the minimum
-// image, so particles may wrap across the box between rebuilds.
+// Verlet pair list of the pair grid: for every sorted particle p, the sorted indices of
+// all particles within sqrt(rv2) (tile order), nbr[p * nl_cap + s], and their number
+// nn[p].  The distance test runs in FP32 on positions relative to the base cell, with a
+// relative margin that covers its rounding, so the list holds at least every pair
+// within the list radius.
+struct ListBuildArgs {
+    int ncell;
+    const int *sys_of_cell;
+    int stage_cap;          // LDS tile capacity (particles)
+    int64_t n;
+    const Pos4 *xs;
+    const int *start;
+    const SysDesc *sd;
+    int *nbr;
+    int *nn;
+    int nl_cap;
+    double rv2;
+    int *flags;
+};
+hipError_t launch_list_build(hipStream_t st, const ListBuildArgs &a);
+size_t list_build_lds_bytes(int stage_cap);
+
+// Pair forces from the pair list, fused with the r-RESPA update of each particle.  The
+// displacement of each listed pair is re-derived from the current wrapped positions with
+// the minimum image, so particles may wrap across the box between rebuilds.  After its
+// force F = F2(x) is summed, particle p (input index q = perm[p]) is updated in
+// Algorithm 2's order with the same expressions as k_int (see IntArgs), F taking the
+// place of F2(x^i):
+//   kick2:  v <- v + dt/(2m) (f2prev + F)
+//   kick3:  v <- v + dt s/(2m) F3, for kick3_end and again for kick3_start
+//   drift:  x <- wrap(x + dt v + dt^2/(2m) F), written to x (input order) and to xs_out
+//           (sorted), and checked against x_ref (skin).
+// xs (read) and xs_out (written) must be different buffers.
 struct PairListArgs {
     int64_t n;
-    const double *xs;       // current wrapped positions in the list's sorted order, SoA
+    const Pos4 *xs;         // current wrapped positions in the list's sorted order
     const int *perm;        // sorted -> input index
     const int *nbr;         // [n][nl_cap]
     const int *nn;          // [n]
@@ -205,9 +250,18 @@ struct PairListArgs {
     const SysDesc *sd;
     const int *sys_of;
     double *f;              // out [n][3], input order
-    double *pe;             // out [n][2], sorted order
+    double *pe;             // out [n][2], sorted order, or null (no energies)
     double eps, sigma2, rc2, ushift;
     int *flags;
+    // fused update (all optional)
+    int kick2, kick3_end, kick3_start, drift;
+    double *x, *v;          // [n][3] input order
+    const double *f2prev;   // F2 of the previous inner position (kick2)
+    const double *f3;       // F3 (kick3)
+    double c2, c3, dt, cx;
+    Pos4 *xs_out;           // [n] sorted positions after the drift
+    const double *x_ref;    // positions at the last list build (input order)
+    double half_skin2;
 };
 hipError_t launch_pair_list(hipStream_t st, const PairListArgs &a, bool fp32);
 size_t pair_lds_bytes(int stage_cap);
@@ -218,7 +272,7 @@ hipError_t configure_kernel_lds(size_t max_bytes);
 // Triplet forces: one workgroup per base cell, forward half stencil in LDS.
 struct TripletArgs {
     int ncell;              // total cells (grid size)
-    const double *xs;
+    const Pos4 *xs;
     const int *start;
     const SysDesc *sd;
     const int *sys_of_cell; // [ncell]
@@ -254,7 +308,7 @@ struct IntArgs {
     const SysDesc *sd;      // any grid: only the box edges are used
     const int *sys_of;
     const int *inv_perm;    // input -> sorted index of the pair grid, or null
-    double *xs;             // sorted positions of the pair grid, or null
+    Pos4 *xs;               // sorted positions of the pair grid, or null
     const double *x_ref;    // positions at the last list build, or null
     double half_skin2;      // (skin / 2)^2
     int *flags;

@@ -34,9 +34,12 @@ __global__ void __launch_bounds__(256) k_int(IntArgs a) {
     }
     if (!a.drift) return;
     if (a.xs) {
-        const int64_t p = a.inv_perm[i];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) a.xs[k * a.n + p] = xn[k];
+        Pos4 w;
+        w.x = xn[0];
+        w.y = xn[1];
+        w.z = xn[2];
+        w.w = 0.0;
+        a.xs[a.inv_perm[i]] = w;
     }
     if (a.x_ref) {
         double dd[3];

@@ -1,16 +1,25 @@
 // Lennard-Jones 12-6 pair forces (Sec. 2.1), evaluated every inner step of r-RESPA
 // (Sec. 4.1, Algorithm 2).
 //
-// GPU formulation: each particle gathers its own force from the full 3x3x3 stencil of
-// linked cells, so no force is ever scattered to another particle (no atomics, a fixed
-// summation order, bitwise-reproducible results).  Newton's third law is not used for
-// pairs: on a GPU it would trade 2x cheaper arithmetic for a scatter of N x 27 partial
-// forces through HBM, which costs more than the pair arithmetic it saves.
+// GPU formulation: each particle gathers its own force from its neighbours, so no force
+// is ever scattered to another particle (no atomics, a fixed summation order,
+// bitwise-reproducible results).  Newton's third law is not used for pairs: on a GPU it
+// would trade 2x cheaper arithmetic for a scatter of partial forces through memory,
+// which costs more than the pair arithmetic it saves.
 //
-// One workgroup (4 wavefronts) per base cell stages the 27 cells of its stencil in LDS
-// once (FP64 positions + image-shift code).  Groups of 16 lanes each take one particle
-// of the base cell and sweep the tile with stride 16; a 4-step shuffle butterfly
-// combines the group.
+// Three kernels:
+//  * k_pair: linked-cell tile kernel.  One workgroup (4 wavefronts) per base cell stages
+//    the 27 cells of its stencil in LDS once (FP64 positions + image shifts); groups of
+//    16 lanes each take one particle of the base cell and sweep the tile with stride 16.
+//    Used for standalone force calls and when no pair list is kept.
+//  * k_list_build: the same stencil on the pair-list grid (cells >= rc + skin), one
+//    wavefront per particle, FP32 distance test, ballot compaction of every neighbour
+//    within rc + skin into the particle's row of the Verlet list.  Runs once per outer
+//    r-RESPA cycle.
+//  * k_pair_list: 16 lanes per particle walk its list row (four gathers in flight per
+//    lane), a DPP butterfly inside the 16-lane row combines them in fixed order, and
+//    the particle's r-RESPA update is fused behind the force (one launch per inner
+//    step).  Energies and virials are summed only when asked for (full steps).
 // Cutoff geometry is always FP64 and canonical (bit-identical pair set in both
 // precisions); T is the precision of the LJ arithmetic.  Forces accumulate in FP64.
 #include "common.h"
@@ -55,17 +64,15 @@ struct alignas(16) PairEnt {
 };
 static_assert(sizeof(PairEnt) == 48, "48-byte LDS entries");
 
-size_t pair_lds_bytes(int cap) { return (size_t)cap * (sizeof(PairEnt) + sizeof(int)); }
+size_t pair_lds_bytes(int cap) { return (size_t)cap * sizeof(PairEnt); }
 
 template <typename T>
 __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     const int CAP = a.stage_cap;
     PairEnt *tile = (PairEnt *)smem_raw;
-    int *tslot = (int *)(tile + CAP);  // sorted index of each tile entry
     const int base = blockIdx.x;
     const int lane = threadIdx.x;  // thread index in the workgroup
-    const int64_t n = a.n;
     const SysDesc &d = a.sd[a.sys_of_cell[base]];
     const int loc = base - d.cell0;
     const int cx = loc % d.nc[0], cy = (loc / d.nc[0]) % d.nc[1], cz = loc / (d.nc[0] * d.nc[1]);
@@ -83,23 +90,21 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
         const int o = stencil_cell_of<kNumFull>(tab, t);
         const int src = tab.begin[o] + (t - tab.off[o]);
         const int code = tab.code[o];
+        const Pos4 ps = a.xs[src];
         PairEnt e;
-        e.x = a.xs[src];
-        e.y = a.xs[n + src];
-        e.z = a.xs[2 * n + src];
+        e.x = ps.x;
+        e.y = ps.y;
+        e.z = ps.z;
         e.sx = (double)((code & 3) - 1) * d.L[0];
         e.sy = (double)(((code >> 2) & 3) - 1) * d.L[1];
         e.sz = (double)(((code >> 4) & 3) - 1) * d.L[2];
         tile[t] = e;
-        tslot[t] = src;
     }
     __syncthreads();
 
     const int g = lane / kPairGroup, r = lane % kPairGroup;  // group and lane in group
     const T sigma2 = (T)a.sigma2, eps24 = (T)(24.0 * a.eps), eps4 = (T)(4.0 * a.eps);
     const int pbase = a.start[base];
-    const bool build = a.nbr != nullptr;
-    const int gshift = kPairGroup * ((lane % kWave) / kPairGroup);  // group's bits in the ballot
     for (int ib = 0; ib < nself; ib += kPairGroups) {
         const int i = ib + g;
         const bool act = i < nself;
@@ -107,10 +112,8 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
         const PairEnt pi = tile[self];
         const int64_t p = pbase + i;
         double fx = 0.0, fy = 0.0, fz = 0.0, u = 0.0, w = 0.0;
-        int cnt = 0;  // pair-list entries of this group's particle (uniform in the group)
         for (int t0 = 0; t0 < nst; t0 += kPairGroup) {
             const int t = t0 + r;
-            bool near = false;
             if (act && t < nst && t != self) {
                 const PairEnt e = tile[t];
                 const double dx = disp1(pi.x, e.x, e.sx);
@@ -126,14 +129,6 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
                     u += (double)e4 - a.ushift;
                     w += (double)(fr * (T)r2);
                 }
-                near = r2 <= a.rcv2;
-            }
-            if (build) {
-                const uint64_t mask = __ballot(near);
-                const unsigned gbits = (unsigned)(mask >> gshift) & 0xffffu;
-                const int pos = cnt + __popc(gbits & ((1u << r) - 1u));
-                if (near && pos < a.nl_cap) a.nbr[p * a.nl_cap + pos] = tslot[t];
-                cnt += __popc(gbits);
             }
         }
 #pragma unroll
@@ -154,82 +149,241 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
             a.pe[2 * p + 1] = 0.5 * w;
             if (!isfinite(fx) || !isfinite(fy) || !isfinite(fz) || !isfinite(u))
                 atomicOr(a.flags, kFlagNonFinite);
-            if (build) {
-                a.nn[p] = min(cnt, a.nl_cap);
-                if (cnt > a.nl_cap) atomicOr(a.flags, kFlagPairList);
-            }
         }
     }
 }
 
-// Per-step pair forces from the list: 8 lanes per particle take every 8th list entry,
-// and a DPP butterfly inside each 8-lane row segment combines them in fixed order.
-constexpr int kListGroup = 8;
+// ---------------------------------------------------------------- pair list build
+// Staged entry: FP32 position relative to the base cell's corner, image shift applied,
+// and the sorted particle index.  16 bytes: consecutive lanes read consecutive
+// ds_read_b128 words without bank conflicts.
+struct alignas(16) BuildEnt {
+    float x, y, z;
+    int slot;
+};
+
+size_t list_build_lds_bytes(int cap) { return (size_t)cap * sizeof(BuildEnt); }
+
+__global__ void __launch_bounds__(kPairThreads) k_list_build(ListBuildArgs a) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    BuildEnt *tile = (BuildEnt *)smem_raw;
+    const int CAP = a.stage_cap;
+    const int base = blockIdx.x;
+    const int lane = threadIdx.x;
+    const SysDesc &d = a.sd[a.sys_of_cell[base]];
+    const int loc = base - d.cell0;
+    const int cx = loc % d.nc[0], cy = (loc / d.nc[0]) % d.nc[1], cz = loc / (d.nc[0] * d.nc[1]);
+    // positions are staged relative to the base cell's corner: small magnitudes, so
+    // FP32 keeps about 1e-7 relative accuracy on every pair distance
+    const double ox = cx * (d.L[0] / d.nc[0]), oy = cy * (d.L[1] / d.nc[1]),
+                 oz = cz * (d.L[2] / d.nc[2]);
+
+    __shared__ StencilTable<kNumFull> tab;
+    int nst = stencil_table<kNumFull, false>(tab, d, cx, cy, cz, a.start);
+    const int s13 = tab.off[13];
+    int nself = tab.off[14] - s13;
+    if (nst > CAP) {
+        if (lane == 0) atomicOr(a.flags, kFlagStageOverflow);
+        nst = CAP;
+        nself = max(0, min(nself, CAP - s13));
+    }
+    for (int t = lane; t < nst; t += kPairThreads) {
+        const int o = stencil_cell_of<kNumFull>(tab, t);
+        const int src = tab.begin[o] + (t - tab.off[o]);
+        const int code = tab.code[o];
+        const Pos4 ps = a.xs[src];
+        BuildEnt e;
+        e.x = (float)((ps.x + (double)((code & 3) - 1) * d.L[0]) - ox);
+        e.y = (float)((ps.y + (double)(((code >> 2) & 3) - 1) * d.L[1]) - oy);
+        e.z = (float)((ps.z + (double)(((code >> 4) & 3) - 1) * d.L[2]) - oz);
+        e.slot = src;
+        tile[t] = e;
+    }
+    __syncthreads();
+
+    // the relative margin (1e-5) dwarfs the FP32 rounding of staged positions and of
+    // the squared distance, so every pair within the list radius is kept
+    const float rv2 = (float)(a.rv2 * (1.0 + 1e-5));
+    const int wave = lane / kWave, wl = lane % kWave;
+    const uint64_t below = wl == 0 ? 0ull : (~0ull >> (kWave - wl));
+    const int pbase = a.start[base];
+    // one wavefront per base-cell particle, all 64 lanes sweeping the tile
+    for (int i = wave; i < nself; i += kPairThreads / kWave) {
+        const int self = s13 + i;
+        const BuildEnt pi = tile[self];
+        const int64_t p = pbase + i;
+        int cnt = 0;
+        for (int t0 = 0; t0 < nst; t0 += kWave) {
+            const int t = t0 + wl;
+            bool near = false;
+            int slot = 0;
+            if (t < nst && t != self) {
+                const BuildEnt e = tile[t];
+                const float dx = e.x - pi.x, dy = e.y - pi.y, dz = e.z - pi.z;
+                near = (dx * dx + dy * dy) + dz * dz <= rv2;
+                slot = e.slot;
+            }
+            const uint64_t mask = __ballot(near);
+            const int pos = cnt + __popcll(mask & below);
+            if (near && pos < a.nl_cap) a.nbr[p * a.nl_cap + pos] = slot;
+            cnt += __popcll(mask);
+        }
+        if (wl == 0) {
+            a.nn[p] = min(cnt, a.nl_cap);
+            if (cnt > a.nl_cap) atomicOr(a.flags, kFlagPairList);
+        }
+    }
+}
+
+hipError_t launch_list_build(hipStream_t st, const ListBuildArgs &a) {
+    if (a.ncell <= 0) return hipSuccess;
+    k_list_build<<<a.ncell, kPairThreads, list_build_lds_bytes(a.stage_cap), st>>>(a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- list forces + update
+constexpr int kListGroup = 16;  // lanes per particle: one DPP row
 
 template <int CTRL>
-__device__ __forceinline__ double dpp8(double v) {
+__device__ __forceinline__ double dpp_row(double v) {
     const long long b = __builtin_bit_cast(long long, v);
     const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
     const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
     return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
 
-__device__ __forceinline__ double sum8(double v) {
-    v += dpp8<0xB1>(v);   // quad_perm [1,0,3,2]
-    v += dpp8<0x4E>(v);   // quad_perm [2,3,0,1]
-    v += dpp8<0x141>(v);  // row_half_mirror: lane i <- lane 7-i within 8
+// Sum over a 16-lane DPP row; every lane of the row ends with the same value.
+__device__ __forceinline__ double sum16(double v) {
+    v += dpp_row<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_row<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_row<0x141>(v);  // row_half_mirror
+    v += dpp_row<0x140>(v);  // row_mirror
     return v;
 }
 
-template <typename T>
+template <typename T, bool ENERGY>
+__device__ __forceinline__ void lj_accumulate(const Pos4 &pi, const Pos4 &e, const double *L,
+                                              const double *iL, double rc2, T sigma2, T eps24,
+                                              T eps4, double ushift, double &fx, double &fy,
+                                              double &fz, double &u, double &w) {
+    // minimum image fl(fl(x_q - x_p) + S), S = -L rint((x_q - x_p) / L) in {-L, 0, +L}:
+    // the product L * rint(.) is exact, so the fma rounds once, like the addition
+    double dx = e.x - pi.x, dy = e.y - pi.y, dz = e.z - pi.z;
+    dx = fma(-L[0], rint(dx * iL[0]), dx);
+    dy = fma(-L[1], rint(dy * iL[1]), dy);
+    dz = fma(-L[2], rint(dz * iL[2]), dz);
+    const double r2 = norm2(dx, dy, dz);
+    if (r2 <= rc2) {
+        T fr, e4;
+        lj_terms<T>(r2, sigma2, eps24, eps4, fr, e4);
+        fx -= (double)(fr * (T)dx);
+        fy -= (double)(fr * (T)dy);
+        fz -= (double)(fr * (T)dz);
+        if (ENERGY) {
+            u += (double)e4 - ushift;
+            w += (double)(fr * (T)r2);
+        }
+    }
+}
+
+// Entries per lane per pass: all their index loads, then all their position gathers,
+// are in flight together.
+constexpr int kListUnroll = 4;
+
+template <typename T, bool ENERGY>
 __global__ void __launch_bounds__(256) k_pair_list(PairListArgs a) {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t p = gid / kListGroup;
     const int r = (int)(gid % kListGroup);
     const bool act = p < a.n;
+
+    // per-particle loads first; the operands of the fused update are then issued
+    // together with the first list indices, so the two latencies overlap (lane r < 3
+    // owns component r of the update)
+    const int64_t pp = act ? p : 0;
+    const int cnt = act ? a.nn[pp] : 0;
+    const Pos4 pi = a.xs[pp];
+    const int64_t q = 3 * (int64_t)a.perm[pp] + (r < 3 ? r : 0);
+    const SysDesc &d = a.sd[a.sys_of[pp]];
+    const double L[3] = {d.L[0], d.L[1], d.L[2]};
+    const double iL[3] = {d.iL[0], d.iL[1], d.iL[2]};
+    const bool upd = act && r < 3 && a.v != nullptr;
+    double vq = 0.0, f2p = 0.0, f3q = 0.0, xq = 0.0, xr = 0.0;
+    if (upd) {
+        vq = a.v[q];
+        if (a.kick2) f2p = a.f2prev[q];
+        if (a.kick3_end || a.kick3_start) f3q = a.f3[q];
+        if (a.drift) {
+            xq = a.x[q];
+            if (a.x_ref) xr = a.x_ref[q];
+        }
+    }
+
     double fx = 0.0, fy = 0.0, fz = 0.0, u = 0.0, w = 0.0;
-    if (act) {
-        const int64_t n = a.n;
-        const SysDesc &d = a.sd[a.sys_of[p]];
-        const double L0 = d.L[0], L1 = d.L[1], L2 = d.L[2];
-        const double h0 = 0.5 * L0, h1 = 0.5 * L1, h2 = 0.5 * L2;
-        const double xp = a.xs[p], yp = a.xs[n + p], zp = a.xs[2 * n + p];
+    {
         const T sigma2 = (T)a.sigma2, eps24 = (T)(24.0 * a.eps), eps4 = (T)(4.0 * a.eps);
-        const int cnt = a.nn[p];
-        const int *row = a.nbr + p * a.nl_cap;
-        for (int s = r; s < cnt; s += kListGroup) {
-            const int64_t q = row[s];
-            // minimum image by comparison: fl(fl(x_q - x_p) + S), S in {-L, 0, +L}
-            double dx = a.xs[q] - xp, dy = a.xs[n + q] - yp, dz = a.xs[2 * n + q] - zp;
-            dx = dx > h0 ? dx - L0 : (dx < -h0 ? dx + L0 : dx);
-            dy = dy > h1 ? dy - L1 : (dy < -h1 ? dy + L1 : dy);
-            dz = dz > h2 ? dz - L2 : (dz < -h2 ? dz + L2 : dz);
-            const double r2 = norm2(dx, dy, dz);
-            if (r2 <= a.rc2) {
-                T fr, e4;
-                lj_terms<T>(r2, sigma2, eps24, eps4, fr, e4);
-                fx -= (double)(fr * (T)dx);
-                fy -= (double)(fr * (T)dy);
-                fz -= (double)(fr * (T)dz);
-                u += (double)e4 - a.ushift;
-                w += (double)(fr * (T)r2);
+        const int *row = a.nbr + pp * a.nl_cap;
+        for (int s0 = r; s0 < cnt; s0 += kListUnroll * kListGroup) {
+            int qn[kListUnroll];
+#pragma unroll
+            for (int k = 0; k < kListUnroll; ++k) {
+                const int s = s0 + k * kListGroup;
+                qn[k] = s < cnt ? row[s] : (int)pp;
+            }
+            Pos4 e[kListUnroll];
+#pragma unroll
+            for (int k = 0; k < kListUnroll; ++k) e[k] = a.xs[qn[k]];
+#pragma unroll
+            for (int k = 0; k < kListUnroll; ++k)
+                if (s0 + k * kListGroup < cnt)
+                    lj_accumulate<T, ENERGY>(pi, e[k], L, iL, a.rc2, sigma2, eps24, eps4, a.ushift,
+                                             fx, fy, fz, u, w);
+        }
+    }
+    fx = sum16(fx);
+    fy = sum16(fy);
+    fz = sum16(fz);
+    if (ENERGY) {
+        u = sum16(u);
+        w = sum16(w);
+    }
+
+    // ---- fused update of component r, in Algorithm 2's order
+    double dd2 = 0.0;
+    if (act && r < 3) {
+        const double F = r == 0 ? fx : (r == 1 ? fy : fz);
+        a.f[q] = F;
+        if (upd) {
+            if (a.kick2) vq = vq + a.c2 * (f2p + F);
+            if (a.kick3_end) vq = vq + a.c3 * f3q;
+            if (a.kick3_start) vq = vq + a.c3 * f3q;
+            a.v[q] = vq;
+            if (a.drift) {
+                const double Lr = L[r];
+                const double xn = wrap1(xq + a.dt * vq + a.cx * F, Lr);
+                a.x[q] = xn;
+                if (a.xs_out) reinterpret_cast<double *>(a.xs_out + p)[r] = xn;
+                if (a.x_ref) {
+                    double t = xn - xr;
+                    const double h = 0.5 * Lr;
+                    t = t > h ? t - Lr : (t < -h ? t + Lr : t);
+                    dd2 = t * t;
+                }
             }
         }
     }
-    fx = sum8(fx);
-    fy = sum8(fy);
-    fz = sum8(fz);
-    u = sum8(u);
-    w = sum8(w);
+    // displacement since the list build: (dx^2 + dy^2) + dz^2 in lane r = 0
+    const double d1 = __shfl_down(dd2, 1, kListGroup);
+    const double d2 = __shfl_down(dd2, 2, kListGroup);
     if (act && r == 0) {
-        const int64_t q = a.perm[p];
-        a.f[3 * q] = fx;
-        a.f[3 * q + 1] = fy;
-        a.f[3 * q + 2] = fz;
-        a.pe[2 * p] = 0.5 * u;
-        a.pe[2 * p + 1] = 0.5 * w;
-        if (!isfinite(fx) || !isfinite(fy) || !isfinite(fz) || !isfinite(u))
+        if (ENERGY) {
+            a.pe[2 * p] = 0.5 * u;
+            a.pe[2 * p + 1] = 0.5 * w;
+        }
+        if (!isfinite(fx) || !isfinite(fy) || !isfinite(fz) || (ENERGY && !isfinite(u)))
             atomicOr(a.flags, kFlagNonFinite);
+        if (upd && a.drift && a.x_ref && !((dd2 + d1) + d2 <= a.half_skin2))
+            atomicOr(a.flags, kFlagSkin);
     }
 }
 
@@ -237,17 +391,22 @@ hipError_t launch_pair_list(hipStream_t st, const PairListArgs &a, bool fp32) {
     const int64_t threads = a.n * kListGroup;
     const unsigned blocks = (unsigned)((threads + 255) / 256);
     if (blocks == 0) return hipSuccess;
-    if (fp32)
-        k_pair_list<float><<<blocks, 256, 0, st>>>(a);
-    else
-        k_pair_list<double><<<blocks, 256, 0, st>>>(a);
+    const bool energy = a.pe != nullptr;
+    if (fp32) {
+        if (energy) k_pair_list<float, true><<<blocks, 256, 0, st>>>(a);
+        else k_pair_list<float, false><<<blocks, 256, 0, st>>>(a);
+    } else {
+        if (energy) k_pair_list<double, true><<<blocks, 256, 0, st>>>(a);
+        else k_pair_list<double, false><<<blocks, 256, 0, st>>>(a);
+    }
     return hipGetLastError();
 }
 
 hipError_t configure_triplet_lds(size_t max_bytes);
 
 hipError_t configure_kernel_lds(size_t max_bytes) {
-    const void *fns[] = {(const void *)k_pair<double>, (const void *)k_pair<float>};
+    const void *fns[] = {(const void *)k_pair<double>, (const void *)k_pair<float>,
+                         (const void *)k_list_build};
     for (const void *f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_bytes);
         if (e != hipSuccess) return e;

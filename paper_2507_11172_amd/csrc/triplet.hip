@@ -207,10 +207,11 @@ __global__ void __launch_bounds__(kTripThreads) k_triplet(TripletArgs a) {
         const int o = stencil_cell_of<kNumHalf>(tab, t);
         const int src = tab.begin[o] + (t - tab.off[o]);
         const int code = tab.code[o];
+        const Pos4 ps = a.xs[src];
         TileEnt e;
-        e.x = a.xs[src];
-        e.y = a.xs[n + src];
-        e.z = a.xs[2 * n + src];
+        e.x = ps.x;
+        e.y = ps.y;
+        e.z = ps.z;
         e.sx = (double)((code & 3) - 1) * L0;
         e.sy = (double)(((code >> 2) & 3) - 1) * L1;
         e.sz = (double)(((code >> 4) & 3) - 1) * L2;
