@@ -183,7 +183,7 @@ void size_tiles(mts_system *s) {
     const double rc3 = s->p.rc_triplet, rv = s->p.rc_pair + s->skin;
     s->stage_cap = std::min(2048, round_up((int)std::ceil(kNumHalf * vt * 1.1) + 16, 32));
     s->pair_cap = std::min(2048, round_up((int)std::ceil(kNumFull * vp * 1.1) + 16, 32));
-    s->list_cap = std::min(1024, round_up((int)std::ceil(1.6 * rho_t * (2.0 / 3.0) * M_PI * rc3 * rc3 * rc3) + 16, 32));
+    s->list_cap = std::min(1024, round_up((int)std::ceil(1.3 * rho_t * (2.0 / 3.0) * M_PI * rc3 * rc3 * rc3) + 16, 16));
     s->nl_cap = std::min(2048, round_up((int)std::ceil(1.3 * rho_p * (4.0 / 3.0) * M_PI * rv * rv * rv) + 16, 32));
 }
 
@@ -251,6 +251,7 @@ mts_status alloc_all(mts_system *s) {
     }
     if (n > 0) HIP_TRY(s, hipMemcpy(s->sys_of, so.data(), sizeof(int) * n, hipMemcpyHostToDevice));
     HIP_TRY(s, hipMemset(s->flags, 0, sizeof(int)));
+    HIP_TRY(s, hipMemset(s->ce, 0, 2 * sizeof(double) * s->gt.ncell));
     HIP_TRY(s, hipMemset(s->pf, 0, sizeof(double) * kNumHalf * 3 * (n > 0 ? n : 1)));
     return MTS_OK;
 }
@@ -430,7 +431,8 @@ mts_status enqueue_pair_list(mts_system *s, const Pos4 *xs_in, double *f2, const
     return MTS_OK;
 }
 
-mts_status enqueue_triplet(mts_system *s, double *f3, int *list_ijk, long long list_rows) {
+mts_status enqueue_triplet(mts_system *s, double *f3, int *list_ijk, long long list_rows,
+                           bool energy) {
     const Grid &g = s->gt;
     TripletArgs a{};
     a.ncell = g.ncell;
@@ -440,7 +442,7 @@ mts_status enqueue_triplet(mts_system *s, double *f3, int *list_ijk, long long l
     a.sys_of_cell = g.sys_of_cell;
     a.perm = g.perm;
     a.pf = s->pf;
-    a.ce = s->ce;
+    a.ce = energy ? s->ce : nullptr;
     a.cc = s->cc;
     a.n = s->n;
     a.nu = s->p.nu;
@@ -466,7 +468,7 @@ mts_status enqueue_reduce(mts_system *s, const double *v, bool pair, bool trip, 
     a.v = v;
     a.half_mass = 0.5 * s->p.mass;
     a.pe = pair ? s->pe : nullptr;
-    a.ce = trip ? s->ce : nullptr;
+    a.ce = trip && out ? s->ce : nullptr;  // energies are only written when asked for
     a.cc = trip ? s->cc : nullptr;
     a.out = out;
     a.stride = stride;
@@ -513,22 +515,22 @@ mts_status enqueue_int(mts_system *s, const double *f2prev, const double *f2cur,
 
 // Rebins both grids at the internal positions, rebuilds the pair list and computes F3
 // into s->f3 (list mode); the caller then computes F2 from the new list.
-mts_status enqueue_full_step_list(mts_system *s) {
+mts_status enqueue_full_step_list(mts_system *s, bool energy) {
     MTS_TRY(enqueue_bin(s, kBinPair | kBinTriplet, s->xi, true));
     MTS_TRY(enqueue_list_build(s));
-    MTS_TRY(enqueue_triplet(s, s->f3, nullptr, 0));
+    MTS_TRY(enqueue_triplet(s, s->f3, nullptr, 0, energy));
     return MTS_OK;
 }
 
 // Forces at the internal positions x^0 of a call: F3 into s->f3, F2 into f2.
-mts_status enqueue_entry_forces(mts_system *s, double *f2) {
+mts_status enqueue_entry_forces(mts_system *s, double *f2, bool energy) {
     if (s->skin > 0.0) {
-        MTS_TRY(enqueue_full_step_list(s));
+        MTS_TRY(enqueue_full_step_list(s, energy));
         MTS_TRY(enqueue_pair_list(s, s->gp.xs, f2, Fused{}, true));
     } else {
         MTS_TRY(enqueue_bin(s, kBinPair | kBinTriplet, s->xi, false));
         MTS_TRY(enqueue_pair(s, f2));
-        MTS_TRY(enqueue_triplet(s, s->f3, nullptr, 0));
+        MTS_TRY(enqueue_triplet(s, s->f3, nullptr, 0, energy));
     }
     return MTS_OK;
 }
@@ -557,7 +559,7 @@ mts_status enqueue_cycle(mts_system *s, double *f2_0, double *f2_1, bool energie
             u.xs_out = i + 1 < k ? buf[(i + 1) & 1] : nullptr;  // x^k: a rebinning follows
             MTS_TRY(enqueue_pair_list(s, buf[i & 1], f2[i & 1], u, false));
         }
-        MTS_TRY(enqueue_full_step_list(s));
+        MTS_TRY(enqueue_full_step_list(s, energies));
         Fused u;
         u.kick2 = true;
         u.kick3_end = true;
@@ -570,7 +572,7 @@ mts_status enqueue_cycle(mts_system *s, double *f2_0, double *f2_1, bool energie
             if (i == k - 1) {
                 MTS_TRY(enqueue_bin(s, kBinPair | kBinTriplet, s->xi, false));
                 MTS_TRY(enqueue_pair(s, next));
-                MTS_TRY(enqueue_triplet(s, s->f3, nullptr, 0));
+                MTS_TRY(enqueue_triplet(s, s->f3, nullptr, 0, energies));
             } else {
                 MTS_TRY(enqueue_bin(s, kBinPair, s->xi, false));
                 MTS_TRY(enqueue_pair(s, next));
@@ -622,7 +624,7 @@ mts_status respa_internal(mts_system *s, double *x, double *v, int64_t n_iter, d
         HIP_TRY(s, hipMemcpyAsync(s->vi, v, bytes, hipMemcpyDeviceToDevice, s->st));
     }
     // Algorithm 2, lines 1-2: F2(x^0), F3(x^0); energies of x^0 in row 0
-    MTS_TRY(enqueue_entry_forces(s, s->f2a));
+    MTS_TRY(enqueue_entry_forces(s, s->f2a, energies));
     if (energies) {
         HIP_TRY(s, launch_set_int(s->st, s->row, 0));
         MTS_TRY(enqueue_reduce(s, s->vi, true, true, s->e_buf, kNE, s->row, nullptr));
@@ -784,7 +786,7 @@ mts_status mts_compute_triplet_forces(mts_system *sys, const double *x, double *
     if (!sys) return MTS_ERR_INVALID_ARG;
     if ((!x || !f3) && sys->n > 0) return fail(sys, MTS_ERR_INVALID_ARG, "x or f3 is NULL");
     MTS_TRY(enqueue_bin(sys, kBinTriplet, x, false));
-    MTS_TRY(enqueue_triplet(sys, f3, nullptr, 0));
+    MTS_TRY(enqueue_triplet(sys, f3, nullptr, 0, ew != nullptr));
     if (ew) MTS_TRY(enqueue_reduce(sys, nullptr, false, true, ew, 2, nullptr, nullptr));
     return MTS_OK;
 }
@@ -885,7 +887,7 @@ mts_status mts_get_cell_index(mts_system *sys, int32_t *cell) {
 mts_status mts_count_triplets(mts_system *sys, const double *x, int64_t *count) {
     if (!sys || !count || (!x && sys->n > 0)) return MTS_ERR_INVALID_ARG;
     MTS_TRY(enqueue_bin(sys, kBinTriplet, x, false));
-    MTS_TRY(enqueue_triplet(sys, nullptr, nullptr, 0));
+    MTS_TRY(enqueue_triplet(sys, nullptr, nullptr, 0, false));
     MTS_TRY(enqueue_reduce(sys, nullptr, false, true, nullptr, 2, nullptr, sys->cnt_sys));
     std::vector<long long> c(sys->nsys);
     HIP_TRY(sys, hipMemcpyAsync(c.data(), sys->cnt_sys, sizeof(long long) * sys->nsys,
@@ -903,7 +905,7 @@ mts_status mts_list_triplets(mts_system *sys, const double *x, int32_t *ijk, int
     if (!ijk || cap == 0) return mts_count_triplets(sys, x, n);
     HIP_TRY(sys, hipMemsetAsync(sys->list_n, 0, sizeof(unsigned long long), sys->st));
     MTS_TRY(enqueue_bin(sys, kBinTriplet, x, false));
-    MTS_TRY(enqueue_triplet(sys, nullptr, ijk, cap));
+    MTS_TRY(enqueue_triplet(sys, nullptr, ijk, cap, false));
     unsigned long long total = 0;
     HIP_TRY(sys, hipMemcpyAsync(&total, sys->list_n, sizeof(unsigned long long), hipMemcpyDeviceToHost, sys->st));
     MTS_TRY(mts_sync(sys));

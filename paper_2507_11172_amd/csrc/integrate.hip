@@ -95,8 +95,9 @@ __global__ void __launch_bounds__(kRed) k_reduce_part(ReduceArgs a) {
         for (int q = cb + t; q < ce; q += kRed) {
             u3 += a.ce[2 * q];
             w3 += a.ce[2 * q + 1];
-            if (a.cc) cnt += (double)a.cc[q];
         }
+    if (a.cc)
+        for (int q = cb + t; q < ce; q += kRed) cnt += (double)a.cc[q];
     kin = block_sum(kin, red);
     u2 = block_sum(u2, red);
     w2 = block_sum(w2, red);

@@ -17,13 +17,14 @@
 //    round-robin.
 //  * Per anchor (one wave):
 //      A. filter the tile to the anchor's forward neighbours within rc3 -- ballot +
-//         prefix-count compaction into the wave's list (tile index, displacement u from
-//         the anchor, |u|^2);
+//         prefix-count compaction into the wave's list (a copy of the tile entry, the
+//         displacement u from the anchor and |u|^2, the tile index);
 //      B. each lane owns one list entry j (kept in registers) and walks its partners
-//         k = j + 1 .. j + m/2 around the list, so all m(m-1)/2 pairs are visited once
-//         with balanced lanes; the third edge j-k is tested with the canonical FP64
-//         displacement and hits are compacted into a queue;
-//      C. evaluate ATM on full waves of queued hits.
+//         k = j + 1 .. j + m/2 around the list, two per round, so all m(m-1)/2 pairs
+//         are visited once with balanced lanes; the third edge j-k is tested with the
+//         canonical FP64 displacement and hits are compacted into a queue;
+//      C. evaluate ATM two queued hits per lane (two independent chains in flight)
+//         once 128 are pending, and on the rest at the end of the anchor.
 //  * Accumulation.  The anchor's force stays in registers and is summed across the wave
 //    with DPP row operations; partner forces go to the wave's per-list-slot FP64
 //    partials (LDS atomics inside one wave: a fixed order).  When the anchor is done,
@@ -43,59 +44,60 @@ namespace mts {
 
 constexpr int kTripWaves = 4;
 constexpr int kTripThreads = kTripWaves * kWave;
-constexpr int kQueueCap = 2 * kWave;
+// Hit queue: evaluated two hits per lane once 2 x 64 are pending; one round of tests
+// pushes at most 2 x 64 more.
+constexpr int kQueueCap = 4 * kWave;
 
 // LDS layout.  Entries read by consecutive lanes are 48-byte structures read as three
 // 16-byte words: an odd multiple of 16 bytes is free of bank conflicts for
 // ds_read_b128 across 16 lanes.  Accumulators updated at scattered addresses are
 // structure-of-arrays.
-struct alignas(16) TileEnt {   // one staged particle
-    double x, y, z;            // wrapped FP64 position
-    double sx, sy, sz;         // image shift (0 or +-L) seen from the base cell
+struct alignas(16) PosEnt {    // a staged particle: wrapped FP64 position and the image
+    double x, y, z;            // shift (0 or +-L per component) seen from the base cell
+    double sx, sy, sz;
 };
 
-struct alignas(16) ListEnt {   // one forward neighbour of the current anchor
-    double ux, uy, uz, a;      // canonical displacement anchor -> partner, and |u|^2
-    int t;                     // tile index
-    int pad0;
-    double pad1;
+struct alignas(16) DispEnt {   // forward neighbour j of the current anchor: canonical
+    double ux, uy, uz, a;      // displacement anchor -> j and its square |u|^2
 };
 
-static_assert(sizeof(TileEnt) == 48 && sizeof(ListEnt) == 48, "48-byte LDS entries");
+static_assert(sizeof(PosEnt) == 48 && sizeof(DispEnt) == 32, "LDS entry sizes");
 
 struct Tile {                  // staged neighbour cells, CAP entries
-    TileEnt *e;
+    PosEnt *e;
     double *fx, *fy, *fz;      // force accumulators
-    int *o;                    // half-stencil offset index (selects the partial slot)
-    int *slot;                 // sorted particle index
 };
 
 struct List {                  // one wave's forward-neighbour list, LC entries
-    ListEnt *e;
+    PosEnt *pos;               // copy of the tile entry (the j-k cutoff test)
+    DispEnt *u;                // displacement from the anchor (the ATM arithmetic)
     double *px, *py, *pz;      // partner force partials of the current anchor
+    int *t;                    // tile index
     int *q;                    // hit queue, kQueueCap entries: j | k << 16
 };
 
 size_t triplet_lds_bytes(int cap, int lcap) {
-    return (size_t)cap * (sizeof(TileEnt) + 3 * sizeof(double) + 2 * sizeof(int)) +
-           (size_t)kTripWaves * lcap * (sizeof(ListEnt) + 3 * sizeof(double)) +
+    return (size_t)cap * (sizeof(PosEnt) + 3 * sizeof(double)) +
+           (size_t)kTripWaves * lcap * (sizeof(PosEnt) + sizeof(DispEnt) + 3 * sizeof(double) + sizeof(int)) +
            (size_t)kTripWaves * kQueueCap * sizeof(int);
 }
 
-// Carves the dynamic LDS block (cap and lc are multiples of 32, so every array starts
-// 16-byte aligned): 48-byte entries, then doubles, then ints.
+// Carves the dynamic LDS block (cap is a multiple of 32 and lc of 16, so every array
+// starts 16-byte aligned): 48- and 32-byte entries, then doubles, then ints.
 __device__ __forceinline__ void carve(unsigned char *raw, int cap, int lc, int wave, Tile &T,
                                       List &L) {
-    T.e = (TileEnt *)raw;
-    ListEnt *le = (ListEnt *)(T.e + cap);
-    L.e = le + (size_t)wave * lc;
-    double *dp = (double *)(le + (size_t)kTripWaves * lc);
+    T.e = (PosEnt *)raw;
+    PosEnt *lp = T.e + cap;
+    L.pos = lp + (size_t)wave * lc;
+    DispEnt *lu = (DispEnt *)(lp + (size_t)kTripWaves * lc);
+    L.u = lu + (size_t)wave * lc;
+    double *dp = (double *)(lu + (size_t)kTripWaves * lc);
     T.fx = dp; T.fy = dp + cap; T.fz = dp + 2 * cap;
     double *pw = dp + 3 * (size_t)cap + (size_t)wave * 3 * lc;
     L.px = pw; L.py = pw + lc; L.pz = pw + 2 * lc;
     int *ip = (int *)(dp + 3 * (size_t)cap + (size_t)kTripWaves * 3 * lc);
-    T.o = ip; T.slot = ip + cap;
-    L.q = ip + 2 * cap + (size_t)wave * kQueueCap;
+    L.t = ip + (size_t)wave * lc;
+    L.q = ip + (size_t)kTripWaves * lc + (size_t)wave * kQueueCap;
 }
 
 // 1/sqrt(x): hardware estimate refined by two Newton-Raphson steps y <- y (3 - x y^2)/2
@@ -141,6 +143,39 @@ __device__ __forceinline__ void atm_terms(T a, T b, T c, T nu, T &phi, T &ga, T 
     phi = nu * fma(q, tt, p32);
 }
 
+// One queued triplet (anchor, j, k): forces on all three members (j and k as list
+// partials, the anchor's in the caller's registers), energy and virial.
+template <typename T>
+struct AtmOut {
+    T fix, fiy, fiz, fjx, fjy, fjz, fkx, fky, fkz, phi, vir;
+};
+
+template <typename T>
+__device__ __forceinline__ AtmOut<T> atm_triplet(const DispEnt &lj, const DispEnt &lk, T nu) {
+    // third edge for the force arithmetic: v = w - u (the cutoff test used the canonical
+    // displacement; the two differ by rounding only)
+    const T ux = (T)lj.ux, uy = (T)lj.uy, uz = (T)lj.uz;
+    const T wx = (T)lk.ux, wy = (T)lk.uy, wz = (T)lk.uz;
+    const T vx = wx - ux, vy = wy - uy, vz = wz - uz;
+    const T cc = (vx * vx + vy * vy) + vz * vz;
+    const T aa = (T)lj.a, bb = (T)lk.a;
+    T phi, ga, gb, gc;
+    atm_terms<T>(aa, bb, cc, nu, phi, ga, gb, gc);
+    AtmOut<T> o;
+    o.fix = fma(ga, ux, gb * wx);
+    o.fiy = fma(ga, uy, gb * wy);
+    o.fiz = fma(ga, uz, gb * wz);
+    o.fjx = fma(gc, vx, -ga * ux);
+    o.fjy = fma(gc, vy, -ga * uy);
+    o.fjz = fma(gc, vz, -ga * uz);
+    o.fkx = -(o.fix + o.fjx);
+    o.fky = -(o.fiy + o.fjy);
+    o.fkz = -(o.fiz + o.fjz);
+    o.phi = phi;
+    o.vir = -fma(aa, ga, fma(bb, gb, cc * gc));
+    return o;
+}
+
 // Wave-wide sum landing in lane 63, by DPP: quad swaps, half-row and row mirrors, then
 // row broadcasts 15 and 31 (fixed order, so bitwise reproducible).  Returned to every
 // lane through a read of lane 63.
@@ -165,17 +200,13 @@ __device__ __forceinline__ double wave_sum(double v) {
     return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
 
-__device__ __forceinline__ int wave_sum_int(int v) {
-    v += __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xf, 0xf, false);
-    v += __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xf, 0xf, false);
-    v += __builtin_amdgcn_update_dpp(0, v, 0x141, 0xf, 0xf, false);
-    v += __builtin_amdgcn_update_dpp(0, v, 0x140, 0xf, 0xf, false);
-    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);
-    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);
-    return __builtin_amdgcn_readlane(v, 63);
+// Sorted particle index of tile entry t (debug listing only).
+__device__ __forceinline__ int tile_slot(const StencilTable<kNumHalf> &tab, int t) {
+    const int o = stencil_cell_of<kNumHalf>(tab, t);
+    return tab.begin[o] + (t - tab.off[o]);
 }
 
-template <typename T, bool LIST>
+template <typename T, bool LIST, bool ENERGY>
 __global__ void __launch_bounds__(kTripThreads) k_triplet(TripletArgs a) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     __shared__ int s_turn;
@@ -208,7 +239,7 @@ __global__ void __launch_bounds__(kTripThreads) k_triplet(TripletArgs a) {
         const int src = tab.begin[o] + (t - tab.off[o]);
         const int code = tab.code[o];
         const Pos4 ps = a.xs[src];
-        TileEnt e;
+        PosEnt e;
         e.x = ps.x;
         e.y = ps.y;
         e.z = ps.z;
@@ -216,8 +247,6 @@ __global__ void __launch_bounds__(kTripThreads) k_triplet(TripletArgs a) {
         e.sy = (double)(((code >> 2) & 3) - 1) * L1;
         e.sz = (double)(((code >> 4) & 3) - 1) * L2;
         tile.e[t] = e;
-        tile.o[t] = code >> 8;
-        tile.slot[t] = src;
         tile.fx[t] = 0.0;
         tile.fy[t] = 0.0;
         tile.fz[t] = 0.0;
@@ -230,41 +259,44 @@ __global__ void __launch_bounds__(kTripThreads) k_triplet(TripletArgs a) {
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
     int *Q = L.q;
     double U = 0.0, W = 0.0;
-    int ntrip = 0;
+    int ntrip = 0;  // wave-uniform
 
     for (int ia = wave; ia < nself; ia += kTripWaves) {
-        const TileEnt an = tile.e[ia];  // anchor: base cell, zero shift
-        // ---- A: forward neighbours of the anchor within rc3 (tile order > ia)
+        const PosEnt an = tile.e[ia];  // anchor: base cell, zero shift
+        // ---- A: forward neighbours of the anchor within rc3 (tile order > ia), two
+        // tile entries per lane per round; the compaction keeps tile order
         int m = 0;
-        for (int t0 = ia + 1; t0 < nst; t0 += kWave) {
-            const int t = t0 + lane;
-            bool in = false;
-            double dx = 0, dy = 0, dz = 0, r2 = 0;
-            if (t < nst) {
-                const TileEnt e = tile.e[t];
-                dx = disp1(an.x, e.x, e.sx);
-                dy = disp1(an.y, e.y, e.sy);
-                dz = disp1(an.z, e.z, e.sz);
-                r2 = norm2(dx, dy, dz);
-                in = r2 <= rc2;
-            }
-            const uint64_t mask = __ballot(in);
-            const int pos = m + __popcll(mask & lt_mask);
+        auto keep = [&](bool in, int pos, int t, const PosEnt &e, double dx, double dy,
+                        double dz, double r2) {
             if (in && pos < LC) {
-                ListEnt le;
-                le.ux = dx;
-                le.uy = dy;
-                le.uz = dz;
-                le.a = r2;
-                le.t = t;
-                le.pad0 = 0;
-                le.pad1 = 0.0;
-                L.e[pos] = le;
+                L.pos[pos] = e;
+                DispEnt de;
+                de.ux = dx;
+                de.uy = dy;
+                de.uz = dz;
+                de.a = r2;
+                L.u[pos] = de;
+                L.t[pos] = t;
                 L.px[pos] = 0.0;
                 L.py[pos] = 0.0;
                 L.pz[pos] = 0.0;
             }
-            m += __popcll(mask);
+        };
+        for (int t0 = ia + 1; t0 < nst; t0 += 2 * kWave) {
+            const int t1 = t0 + lane, t2 = t0 + kWave + lane;
+            const PosEnt e1 = tile.e[t1 < nst ? t1 : ia];
+            const PosEnt e2 = tile.e[t2 < nst ? t2 : ia];
+            const double dx1 = disp1(an.x, e1.x, e1.sx), dy1 = disp1(an.y, e1.y, e1.sy),
+                         dz1 = disp1(an.z, e1.z, e1.sz);
+            const double dx2 = disp1(an.x, e2.x, e2.sx), dy2 = disp1(an.y, e2.y, e2.sy),
+                         dz2 = disp1(an.z, e2.z, e2.sz);
+            const double r21 = norm2(dx1, dy1, dz1), r22 = norm2(dx2, dy2, dz2);
+            const bool in1 = t1 < nst && r21 <= rc2, in2 = t2 < nst && r22 <= rc2;
+            const uint64_t m1 = __ballot(in1), m2 = __ballot(in2);
+            const int n1 = __popcll(m1);
+            keep(in1, m + __popcll(m1 & lt_mask), t1, e1, dx1, dy1, dz1, r21);
+            keep(in2, m + n1 + __popcll(m2 & lt_mask), t2, e2, dx2, dy2, dz2, r22);
+            m += n1 + __popcll(m2);
         }
         if (m > LC) {
             if (lane == 0) atomicOr(a.flags, kFlagListOverflow);
@@ -272,101 +304,118 @@ __global__ void __launch_bounds__(kTripThreads) k_triplet(TripletArgs a) {
         }
         __builtin_amdgcn_wave_barrier();
 
-        // ---- B + C
+        // ---- B + C: j-k tests, queued hits evaluated two per lane
         double fax = 0.0, fay = 0.0, faz = 0.0;
-        int qn = 0;
-        auto evaluate = [&](int cnt) {
-            if (lane < cnt) {
-                const int e = Q[lane];
-                const int j = e & 0xffff, k = e >> 16;
-                const ListEnt lj = L.e[j], lk = L.e[k];
-                const double uxd = lj.ux, uyd = lj.uy, uzd = lj.uz, ad = lj.a;
-                const double wxd = lk.ux, wyd = lk.uy, wzd = lk.uz, bd = lk.a;
-                // third edge for the force arithmetic: v = w - u (the cutoff test used the
-                // canonical displacement; the two differ by rounding only)
-                const T ux = (T)uxd, uy = (T)uyd, uz = (T)uzd;
-                const T wx = (T)wxd, wy = (T)wyd, wz = (T)wzd;
-                const T vx = wx - ux, vy = wy - uy, vz = wz - uz;
-                const T cc = (vx * vx + vy * vy) + vz * vz;
-                const T aa = (T)ad, bb = (T)bd;
-                T phi, ga, gb, gc;
-                atm_terms<T>(aa, bb, cc, nu, phi, ga, gb, gc);
-                const T fix = fma(ga, ux, gb * wx), fiy = fma(ga, uy, gb * wy),
-                        fiz = fma(ga, uz, gb * wz);
-                const T fjx = fma(gc, vx, -ga * ux), fjy = fma(gc, vy, -ga * uy),
-                        fjz = fma(gc, vz, -ga * uz);
-                const T fkx = -(fix + fjx), fky = -(fiy + fjy), fkz = -(fiz + fjz);
-                fax += (double)fix;
-                fay += (double)fiy;
-                faz += (double)fiz;
-                atomicAdd(&L.px[j], (double)fjx);
-                atomicAdd(&L.py[j], (double)fjy);
-                atomicAdd(&L.pz[j], (double)fjz);
-                atomicAdd(&L.px[k], (double)fkx);
-                atomicAdd(&L.py[k], (double)fky);
-                atomicAdd(&L.pz[k], (double)fkz);
-                U += (double)phi;
-                W -= (double)fma(aa, ga, fma(bb, gb, cc * gc));
-                ++ntrip;
-                if (LIST) {
-                    const long long s = (long long)atomicAdd(a.list_n, 1ull);
-                    if (s < a.list_rows) {
-                        const int p0 = a.perm[tile.slot[ia]], p1 = a.perm[tile.slot[lj.t]],
-                                  p2 = a.perm[tile.slot[lk.t]];
-                        const int lo = min(p0, min(p1, p2)), hi = max(p0, max(p1, p2));
-                        a.list_ijk[3 * s] = lo;
-                        a.list_ijk[3 * s + 1] = p0 + p1 + p2 - lo - hi;
-                        a.list_ijk[3 * s + 2] = hi;
-                    }
+        int qn = 0;  // wave-uniform
+        auto scatter = [&](const AtmOut<T> &o, int j, int k) {
+            atomicAdd(&L.px[j], (double)o.fjx);
+            atomicAdd(&L.py[j], (double)o.fjy);
+            atomicAdd(&L.pz[j], (double)o.fjz);
+            atomicAdd(&L.px[k], (double)o.fkx);
+            atomicAdd(&L.py[k], (double)o.fky);
+            atomicAdd(&L.pz[k], (double)o.fkz);
+            if (LIST) {
+                const long long sidx = (long long)atomicAdd(a.list_n, 1ull);
+                if (sidx < a.list_rows) {
+                    const int p0 = a.perm[tile_slot(tab, ia)];
+                    const int p1 = a.perm[tile_slot(tab, L.t[j])];
+                    const int p2 = a.perm[tile_slot(tab, L.t[k])];
+                    const int lo = min(p0, min(p1, p2)), hi = max(p0, max(p1, p2));
+                    a.list_ijk[3 * sidx] = lo;
+                    a.list_ijk[3 * sidx + 1] = p0 + p1 + p2 - lo - hi;
+                    a.list_ijk[3 * sidx + 2] = hi;
                 }
             }
-            __builtin_amdgcn_wave_barrier();
         };
-        auto push = [&](bool hit, int j, int k) {
-            const uint64_t mask = __ballot(hit);
-            if (hit) Q[qn + __popcll(mask & lt_mask)] = j | (k << 16);
-            qn += __popcll(mask);
-            __builtin_amdgcn_wave_barrier();
-            if (qn >= kWave) {
-                evaluate(kWave);
-                qn -= kWave;
-                int rest = 0;
-                if (lane < qn) rest = Q[kWave + lane];
-                __builtin_amdgcn_wave_barrier();
-                if (lane < qn) Q[lane] = rest;
-                __builtin_amdgcn_wave_barrier();
+        // Two queued hits per lane, computed as two independent straight-line chains
+        // (lanes without a second hit recompute their first, lanes without any hit
+        // compute on entry 0; such results are selected away).  The register sums take
+        // both chains unconditionally, which keeps the compiler from sinking the second
+        // chain behind the first one's scatter.
+        auto evaluate = [&](int cnt) {
+            const bool v1 = lane < cnt, v2 = lane + kWave < cnt;
+            const int e1 = v1 ? Q[lane] : 0;
+            const int e2 = v2 ? Q[lane + kWave] : e1;
+            const int j1 = e1 & 0xffff, k1 = e1 >> 16, j2 = e2 & 0xffff, k2 = e2 >> 16;
+            const DispEnt uj1 = L.u[j1], uk1 = L.u[k1], uj2 = L.u[j2], uk2 = L.u[k2];
+            const AtmOut<T> o1 = atm_triplet<T>(uj1, uk1, nu);
+            const AtmOut<T> o2 = atm_triplet<T>(uj2, uk2, nu);
+            fax += v1 ? (double)o1.fix : 0.0;
+            fay += v1 ? (double)o1.fiy : 0.0;
+            faz += v1 ? (double)o1.fiz : 0.0;
+            fax += v2 ? (double)o2.fix : 0.0;
+            fay += v2 ? (double)o2.fiy : 0.0;
+            faz += v2 ? (double)o2.fiz : 0.0;
+            if (ENERGY) {
+                U += v1 ? (double)o1.phi : 0.0;
+                W += v1 ? (double)o1.vir : 0.0;
+                U += v2 ? (double)o2.phi : 0.0;
+                W += v2 ? (double)o2.vir : 0.0;
             }
+            if (v1) scatter(o1, j1, k1);
+            if (v2) scatter(o2, j2, k2);
+            __builtin_amdgcn_wave_barrier();
         };
 
         if (m >= 2) {
             const int D = m >> 1;
             const bool even = (m & 1) == 0;
             // Lane -> (j, phase): with P = max(1, 64 / m) phases, lane l takes entry
-            // j = jb + l % span and circular distances dd = 1 + phase, 1 + phase + P, ...
+            // j = jb + l % span and the circular distances dd = 1 + phase + 2 P r and
+            // 1 + phase + (2 r + 1) P in round r, so all m(m-1)/2 pairs j < k (as
+            // unordered pairs) are tested once: dd <= D, and for even m the distance D
+            // only from j < D.
             const int P = m < kWave ? kWave / m : 1;
             const int span = m < kWave ? m : kWave;
             for (int jb = 0; jb < m; jb += span) {
                 const int j = jb + lane % span;
                 const int phase = lane / span;
                 const bool lane_ok = phase < P && j < m;
-                TileEnt ej{};
-                if (lane_ok) ej = tile.e[L.e[j].t];
-                for (int d0 = 1; d0 <= D; d0 += P) {
-                    const int dd = d0 + phase;
-                    int k = j + dd;
-                    if (k >= m) k -= m;
-                    bool hit = false;
-                    if (lane_ok && dd <= D && !(even && dd == D && j >= D)) {
-                        const TileEnt ek = tile.e[L.e[k].t];
-                        const double vx = disp1(ej.x, ek.x, ek.sx - ej.sx);
-                        const double vy = disp1(ej.y, ek.y, ek.sy - ej.sy);
-                        const double vz = disp1(ej.z, ek.z, ek.sz - ej.sz);
-                        hit = norm2(vx, vy, vz) <= rc2;
+                PosEnt ej{};
+                if (lane_ok) ej = L.pos[j];
+                for (int d0 = 1; d0 <= D; d0 += 2 * P) {
+                    const int dd1 = d0 + phase, dd2 = d0 + P + phase;
+                    int k1 = j + dd1, k2 = j + dd2;
+                    if (k1 >= m) k1 -= m;
+                    if (k2 >= m) k2 -= m;
+                    const bool c1 = lane_ok && dd1 <= D && !(even && dd1 == D && j >= D);
+                    const bool c2 = lane_ok && dd2 <= D && !(even && dd2 == D && j >= D);
+                    bool hit1 = false, hit2 = false;
+                    if (c1) {  // c2 implies c1; both tests run as straight-line code
+                        const PosEnt ek1 = L.pos[k1];
+                        const PosEnt ek2 = L.pos[c2 ? k2 : k1];
+                        const double vx1 = disp1(ej.x, ek1.x, ek1.sx - ej.sx);
+                        const double vy1 = disp1(ej.y, ek1.y, ek1.sy - ej.sy);
+                        const double vz1 = disp1(ej.z, ek1.z, ek1.sz - ej.sz);
+                        const double vx2 = disp1(ej.x, ek2.x, ek2.sx - ej.sx);
+                        const double vy2 = disp1(ej.y, ek2.y, ek2.sy - ej.sy);
+                        const double vz2 = disp1(ej.z, ek2.z, ek2.sz - ej.sz);
+                        hit1 = norm2(vx1, vy1, vz1) <= rc2;
+                        hit2 = c2 && norm2(vx2, vy2, vz2) <= rc2;
                     }
-                    push(hit, j, k);
+                    const uint64_t m1 = __ballot(hit1), m2 = __ballot(hit2);
+                    const int n1 = __popcll(m1);
+                    if (hit1) Q[qn + __popcll(m1 & lt_mask)] = j | (k1 << 16);
+                    if (hit2) Q[qn + n1 + __popcll(m2 & lt_mask)] = j | (k2 << 16);
+                    qn += n1 + __popcll(m2);
+                    __builtin_amdgcn_wave_barrier();
+                    if (qn >= 2 * kWave) {
+                        evaluate(2 * kWave);
+                        ntrip += 2 * kWave;
+                        qn -= 2 * kWave;
+                        const int r1 = lane < qn ? Q[2 * kWave + lane] : 0;
+                        const int r2 = lane + kWave < qn ? Q[3 * kWave + lane] : 0;
+                        __builtin_amdgcn_wave_barrier();
+                        if (lane < qn) Q[lane] = r1;
+                        if (lane + kWave < qn) Q[kWave + lane] = r2;
+                        __builtin_amdgcn_wave_barrier();
+                    }
                 }
             }
-            if (qn > 0) evaluate(qn);
+            if (qn > 0) {
+                evaluate(qn);
+                ntrip += qn;
+            }
         }
         fax = wave_sum(fax);
         fay = wave_sum(fay);
@@ -380,7 +429,7 @@ __global__ void __launch_bounds__(kTripThreads) k_triplet(TripletArgs a) {
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         for (int t = lane; t < m; t += kWave) {
-            const int te = L.e[t].t;
+            const int te = L.t[t];
             tile.fx[te] += L.px[t];
             tile.fy[te] += L.py[t];
             tile.fz[te] += L.pz[t];
@@ -393,9 +442,10 @@ __global__ void __launch_bounds__(kTripThreads) k_triplet(TripletArgs a) {
         __builtin_amdgcn_wave_barrier();
         if (lane == 0) __hip_atomic_store(&s_turn, ia + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
-    U = wave_sum(U);
-    W = wave_sum(W);
-    ntrip = wave_sum_int(ntrip);
+    if (ENERGY) {
+        U = wave_sum(U);
+        W = wave_sum(W);
+    }
     if (lane == 0) {
         s_red[wave][0] = U;
         s_red[wave][1] = W;
@@ -405,23 +455,25 @@ __global__ void __launch_bounds__(kTripThreads) k_triplet(TripletArgs a) {
 
     // ---- flush the tile's forces: slot (offset, particle) has exactly one writer
     for (int t = tid; t < nst; t += kTripThreads) {
-        const int o = tile.o[t];
-        const int64_t p = tile.slot[t];
+        const int o = stencil_cell_of<kNumHalf>(tab, t);
+        const int64_t p = tab.begin[o] + (t - tab.off[o]);
         a.pf[(3 * o) * n + p] = tile.fx[t];
         a.pf[(3 * o + 1) * n + p] = tile.fy[t];
         a.pf[(3 * o + 2) * n + p] = tile.fz[t];
     }
     if (tid == 0) {
-        double u = 0.0, w = 0.0;
         long long c = 0;
-        for (int q = 0; q < kTripWaves; ++q) {
-            u += s_red[q][0];
-            w += s_red[q][1];
-            c += s_cnt[q];
-        }
-        a.ce[2 * base] = u;
-        a.ce[2 * base + 1] = w;
+        for (int q = 0; q < kTripWaves; ++q) c += s_cnt[q];
         a.cc[base] = c;
+        if (ENERGY) {
+            double u = 0.0, w = 0.0;
+            for (int q = 0; q < kTripWaves; ++q) {
+                u += s_red[q][0];
+                w += s_red[q][1];
+            }
+            a.ce[2 * base] = u;
+            a.ce[2 * base + 1] = w;
+        }
     }
 }
 
@@ -444,22 +496,32 @@ __global__ void __launch_bounds__(256) k_triplet_gather(int64_t n, const double 
     if (!isfinite(s[0]) || !isfinite(s[1]) || !isfinite(s[2])) atomicOr(flags, kFlagNonFinite);
 }
 
-template <typename T, bool LIST>
+template <typename T, bool LIST, bool ENERGY>
 static hipError_t launch_triplet_t(hipStream_t st, const TripletArgs &a) {
     const size_t lds = triplet_lds_bytes(a.stage_cap, a.list_cap);
-    k_triplet<T, LIST><<<a.ncell, kTripThreads, lds, st>>>(a);
+    k_triplet<T, LIST, ENERGY><<<a.ncell, kTripThreads, lds, st>>>(a);
     return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_triplet_p(hipStream_t st, const TripletArgs &a, bool listing) {
+    if (listing) return launch_triplet_t<T, true, false>(st, a);
+    if (a.ce) return launch_triplet_t<T, false, true>(st, a);
+    return launch_triplet_t<T, false, false>(st, a);
 }
 
 hipError_t launch_triplet(hipStream_t st, const TripletArgs &a, bool fp32, bool listing) {
     if (a.ncell <= 0) return hipSuccess;
-    if (listing) return fp32 ? launch_triplet_t<float, true>(st, a) : launch_triplet_t<double, true>(st, a);
-    return fp32 ? launch_triplet_t<float, false>(st, a) : launch_triplet_t<double, false>(st, a);
+    return fp32 ? launch_triplet_p<float>(st, a, listing) : launch_triplet_p<double>(st, a, listing);
 }
 
 hipError_t configure_triplet_lds(size_t max_bytes) {
-    const void *fns[] = {(const void *)k_triplet<double, false>, (const void *)k_triplet<float, false>,
-                         (const void *)k_triplet<double, true>, (const void *)k_triplet<float, true>};
+    const void *fns[] = {(const void *)k_triplet<double, false, false>,
+                         (const void *)k_triplet<double, false, true>,
+                         (const void *)k_triplet<double, true, false>,
+                         (const void *)k_triplet<float, false, false>,
+                         (const void *)k_triplet<float, false, true>,
+                         (const void *)k_triplet<float, true, false>};
     for (const void *f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_bytes);
         if (e != hipSuccess) return e;

@@ -61,6 +61,10 @@ def load_library(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise ImportError("libmts.so is not built (%s); run __graft_entry__.build() or "
                           "python paper_2507_11172_amd/build.py" % path)
+    # PyTorch ships its own HIP runtime under the same soname as the system one.  Loading
+    # torch first makes libmts.so bind to that runtime, so that device pointers from torch
+    # tensors and the library's own allocations live in one HIP context.
+    import torch  # noqa: F401
     L = C.CDLL(path)
     vp = C.c_void_p
     L.mts_init_system.argtypes = [C.POINTER(mts_params), C.c_int32, C.POINTER(C.c_int64),
