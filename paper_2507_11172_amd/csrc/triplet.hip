@@ -64,34 +64,36 @@ struct alignas(16) DispEnt {   // forward neighbour j of the current anchor: can
 static_assert(sizeof(PosEnt) == 48 && sizeof(DispEnt) == 32, "LDS entry sizes");
 
 struct Tile {                  // staged neighbour cells, CAP entries
-    PosEnt *e;
+    PosEnt *e;                 // FP64 (canonical tests, displacements)
+    float4 *r;                 // FP32 position relative to the base cell (prefilter)
     double *fx, *fy, *fz;      // force accumulators
 };
 
 struct List {                  // one wave's forward-neighbour list, LC entries
-    PosEnt *pos;               // copy of the tile entry (the j-k cutoff test)
-    DispEnt *u;                // displacement from the anchor (the ATM arithmetic)
+    DispEnt *u;                // FP64 displacement from the anchor (ATM arithmetic)
+    float4 *f;                 // the same in FP32 (j-k prefilter)
     double *px, *py, *pz;      // partner force partials of the current anchor
     int *t;                    // tile index
     int *q;                    // hit queue, kQueueCap entries: j | k << 16
 };
 
 size_t triplet_lds_bytes(int cap, int lcap) {
-    return (size_t)cap * (sizeof(PosEnt) + 3 * sizeof(double)) +
-           (size_t)kTripWaves * lcap * (sizeof(PosEnt) + sizeof(DispEnt) + 3 * sizeof(double) + sizeof(int)) +
+    return (size_t)cap * (sizeof(PosEnt) + sizeof(float4) + 3 * sizeof(double)) +
+           (size_t)kTripWaves * lcap * (sizeof(DispEnt) + sizeof(float4) + 3 * sizeof(double) + sizeof(int)) +
            (size_t)kTripWaves * kQueueCap * sizeof(int);
 }
 
 // Carves the dynamic LDS block (cap is a multiple of 32 and lc of 16, so every array
-// starts 16-byte aligned): 48- and 32-byte entries, then doubles, then ints.
+// starts 16-byte aligned): 48-, 32- and 16-byte entries, then doubles, then ints.
 __device__ __forceinline__ void carve(unsigned char *raw, int cap, int lc, int wave, Tile &T,
                                       List &L) {
     T.e = (PosEnt *)raw;
-    PosEnt *lp = T.e + cap;
-    L.pos = lp + (size_t)wave * lc;
-    DispEnt *lu = (DispEnt *)(lp + (size_t)kTripWaves * lc);
+    DispEnt *lu = (DispEnt *)(T.e + cap);
     L.u = lu + (size_t)wave * lc;
-    double *dp = (double *)(lu + (size_t)kTripWaves * lc);
+    float4 *fr = (float4 *)(lu + (size_t)kTripWaves * lc);
+    T.r = fr;
+    L.f = fr + cap + (size_t)wave * lc;
+    double *dp = (double *)(fr + cap + (size_t)kTripWaves * lc);
     T.fx = dp; T.fy = dp + cap; T.fz = dp + 2 * cap;
     double *pw = dp + 3 * (size_t)cap + (size_t)wave * 3 * lc;
     L.px = pw; L.py = pw + lc; L.pz = pw + 2 * lc;
@@ -99,6 +101,13 @@ __device__ __forceinline__ void carve(unsigned char *raw, int cap, int lc, int w
     L.t = ip + (size_t)wave * lc;
     L.q = ip + (size_t)kTripWaves * lc + (size_t)wave * kQueueCap;
 }
+
+// FP32 prefilter of a cutoff test.  Positions relative to the base cell (|x| < 3 h <=
+// 6 rc) and displacements from the anchor (|u| <= rc) carry FP32 errors below 1e-6
+// relative to rc^2 in a squared distance, so a relative band of 1e-5 around rc^2
+// separates certain hits (below), certain misses (above) and the rare ambiguous cases,
+// which are settled by the canonical FP64 test: the triplet set is exactly the FP64 one.
+constexpr float kPrefilterBand = 1e-5f;
 
 // 1/sqrt(x): hardware estimate refined by two Newton-Raphson steps y <- y (3 - x y^2)/2
 // (quadratic convergence from the ~2^-22 estimate to below one FP64 ulp of error).
@@ -222,6 +231,7 @@ __global__ void __launch_bounds__(kTripThreads) k_triplet(TripletArgs a) {
     const int loc = base - d.cell0;
     const int cx = loc % d.nc[0], cy = (loc / d.nc[0]) % d.nc[1], cz = loc / (d.nc[0] * d.nc[1]);
     const double L0 = d.L[0], L1 = d.L[1], L2 = d.L[2];
+    const double ox = cx * (L0 / d.nc[0]), oy = cy * (L1 / d.nc[1]), oz = cz * (L2 / d.nc[2]);
     Tile tile;
     List L;
     carve(smem_raw, CAP, LC, wave, tile, L);
@@ -247,6 +257,8 @@ __global__ void __launch_bounds__(kTripThreads) k_triplet(TripletArgs a) {
         e.sy = (double)(((code >> 2) & 3) - 1) * L1;
         e.sz = (double)(((code >> 4) & 3) - 1) * L2;
         tile.e[t] = e;
+        tile.r[t] = make_float4((float)((e.x + e.sx) - ox), (float)((e.y + e.sy) - oy),
+                               (float)((e.z + e.sz) - oz), 0.0f);
         tile.fx[t] = 0.0;
         tile.fy[t] = 0.0;
         tile.fz[t] = 0.0;
@@ -256,6 +268,8 @@ __global__ void __launch_bounds__(kTripThreads) k_triplet(TripletArgs a) {
 
     const T nu = (T)a.nu;
     const double rc2 = a.rc2;
+    const float pf_lo = (float)rc2 * (1.0f - kPrefilterBand);
+    const float pf_hi = (float)rc2 * (1.0f + kPrefilterBand);
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
     int *Q = L.q;
     double U = 0.0, W = 0.0;
@@ -263,44 +277,58 @@ __global__ void __launch_bounds__(kTripThreads) k_triplet(TripletArgs a) {
 
     for (int ia = wave; ia < nself; ia += kTripWaves) {
         const PosEnt an = tile.e[ia];  // anchor: base cell, zero shift
-        // ---- A: forward neighbours of the anchor within rc3 (tile order > ia), two
-        // tile entries per lane per round; the compaction keeps tile order
+        const float4 ar = tile.r[ia];
+        // ---- A1: FP32 prefilter of the tile entries after the anchor (tile order);
+        // certain and ambiguous candidates are compacted into L.t, in tile order
+        int mc = 0;
+        for (int t0 = ia + 1; t0 < nst; t0 += 2 * kWave) {
+            const int t1 = t0 + lane, t2 = t0 + kWave + lane;
+            const float4 r1 = tile.r[t1 < nst ? t1 : ia];
+            const float4 r2 = tile.r[t2 < nst ? t2 : ia];
+            const float x1 = r1.x - ar.x, y1 = r1.y - ar.y, z1 = r1.z - ar.z;
+            const float x2 = r2.x - ar.x, y2 = r2.y - ar.y, z2 = r2.z - ar.z;
+            const bool in1 = t1 < nst && (x1 * x1 + y1 * y1) + z1 * z1 <= pf_hi;
+            const bool in2 = t2 < nst && (x2 * x2 + y2 * y2) + z2 * z2 <= pf_hi;
+            const uint64_t m1 = __ballot(in1), m2 = __ballot(in2);
+            const int n1 = __popcll(m1);
+            const int p1 = mc + __popcll(m1 & lt_mask), p2 = mc + n1 + __popcll(m2 & lt_mask);
+            if (in1 && p1 < LC) L.t[p1] = t1;
+            if (in2 && p2 < LC) L.t[p2] = t2;
+            mc += n1 + __popcll(m2);
+        }
+        if (mc > LC) {
+            if (lane == 0) atomicOr(a.flags, kFlagListOverflow);
+            mc = LC;
+        }
+        __builtin_amdgcn_wave_barrier();
+        // ---- A2: canonical FP64 displacement and test of every candidate; the final
+        // list keeps the candidates' (tile) order
         int m = 0;
-        auto keep = [&](bool in, int pos, int t, const PosEnt &e, double dx, double dy,
-                        double dz, double r2) {
-            if (in && pos < LC) {
-                L.pos[pos] = e;
+        for (int c0 = 0; c0 < mc; c0 += kWave) {
+            const int c = c0 + lane;
+            const int t = c < mc ? L.t[c] : ia;
+            const PosEnt e = tile.e[t];
+            const double dx = disp1(an.x, e.x, e.sx), dy = disp1(an.y, e.y, e.sy),
+                         dz = disp1(an.z, e.z, e.sz);
+            const double r2 = norm2(dx, dy, dz);
+            const bool in = c < mc && r2 <= rc2;
+            const uint64_t mk = __ballot(in);
+            const int pos = m + __popcll(mk & lt_mask);
+            __builtin_amdgcn_wave_barrier();  // all reads of this round before the writes
+            if (in) {
                 DispEnt de;
                 de.ux = dx;
                 de.uy = dy;
                 de.uz = dz;
                 de.a = r2;
                 L.u[pos] = de;
+                L.f[pos] = make_float4((float)dx, (float)dy, (float)dz, 0.0f);
                 L.t[pos] = t;
                 L.px[pos] = 0.0;
                 L.py[pos] = 0.0;
                 L.pz[pos] = 0.0;
             }
-        };
-        for (int t0 = ia + 1; t0 < nst; t0 += 2 * kWave) {
-            const int t1 = t0 + lane, t2 = t0 + kWave + lane;
-            const PosEnt e1 = tile.e[t1 < nst ? t1 : ia];
-            const PosEnt e2 = tile.e[t2 < nst ? t2 : ia];
-            const double dx1 = disp1(an.x, e1.x, e1.sx), dy1 = disp1(an.y, e1.y, e1.sy),
-                         dz1 = disp1(an.z, e1.z, e1.sz);
-            const double dx2 = disp1(an.x, e2.x, e2.sx), dy2 = disp1(an.y, e2.y, e2.sy),
-                         dz2 = disp1(an.z, e2.z, e2.sz);
-            const double r21 = norm2(dx1, dy1, dz1), r22 = norm2(dx2, dy2, dz2);
-            const bool in1 = t1 < nst && r21 <= rc2, in2 = t2 < nst && r22 <= rc2;
-            const uint64_t m1 = __ballot(in1), m2 = __ballot(in2);
-            const int n1 = __popcll(m1);
-            keep(in1, m + __popcll(m1 & lt_mask), t1, e1, dx1, dy1, dz1, r21);
-            keep(in2, m + n1 + __popcll(m2 & lt_mask), t2, e2, dx2, dy2, dz2, r22);
-            m += n1 + __popcll(m2);
-        }
-        if (m > LC) {
-            if (lane == 0) atomicOr(a.flags, kFlagListOverflow);
-            m = LC;
+            m += __popcll(mk);
         }
         __builtin_amdgcn_wave_barrier();
 
@@ -371,8 +399,8 @@ __global__ void __launch_bounds__(kTripThreads) k_triplet(TripletArgs a) {
                 const int j = jb + lane % span;
                 const int phase = lane / span;
                 const bool lane_ok = phase < P && j < m;
-                PosEnt ej{};
-                if (lane_ok) ej = L.pos[j];
+                float4 fj = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                if (lane_ok) fj = L.f[j];
                 for (int d0 = 1; d0 <= D; d0 += 2 * P) {
                     const int dd1 = d0 + phase, dd2 = d0 + P + phase;
                     int k1 = j + dd1, k2 = j + dd2;
@@ -380,18 +408,34 @@ __global__ void __launch_bounds__(kTripThreads) k_triplet(TripletArgs a) {
                     if (k2 >= m) k2 -= m;
                     const bool c1 = lane_ok && dd1 <= D && !(even && dd1 == D && j >= D);
                     const bool c2 = lane_ok && dd2 <= D && !(even && dd2 == D && j >= D);
-                    bool hit1 = false, hit2 = false;
-                    if (c1) {  // c2 implies c1; both tests run as straight-line code
-                        const PosEnt ek1 = L.pos[k1];
-                        const PosEnt ek2 = L.pos[c2 ? k2 : k1];
-                        const double vx1 = disp1(ej.x, ek1.x, ek1.sx - ej.sx);
-                        const double vy1 = disp1(ej.y, ek1.y, ek1.sy - ej.sy);
-                        const double vz1 = disp1(ej.z, ek1.z, ek1.sz - ej.sz);
-                        const double vx2 = disp1(ej.x, ek2.x, ek2.sx - ej.sx);
-                        const double vy2 = disp1(ej.y, ek2.y, ek2.sy - ej.sy);
-                        const double vz2 = disp1(ej.z, ek2.z, ek2.sz - ej.sz);
-                        hit1 = norm2(vx1, vy1, vz1) <= rc2;
-                        hit2 = c2 && norm2(vx2, vy2, vz2) <= rc2;
+                    // c2 implies c1; both tests run as straight-line code
+                    const float4 fk1 = L.f[c1 ? k1 : 0];
+                    const float4 fk2 = L.f[c2 ? k2 : 0];
+                    const float vx1 = fk1.x - fj.x, vy1 = fk1.y - fj.y, vz1 = fk1.z - fj.z;
+                    const float vx2 = fk2.x - fj.x, vy2 = fk2.y - fj.y, vz2 = fk2.z - fj.z;
+                    const float q1 = (vx1 * vx1 + vy1 * vy1) + vz1 * vz1;
+                    const float q2 = (vx2 * vx2 + vy2 * vy2) + vz2 * vz2;
+                    bool hit1 = c1 && q1 <= pf_lo, hit2 = c2 && q2 <= pf_lo;
+                    const bool amb1 = c1 && q1 > pf_lo && q1 <= pf_hi;
+                    const bool amb2 = c2 && q2 > pf_lo && q2 <= pf_hi;
+                    if (__ballot(amb1 || amb2)) {  // rare: settle with the FP64 test
+                        if (amb1 || amb2) {
+                            const PosEnt ej = tile.e[L.t[j]];
+                            const PosEnt ek = tile.e[L.t[amb1 ? k1 : k2]];
+                            const double vx = disp1(ej.x, ek.x, ek.sx - ej.sx);
+                            const double vy = disp1(ej.y, ek.y, ek.sy - ej.sy);
+                            const double vz = disp1(ej.z, ek.z, ek.sz - ej.sz);
+                            const bool h = norm2(vx, vy, vz) <= rc2;
+                            if (amb1) hit1 = h;
+                            else hit2 = h;
+                            if (amb1 && amb2) {
+                                const PosEnt ek2 = tile.e[L.t[k2]];
+                                const double wx = disp1(ej.x, ek2.x, ek2.sx - ej.sx);
+                                const double wy = disp1(ej.y, ek2.y, ek2.sy - ej.sy);
+                                const double wz = disp1(ej.z, ek2.z, ek2.sz - ej.sz);
+                                hit2 = norm2(wx, wy, wz) <= rc2;
+                            }
+                        }
                     }
                     const uint64_t m1 = __ballot(hit1), m2 = __ballot(hit2);
                     const int n1 = __popcll(m1);

@@ -84,6 +84,36 @@ def test_triplet_set_bit_exact(case):
     assert np.array_equal(g, ref.astype(np.int64))
 
 
+def test_exact_shell_at_cutoff():
+    """Perfect FCC with a = 1.25: positions, differences and squared distances are exact
+    in FP64, and a whole neighbour shell lies exactly at rc = 2.5 (inclusive).  Every
+    such edge falls in the FP32 prefilters' ambiguous band and is settled by the FP64
+    test; the triplet set and the energies must match the oracle's exactly."""
+    torch = _torch()
+    x = W.fcc_sites((5, 5, 5), np.full(3, 1.25))
+    box = np.full(3, 6.25)
+    n = x.shape[0]
+    w = W.Workload("shell", x, np.zeros_like(x), box[None, :], np.array([n]), np.array([0.0]))
+    ref = oracle.triplet_list(x, box, rc=2.5)
+    r2 = oracle.pair_forces(x, box, rc=2.5)
+    r3 = oracle.triplet_forces(x, box, rc=2.5)
+    with _system(w) as s:
+        xd = _dev(x)
+        got, total = s.list_triplets(xd, ref.shape[0] + 16)
+        e2 = torch.zeros((1, 2), dtype=torch.float64, device="cuda")
+        e3 = torch.zeros((1, 2), dtype=torch.float64, device="cuda")
+        f = torch.empty_like(xd)
+        s.compute_pair_forces(xd, f, e2)
+        s.compute_triplet_forces(xd, f, e3)
+        s.sync()
+    assert total == ref.shape[0]
+    g = got.cpu().numpy().astype(np.int64)
+    g = g[np.lexsort((g[:, 2], g[:, 1], g[:, 0]))]
+    assert np.array_equal(g, ref.astype(np.int64))
+    assert e2.cpu().numpy()[0, 0] == pytest.approx(r2.energy, rel=1e-12)
+    assert e3.cpu().numpy()[0, 0] == pytest.approx(r3.energy, rel=1e-12)
+
+
 @pytest.mark.parametrize("case", ["fcc500", "smallbox", "fcc256"])
 def test_fp64_forces_and_energies(case):
     torch = _torch()
