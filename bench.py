@@ -1,14 +1,21 @@
 """Benchmark: r-RESPA MD steps/s and three-body triplets/s on one MI355X.
 
-One bench "step" is one r-RESPA outer cycle (Sec. 4.1, Algorithm 2): k inner steps,
-each with cell binning, Lennard-Jones forces and the velocity-Verlet updates, plus one
-Axilrod-Teller-Muto evaluation with its kicks and the energy reductions of that full
-step.  The timed region is a single respa_step call of steps * k inner steps on inputs
-already resident in HBM.
+One bench "step" is one r-RESPA outer cycle (Sec. 4.1, Algorithm 2): k inner steps with
+Lennard-Jones forces and the velocity-Verlet updates, plus one Axilrod-Teller-Muto
+evaluation with its kicks and the energy reductions of that full step.  The timed region
+is a single respa_step call of steps * k inner steps on inputs already resident in HBM.
 
 Default workload: 32,000 particles (20^3 FCC cells, rho 0.8, T 0.7, jitter 0.05), LJ
-eps = sigma = 1 with rc 2.5, ATM nu = 0.073 with rc3 2.5, dt 0.001, k = 10, FP64.
-Prints one JSON line.
+eps = sigma = 1 with rc 2.5, ATM nu = 0.073 with rc3 2.5, dt 0.001, k = 10, FP64, with
+the FP32 form and the CPU oracle timed beside it.  Other workloads (--workload):
+  fcc500   500 particles, k = 1 (velocity Verlet), FP64
+  fcc1m    1,048,576 particles (64^3 FCC cells), FP32 form (--k to sweep 1, 5, 10, 20)
+  slab25   500,000-particle liquid slab + vapour, 1:1:3 box, rc3 2.5, FP32 form, k = 10
+  slab30   the same with rc3 3.0
+  batched  256 replicas of 200..20,000 particles in one handle, FP32 form, k = 10, with
+           the same replicas run one handle at a time for comparison
+Prints one JSON line.  For several systems "value" is the aggregate over systems
+(system inner steps per second).
 """
 from __future__ import annotations
 
@@ -24,20 +31,26 @@ if ROOT not in sys.path:
 
 METRIC = "3-body triplets/s + r-RESPA MD steps/s, FP32 vs FP64 GPU at stated force error"
 # Algorithmic work per in-cutoff ATM triplet (edge, ATM arithmetic, three forces and their
-# accumulation; FMA = 2), and the published MI355X vector peaks.
+# accumulation; FMA = 2), and the published MI355X vector peaks (the FP32 figure assumes
+# packed FP32 instructions, which this build does not emit: its FP32 arithmetic runs at
+# the unpacked rate, equal to the FP64 one).
 FLOPS_PER_TRIPLET = 100.0
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
 
 
 def _workload(name: str):
     from paper_2507_11172_amd import workloads as W
-    if name == "fcc32k":
-        return W.fp64_at_scale()
-    if name == "fcc500":
-        return W.plain_fp64()
-    if name == "fcc1m":
-        return W.precision_form(10)
-    raise SystemExit("unknown workload %s" % name)
+    table = {
+        "fcc32k": W.fp64_at_scale,
+        "fcc500": W.plain_fp64,
+        "fcc1m": lambda: W.precision_form(10),
+        "slab25": lambda: W.inhomogeneous(2.5),
+        "slab30": lambda: W.inhomogeneous(3.0),
+        "batched": W.batched,
+    }
+    if name not in table:
+        raise SystemExit("unknown workload %s (one of %s)" % (name, ", ".join(table)))
+    return table[name]()
 
 
 def _params(w, precision: str, k: int):
@@ -46,8 +59,17 @@ def _params(w, precision: str, k: int):
                       rc_triplet=w.rc_triplet, mass=w.mass, dt=w.dt, k=k, precision=precision)
 
 
-def run_gpu(w, precision: str, k: int, steps: int, warmup: int):
+def _drift_stats(en, n_particles):
+    """Energy drift per particle and RVITE (Eq. 4) per system from the full-step records
+    [rows][systems][K, U2, U3, W2, W3]; means over systems."""
     import numpy as np
+    tot = en[:, :, 0] + en[:, :, 1] + en[:, :, 2]
+    drift = np.abs(tot[-1] - tot[0]) / n_particles
+    rvite = np.mean(np.abs(tot - tot.mean(axis=0)), axis=0) / np.mean(en[:, :, 0], axis=0)
+    return float(drift.mean()), float(rvite.mean())
+
+
+def run_gpu(w, precision: str, k: int, steps: int, warmup: int):
     import torch
     from paper_2507_11172_amd import mts
 
@@ -55,12 +77,23 @@ def run_gpu(w, precision: str, k: int, steps: int, warmup: int):
     sysm = mts.System(_params(w, precision, k), w.n_particles.tolist(), w.box)
     x = torch.tensor(w.x, dtype=torch.float64, device=dev)
     v = torch.tensor(w.v, dtype=torch.float64, device=dev)
-    if warmup > 0:
-        sysm.respa_step(x, v, warmup * k)
-    sysm.sync()
+    x0, v0 = x.clone(), v.clone()
+    for attempt in range(3):
+        if warmup > 0:
+            sysm.respa_step(x, v, warmup * k)
+        try:
+            sysm.sync()
+            break
+        except mts.MTSError as err:
+            # a tile or list outgrew its initial size: the library has enlarged it, and
+            # the warm-up is repeated from the initial state
+            if err.code != mts.MTS_ERR_CAPACITY or attempt == 2:
+                raise
+            x.copy_(x0)
+            v.copy_(v0)
+    e = torch.zeros((steps + 1, w.n_systems, mts.MTS_NE), dtype=torch.float64, device=dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    e = torch.zeros((steps + 1, w.n_systems, mts.MTS_NE), dtype=torch.float64, device=dev)
     sysm.respa_step(x, v, steps * k, e)
     sysm.sync()
     torch.cuda.synchronize()
@@ -73,9 +106,8 @@ def run_gpu(w, precision: str, k: int, steps: int, warmup: int):
     sysm.enable_kernel_timing(False)
     n_trip = sysm.count_triplets(x)
     sysm.sync()
-    en = e.cpu().numpy()[:, 0, :]
-    tot = en[:, 0] + en[:, 1] + en[:, 2]
     sysm.close()
+    drift, rvite = _drift_stats(e.cpu().numpy(), w.n_particles)
     trip_launches, trip_ms = times["triplet"]
     pair_launches, pair_ms = times["pair"]
     return {
@@ -84,11 +116,61 @@ def run_gpu(w, precision: str, k: int, steps: int, warmup: int):
         "triplets_per_eval": n_trip,
         "triplet_kernel_ms": trip_ms / max(trip_launches, 1),
         "pair_kernel_ms": pair_ms / max(pair_launches, 1),
-        "triplet_launches": trip_launches,
-        "pair_launches": pair_launches,
-        "energy_drift_per_particle": float(abs(tot[-1] - tot[0]) / w.n_total),
-        "rvite": float(np.mean(np.abs(tot - tot.mean())) / np.mean(en[:, 0])),
+        "energy_drift_per_particle": drift,
+        "rvite": rvite,
     }
+
+
+def run_per_system_loop(w, precision: str, k: int, steps: int):
+    """The same replicas, one handle each, stepped one after another: aggregate system
+    inner steps per second of that launch loop."""
+    import torch
+    from paper_2507_11172_amd import mts
+
+    dev = torch.device("cuda:0")
+    handles, xs, vs = [], [], []
+    off = 0
+    for r in range(w.n_systems):
+        n = int(w.n_particles[r])
+        handles.append(mts.System(_params(w, precision, k), [n], w.box[r:r + 1]))
+        xs.append(torch.tensor(w.x[off:off + n], dtype=torch.float64, device=dev))
+        vs.append(torch.tensor(w.v[off:off + n], dtype=torch.float64, device=dev))
+        off += n
+    for h, x, v in zip(handles, xs, vs):  # warm-up: graphs captured, caches sized
+        for attempt in range(3):
+            h.respa_step(x, v, k)
+            try:
+                h.sync()
+                break
+            except mts.MTSError as err:
+                if err.code != mts.MTS_ERR_CAPACITY or attempt == 2:
+                    raise
+    x0 = [x.clone() for x in xs]
+    v0 = [v.clone() for v in vs]
+    for attempt in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for h, x, v in zip(handles, xs, vs):
+            h.respa_step(x, v, steps * k)
+        grown = False
+        for h in handles:
+            try:
+                h.sync()
+            except mts.MTSError as err:
+                # a replica's list outgrew its size mid-run: enlarged, timed again
+                if err.code != mts.MTS_ERR_CAPACITY or attempt == 2:
+                    raise
+                grown = True
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        if not grown:
+            break
+        for x, v, a, b in zip(xs, vs, x0, v0):
+            x.copy_(a)
+            v.copy_(b)
+    for h in handles:
+        h.close()
+    return w.n_systems * steps * k / elapsed
 
 
 def cpu_baseline(w, k: int):
@@ -113,15 +195,19 @@ def cpu_baseline(w, k: int):
 
 
 def main(argv=None):
-    ap = argparse.ArgumentParser(description=__doc__)
+    ap = argparse.ArgumentParser(description=__doc__,
+                                 formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100, help="timed r-RESPA outer cycles")
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="fcc32k")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--precision", default="", choices=["", "fp64", "fp32"],
+                    help="default: fp64 for fcc32k and fcc500, the FP32 form otherwise")
     ap.add_argument("--k", type=int, default=0, help="override the step-size factor")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32-form", action="store_true")
+    ap.add_argument("--loop-steps", type=int, default=5,
+                    help="cycles of the one-handle-per-replica loop (batched workload)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -130,12 +216,13 @@ def main(argv=None):
 
     w = _workload(args.workload)
     k = args.k or w.k
-    r = run_gpu(w, args.precision, k, args.steps, args.warmup)
-    steps_per_s = r["inner_steps"] / r["elapsed_s"]
+    precision = args.precision or w.precision
+    r = run_gpu(w, precision, k, args.steps, args.warmup)
+    steps_per_s = w.n_systems * r["inner_steps"] / r["elapsed_s"]
     ms_per_cycle = 1e3 * r["elapsed_s"] / args.steps
     trip_s = r["triplet_kernel_ms"] * 1e-3
     achieved = FLOPS_PER_TRIPLET * r["triplets_per_eval"] / trip_s / 1e12 if trip_s > 0 else 0.0
-    peak = PEAK_TFLOPS[args.precision]
+    peak = PEAK_TFLOPS[precision]
     out = {
         "metric": METRIC,
         "value": steps_per_s,
@@ -147,10 +234,10 @@ def main(argv=None):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "dtype": "f64" if precision == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": w.name, "n_particles": w.n_total, "k": k,
-                   "inner_steps": r["inner_steps"], "precision": args.precision,
+        "config": {"workload": w.name, "n_particles": w.n_total, "n_systems": w.n_systems,
+                   "k": k, "inner_steps": r["inner_steps"], "precision": precision,
                    "rc_pair": w.rc_pair, "rc_triplet": w.rc_triplet, "nu": w.nu, "dt": w.dt,
                    "step": "one r-RESPA outer cycle (k inner steps + 1 triplet evaluation)"},
         "triplets_per_s": r["triplets_per_eval"] / trip_s if trip_s > 0 else None,
@@ -161,11 +248,16 @@ def main(argv=None):
         "roofline": {"bound": "alu", "kernel": "k_triplet", "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None},
     }
-    if not args.no_fp32_form and args.precision == "fp64":
+    if w.n_systems > 1:
+        out["per_system_loop"] = {
+            "value": run_per_system_loop(w, precision, k, args.loop_steps),
+            "unit": "MD steps/s", "cycles": args.loop_steps,
+            "note": "the same replicas, one handle each, stepped one after another"}
+    if not args.no_fp32_form and precision == "fp64":
         r32 = run_gpu(w, "fp32", k, args.steps, args.warmup)
         t32 = r32["triplet_kernel_ms"] * 1e-3
         out["fp32_form"] = {
-            "value": r32["inner_steps"] / r32["elapsed_s"], "unit": "MD steps/s",
+            "value": w.n_systems * r32["inner_steps"] / r32["elapsed_s"], "unit": "MD steps/s",
             "triplets_per_s": r32["triplets_per_eval"] / t32 if t32 > 0 else None,
             "kernel_ms": {"triplet": r32["triplet_kernel_ms"], "pair": r32["pair_kernel_ms"]},
             "roofline_frac_fp32_peak": (FLOPS_PER_TRIPLET * r32["triplets_per_eval"] / t32 / 1e12
@@ -174,7 +266,10 @@ def main(argv=None):
             "rvite": r32["rvite"],
         }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, k)
+        if w.n_systems == 1 and w.n_total <= 40_000:
+            out["cpu_baseline"] = cpu_baseline(w, k)
+        else:
+            out["cpu_baseline"] = None  # the brute-force oracle is O(N^2) or worse here
     print(json.dumps(out), flush=True)
     return 0
 

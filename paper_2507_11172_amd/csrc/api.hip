@@ -183,7 +183,7 @@ void size_tiles(mts_system *s) {
     const double rc3 = s->p.rc_triplet, rv = s->p.rc_pair + s->skin;
     s->stage_cap = std::min(2048, round_up((int)std::ceil(kNumHalf * vt * 1.1) + 16, 32));
     s->pair_cap = std::min(2048, round_up((int)std::ceil(kNumFull * vp * 1.1) + 16, 32));
-    s->list_cap = std::min(1024, round_up((int)std::ceil(1.3 * rho_t * (2.0 / 3.0) * M_PI * rc3 * rc3 * rc3) + 16, 16));
+    s->list_cap = std::min(1024, round_up((int)std::ceil(1.6 * rho_t * (2.0 / 3.0) * M_PI * rc3 * rc3 * rc3) + 8, 16));
     s->nl_cap = std::min(2048, round_up((int)std::ceil(1.3 * rho_p * (4.0 / 3.0) * M_PI * rv * rv * rv) + 16, 32));
 }
 

@@ -326,3 +326,63 @@ def test_cycle_graph_matches_eager_bitwise(k):
             out.append((x.cpu(), v.cpu(), e.cpu()))
     for a, b in zip(out[0], out[1]):
         assert torch.equal(a, b)
+
+
+def test_batched_replicas_match_single_systems():
+    """One batched handle over uneven replicas gives, bit for bit, the forces, trajectories
+    and per-system energies of each replica run on its own (same explicit skin)."""
+    torch = _torch()
+    from paper_2507_11172_amd import mts
+    w = W.batched(n_replicas=6, n_min=200, n_max=3000)
+    k, n_iter = 5, 20
+    kw = dict(k=k, skin=0.3)
+    with _system(w, **kw) as s:
+        x, v = _dev(w.x), _dev(w.v)
+        f2, f3 = torch.empty_like(x), torch.empty_like(x)
+        s.compute_pair_forces(x, f2)
+        s.compute_triplet_forces(x, f3)
+        e = torch.zeros((n_iter // k + 1, w.n_systems, mts.MTS_NE), dtype=torch.float64,
+                        device="cuda")
+        s.respa_step(x, v, n_iter, e)
+        s.sync()
+        fb2, fb3, xb, vb, eb = f2.cpu(), f3.cpu(), x.cpu(), v.cpu(), e.cpu()
+    off = 0
+    for r in range(w.n_systems):
+        n = int(w.n_particles[r])
+        sl = slice(off, off + n)
+        wr = W.Workload("rep%d" % r, w.x[sl], w.v[sl], w.box[r:r + 1], np.array([n]),
+                        w.temperature[r:r + 1])
+        with _system(wr, **kw) as s:
+            x, v = _dev(wr.x), _dev(wr.v)
+            f2, f3 = torch.empty_like(x), torch.empty_like(x)
+            s.compute_pair_forces(x, f2)
+            s.compute_triplet_forces(x, f3)
+            e = torch.zeros((n_iter // k + 1, 1, mts.MTS_NE), dtype=torch.float64, device="cuda")
+            s.respa_step(x, v, n_iter, e)
+            s.sync()
+        assert torch.equal(fb2[sl], f2.cpu()) and torch.equal(fb3[sl], f3.cpu()), r
+        assert torch.equal(xb[sl], x.cpu()) and torch.equal(vb[sl], v.cpu()), r
+        assert torch.equal(eb[:, r, :], e.cpu()[:, 0, :]), r
+        off += n
+
+
+def test_batched_replicas_forces_vs_oracle():
+    """Per-replica forces of a batched call against the oracle (FP64 bar)."""
+    torch = _torch()
+    w = W.batched(n_replicas=5, n_min=200, n_max=1500)
+    with _system(w) as s:
+        x = _dev(w.x)
+        f2, f3 = torch.empty_like(x), torch.empty_like(x)
+        s.compute_pair_forces(x, f2)
+        s.compute_triplet_forces(x, f3)
+        s.sync()
+    f2, f3 = f2.cpu().numpy(), f3.cpu().numpy()
+    off = 0
+    for r in range(w.n_systems):
+        n = int(w.n_particles[r])
+        sl = slice(off, off + n)
+        r2 = oracle.pair_forces(w.x[sl], w.box[r], rc=w.rc_pair)
+        r3 = oracle.triplet_forces(w.x[sl], w.box[r], rc=w.rc_triplet)
+        assert rel_err(f2[sl], r2.f) <= 1e-12, r
+        assert rel_err(f3[sl], r3.f) <= 1e-12, r
+        off += n
