@@ -386,3 +386,64 @@ def test_batched_replicas_forces_vs_oracle():
         assert rel_err(f2[sl], r2.f) <= 1e-12, r
         assert rel_err(f3[sl], r3.f) <= 1e-12, r
         off += n
+
+
+def _forces_and_energies(w, precision):
+    torch = _torch()
+    with _system(w, precision=precision) as s:
+        x = _dev(w.x)
+        f2, f3 = torch.empty_like(x), torch.empty_like(x)
+        e2 = torch.zeros((1, 2), dtype=torch.float64, device="cuda")
+        e3 = torch.zeros((1, 2), dtype=torch.float64, device="cuda")
+        s.compute_pair_forces(x, f2, e2)
+        s.compute_triplet_forces(x, f3, e3)
+        s.sync()
+    return (f2.cpu().numpy(), f3.cpu().numpy(), float(e2.cpu()[0, 0]), float(e3.cpu()[0, 0]))
+
+
+def _subset_bar(f, ref):
+    return np.abs(f - ref).max() / np.sqrt(np.mean(np.sum(ref * ref, axis=1)))
+
+
+@pytest.mark.slow
+def test_precision_form_1m_particles():
+    """1,048,576 particles: the FP32 form against the FP64 GPU run on every particle, and
+    both against the oracle's exact subset mode on 4,000 seeded particles."""
+    w = W.precision_form(10)
+    n = w.n_total
+    a2, a3, u2, u3 = _forces_and_energies(w, "fp64")
+    b2, b3, v2, v3 = _forces_and_energies(w, "fp32")
+    assert rel_err(b2, a2) <= 1e-5 and rel_err(b3, a3) <= 1e-5
+    assert abs((v2 + v3) - (u2 + u3)) / n <= 1e-7
+    idx = np.sort(W.rng_for(78).choice(n, size=4000, replace=False))
+    r2, r3 = oracle.subset_forces(w.x, w.box[0], idx)
+    assert _subset_bar(a2[idx], r2) <= 1e-12 and _subset_bar(a3[idx], r3) <= 1e-12
+    assert _subset_bar(b2[idx], r2) <= 1e-5 and _subset_bar(b3[idx], r3) <= 1e-5
+
+
+def test_fcc4000_energies_vs_oracle():
+    """Standalone 4,000-particle system: total energies of both forms against the oracle's
+    full brute force (FP64 to 1e-12 relative, FP32 form to 1e-7 per particle)."""
+    w = W.fcc4000()
+    box = w.box[0]
+    r2 = oracle.pair_forces(w.x, box)
+    r3 = oracle.triplet_forces(w.x, box)
+    a2, a3, u2, u3 = _forces_and_energies(w, "fp64")
+    b2, b3, v2, v3 = _forces_and_energies(w, "fp32")
+    assert u2 == pytest.approx(r2.energy, rel=1e-12) and u3 == pytest.approx(r3.energy, rel=1e-12)
+    assert abs((v2 + v3) - (r2.energy + r3.energy)) / w.n_total <= 1e-7
+    assert rel_err(a3, r3.f) <= 1e-12 and rel_err(b3, r3.f) <= 1e-5
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("rc3", [2.5, 3.0])
+def test_inhomogeneous_slab_subset(rc3):
+    """500,000-particle liquid slab in vapour: forces on 1,500 seeded particles (liquid,
+    interface and vapour alike) against the oracle's subset mode, both forms."""
+    w = W.inhomogeneous(rc3)
+    a2, a3, _, _ = _forces_and_energies(w, "fp64")
+    b2, b3, _, _ = _forces_and_energies(w, "fp32")
+    idx = np.sort(W.rng_for(79).choice(w.n_total, size=1500, replace=False))
+    r2, r3 = oracle.subset_forces(w.x, w.box[0], idx, rc3=rc3)
+    assert _subset_bar(a2[idx], r2) <= 1e-12 and _subset_bar(a3[idx], r3) <= 1e-12
+    assert _subset_bar(b2[idx], r2) <= 1e-5 and _subset_bar(b3[idx], r3) <= 1e-5
