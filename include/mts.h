@@ -132,8 +132,9 @@ mts_status mts_compute_triplet_forces(mts_system *sys, const double *x, double *
 mts_status mts_respa_step(mts_system *sys, double *x, double *v, int64_t n_iter, double *e_full);
 
 /* Waits for the stream and reports device flags raised since the last mts_sync:
- * MTS_ERR_CAPACITY (the affected forces are wrong; capacities are enlarged for the
- * next call) or MTS_ERR_NONFINITE.  Clears the flags. */
+ * MTS_ERR_CAPACITY (the affected forces are wrong; the tile or list capacities, or the
+ * pair-list skin when a particle outran half of it, are enlarged for the next call) or
+ * MTS_ERR_NONFINITE.  Clears the flags. */
 mts_status mts_sync(mts_system *sys);
 
 /* Text of the last error on this handle ("" if none); valid until the next call. */
@@ -173,6 +174,45 @@ enum {
 
 /* Sets an option (see the MTS_OPT_ constants).  MTS_ERR_INVALID_ARG for unknown options. */
 mts_status mts_set_option(mts_system *sys, int32_t option, int64_t value);
+
+/* ---- autotuning ---- */
+
+/* A handle's tunable configuration. */
+typedef struct {
+    double skin;          /* Verlet pair-list skin in use (0: no list; the pair grid is
+                             rebinned every inner step) */
+    double cell_factor;   /* triplet cells have edges >= cell_factor * rc_triplet (>= 1) */
+    int32_t list_lanes;   /* lanes per particle of the list force kernel (8 or 16) */
+    int32_t stage_cap;    /* triplet tile capacity (particles staged per workgroup) */
+    int32_t list_cap;     /* forward-neighbour list capacity per anchor particle */
+    int32_t pair_cap;     /* pair tile capacity */
+    int32_t nl_cap;       /* pair-list row capacity */
+    int32_t trials;       /* configurations the last mts_autotune timed (0: cached/untuned) */
+    double cycle_ms;      /* measured ms per outer r-RESPA cycle (0: untuned) */
+} mts_tuning;
+
+/* Chooses, by measurement on the caller's input, the configuration that runs one outer
+ * r-RESPA cycle fastest -- the role AutoPas's run-time algorithm selection plays for the
+ * paper's CPU code (Sec. 4.1, cutoff implementation).  Candidates: pair-list skin
+ * (none, 0.15, 0.3, 0.5 sigma; only skins that a particle 1.5 times faster than the
+ * fastest one in v would not outrun in one outer cycle), triplet cell factor (1, 1.12,
+ * 1.25) and list-kernel
+ * lanes (16, 8), searched one knob at a time from the current configuration; each
+ * candidate gets tile and list capacities sized from the maxima observed on x, a warm-up
+ * cycle and the faster of two timed runs of about 4 ms (at least 3 cycles each), and
+ * replaces the best so far only if at least 2% faster.  The search stops once budget_ms
+ * of wall time is spent (<= 0: 2000 ms).  It runs on copies: x, v (dev [N][3]) are read,
+ * not modified.  The winner stays on the handle and is cached for the process by problem
+ * shape (parameters, particle counts, boxes): a later call on a handle of that shape
+ * applies it without timing.  Every configuration yields the same triplet and pair sets
+ * and forces within the oracle tolerances.  Synchronising; out (host) may be NULL.
+ * MTS_ERR_CAPACITY if no candidate ran without overflow (the handle then keeps its
+ * previous configuration). */
+mts_status mts_autotune(mts_system *sys, const double *x, const double *v, int32_t budget_ms,
+                        mts_tuning *out);
+
+/* The handle's current configuration (host out). */
+mts_status mts_get_tuning(const mts_system *sys, mts_tuning *out);
 
 /* ---- profiling hook ---- */
 

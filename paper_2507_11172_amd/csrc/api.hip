@@ -11,9 +11,12 @@
 // instead of a full rebinning.  A particle that moves more than half the skin raises a
 // device flag that mts_sync reports (the list is rebuilt at every full step anyway).
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -41,6 +44,26 @@ struct Grid {
     Pos4 *xs2 = nullptr;          // [n] second position buffer (pair grid: list steps)
 };
 
+// Tunable choices of a handle (see mts_tuning in mts.h).
+struct Config {
+    double skin = 0.0;            // pair-list skin in use (0: no list, rebin every step)
+    double cell_factor = 1.0;     // triplet cell edge >= cell_factor * rc_triplet
+    int lanes = 16;               // lanes per particle in the list force kernel
+    int stage_cap = 0, list_cap = 0, pair_cap = 0, nl_cap = 0;  // 0: sized by heuristics
+};
+
+// Everything that depends on the configuration: the two cell grids, the capacities and
+// the buffers sized by them.  Rebuilt as a whole by build_layout.
+struct Layout {
+    Config cfg;
+    Grid gt, gp;                  // triplet grid, pair grid
+    double skin = 0.0;            // == cfg.skin
+    int stage_cap = 0, list_cap = 0, pair_cap = 0, nl_cap = 0;
+    double *ce = nullptr;         // [ncell_t][2] per-cell triplet energy/virial
+    long long *cc = nullptr;      // [ncell_t] per-cell triplet counts
+    int *nbr = nullptr;           // [n][nl_cap] pair list (pair-grid sorted indices)
+};
+
 }  // namespace
 
 struct mts_system {
@@ -49,10 +72,13 @@ struct mts_system {
     int64_t n = 0;
     hipStream_t st = nullptr;
     bool fp32 = false;
-    Grid gt, gp;                  // triplet grid, pair grid
-    double skin = 0.0;            // pair-list skin in use (0: no list, rebin every step)
-    int stage_cap = 0, list_cap = 0, pair_cap = 0, nl_cap = 0;
+    std::vector<SysDesc> base;    // per-system boxes and particle ranges (no grid yet)
+    double lmin = 0.0;            // smallest box edge over all systems
+    Layout lo;
     size_t max_lds = 64 * 1024;   // per-workgroup LDS limit of the device
+    bool collect_stats = false;   // kernels record tile and list maxima into stats
+    double tuned_ms = 0.0;        // measured cycle time of the configuration (autotune)
+    int tuned_trials = 0;
     double ushift = 0.0;
     std::string err;
 
@@ -62,11 +88,9 @@ struct mts_system {
     double *f2a = nullptr, *f2b = nullptr, *f3 = nullptr;  // [n][3] force caches
     double *pf = nullptr;         // [14][3][n] triplet partial slots
     double *pe = nullptr;         // [n][2] per-particle pair energy/virial (pair-grid order)
-    double *ce = nullptr;         // [ncell_t][2] per-cell triplet energy/virial
-    long long *cc = nullptr;      // [ncell_t] per-cell triplet counts
     long long *cnt_sys = nullptr; // [nsys]
-    int *nbr = nullptr;           // [n][nl_cap] pair list (pair-grid sorted indices)
     int *nn = nullptr;            // [n]
+    int *stats = nullptr;         // [4] observed maxima (tile and list sizes), tuning only
     double *x_ref = nullptr;      // [n][3] wrapped positions at the last list build
     int *flags = nullptr;
     int *row = nullptr;
@@ -168,6 +192,9 @@ double max_cell_volume(const Grid &g, double &rho_max) {
     return v;
 }
 
+// The triplet kernel's hit queue stores list positions in 8 bits.
+constexpr int kMaxListCap = 256;
+
 // Tile and list capacities.  A cell of volume h^3 holds about rho h^3 particles; sizing
 // assumes a local density of max(0.9, 1.2 x the system's mean), which covers LJ liquids
 // and crystals near the densities of the paper's scenarios, including a liquid slab
@@ -175,16 +202,16 @@ double max_cell_volume(const Grid &g, double &rho_max) {
 // and the pair tile all 27 cells of the pair grid; a forward-neighbour list holds about
 // half a cutoff sphere and a pair-list row a whole (rc + skin) sphere.  Overflow is
 // detected on the device, reported by mts_sync, and doubles the capacity for the next
-// call.
-void size_tiles(mts_system *s) {
+// call; mts_autotune sizes them from the maxima observed on the real input instead.
+void size_tiles(const mts_system *s, Layout &lo) {
     double rho_t, rho_p;
-    const double vt = max_cell_volume(s->gt, rho_t);
-    const double vp = max_cell_volume(s->gp, rho_p);
-    const double rc3 = s->p.rc_triplet, rv = s->p.rc_pair + s->skin;
-    s->stage_cap = std::min(2048, round_up((int)std::ceil(kNumHalf * vt * 1.1) + 16, 32));
-    s->pair_cap = std::min(2048, round_up((int)std::ceil(kNumFull * vp * 1.1) + 16, 32));
-    s->list_cap = std::min(1024, round_up((int)std::ceil(1.6 * rho_t * (2.0 / 3.0) * M_PI * rc3 * rc3 * rc3) + 8, 16));
-    s->nl_cap = std::min(2048, round_up((int)std::ceil(1.3 * rho_p * (4.0 / 3.0) * M_PI * rv * rv * rv) + 16, 32));
+    const double vt = max_cell_volume(lo.gt, rho_t);
+    const double vp = max_cell_volume(lo.gp, rho_p);
+    const double rc3 = s->p.rc_triplet, rv = s->p.rc_pair + lo.skin;
+    lo.stage_cap = std::min(2048, round_up((int)std::ceil(kNumHalf * vt * 1.1) + 16, 32));
+    lo.pair_cap = std::min(2048, round_up((int)std::ceil(kNumFull * vp * 1.1) + 16, 32));
+    lo.list_cap = std::min(kMaxListCap, round_up((int)std::ceil(1.6 * rho_t * (2.0 / 3.0) * M_PI * rc3 * rc3 * rc3) + 8, 16));
+    lo.nl_cap = std::min(2048, round_up((int)std::ceil(1.3 * rho_p * (4.0 / 3.0) * M_PI * rv * rv * rv) + 16, 32));
 }
 
 mts_status alloc_grid(mts_system *s, Grid &g) {
@@ -216,12 +243,72 @@ void free_grid(Grid &g) {
                     g.perm, g.inv_perm, g.xs, g.xs2};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
+    g = Grid{};
 }
 
+void free_layout(Layout &lo) {
+    free_grid(lo.gt);
+    free_grid(lo.gp);
+    void *ptrs[] = {lo.ce, lo.cc, lo.nbr};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    lo = Layout{};
+}
+
+// Cells are strictly wider than the cutoff, with margin for rounding, so that any
+// interacting pair lies in adjacent cells.
+constexpr double kCellMargin = 1.0 + 1e-9;
+
+// The pair-list skin actually used for a requested one: shrunk so that every box edge
+// exceeds 2 (rc + skin) -- a pair then has one image within the list radius -- and
+// dropped (no list; every step rebins) below 0.05 sigma, where a list does not pay.
+double effective_skin(const mts_system *s, double skin) {
+    skin = std::min(skin, 0.4999 * s->lmin / kCellMargin - s->p.rc_pair);
+    return skin >= 0.05 * s->p.sigma ? skin : 0.0;
+}
+
+// Builds a complete layout for cfg into `out` without touching the handle's own.
+mts_status build_layout(mts_system *s, const Config &cfg, Layout &out) {
+    out = Layout{};
+    out.cfg = cfg;
+    out.skin = cfg.skin;
+    mts_status r = make_grid(out.gt, s->base, cfg.cell_factor * s->p.rc_triplet * kCellMargin);
+    if (r == MTS_OK) r = make_grid(out.gp, s->base, (s->p.rc_pair + cfg.skin) * kCellMargin);
+    if (r != MTS_OK) {
+        out = Layout{};
+        return r;
+    }
+    size_tiles(s, out);
+    if (cfg.stage_cap > 0) out.stage_cap = cfg.stage_cap;
+    if (cfg.list_cap > 0) out.list_cap = cfg.list_cap;
+    if (cfg.pair_cap > 0) out.pair_cap = cfg.pair_cap;
+    if (cfg.nl_cap > 0) out.nl_cap = cfg.nl_cap;
+    out.cfg.stage_cap = out.stage_cap;
+    out.cfg.list_cap = out.list_cap;
+    out.cfg.pair_cap = out.pair_cap;
+    out.cfg.nl_cap = out.nl_cap;
+    if (triplet_lds_bytes(out.stage_cap, out.list_cap) > s->max_lds ||
+        pair_lds_bytes(out.pair_cap) > s->max_lds) {
+        out = Layout{};
+        return MTS_ERR_UNSUPPORTED;
+    }
+    r = alloc_grid(s, out.gt);
+    if (r == MTS_OK) r = alloc_grid(s, out.gp);
+    if (r == MTS_OK && (dalloc(&out.ce, 2 * (size_t)out.gt.ncell) != hipSuccess ||
+                        dalloc(&out.cc, out.gt.ncell) != hipSuccess ||
+                        dalloc(&out.nbr, (size_t)s->n * out.nl_cap) != hipSuccess ||
+                        hipMemset(out.ce, 0, 2 * sizeof(double) * out.gt.ncell) != hipSuccess))
+        r = fail(s, MTS_ERR_OOM, "device memory for the cell grids and lists");
+    if (r != MTS_OK) {
+        free_layout(out);
+        return r == MTS_ERR_HIP ? MTS_ERR_OOM : r;
+    }
+    return MTS_OK;
+}
+
+// Buffers that depend on the particle and system counts only.
 mts_status alloc_all(mts_system *s) {
     const int64_t n = s->n;
-    MTS_TRY(alloc_grid(s, s->gt));
-    MTS_TRY(alloc_grid(s, s->gp));
     HIP_TRY(s, dalloc(&s->sys_of, n));
     HIP_TRY(s, dalloc(&s->red_part, (size_t)s->nsys * kRedChunks * 6));
     HIP_TRY(s, dalloc(&s->f2a, 3 * n));
@@ -229,11 +316,9 @@ mts_status alloc_all(mts_system *s) {
     HIP_TRY(s, dalloc(&s->f3, 3 * n));
     HIP_TRY(s, dalloc(&s->pf, (size_t)kNumHalf * 3 * n));
     HIP_TRY(s, dalloc(&s->pe, 2 * n));
-    HIP_TRY(s, dalloc(&s->ce, 2 * (size_t)s->gt.ncell));
-    HIP_TRY(s, dalloc(&s->cc, s->gt.ncell));
     HIP_TRY(s, dalloc(&s->cnt_sys, s->nsys));
-    HIP_TRY(s, dalloc(&s->nbr, (size_t)n * s->nl_cap));
     HIP_TRY(s, dalloc(&s->nn, n));
+    HIP_TRY(s, dalloc(&s->stats, 4));
     HIP_TRY(s, dalloc(&s->x_ref, 3 * n));
     HIP_TRY(s, dalloc(&s->flags, 1));
     HIP_TRY(s, dalloc(&s->row, 1));
@@ -246,12 +331,11 @@ mts_status alloc_all(mts_system *s) {
 
     std::vector<int> so(n > 0 ? n : 1);
     for (int q = 0; q < s->nsys; ++q) {
-        const SysDesc &d = s->gt.hsd[q];
+        const SysDesc &d = s->base[q];
         for (int64_t i = 0; i < d.n; ++i) so[d.p0 + i] = q;
     }
     if (n > 0) HIP_TRY(s, hipMemcpy(s->sys_of, so.data(), sizeof(int) * n, hipMemcpyHostToDevice));
     HIP_TRY(s, hipMemset(s->flags, 0, sizeof(int)));
-    HIP_TRY(s, hipMemset(s->ce, 0, 2 * sizeof(double) * s->gt.ncell));
     HIP_TRY(s, hipMemset(s->pf, 0, sizeof(double) * kNumHalf * 3 * (n > 0 ? n : 1)));
     return MTS_OK;
 }
@@ -265,6 +349,18 @@ void drop_graphs(mts_system *s) {
             }
 }
 
+// Replaces the handle's layout by one built for cfg (the old one stays on failure).
+mts_status set_layout(mts_system *s, const Config &cfg) {
+    Layout nl;
+    MTS_TRY(build_layout(s, cfg, nl));
+    if (s->ist) (void)hipStreamSynchronize(s->ist);
+    (void)hipStreamSynchronize(s->st);
+    drop_graphs(s);  // captured launches carry the old buffers and sizes
+    free_layout(s->lo);
+    s->lo = nl;
+    return MTS_OK;
+}
+
 void free_all(mts_system *s) {
     drop_graphs(s);
     if (s->ev_in) (void)hipEventDestroy(s->ev_in);
@@ -272,11 +368,10 @@ void free_all(mts_system *s) {
     if (s->ist) (void)hipStreamDestroy(s->ist);
     for (int c = 0; c < 2; ++c)
         for (hipEvent_t e : s->ev_pool[c]) (void)hipEventDestroy(e);
-    free_grid(s->gt);
-    free_grid(s->gp);
-    void *ptrs[] = {s->sys_of, s->red_part, s->f2a, s->f2b, s->f3, s->pf, s->pe, s->ce, s->cc,
-                    s->cnt_sys, s->nbr, s->nn, s->x_ref, s->flags, s->row, s->e_buf, s->list_n,
-                    s->xi, s->vi};
+    free_layout(s->lo);
+    void *ptrs[] = {s->sys_of, s->red_part, s->f2a, s->f2b, s->f3, s->pf, s->pe, s->cnt_sys,
+                    s->nn, s->stats, s->x_ref, s->flags, s->row, s->e_buf, s->list_n, s->xi,
+                    s->vi};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -327,19 +422,19 @@ mts_status enqueue_bin(mts_system *s, int which, const double *x, bool with_ref)
     a.x = x;
     a.sys_of = s->sys_of;
     a.flags = s->flags;
-    if (which & kBinPair) fill_bin_grid(a.g[a.ng++], s->gp, with_ref ? s->x_ref : nullptr);
-    if (which & kBinTriplet) fill_bin_grid(a.g[a.ng++], s->gt, nullptr);
+    if (which & kBinPair) fill_bin_grid(a.g[a.ng++], s->lo.gp, with_ref ? s->x_ref : nullptr);
+    if (which & kBinTriplet) fill_bin_grid(a.g[a.ng++], s->lo.gt, nullptr);
     HIP_TRY(s, launch_bin(s->st, a));
     return MTS_OK;
 }
 
 // F2 from the pair grid's cell tiles (no list).
 mts_status enqueue_pair(mts_system *s, double *f2) {
-    const Grid &g = s->gp;
+    const Grid &g = s->lo.gp;
     PairArgs a{};
     a.ncell = g.ncell;
     a.sys_of_cell = g.sys_of_cell;
-    a.stage_cap = s->pair_cap;
+    a.stage_cap = s->lo.pair_cap;
     a.n = s->n;
     a.xs = g.xs;
     a.perm = g.perm;
@@ -361,21 +456,22 @@ mts_status enqueue_pair(mts_system *s, double *f2) {
 
 // Verlet list of the pair grid at its current binning.
 mts_status enqueue_list_build(mts_system *s) {
-    const Grid &g = s->gp;
+    const Grid &g = s->lo.gp;
     ListBuildArgs a{};
     a.ncell = g.ncell;
     a.sys_of_cell = g.sys_of_cell;
-    a.stage_cap = s->pair_cap;
+    a.stage_cap = s->lo.pair_cap;
     a.n = s->n;
     a.xs = g.xs;
     a.start = g.start;
     a.sd = g.sd;
-    a.nbr = s->nbr;
+    a.nbr = s->lo.nbr;
     a.nn = s->nn;
-    a.nl_cap = s->nl_cap;
-    const double rv = s->p.rc_pair + s->skin;
+    a.nl_cap = s->lo.nl_cap;
+    const double rv = s->p.rc_pair + s->lo.skin;
     a.rv2 = rv * rv;
     a.flags = s->flags;
+    a.stats = s->collect_stats ? s->stats + 2 : nullptr;
     HIP_TRY(s, launch_list_build(s->st, a));
     return MTS_OK;
 }
@@ -395,11 +491,12 @@ mts_status enqueue_pair_list(mts_system *s, const Pos4 *xs_in, double *f2, const
     PairListArgs a{};
     a.n = s->n;
     a.xs = xs_in;
-    a.perm = s->gp.perm;
-    a.nbr = s->nbr;
+    a.perm = s->lo.gp.perm;
+    a.lanes = s->lo.cfg.lanes;
+    a.nbr = s->lo.nbr;
     a.nn = s->nn;
-    a.nl_cap = s->nl_cap;
-    a.sd = s->gp.sd;
+    a.nl_cap = s->lo.nl_cap;
+    a.sd = s->lo.gp.sd;
     a.sys_of = s->sys_of;
     a.f = f2;
     a.pe = energy ? s->pe : nullptr;
@@ -423,7 +520,7 @@ mts_status enqueue_pair_list(mts_system *s, const Pos4 *xs_in, double *f2, const
         a.cx = (dt * dt) / (2.0 * m);
         a.xs_out = u.xs_out;
         a.x_ref = u.drift && u.xs_out ? s->x_ref : nullptr;
-        a.half_skin2 = 0.25 * s->skin * s->skin;
+        a.half_skin2 = 0.25 * s->lo.skin * s->lo.skin;
     }
     const long ts = timer_begin(s, 1);
     HIP_TRY(s, launch_pair_list(s->st, a, s->fp32));
@@ -433,7 +530,7 @@ mts_status enqueue_pair_list(mts_system *s, const Pos4 *xs_in, double *f2, const
 
 mts_status enqueue_triplet(mts_system *s, double *f3, int *list_ijk, long long list_rows,
                            bool energy) {
-    const Grid &g = s->gt;
+    const Grid &g = s->lo.gt;
     TripletArgs a{};
     a.ncell = g.ncell;
     a.xs = g.xs;
@@ -442,17 +539,18 @@ mts_status enqueue_triplet(mts_system *s, double *f3, int *list_ijk, long long l
     a.sys_of_cell = g.sys_of_cell;
     a.perm = g.perm;
     a.pf = s->pf;
-    a.ce = energy ? s->ce : nullptr;
-    a.cc = s->cc;
+    a.ce = energy ? s->lo.ce : nullptr;
+    a.cc = s->lo.cc;
     a.n = s->n;
     a.nu = s->p.nu;
     a.rc2 = s->p.rc_triplet * s->p.rc_triplet;
-    a.stage_cap = s->stage_cap;
-    a.list_cap = s->list_cap;
+    a.stage_cap = s->lo.stage_cap;
+    a.list_cap = s->lo.list_cap;
     a.flags = s->flags;
     a.list_ijk = list_ijk;
     a.list_n = s->list_n;
     a.list_rows = list_rows;
+    a.stats = s->collect_stats ? s->stats : nullptr;
     const long ts = timer_begin(s, 0);
     HIP_TRY(s, launch_triplet(s->st, a, s->fp32, list_ijk != nullptr));
     timer_end(s, 0, ts);
@@ -464,12 +562,12 @@ mts_status enqueue_reduce(mts_system *s, const double *v, bool pair, bool trip, 
                           int stride, const int *row, long long *count_out) {
     ReduceArgs a{};
     a.nsys = s->nsys;
-    a.sd = s->gt.sd;
+    a.sd = s->lo.gt.sd;
     a.v = v;
     a.half_mass = 0.5 * s->p.mass;
     a.pe = pair ? s->pe : nullptr;
-    a.ce = trip && out ? s->ce : nullptr;  // energies are only written when asked for
-    a.cc = trip ? s->cc : nullptr;
+    a.ce = trip && out ? s->lo.ce : nullptr;  // energies are only written when asked for
+    a.cc = trip ? s->lo.cc : nullptr;
     a.out = out;
     a.stride = stride;
     a.count_out = count_out;
@@ -500,13 +598,13 @@ mts_status enqueue_int(mts_system *s, const double *f2prev, const double *f2cur,
     a.kick3_end = kick3_end;
     a.kick3_start = kick3_start;
     a.drift = drift;
-    a.sd = s->gt.sd;
+    a.sd = s->lo.gt.sd;
     a.sys_of = s->sys_of;
     if (drift && xs_out) {
-        a.inv_perm = s->gp.inv_perm;
+        a.inv_perm = s->lo.gp.inv_perm;
         a.xs = xs_out;
         a.x_ref = s->x_ref;
-        a.half_skin2 = 0.25 * s->skin * s->skin;
+        a.half_skin2 = 0.25 * s->lo.skin * s->lo.skin;
     }
     a.flags = s->flags;
     HIP_TRY(s, launch_int(s->st, a));
@@ -524,9 +622,9 @@ mts_status enqueue_full_step_list(mts_system *s, bool energy) {
 
 // Forces at the internal positions x^0 of a call: F3 into s->f3, F2 into f2.
 mts_status enqueue_entry_forces(mts_system *s, double *f2, bool energy) {
-    if (s->skin > 0.0) {
+    if (s->lo.skin > 0.0) {
         MTS_TRY(enqueue_full_step_list(s, energy));
-        MTS_TRY(enqueue_pair_list(s, s->gp.xs, f2, Fused{}, true));
+        MTS_TRY(enqueue_pair_list(s, s->lo.gp.xs, f2, Fused{}, true));
     } else {
         MTS_TRY(enqueue_bin(s, kBinPair | kBinTriplet, s->xi, false));
         MTS_TRY(enqueue_pair(s, f2));
@@ -548,8 +646,8 @@ mts_status enqueue_entry_forces(mts_system *s, double *f2, bool energy) {
 mts_status enqueue_cycle(mts_system *s, double *f2_0, double *f2_1, bool energies) {
     const int k = s->p.k;
     double *f2[2] = {f2_0, f2_1};
-    if (s->skin > 0.0) {
-        Pos4 *buf[2] = {s->gp.xs, s->gp.xs2};  // x^i lives in buf[i & 1] for 0 < i < k
+    if (s->lo.skin > 0.0) {
+        Pos4 *buf[2] = {s->lo.gp.xs, s->lo.gp.xs2};  // x^i lives in buf[i & 1] for 0 < i < k
         MTS_TRY(enqueue_int(s, nullptr, f2[0], false, false, true, true, k > 1 ? buf[1] : nullptr));
         for (int i = 1; i < k; ++i) {
             Fused u;
@@ -564,7 +662,7 @@ mts_status enqueue_cycle(mts_system *s, double *f2_0, double *f2_1, bool energie
         u.kick2 = true;
         u.kick3_end = true;
         u.f2prev = f2[(k - 1) & 1];
-        MTS_TRY(enqueue_pair_list(s, s->gp.xs, f2[k & 1], u, energies));
+        MTS_TRY(enqueue_pair_list(s, s->lo.gp.xs, f2[k & 1], u, energies));
     } else {
         for (int i = 0; i < k; ++i) {
             double *prev = f2[(i + 1) & 1], *cur = f2[i & 1], *next = f2[(i + 1) & 1];
@@ -655,6 +753,58 @@ double lj_energy(double r2, double eps, double sigma) {
     return 4.0 * eps * (s6 * s6 - s6);
 }
 
+// ---- autotuning (see mts_autotune)
+
+std::mutex &tune_mutex() {
+    static std::mutex m;
+    return m;
+}
+
+// Tuned configurations of this process, keyed by the shape of the problem.
+std::map<std::string, std::pair<Config, double>> &tune_cache() {
+    static std::map<std::string, std::pair<Config, double>> c;
+    return c;
+}
+
+std::string shape_key(const mts_system *s) {
+    std::string k;
+    char buf[160];
+    snprintf(buf, sizeof buf, "%.17g|%.17g|%.17g|%.17g|%.17g|%.17g|%.17g|%d|%d|%d", s->p.epsilon,
+             s->p.sigma, s->p.rc_pair, s->p.nu, s->p.rc_triplet, s->p.mass, s->p.dt, s->p.k,
+             s->p.precision, s->nsys);
+    k = buf;
+    for (const SysDesc &d : s->base) {
+        snprintf(buf, sizeof buf, "|%lld:%.17g,%.17g,%.17g", (long long)d.n, d.L[0], d.L[1], d.L[2]);
+        k += buf;
+    }
+    return k;
+}
+
+// Largest triplet tile, forward-neighbour candidate list, pair tile and pair-list row
+// seen on positions x with the current layout (the kernels record them with atomic
+// maxima; a capacity overflow raised meanwhile is cleared, the maxima are what counts).
+mts_status observe(mts_system *s, const double *x, int obs[4]) {
+    HIP_TRY(s, hipMemsetAsync(s->stats, 0, 4 * sizeof(int), s->st));
+    s->collect_stats = true;
+    mts_status r = enqueue_bin(s, kBinPair | kBinTriplet, x, false);
+    if (r == MTS_OK) r = enqueue_list_build(s);
+    if (r == MTS_OK) r = enqueue_triplet(s, nullptr, nullptr, 0, false);
+    s->collect_stats = false;
+    MTS_TRY(r);
+    HIP_TRY(s, hipMemcpyAsync(obs, s->stats, 4 * sizeof(int), hipMemcpyDeviceToHost, s->st));
+    HIP_TRY(s, hipStreamSynchronize(s->st));
+    HIP_TRY(s, hipMemset(s->flags, 0, sizeof(int)));
+    return MTS_OK;
+}
+
+// Capacities for the observed maxima, with room for the fluctuations of a run.
+void caps_from_observed(Config &c, const int obs[4]) {
+    c.stage_cap = std::min(2048, round_up((int)std::ceil(1.15 * obs[0]) + 16, 32));
+    c.list_cap = std::min(kMaxListCap, round_up((int)std::ceil(1.2 * obs[1]) + 8, 16));
+    c.pair_cap = std::min(2048, round_up((int)std::ceil(1.15 * obs[2]) + 16, 32));
+    if (c.skin > 0.0) c.nl_cap = std::min(2048, round_up((int)std::ceil(1.2 * obs[3]) + 16, 32));
+}
+
 }  // namespace
 
 extern "C" {
@@ -683,9 +833,6 @@ mts_status mts_init_system(const mts_params *params, int32_t n_systems, const in
     if (v != MTS_OK) return v;
     if (n_systems < 1 || !n_particles || !box) return MTS_ERR_INVALID_ARG;
     const double rc_max = std::max(params->rc_pair, params->rc_triplet);
-    // cells strictly wider than the cutoff, with margin for rounding, so that any
-    // interacting pair lies in adjacent cells
-    const double margin = 1.0 + 1e-9;
     std::vector<SysDesc> base;
     int64_t p0 = 0;
     double lmin = INFINITY;
@@ -695,7 +842,7 @@ mts_status mts_init_system(const mts_params *params, int32_t n_systems, const in
         for (int k = 0; k < 3; ++k) {
             const double L = box[3 * q + k];
             if (!finite_pos(L)) return MTS_ERR_INVALID_ARG;
-            if (!(L > 2.0 * rc_max * margin)) return MTS_ERR_BOX_TOO_SMALL;
+            if (!(L > 2.0 * rc_max * kCellMargin)) return MTS_ERR_BOX_TOO_SMALL;
             d.L[k] = L;
             d.iL[k] = 1.0 / L;
             lmin = std::min(lmin, L);
@@ -713,26 +860,11 @@ mts_status mts_init_system(const mts_params *params, int32_t n_systems, const in
     s->n = p0;
     s->st = (hipStream_t)stream;
     s->fp32 = params->precision == MTS_FP32;
-    // Pair-list skin: the requested one, by default max(0.3 sigma, 12 k dt sqrt(eps/m))
-    // (room for particles at four times a typical thermal speed of LJ fluids), shrunk so
-    // that every box edge exceeds 2 (rc + skin) -- a pair then has one image within the
-    // list radius.  Below 0.05 sigma the list is not worth it: every step rebins instead.
-    double skin = params->skin > 0.0
-                      ? params->skin
-                      : std::max(0.3 * params->sigma,
-                                 12.0 * params->k * params->dt * std::sqrt(params->epsilon / params->mass));
-    skin = std::min(skin, 0.4999 * lmin / margin - params->rc_pair);
-    s->skin = skin >= 0.05 * params->sigma ? skin : 0.0;
-    mts_status g1 = make_grid(s->gt, base, params->rc_triplet * margin);
-    mts_status g2 = g1 == MTS_OK ? make_grid(s->gp, base, (params->rc_pair + s->skin) * margin) : g1;
-    if (g2 != MTS_OK) {
-        delete s;
-        return g2;
-    }
+    s->base = base;
+    s->lmin = lmin;
     s->ushift = params->lj_energy_shift
                     ? lj_energy(params->rc_pair * params->rc_pair, params->epsilon, params->sigma)
                     : 0.0;
-    size_tiles(s);
     {
         int dev = 0, lds = 0;
         if (hipGetDevice(&dev) == hipSuccess &&
@@ -744,12 +876,17 @@ mts_status mts_init_system(const mts_params *params, int32_t n_systems, const in
         if (configure_kernel_lds(s->max_lds) != hipSuccess) s->max_lds = 64 * 1024 - 1024;
         (void)hipGetLastError();  // do not leave a failed attribute call as a sticky error
     }
-    if (triplet_lds_bytes(s->stage_cap, s->list_cap) > s->max_lds ||
-        pair_lds_bytes(s->pair_cap) > s->max_lds) {
-        delete s;
-        return MTS_ERR_UNSUPPORTED;
-    }
+    // Default configuration.  Pair-list skin: the requested one, by default
+    // max(0.3 sigma, 12 k dt sqrt(eps/m)) (room for particles at four times a typical
+    // thermal speed of LJ fluids); triplet cells of edge >= rc3; 16 lanes per particle.
+    Config cfg;
+    cfg.skin = effective_skin(
+        s, params->skin > 0.0
+               ? params->skin
+               : std::max(0.3 * params->sigma,
+                          12.0 * params->k * params->dt * std::sqrt(params->epsilon / params->mass)));
     mts_status a = alloc_all(s);
+    if (a == MTS_OK) a = build_layout(s, cfg, s->lo);
     if (a != MTS_OK) {
         free_all(s);
         delete s;
@@ -828,42 +965,52 @@ mts_status mts_sync(mts_system *sys) {
     HIP_TRY(sys, hipMemcpy(&flags, sys->flags, sizeof(int), hipMemcpyDeviceToHost));
     HIP_TRY(sys, hipMemset(sys->flags, 0, sizeof(int)));
     if (flags & (kFlagStageOverflow | kFlagListOverflow | kFlagPairList)) {
-        const int old_s = sys->stage_cap, old_l = sys->list_cap, old_p = sys->pair_cap,
-                  old_n = sys->nl_cap;
+        const int old_s = sys->lo.stage_cap, old_l = sys->lo.list_cap, old_p = sys->lo.pair_cap,
+                  old_n = sys->lo.nl_cap;
         if (flags & kFlagStageOverflow) {
-            sys->stage_cap = std::min(4096, 2 * sys->stage_cap);
-            sys->pair_cap = std::min(4096, 2 * sys->pair_cap);
+            sys->lo.stage_cap = std::min(4096, 2 * sys->lo.stage_cap);
+            sys->lo.pair_cap = std::min(4096, 2 * sys->lo.pair_cap);
         }
-        if (flags & kFlagListOverflow) sys->list_cap = std::min(2048, 2 * sys->list_cap);
-        if (triplet_lds_bytes(sys->stage_cap, sys->list_cap) > sys->max_lds) {
-            sys->stage_cap = old_s;
-            sys->list_cap = old_l;
+        if (flags & kFlagListOverflow) sys->lo.list_cap = std::min(kMaxListCap, 2 * sys->lo.list_cap);
+        if (triplet_lds_bytes(sys->lo.stage_cap, sys->lo.list_cap) > sys->max_lds) {
+            sys->lo.stage_cap = old_s;
+            sys->lo.list_cap = old_l;
         }
-        if (pair_lds_bytes(sys->pair_cap) > sys->max_lds) sys->pair_cap = old_p;
+        if (pair_lds_bytes(sys->lo.pair_cap) > sys->max_lds) sys->lo.pair_cap = old_p;
         if (flags & kFlagPairList) {
-            const int cap = std::min(4096, 2 * sys->nl_cap);
+            const int cap = std::min(4096, 2 * sys->lo.nl_cap);
             int *nb = nullptr;
             if (dalloc(&nb, (size_t)sys->n * cap) == hipSuccess) {
-                (void)hipFree(sys->nbr);
-                sys->nbr = nb;
-                sys->nl_cap = cap;
+                (void)hipFree(sys->lo.nbr);
+                sys->lo.nbr = nb;
+                sys->lo.nl_cap = cap;
             }
         }
+        sys->lo.cfg.stage_cap = sys->lo.stage_cap;
+        sys->lo.cfg.list_cap = sys->lo.list_cap;
+        sys->lo.cfg.pair_cap = sys->lo.pair_cap;
+        sys->lo.cfg.nl_cap = sys->lo.nl_cap;
         drop_graphs(sys);  // captured launches carry the old sizes and pointers
         char buf[240];
         snprintf(buf, sizeof buf,
                  "capacity overflow (flags %d): triplet tile %d -> %d, pair tile %d -> %d, "
                  "neighbour list %d -> %d, pair list %d -> %d; results since the last sync "
                  "are invalid",
-                 flags, old_s, sys->stage_cap, old_p, sys->pair_cap, old_l, sys->list_cap, old_n,
-                 sys->nl_cap);
+                 flags, old_s, sys->lo.stage_cap, old_p, sys->lo.pair_cap, old_l, sys->lo.list_cap, old_n,
+                 sys->lo.nl_cap);
         return fail(sys, MTS_ERR_CAPACITY, buf);
     }
     if (flags & kFlagSkin) {
-        char buf[200];
+        // the next call runs with a doubled skin (as far as the boxes allow)
+        const double old_skin = sys->lo.skin;
+        Config c = sys->lo.cfg;
+        c.skin = effective_skin(sys, 2.0 * old_skin);
+        if (c.skin > old_skin) (void)set_layout(sys, c);
+        char buf[240];
         snprintf(buf, sizeof buf,
                  "a particle moved more than half the pair-list skin (%.3g) between full steps; "
-                 "pair forces since the last sync may miss pairs", sys->skin);
+                 "pair forces since the last sync may miss pairs; skin now %.3g", old_skin,
+                 sys->lo.skin);
         return fail(sys, MTS_ERR_CAPACITY, buf);
     }
     if (flags & kFlagNonFinite) return fail(sys, MTS_ERR_NONFINITE, "non-finite force or energy");
@@ -874,13 +1021,13 @@ const char *mts_last_error(const mts_system *sys) { return sys ? sys->err.c_str(
 
 mts_status mts_get_grid(const mts_system *sys, int32_t system, int32_t n_cells[3]) {
     if (!sys || !n_cells || system < 0 || system >= sys->nsys) return MTS_ERR_INVALID_ARG;
-    for (int k = 0; k < 3; ++k) n_cells[k] = sys->gt.hsd[system].nc[k];
+    for (int k = 0; k < 3; ++k) n_cells[k] = sys->lo.gt.hsd[system].nc[k];
     return MTS_OK;
 }
 
 mts_status mts_get_cell_index(mts_system *sys, int32_t *cell) {
     if (!sys || (!cell && sys->n > 0)) return MTS_ERR_INVALID_ARG;
-    HIP_TRY(sys, launch_local_cell_index(sys->st, sys->n, sys->gt.cell_of, sys->gt.sd, sys->sys_of, cell));
+    HIP_TRY(sys, launch_local_cell_index(sys->st, sys->n, sys->lo.gt.cell_of, sys->lo.gt.sd, sys->sys_of, cell));
     return MTS_OK;
 }
 
@@ -910,6 +1057,176 @@ mts_status mts_list_triplets(mts_system *sys, const double *x, int32_t *ijk, int
     HIP_TRY(sys, hipMemcpyAsync(&total, sys->list_n, sizeof(unsigned long long), hipMemcpyDeviceToHost, sys->st));
     MTS_TRY(mts_sync(sys));
     *n = (int64_t)total;
+    return MTS_OK;
+}
+
+static mts_status time_cycles(mts_system *s, const double *x, const double *v, double *tx,
+                              double *tv, int cycles, double &ms) {
+    const int k = s->p.k;
+    const int64_t bytes = 3 * s->n * (int64_t)sizeof(double);
+    HIP_TRY(s, hipMemcpyAsync(tx, x, bytes, hipMemcpyDeviceToDevice, s->st));
+    HIP_TRY(s, hipMemcpyAsync(tv, v, bytes, hipMemcpyDeviceToDevice, s->st));
+    MTS_TRY(mts_respa_step(s, tx, tv, k, nullptr));  // warm-up: captures the cycle graphs
+    MTS_TRY(mts_sync(s));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(s, hipEventCreate(&e0));
+    hipError_t he = hipEventCreate(&e1);
+    if (he != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(s, he, "hipEventCreate");
+    }
+    mts_status r = MTS_OK;
+    if (hipEventRecord(e0, s->st) != hipSuccess) r = fail(s, MTS_ERR_HIP, "hipEventRecord");
+    if (r == MTS_OK) r = mts_respa_step(s, tx, tv, (int64_t)cycles * k, nullptr);
+    if (r == MTS_OK && hipEventRecord(e1, s->st) != hipSuccess) r = fail(s, MTS_ERR_HIP, "hipEventRecord");
+    if (r == MTS_OK) r = mts_sync(s);
+    float t = 0.0f;
+    if (r == MTS_OK && hipEventElapsedTime(&t, e0, e1) != hipSuccess) r = fail(s, MTS_ERR_HIP, "hipEventElapsedTime");
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ms = (double)t / cycles;
+    return r;
+}
+
+static void fill_tuning(const mts_system *s, mts_tuning *out) {
+    const Config &c = s->lo.cfg;
+    out->skin = c.skin;
+    out->cell_factor = c.cell_factor;
+    out->list_lanes = c.lanes;
+    out->stage_cap = s->lo.stage_cap;
+    out->list_cap = s->lo.list_cap;
+    out->pair_cap = s->lo.pair_cap;
+    out->nl_cap = s->lo.nl_cap;
+    out->cycle_ms = s->tuned_ms;
+    out->trials = s->tuned_trials;
+}
+
+mts_status mts_get_tuning(const mts_system *sys, mts_tuning *out) {
+    if (!sys || !out) return MTS_ERR_INVALID_ARG;
+    fill_tuning(sys, out);
+    return MTS_OK;
+}
+
+mts_status mts_autotune(mts_system *sys, const double *x, const double *v, int32_t budget_ms,
+                        mts_tuning *out) {
+    if (!sys) return MTS_ERR_INVALID_ARG;
+    if ((!x || !v) && sys->n > 0) return fail(sys, MTS_ERR_INVALID_ARG, "x or v is NULL");
+    if (sys->timing) return fail(sys, MTS_ERR_INVALID_ARG, "kernel timing is enabled");
+    MTS_TRY(mts_sync(sys));
+    const std::string key = shape_key(sys);
+    {
+        std::lock_guard<std::mutex> lk(tune_mutex());
+        auto it = tune_cache().find(key);
+        if (it != tune_cache().end()) {
+            MTS_TRY(set_layout(sys, it->second.first));
+            sys->tuned_ms = it->second.second;
+            sys->tuned_trials = 0;
+            if (out) fill_tuning(sys, out);
+            return MTS_OK;
+        }
+    }
+    if (sys->n == 0) {
+        if (out) fill_tuning(sys, out);
+        return MTS_OK;
+    }
+    const auto t_start = std::chrono::steady_clock::now();
+    const double budget = budget_ms > 0 ? (double)budget_ms : 2000.0;
+    double *tx = nullptr, *tv = nullptr;
+    HIP_TRY(sys, dalloc(&tx, 3 * sys->n));
+    if (dalloc(&tv, 3 * sys->n) != hipSuccess) {
+        (void)hipFree(tx);
+        return fail(sys, MTS_ERR_OOM, "autotune scratch");
+    }
+    // Smallest skin worth trying: a particle 1.5x faster than the fastest one of the input
+    // must stay within half the skin over a whole outer cycle.
+    double vmax = 0.0;
+    {
+        std::vector<double> hv(3 * sys->n);
+        if (hipMemcpy(hv.data(), v, hv.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
+            (void)hipFree(tx);
+            (void)hipFree(tv);
+            return fail(sys, MTS_ERR_HIP, "autotune: reading v");
+        }
+        for (int64_t i = 0; i < sys->n; ++i) {
+            const double a = hv[3 * i], b = hv[3 * i + 1], c = hv[3 * i + 2];
+            vmax = std::max(vmax, std::sqrt((a * a + b * b) + c * c));
+        }
+    }
+    const double min_skin = 2.0 * 1.5 * vmax * sys->p.k * sys->p.dt;
+    const Config start = sys->lo.cfg;
+    int trials = 0;
+    // One configuration: layout with heuristic capacities, capacities from the maxima
+    // observed on x, then the timed cycles.  Returns the ms per cycle, or +inf when the
+    // configuration does not fit (box, LDS) or overflowed during the run.
+    auto trial = [&](Config c) -> std::pair<double, Config> {
+        c.stage_cap = c.list_cap = c.pair_cap = c.nl_cap = 0;
+        if (set_layout(sys, c) != MTS_OK) return {INFINITY, c};
+        int obs[4] = {0, 0, 0, 0};
+        if (observe(sys, x, obs) != MTS_OK) return {INFINITY, c};
+        caps_from_observed(c, obs);
+        if (set_layout(sys, c) != MTS_OK) return {INFINITY, c};
+        ++trials;
+        // enough cycles for about 4 ms of work (at least 3), timed twice: the faster run
+        double ms = INFINITY, once = 0.0;
+        int cycles = 3;
+        for (int rep = 0; rep < 2; ++rep) {
+            if (time_cycles(sys, x, v, tx, tv, cycles, once) != MTS_OK) {
+                (void)mts_sync(sys);  // clears the flags and the error of an overflowed run
+                return {INFINITY, sys->lo.cfg};
+            }
+            ms = std::min(ms, once);
+            if (rep == 0 && once > 0.0) cycles = std::max(3, std::min(200, (int)std::ceil(4.0 / once)));
+        }
+        return {ms, sys->lo.cfg};
+    };
+    auto over_budget = [&]() {
+        const double el = std::chrono::duration<double, std::milli>(
+                              std::chrono::steady_clock::now() - t_start).count();
+        return el > budget;
+    };
+    std::pair<double, Config> best = trial(start);
+    // coordinate descent over the pair-list skin, the triplet cell size and the lanes
+    // per particle of the list force kernel
+    std::vector<double> skins = {0.0, 0.15 * sys->p.sigma, 0.3 * sys->p.sigma, 0.5 * sys->p.sigma};
+    for (double sk : skins) {
+        if (over_budget()) break;
+        Config c = best.second;
+        c.skin = effective_skin(sys, sk);
+        if (c.skin == best.second.skin || (c.skin > 0.0 && c.skin < min_skin)) continue;
+        auto r = trial(c);
+        if (r.first < 0.98 * best.first) best = r;
+    }
+    for (double f : {1.0, 1.12, 1.25}) {
+        if (over_budget()) break;
+        Config c = best.second;
+        if (c.cell_factor == f) continue;
+        c.cell_factor = f;
+        auto r = trial(c);
+        if (r.first < 0.98 * best.first) best = r;
+    }
+    for (int g : {16, 8}) {
+        if (over_budget() || best.second.skin == 0.0) break;
+        Config c = best.second;
+        if (c.lanes == g) continue;
+        c.lanes = g;
+        auto r = trial(c);
+        if (r.first < 0.98 * best.first) best = r;
+    }
+    (void)hipFree(tx);
+    (void)hipFree(tv);
+    if (!std::isfinite(best.first)) {
+        // nothing could be timed: back to the configuration the handle had
+        MTS_TRY(set_layout(sys, start));
+        return fail(sys, MTS_ERR_CAPACITY, "autotune: no configuration ran without overflow");
+    }
+    MTS_TRY(set_layout(sys, best.second));
+    sys->tuned_ms = best.first;
+    sys->tuned_trials = trials;
+    {
+        std::lock_guard<std::mutex> lk(tune_mutex());
+        tune_cache()[key] = {best.second, best.first};
+    }
+    if (out) fill_tuning(sys, out);
     return MTS_OK;
 }
 

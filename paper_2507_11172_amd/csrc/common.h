@@ -225,6 +225,7 @@ struct ListBuildArgs {
     int nl_cap;
     double rv2;
     int *flags;
+    int *stats;             // optional: [2] atomic max of the tile size and the row length
 };
 hipError_t launch_list_build(hipStream_t st, const ListBuildArgs &a);
 size_t list_build_lds_bytes(int stage_cap);
@@ -244,6 +245,7 @@ struct PairListArgs {
     int64_t n;
     const Pos4 *xs;         // current wrapped positions in the list's sorted order
     const int *perm;        // sorted -> input index
+    int lanes;              // lanes per particle: 8 or 16
     const int *nbr;         // [n][nl_cap]
     const int *nn;          // [n]
     int nl_cap;
@@ -287,6 +289,8 @@ struct TripletArgs {
     int *list_ijk;          // optional triplet listing [list_cap_rows][3]
     unsigned long long *list_n;  // listing counter
     long long list_rows;
+    int *stats;             // optional: [2] atomic max of the tile size and of the anchor
+                            // list length before capping
 };
 hipError_t launch_triplet(hipStream_t st, const TripletArgs &a, bool fp32, bool listing);
 size_t triplet_lds_bytes(int stage_cap, int list_cap);

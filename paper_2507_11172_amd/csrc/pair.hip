@@ -16,8 +16,9 @@
 //    wavefront per particle, FP32 distance test, ballot compaction of every neighbour
 //    within rc + skin into the particle's row of the Verlet list.  Runs once per outer
 //    r-RESPA cycle.
-//  * k_pair_list: 16 lanes per particle walk its list row (four gathers in flight per
-//    lane), a DPP butterfly inside the 16-lane row combines them in fixed order, and
+//  * k_pair_list: 8 or 16 lanes per particle (a tuning choice) walk its list row (four
+//    gathers in flight per lane), a DPP butterfly inside the group combines them in
+//    fixed order, and
 //    the particle's r-RESPA update is fused behind the force (one launch per inner
 //    step).  Energies and virials are summed only when asked for (full steps).
 // Cutoff geometry is always FP64 and canonical (bit-identical pair set in both
@@ -182,6 +183,7 @@ __global__ void __launch_bounds__(kPairThreads) k_list_build(ListBuildArgs a) {
     int nst = stencil_table<kNumFull, false>(tab, d, cx, cy, cz, a.start);
     const int s13 = tab.off[13];
     int nself = tab.off[14] - s13;
+    if (a.stats && lane == 0) atomicMax(&a.stats[0], nst);
     if (nst > CAP) {
         if (lane == 0) atomicOr(a.flags, kFlagStageOverflow);
         nst = CAP;
@@ -231,6 +233,7 @@ __global__ void __launch_bounds__(kPairThreads) k_list_build(ListBuildArgs a) {
         if (wl == 0) {
             a.nn[p] = min(cnt, a.nl_cap);
             if (cnt > a.nl_cap) atomicOr(a.flags, kFlagPairList);
+            if (a.stats) atomicMax(&a.stats[1], cnt);
         }
     }
 }
@@ -242,7 +245,6 @@ hipError_t launch_list_build(hipStream_t st, const ListBuildArgs &a) {
 }
 
 // ---------------------------------------------------------------- list forces + update
-constexpr int kListGroup = 16;  // lanes per particle: one DPP row
 
 template <int CTRL>
 __device__ __forceinline__ double dpp_row(double v) {
@@ -252,12 +254,15 @@ __device__ __forceinline__ double dpp_row(double v) {
     return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Sum over a 16-lane DPP row; every lane of the row ends with the same value.
-__device__ __forceinline__ double sum16(double v) {
+// Sum over G = 8 or 16 consecutive lanes (inside one DPP row); every lane of the group
+// ends with the same value.
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+    static_assert(G == 8 || G == 16, "groups of 8 or 16 lanes");
     v += dpp_row<0xB1>(v);   // quad_perm [1,0,3,2]
     v += dpp_row<0x4E>(v);   // quad_perm [2,3,0,1]
     v += dpp_row<0x141>(v);  // row_half_mirror
-    v += dpp_row<0x140>(v);  // row_mirror
+    if (G == 16) v += dpp_row<0x140>(v);  // row_mirror
     return v;
 }
 
@@ -290,11 +295,11 @@ __device__ __forceinline__ void lj_accumulate(const Pos4 &pi, const Pos4 &e, con
 // are in flight together.
 constexpr int kListUnroll = 4;
 
-template <typename T, bool ENERGY>
+template <typename T, bool ENERGY, int G>
 __global__ void __launch_bounds__(256) k_pair_list(PairListArgs a) {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t p = gid / kListGroup;
-    const int r = (int)(gid % kListGroup);
+    const int64_t p = gid / G;
+    const int r = (int)(gid % G);
     const bool act = p < a.n;
 
     // per-particle loads first; the operands of the fused update are then issued
@@ -323,11 +328,11 @@ __global__ void __launch_bounds__(256) k_pair_list(PairListArgs a) {
     {
         const T sigma2 = (T)a.sigma2, eps24 = (T)(24.0 * a.eps), eps4 = (T)(4.0 * a.eps);
         const int *row = a.nbr + pp * a.nl_cap;
-        for (int s0 = r; s0 < cnt; s0 += kListUnroll * kListGroup) {
+        for (int s0 = r; s0 < cnt; s0 += kListUnroll * G) {
             int qn[kListUnroll];
 #pragma unroll
             for (int k = 0; k < kListUnroll; ++k) {
-                const int s = s0 + k * kListGroup;
+                const int s = s0 + k * G;
                 qn[k] = s < cnt ? row[s] : (int)pp;
             }
             Pos4 e[kListUnroll];
@@ -335,17 +340,17 @@ __global__ void __launch_bounds__(256) k_pair_list(PairListArgs a) {
             for (int k = 0; k < kListUnroll; ++k) e[k] = a.xs[qn[k]];
 #pragma unroll
             for (int k = 0; k < kListUnroll; ++k)
-                if (s0 + k * kListGroup < cnt)
+                if (s0 + k * G < cnt)
                     lj_accumulate<T, ENERGY>(pi, e[k], L, iL, a.rc2, sigma2, eps24, eps4, a.ushift,
                                              fx, fy, fz, u, w);
         }
     }
-    fx = sum16(fx);
-    fy = sum16(fy);
-    fz = sum16(fz);
+    fx = group_sum<G>(fx);
+    fy = group_sum<G>(fy);
+    fz = group_sum<G>(fz);
     if (ENERGY) {
-        u = sum16(u);
-        w = sum16(w);
+        u = group_sum<G>(u);
+        w = group_sum<G>(w);
     }
 
     // ---- fused update of component r, in Algorithm 2's order
@@ -373,8 +378,8 @@ __global__ void __launch_bounds__(256) k_pair_list(PairListArgs a) {
         }
     }
     // displacement since the list build: (dx^2 + dy^2) + dz^2 in lane r = 0
-    const double d1 = __shfl_down(dd2, 1, kListGroup);
-    const double d2 = __shfl_down(dd2, 2, kListGroup);
+    const double d1 = __shfl_down(dd2, 1, G);
+    const double d2 = __shfl_down(dd2, 2, G);
     if (act && r == 0) {
         if (ENERGY) {
             a.pe[2 * p] = 0.5 * u;
@@ -387,19 +392,26 @@ __global__ void __launch_bounds__(256) k_pair_list(PairListArgs a) {
     }
 }
 
-hipError_t launch_pair_list(hipStream_t st, const PairListArgs &a, bool fp32) {
-    const int64_t threads = a.n * kListGroup;
+template <int G>
+static hipError_t launch_pair_list_g(hipStream_t st, const PairListArgs &a, bool fp32) {
+    const int64_t threads = a.n * G;
     const unsigned blocks = (unsigned)((threads + 255) / 256);
     if (blocks == 0) return hipSuccess;
     const bool energy = a.pe != nullptr;
     if (fp32) {
-        if (energy) k_pair_list<float, true><<<blocks, 256, 0, st>>>(a);
-        else k_pair_list<float, false><<<blocks, 256, 0, st>>>(a);
+        if (energy) k_pair_list<float, true, G><<<blocks, 256, 0, st>>>(a);
+        else k_pair_list<float, false, G><<<blocks, 256, 0, st>>>(a);
     } else {
-        if (energy) k_pair_list<double, true><<<blocks, 256, 0, st>>>(a);
-        else k_pair_list<double, false><<<blocks, 256, 0, st>>>(a);
+        if (energy) k_pair_list<double, true, G><<<blocks, 256, 0, st>>>(a);
+        else k_pair_list<double, false, G><<<blocks, 256, 0, st>>>(a);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_pair_list(hipStream_t st, const PairListArgs &a, bool fp32) {
+    if (a.lanes == 8) return launch_pair_list_g<8>(st, a, fp32);
+    if (a.lanes == 16) return launch_pair_list_g<16>(st, a, fp32);
+    return hipErrorInvalidValue;
 }
 
 hipError_t configure_triplet_lds(size_t max_bytes);

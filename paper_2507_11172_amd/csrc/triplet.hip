@@ -48,23 +48,40 @@ constexpr int kTripThreads = kTripWaves * kWave;
 // pushes at most 2 x 64 more.
 constexpr int kQueueCap = 4 * kWave;
 
-// LDS layout.  Entries read by consecutive lanes are 48-byte structures read as three
-// 16-byte words: an odd multiple of 16 bytes is free of bank conflicts for
-// ds_read_b128 across 16 lanes.  Accumulators updated at scattered addresses are
-// structure-of-arrays.
-struct alignas(16) PosEnt {    // a staged particle: wrapped FP64 position and the image
-    double x, y, z;            // shift (0 or +-L per component) seen from the base cell
-    double sx, sy, sz;
+// LDS layout.  The hot scans read 16-byte FP32 copies (ds_read_b128 by consecutive
+// lanes, free of bank conflicts); the FP64 entries (32 bytes) are read only for the
+// anchor's candidates and for the rare ambiguous cutoff tests.  Accumulators updated at
+// scattered addresses are structure-of-arrays.
+struct PosEnt {                // a staged particle in registers: wrapped FP64 position
+    double x, y, z;            // and the image shift (0 or +-L per component) seen from
+    double sx, sy, sz;         // the base cell
+};
+
+struct alignas(16) TileEnt {   // its LDS form: the shift as a 2-bit code per component
+    double x, y, z;
+    int code;
+    int pad;
 };
 
 struct alignas(16) DispEnt {   // forward neighbour j of the current anchor: canonical
     double ux, uy, uz, a;      // displacement anchor -> j and its square |u|^2
 };
 
-static_assert(sizeof(PosEnt) == 48 && sizeof(DispEnt) == 32, "LDS entry sizes");
+static_assert(sizeof(TileEnt) == 32 && sizeof(DispEnt) == 32, "LDS entry sizes");
+
+__device__ __forceinline__ PosEnt unpack(const TileEnt &t, double L0, double L1, double L2) {
+    PosEnt e;
+    e.x = t.x;
+    e.y = t.y;
+    e.z = t.z;
+    e.sx = (double)((t.code & 3) - 1) * L0;
+    e.sy = (double)(((t.code >> 2) & 3) - 1) * L1;
+    e.sz = (double)(((t.code >> 4) & 3) - 1) * L2;
+    return e;
+}
 
 struct Tile {                  // staged neighbour cells, CAP entries
-    PosEnt *e;                 // FP64 (canonical tests, displacements)
+    TileEnt *e;                // FP64 (canonical tests, displacements)
     float4 *r;                 // FP32 position relative to the base cell (prefilter)
     double *fx, *fy, *fz;      // force accumulators
 };
@@ -74,20 +91,20 @@ struct List {                  // one wave's forward-neighbour list, LC entries
     float4 *f;                 // the same in FP32 (j-k prefilter)
     double *px, *py, *pz;      // partner force partials of the current anchor
     int *t;                    // tile index
-    int *q;                    // hit queue, kQueueCap entries: j | k << 16
+    unsigned short *q;         // hit queue, kQueueCap entries: j | k << 8 (lists <= 256)
 };
 
 size_t triplet_lds_bytes(int cap, int lcap) {
-    return (size_t)cap * (sizeof(PosEnt) + sizeof(float4) + 3 * sizeof(double)) +
+    return (size_t)cap * (sizeof(TileEnt) + sizeof(float4) + 3 * sizeof(double)) +
            (size_t)kTripWaves * lcap * (sizeof(DispEnt) + sizeof(float4) + 3 * sizeof(double) + sizeof(int)) +
-           (size_t)kTripWaves * kQueueCap * sizeof(int);
+           (size_t)kTripWaves * kQueueCap * sizeof(unsigned short);
 }
 
 // Carves the dynamic LDS block (cap is a multiple of 32 and lc of 16, so every array
-// starts 16-byte aligned): 48-, 32- and 16-byte entries, then doubles, then ints.
+// starts 16-byte aligned): 32- and 16-byte entries, then doubles, ints and the queue.
 __device__ __forceinline__ void carve(unsigned char *raw, int cap, int lc, int wave, Tile &T,
                                       List &L) {
-    T.e = (PosEnt *)raw;
+    T.e = (TileEnt *)raw;
     DispEnt *lu = (DispEnt *)(T.e + cap);
     L.u = lu + (size_t)wave * lc;
     float4 *fr = (float4 *)(lu + (size_t)kTripWaves * lc);
@@ -99,7 +116,7 @@ __device__ __forceinline__ void carve(unsigned char *raw, int cap, int lc, int w
     L.px = pw; L.py = pw + lc; L.pz = pw + 2 * lc;
     int *ip = (int *)(dp + 3 * (size_t)cap + (size_t)kTripWaves * 3 * lc);
     L.t = ip + (size_t)wave * lc;
-    L.q = ip + (size_t)kTripWaves * lc + (size_t)wave * kQueueCap;
+    L.q = (unsigned short *)(ip + (size_t)kTripWaves * lc) + (size_t)wave * kQueueCap;
 }
 
 // FP32 prefilter of a cutoff test.  Positions relative to the base cell (|x| < 3 h <=
@@ -239,6 +256,7 @@ __global__ void __launch_bounds__(kTripThreads) k_triplet(TripletArgs a) {
     // ---- stage the base cell and its 13 forward cells (shared by the workgroup)
     int nst = stencil_table<kNumHalf, true>(tab, d, cx, cy, cz, a.start);
     int nself = tab.off[1];
+    if (a.stats && tid == 0) atomicMax(&a.stats[0], nst);
     if (nst > CAP) {
         if (tid == 0) atomicOr(a.flags, kFlagStageOverflow);
         nst = CAP;
@@ -249,14 +267,14 @@ __global__ void __launch_bounds__(kTripThreads) k_triplet(TripletArgs a) {
         const int src = tab.begin[o] + (t - tab.off[o]);
         const int code = tab.code[o];
         const Pos4 ps = a.xs[src];
-        PosEnt e;
-        e.x = ps.x;
-        e.y = ps.y;
-        e.z = ps.z;
-        e.sx = (double)((code & 3) - 1) * L0;
-        e.sy = (double)(((code >> 2) & 3) - 1) * L1;
-        e.sz = (double)(((code >> 4) & 3) - 1) * L2;
-        tile.e[t] = e;
+        TileEnt te;
+        te.x = ps.x;
+        te.y = ps.y;
+        te.z = ps.z;
+        te.code = code & 0xff;
+        te.pad = 0;
+        tile.e[t] = te;
+        const PosEnt e = unpack(te, L0, L1, L2);
         tile.r[t] = make_float4((float)((e.x + e.sx) - ox), (float)((e.y + e.sy) - oy),
                                (float)((e.z + e.sz) - oz), 0.0f);
         tile.fx[t] = 0.0;
@@ -271,12 +289,12 @@ __global__ void __launch_bounds__(kTripThreads) k_triplet(TripletArgs a) {
     const float pf_lo = (float)rc2 * (1.0f - kPrefilterBand);
     const float pf_hi = (float)rc2 * (1.0f + kPrefilterBand);
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
-    int *Q = L.q;
+    unsigned short *Q = L.q;
     double U = 0.0, W = 0.0;
     int ntrip = 0;  // wave-uniform
 
     for (int ia = wave; ia < nself; ia += kTripWaves) {
-        const PosEnt an = tile.e[ia];  // anchor: base cell, zero shift
+        const PosEnt an = unpack(tile.e[ia], L0, L1, L2);  // anchor: base cell, zero shift
         const float4 ar = tile.r[ia];
         // ---- A1: FP32 prefilter of the tile entries after the anchor (tile order);
         // certain and ambiguous candidates are compacted into L.t, in tile order
@@ -296,6 +314,7 @@ __global__ void __launch_bounds__(kTripThreads) k_triplet(TripletArgs a) {
             if (in2 && p2 < LC) L.t[p2] = t2;
             mc += n1 + __popcll(m2);
         }
+        if (a.stats && lane == 0) atomicMax(&a.stats[1], mc);
         if (mc > LC) {
             if (lane == 0) atomicOr(a.flags, kFlagListOverflow);
             mc = LC;
@@ -307,7 +326,7 @@ __global__ void __launch_bounds__(kTripThreads) k_triplet(TripletArgs a) {
         for (int c0 = 0; c0 < mc; c0 += kWave) {
             const int c = c0 + lane;
             const int t = c < mc ? L.t[c] : ia;
-            const PosEnt e = tile.e[t];
+            const PosEnt e = unpack(tile.e[t], L0, L1, L2);
             const double dx = disp1(an.x, e.x, e.sx), dy = disp1(an.y, e.y, e.sy),
                          dz = disp1(an.z, e.z, e.sz);
             const double r2 = norm2(dx, dy, dz);
@@ -364,7 +383,7 @@ __global__ void __launch_bounds__(kTripThreads) k_triplet(TripletArgs a) {
             const bool v1 = lane < cnt, v2 = lane + kWave < cnt;
             const int e1 = v1 ? Q[lane] : 0;
             const int e2 = v2 ? Q[lane + kWave] : e1;
-            const int j1 = e1 & 0xffff, k1 = e1 >> 16, j2 = e2 & 0xffff, k2 = e2 >> 16;
+            const int j1 = e1 & 0xff, k1 = e1 >> 8, j2 = e2 & 0xff, k2 = e2 >> 8;
             const DispEnt uj1 = L.u[j1], uk1 = L.u[k1], uj2 = L.u[j2], uk2 = L.u[k2];
             const AtmOut<T> o1 = atm_triplet<T>(uj1, uk1, nu);
             const AtmOut<T> o2 = atm_triplet<T>(uj2, uk2, nu);
@@ -420,8 +439,8 @@ __global__ void __launch_bounds__(kTripThreads) k_triplet(TripletArgs a) {
                     const bool amb2 = c2 && q2 > pf_lo && q2 <= pf_hi;
                     if (__ballot(amb1 || amb2)) {  // rare: settle with the FP64 test
                         if (amb1 || amb2) {
-                            const PosEnt ej = tile.e[L.t[j]];
-                            const PosEnt ek = tile.e[L.t[amb1 ? k1 : k2]];
+                            const PosEnt ej = unpack(tile.e[L.t[j]], L0, L1, L2);
+                            const PosEnt ek = unpack(tile.e[L.t[amb1 ? k1 : k2]], L0, L1, L2);
                             const double vx = disp1(ej.x, ek.x, ek.sx - ej.sx);
                             const double vy = disp1(ej.y, ek.y, ek.sy - ej.sy);
                             const double vz = disp1(ej.z, ek.z, ek.sz - ej.sz);
@@ -429,7 +448,7 @@ __global__ void __launch_bounds__(kTripThreads) k_triplet(TripletArgs a) {
                             if (amb1) hit1 = h;
                             else hit2 = h;
                             if (amb1 && amb2) {
-                                const PosEnt ek2 = tile.e[L.t[k2]];
+                                const PosEnt ek2 = unpack(tile.e[L.t[k2]], L0, L1, L2);
                                 const double wx = disp1(ej.x, ek2.x, ek2.sx - ej.sx);
                                 const double wy = disp1(ej.y, ek2.y, ek2.sy - ej.sy);
                                 const double wz = disp1(ej.z, ek2.z, ek2.sz - ej.sz);
@@ -439,8 +458,8 @@ __global__ void __launch_bounds__(kTripThreads) k_triplet(TripletArgs a) {
                     }
                     const uint64_t m1 = __ballot(hit1), m2 = __ballot(hit2);
                     const int n1 = __popcll(m1);
-                    if (hit1) Q[qn + __popcll(m1 & lt_mask)] = j | (k1 << 16);
-                    if (hit2) Q[qn + n1 + __popcll(m2 & lt_mask)] = j | (k2 << 16);
+                    if (hit1) Q[qn + __popcll(m1 & lt_mask)] = (unsigned short)(j | (k1 << 8));
+                    if (hit2) Q[qn + n1 + __popcll(m2 & lt_mask)] = (unsigned short)(j | (k2 << 8));
                     qn += n1 + __popcll(m2);
                     __builtin_amdgcn_wave_barrier();
                     if (qn >= 2 * kWave) {
@@ -450,8 +469,8 @@ __global__ void __launch_bounds__(kTripThreads) k_triplet(TripletArgs a) {
                         const int r1 = lane < qn ? Q[2 * kWave + lane] : 0;
                         const int r2 = lane + kWave < qn ? Q[3 * kWave + lane] : 0;
                         __builtin_amdgcn_wave_barrier();
-                        if (lane < qn) Q[lane] = r1;
-                        if (lane + kWave < qn) Q[kWave + lane] = r2;
+                        if (lane < qn) Q[lane] = (unsigned short)r1;
+                        if (lane + kWave < qn) Q[kWave + lane] = (unsigned short)r2;
                         __builtin_amdgcn_wave_barrier();
                     }
                 }

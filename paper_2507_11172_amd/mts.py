@@ -31,7 +31,8 @@ MTS_NE = 5
 EXPORTS = ("mts_init_system", "mts_destroy_system", "mts_build_cells", "mts_compute_pair_forces",
            "mts_compute_triplet_forces", "mts_respa_step", "mts_sync", "mts_last_error",
            "mts_status_string", "mts_get_grid", "mts_get_cell_index", "mts_count_triplets",
-           "mts_list_triplets", "mts_enable_kernel_timing", "mts_kernel_times", "mts_set_option")
+           "mts_list_triplets", "mts_enable_kernel_timing", "mts_kernel_times", "mts_set_option",
+           "mts_autotune", "mts_get_tuning")
 MTS_OPT_CYCLE_GRAPH = 1
 
 
@@ -48,6 +49,12 @@ class mts_params(C.Structure):
                 ("dt", C.c_double), ("skin", C.c_double), ("k", C.c_int32),
                 ("precision", C.c_int32),
                 ("lj_energy_shift", C.c_int32), ("reserved", C.c_int32)]
+
+
+class mts_tuning(C.Structure):
+    _fields_ = [("skin", C.c_double), ("cell_factor", C.c_double), ("list_lanes", C.c_int32),
+                ("stage_cap", C.c_int32), ("list_cap", C.c_int32), ("pair_cap", C.c_int32),
+                ("nl_cap", C.c_int32), ("trials", C.c_int32), ("cycle_ms", C.c_double)]
 
 
 _LIB = None
@@ -88,9 +95,12 @@ def load_library(path: str = LIB_PATH):
     L.mts_set_option.argtypes = [vp, C.c_int32, C.c_int64]
     L.mts_set_option.restype = C.c_int32
     L.mts_kernel_times.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
-    for name in ("mts_enable_kernel_timing", "mts_kernel_times", "mts_init_system", "mts_build_cells", "mts_compute_pair_forces",
-                 "mts_compute_triplet_forces", "mts_respa_step", "mts_sync", "mts_get_grid",
-                 "mts_get_cell_index", "mts_count_triplets", "mts_list_triplets"):
+    L.mts_autotune.argtypes = [vp, vp, vp, C.c_int32, C.POINTER(mts_tuning)]
+    L.mts_get_tuning.argtypes = [vp, C.POINTER(mts_tuning)]
+    for name in ("mts_enable_kernel_timing", "mts_kernel_times", "mts_init_system",
+                 "mts_build_cells", "mts_compute_pair_forces", "mts_compute_triplet_forces",
+                 "mts_respa_step", "mts_sync", "mts_get_grid", "mts_get_cell_index",
+                 "mts_count_triplets", "mts_list_triplets", "mts_autotune", "mts_get_tuning"):
         getattr(L, name).restype = C.c_int32
     _LIB = L
     return L
@@ -227,6 +237,23 @@ class System:
                                                 int(cap), C.byref(c)), "mts_list_triplets")
         total = int(c.value)
         return buf[:min(total, cap)], total
+
+    @staticmethod
+    def _tuning_dict(t: "mts_tuning") -> dict:
+        return {name: getattr(t, name) for name, _ in mts_tuning._fields_}
+
+    def autotune(self, x, v, budget_ms: int = 2000) -> dict:
+        """Times candidate configurations on (x, v) (not modified) and keeps the fastest;
+        returns it as a dict (see mts_tuning)."""
+        t = mts_tuning()
+        self._check(self._lib.mts_autotune(self._h, self._vec(x, "x"), self._vec(v, "v"),
+                                           int(budget_ms), C.byref(t)), "mts_autotune")
+        return self._tuning_dict(t)
+
+    def tuning(self) -> dict:
+        t = mts_tuning()
+        self._check(self._lib.mts_get_tuning(self._h, C.byref(t)), "mts_get_tuning")
+        return self._tuning_dict(t)
 
     def set_option(self, option: int, value: int):
         self._check(self._lib.mts_set_option(self._h, int(option), int(value)), "mts_set_option")

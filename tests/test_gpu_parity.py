@@ -447,3 +447,41 @@ def test_inhomogeneous_slab_subset(rc3):
     r2, r3 = oracle.subset_forces(w.x, w.box[0], idx, rc3=rc3)
     assert _subset_bar(a2[idx], r2) <= 1e-12 and _subset_bar(a3[idx], r3) <= 1e-12
     assert _subset_bar(b2[idx], r2) <= 1e-5 and _subset_bar(b3[idx], r3) <= 1e-5
+
+
+@pytest.mark.parametrize("case", ["fcc500", "fcc256"])
+def test_autotune_keeps_parity_and_caches(case):
+    """The tuned configuration (whatever it is) keeps the oracle bars; a second handle of
+    the same shape gets it from the process cache without timing."""
+    torch = _torch()
+    w = CASES[case]()
+    box = w.box[0]
+    k, n_iter = 5, 40
+    x, v = _dev(w.x), _dev(w.v)
+    with _system(w, k=k) as s:
+        t = s.autotune(x, v, budget_ms=1500)
+        assert t["trials"] >= 1 and t["cycle_ms"] > 0.0
+        assert torch.equal(x, _dev(w.x)) and torch.equal(v, _dev(w.v))  # inputs untouched
+        f2, f3 = torch.empty_like(x), torch.empty_like(x)
+        s.compute_pair_forces(x, f2)
+        s.compute_triplet_forces(x, f3)
+        ref = oracle.triplet_list(w.x, box, rc=w.rc_triplet)
+        got, total = s.list_triplets(x, ref.shape[0] + 16)
+        xr, vr = _dev(w.x), _dev(w.v)
+        s.respa_step(xr, vr, n_iter)
+        s.sync()
+    assert rel_err(f2.cpu().numpy(), oracle.pair_forces(w.x, box).f) <= 1e-12
+    assert rel_err(f3.cpu().numpy(), oracle.triplet_forces(w.x, box).f) <= 1e-12
+    g = got.cpu().numpy().astype(np.int64)
+    assert total == ref.shape[0]
+    assert np.array_equal(g[np.lexsort((g[:, 2], g[:, 1], g[:, 0]))], ref.astype(np.int64))
+    xo, vo, _ = oracle.respa(w.x, w.v, box, n_iter=n_iter, k=k)
+    dx = xr.cpu().numpy() - xo
+    dx -= box * np.rint(dx / box)
+    assert np.abs(dx).max() <= 1e-10
+    with _system(w, k=k) as s2:
+        t2 = s2.autotune(x, v, budget_ms=1500)
+        assert t2["trials"] == 0
+        for key in ("skin", "cell_factor", "list_lanes", "stage_cap", "list_cap", "nl_cap"):
+            assert t2[key] == t[key], key
+        assert s2.tuning()["list_lanes"] == t["list_lanes"]
