@@ -36,6 +36,12 @@ METRIC = "3-body triplets/s + r-RESPA MD steps/s, FP32 vs FP64 GPU at stated for
 # the unpacked rate, equal to the FP64 one).
 FLOPS_PER_TRIPLET = 100.0
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
+# HBM bytes per launch of the FP64 triplet kernel with energy records on the default
+# workload, from FETCH_SIZE and WRITE_SIZE counter runs of `bench.py --traffic-probe`
+# scaled by the counts of a 256 MiB copy (FETCH_SIZE reads half the copied bytes: factor
+# 2.0; WRITE_SIZE factor 1.0).  Valid for this kernel version only; other workloads and
+# precisions report null.
+TRIPLET_TRAFFIC_BYTES = {("fcc32k_fp64_k10", "fp64"): 21462530}
 
 
 def _workload(name: str):
@@ -113,9 +119,12 @@ def run_gpu(w, precision: str, k: int, steps: int, warmup: int, tune_ms: int):
         elapsed = time.perf_counter() - t0
         break
 
-    # live per-launch HIP-event timing of the force kernels, on the handle's stream
+    # live per-launch HIP-event timing of the force kernels, on the handle's stream (with
+    # the energy records, as in the timed region: the same kernel variants)
+    nt = max(2, min(steps, 20))
     sysm.enable_kernel_timing(True)
-    sysm.respa_step(x, v, max(2, min(steps, 20)) * k)
+    sysm.respa_step(x, v, nt * k,
+                    torch.zeros((nt + 1, w.n_systems, mts.MTS_NE), dtype=torch.float64, device=dev))
     times = sysm.kernel_times()
     sysm.enable_kernel_timing(False)
     n_trip = sysm.count_triplets(x)
@@ -209,6 +218,32 @@ def cpu_baseline(w, k: int):
             "triplets_per_s": r3.count / t_trip}
 
 
+def traffic_probe(w, precision: str, k: int, tune_ms: int):
+    """For HBM counter runs (FETCH_SIZE / WRITE_SIZE): the tuned triplet-force call with
+    energies, five times, then three copies of a 256 MiB tensor (the calibration kernel:
+    262,144 KiB read and written each)."""
+    import torch
+    from paper_2507_11172_amd import mts
+
+    dev = torch.device("cuda:0")
+    x = torch.tensor(w.x, dtype=torch.float64, device=dev)
+    v = torch.tensor(w.v, dtype=torch.float64, device=dev)
+    with mts.System(_params(w, precision, k), w.n_particles.tolist(), w.box) as sysm:
+        if tune_ms > 0:
+            sysm.autotune(x, v, tune_ms)
+        f = torch.empty_like(x)
+        ew = torch.zeros((w.n_systems, 2), dtype=torch.float64, device=dev)
+        for _ in range(5):
+            sysm.compute_triplet_forces(x, f, ew)
+        sysm.sync()
+    a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev).fill_(1.0)
+    for _ in range(3):
+        b = a.clone()
+    torch.cuda.synchronize()
+    print("traffic probe done (%d-particle workload, calibration copy %d bytes)"
+          % (w.n_total, b.numel() * 4), flush=True)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__,
                                  formatter_class=argparse.RawDescriptionHelpFormatter)
@@ -223,6 +258,8 @@ def main(argv=None):
     ap.add_argument("--no-fp32-form", action="store_true")
     ap.add_argument("--tune-ms", type=int, default=3000,
                     help="autotuning budget before the timed region (0: default configuration)")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="only run the kernels of the HBM counter runs, print no bench line")
     ap.add_argument("--loop-steps", type=int, default=5,
                     help="cycles of the one-handle-per-replica loop (batched workload)")
     args = ap.parse_args(argv)
@@ -234,6 +271,9 @@ def main(argv=None):
     w = _workload(args.workload)
     k = args.k or w.k
     precision = args.precision or w.precision
+    if args.traffic_probe:
+        traffic_probe(w, precision, k, args.tune_ms)
+        return 0
     r = run_gpu(w, precision, k, args.steps, args.warmup, args.tune_ms)
     steps_per_s = w.n_systems * r["inner_steps"] / r["elapsed_s"]
     ms_per_cycle = 1e3 * r["elapsed_s"] / args.steps
@@ -263,7 +303,8 @@ def main(argv=None):
         "energy_drift_per_particle": r["energy_drift_per_particle"],
         "rvite": r["rvite"],
         "roofline": {"bound": "alu", "kernel": "k_triplet", "achieved": achieved, "peak": peak,
-                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None},
+                     "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": TRIPLET_TRAFFIC_BYTES.get((w.name, precision))},
         "tuning": r["tuning"],
     }
     if w.n_systems > 1:
