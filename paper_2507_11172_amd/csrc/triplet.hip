@@ -46,7 +46,14 @@ constexpr int kTripWaves = 4;
 constexpr int kTripThreads = kTripWaves * kWave;
 // Hit queue: evaluated two hits per lane once 2 x 64 are pending; one round of tests
 // pushes at most 2 x 64 more.
-constexpr int kQueueCap = 4 * kWave;
+constexpr int kQueueCap = 4 * kWave;   // a ring: at most 2 x 64 pending + 2 x 64 pushed
+constexpr int kQueueMask = kQueueCap - 1;
+
+// Number of set bits of mask in the lanes below this one.
+__device__ __forceinline__ int below(uint64_t mask) {
+    return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+}
 
 // LDS layout.  The hot scans read 16-byte FP32 copies (ds_read_b128 by consecutive
 // lanes, free of bank conflicts); the FP64 entries (32 bytes) are read only for the
@@ -353,7 +360,7 @@ __global__ void __launch_bounds__(kTripThreads) k_triplet(TripletArgs a) {
 
         // ---- B + C: j-k tests, queued hits evaluated two per lane
         double fax = 0.0, fay = 0.0, faz = 0.0;
-        int qn = 0;  // wave-uniform
+        int qh = 0, qt = 0;  // ring queue head and tail (wave-uniform)
         auto scatter = [&](const AtmOut<T> &o, int j, int k) {
             atomicAdd(&L.px[j], (double)o.fjx);
             atomicAdd(&L.py[j], (double)o.fjy);
@@ -381,8 +388,9 @@ __global__ void __launch_bounds__(kTripThreads) k_triplet(TripletArgs a) {
         // chain behind the first one's scatter.
         auto evaluate = [&](int cnt) {
             const bool v1 = lane < cnt, v2 = lane + kWave < cnt;
-            const int e1 = v1 ? Q[lane] : 0;
-            const int e2 = v2 ? Q[lane + kWave] : e1;
+            const int e1 = v1 ? Q[(qh + lane) & kQueueMask] : 0;
+            const int e2 = v2 ? Q[(qh + kWave + lane) & kQueueMask] : e1;
+            qh += cnt;
             const int j1 = e1 & 0xff, k1 = e1 >> 8, j2 = e2 & 0xff, k2 = e2 >> 8;
             const DispEnt uj1 = L.u[j1], uk1 = L.u[k1], uj2 = L.u[j2], uk2 = L.u[k2];
             const AtmOut<T> o1 = atm_triplet<T>(uj1, uk1, nu);
@@ -408,26 +416,24 @@ __global__ void __launch_bounds__(kTripThreads) k_triplet(TripletArgs a) {
             const int D = m >> 1;
             const bool even = (m & 1) == 0;
             // Lane -> (j, phase): with P = max(1, 64 / m) phases, lane l takes entry
-            // j = jb + l % span and the circular distances dd = 1 + phase + 2 P r and
-            // 1 + phase + (2 r + 1) P in round r, so all m(m-1)/2 pairs j < k (as
-            // unordered pairs) are tested once: dd <= D, and for even m the distance D
-            // only from j < D.
+            // j = jb + l % span and the circular distances dd = 1 + phase, 1 + phase + P,
+            // 1 + phase + 2P, ... (two per round), so all m(m-1)/2 unordered pairs are
+            // tested once: dd <= D, and for even m the distance D only from j < D.
             const int P = m < kWave ? kWave / m : 1;
             const int span = m < kWave ? m : kWave;
             for (int jb = 0; jb < m; jb += span) {
                 const int j = jb + lane % span;
                 const int phase = lane / span;
-                const bool lane_ok = phase < P && j < m;
-                float4 fj = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                if (lane_ok) fj = L.f[j];
+                // largest distance this lane tests (-1: idle lane)
+                const int Dj = (phase < P && j < m) ? ((even && j >= D) ? D - 1 : D) : -1;
+                const float4 fj = L.f[Dj >= 0 ? j : 0];
+                int dd = 1 + phase;
+                int k1 = j + dd;
+                k1 -= k1 >= m ? m : 0;
                 for (int d0 = 1; d0 <= D; d0 += 2 * P) {
-                    const int dd1 = d0 + phase, dd2 = d0 + P + phase;
-                    int k1 = j + dd1, k2 = j + dd2;
-                    if (k1 >= m) k1 -= m;
-                    if (k2 >= m) k2 -= m;
-                    const bool c1 = lane_ok && dd1 <= D && !(even && dd1 == D && j >= D);
-                    const bool c2 = lane_ok && dd2 <= D && !(even && dd2 == D && j >= D);
-                    // c2 implies c1; both tests run as straight-line code
+                    int k2 = k1 + P;
+                    k2 -= k2 >= m ? m : 0;
+                    const bool c1 = dd <= Dj, c2 = dd + P <= Dj;  // c2 implies c1
                     const float4 fk1 = L.f[c1 ? k1 : 0];
                     const float4 fk2 = L.f[c2 ? k2 : 0];
                     const float vx1 = fk1.x - fj.x, vy1 = fk1.y - fj.y, vz1 = fk1.z - fj.z;
@@ -456,28 +462,25 @@ __global__ void __launch_bounds__(kTripThreads) k_triplet(TripletArgs a) {
                             }
                         }
                     }
+                    // append the hits to the ring queue, lane order, first then second
                     const uint64_t m1 = __ballot(hit1), m2 = __ballot(hit2);
                     const int n1 = __popcll(m1);
-                    if (hit1) Q[qn + __popcll(m1 & lt_mask)] = (unsigned short)(j | (k1 << 8));
-                    if (hit2) Q[qn + n1 + __popcll(m2 & lt_mask)] = (unsigned short)(j | (k2 << 8));
-                    qn += n1 + __popcll(m2);
+                    if (hit1) Q[(qt + below(m1)) & kQueueMask] = (unsigned short)(j | (k1 << 8));
+                    if (hit2) Q[(qt + n1 + below(m2)) & kQueueMask] = (unsigned short)(j | (k2 << 8));
+                    qt += n1 + __popcll(m2);
                     __builtin_amdgcn_wave_barrier();
-                    if (qn >= 2 * kWave) {
+                    if (qt - qh >= 2 * kWave) {
                         evaluate(2 * kWave);
                         ntrip += 2 * kWave;
-                        qn -= 2 * kWave;
-                        const int r1 = lane < qn ? Q[2 * kWave + lane] : 0;
-                        const int r2 = lane + kWave < qn ? Q[3 * kWave + lane] : 0;
-                        __builtin_amdgcn_wave_barrier();
-                        if (lane < qn) Q[lane] = (unsigned short)r1;
-                        if (lane + kWave < qn) Q[kWave + lane] = (unsigned short)r2;
-                        __builtin_amdgcn_wave_barrier();
                     }
+                    dd += 2 * P;
+                    k1 = k2 + P;
+                    k1 -= k1 >= m ? m : 0;
                 }
             }
-            if (qn > 0) {
-                evaluate(qn);
-                ntrip += qn;
+            if (qt > qh) {
+                ntrip += qt - qh;
+                evaluate(qt - qh);
             }
         }
         fax = wave_sum(fax);
