@@ -321,7 +321,7 @@ mts_status alloc_all(mts_system *s) {
     HIP_TRY(s, dalloc(&s->stats, 4));
     HIP_TRY(s, dalloc(&s->x_ref, 3 * n));
     HIP_TRY(s, dalloc(&s->flags, 1));
-    HIP_TRY(s, dalloc(&s->row, 1));
+    HIP_TRY(s, dalloc(&s->row, 2));
     HIP_TRY(s, dalloc(&s->list_n, 1));
     HIP_TRY(s, dalloc(&s->xi, 3 * n));
     HIP_TRY(s, dalloc(&s->vi, 3 * n));
@@ -455,7 +455,7 @@ mts_status enqueue_pair(mts_system *s, double *f2) {
 }
 
 // Verlet list of the pair grid at its current binning.
-mts_status enqueue_list_build(mts_system *s) {
+ListBuildArgs list_build_args(const mts_system *s) {
     const Grid &g = s->lo.gp;
     ListBuildArgs a{};
     a.ncell = g.ncell;
@@ -472,13 +472,18 @@ mts_status enqueue_list_build(mts_system *s) {
     a.rv2 = rv * rv;
     a.flags = s->flags;
     a.stats = s->collect_stats ? s->stats + 2 : nullptr;
-    HIP_TRY(s, launch_list_build(s->st, a));
+    return a;
+}
+
+mts_status enqueue_list_build(mts_system *s) {
+    HIP_TRY(s, launch_list_build(s->st, list_build_args(s)));
     return MTS_OK;
 }
 
 // Update steps fused behind the list forces (see PairListArgs).
 struct Fused {
     bool kick2 = false, kick3_end = false, kick3_start = false, drift = false;
+    bool gather3 = false;  // gather F3 from the partial slots (into s->f3) first
     const double *f2prev = nullptr;
     Pos4 *xs_out = nullptr;
 };
@@ -505,6 +510,11 @@ mts_status enqueue_pair_list(mts_system *s, const Pos4 *xs_in, double *f2, const
     a.rc2 = s->p.rc_pair * s->p.rc_pair;
     a.ushift = s->ushift;
     a.flags = s->flags;
+    if (u.gather3) {
+        a.pf = s->pf;
+        a.inv_perm3 = s->lo.gt.inv_perm;
+        a.f3_out = s->f3;
+    }
     if (u.kick2 || u.kick3_end || u.kick3_start || u.drift) {
         a.kick2 = u.kick2;
         a.kick3_end = u.kick3_end;
@@ -528,8 +538,7 @@ mts_status enqueue_pair_list(mts_system *s, const Pos4 *xs_in, double *f2, const
     return MTS_OK;
 }
 
-mts_status enqueue_triplet(mts_system *s, double *f3, int *list_ijk, long long list_rows,
-                           bool energy) {
+TripletArgs triplet_args(const mts_system *s, int *list_ijk, long long list_rows, bool energy) {
     const Grid &g = s->lo.gt;
     TripletArgs a{};
     a.ncell = g.ncell;
@@ -551,15 +560,30 @@ mts_status enqueue_triplet(mts_system *s, double *f3, int *list_ijk, long long l
     a.list_n = s->list_n;
     a.list_rows = list_rows;
     a.stats = s->collect_stats ? s->stats : nullptr;
+    return a;
+}
+
+mts_status enqueue_triplet(mts_system *s, double *f3, int *list_ijk, long long list_rows,
+                           bool energy) {
     const long ts = timer_begin(s, 0);
-    HIP_TRY(s, launch_triplet(s->st, a, s->fp32, list_ijk != nullptr));
+    HIP_TRY(s, launch_triplet(s->st, triplet_args(s, list_ijk, list_rows, energy), s->fp32,
+                              list_ijk != nullptr));
     timer_end(s, 0, ts);
-    if (f3) HIP_TRY(s, launch_triplet_gather(s->st, s->n, s->pf, g.perm, f3, s->flags));
+    if (f3) HIP_TRY(s, launch_triplet_gather(s->st, s->n, s->pf, s->lo.gt.perm, f3, s->flags));
+    return MTS_OK;
+}
+
+// The triplet partial slots and the new pair list in one launch (timed as class 0).
+mts_status enqueue_triplet_and_list(mts_system *s, bool energy) {
+    const long ts = timer_begin(s, 0);
+    HIP_TRY(s, launch_triplet_and_list(s->st, triplet_args(s, nullptr, 0, energy),
+                                       list_build_args(s), s->fp32));
+    timer_end(s, 0, ts);
     return MTS_OK;
 }
 
 mts_status enqueue_reduce(mts_system *s, const double *v, bool pair, bool trip, double *out,
-                          int stride, const int *row, long long *count_out) {
+                          int stride, int *row, long long *count_out) {
     ReduceArgs a{};
     a.nsys = s->nsys;
     a.sd = s->lo.gt.sd;
@@ -611,12 +635,18 @@ mts_status enqueue_int(mts_system *s, const double *f2prev, const double *f2cur,
     return MTS_OK;
 }
 
-// Rebins both grids at the internal positions, rebuilds the pair list and computes F3
-// into s->f3 (list mode); the caller then computes F2 from the new list.
+// Rebins both grids at the internal positions, rebuilds the pair list and computes the
+// triplet partial slots (list mode); the caller's list force kernel then gathers F3.
 mts_status enqueue_full_step_list(mts_system *s, bool energy) {
     MTS_TRY(enqueue_bin(s, kBinPair | kBinTriplet, s->xi, true));
-    MTS_TRY(enqueue_list_build(s));
-    MTS_TRY(enqueue_triplet(s, s->f3, nullptr, 0, energy));
+    // The list-build workgroups of a shared launch reserve the triplet tile's LDS; past
+    // 64 KB (fewer than two triplet workgroups per CU) they run apart instead.
+    if (triplet_lds_bytes(s->lo.stage_cap, s->lo.list_cap) <= 64 * 1024) {
+        MTS_TRY(enqueue_triplet_and_list(s, energy));
+    } else {
+        MTS_TRY(enqueue_list_build(s));
+        MTS_TRY(enqueue_triplet(s, nullptr, nullptr, 0, energy));
+    }
     return MTS_OK;
 }
 
@@ -624,7 +654,9 @@ mts_status enqueue_full_step_list(mts_system *s, bool energy) {
 mts_status enqueue_entry_forces(mts_system *s, double *f2, bool energy) {
     if (s->lo.skin > 0.0) {
         MTS_TRY(enqueue_full_step_list(s, energy));
-        MTS_TRY(enqueue_pair_list(s, s->lo.gp.xs, f2, Fused{}, true));
+        Fused g;
+        g.gather3 = true;
+        MTS_TRY(enqueue_pair_list(s, s->lo.gp.xs, f2, g, true));
     } else {
         MTS_TRY(enqueue_bin(s, kBinPair | kBinTriplet, s->xi, false));
         MTS_TRY(enqueue_pair(s, f2));
@@ -636,12 +668,13 @@ mts_status enqueue_entry_forces(mts_system *s, double *f2, bool energy) {
 // One outer cycle of Algorithm 2 on the internal copies xi, vi.  On entry F2 of the
 // cycle's first position x^0 is in f2[0] and F3(x^0) in s->f3; on exit F2(x^k) is in
 // f2[k % 2] and F3(x^k) in s->f3, with the closing F3 half kick applied.
-// With a pair list (launches per cycle: k + 8, plus 3 with energies):
+// With a pair list (launches per cycle: k + 6, plus 2 with energies):
 //   step 0:          k_int: opening F3 kick, drift to x^1 (also into sorted buffer B)
 //   x^i, 0 < i < k:  k_pair_list at x^i: F2(x^i), then kick2 of step i-1 and the drift
 //                    of step i, positions ping-ponging between sorted buffers A and B
-//   x^k:             rebin both grids, rebuild the list, F3(x^k); k_pair_list at x^k:
-//                    F2(x^k), last kick2 and the closing F3 kick
+//   x^k:             rebin both grids (4 launches); one launch for the triplet partial
+//                    slots of x^k and the new pair list; k_pair_list at x^k: F2(x^k),
+//                    F3(x^k) gathered from the slots, last kick2 and the closing F3 kick
 // Without a list (skin 0) every step rebins the pair grid and runs the tile kernel.
 mts_status enqueue_cycle(mts_system *s, double *f2_0, double *f2_1, bool energies) {
     const int k = s->p.k;
@@ -659,6 +692,7 @@ mts_status enqueue_cycle(mts_system *s, double *f2_0, double *f2_1, bool energie
         }
         MTS_TRY(enqueue_full_step_list(s, energies));
         Fused u;
+        u.gather3 = true;
         u.kick2 = true;
         u.kick3_end = true;
         u.f2prev = f2[(k - 1) & 1];
@@ -680,7 +714,6 @@ mts_status enqueue_cycle(mts_system *s, double *f2_0, double *f2_1, bool energie
     }
     if (energies) {
         MTS_TRY(enqueue_reduce(s, s->vi, true, true, s->e_buf, kNE, s->row, nullptr));
-        HIP_TRY(s, launch_bump_row(s->st, s->row));
     }
     return MTS_OK;
 }
@@ -726,7 +759,6 @@ mts_status respa_internal(mts_system *s, double *x, double *v, int64_t n_iter, d
     if (energies) {
         HIP_TRY(s, launch_set_int(s->st, s->row, 0));
         MTS_TRY(enqueue_reduce(s, s->vi, true, true, s->e_buf, kNE, s->row, nullptr));
-        HIP_TRY(s, launch_bump_row(s->st, s->row));
     }
     const bool graph = s->use_graph && !s->timing;
     for (int64_t c = 0; c < cycles; ++c) {

@@ -264,6 +264,11 @@ struct PairListArgs {
     Pos4 *xs_out;           // [n] sorted positions after the drift
     const double *x_ref;    // positions at the last list build (input order)
     double half_skin2;
+    // optional: F3 gathered here from the triplet kernel's partial slots (fixed slot
+    // order, as k_triplet_gather), written to f3_out and used by the kicks instead of f3
+    const double *pf;       // [14][3][n] partial slots, or null
+    const int *inv_perm3;   // input -> sorted index of the triplet grid
+    double *f3_out;         // [n][3]
 };
 hipError_t launch_pair_list(hipStream_t st, const PairListArgs &a, bool fp32);
 size_t pair_lds_bytes(int stage_cap);
@@ -293,6 +298,10 @@ struct TripletArgs {
                             // list length before capping
 };
 hipError_t launch_triplet(hipStream_t st, const TripletArgs &a, bool fp32, bool listing);
+// One launch: the triplet forces of every triplet-grid cell, then (remaining workgroups)
+// the pair list of every pair-grid cell.
+hipError_t launch_triplet_and_list(hipStream_t st, const TripletArgs &a, const ListBuildArgs &b,
+                                   bool fp32);
 size_t triplet_lds_bytes(int stage_cap, int list_cap);
 hipError_t launch_triplet_gather(hipStream_t st, int64_t n, const double *pf, const int *perm,
                                  double *f, int *flags);
@@ -332,12 +341,13 @@ struct ReduceArgs {
     int stride;             // 5: {K,U2,U3,W2,W3}; 2: {U,W} from whichever source is non-null
     long long *count_out;   // [nsys] triplet counts or null
     int *flags;
-    const int *row;         // optional device row index: out += (*row) * nsys * stride
+    int *row;               // optional device row counter [2]: row[0] is the row to write
+                            // (out += row * nsys * stride) and is advanced by one; row[1]
+                            // holds the row in use between the two passes
     double *part;           // scratch [nsys][kRedChunks][6]
 };
 constexpr int kRedChunks = 64;
 hipError_t launch_reduce(hipStream_t st, const ReduceArgs &a);
-hipError_t launch_bump_row(hipStream_t st, int *row);
 hipError_t launch_set_int(hipStream_t st, int *p, int v);  // a kernel, so it may be captured
 
 }  // namespace mts

@@ -80,6 +80,11 @@ __global__ void __launch_bounds__(kRed) k_reduce_part(ReduceArgs a) {
     const int64_t pb = d.p0 + c * lp, pe = d.p0 + min(d.n, (c + 1) * lp);
     const int lc = (d.ncell + kRedChunks - 1) / kRedChunks;
     const int cb = d.cell0 + c * lc, ce = d.cell0 + min(d.ncell, (c + 1) * lc);
+    if (a.row && blockIdx.x == 0 && t == 0) {  // the row this record goes to; advance
+        const int r = a.row[0];
+        a.row[1] = r;
+        a.row[0] = r + 1;
+    }
     double kin = 0.0, u2 = 0.0, w2 = 0.0, u3 = 0.0, w3 = 0.0, cnt = 0.0;
     if (a.v)
         for (int64_t i = pb + t; i < pe; i += kRed) {
@@ -120,7 +125,7 @@ __global__ void k_reduce_final(ReduceArgs a) {
     const double kin = r[0] * a.half_mass;
     double *out = a.out;
     if (out) {
-        if (a.row) out += (int64_t)(*a.row) * a.nsys * a.stride;
+        if (a.row) out += (int64_t)a.row[1] * a.nsys * a.stride;
         out += (int64_t)s * a.stride;
         if (a.stride == kNE) {
             out[0] = kin; out[1] = r[1]; out[2] = r[2]; out[3] = r[3]; out[4] = r[4];
@@ -134,8 +139,6 @@ __global__ void k_reduce_final(ReduceArgs a) {
     for (int q = 0; q < 5; ++q) ok = ok && isfinite(r[q]);
     if (!ok) atomicOr(a.flags, kFlagNonFinite);
 }
-
-__global__ void k_bump_row(int *row) { *row += 1; }
 
 __global__ void k_set_int(int *p, int v) { *p = v; }
 
@@ -160,9 +163,5 @@ hipError_t launch_set_int(hipStream_t st, int *p, int v) {
     return hipGetLastError();
 }
 
-hipError_t launch_bump_row(hipStream_t st, int *row) {
-    k_bump_row<<<1, 1, 0, st>>>(row);
-    return hipGetLastError();
-}
 
 }  // namespace mts

@@ -38,7 +38,10 @@
 // Cutoff geometry is FP64 and canonical, so the triplet set is bit-identical to the
 // FP64 oracle's in both precisions; T is the precision of the ATM arithmetic.  LDS
 // arrays are structure-of-arrays so that consecutive lanes touch consecutive banks.
+#include <algorithm>
+
 #include "common.h"
+#include "list_build.h"
 
 namespace mts {
 
@@ -239,15 +242,15 @@ __device__ __forceinline__ int tile_slot(const StencilTable<kNumHalf> &tab, int 
     return tab.begin[o] + (t - tab.off[o]);
 }
 
+// The triplet work of one base cell (one workgroup of kTripThreads threads).
 template <typename T, bool LIST, bool ENERGY>
-__global__ void __launch_bounds__(kTripThreads) k_triplet(TripletArgs a) {
-    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+__device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
+                                              unsigned char *smem_raw) {
     __shared__ int s_turn;
     __shared__ double s_red[kTripWaves][2];
     __shared__ int s_cnt[kTripWaves];
     __shared__ StencilTable<kNumHalf> tab;
     const int CAP = a.stage_cap, LC = a.list_cap;
-    const int base = blockIdx.x;
     const int tid = threadIdx.x;
     const int wave = tid / kWave, lane = tid % kWave;
     const int64_t n = a.n;
@@ -563,6 +566,43 @@ __global__ void __launch_bounds__(256) k_triplet_gather(int64_t n, const double 
 }
 
 template <typename T, bool LIST, bool ENERGY>
+__global__ void __launch_bounds__(kTripThreads) k_triplet(TripletArgs a) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    triplet_block<T, LIST, ENERGY>(a, blockIdx.x, smem_raw);
+}
+
+// The triplet forces of every triplet-grid cell and, in the same launch, the Verlet list
+// rows of every pair-grid cell (workgroups past the triplet cells): the list build fills
+// the compute units that the triplet workgroups leave idle as they drain.
+template <typename T, bool ENERGY>
+__global__ void __launch_bounds__(kTripThreads) k_triplet_and_list(TripletArgs a, ListBuildArgs b) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    if ((int)blockIdx.x < a.ncell)
+        triplet_block<T, false, ENERGY>(a, blockIdx.x, smem_raw);
+    else
+        list_build_block(b, (int)blockIdx.x - a.ncell, smem_raw);
+}
+
+template <typename T, bool ENERGY>
+static hipError_t launch_triplet_and_list_t(hipStream_t st, const TripletArgs &a,
+                                            const ListBuildArgs &b) {
+    const size_t lds = std::max(triplet_lds_bytes(a.stage_cap, a.list_cap),
+                                list_build_bytes(b.stage_cap));
+    k_triplet_and_list<T, ENERGY><<<a.ncell + b.ncell, kTripThreads, lds, st>>>(a, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_triplet_and_list(hipStream_t st, const TripletArgs &a, const ListBuildArgs &b,
+                                   bool fp32) {
+    if (a.ncell + b.ncell <= 0) return hipSuccess;
+    if (fp32)
+        return a.ce ? launch_triplet_and_list_t<float, true>(st, a, b)
+                    : launch_triplet_and_list_t<float, false>(st, a, b);
+    return a.ce ? launch_triplet_and_list_t<double, true>(st, a, b)
+                : launch_triplet_and_list_t<double, false>(st, a, b);
+}
+
+template <typename T, bool LIST, bool ENERGY>
 static hipError_t launch_triplet_t(hipStream_t st, const TripletArgs &a) {
     const size_t lds = triplet_lds_bytes(a.stage_cap, a.list_cap);
     k_triplet<T, LIST, ENERGY><<<a.ncell, kTripThreads, lds, st>>>(a);
@@ -587,7 +627,11 @@ hipError_t configure_triplet_lds(size_t max_bytes) {
                          (const void *)k_triplet<double, true, false>,
                          (const void *)k_triplet<float, false, false>,
                          (const void *)k_triplet<float, false, true>,
-                         (const void *)k_triplet<float, true, false>};
+                         (const void *)k_triplet<float, true, false>,
+                         (const void *)k_triplet_and_list<double, false>,
+                         (const void *)k_triplet_and_list<double, true>,
+                         (const void *)k_triplet_and_list<float, false>,
+                         (const void *)k_triplet_and_list<float, true>};
     for (const void *f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_bytes);
         if (e != hipSuccess) return e;
