@@ -41,7 +41,7 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
 # scaled by the counts of a 256 MiB copy (FETCH_SIZE reads half the copied bytes: factor
 # 2.0; WRITE_SIZE factor 1.0).  Valid for this kernel version only; other workloads and
 # precisions report null.
-TRIPLET_TRAFFIC_BYTES = {("fcc32k_fp64_k10", "fp64"): 21462530}
+TRIPLET_TRAFFIC_BYTES = {}
 
 
 def _workload(name: str):
@@ -302,7 +302,10 @@ def main(argv=None):
         "kernel_ms": {"triplet": r["triplet_kernel_ms"], "pair": r["pair_kernel_ms"]},
         "energy_drift_per_particle": r["energy_drift_per_particle"],
         "rvite": r["rvite"],
-        "roofline": {"bound": "alu", "kernel": "k_triplet", "achieved": achieved, "peak": peak,
+        "roofline": {"bound": "alu",
+                     "kernel": ("k_triplet_and_list" if r["tuning"].get("shared_launch")
+                                else "k_triplet"),
+                     "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": TRIPLET_TRAFFIC_BYTES.get((w.name, precision))},
         "tuning": r["tuning"],

@@ -188,6 +188,7 @@ typedef struct {
     int32_t pair_cap;     /* pair tile capacity */
     int32_t nl_cap;       /* pair-list row capacity */
     int32_t trials;       /* configurations the last mts_autotune timed (0: cached/untuned) */
+    int32_t shared_launch;/* 1: the pair list is built in the triplet kernel's launch */
     double cycle_ms;      /* measured ms per outer r-RESPA cycle (0: untuned) */
 } mts_tuning;
 
@@ -221,7 +222,8 @@ mts_status mts_get_tuning(const mts_system *sys, mts_tuning *out);
  * HIP events recorded on the handle's stream. */
 mts_status mts_enable_kernel_timing(mts_system *sys, int32_t enable);
 
-/* Synchronising.  For kernel class 0 (triplet forces) and 1 (pair forces): launches[c]
+/* Synchronising.  For kernel class 0 (the triplet-force launch, which also builds the
+ * pair list when mts_tuning.shared_launch is 1) and 1 (pair forces): launches[c]
  * receives the number of timed launches since the last call and ms[c] their summed
  * duration in milliseconds (host arrays of 2).  Resets the counters. */
 mts_status mts_kernel_times(mts_system *sys, int64_t launches[2], double ms[2]);

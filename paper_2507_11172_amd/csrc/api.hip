@@ -416,8 +416,10 @@ void fill_bin_grid(BinGrid &b, Grid &g, double *x_ref) {
 
 // Counting sort of x into the pair grid and/or the triplet grid (one launch per pass);
 // with_ref also records the wrapped positions as the reference of the next skin check.
-mts_status enqueue_bin(mts_system *s, int which, const double *x, bool with_ref) {
+mts_status enqueue_bin(mts_system *s, int which, const double *x, bool with_ref,
+                       bool counted = false) {
     BinArgs a{};
+    a.counted = counted;
     a.n = s->n;
     a.x = x;
     a.sys_of = s->sys_of;
@@ -484,6 +486,7 @@ mts_status enqueue_list_build(mts_system *s) {
 struct Fused {
     bool kick2 = false, kick3_end = false, kick3_start = false, drift = false;
     bool gather3 = false;  // gather F3 from the partial slots (into s->f3) first
+    bool bin = false;      // with drift: first binning pass of both grids
     const double *f2prev = nullptr;
     Pos4 *xs_out = nullptr;
 };
@@ -510,6 +513,11 @@ mts_status enqueue_pair_list(mts_system *s, const Pos4 *xs_in, double *f2, const
     a.rc2 = s->p.rc_pair * s->p.rc_pair;
     a.ushift = s->ushift;
     a.flags = s->flags;
+    if (u.bin) {
+        a.nbin = 2;
+        fill_bin_grid(a.bin[0], s->lo.gp, nullptr);
+        fill_bin_grid(a.bin[1], s->lo.gt, nullptr);
+    }
     if (u.gather3) {
         a.pf = s->pf;
         a.inv_perm3 = s->lo.gt.inv_perm;
@@ -635,13 +643,17 @@ mts_status enqueue_int(mts_system *s, const double *f2prev, const double *f2cur,
     return MTS_OK;
 }
 
+// The list-build workgroups of a shared launch reserve the triplet tile's LDS; past
+// 64 KB (fewer than two triplet workgroups per CU) they run apart instead.
+bool shared_launch(const mts_system *s) {
+    return s->lo.skin > 0.0 && triplet_lds_bytes(s->lo.stage_cap, s->lo.list_cap) <= 64 * 1024;
+}
+
 // Rebins both grids at the internal positions, rebuilds the pair list and computes the
 // triplet partial slots (list mode); the caller's list force kernel then gathers F3.
-mts_status enqueue_full_step_list(mts_system *s, bool energy) {
-    MTS_TRY(enqueue_bin(s, kBinPair | kBinTriplet, s->xi, true));
-    // The list-build workgroups of a shared launch reserve the triplet tile's LDS; past
-    // 64 KB (fewer than two triplet workgroups per CU) they run apart instead.
-    if (triplet_lds_bytes(s->lo.stage_cap, s->lo.list_cap) <= 64 * 1024) {
+mts_status enqueue_full_step_list(mts_system *s, bool energy, bool counted = false) {
+    MTS_TRY(enqueue_bin(s, kBinPair | kBinTriplet, s->xi, true, counted));
+    if (shared_launch(s)) {
         MTS_TRY(enqueue_triplet_and_list(s, energy));
     } else {
         MTS_TRY(enqueue_list_build(s));
@@ -668,11 +680,12 @@ mts_status enqueue_entry_forces(mts_system *s, double *f2, bool energy) {
 // One outer cycle of Algorithm 2 on the internal copies xi, vi.  On entry F2 of the
 // cycle's first position x^0 is in f2[0] and F3(x^0) in s->f3; on exit F2(x^k) is in
 // f2[k % 2] and F3(x^k) in s->f3, with the closing F3 half kick applied.
-// With a pair list (launches per cycle: k + 6, plus 2 with energies):
+// With a pair list (launches per cycle: k + 5 for k > 1, plus 2 with energies):
 //   step 0:          k_int: opening F3 kick, drift to x^1 (also into sorted buffer B)
 //   x^i, 0 < i < k:  k_pair_list at x^i: F2(x^i), then kick2 of step i-1 and the drift
 //                    of step i, positions ping-ponging between sorted buffers A and B
-//   x^k:             rebin both grids (4 launches); one launch for the triplet partial
+//   x^k:             rebin both grids (3 launches: the last k_pair_list did the first
+//                    pass); one launch for the triplet partial
 //                    slots of x^k and the new pair list; k_pair_list at x^k: F2(x^k),
 //                    F3(x^k) gathered from the slots, last kick2 and the closing F3 kick
 // Without a list (skin 0) every step rebins the pair grid and runs the tile kernel.
@@ -688,9 +701,10 @@ mts_status enqueue_cycle(mts_system *s, double *f2_0, double *f2_1, bool energie
             u.drift = true;
             u.f2prev = f2[(i - 1) & 1];
             u.xs_out = i + 1 < k ? buf[(i + 1) & 1] : nullptr;  // x^k: a rebinning follows
+            u.bin = i + 1 == k;  // ... whose first pass this kernel does
             MTS_TRY(enqueue_pair_list(s, buf[i & 1], f2[i & 1], u, false));
         }
-        MTS_TRY(enqueue_full_step_list(s, energies));
+        MTS_TRY(enqueue_full_step_list(s, energies, k > 1));
         Fused u;
         u.gather3 = true;
         u.kick2 = true;
@@ -1131,6 +1145,7 @@ static void fill_tuning(const mts_system *s, mts_tuning *out) {
     out->nl_cap = s->lo.nl_cap;
     out->cycle_ms = s->tuned_ms;
     out->trials = s->tuned_trials;
+    out->shared_launch = shared_launch(s) ? 1 : 0;
 }
 
 mts_status mts_get_tuning(const mts_system *sys, mts_tuning *out) {

@@ -107,7 +107,7 @@ static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b -
 hipError_t launch_bin(hipStream_t st, const BinArgs &a) {
     if (a.ng < 1 || a.ng > 2) return hipErrorInvalidValue;
     const dim3 grid(blocks_for(a.n, 256), (unsigned)a.ng);
-    if (a.n > 0) k_bin_count<<<grid, 256, 0, st>>>(a);
+    if (a.n > 0 && !a.counted) k_bin_count<<<grid, 256, 0, st>>>(a);
     k_scan<<<(unsigned)a.ng, 1024, 0, st>>>(a);  // also for n = 0: start[] must be valid
     if (a.n > 0) {
         k_bin_scatter<<<grid, 256, 0, st>>>(a);
