@@ -226,10 +226,17 @@ __global__ void __launch_bounds__(256) k_pair_list(PairListArgs a) {
     const int r = (int)(gid % G);
     const bool act = p < a.n;
 
-    // per-particle loads first; the operands of the fused update are then issued
-    // together with the first list indices, so the two latencies overlap (lane r < 3
-    // owns component r of the update)
+    // The first 64 list entries of the row are loaded before the row length is known
+    // (the row is allocated to nl_cap entries; entries past the length are ignored), so
+    // that the index loads, the per-particle loads and, next, the operands of the fused
+    // update overlap with the position gathers (lane r < 3 owns component r of the
+    // update).
     const int64_t pp = act ? p : 0;
+    const int *row = a.nbr + pp * a.nl_cap;
+    constexpr int U = 64 / G;  // entries per lane in the first pass
+    int qn[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) qn[k] = row[min(r + k * G, a.nl_cap - 1)];
     const int cnt = act ? a.nn[pp] : 0;
     const Pos4 pi = a.xs[pp];
     const int64_t q = 3 * (int64_t)a.perm[pp] + (r < 3 ? r : 0);
@@ -262,8 +269,17 @@ __global__ void __launch_bounds__(256) k_pair_list(PairListArgs a) {
     double fx = 0.0, fy = 0.0, fz = 0.0, u = 0.0, w = 0.0;
     {
         const T sigma2 = (T)a.sigma2, eps24 = (T)(24.0 * a.eps), eps4 = (T)(4.0 * a.eps);
-        const int *row = a.nbr + pp * a.nl_cap;
-        for (int s0 = r; s0 < cnt; s0 += kListUnroll * G) {
+        {
+            Pos4 e[U];
+#pragma unroll
+            for (int k = 0; k < U; ++k) e[k] = a.xs[r + k * G < cnt ? qn[k] : (int)pp];
+#pragma unroll
+            for (int k = 0; k < U; ++k)
+                if (r + k * G < cnt)
+                    lj_accumulate<T, ENERGY>(pi, e[k], L, iL, a.rc2, sigma2, eps24, eps4, a.ushift,
+                                             fx, fy, fz, u, w);
+        }
+        for (int s0 = r + 64; s0 < cnt; s0 += kListUnroll * G) {  // rows longer than 64
             int qn[kListUnroll];
 #pragma unroll
             for (int k = 0; k < kListUnroll; ++k) {
