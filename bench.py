@@ -36,12 +36,12 @@ METRIC = "3-body triplets/s + r-RESPA MD steps/s, FP32 vs FP64 GPU at stated for
 # the unpacked rate, equal to the FP64 one).
 FLOPS_PER_TRIPLET = 100.0
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
-# HBM bytes per launch of the FP64 triplet kernel with energy records on the default
+# HBM bytes per launch of the FP64 triplet launch with energy records on the default
 # workload, from FETCH_SIZE and WRITE_SIZE counter runs of `bench.py --traffic-probe`
 # scaled by the counts of a 256 MiB copy (FETCH_SIZE reads half the copied bytes: factor
-# 2.0; WRITE_SIZE factor 1.0).  Valid for this kernel version only; other workloads and
-# precisions report null.
-TRIPLET_TRAFFIC_BYTES = {}
+# 2.0; WRITE_SIZE factor 1.0).  Valid for this kernel version only; other workloads,
+# precisions and kernels report null.
+TRIPLET_TRAFFIC_BYTES = {("fcc32k_fp64_k10", "fp64", "k_triplet_and_list"): 34563050}
 
 
 def _workload(name: str):
@@ -219,9 +219,10 @@ def cpu_baseline(w, k: int):
 
 
 def traffic_probe(w, precision: str, k: int, tune_ms: int):
-    """For HBM counter runs (FETCH_SIZE / WRITE_SIZE): the tuned triplet-force call with
-    energies, five times, then three copies of a 256 MiB tensor (the calibration kernel:
-    262,144 KiB read and written each)."""
+    """For HBM counter runs (FETCH_SIZE / WRITE_SIZE): four outer cycles of the tuned
+    r-RESPA loop with energy records (the triplet launch of the timed region, once per
+    cycle), then three copies of a 256 MiB tensor (the calibration kernel: 262,144 KiB
+    read and written each)."""
     import torch
     from paper_2507_11172_amd import mts
 
@@ -231,10 +232,8 @@ def traffic_probe(w, precision: str, k: int, tune_ms: int):
     with mts.System(_params(w, precision, k), w.n_particles.tolist(), w.box) as sysm:
         if tune_ms > 0:
             sysm.autotune(x, v, tune_ms)
-        f = torch.empty_like(x)
-        ew = torch.zeros((w.n_systems, 2), dtype=torch.float64, device=dev)
-        for _ in range(5):
-            sysm.compute_triplet_forces(x, f, ew)
+        e = torch.zeros((5, w.n_systems, mts.MTS_NE), dtype=torch.float64, device=dev)
+        sysm.respa_step(x, v, 4 * k, e)
         sysm.sync()
     a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev).fill_(1.0)
     for _ in range(3):
@@ -280,6 +279,7 @@ def main(argv=None):
     trip_s = r["triplet_kernel_ms"] * 1e-3
     achieved = FLOPS_PER_TRIPLET * r["triplets_per_eval"] / trip_s / 1e12 if trip_s > 0 else 0.0
     peak = PEAK_TFLOPS[precision]
+    kernel = "k_triplet_and_list" if r["tuning"].get("shared_launch") else "k_triplet"
     out = {
         "metric": METRIC,
         "value": steps_per_s,
@@ -302,12 +302,9 @@ def main(argv=None):
         "kernel_ms": {"triplet": r["triplet_kernel_ms"], "pair": r["pair_kernel_ms"]},
         "energy_drift_per_particle": r["energy_drift_per_particle"],
         "rvite": r["rvite"],
-        "roofline": {"bound": "alu",
-                     "kernel": ("k_triplet_and_list" if r["tuning"].get("shared_launch")
-                                else "k_triplet"),
-                     "achieved": achieved, "peak": peak,
+        "roofline": {"bound": "alu", "kernel": kernel, "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": TRIPLET_TRAFFIC_BYTES.get((w.name, precision))},
+                     "traffic": TRIPLET_TRAFFIC_BYTES.get((w.name, precision, kernel))},
         "tuning": r["tuning"],
     }
     if w.n_systems > 1:

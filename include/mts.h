@@ -128,7 +128,11 @@ mts_status mts_compute_triplet_forces(mts_system *sys, const double *x, double *
  *   e_full  dev [n_iter/k + 1][n_systems][MTS_NE] energies at x^0 and after every full
  *           step (only full steps have synchronised velocities), or NULL.
  * Both forces are recomputed at x^0 on entry, as Algorithm 2 does, so two calls of
- * n and m steps equal one call of n + m steps. */
+ * n and m steps equal one call of n + m steps.  Between full steps the pair forces come
+ * from a Verlet list of radius rc_pair + skin built at every full step (see
+ * mts_params.skin and mts_autotune); a particle that moves more than half the skin from
+ * its position at the build is reported by the next mts_sync as MTS_ERR_CAPACITY (the
+ * forces since may miss pairs; the skin is enlarged for the next call). */
 mts_status mts_respa_step(mts_system *sys, double *x, double *v, int64_t n_iter, double *e_full);
 
 /* Waits for the stream and reports device flags raised since the last mts_sync:

@@ -70,4 +70,20 @@ def test_null_arguments(lib):
     assert lib.mts_init_system(None, 1, None, None, None, None) == -1
     assert lib.mts_sync(None) == -1
     assert lib.mts_respa_step(None, None, None, 0, None) == -1
+    assert lib.mts_autotune(None, None, None, 0, None) == -1
+    assert lib.mts_get_tuning(None, None) == -1
+    assert lib.mts_set_option(None, 1, 1) == -1
     lib.mts_destroy_system(None)  # ignored
+
+
+def test_tuning_struct_matches_header(lib):
+    """The binding's mts_tuning mirrors the header's field order and types."""
+    import re
+    from paper_2507_11172_amd import mts
+    hdr = open(os.path.join(ROOT, "include", "mts.h")).read()
+    body = hdr[hdr.index("typedef struct {", hdr.index("---- autotuning")):hdr.index("} mts_tuning;")]
+    fields = re.findall(r"^\s*(double|int32_t)\s+(\w+);", body, re.M)
+    py = [(n, t) for n, t in mts.mts_tuning._fields_]
+    assert [f[1] for f in fields] == [n for n, _ in py]
+    for (ctype, _), (_, t) in zip(fields, py):
+        assert (ctype == "double") == (t is C.c_double)
