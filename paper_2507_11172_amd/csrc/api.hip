@@ -199,8 +199,10 @@ constexpr int kMaxListCap = 256;
 // assumes a local density of max(0.9, 1.2 x the system's mean), which covers LJ liquids
 // and crystals near the densities of the paper's scenarios, including a liquid slab
 // inside a dilute box.  The triplet tile holds the 14 cells of the forward half stencil
-// and the pair tile all 27 cells of the pair grid; a forward-neighbour list holds about
-// half a cutoff sphere and a pair-list row a whole (rc + skin) sphere.  Overflow is
+// and the pair tile all 27 cells of the pair grid.  An anchor's forward-neighbour list
+// holds half a cutoff sphere on average but, for an anchor at the low corner of its cell,
+// up to about a whole one, so it is sized like a pair-list row (a whole (rc + skin)
+// sphere).  Overflow is
 // detected on the device, reported by mts_sync, and doubles the capacity for the next
 // call; mts_autotune sizes them from the maxima observed on the real input instead.
 void size_tiles(const mts_system *s, Layout &lo) {
@@ -210,7 +212,7 @@ void size_tiles(const mts_system *s, Layout &lo) {
     const double rc3 = s->p.rc_triplet, rv = s->p.rc_pair + lo.skin;
     lo.stage_cap = std::min(2048, round_up((int)std::ceil(kNumHalf * vt * 1.1) + 16, 32));
     lo.pair_cap = std::min(2048, round_up((int)std::ceil(kNumFull * vp * 1.1) + 16, 32));
-    lo.list_cap = std::min(kMaxListCap, round_up((int)std::ceil(1.6 * rho_t * (2.0 / 3.0) * M_PI * rc3 * rc3 * rc3) + 8, 16));
+    lo.list_cap = std::min(kMaxListCap, round_up((int)std::ceil(1.25 * rho_t * (4.0 / 3.0) * M_PI * rc3 * rc3 * rc3) + 8, 16));
     lo.nl_cap = std::min(2048, round_up((int)std::ceil(1.3 * rho_p * (4.0 / 3.0) * M_PI * rv * rv * rv) + 16, 32));
 }
 
@@ -336,7 +338,7 @@ mts_status alloc_all(mts_system *s) {
     }
     if (n > 0) HIP_TRY(s, hipMemcpy(s->sys_of, so.data(), sizeof(int) * n, hipMemcpyHostToDevice));
     HIP_TRY(s, hipMemset(s->flags, 0, sizeof(int)));
-    HIP_TRY(s, hipMemset(s->pf, 0, sizeof(double) * kNumHalf * 3 * (n > 0 ? n : 1)));
+    if (n > 0) HIP_TRY(s, hipMemset(s->pf, 0, sizeof(double) * kNumHalf * 3 * n));
     return MTS_OK;
 }
 

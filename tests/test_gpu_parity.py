@@ -485,3 +485,92 @@ def test_autotune_keeps_parity_and_caches(case):
         for key in ("skin", "cell_factor", "list_lanes", "stage_cap", "list_cap", "nl_cap"):
             assert t2[key] == t[key], key
         assert s2.tuning()["list_lanes"] == t["list_lanes"]
+
+
+def test_empty_and_tiny_systems():
+    """Degenerate inputs: an empty system, one particle, two particles, and a ragged batch
+    that mixes them with a regular system -- forces, counts and trajectories vs the oracle."""
+    torch = _torch()
+    from paper_2507_11172_amd import mts
+    box = np.array([8.55, 8.55, 8.55])
+    rng = W.rng_for(11)
+    tiny = {0: np.zeros((0, 3)), 1: np.array([[1.0, 2.0, 3.0]]),
+            2: np.array([[1.0, 1.0, 1.0], [2.1, 1.3, 0.9]])}
+    for n, x in tiny.items():
+        w = W.Workload("tiny%d" % n, x, np.zeros_like(x), box[None, :], np.array([n]),
+                       np.array([0.0]))
+        with _system(w, k=2) as s:
+            xd = torch.tensor(x, dtype=torch.float64, device="cuda").reshape(n, 3)
+            f2, f3 = torch.zeros_like(xd), torch.zeros_like(xd)
+            e2 = torch.zeros((1, 2), dtype=torch.float64, device="cuda")
+            e3 = torch.zeros((1, 2), dtype=torch.float64, device="cuda")
+            s.compute_pair_forces(xd, f2, e2)
+            s.compute_triplet_forces(xd, f3, e3)
+            assert s.count_triplets(xd) == 0
+            v = torch.zeros_like(xd)
+            e = torch.zeros((3, 1, mts.MTS_NE), dtype=torch.float64, device="cuda")
+            s.respa_step(xd, v, 4, e)
+            s.sync()
+        r2 = oracle.pair_forces(x, box) if n else None
+        if n:
+            assert np.abs(f2.cpu().numpy() - r2.f).max() <= 1e-12 * max(1.0, np.abs(r2.f).max())
+            assert float(e2.cpu()[0, 0]) == pytest.approx(r2.energy, rel=1e-12, abs=1e-14)
+        assert not f3.cpu().numpy().any() and float(e3.cpu()[0, 0]) == 0.0
+    # ragged batch: empty, one, two and a regular 500-particle system in one handle
+    wr = W.plain_fp64()
+    xs = [tiny[0], tiny[1], tiny[2], wr.x]
+    ns = [0, 1, 2, wr.n_total]
+    wb = W.Workload("ragged", np.concatenate(xs), np.zeros((sum(ns), 3)),
+                    np.stack([box, box, box, wr.box[0]]), np.array(ns), np.zeros(4))
+    with _system(wb) as s:
+        x = _dev(wb.x)
+        f3 = torch.empty_like(x)
+        s.compute_triplet_forces(x, f3)
+        assert s.count_triplets(x) == oracle.triplet_forces(wr.x, wr.box[0]).count
+        s.sync()
+    ref = oracle.triplet_forces(wr.x, wr.box[0]).f
+    assert not f3.cpu().numpy()[:3].any()
+    assert rel_err(f3.cpu().numpy()[3:], ref) <= 1e-12
+
+
+def test_dilute_gas_has_no_interactions():
+    """Particles farther apart than both cutoffs: zero forces, energies and triplets."""
+    torch = _torch()
+    g = np.arange(4) * 3.0 + 0.5
+    x = np.stack(np.meshgrid(g, g, g, indexing="ij"), axis=-1).reshape(-1, 3)
+    w = W.Workload("dilute", x, np.zeros_like(x), np.full((1, 3), 12.0), np.array([64]),
+                   np.array([0.0]))
+    with _system(w) as s:
+        xd = _dev(x)
+        f2, f3 = torch.empty_like(xd), torch.empty_like(xd)
+        e2 = torch.zeros((1, 2), dtype=torch.float64, device="cuda")
+        e3 = torch.zeros((1, 2), dtype=torch.float64, device="cuda")
+        s.compute_pair_forces(xd, f2, e2)
+        s.compute_triplet_forces(xd, f3, e3)
+        assert s.count_triplets(xd) == 0
+        s.sync()
+    assert not f2.cpu().numpy().any() and not f3.cpu().numpy().any()
+    assert float(e2.cpu()[0, 0]) == 0.0 and float(e3.cpu()[0, 0]) == 0.0
+
+
+def test_long_three_body_cutoff_big_lists():
+    """rc3 = 4.0 at rho 0.8: about 107 forward neighbours per anchor (the hit queue packs
+    list positions in 8 bits) -- triplet set and forces against the oracle."""
+    torch = _torch()
+    rng = W.rng_for(23)
+    n = 1500  # box 12.3: three triplet cells per edge
+    x, box = W.fcc_subset(n, 0.8, 0.05, rng)
+    w = W.Workload("long_rc3", x, np.zeros_like(x), box[None, :], np.array([n]),
+                   np.array([0.0]), rc_triplet=4.0)
+    ref = oracle.triplet_list(x, box, rc=4.0)
+    r3 = oracle.triplet_forces(x, box, rc=4.0)
+    with _system(w) as s:
+        xd = _dev(x)
+        got, total = s.list_triplets(xd, ref.shape[0] + 16)
+        f3 = torch.empty_like(xd)
+        s.compute_triplet_forces(xd, f3)
+        s.sync()
+    assert total == ref.shape[0]
+    g = got.cpu().numpy().astype(np.int64)
+    assert np.array_equal(g[np.lexsort((g[:, 2], g[:, 1], g[:, 0]))], ref.astype(np.int64))
+    assert rel_err(f3.cpu().numpy(), r3.f) <= 1e-12
