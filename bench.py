@@ -280,6 +280,9 @@ def main(argv=None):
     achieved = FLOPS_PER_TRIPLET * r["triplets_per_eval"] / trip_s / 1e12 if trip_s > 0 else 0.0
     peak = PEAK_TFLOPS[precision]
     kernel = "k_triplet_and_list" if r["tuning"].get("shared_launch") else "k_triplet"
+    ncls = int(r["tuning"].get("tile_classes", 1))
+    if ncls > 1:  # one launch per tile class, timed together
+        kernel += " + k_triplet x %d (tile classes)" % (ncls - 1)
     out = {
         "metric": METRIC,
         "value": steps_per_s,

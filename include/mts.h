@@ -187,12 +187,15 @@ typedef struct {
                              rebinned every inner step) */
     double cell_factor;   /* triplet cells have edges >= cell_factor * rc_triplet (>= 1) */
     int32_t list_lanes;   /* lanes per particle of the list force kernel (8 or 16) */
-    int32_t stage_cap;    /* triplet tile capacity (particles staged per workgroup) */
+    int32_t stage_cap;    /* largest triplet tile capacity (particles staged per workgroup)
+                             over the tile classes */
     int32_t list_cap;     /* forward-neighbour list capacity per anchor particle */
     int32_t pair_cap;     /* pair tile capacity */
     int32_t nl_cap;       /* pair-list row capacity */
     int32_t trials;       /* configurations the last mts_autotune timed (0: cached/untuned) */
     int32_t shared_launch;/* 1: the pair list is built in the triplet kernel's launch */
+    int32_t tile_classes; /* triplet launches per force evaluation: systems are grouped by
+                             the workgroups per CU their tile size allows, one launch each */
     double cycle_ms;      /* measured ms per outer r-RESPA cycle (0: untuned) */
 } mts_tuning;
 

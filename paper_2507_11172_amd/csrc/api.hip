@@ -49,8 +49,11 @@ struct Config {
     double skin = 0.0;            // pair-list skin in use (0: no list, rebin every step)
     double cell_factor = 1.0;     // triplet cell edge >= cell_factor * rc_triplet
     int lanes = 16;               // lanes per particle in the list force kernel
-    int stage_cap = 0, list_cap = 0, pair_cap = 0, nl_cap = 0;  // 0: sized by heuristics
+    int list_cap = 0, pair_cap = 0, nl_cap = 0;  // 0: sized by heuristics
+    std::vector<int> tile_need;   // triplet tile entries each system needs (empty: heuristic)
 };
+
+constexpr int kMaxTileClasses = 8;
 
 // Everything that depends on the configuration: the two cell grids, the capacities and
 // the buffers sized by them.  Rebuilt as a whole by build_layout.
@@ -58,7 +61,15 @@ struct Layout {
     Config cfg;
     Grid gt, gp;                  // triplet grid, pair grid
     double skin = 0.0;            // == cfg.skin
-    int stage_cap = 0, list_cap = 0, pair_cap = 0, nl_cap = 0;
+    int stage_cap = 0, list_cap = 0, pair_cap = 0, nl_cap = 0;  // stage_cap: largest class
+    // Tile classes: the triplet cells of systems whose tiles allow the same number of
+    // workgroups per CU form one class and one launch, which stages up to cls_cap[c]
+    // entries and covers the cells cls_cells[cls_off[c] .. cls_off[c + 1]).
+    int ncls = 0;
+    int cls_cap[kMaxTileClasses] = {};
+    int cls_off[kMaxTileClasses + 1] = {};
+    std::vector<int> cls_order;   // host copy of the cell order (all classes)
+    int *cls_cells = nullptr;     // [ncell_t] device; nullptr with one class (identity)
     double *ce = nullptr;         // [ncell_t][2] per-cell triplet energy/virial
     long long *cc = nullptr;      // [ncell_t] per-cell triplet counts
     int *nbr = nullptr;           // [n][nl_cap] pair list (pair-grid sorted indices)
@@ -76,6 +87,7 @@ struct mts_system {
     double lmin = 0.0;            // smallest box edge over all systems
     Layout lo;
     size_t max_lds = 64 * 1024;   // per-workgroup LDS limit of the device
+    size_t lds_per_cu = 64 * 1024;  // LDS of one CU
     bool collect_stats = false;   // kernels record tile and list maxima into stats
     double tuned_ms = 0.0;        // measured cycle time of the configuration (autotune)
     int tuned_trials = 0;
@@ -91,6 +103,8 @@ struct mts_system {
     long long *cnt_sys = nullptr; // [nsys]
     int *nn = nullptr;            // [n]
     int *stats = nullptr;         // [4] observed maxima (tile and list sizes), tuning only
+    int *tile_obs = nullptr;      // [nsys] largest triplet tile seen per system (overflow,
+                                  // tuning), zeroed after reading
     double *x_ref = nullptr;      // [n][3] wrapped positions at the last list build
     int *flags = nullptr;
     int *row = nullptr;
@@ -207,10 +221,16 @@ constexpr int kMaxListCap = 256;
 // call; mts_autotune sizes them from the maxima observed on the real input instead.
 void size_tiles(const mts_system *s, Layout &lo) {
     double rho_t, rho_p;
-    const double vt = max_cell_volume(lo.gt, rho_t);
+    (void)max_cell_volume(lo.gt, rho_t);
     const double vp = max_cell_volume(lo.gp, rho_p);
     const double rc3 = s->p.rc_triplet, rv = s->p.rc_pair + lo.skin;
-    lo.stage_cap = std::min(2048, round_up((int)std::ceil(kNumHalf * vt * 1.1) + 16, 32));
+    lo.cfg.tile_need.resize(s->nsys);
+    for (int q = 0; q < s->nsys; ++q) {
+        const SysDesc &d = lo.gt.hsd[q];
+        const double rho = std::max(0.9, 1.2 * (double)d.n / (d.L[0] * d.L[1] * d.L[2]));
+        const double v = rho * (d.L[0] / d.nc[0]) * (d.L[1] / d.nc[1]) * (d.L[2] / d.nc[2]);
+        lo.cfg.tile_need[q] = (int)std::ceil(kNumHalf * v * 1.1) + 16;
+    }
     lo.pair_cap = std::min(2048, round_up((int)std::ceil(kNumFull * vp * 1.1) + 16, 32));
     lo.list_cap = std::min(kMaxListCap, round_up((int)std::ceil(1.25 * rho_t * (4.0 / 3.0) * M_PI * rc3 * rc3 * rc3) + 8, 16));
     lo.nl_cap = std::min(2048, round_up((int)std::ceil(1.3 * rho_p * (4.0 / 3.0) * M_PI * rv * rv * rv) + 16, 32));
@@ -251,7 +271,7 @@ void free_grid(Grid &g) {
 void free_layout(Layout &lo) {
     free_grid(lo.gt);
     free_grid(lo.gp);
-    void *ptrs[] = {lo.ce, lo.cc, lo.nbr};
+    void *ptrs[] = {lo.ce, lo.cc, lo.nbr, lo.cls_cells};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     lo = Layout{};
@@ -269,6 +289,74 @@ double effective_skin(const mts_system *s, double skin) {
     return skin >= 0.05 * s->p.sigma ? skin : 0.0;
 }
 
+// Largest tile capacity (a multiple of 32) whose triplet workgroup fits `limit` bytes of
+// LDS with lists of lc entries.
+int cap_for_lds(const mts_system *s, int lc, size_t limit) {
+    const size_t fixed = triplet_lds_bytes(0, lc, s->fp32);
+    const size_t per = triplet_lds_bytes(1, lc, s->fp32) - fixed;
+    if (limit < fixed) return 0;
+    return (int)std::min<size_t>(4096, (limit - fixed) / per) / 32 * 32;
+}
+
+// Groups the systems into tile classes.  A system's tile need fixes how many triplet
+// workgroups fit on one CU (LDS and registers); systems with the same count share a
+// class, which gets the largest capacity with that count -- headroom against overflow at
+// no cost in occupancy.  A batch of boxes too small for three cells per edge (large cells,
+// tiles up to ~1.75 N) thus no longer drags every other system's workgroups down to its
+// own occupancy.  Classes run in order of decreasing occupancy, each as one launch; the
+// cell order lists each class's cells in system order.
+mts_status classify(const mts_system *s, Layout &lo) {
+    const int lc = lo.list_cap;
+    const int cmax = cap_for_lds(s, lc, s->max_lds);
+    auto occ = [&](int cap) {
+        const size_t b = triplet_lds_bytes(cap, lc, s->fp32);
+        const int r = triplet_blocks_per_cu(s->fp32, b, s->lds_per_cu);
+        return r > 0 ? r : std::max(1, std::min(2, (int)(s->lds_per_cu / (b + 2048))));
+    };
+    std::vector<int> occ_of(s->nsys), level;
+    for (int q = 0; q < s->nsys; ++q) {
+        const int c = round_up(std::max(32, lo.cfg.tile_need[q]), 32);
+        if (c > cmax) return MTS_ERR_UNSUPPORTED;
+        occ_of[q] = occ(c);
+        if (std::find(level.begin(), level.end(), occ_of[q]) == level.end()) level.push_back(occ_of[q]);
+    }
+    if ((int)level.size() > kMaxTileClasses) return MTS_ERR_UNSUPPORTED;
+    std::sort(level.begin(), level.end(), [](int a, int b) { return a > b; });
+    lo.ncls = (int)level.size();
+    lo.stage_cap = 0;
+    lo.cls_order.clear();
+    for (int c = 0; c < lo.ncls; ++c) {
+        int lo_i = 1;
+        for (int q = 0; q < s->nsys; ++q)
+            if (occ_of[q] == level[c]) lo_i = std::max(lo_i, round_up(std::max(32, lo.cfg.tile_need[q]), 32) / 32);
+        int hi_i = cmax / 32;
+        while (lo_i < hi_i) {  // largest capacity with at least this occupancy
+            const int mid = (lo_i + hi_i + 1) / 2;
+            if (occ(32 * mid) >= level[c]) lo_i = mid;
+            else hi_i = mid - 1;
+        }
+        lo.cls_cap[c] = 32 * lo_i;
+        lo.stage_cap = std::max(lo.stage_cap, lo.cls_cap[c]);
+        lo.cls_off[c] = (int)lo.cls_order.size();
+        for (int q = 0; q < s->nsys; ++q)
+            if (occ_of[q] == level[c]) {
+                const SysDesc &d = lo.gt.hsd[q];
+                for (int k = 0; k < d.ncell; ++k) lo.cls_order.push_back(d.cell0 + k);
+            }
+    }
+    lo.cls_off[lo.ncls] = (int)lo.cls_order.size();
+    return MTS_OK;
+}
+
+// The class cell order on the device (none with a single class: identity order).
+mts_status upload_classes(mts_system *s, Layout &lo) {
+    if (lo.ncls <= 1) return MTS_OK;
+    if (!lo.cls_cells) HIP_TRY(s, dalloc(&lo.cls_cells, lo.gt.ncell));
+    HIP_TRY(s, hipMemcpy(lo.cls_cells, lo.cls_order.data(), sizeof(int) * lo.cls_order.size(),
+                         hipMemcpyHostToDevice));
+    return MTS_OK;
+}
+
 // Builds a complete layout for cfg into `out` without touching the handle's own.
 mts_status build_layout(mts_system *s, const Config &cfg, Layout &out) {
     out = Layout{};
@@ -281,21 +369,20 @@ mts_status build_layout(mts_system *s, const Config &cfg, Layout &out) {
         return r;
     }
     size_tiles(s, out);
-    if (cfg.stage_cap > 0) out.stage_cap = cfg.stage_cap;
+    if ((int)cfg.tile_need.size() == s->nsys) out.cfg.tile_need = cfg.tile_need;
     if (cfg.list_cap > 0) out.list_cap = cfg.list_cap;
     if (cfg.pair_cap > 0) out.pair_cap = cfg.pair_cap;
     if (cfg.nl_cap > 0) out.nl_cap = cfg.nl_cap;
-    out.cfg.stage_cap = out.stage_cap;
     out.cfg.list_cap = out.list_cap;
     out.cfg.pair_cap = out.pair_cap;
     out.cfg.nl_cap = out.nl_cap;
-    if (triplet_lds_bytes(out.stage_cap, out.list_cap) > s->max_lds ||
-        pair_lds_bytes(out.pair_cap) > s->max_lds) {
+    if (classify(s, out) != MTS_OK || pair_lds_bytes(out.pair_cap) > s->max_lds) {
         out = Layout{};
         return MTS_ERR_UNSUPPORTED;
     }
     r = alloc_grid(s, out.gt);
     if (r == MTS_OK) r = alloc_grid(s, out.gp);
+    if (r == MTS_OK) r = upload_classes(s, out);
     if (r == MTS_OK && (dalloc(&out.ce, 2 * (size_t)out.gt.ncell) != hipSuccess ||
                         dalloc(&out.cc, out.gt.ncell) != hipSuccess ||
                         dalloc(&out.nbr, (size_t)s->n * out.nl_cap) != hipSuccess ||
@@ -321,6 +408,8 @@ mts_status alloc_all(mts_system *s) {
     HIP_TRY(s, dalloc(&s->cnt_sys, s->nsys));
     HIP_TRY(s, dalloc(&s->nn, n));
     HIP_TRY(s, dalloc(&s->stats, 4));
+    HIP_TRY(s, dalloc(&s->tile_obs, s->nsys));
+    HIP_TRY(s, hipMemset(s->tile_obs, 0, sizeof(int) * s->nsys));
     HIP_TRY(s, dalloc(&s->x_ref, 3 * n));
     HIP_TRY(s, dalloc(&s->flags, 1));
     HIP_TRY(s, dalloc(&s->row, 2));
@@ -372,8 +461,8 @@ void free_all(mts_system *s) {
         for (hipEvent_t e : s->ev_pool[c]) (void)hipEventDestroy(e);
     free_layout(s->lo);
     void *ptrs[] = {s->sys_of, s->red_part, s->f2a, s->f2b, s->f3, s->pf, s->pe, s->cnt_sys,
-                    s->nn, s->stats, s->x_ref, s->flags, s->row, s->e_buf, s->list_n, s->xi,
-                    s->vi};
+                    s->nn, s->stats, s->tile_obs, s->x_ref, s->flags, s->row, s->e_buf, s->list_n,
+                    s->xi, s->vi};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -548,10 +637,14 @@ mts_status enqueue_pair_list(mts_system *s, const Pos4 *xs_in, double *f2, const
     return MTS_OK;
 }
 
-TripletArgs triplet_args(const mts_system *s, int *list_ijk, long long list_rows, bool energy) {
-    const Grid &g = s->lo.gt;
+// Arguments of the launch of tile class cls.
+TripletArgs triplet_args(const mts_system *s, int cls, int *list_ijk, long long list_rows,
+                         bool energy) {
+    const Layout &lo = s->lo;
+    const Grid &g = lo.gt;
     TripletArgs a{};
-    a.ncell = g.ncell;
+    a.ncell = lo.cls_off[cls + 1] - lo.cls_off[cls];
+    a.cell_map = lo.cls_cells ? lo.cls_cells + lo.cls_off[cls] : nullptr;
     a.xs = g.xs;
     a.start = g.start;
     a.sd = g.sd;
@@ -563,31 +656,37 @@ TripletArgs triplet_args(const mts_system *s, int *list_ijk, long long list_rows
     a.n = s->n;
     a.nu = s->p.nu;
     a.rc2 = s->p.rc_triplet * s->p.rc_triplet;
-    a.stage_cap = s->lo.stage_cap;
-    a.list_cap = s->lo.list_cap;
+    a.stage_cap = lo.cls_cap[cls];
+    a.list_cap = lo.list_cap;
     a.flags = s->flags;
     a.list_ijk = list_ijk;
     a.list_n = s->list_n;
     a.list_rows = list_rows;
     a.stats = s->collect_stats ? s->stats : nullptr;
+    a.tile_obs = s->tile_obs;
     return a;
 }
 
+// The triplet partial slots of every cell: one launch per tile class.
 mts_status enqueue_triplet(mts_system *s, double *f3, int *list_ijk, long long list_rows,
                            bool energy) {
     const long ts = timer_begin(s, 0);
-    HIP_TRY(s, launch_triplet(s->st, triplet_args(s, list_ijk, list_rows, energy), s->fp32,
-                              list_ijk != nullptr));
+    for (int c = 0; c < s->lo.ncls; ++c)
+        HIP_TRY(s, launch_triplet(s->st, triplet_args(s, c, list_ijk, list_rows, energy), s->fp32,
+                                  list_ijk != nullptr));
     timer_end(s, 0, ts);
     if (f3) HIP_TRY(s, launch_triplet_gather(s->st, s->n, s->pf, s->lo.gt.perm, f3, s->flags));
     return MTS_OK;
 }
 
-// The triplet partial slots and the new pair list in one launch (timed as class 0).
+// The triplet partial slots and the new pair list: the list build shares the launch of
+// the first tile class (timed together as kernel class 0).
 mts_status enqueue_triplet_and_list(mts_system *s, bool energy) {
     const long ts = timer_begin(s, 0);
-    HIP_TRY(s, launch_triplet_and_list(s->st, triplet_args(s, nullptr, 0, energy),
+    HIP_TRY(s, launch_triplet_and_list(s->st, triplet_args(s, 0, nullptr, 0, energy),
                                        list_build_args(s), s->fp32));
+    for (int c = 1; c < s->lo.ncls; ++c)
+        HIP_TRY(s, launch_triplet(s->st, triplet_args(s, c, nullptr, 0, energy), s->fp32, false));
     timer_end(s, 0, ts);
     return MTS_OK;
 }
@@ -645,10 +744,10 @@ mts_status enqueue_int(mts_system *s, const double *f2prev, const double *f2cur,
     return MTS_OK;
 }
 
-// The list-build workgroups of a shared launch reserve the triplet tile's LDS; past
+// The list-build workgroups of a shared launch reserve the first tile class's LDS; past
 // 64 KB (fewer than two triplet workgroups per CU) they run apart instead.
 bool shared_launch(const mts_system *s) {
-    return s->lo.skin > 0.0 && triplet_lds_bytes(s->lo.stage_cap, s->lo.list_cap) <= 64 * 1024;
+    return s->lo.skin > 0.0 && triplet_lds_bytes(s->lo.cls_cap[0], s->lo.list_cap, s->fp32) <= 64 * 1024;
 }
 
 // Rebins both grids at the internal positions, rebuilds the pair list and computes the
@@ -831,8 +930,9 @@ std::string shape_key(const mts_system *s) {
 // Largest triplet tile, forward-neighbour candidate list, pair tile and pair-list row
 // seen on positions x with the current layout (the kernels record them with atomic
 // maxima; a capacity overflow raised meanwhile is cleared, the maxima are what counts).
-mts_status observe(mts_system *s, const double *x, int obs[4]) {
+mts_status observe(mts_system *s, const double *x, int obs[4], std::vector<int> &tile) {
     HIP_TRY(s, hipMemsetAsync(s->stats, 0, 4 * sizeof(int), s->st));
+    HIP_TRY(s, hipMemsetAsync(s->tile_obs, 0, sizeof(int) * s->nsys, s->st));
     s->collect_stats = true;
     mts_status r = enqueue_bin(s, kBinPair | kBinTriplet, x, false);
     if (r == MTS_OK) r = enqueue_list_build(s);
@@ -840,14 +940,18 @@ mts_status observe(mts_system *s, const double *x, int obs[4]) {
     s->collect_stats = false;
     MTS_TRY(r);
     HIP_TRY(s, hipMemcpyAsync(obs, s->stats, 4 * sizeof(int), hipMemcpyDeviceToHost, s->st));
+    tile.assign(s->nsys, 0);
+    HIP_TRY(s, hipMemcpyAsync(tile.data(), s->tile_obs, sizeof(int) * s->nsys, hipMemcpyDeviceToHost, s->st));
     HIP_TRY(s, hipStreamSynchronize(s->st));
     HIP_TRY(s, hipMemset(s->flags, 0, sizeof(int)));
+    HIP_TRY(s, hipMemset(s->tile_obs, 0, sizeof(int) * s->nsys));
     return MTS_OK;
 }
 
 // Capacities for the observed maxima, with room for the fluctuations of a run.
-void caps_from_observed(Config &c, const int obs[4]) {
-    c.stage_cap = std::min(2048, round_up((int)std::ceil(1.15 * obs[0]) + 16, 32));
+void caps_from_observed(Config &c, const int obs[4], const std::vector<int> &tile) {
+    c.tile_need.resize(tile.size());
+    for (size_t q = 0; q < tile.size(); ++q) c.tile_need[q] = (int)std::ceil(1.15 * tile[q]) + 16;
     c.list_cap = std::min(kMaxListCap, round_up((int)std::ceil(1.2 * obs[1]) + 8, 16));
     c.pair_cap = std::min(2048, round_up((int)std::ceil(1.15 * obs[2]) + 16, 32));
     if (c.skin > 0.0) c.nl_cap = std::min(2048, round_up((int)std::ceil(1.2 * obs[3]) + 16, 32));
@@ -919,6 +1023,11 @@ mts_status mts_init_system(const mts_params *params, int32_t n_systems, const in
             hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
             lds > 0)
             s->max_lds = (size_t)lds;
+        if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) == hipSuccess &&
+            lds > 0)
+            s->lds_per_cu = (size_t)lds;
+        else
+            s->lds_per_cu = s->max_lds;
         // keep room for the kernels' static LDS
         s->max_lds = s->max_lds > 1024 ? s->max_lds - 1024 : s->max_lds;
         if (configure_kernel_lds(s->max_lds) != hipSuccess) s->max_lds = 64 * 1024 - 1024;
@@ -1013,18 +1122,27 @@ mts_status mts_sync(mts_system *sys) {
     HIP_TRY(sys, hipMemcpy(&flags, sys->flags, sizeof(int), hipMemcpyDeviceToHost));
     HIP_TRY(sys, hipMemset(sys->flags, 0, sizeof(int)));
     if (flags & (kFlagStageOverflow | kFlagListOverflow | kFlagPairList)) {
-        const int old_s = sys->lo.stage_cap, old_l = sys->lo.list_cap, old_p = sys->lo.pair_cap,
-                  old_n = sys->lo.nl_cap;
+        Layout &lo = sys->lo;
+        const int old_s = lo.stage_cap, old_l = lo.list_cap, old_p = lo.pair_cap, old_n = lo.nl_cap;
+        const std::vector<int> old_need = lo.cfg.tile_need;
         if (flags & kFlagStageOverflow) {
-            sys->lo.stage_cap = std::min(4096, 2 * sys->lo.stage_cap);
-            sys->lo.pair_cap = std::min(4096, 2 * sys->lo.pair_cap);
+            // triplet tiles: every overflowing system recorded its size; pair tiles double
+            std::vector<int> obs(sys->nsys, 0);
+            HIP_TRY(sys, hipMemcpy(obs.data(), sys->tile_obs, sizeof(int) * sys->nsys, hipMemcpyDeviceToHost));
+            HIP_TRY(sys, hipMemset(sys->tile_obs, 0, sizeof(int) * sys->nsys));
+            for (int q = 0; q < sys->nsys; ++q)
+                if (obs[q] > 0)
+                    lo.cfg.tile_need[q] = std::max(lo.cfg.tile_need[q], (int)std::ceil(1.15 * obs[q]) + 16);
+            lo.pair_cap = std::min(4096, 2 * lo.pair_cap);
         }
-        if (flags & kFlagListOverflow) sys->lo.list_cap = std::min(kMaxListCap, 2 * sys->lo.list_cap);
-        if (triplet_lds_bytes(sys->lo.stage_cap, sys->lo.list_cap) > sys->max_lds) {
-            sys->lo.stage_cap = old_s;
-            sys->lo.list_cap = old_l;
+        if (flags & kFlagListOverflow) lo.list_cap = std::min(kMaxListCap, 2 * lo.list_cap);
+        if (classify(sys, lo) != MTS_OK) {  // beyond the LDS of a workgroup: keep the old sizes
+            lo.cfg.tile_need = old_need;
+            lo.list_cap = old_l;
+            (void)classify(sys, lo);
         }
-        if (pair_lds_bytes(sys->lo.pair_cap) > sys->max_lds) sys->lo.pair_cap = old_p;
+        MTS_TRY(upload_classes(sys, lo));
+        if (pair_lds_bytes(lo.pair_cap) > sys->max_lds) lo.pair_cap = old_p;
         if (flags & kFlagPairList) {
             const int cap = std::min(4096, 2 * sys->lo.nl_cap);
             int *nb = nullptr;
@@ -1034,7 +1152,6 @@ mts_status mts_sync(mts_system *sys) {
                 sys->lo.nl_cap = cap;
             }
         }
-        sys->lo.cfg.stage_cap = sys->lo.stage_cap;
         sys->lo.cfg.list_cap = sys->lo.list_cap;
         sys->lo.cfg.pair_cap = sys->lo.pair_cap;
         sys->lo.cfg.nl_cap = sys->lo.nl_cap;
@@ -1148,6 +1265,7 @@ static void fill_tuning(const mts_system *s, mts_tuning *out) {
     out->cycle_ms = s->tuned_ms;
     out->trials = s->tuned_trials;
     out->shared_launch = shared_launch(s) ? 1 : 0;
+    out->tile_classes = s->lo.ncls;
 }
 
 mts_status mts_get_tuning(const mts_system *sys, mts_tuning *out) {
@@ -1208,11 +1326,13 @@ mts_status mts_autotune(mts_system *sys, const double *x, const double *v, int32
     // observed on x, then the timed cycles.  Returns the ms per cycle, or +inf when the
     // configuration does not fit (box, LDS) or overflowed during the run.
     auto trial = [&](Config c) -> std::pair<double, Config> {
-        c.stage_cap = c.list_cap = c.pair_cap = c.nl_cap = 0;
+        c.tile_need.clear();
+        c.list_cap = c.pair_cap = c.nl_cap = 0;
         if (set_layout(sys, c) != MTS_OK) return {INFINITY, c};
         int obs[4] = {0, 0, 0, 0};
-        if (observe(sys, x, obs) != MTS_OK) return {INFINITY, c};
-        caps_from_observed(c, obs);
+        std::vector<int> tile;
+        if (observe(sys, x, obs, tile) != MTS_OK) return {INFINITY, c};
+        caps_from_observed(c, obs, tile);
         if (set_layout(sys, c) != MTS_OK) return {INFINITY, c};
         ++trials;
         // enough cycles for about 4 ms of work (at least 3), timed twice: the faster run

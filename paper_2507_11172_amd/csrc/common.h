@@ -284,7 +284,9 @@ hipError_t configure_kernel_lds(size_t max_bytes);
 
 // Triplet forces: one workgroup per base cell, forward half stencil in LDS.
 struct TripletArgs {
-    int ncell;              // total cells (grid size)
+    int ncell;              // base cells of this launch (one workgroup each)
+    const int *cell_map;    // [ncell] triplet-grid cell of each workgroup, or nullptr:
+                            // workgroup b takes cell b
     const Pos4 *xs;
     const int *start;
     const SysDesc *sd;
@@ -302,13 +304,18 @@ struct TripletArgs {
     long long list_rows;
     int *stats;             // optional: [2] atomic max of the tile size and of the anchor
                             // list length before capping
+    int *tile_obs;          // [nsys] atomic max of the tile size per system, recorded on
+                            // overflow and whenever stats is set
 };
 hipError_t launch_triplet(hipStream_t st, const TripletArgs &a, bool fp32, bool listing);
 // One launch: the triplet forces of every triplet-grid cell, then (remaining workgroups)
 // the pair list of every pair-grid cell.
 hipError_t launch_triplet_and_list(hipStream_t st, const TripletArgs &a, const ListBuildArgs &b,
                                    bool fp32);
-size_t triplet_lds_bytes(int stage_cap, int list_cap);
+size_t triplet_lds_bytes(int stage_cap, int list_cap, bool fp32);
+// Triplet workgroups that fit on one CU (registers, and lds bytes of dynamic LDS each out
+// of lds_per_cu); -1: unknown.
+int triplet_blocks_per_cu(bool fp32, size_t lds, size_t lds_per_cu);
 hipError_t launch_triplet_gather(hipStream_t st, int64_t n, const double *pf, const int *perm,
                                  double *f, int *flags);
 

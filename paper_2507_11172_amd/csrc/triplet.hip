@@ -73,11 +73,17 @@ struct alignas(16) TileEnt {   // its LDS form: the shift as a 2-bit code per co
     int pad;
 };
 
-struct alignas(16) DispEnt {   // forward neighbour j of the current anchor: canonical
-    double ux, uy, uz, a;      // displacement anchor -> j and its square |u|^2
+// Forward neighbour j of the current anchor: the canonical displacement anchor -> j and
+// its square |u|^2, rounded to the precision T of the ATM arithmetic (16 bytes in FP32,
+// 32 in FP64).  The j-k sweep reads FP32 entries: the FP32 form's own, or an FP32 copy
+// beside the FP64 form's.
+template <typename T>
+struct alignas(16) ListEnt {
+    T ux, uy, uz, a;
 };
 
-static_assert(sizeof(TileEnt) == 32 && sizeof(DispEnt) == 32, "LDS entry sizes");
+static_assert(sizeof(TileEnt) == 32 && sizeof(ListEnt<double>) == 32 &&
+              sizeof(ListEnt<float>) == 16, "LDS entry sizes");
 
 __device__ __forceinline__ PosEnt unpack(const TileEnt &t, double L0, double L1, double L2) {
     PosEnt e;
@@ -96,32 +102,40 @@ struct Tile {                  // staged neighbour cells, CAP entries
     double *fx, *fy, *fz;      // force accumulators
 };
 
+template <typename T>
 struct List {                  // one wave's forward-neighbour list, LC entries
-    DispEnt *u;                // FP64 displacement from the anchor (ATM arithmetic)
-    float4 *f;                 // the same in FP32 (j-k prefilter)
+    ListEnt<T> *u;             // displacement from the anchor (ATM arithmetic)
+    ListEnt<float> *f;         // the same in FP32 (j-k prefilter; == u in the FP32 form)
     double *px, *py, *pz;      // partner force partials of the current anchor
     int *t;                    // tile index
     unsigned short *q;         // hit queue, kQueueCap entries: j | k << 8 (lists <= 256)
 };
 
-size_t triplet_lds_bytes(int cap, int lcap) {
+size_t triplet_lds_bytes(int cap, int lcap, bool fp32) {
+    const size_t ent = fp32 ? sizeof(ListEnt<float>) : sizeof(ListEnt<double>) + sizeof(ListEnt<float>);
     return (size_t)cap * (sizeof(TileEnt) + sizeof(float4) + 3 * sizeof(double)) +
-           (size_t)kTripWaves * lcap * (sizeof(DispEnt) + sizeof(float4) + 3 * sizeof(double) + sizeof(int)) +
+           (size_t)kTripWaves * lcap * (ent + 3 * sizeof(double) + sizeof(int)) +
            (size_t)kTripWaves * kQueueCap * sizeof(unsigned short);
 }
 
 // Carves the dynamic LDS block (cap is a multiple of 32 and lc of 16, so every array
 // starts 16-byte aligned): 32- and 16-byte entries, then doubles, ints and the queue.
-__device__ __forceinline__ void carve(unsigned char *raw, int cap, int lc, int wave, Tile &T,
-                                      List &L) {
-    T.e = (TileEnt *)raw;
-    DispEnt *lu = (DispEnt *)(T.e + cap);
+template <typename T>
+__device__ __forceinline__ void carve(unsigned char *raw, int cap, int lc, int wave, Tile &tl,
+                                      List<T> &L) {
+    tl.e = (TileEnt *)raw;
+    tl.r = (float4 *)(tl.e + cap);
+    ListEnt<T> *lu = (ListEnt<T> *)(tl.r + cap);
     L.u = lu + (size_t)wave * lc;
-    float4 *fr = (float4 *)(lu + (size_t)kTripWaves * lc);
-    T.r = fr;
-    L.f = fr + cap + (size_t)wave * lc;
-    double *dp = (double *)(fr + cap + (size_t)kTripWaves * lc);
-    T.fx = dp; T.fy = dp + cap; T.fz = dp + 2 * cap;
+    ListEnt<float> *lf = (ListEnt<float> *)(lu + (size_t)kTripWaves * lc);
+    if (sizeof(T) == sizeof(float)) {
+        L.f = (ListEnt<float> *)L.u;
+    } else {
+        L.f = lf + (size_t)wave * lc;
+        lf += (size_t)kTripWaves * lc;
+    }
+    double *dp = (double *)lf;
+    tl.fx = dp; tl.fy = dp + cap; tl.fz = dp + 2 * cap;
     double *pw = dp + 3 * (size_t)cap + (size_t)wave * 3 * lc;
     L.px = pw; L.py = pw + lc; L.pz = pw + 2 * lc;
     int *ip = (int *)(dp + 3 * (size_t)cap + (size_t)kTripWaves * 3 * lc);
@@ -187,14 +201,14 @@ struct AtmOut {
 };
 
 template <typename T>
-__device__ __forceinline__ AtmOut<T> atm_triplet(const DispEnt &lj, const DispEnt &lk, T nu) {
+__device__ __forceinline__ AtmOut<T> atm_triplet(const ListEnt<T> &lj, const ListEnt<T> &lk, T nu) {
     // third edge for the force arithmetic: v = w - u (the cutoff test used the canonical
     // displacement; the two differ by rounding only)
-    const T ux = (T)lj.ux, uy = (T)lj.uy, uz = (T)lj.uz;
-    const T wx = (T)lk.ux, wy = (T)lk.uy, wz = (T)lk.uz;
+    const T ux = lj.ux, uy = lj.uy, uz = lj.uz;
+    const T wx = lk.ux, wy = lk.uy, wz = lk.uz;
     const T vx = wx - ux, vy = wy - uy, vz = wz - uz;
     const T cc = (vx * vx + vy * vy) + vz * vz;
-    const T aa = (T)lj.a, bb = (T)lk.a;
+    const T aa = lj.a, bb = lk.a;
     T phi, ga, gb, gc;
     atm_terms<T>(aa, bb, cc, nu, phi, ga, gb, gc);
     AtmOut<T> o;
@@ -254,19 +268,21 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
     const int tid = threadIdx.x;
     const int wave = tid / kWave, lane = tid % kWave;
     const int64_t n = a.n;
-    const SysDesc &d = a.sd[a.sys_of_cell[base]];
+    const int sysq = a.sys_of_cell[base];
+    const SysDesc &d = a.sd[sysq];
     const int loc = base - d.cell0;
     const int cx = loc % d.nc[0], cy = (loc / d.nc[0]) % d.nc[1], cz = loc / (d.nc[0] * d.nc[1]);
     const double L0 = d.L[0], L1 = d.L[1], L2 = d.L[2];
     const double ox = cx * (L0 / d.nc[0]), oy = cy * (L1 / d.nc[1]), oz = cz * (L2 / d.nc[2]);
     Tile tile;
-    List L;
-    carve(smem_raw, CAP, LC, wave, tile, L);
+    List<T> L;
+    carve<T>(smem_raw, CAP, LC, wave, tile, L);
 
     // ---- stage the base cell and its 13 forward cells (shared by the workgroup)
     int nst = stencil_table<kNumHalf, true>(tab, d, cx, cy, cz, a.start);
     int nself = tab.off[1];
     if (a.stats && tid == 0) atomicMax(&a.stats[0], nst);
+    if ((a.stats || nst > CAP) && tid == 0) atomicMax(&a.tile_obs[sysq], nst);
     if (nst > CAP) {
         if (tid == 0) atomicOr(a.flags, kFlagStageOverflow);
         nst = CAP;
@@ -345,13 +361,14 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
             const int pos = m + __popcll(mk & lt_mask);
             __builtin_amdgcn_wave_barrier();  // all reads of this round before the writes
             if (in) {
-                DispEnt de;
-                de.ux = dx;
-                de.uy = dy;
-                de.uz = dz;
-                de.a = r2;
+                ListEnt<T> de;
+                de.ux = (T)dx;
+                de.uy = (T)dy;
+                de.uz = (T)dz;
+                de.a = (T)r2;
                 L.u[pos] = de;
-                L.f[pos] = make_float4((float)dx, (float)dy, (float)dz, 0.0f);
+                if (sizeof(T) != sizeof(float))
+                    L.f[pos] = ListEnt<float>{(float)dx, (float)dy, (float)dz, (float)r2};
                 L.t[pos] = t;
                 L.px[pos] = 0.0;
                 L.py[pos] = 0.0;
@@ -395,7 +412,7 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
             const int e2 = v2 ? Q[(qh + kWave + lane) & kQueueMask] : e1;
             qh += cnt;
             const int j1 = e1 & 0xff, k1 = e1 >> 8, j2 = e2 & 0xff, k2 = e2 >> 8;
-            const DispEnt uj1 = L.u[j1], uk1 = L.u[k1], uj2 = L.u[j2], uk2 = L.u[k2];
+            const ListEnt<T> uj1 = L.u[j1], uk1 = L.u[k1], uj2 = L.u[j2], uk2 = L.u[k2];
             const AtmOut<T> o1 = atm_triplet<T>(uj1, uk1, nu);
             const AtmOut<T> o2 = atm_triplet<T>(uj2, uk2, nu);
             fax += v1 ? (double)o1.fix : 0.0;
@@ -429,7 +446,7 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
                 const int phase = lane / span;
                 // largest distance this lane tests (-1: idle lane)
                 const int Dj = (phase < P && j < m) ? ((even && j >= D) ? D - 1 : D) : -1;
-                const float4 fj = L.f[Dj >= 0 ? j : 0];
+                const ListEnt<float> fj = L.f[Dj >= 0 ? j : 0];
                 int dd = 1 + phase;
                 int k1 = j + dd;
                 k1 -= k1 >= m ? m : 0;
@@ -437,10 +454,10 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
                     int k2 = k1 + P;
                     k2 -= k2 >= m ? m : 0;
                     const bool c1 = dd <= Dj, c2 = dd + P <= Dj;  // c2 implies c1
-                    const float4 fk1 = L.f[c1 ? k1 : 0];
-                    const float4 fk2 = L.f[c2 ? k2 : 0];
-                    const float vx1 = fk1.x - fj.x, vy1 = fk1.y - fj.y, vz1 = fk1.z - fj.z;
-                    const float vx2 = fk2.x - fj.x, vy2 = fk2.y - fj.y, vz2 = fk2.z - fj.z;
+                    const ListEnt<float> fk1 = L.f[c1 ? k1 : 0];
+                    const ListEnt<float> fk2 = L.f[c2 ? k2 : 0];
+                    const float vx1 = fk1.ux - fj.ux, vy1 = fk1.uy - fj.uy, vz1 = fk1.uz - fj.uz;
+                    const float vx2 = fk2.ux - fj.ux, vy2 = fk2.uy - fj.uy, vz2 = fk2.uz - fj.uz;
                     const float q1 = (vx1 * vx1 + vy1 * vy1) + vz1 * vz1;
                     const float q2 = (vx2 * vx2 + vy2 * vy2) + vz2 * vz2;
                     bool hit1 = c1 && q1 <= pf_lo, hit2 = c2 && q2 <= pf_lo;
@@ -568,7 +585,7 @@ __global__ void __launch_bounds__(256) k_triplet_gather(int64_t n, const double 
 template <typename T, bool LIST, bool ENERGY>
 __global__ void __launch_bounds__(kTripThreads) k_triplet(TripletArgs a) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
-    triplet_block<T, LIST, ENERGY>(a, blockIdx.x, smem_raw);
+    triplet_block<T, LIST, ENERGY>(a, a.cell_map ? a.cell_map[blockIdx.x] : (int)blockIdx.x, smem_raw);
 }
 
 // The triplet forces of every triplet-grid cell and, in the same launch, the Verlet list
@@ -578,7 +595,8 @@ template <typename T, bool ENERGY>
 __global__ void __launch_bounds__(kTripThreads) k_triplet_and_list(TripletArgs a, ListBuildArgs b) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     if ((int)blockIdx.x < a.ncell)
-        triplet_block<T, false, ENERGY>(a, blockIdx.x, smem_raw);
+        triplet_block<T, false, ENERGY>(a, a.cell_map ? a.cell_map[blockIdx.x] : (int)blockIdx.x,
+                                        smem_raw);
     else
         list_build_block(b, (int)blockIdx.x - a.ncell, smem_raw);
 }
@@ -586,7 +604,7 @@ __global__ void __launch_bounds__(kTripThreads) k_triplet_and_list(TripletArgs a
 template <typename T, bool ENERGY>
 static hipError_t launch_triplet_and_list_t(hipStream_t st, const TripletArgs &a,
                                             const ListBuildArgs &b) {
-    const size_t lds = std::max(triplet_lds_bytes(a.stage_cap, a.list_cap),
+    const size_t lds = std::max(triplet_lds_bytes(a.stage_cap, a.list_cap, sizeof(T) == 4),
                                 list_build_bytes(b.stage_cap));
     k_triplet_and_list<T, ENERGY><<<a.ncell + b.ncell, kTripThreads, lds, st>>>(a, b);
     return hipGetLastError();
@@ -604,7 +622,7 @@ hipError_t launch_triplet_and_list(hipStream_t st, const TripletArgs &a, const L
 
 template <typename T, bool LIST, bool ENERGY>
 static hipError_t launch_triplet_t(hipStream_t st, const TripletArgs &a) {
-    const size_t lds = triplet_lds_bytes(a.stage_cap, a.list_cap);
+    const size_t lds = triplet_lds_bytes(a.stage_cap, a.list_cap, sizeof(T) == 4);
     k_triplet<T, LIST, ENERGY><<<a.ncell, kTripThreads, lds, st>>>(a);
     return hipGetLastError();
 }
@@ -637,6 +655,23 @@ hipError_t configure_triplet_lds(size_t max_bytes) {
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+int triplet_blocks_per_cu(bool fp32, size_t lds, size_t lds_per_cu) {
+    // the variant with the most registers of each precision
+    const void *f = fp32 ? (const void *)k_triplet_and_list<float, true>
+                         : (const void *)k_triplet_and_list<double, true>;
+    int nb = 0;
+    hipFuncAttributes fa{};
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kTripThreads, 0) != hipSuccess ||
+        hipFuncGetAttributes(&fa, f) != hipSuccess) {
+        (void)hipGetLastError();  // leave no sticky error for the next launch check
+        return -1;
+    }
+    // LDS goes out in granules: static + dynamic bytes rounded up to 512, plus 512 of
+    // margin for a coarser granule
+    const size_t per = (fa.sharedSizeBytes + lds + 511) / 512 * 512 + 512;
+    return std::min(nb, (int)(lds_per_cu / per));
 }
 
 hipError_t launch_triplet_gather(hipStream_t st, int64_t n, const double *pf, const int *perm,

@@ -388,6 +388,80 @@ def test_batched_replicas_forces_vs_oracle():
         off += n
 
 
+def _class_batch():
+    """A liquid-density box with five cells per edge, one too small for three cells per
+    edge (two large cells: its triplet tile holds ~1.75 N entries) and one in between."""
+    specs = [(2048, 0.8, 71), (365, 0.9, 72), (1200, 0.7, 73)]
+    xs, vs, boxes = [], [], []
+    for n, rho, seed in specs:
+        rng = W.rng_for(seed)
+        x, box = W.fcc_subset(n, rho, 0.05, rng)
+        xs.append(x)
+        vs.append(W.maxwell_boltzmann(n, 0.8, rng))
+        boxes.append(box)
+    ns = np.array([n for n, _, _ in specs])
+    return W.Workload("classes", np.concatenate(xs), np.concatenate(vs), np.stack(boxes), ns,
+                      np.full(len(specs), 0.8))
+
+
+def test_tile_classes_match_oracle_and_single_systems():
+    """Systems whose tiles allow different workgroups per CU run as separate launches (tile
+    classes); forces, triplet sets, trajectories and energies stay those of each system on
+    its own handle (bitwise) and of the oracle."""
+    torch = _torch()
+    from paper_2507_11172_amd import mts
+    w = _class_batch()
+    k, n_iter = 5, 20
+    kw = dict(k=k, skin=0.3)
+    with _system(w, **kw) as s:
+        assert s.tuning()["tile_classes"] >= 2
+        x, v = _dev(w.x), _dev(w.v)
+        f2, f3 = torch.empty_like(x), torch.empty_like(x)
+        s.compute_pair_forces(x, f2)
+        s.compute_triplet_forces(x, f3)
+        e = torch.zeros((n_iter // k + 1, w.n_systems, mts.MTS_NE), dtype=torch.float64,
+                        device="cuda")
+        s.respa_step(x, v, n_iter, e)
+        s.sync()
+        fb2, fb3, xb, vb, eb = f2.cpu(), f3.cpu(), x.cpu(), v.cpu(), e.cpu()
+        got, total = s.list_triplets(_dev(w.x), 2_000_000)
+    g = got.cpu().numpy().astype(np.int64)
+    refs = []
+    off = 0
+    for r in range(w.n_systems):
+        n = int(w.n_particles[r])
+        sl = slice(off, off + n)
+        ref = oracle.triplet_list(w.x[sl], w.box[r], rc=w.rc_triplet).astype(np.int64) + off
+        refs.append(ref)
+        assert rel_err(fb3[sl].numpy(), oracle.triplet_forces(w.x[sl], w.box[r]).f) <= 1e-12, r
+        wr = W.Workload("rep%d" % r, w.x[sl], w.v[sl], w.box[r:r + 1], np.array([n]),
+                        w.temperature[r:r + 1])
+        with _system(wr, **kw) as s1:
+            x, v = _dev(wr.x), _dev(wr.v)
+            f2, f3 = torch.empty_like(x), torch.empty_like(x)
+            s1.compute_pair_forces(x, f2)
+            s1.compute_triplet_forces(x, f3)
+            e = torch.zeros((n_iter // k + 1, 1, mts.MTS_NE), dtype=torch.float64, device="cuda")
+            s1.respa_step(x, v, n_iter, e)
+            s1.sync()
+        assert torch.equal(fb2[sl], f2.cpu()) and torch.equal(fb3[sl], f3.cpu()), r
+        assert torch.equal(xb[sl], x.cpu()) and torch.equal(vb[sl], v.cpu()), r
+        assert torch.equal(eb[:, r, :], e.cpu()[:, 0, :]), r
+        off += n
+    ref = np.concatenate(refs)
+    ref = ref[np.lexsort((ref[:, 2], ref[:, 1], ref[:, 0]))]
+    assert total == ref.shape[0]
+    assert np.array_equal(g[np.lexsort((g[:, 2], g[:, 1], g[:, 0]))], ref)
+    # the FP32 form: its own class split (smaller list entries), same bar as elsewhere
+    with _system(w, precision="fp32") as s:
+        assert s.tuning()["tile_classes"] >= 2
+        x = _dev(w.x)
+        f3 = torch.empty_like(x)
+        s.compute_triplet_forces(x, f3)
+        s.sync()
+    assert rel_err(f3.cpu().numpy(), fb3.numpy()) <= 1e-5
+
+
 def _forces_and_energies(w, precision):
     torch = _torch()
     with _system(w, precision=precision) as s:
