@@ -16,13 +16,15 @@
 //    LDS-staged neighbour-cell tile shared by the workgroup.  Waves take anchors
 //    round-robin.
 //  * Per anchor (one wave):
-//      A. filter the tile to the anchor's forward neighbours within rc3 -- ballot +
-//         prefix-count compaction into the wave's list (a copy of the tile entry, the
-//         displacement u from the anchor and |u|^2, the tile index);
+//      A. the canonical FP64 displacement of every tile entry after the anchor and its
+//         exact cutoff test, two entries per lane per round -- ballot + prefix-count
+//         compaction into the wave's list (the displacement u from the anchor and
+//         |u|^2, the tile index), in tile order;
 //      B. each lane owns one list entry j (kept in registers) and walks its partners
 //         k = j + 1 .. j + m/2 around the list, two per round, so all m(m-1)/2 pairs
-//         are visited once with balanced lanes; the third edge j-k is tested with the
-//         canonical FP64 displacement and hits are compacted into a queue;
+//         are visited once with balanced lanes; the third edge j-k is prefiltered in
+//         FP32 and settled, when within rounding of the cutoff, with the canonical FP64
+//         displacement; hits are compacted into a queue;
 //      C. evaluate ATM two queued hits per lane (two independent chains in flight)
 //         once 128 are pending, and on the rest at the end of the anchor.
 //  * Accumulation.  The anchor's force stays in registers and is summed across the wave
@@ -76,7 +78,8 @@ struct alignas(16) TileEnt {   // its LDS form: the shift as a 2-bit code per co
 // Forward neighbour j of the current anchor: the canonical displacement anchor -> j and
 // its square |u|^2, rounded to the precision T of the ATM arithmetic (16 bytes in FP32,
 // 32 in FP64).  The j-k sweep reads FP32 entries: the FP32 form's own, or an FP32 copy
-// beside the FP64 form's.
+// beside the FP64 form's (at the FP64 rate of CDNA4 the FP64 test costs the same ALU
+// time, but twice the LDS bytes).
 template <typename T>
 struct alignas(16) ListEnt {
     T ux, uy, uz, a;
@@ -98,7 +101,8 @@ __device__ __forceinline__ PosEnt unpack(const TileEnt &t, double L0, double L1,
 
 struct Tile {                  // staged neighbour cells, CAP entries
     TileEnt *e;                // FP64 (canonical tests, displacements)
-    float4 *r;                 // FP32 position relative to the base cell (prefilter)
+    float4 *r;                 // FP64 form only: FP32 position relative to the base cell
+                               // (prefilter of the anchor lists)
     double *fx, *fy, *fz;      // force accumulators
 };
 
@@ -113,7 +117,7 @@ struct List {                  // one wave's forward-neighbour list, LC entries
 
 size_t triplet_lds_bytes(int cap, int lcap, bool fp32) {
     const size_t ent = fp32 ? sizeof(ListEnt<float>) : sizeof(ListEnt<double>) + sizeof(ListEnt<float>);
-    return (size_t)cap * (sizeof(TileEnt) + sizeof(float4) + 3 * sizeof(double)) +
+    return (size_t)cap * (sizeof(TileEnt) + (fp32 ? 0 : sizeof(float4)) + 3 * sizeof(double)) +
            (size_t)kTripWaves * lcap * (ent + 3 * sizeof(double) + sizeof(int)) +
            (size_t)kTripWaves * kQueueCap * sizeof(unsigned short);
 }
@@ -124,8 +128,8 @@ template <typename T>
 __device__ __forceinline__ void carve(unsigned char *raw, int cap, int lc, int wave, Tile &tl,
                                       List<T> &L) {
     tl.e = (TileEnt *)raw;
-    tl.r = (float4 *)(tl.e + cap);
-    ListEnt<T> *lu = (ListEnt<T> *)(tl.r + cap);
+    tl.r = sizeof(T) == sizeof(float) ? nullptr : (float4 *)(tl.e + cap);
+    ListEnt<T> *lu = (ListEnt<T> *)(sizeof(T) == sizeof(float) ? (void *)(tl.e + cap) : (void *)(tl.r + cap));
     L.u = lu + (size_t)wave * lc;
     ListEnt<float> *lf = (ListEnt<float> *)(lu + (size_t)kTripWaves * lc);
     if (sizeof(T) == sizeof(float)) {
@@ -143,11 +147,11 @@ __device__ __forceinline__ void carve(unsigned char *raw, int cap, int lc, int w
     L.q = (unsigned short *)(ip + (size_t)kTripWaves * lc) + (size_t)wave * kQueueCap;
 }
 
-// FP32 prefilter of a cutoff test.  Positions relative to the base cell (|x| < 3 h <=
-// 6 rc) and displacements from the anchor (|u| <= rc) carry FP32 errors below 1e-6
-// relative to rc^2 in a squared distance, so a relative band of 1e-5 around rc^2
-// separates certain hits (below), certain misses (above) and the rare ambiguous cases,
-// which are settled by the canonical FP64 test: the triplet set is exactly the FP64 one.
+// FP32 prefilter of the j-k cutoff test, on v = w - u from the FP32 list entries.  The
+// displacements (|u| <= rc) carry FP32 errors below 1e-6 relative to rc^2 in a squared
+// distance, so a relative band of 1e-5 around rc^2 separates certain hits (below),
+// certain misses (above) and the rare ambiguous cases, which are settled by the canonical
+// FP64 test: the triplet set is exactly the FP64 one.
 constexpr float kPrefilterBand = 1e-5f;
 
 // 1/sqrt(x): hardware estimate refined by two Newton-Raphson steps y <- y (3 - x y^2)/2
@@ -300,9 +304,11 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
         te.code = code & 0xff;
         te.pad = 0;
         tile.e[t] = te;
-        const PosEnt e = unpack(te, L0, L1, L2);
-        tile.r[t] = make_float4((float)((e.x + e.sx) - ox), (float)((e.y + e.sy) - oy),
-                               (float)((e.z + e.sz) - oz), 0.0f);
+        if constexpr (sizeof(T) != sizeof(float)) {
+            const PosEnt e = unpack(te, L0, L1, L2);
+            tile.r[t] = make_float4((float)((e.x + e.sx) - ox), (float)((e.y + e.sy) - oy),
+                                   (float)((e.z + e.sz) - oz), 0.0f);
+        }
         tile.fx[t] = 0.0;
         tile.fy[t] = 0.0;
         tile.fz[t] = 0.0;
@@ -312,69 +318,103 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
 
     const T nu = (T)a.nu;
     const double rc2 = a.rc2;
-    const float pf_lo = (float)rc2 * (1.0f - kPrefilterBand);
-    const float pf_hi = (float)rc2 * (1.0f + kPrefilterBand);
-    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+    const float jk_lo = (float)rc2 * (1.0f - kPrefilterBand);
+    const float jk_hi = (float)rc2 * (1.0f + kPrefilterBand);
     unsigned short *Q = L.q;
     double U = 0.0, W = 0.0;
     int ntrip = 0;  // wave-uniform
 
     for (int ia = wave; ia < nself; ia += kTripWaves) {
         const PosEnt an = unpack(tile.e[ia], L0, L1, L2);  // anchor: base cell, zero shift
-        const float4 ar = tile.r[ia];
-        // ---- A1: FP32 prefilter of the tile entries after the anchor (tile order);
-        // certain and ambiguous candidates are compacted into L.t, in tile order
-        int mc = 0;
-        for (int t0 = ia + 1; t0 < nst; t0 += 2 * kWave) {
-            const int t1 = t0 + lane, t2 = t0 + kWave + lane;
-            const float4 r1 = tile.r[t1 < nst ? t1 : ia];
-            const float4 r2 = tile.r[t2 < nst ? t2 : ia];
-            const float x1 = r1.x - ar.x, y1 = r1.y - ar.y, z1 = r1.z - ar.z;
-            const float x2 = r2.x - ar.x, y2 = r2.y - ar.y, z2 = r2.z - ar.z;
-            const bool in1 = t1 < nst && (x1 * x1 + y1 * y1) + z1 * z1 <= pf_hi;
-            const bool in2 = t2 < nst && (x2 * x2 + y2 * y2) + z2 * z2 <= pf_hi;
-            const uint64_t m1 = __ballot(in1), m2 = __ballot(in2);
-            const int n1 = __popcll(m1);
-            const int p1 = mc + __popcll(m1 & lt_mask), p2 = mc + n1 + __popcll(m2 & lt_mask);
-            if (in1 && p1 < LC) L.t[p1] = t1;
-            if (in2 && p2 < LC) L.t[p2] = t2;
-            mc += n1 + __popcll(m2);
-        }
-        if (a.stats && lane == 0) atomicMax(&a.stats[1], mc);
-        if (mc > LC) {
-            if (lane == 0) atomicOr(a.flags, kFlagListOverflow);
-            mc = LC;
-        }
-        __builtin_amdgcn_wave_barrier();
-        // ---- A2: canonical FP64 displacement and test of every candidate; the final
-        // list keeps the candidates' (tile) order
         int m = 0;
-        for (int c0 = 0; c0 < mc; c0 += kWave) {
-            const int c = c0 + lane;
-            const int t = c < mc ? L.t[c] : ia;
-            const PosEnt e = unpack(tile.e[t], L0, L1, L2);
-            const double dx = disp1(an.x, e.x, e.sx), dy = disp1(an.y, e.y, e.sy),
-                         dz = disp1(an.z, e.z, e.sz);
-            const double r2 = norm2(dx, dy, dz);
-            const bool in = c < mc && r2 <= rc2;
-            const uint64_t mk = __ballot(in);
-            const int pos = m + __popcll(mk & lt_mask);
-            __builtin_amdgcn_wave_barrier();  // all reads of this round before the writes
-            if (in) {
-                ListEnt<T> de;
-                de.ux = (T)dx;
-                de.uy = (T)dy;
-                de.uz = (T)dz;
-                de.a = (T)r2;
-                L.u[pos] = de;
-                if (sizeof(T) != sizeof(float))
-                    L.f[pos] = ListEnt<float>{(float)dx, (float)dy, (float)dz, (float)r2};
-                L.t[pos] = t;
-                L.px[pos] = 0.0;
-                L.py[pos] = 0.0;
-                L.pz[pos] = 0.0;
+        if constexpr (sizeof(T) != sizeof(float)) {
+            // ---- A1: FP32 prefilter of the tile entries after the anchor (tile order);
+            // certain and ambiguous candidates are compacted into L.t, in tile order
+            const float4 ar = tile.r[ia];
+            const float pf_hi = (float)rc2 * (1.0f + kPrefilterBand);
+            int mc = 0;
+            for (int t0 = ia + 1; t0 < nst; t0 += 2 * kWave) {
+                const int t1 = t0 + lane, t2 = t0 + kWave + lane;
+                const float4 r1 = tile.r[t1 < nst ? t1 : ia];
+                const float4 r2 = tile.r[t2 < nst ? t2 : ia];
+                const float x1 = r1.x - ar.x, y1 = r1.y - ar.y, z1 = r1.z - ar.z;
+                const float x2 = r2.x - ar.x, y2 = r2.y - ar.y, z2 = r2.z - ar.z;
+                const bool in1 = t1 < nst && (x1 * x1 + y1 * y1) + z1 * z1 <= pf_hi;
+                const bool in2 = t2 < nst && (x2 * x2 + y2 * y2) + z2 * z2 <= pf_hi;
+                const uint64_t m1 = __ballot(in1), m2 = __ballot(in2);
+                const int n1 = __popcll(m1);
+                const int p1 = mc + below(m1), p2 = mc + n1 + below(m2);
+                if (in1 && p1 < LC) L.t[p1] = t1;
+                if (in2 && p2 < LC) L.t[p2] = t2;
+                mc += n1 + __popcll(m2);
             }
-            m += __popcll(mk);
+            if (a.stats && lane == 0) atomicMax(&a.stats[1], mc);
+            if (mc > LC) {
+                if (lane == 0) atomicOr(a.flags, kFlagListOverflow);
+                mc = LC;
+            }
+            __builtin_amdgcn_wave_barrier();
+            // ---- A2: canonical FP64 displacement and exact test of every candidate; the
+            // list keeps the candidates' (tile) order
+            for (int c0 = 0; c0 < mc; c0 += kWave) {
+                const int c = c0 + lane;
+                const int t = c < mc ? L.t[c] : ia;
+                const PosEnt e = unpack(tile.e[t], L0, L1, L2);
+                const double dx = disp1(an.x, e.x, e.sx), dy = disp1(an.y, e.y, e.sy),
+                             dz = disp1(an.z, e.z, e.sz);
+                const double r2 = norm2(dx, dy, dz);
+                const bool in = c < mc && r2 <= rc2;
+                const uint64_t mk = __ballot(in);
+                const int pos = m + below(mk);
+                __builtin_amdgcn_wave_barrier();  // all reads of this round before the writes
+                if (in) {
+                    L.u[pos] = ListEnt<T>{(T)dx, (T)dy, (T)dz, (T)r2};
+                    L.f[pos] = ListEnt<float>{(float)dx, (float)dy, (float)dz, (float)r2};
+                    L.t[pos] = t;
+                    L.px[pos] = 0.0;
+                    L.py[pos] = 0.0;
+                    L.pz[pos] = 0.0;
+                }
+                m += __popcll(mk);
+            }
+        } else {
+            // ---- A: canonical FP64 displacement and exact test of the tile entries after the
+            // anchor, two per lane per round; ballot + prefix-count compaction keeps tile order
+            for (int t0 = ia + 1; t0 < nst; t0 += 2 * kWave) {
+                const int t1 = t0 + lane, t2 = t0 + kWave + lane;
+                const PosEnt e1 = unpack(tile.e[t1 < nst ? t1 : ia], L0, L1, L2);
+                const PosEnt e2 = unpack(tile.e[t2 < nst ? t2 : ia], L0, L1, L2);
+                const double x1 = disp1(an.x, e1.x, e1.sx), y1 = disp1(an.y, e1.y, e1.sy),
+                             z1 = disp1(an.z, e1.z, e1.sz);
+                const double x2 = disp1(an.x, e2.x, e2.sx), y2 = disp1(an.y, e2.y, e2.sy),
+                             z2 = disp1(an.z, e2.z, e2.sz);
+                const double q1 = norm2(x1, y1, z1), q2 = norm2(x2, y2, z2);
+                const bool in1 = t1 < nst && q1 <= rc2;
+                const bool in2 = t2 < nst && q2 <= rc2;
+                const uint64_t m1 = __ballot(in1), m2 = __ballot(in2);
+                const int n1 = __popcll(m1);
+                const int p1 = m + below(m1), p2 = m + n1 + below(m2);
+                if (in1 && p1 < LC) {
+                    L.u[p1] = ListEnt<T>{(T)x1, (T)y1, (T)z1, (T)q1};
+                    L.t[p1] = t1;
+                    L.px[p1] = 0.0;
+                    L.py[p1] = 0.0;
+                    L.pz[p1] = 0.0;
+                }
+                if (in2 && p2 < LC) {
+                    L.u[p2] = ListEnt<T>{(T)x2, (T)y2, (T)z2, (T)q2};
+                    L.t[p2] = t2;
+                    L.px[p2] = 0.0;
+                    L.py[p2] = 0.0;
+                    L.pz[p2] = 0.0;
+                }
+                m += n1 + __popcll(m2);
+            }
+            if (a.stats && lane == 0) atomicMax(&a.stats[1], m);
+            if (m > LC) {
+                if (lane == 0) atomicOr(a.flags, kFlagListOverflow);
+                m = LC;
+            }
         }
         __builtin_amdgcn_wave_barrier();
 
@@ -460,9 +500,9 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
                     const float vx2 = fk2.ux - fj.ux, vy2 = fk2.uy - fj.uy, vz2 = fk2.uz - fj.uz;
                     const float q1 = (vx1 * vx1 + vy1 * vy1) + vz1 * vz1;
                     const float q2 = (vx2 * vx2 + vy2 * vy2) + vz2 * vz2;
-                    bool hit1 = c1 && q1 <= pf_lo, hit2 = c2 && q2 <= pf_lo;
-                    const bool amb1 = c1 && q1 > pf_lo && q1 <= pf_hi;
-                    const bool amb2 = c2 && q2 > pf_lo && q2 <= pf_hi;
+                    bool hit1 = c1 && q1 <= jk_lo, hit2 = c2 && q2 <= jk_lo;
+                    const bool amb1 = c1 && q1 > jk_lo && q1 <= jk_hi;
+                    const bool amb2 = c2 && q2 > jk_lo && q2 <= jk_hi;
                     if (__ballot(amb1 || amb2)) {  // rare: settle with the FP64 test
                         if (amb1 || amb2) {
                             const PosEnt ej = unpack(tile.e[L.t[j]], L0, L1, L2);
