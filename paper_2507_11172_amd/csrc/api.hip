@@ -97,6 +97,7 @@ struct mts_system {
     // device buffers (library-owned)
     int *sys_of = nullptr;        // [n]
     double *red_part = nullptr;   // [nsys][kRedChunks][6] reduction partials
+    int *red_done = nullptr;      // [nsys + 1] reduction completion counters (zero at rest)
     double *f2a = nullptr, *f2b = nullptr, *f3 = nullptr;  // [n][3] force caches
     double *pf = nullptr;         // [14][3][n] triplet partial slots
     double *pe = nullptr;         // [n][2] per-particle pair energy/virial (pair-grid order)
@@ -400,6 +401,8 @@ mts_status alloc_all(mts_system *s) {
     const int64_t n = s->n;
     HIP_TRY(s, dalloc(&s->sys_of, n));
     HIP_TRY(s, dalloc(&s->red_part, (size_t)s->nsys * kRedChunks * 6));
+    HIP_TRY(s, dalloc(&s->red_done, (size_t)s->nsys + 1));
+    HIP_TRY(s, hipMemset(s->red_done, 0, sizeof(int) * (s->nsys + 1)));
     HIP_TRY(s, dalloc(&s->f2a, 3 * n));
     HIP_TRY(s, dalloc(&s->f2b, 3 * n));
     HIP_TRY(s, dalloc(&s->f3, 3 * n));
@@ -460,7 +463,7 @@ void free_all(mts_system *s) {
     for (int c = 0; c < 2; ++c)
         for (hipEvent_t e : s->ev_pool[c]) (void)hipEventDestroy(e);
     free_layout(s->lo);
-    void *ptrs[] = {s->sys_of, s->red_part, s->f2a, s->f2b, s->f3, s->pf, s->pe, s->cnt_sys,
+    void *ptrs[] = {s->sys_of, s->red_part, s->red_done, s->f2a, s->f2b, s->f3, s->pf, s->pe, s->cnt_sys,
                     s->nn, s->stats, s->tile_obs, s->x_ref, s->flags, s->row, s->e_buf, s->list_n,
                     s->xi, s->vi};
     for (void *p : ptrs)
@@ -707,6 +710,7 @@ mts_status enqueue_reduce(mts_system *s, const double *v, bool pair, bool trip, 
     a.flags = s->flags;
     a.row = row;
     a.part = s->red_part;
+    a.done = s->red_done;
     HIP_TRY(s, launch_reduce(s->st, a));
     return MTS_OK;
 }
@@ -781,7 +785,7 @@ mts_status enqueue_entry_forces(mts_system *s, double *f2, bool energy) {
 // One outer cycle of Algorithm 2 on the internal copies xi, vi.  On entry F2 of the
 // cycle's first position x^0 is in f2[0] and F3(x^0) in s->f3; on exit F2(x^k) is in
 // f2[k % 2] and F3(x^k) in s->f3, with the closing F3 half kick applied.
-// With a pair list (launches per cycle: k + 5 for k > 1, plus 2 with energies):
+// With a pair list (launches per cycle: k + 5 for k > 1, plus 1 with energies):
 //   step 0:          k_int: opening F3 kick, drift to x^1 (also into sorted buffer B)
 //   x^i, 0 < i < k:  k_pair_list at x^i: F2(x^i), then kick2 of step i-1 and the drift
 //                    of step i, positions ping-ponging between sorted buffers A and B

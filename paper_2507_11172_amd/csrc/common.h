@@ -354,10 +354,10 @@ struct ReduceArgs {
     int stride;             // 5: {K,U2,U3,W2,W3}; 2: {U,W} from whichever source is non-null
     long long *count_out;   // [nsys] triplet counts or null
     int *flags;
-    int *row;               // optional device row counter [2]: row[0] is the row to write
-                            // (out += row * nsys * stride) and is advanced by one; row[1]
-                            // holds the row in use between the two passes
+    int *row;               // optional device row counter: row[0] is the row to write
+                            // (out += row * nsys * stride) and is advanced by one
     double *part;           // scratch [nsys][kRedChunks][6]
+    int *done;              // [nsys + 1] completion counters, zero between launches
 };
 constexpr int kRedChunks = 64;
 hipError_t launch_reduce(hipStream_t st, const ReduceArgs &a);

@@ -56,23 +56,22 @@ __global__ void __launch_bounds__(256) k_int(IntArgs a) {
 
 constexpr int kRed = 256;
 
-__device__ __forceinline__ double block_sum(double v, double *red) {
-    const int t = threadIdx.x;
-    red[t] = v;
-    __syncthreads();
-    for (int s = kRed / 2; s > 0; s >>= 1) {
-        if (t < s) red[t] += red[t + s];
-        __syncthreads();
-    }
-    const double r = red[0];
-    __syncthreads();
-    return r;
+// Wave-wide sum by butterfly shuffles (fixed order: bitwise reproducible), in every lane.
+__device__ __forceinline__ double wave_sum_xor(double v) {
+#pragma unroll
+    for (int m = 1; m < kWave; m <<= 1) v += __shfl_xor(v, m);
+    return v;
 }
 
-// Pass 1: block (system s, chunk c) sums a fixed contiguous chunk of the system's
-// particles (kinetic, pair energy/virial) and cells (triplet energy/virial/count).
-__global__ void __launch_bounds__(kRed) k_reduce_part(ReduceArgs a) {
-    __shared__ double red[kRed];
+// One launch per reduction.  Block (system s, chunk c) sums a fixed contiguous chunk of the
+// system's particles (kinetic, pair energy/virial) and cells (triplet energy/virial/count)
+// and stores the six partials; the block that finishes a system's chunks last (a
+// device-scope counter per system) then sums that system's partials in a fixed order (one
+// lane per chunk, butterfly) and writes its record.  The last system to finish advances the record row and every counter
+// is left at zero for the next launch, so the kernel can be replayed from a graph.
+__global__ void __launch_bounds__(kRed) k_reduce(ReduceArgs a) {
+    __shared__ double red[kRed / kWave][6];
+    __shared__ int s_last;
     const int s = blockIdx.x / kRedChunks, c = blockIdx.x % kRedChunks;
     const int t = threadIdx.x;
     const SysDesc &d = a.sd[s];
@@ -80,52 +79,55 @@ __global__ void __launch_bounds__(kRed) k_reduce_part(ReduceArgs a) {
     const int64_t pb = d.p0 + c * lp, pe = d.p0 + min(d.n, (c + 1) * lp);
     const int lc = (d.ncell + kRedChunks - 1) / kRedChunks;
     const int cb = d.cell0 + c * lc, ce = d.cell0 + min(d.ncell, (c + 1) * lc);
-    if (a.row && blockIdx.x == 0 && t == 0) {  // the row this record goes to; advance
-        const int r = a.row[0];
-        a.row[1] = r;
-        a.row[0] = r + 1;
-    }
-    double kin = 0.0, u2 = 0.0, w2 = 0.0, u3 = 0.0, w3 = 0.0, cnt = 0.0;
+    double v6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // K, U2, U3, W2, W3, count
     if (a.v)
         for (int64_t i = pb + t; i < pe; i += kRed) {
             const double vx = a.v[3 * i], vy = a.v[3 * i + 1], vz = a.v[3 * i + 2];
-            kin += (vx * vx + vy * vy) + vz * vz;
+            v6[0] += (vx * vx + vy * vy) + vz * vz;
         }
     if (a.pe)
         for (int64_t p = pb + t; p < pe; p += kRed) {
-            u2 += a.pe[2 * p];
-            w2 += a.pe[2 * p + 1];
+            v6[1] += a.pe[2 * p];
+            v6[3] += a.pe[2 * p + 1];
         }
     if (a.ce)
         for (int q = cb + t; q < ce; q += kRed) {
-            u3 += a.ce[2 * q];
-            w3 += a.ce[2 * q + 1];
+            v6[2] += a.ce[2 * q];
+            v6[4] += a.ce[2 * q + 1];
         }
     if (a.cc)
-        for (int q = cb + t; q < ce; q += kRed) cnt += (double)a.cc[q];
-    kin = block_sum(kin, red);
-    u2 = block_sum(u2, red);
-    w2 = block_sum(w2, red);
-    u3 = block_sum(u3, red);
-    w3 = block_sum(w3, red);
-    cnt = block_sum(cnt, red);
+        for (int q = cb + t; q < ce; q += kRed) v6[5] += (double)a.cc[q];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) v6[k] = wave_sum_xor(v6[k]);
+    if (t % kWave == 0)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) red[t / kWave][k] = v6[k];
+    __syncthreads();
     if (t == 0) {
         double *o = a.part + 6 * (size_t)blockIdx.x;
-        o[0] = kin; o[1] = u2; o[2] = u3; o[3] = w2; o[4] = w3; o[5] = cnt;
+        for (int k = 0; k < 6; ++k) {
+            double r = 0.0;
+            for (int w = 0; w < kRed / kWave; ++w) r += red[w][k];
+            o[k] = r;
+        }
+        __threadfence();  // the partials before the count (release)
+        s_last = atomicAdd(&a.done[s], 1) == kRedChunks - 1;
     }
-}
-
-// Pass 2: one thread per system sums its kRedChunks partials in chunk order.
-__global__ void k_reduce_final(ReduceArgs a) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= a.nsys) return;
-    double r[6] = {0, 0, 0, 0, 0, 0};
-    for (int c = 0; c < kRedChunks; ++c)
-        for (int q = 0; q < 6; ++q) r[q] += a.part[6 * ((size_t)s * kRedChunks + c) + q];
+    __syncthreads();
+    if (!s_last || t >= kWave) return;
+    __threadfence();  // acquire: every chunk's partials of system s are visible
+    // lane q holds chunk q's partials; butterfly sums in a fixed order
+    static_assert(kRedChunks == kWave, "one lane per chunk");
+    const double *part = a.part + 6 * ((size_t)s * kRedChunks + t);
+    double r[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) r[k] = wave_sum_xor(part[k]);
+    if (t != 0) return;
+    a.done[s] = 0;
     const double kin = r[0] * a.half_mass;
     double *out = a.out;
     if (out) {
-        if (a.row) out += (int64_t)a.row[1] * a.nsys * a.stride;
+        if (a.row) out += (int64_t)a.row[0] * a.nsys * a.stride;
         out += (int64_t)s * a.stride;
         if (a.stride == kNE) {
             out[0] = kin; out[1] = r[1]; out[2] = r[2]; out[3] = r[3]; out[4] = r[4];
@@ -138,6 +140,12 @@ __global__ void k_reduce_final(ReduceArgs a) {
     bool ok = true;
     for (int q = 0; q < 5; ++q) ok = ok && isfinite(r[q]);
     if (!ok) atomicOr(a.flags, kFlagNonFinite);
+    // the last system advances the row: every system has read it by then
+    __threadfence();
+    if (atomicAdd(&a.done[a.nsys], 1) == a.nsys - 1) {
+        a.done[a.nsys] = 0;
+        if (a.row) a.row[0] += 1;
+    }
 }
 
 __global__ void k_set_int(int *p, int v) { *p = v; }
@@ -151,10 +159,7 @@ hipError_t launch_int(hipStream_t st, const IntArgs &a) {
 
 hipError_t launch_reduce(hipStream_t st, const ReduceArgs &a) {
     if (a.nsys <= 0) return hipSuccess;
-    k_reduce_part<<<a.nsys * kRedChunks, kRed, 0, st>>>(a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    k_reduce_final<<<(a.nsys + 63) / 64, 64, 0, st>>>(a);
+    k_reduce<<<a.nsys * kRedChunks, kRed, 0, st>>>(a);
     return hipGetLastError();
 }
 
