@@ -60,6 +60,15 @@ typedef enum {
                      integration and energy reductions in FP64 */
 } mts_precision;
 
+/* How interactions are found. */
+typedef enum {
+    MTS_CUTOFF = 0, /* periodic boxes; pairs within rc_pair, triplets with all three edges
+                       within rc_triplet, through linked cells (Sec. 4.1, cutoff) */
+    MTS_DIRECT = 1  /* DirectSum (Sec. 3.1, 4.1): every pair and every triplet of a system,
+                       no cutoff and open boundaries (no images, positions never wrapped);
+                       the cutoffs, skin and box are not used */
+} mts_method;
+
 /* Interaction and integration parameters (Sec. 2.1; appendix table). */
 typedef struct {
     double epsilon;          /* LJ well depth epsilon_LJ */
@@ -75,7 +84,7 @@ typedef struct {
     int32_t k;               /* r-RESPA step-size factor s >= 1 (Sec. 4.1) */
     int32_t precision;       /* mts_precision */
     int32_t lj_energy_shift; /* 1: report U2 shifted by -U(rc_pair) per pair (forces unchanged) */
-    int32_t reserved;        /* must be 0 */
+    int32_t method;          /* mts_method */
 } mts_params;
 
 /* Energy record per system: kinetic K, LJ energy U2, ATM energy U3, pair virial W2,
@@ -83,10 +92,11 @@ typedef struct {
  * (2K + W2 + W3) / (3V)). */
 enum { MTS_NE = 5 };
 
-/* Creates a handle for n_systems independent periodic systems.
+/* Creates a handle for n_systems independent systems (periodic boxes, or open ones with
+ * MTS_DIRECT).
  *   params       host, read during the call.
  *   n_particles  host [n_systems], each >= 0.
- *   box          host [n_systems][3], edge lengths.
+ *   box          host [n_systems][3], edge lengths (> 0; unused with MTS_DIRECT).
  *   stream       hipStream_t to enqueue on (NULL = default stream).
  *   out          host, receives the handle; release it with mts_destroy_system.
  * Fails with MTS_ERR_BOX_TOO_SMALL, MTS_ERR_INVALID_ARG or MTS_ERR_OOM; on failure
@@ -101,18 +111,20 @@ void mts_destroy_system(mts_system *sys);
  * computes each cell index and sorts particles by cell with a stable counting sort
  * (equal cells keep ascending particle order).  x is dev [N][3]; it is read, not
  * modified.  The force calls below bin by themselves; this call exists for the cell
- * inspection exports. */
+ * inspection exports.  MTS_DIRECT handles keep no cells: MTS_ERR_UNSUPPORTED. */
 mts_status mts_build_cells(mts_system *sys, const double *x);
 
-/* F2(x): Lennard-Jones forces (Sec. 2.1; Algorithm 2, "calculate F2b").
+/* F2(x): Lennard-Jones forces (Sec. 2.1; Algorithm 2, "calculate F2b"); with MTS_DIRECT
+ * over every pair of a system, unshifted.
  *   x   dev [N][3] positions (need not be wrapped).
  *   f2  dev [N][3] output, overwritten.
  *   ew  dev [n_systems][2] output {U2, W2}, or NULL. */
 mts_status mts_compute_pair_forces(mts_system *sys, const double *x, double *f2, double *ew);
 
 /* F3(x): Axilrod-Teller-Muto forces over every triplet with all three edges
- * <= rc_triplet (Sec. 2.1, 4.1; Algorithm 2, "calculate F3b").  Newton's third law is
- * applied across each triplet: every triplet is evaluated once.
+ * <= rc_triplet (Sec. 2.1, 4.1; Algorithm 2, "calculate F3b"), or with MTS_DIRECT over
+ * every triplet i < j < k of a system.  Newton's third law is applied across each
+ * triplet: every triplet is evaluated once.
  *   x   dev [N][3] positions.
  *   f3  dev [N][3] output, overwritten.
  *   ew  dev [n_systems][2] output {U3, W3}, or NULL. */
@@ -149,21 +161,23 @@ const char *mts_status_string(int32_t status);
 
 /* ---- inspection exports (used by the parity tests) ---- */
 
-/* Cell grid of one system: n_cells[0..2] along x, y, z (host out). */
+/* Cell grid of one system: n_cells[0..2] along x, y, z (host out).  MTS_DIRECT:
+ * MTS_ERR_UNSUPPORTED (no cells). */
 mts_status mts_get_grid(const mts_system *sys, int32_t system, int32_t n_cells[3]);
 
 /* After mts_build_cells: per-particle linear cell index (c_z * n_y + c_y) * n_x + c_x
- * within its own system's grid.  cell is dev [N] int32, in input particle order. */
+ * within its own system's grid.  cell is dev [N] int32, in input particle order.
+ * MTS_DIRECT: MTS_ERR_UNSUPPORTED. */
 mts_status mts_get_cell_index(mts_system *sys, int32_t *cell);
 
-/* Number of interacting triplets at x, summed over systems.  Synchronising; count is
- * a host pointer. */
+/* Number of interacting triplets at x, summed over systems (MTS_DIRECT: the sum of
+ * C(N, 3), no device work).  Synchronising; count is a host pointer. */
 mts_status mts_count_triplets(mts_system *sys, const double *x, int64_t *count);
 
 /* Lists the interacting triplets at x as particle-index triples (i<j<k, global
  * indices), in no particular order.  ijk is dev [cap][3] int32; *n (host) receives
  * the total count, which may exceed cap (then only cap rows are written).
- * Synchronising. */
+ * Synchronising.  MTS_DIRECT (every i < j < k): MTS_ERR_UNSUPPORTED unless cap is 0. */
 mts_status mts_list_triplets(mts_system *sys, const double *x, int32_t *ijk, int64_t cap,
                              int64_t *n);
 
@@ -199,7 +213,8 @@ typedef struct {
     double cycle_ms;      /* measured ms per outer r-RESPA cycle (0: untuned) */
 } mts_tuning;
 
-/* Chooses, by measurement on the caller's input, the configuration that runs one outer
+/* (MTS_DIRECT handles have nothing to tune: the call returns their configuration.)
+ * Chooses, by measurement on the caller's input, the configuration that runs one outer
  * r-RESPA cycle fastest -- the role AutoPas's run-time algorithm selection plays for the
  * paper's CPU code (Sec. 4.1, cutoff implementation).  Candidates: pair-list skin
  * (none, 0.15, 0.3, 0.5 sigma; only skins that a particle 1.5 times faster than the

@@ -77,8 +77,23 @@ struct Layout {
 
 }  // namespace
 
+// DirectSum mode: the task list of the all-triplets kernel and its partial-force slots.
+struct DirectState {
+    int ntask = 0, nblk = 0, npblk = 0;
+    DirectTask *task = nullptr;   // [ntask]
+    double *pI = nullptr, *pJ = nullptr, *pK = nullptr;  // partial force slots
+    double *ce = nullptr;         // [ntask][2] ATM energy and virial per task
+    int *blk_sys = nullptr, *blk0 = nullptr;    // 64-particle blocks (gather)
+    int *pblk_sys = nullptr, *pblk0 = nullptr;  // 256-particle blocks (pairs)
+    int *task_of = nullptr;       // per system [nb][nb]
+    int64_t *task_of0 = nullptr;
+    SysDesc *sd = nullptr;        // p0, n; cell0/ncell = the system's task range
+};
+
 struct mts_system {
     mts_params p{};
+    bool direct = false;          // DirectSum: all pairs and triplets, open boundaries
+    DirectState dir;
     int nsys = 0;
     int64_t n = 0;
     hipStream_t st = nullptr;
@@ -169,7 +184,7 @@ mts_status validate_params(const mts_params *p, std::string &msg) {
     if (!std::isfinite(p->skin) || p->skin < 0.0) { msg = "skin must be finite and >= 0"; return MTS_ERR_INVALID_ARG; }
     if (p->k < 1) { msg = "k (step-size factor) must be >= 1"; return MTS_ERR_INVALID_ARG; }
     if (p->precision != MTS_FP64 && p->precision != MTS_FP32) { msg = "unknown precision"; return MTS_ERR_INVALID_ARG; }
-    if (p->reserved != 0) { msg = "reserved must be 0"; return MTS_ERR_INVALID_ARG; }
+    if (p->method != MTS_CUTOFF && p->method != MTS_DIRECT) { msg = "unknown method"; return MTS_ERR_INVALID_ARG; }
     return MTS_OK;
 }
 
@@ -455,7 +470,81 @@ mts_status set_layout(mts_system *s, const Config &cfg) {
     return MTS_OK;
 }
 
+void free_direct(DirectState &d) {
+    void *ptrs[] = {d.task, d.pI, d.pJ, d.pK, d.ce, d.blk_sys, d.blk0, d.pblk_sys, d.pblk0,
+                    d.task_of, d.task_of0, d.sd};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    d = DirectState{};
+}
+
+// DirectSum set-up: per system, the block pairs (I <= J) of 64-particle blocks, J
+// ascending (the heaviest tasks first), their K-slot offsets, the lookup table of task
+// indices, and the block tables of the gather and pair kernels.
+mts_status setup_direct(mts_system *s) {
+    DirectState &D = s->dir;
+    std::vector<DirectTask> tasks;
+    std::vector<int> blk_sys, blk0(s->nsys), pblk_sys, pblk0(s->nsys), task_of;
+    std::vector<int64_t> task_of0(s->nsys);
+    std::vector<SysDesc> sd = s->base;
+    int64_t koff = 0;
+    for (int q = 0; q < s->nsys; ++q) {
+        const int n = (int)s->base[q].n;
+        const int nb = (n + kDirBlock - 1) / kDirBlock;
+        sd[q].cell0 = (int)tasks.size();
+        task_of0[q] = (int64_t)task_of.size();
+        task_of.resize(task_of.size() + (size_t)nb * nb, -1);
+        for (int J = 0; J < nb; ++J)
+            for (int I = 0; I <= J; ++I) {
+                task_of[task_of0[q] + (int64_t)I * nb + J] = (int)tasks.size();
+                DirectTask t{};
+                t.sys = q;
+                t.I = I;
+                t.J = J;
+                t.koff = koff;
+                koff += nb - J;
+                tasks.push_back(t);
+            }
+        sd[q].ncell = (int)tasks.size() - sd[q].cell0;
+        blk0[q] = (int)blk_sys.size();
+        for (int b = 0; b < nb; ++b) blk_sys.push_back(q);
+        pblk0[q] = (int)pblk_sys.size();
+        for (int b = 0; b < (n + 255) / 256; ++b) pblk_sys.push_back(q);
+    }
+    if (tasks.size() >= (size_t)1 << 31) return fail(s, MTS_ERR_UNSUPPORTED, "too many particles for DirectSum");
+    D.ntask = (int)tasks.size();
+    D.nblk = (int)blk_sys.size();
+    D.npblk = (int)pblk_sys.size();
+    const size_t slot = 3 * kDirBlock;
+    HIP_TRY(s, dalloc(&D.task, tasks.size()));
+    HIP_TRY(s, dalloc(&D.pI, tasks.size() * slot));
+    HIP_TRY(s, dalloc(&D.pJ, tasks.size() * slot));
+    HIP_TRY(s, dalloc(&D.pK, (size_t)koff * slot));
+    HIP_TRY(s, dalloc(&D.ce, 2 * tasks.size()));
+    HIP_TRY(s, dalloc(&D.blk_sys, blk_sys.size()));
+    HIP_TRY(s, dalloc(&D.blk0, blk0.size()));
+    HIP_TRY(s, dalloc(&D.pblk_sys, pblk_sys.size()));
+    HIP_TRY(s, dalloc(&D.pblk0, pblk0.size()));
+    HIP_TRY(s, dalloc(&D.task_of, task_of.size()));
+    HIP_TRY(s, dalloc(&D.task_of0, task_of0.size()));
+    HIP_TRY(s, dalloc(&D.sd, sd.size()));
+    auto up = [&](void *dst, const void *src, size_t bytes) {
+        return bytes ? hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) : hipSuccess;
+    };
+    HIP_TRY(s, up(D.task, tasks.data(), sizeof(DirectTask) * tasks.size()));
+    HIP_TRY(s, up(D.blk_sys, blk_sys.data(), sizeof(int) * blk_sys.size()));
+    HIP_TRY(s, up(D.blk0, blk0.data(), sizeof(int) * blk0.size()));
+    HIP_TRY(s, up(D.pblk_sys, pblk_sys.data(), sizeof(int) * pblk_sys.size()));
+    HIP_TRY(s, up(D.pblk0, pblk0.data(), sizeof(int) * pblk0.size()));
+    HIP_TRY(s, up(D.task_of, task_of.data(), sizeof(int) * task_of.size()));
+    HIP_TRY(s, up(D.task_of0, task_of0.data(), sizeof(int64_t) * task_of0.size()));
+    HIP_TRY(s, up(D.sd, sd.data(), sizeof(SysDesc) * sd.size()));
+    if (!tasks.empty()) HIP_TRY(s, hipMemset(D.ce, 0, sizeof(double) * 2 * tasks.size()));
+    return MTS_OK;
+}
+
 void free_all(mts_system *s) {
+    free_direct(s->dir);
     drop_graphs(s);
     if (s->ev_in) (void)hipEventDestroy(s->ev_in);
     if (s->ev_out) (void)hipEventDestroy(s->ev_out);
@@ -694,16 +783,64 @@ mts_status enqueue_triplet_and_list(mts_system *s, bool energy) {
     return MTS_OK;
 }
 
+// DirectSum pair forces at x into f2 (halved pair energies into pe when asked for), timed
+// as kernel class 1.
+mts_status enqueue_direct_pair(mts_system *s, const double *x, double *f2, bool energy) {
+    DirectPairArgs a{};
+    a.nblk = s->dir.npblk;
+    a.blk_sys = s->dir.pblk_sys;
+    a.blk0 = s->dir.pblk0;
+    a.sd = s->dir.sd;
+    a.x = x;
+    a.f = f2;
+    a.pe = energy ? s->pe : nullptr;
+    a.eps = s->p.epsilon;
+    a.sigma2 = s->p.sigma * s->p.sigma;
+    a.flags = s->flags;
+    const long ts = timer_begin(s, 1);
+    HIP_TRY(s, launch_direct_pair(s->st, a, s->fp32));
+    timer_end(s, 1, ts);
+    return MTS_OK;
+}
+
+// DirectSum triplet forces at x into f3 (per-task energies when asked for); the triplet
+// kernel is timed as kernel class 0, the gather is not.
+mts_status enqueue_direct_triplet(mts_system *s, const double *x, double *f3, bool energy) {
+    const DirectState &D = s->dir;
+    DirectArgs a{};
+    a.ntask = D.ntask;
+    a.task = D.task;
+    a.sd = D.sd;
+    a.x = x;
+    a.nu = s->p.nu;
+    a.pI = D.pI;
+    a.pJ = D.pJ;
+    a.pK = D.pK;
+    a.ce = D.ce;
+    a.nblk = D.nblk;
+    a.blk_sys = D.blk_sys;
+    a.blk0 = D.blk0;
+    a.task_of = D.task_of;
+    a.task_of0 = D.task_of0;
+    a.flags = s->flags;
+    const long ts = timer_begin(s, 0);
+    HIP_TRY(s, launch_direct_triplet(s->st, a, s->fp32, energy));
+    timer_end(s, 0, ts);
+    HIP_TRY(s, launch_direct_gather(s->st, a, f3));
+    return MTS_OK;
+}
+
 mts_status enqueue_reduce(mts_system *s, const double *v, bool pair, bool trip, double *out,
                           int stride, int *row, long long *count_out) {
     ReduceArgs a{};
     a.nsys = s->nsys;
-    a.sd = s->lo.gt.sd;
+    a.sd = s->direct ? s->dir.sd : s->lo.gt.sd;  // direct: "cells" are the triplet tasks
     a.v = v;
     a.half_mass = 0.5 * s->p.mass;
     a.pe = pair ? s->pe : nullptr;
-    a.ce = trip && out ? s->lo.ce : nullptr;  // energies are only written when asked for
-    a.cc = trip ? s->lo.cc : nullptr;
+    // energies are only written when asked for
+    a.ce = trip && out ? (s->direct ? s->dir.ce : s->lo.ce) : nullptr;
+    a.cc = trip && !s->direct ? s->lo.cc : nullptr;
     a.out = out;
     a.stride = stride;
     a.count_out = count_out;
@@ -735,7 +872,8 @@ mts_status enqueue_int(mts_system *s, const double *f2prev, const double *f2cur,
     a.kick3_end = kick3_end;
     a.kick3_start = kick3_start;
     a.drift = drift;
-    a.sd = s->lo.gt.sd;
+    a.open = s->direct ? 1 : 0;
+    a.sd = s->direct ? s->dir.sd : s->lo.gt.sd;
     a.sys_of = s->sys_of;
     if (drift && xs_out) {
         a.inv_perm = s->lo.gp.inv_perm;
@@ -769,7 +907,10 @@ mts_status enqueue_full_step_list(mts_system *s, bool energy, bool counted = fal
 
 // Forces at the internal positions x^0 of a call: F3 into s->f3, F2 into f2.
 mts_status enqueue_entry_forces(mts_system *s, double *f2, bool energy) {
-    if (s->lo.skin > 0.0) {
+    if (s->direct) {
+        MTS_TRY(enqueue_direct_pair(s, s->xi, f2, energy));
+        MTS_TRY(enqueue_direct_triplet(s, s->xi, s->f3, energy));
+    } else if (s->lo.skin > 0.0) {
         MTS_TRY(enqueue_full_step_list(s, energy));
         Fused g;
         g.gather3 = true;
@@ -794,10 +935,20 @@ mts_status enqueue_entry_forces(mts_system *s, double *f2, bool energy) {
 //                    slots of x^k and the new pair list; k_pair_list at x^k: F2(x^k),
 //                    F3(x^k) gathered from the slots, last kick2 and the closing F3 kick
 // Without a list (skin 0) every step rebins the pair grid and runs the tile kernel.
+// DirectSum: k_int and the all-pairs kernel every step, the all-triplets kernel and its
+// gather at x^k.
 mts_status enqueue_cycle(mts_system *s, double *f2_0, double *f2_1, bool energies) {
     const int k = s->p.k;
     double *f2[2] = {f2_0, f2_1};
-    if (s->lo.skin > 0.0) {
+    if (s->direct) {
+        for (int i = 0; i < k; ++i) {
+            double *prev = f2[(i + 1) & 1], *cur = f2[i & 1], *next = f2[(i + 1) & 1];
+            MTS_TRY(enqueue_int(s, prev, cur, i > 0, false, i == 0, true, nullptr));
+            MTS_TRY(enqueue_direct_pair(s, s->xi, next, energies && i == k - 1));
+            if (i == k - 1) MTS_TRY(enqueue_direct_triplet(s, s->xi, s->f3, energies));
+        }
+        MTS_TRY(enqueue_int(s, f2[(k - 1) & 1], f2[k & 1], true, true, false, false, nullptr));
+    } else if (s->lo.skin > 0.0) {
         Pos4 *buf[2] = {s->lo.gp.xs, s->lo.gp.xs2};  // x^i lives in buf[i & 1] for 0 < i < k
         MTS_TRY(enqueue_int(s, nullptr, f2[0], false, false, true, true, k > 1 ? buf[1] : nullptr));
         for (int i = 1; i < k; ++i) {
@@ -998,7 +1149,8 @@ mts_status mts_init_system(const mts_params *params, int32_t n_systems, const in
         for (int k = 0; k < 3; ++k) {
             const double L = box[3 * q + k];
             if (!finite_pos(L)) return MTS_ERR_INVALID_ARG;
-            if (!(L > 2.0 * rc_max * kCellMargin)) return MTS_ERR_BOX_TOO_SMALL;
+            if (params->method == MTS_CUTOFF && !(L > 2.0 * rc_max * kCellMargin))
+                return MTS_ERR_BOX_TOO_SMALL;
             d.L[k] = L;
             d.iL[k] = 1.0 / L;
             lmin = std::min(lmin, L);
@@ -1012,6 +1164,7 @@ mts_status mts_init_system(const mts_params *params, int32_t n_systems, const in
 
     mts_system *s = new mts_system();
     s->p = *params;
+    s->direct = params->method == MTS_DIRECT;
     s->nsys = n_systems;
     s->n = p0;
     s->st = (hipStream_t)stream;
@@ -1047,7 +1200,7 @@ mts_status mts_init_system(const mts_params *params, int32_t n_systems, const in
                : std::max(0.3 * params->sigma,
                           12.0 * params->k * params->dt * std::sqrt(params->epsilon / params->mass)));
     mts_status a = alloc_all(s);
-    if (a == MTS_OK) a = build_layout(s, cfg, s->lo);
+    if (a == MTS_OK) a = s->direct ? setup_direct(s) : build_layout(s, cfg, s->lo);
     if (a != MTS_OK) {
         free_all(s);
         delete s;
@@ -1067,6 +1220,7 @@ void mts_destroy_system(mts_system *sys) {
 
 mts_status mts_build_cells(mts_system *sys, const double *x) {
     if (!sys) return MTS_ERR_INVALID_ARG;
+    if (sys->direct) return fail(sys, MTS_ERR_UNSUPPORTED, "DirectSum handles keep no cells");
     if (!x && sys->n > 0) return fail(sys, MTS_ERR_INVALID_ARG, "x is NULL");
     return enqueue_bin(sys, kBinPair | kBinTriplet, x, false);
 }
@@ -1074,8 +1228,12 @@ mts_status mts_build_cells(mts_system *sys, const double *x) {
 mts_status mts_compute_pair_forces(mts_system *sys, const double *x, double *f2, double *ew) {
     if (!sys) return MTS_ERR_INVALID_ARG;
     if ((!x || !f2) && sys->n > 0) return fail(sys, MTS_ERR_INVALID_ARG, "x or f2 is NULL");
-    MTS_TRY(enqueue_bin(sys, kBinPair, x, false));
-    MTS_TRY(enqueue_pair(sys, f2));
+    if (sys->direct) {
+        MTS_TRY(enqueue_direct_pair(sys, x, f2, ew != nullptr));
+    } else {
+        MTS_TRY(enqueue_bin(sys, kBinPair, x, false));
+        MTS_TRY(enqueue_pair(sys, f2));
+    }
     if (ew) MTS_TRY(enqueue_reduce(sys, nullptr, true, false, ew, 2, nullptr, nullptr));
     return MTS_OK;
 }
@@ -1083,8 +1241,12 @@ mts_status mts_compute_pair_forces(mts_system *sys, const double *x, double *f2,
 mts_status mts_compute_triplet_forces(mts_system *sys, const double *x, double *f3, double *ew) {
     if (!sys) return MTS_ERR_INVALID_ARG;
     if ((!x || !f3) && sys->n > 0) return fail(sys, MTS_ERR_INVALID_ARG, "x or f3 is NULL");
-    MTS_TRY(enqueue_bin(sys, kBinTriplet, x, false));
-    MTS_TRY(enqueue_triplet(sys, f3, nullptr, 0, ew != nullptr));
+    if (sys->direct) {
+        MTS_TRY(enqueue_direct_triplet(sys, x, f3, ew != nullptr));
+    } else {
+        MTS_TRY(enqueue_bin(sys, kBinTriplet, x, false));
+        MTS_TRY(enqueue_triplet(sys, f3, nullptr, 0, ew != nullptr));
+    }
     if (ew) MTS_TRY(enqueue_reduce(sys, nullptr, false, true, ew, 2, nullptr, nullptr));
     return MTS_OK;
 }
@@ -1190,18 +1352,26 @@ const char *mts_last_error(const mts_system *sys) { return sys ? sys->err.c_str(
 
 mts_status mts_get_grid(const mts_system *sys, int32_t system, int32_t n_cells[3]) {
     if (!sys || !n_cells || system < 0 || system >= sys->nsys) return MTS_ERR_INVALID_ARG;
+    if (sys->direct) return MTS_ERR_UNSUPPORTED;
     for (int k = 0; k < 3; ++k) n_cells[k] = sys->lo.gt.hsd[system].nc[k];
     return MTS_OK;
 }
 
 mts_status mts_get_cell_index(mts_system *sys, int32_t *cell) {
     if (!sys || (!cell && sys->n > 0)) return MTS_ERR_INVALID_ARG;
+    if (sys->direct) return fail(sys, MTS_ERR_UNSUPPORTED, "DirectSum handles keep no cells");
     HIP_TRY(sys, launch_local_cell_index(sys->st, sys->n, sys->lo.gt.cell_of, sys->lo.gt.sd, sys->sys_of, cell));
     return MTS_OK;
 }
 
 mts_status mts_count_triplets(mts_system *sys, const double *x, int64_t *count) {
     if (!sys || !count || (!x && sys->n > 0)) return MTS_ERR_INVALID_ARG;
+    if (sys->direct) {  // every triplet of each system: C(n, 3)
+        int64_t t = 0;
+        for (const SysDesc &d : sys->base) t += d.n * (d.n - 1) * (d.n - 2) / 6;
+        *count = t;
+        return MTS_OK;
+    }
     MTS_TRY(enqueue_bin(sys, kBinTriplet, x, false));
     MTS_TRY(enqueue_triplet(sys, nullptr, nullptr, 0, false));
     MTS_TRY(enqueue_reduce(sys, nullptr, false, true, nullptr, 2, nullptr, sys->cnt_sys));
@@ -1219,6 +1389,7 @@ mts_status mts_list_triplets(mts_system *sys, const double *x, int32_t *ijk, int
                              int64_t *n) {
     if (!sys || !n || cap < 0 || (!x && sys->n > 0)) return MTS_ERR_INVALID_ARG;
     if (!ijk || cap == 0) return mts_count_triplets(sys, x, n);
+    if (sys->direct) return fail(sys, MTS_ERR_UNSUPPORTED, "DirectSum: every i < j < k is a triplet");
     HIP_TRY(sys, hipMemsetAsync(sys->list_n, 0, sizeof(unsigned long long), sys->st));
     MTS_TRY(enqueue_bin(sys, kBinTriplet, x, false));
     MTS_TRY(enqueue_triplet(sys, nullptr, ijk, cap, false));
@@ -1284,6 +1455,10 @@ mts_status mts_autotune(mts_system *sys, const double *x, const double *v, int32
     if ((!x || !v) && sys->n > 0) return fail(sys, MTS_ERR_INVALID_ARG, "x or v is NULL");
     if (sys->timing) return fail(sys, MTS_ERR_INVALID_ARG, "kernel timing is enabled");
     MTS_TRY(mts_sync(sys));
+    if (sys->direct) {  // nothing to choose: no cells, lists or capacities
+        if (out) fill_tuning(sys, out);
+        return MTS_OK;
+    }
     const std::string key = shape_key(sys);
     {
         std::lock_guard<std::mutex> lk(tune_mutex());

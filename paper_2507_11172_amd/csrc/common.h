@@ -331,6 +331,7 @@ struct IntArgs {
     const double *f2prev, *f2cur, *f3;
     double c2, c3, dt, cx;
     int kick2, kick3_end, kick3_start, drift;
+    int open;               // 1: open boundaries, positions are not wrapped (DirectSum)
     const SysDesc *sd;      // any grid: only the box edges are used
     const int *sys_of;
     const int *inv_perm;    // input -> sorted index of the pair grid, or null
@@ -360,6 +361,47 @@ struct ReduceArgs {
     int *done;              // [nsys + 1] completion counters, zero between launches
 };
 constexpr int kRedChunks = 64;
+
+// ---- DirectSum (no cutoff, open boundaries)
+constexpr int kDirBlock = 64;  // particles per block of the all-triplets kernel
+
+// One workgroup of the all-triplets kernel: block pair (I <= J) of system sys, walking the
+// blocks K = J .. nb-1; its F_K partials are pK blocks koff .. koff + nb - 1 - J.
+struct DirectTask {
+    int sys, I, J, pad;
+    int64_t koff;
+};
+struct DirectArgs {
+    int ntask;
+    const DirectTask *task;  // [ntask], systems in order, J ascending (heaviest first)
+    const SysDesc *sd;       // p0, n of each system
+    const double *x;         // [N][3] positions, input order, no wrapping
+    double nu;
+    double *pI, *pJ;         // [ntask][3][kDirBlock] partial forces of blocks I and J
+    double *pK;              // [sum of (nb - J)][3][kDirBlock] partial forces of blocks K
+    double *ce;              // [ntask][2] ATM energy and virial, or null
+    int nblk;                // 64-particle blocks over all systems (gather workgroups)
+    const int *blk_sys;      // [nblk] system of each block
+    const int *blk0;         // [nsys] first block of each system
+    const int *task_of;      // per system [nb][nb]: task index of (I, J), I <= J
+    const int64_t *task_of0; // [nsys] offset of each system's table
+    int *flags;
+};
+// All-triplets forces of every system: the triplet kernel fills the partial slots, the
+// gather sums them into f ([N][3], input order).
+hipError_t launch_direct_triplet(hipStream_t st, const DirectArgs &a, bool fp32, bool energy);
+hipError_t launch_direct_gather(hipStream_t st, const DirectArgs &a, double *f);
+struct DirectPairArgs {
+    int nblk;                // 256-particle blocks over all systems
+    const int *blk_sys, *blk0;
+    const SysDesc *sd;
+    const double *x;
+    double *f;               // [N][3]
+    double *pe;              // [N][2] half of each pair's LJ energy and virial, or null
+    double eps, sigma2;
+    int *flags;
+};
+hipError_t launch_direct_pair(hipStream_t st, const DirectPairArgs &a, bool fp32);
 hipError_t launch_reduce(hipStream_t st, const ReduceArgs &a);
 hipError_t launch_set_int(hipStream_t st, int *p, int v);  // a kernel, so it may be captured
 

@@ -1,0 +1,313 @@
+// DirectSum: every pair and every triplet of a system, with no cutoff and no periodic
+// images (the paper's accuracy reference, Sec. 3.1: all interactions of all particles;
+// open boundaries, Sec. 4.1 notes that its DirectSum has no boundary conditions).  Same
+// LJ and ATM terms as the cutoff path (Sec. 2.1); the triplet set is i < j < k over the
+// system, C(N, 3) of them.
+//
+// k_direct_triplet is the compute-bound kernel: O(N^3) ATM evaluations, Newton's third
+// law across each triplet.  Particles form blocks of 64 (one per lane).  A workgroup of
+// four waves takes a block pair (I <= J) and walks the blocks K >= J:
+//  * lane l owns particle i = 64 I + l; the waves split the j of block J; for each j the
+//    wave sweeps the 64 k of block K in 64 steps, lane l taking k-slot (l + t) mod 64 at
+//    step t, so that every lane evaluates one triplet per step with no divergence;
+//  * F_i stays in the lane's registers, F_j is summed across the wave once per (j, K),
+//    and F_k is accumulated in the register of lane "k-slot": at step t lane m pulls the
+//    contribution of lane (m - t) mod 64 by a cross-lane permute -- no atomics;
+//  * the partial forces of a task go to its own slots (pI, pJ, one pK block per K) and
+//    k_direct_gather sums, for each particle, every slot that holds a contribution to it
+//    in a fixed order.  Results are bitwise reproducible.
+// Block pairs with I = J, or K = J, mask the triplets that are not i < j < k.  Positions
+// are FP64; T is the precision of the ATM arithmetic; forces accumulate in FP64.
+#include "common.h"
+
+namespace mts {
+
+constexpr int kDirThreads = 4 * kWave;
+
+// ATM terms as in the cutoff kernel (law-of-cosines form): phi and g_a = 2 dphi/da etc.
+template <typename T>
+__device__ __forceinline__ T drsqrt(T x);
+template <>
+__device__ __forceinline__ double drsqrt<double>(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    y = y * fma(-h * y, y, 1.5);
+    y = y * fma(-h * y, y, 1.5);
+    return y;
+}
+template <>
+__device__ __forceinline__ float drsqrt<float>(float x) { return __builtin_amdgcn_rsqf(x); }
+
+template <typename T>
+__device__ __forceinline__ void datm(T a, T b, T c, T nu, T &phi, T &ga, T &gb, T &gc) {
+    const T P = a * b * c;
+    const T rs = drsqrt<T>(P);
+    const T ip = rs * rs;
+    const T p32 = rs * ip;
+    const T p52 = p32 * ip;
+    const T t1 = a + b - c, t2 = a - b + c, t3 = b + c - a;
+    const T tt = t1 * t2 * t3;
+    const T q = T(0.375) * p52;
+    const T K = fma(T(-0.9375) * tt, p52, T(-1.5) * p32);
+    const T Kp = K * ip;
+    const T two_nu = T(2) * nu;
+    ga = two_nu * fma(Kp, b * c, q * fma(T(2) * a, t3, -t1 * t2));
+    gb = two_nu * fma(Kp, a * c, q * fma(T(2) * b, t2, -t1 * t3));
+    gc = two_nu * fma(Kp, a * b, q * fma(T(2) * c, t1, -t2 * t3));
+    phi = nu * fma(q, tt, p32);
+}
+
+__device__ __forceinline__ double dwave_sum(double v) {
+#pragma unroll
+    for (int m = 1; m < kWave; m <<= 1) v += __shfl_xor(v, m);
+    return v;
+}
+
+template <typename T, bool ENERGY>
+__global__ void __launch_bounds__(kDirThreads) k_direct_triplet(DirectArgs a) {
+    __shared__ double sx[3][3][kDirBlock];     // blocks I, J, K: [component][slot]
+    __shared__ double red[4][3][kDirBlock];    // per-wave partials of block K, then of I
+    __shared__ double sj[3][kDirBlock];        // F_j partials (one writing wave per j)
+    __shared__ double se[4][2];
+    const DirectTask tk = a.task[blockIdx.x];
+    const SysDesc &d = a.sd[tk.sys];
+    const int n = (int)d.n;
+    const int64_t p0 = d.p0;
+    const int nb = (n + kDirBlock - 1) / kDirBlock;
+    const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
+    for (int e = tid; e < 2 * 3 * kDirBlock; e += kDirThreads) {
+        const int blk = e / (3 * kDirBlock), c = (e / kDirBlock) % 3, slot = e % kDirBlock;
+        const int idx = (blk ? tk.J : tk.I) * kDirBlock + slot;
+        sx[blk][c][slot] = idx < n ? a.x[3 * (p0 + idx) + c] : 0.0;
+    }
+    for (int e = tid; e < 3 * kDirBlock; e += kDirThreads) sj[e / kDirBlock][e % kDirBlock] = 0.0;
+    __syncthreads();
+    const T nu = (T)a.nu;
+    const int i = tk.I * kDirBlock + lane;
+    const bool iv = i < n;
+    const double xi = sx[0][0][lane], yi = sx[0][1][lane], zi = sx[0][2][lane];
+    double fix = 0.0, fiy = 0.0, fiz = 0.0, U = 0.0, W = 0.0;
+    for (int K = tk.J; K < nb; ++K) {
+        __syncthreads();  // every read of the previous block K is done
+        for (int e = tid; e < 3 * kDirBlock; e += kDirThreads) {
+            const int c = e / kDirBlock, slot = e % kDirBlock;
+            const int idx = K * kDirBlock + slot;
+            sx[2][c][slot] = idx < n ? a.x[3 * (p0 + idx) + c] : 0.0;
+        }
+        __syncthreads();
+        double kx = 0.0, ky = 0.0, kz = 0.0;  // F of k-slot `lane` of block K
+        for (int jj = wave; jj < kDirBlock; jj += 4) {
+            const int j = tk.J * kDirBlock + jj;
+            if (j >= n) break;  // wave-uniform
+            const double xj = sx[1][0][jj], yj = sx[1][1][jj], zj = sx[1][2][jj];
+            const T ux = (T)(xj - xi), uy = (T)(yj - yi), uz = (T)(zj - zi);
+            const T aa = fma(uz, uz, fma(uy, uy, ux * ux));
+            const bool ij = iv && i < j;
+            double jx = 0.0, jy = 0.0, jz = 0.0;
+            for (int t = 0; t < kDirBlock; ++t) {
+                const int ks = (lane + t) & (kDirBlock - 1);
+                const int k = K * kDirBlock + ks;
+                const bool ok = ij && j < k && k < n;
+                const double xk = sx[2][0][ks], yk = sx[2][1][ks], zk = sx[2][2][ks];
+                const T wx = (T)(xk - xi), wy = (T)(yk - yi), wz = (T)(zk - zi);
+                const T vx = (T)(xk - xj), vy = (T)(yk - yj), vz = (T)(zk - zj);
+                const T bb = fma(wz, wz, fma(wy, wy, wx * wx));
+                const T cc = fma(vz, vz, fma(vy, vy, vx * vx));
+                T phi, ga, gb, gc;
+                datm<T>(aa, bb, cc, nu, phi, ga, gb, gc);
+                const T f1x = fma(ga, ux, gb * wx), f1y = fma(ga, uy, gb * wy), f1z = fma(ga, uz, gb * wz);
+                const T f2x = fma(gc, vx, -ga * ux), f2y = fma(gc, vy, -ga * uy), f2z = fma(gc, vz, -ga * uz);
+                // invalid triplets (masked) may be non-finite: select, never multiply
+                const double ax = ok ? (double)f1x : 0.0, ay = ok ? (double)f1y : 0.0, az = ok ? (double)f1z : 0.0;
+                const double bx = ok ? (double)f2x : 0.0, by = ok ? (double)f2y : 0.0, bz = ok ? (double)f2z : 0.0;
+                fix += ax; fiy += ay; fiz += az;
+                jx += bx; jy += by; jz += bz;
+                const int src = (lane - t) & (kDirBlock - 1);
+                kx += __shfl(-(ax + bx), src);
+                ky += __shfl(-(ay + by), src);
+                kz += __shfl(-(az + bz), src);
+                if (ENERGY) {
+                    U += ok ? (double)phi : 0.0;
+                    W += ok ? -(double)fma(aa, ga, fma(bb, gb, cc * gc)) : 0.0;
+                }
+            }
+            jx = dwave_sum(jx);
+            jy = dwave_sum(jy);
+            jz = dwave_sum(jz);
+            if (lane == 0) {
+                sj[0][jj] += jx;
+                sj[1][jj] += jy;
+                sj[2][jj] += jz;
+            }
+        }
+        red[wave][0][lane] = kx;
+        red[wave][1][lane] = ky;
+        red[wave][2][lane] = kz;
+        __syncthreads();
+        if (tid < 3 * kDirBlock) {
+            const int c = tid / kDirBlock, slot = tid % kDirBlock;
+            const double r = ((red[0][c][slot] + red[1][c][slot]) + red[2][c][slot]) + red[3][c][slot];
+            a.pK[(tk.koff + (K - tk.J)) * 3 * kDirBlock + tid] = r;
+        }
+    }
+    __syncthreads();
+    red[wave][0][lane] = fix;
+    red[wave][1][lane] = fiy;
+    red[wave][2][lane] = fiz;
+    if (ENERGY) {
+        U = dwave_sum(U);
+        W = dwave_sum(W);
+        if (lane == 0) {
+            se[wave][0] = U;
+            se[wave][1] = W;
+        }
+    }
+    __syncthreads();
+    if (tid < 3 * kDirBlock) {
+        const int c = tid / kDirBlock, slot = tid % kDirBlock;
+        a.pI[(int64_t)blockIdx.x * 3 * kDirBlock + tid] =
+            ((red[0][c][slot] + red[1][c][slot]) + red[2][c][slot]) + red[3][c][slot];
+        a.pJ[(int64_t)blockIdx.x * 3 * kDirBlock + tid] = sj[c][slot];
+    }
+    if (ENERGY && tid == 0) {
+        a.ce[2 * blockIdx.x] = ((se[0][0] + se[1][0]) + se[2][0]) + se[3][0];
+        a.ce[2 * blockIdx.x + 1] = ((se[0][1] + se[1][1]) + se[2][1]) + se[3][1];
+    }
+}
+
+// F3 of every particle of block X of system s (one workgroup per block): the slots that
+// hold contributions to it -- tasks (X, J) as I, tasks (I, X) as J, tasks (I, J <= X) as
+// K -- summed in a fixed order: each wave takes every fourth slot, the four wave sums are
+// added in wave order.
+__global__ void __launch_bounds__(kDirThreads) k_direct_gather(DirectArgs a, double *f) {
+    __shared__ double red[4][3][kDirBlock];
+    const int s = a.blk_sys[blockIdx.x];
+    const SysDesc &d = a.sd[s];
+    const int n = (int)d.n;
+    const int nb = (n + kDirBlock - 1) / kDirBlock;
+    const int X = (int)blockIdx.x - a.blk0[s];
+    const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
+    const int *tid_of = a.task_of + a.task_of0[s];  // [nb][nb], I <= J
+    double acc[3] = {0.0, 0.0, 0.0};
+    // terms: J = X..nb-1 (role I), I = 0..X (role J), then (I, J) with I <= J <= X (role K)
+    const int nI = nb - X, nJ = X + 1, nK = (X + 1) * (X + 2) / 2;
+    for (int q = wave; q < nI + nJ + nK; q += 4) {
+        const double *src;
+        if (q < nI) {
+            src = a.pI + (int64_t)tid_of[X * nb + X + q] * 3 * kDirBlock;
+        } else if (q < nI + nJ) {
+            src = a.pJ + (int64_t)tid_of[(q - nI) * nb + X] * 3 * kDirBlock;
+        } else {
+            // the r-th pair (I, J) with I <= J <= X, in J-major order
+            const int r = q - nI - nJ;
+            int J = (int)((sqrt(8.0 * r + 1.0) - 1.0) * 0.5);
+            while ((J + 1) * (J + 2) / 2 <= r) ++J;
+            while (J * (J + 1) / 2 > r) --J;
+            const int I = r - J * (J + 1) / 2;
+            const DirectTask &t = a.task[tid_of[I * nb + J]];
+            src = a.pK + (t.koff + (X - J)) * 3 * kDirBlock;
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[c] += src[c * kDirBlock + lane];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) red[wave][c][lane] = acc[c];
+    __syncthreads();
+    if (tid < kDirBlock) {
+        const int i = X * kDirBlock + tid;
+        if (i < n) {
+            double o[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                o[c] = ((red[0][c][tid] + red[1][c][tid]) + red[2][c][tid]) + red[3][c][tid];
+            const int64_t p = d.p0 + i;
+            f[3 * p] = o[0];
+            f[3 * p + 1] = o[1];
+            f[3 * p + 2] = o[2];
+            if (!isfinite(o[0]) || !isfinite(o[1]) || !isfinite(o[2])) atomicOr(a.flags, kFlagNonFinite);
+        }
+    }
+}
+
+// LJ forces of every pair (no cutoff, no images): each particle gathers its own force
+// over all others of its system (no scatter, fixed order), 256 particles per workgroup
+// against tiles of 256 staged in LDS.  pe receives half of each pair's energy and virial.
+template <typename T, bool ENERGY>
+__global__ void __launch_bounds__(kDirThreads) k_direct_pair(DirectPairArgs a) {
+    __shared__ double tx[3][kDirThreads];
+    const int s = a.blk_sys[blockIdx.x];
+    const SysDesc &d = a.sd[s];
+    const int n = (int)d.n;
+    const int i = ((int)blockIdx.x - a.blk0[s]) * kDirThreads + (int)threadIdx.x;
+    const bool iv = i < n;
+    const int64_t p = d.p0 + (iv ? i : 0);
+    const double xi = iv ? a.x[3 * p] : 0.0, yi = iv ? a.x[3 * p + 1] : 0.0,
+                 zi = iv ? a.x[3 * p + 2] : 0.0;
+    const T sigma2 = (T)a.sigma2, eps24 = (T)(24.0 * a.eps), eps4 = (T)(4.0 * a.eps);
+    double fx = 0.0, fy = 0.0, fz = 0.0, u = 0.0, w = 0.0;
+    for (int j0 = 0; j0 < n; j0 += kDirThreads) {
+        __syncthreads();
+        const int jl = j0 + (int)threadIdx.x;
+        for (int c = 0; c < 3; ++c) tx[c][threadIdx.x] = jl < n ? a.x[3 * (d.p0 + jl) + c] : 0.0;
+        __syncthreads();
+        const int m = min(kDirThreads, n - j0);
+        for (int t = 0; t < m; ++t) {
+            const T dx = (T)(tx[0][t] - xi), dy = (T)(tx[1][t] - yi), dz = (T)(tx[2][t] - zi);
+            const T r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+            const T inv = T(1) / r2;
+            const T s2 = sigma2 * inv;
+            const T s6 = s2 * s2 * s2;
+            const T s12 = s6 * s6;
+            const T fr = eps24 * fma(T(2), s12, -s6) * inv;
+            const bool ok = iv && j0 + t != i;
+            fx -= ok ? (double)(fr * dx) : 0.0;
+            fy -= ok ? (double)(fr * dy) : 0.0;
+            fz -= ok ? (double)(fr * dz) : 0.0;
+            if (ENERGY) {
+                u += ok ? (double)(eps4 * (s12 - s6)) : 0.0;
+                w += ok ? (double)(fr * r2) : 0.0;
+            }
+        }
+    }
+    if (!iv) return;
+    a.f[3 * p] = fx;
+    a.f[3 * p + 1] = fy;
+    a.f[3 * p + 2] = fz;
+    if (ENERGY) {
+        a.pe[2 * p] = 0.5 * u;
+        a.pe[2 * p + 1] = 0.5 * w;
+    }
+    if (!isfinite(fx) || !isfinite(fy) || !isfinite(fz)) atomicOr(a.flags, kFlagNonFinite);
+}
+
+hipError_t launch_direct_triplet(hipStream_t st, const DirectArgs &a, bool fp32, bool energy) {
+    if (a.ntask <= 0) return hipSuccess;
+    if (fp32) {
+        if (energy) k_direct_triplet<float, true><<<a.ntask, kDirThreads, 0, st>>>(a);
+        else k_direct_triplet<float, false><<<a.ntask, kDirThreads, 0, st>>>(a);
+    } else {
+        if (energy) k_direct_triplet<double, true><<<a.ntask, kDirThreads, 0, st>>>(a);
+        else k_direct_triplet<double, false><<<a.ntask, kDirThreads, 0, st>>>(a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_direct_gather(hipStream_t st, const DirectArgs &a, double *f) {
+    if (a.nblk > 0) k_direct_gather<<<a.nblk, kDirThreads, 0, st>>>(a, f);
+    return hipGetLastError();
+}
+
+hipError_t launch_direct_pair(hipStream_t st, const DirectPairArgs &a, bool fp32) {
+    if (a.nblk <= 0) return hipSuccess;
+    const bool energy = a.pe != nullptr;
+    if (fp32) {
+        if (energy) k_direct_pair<float, true><<<a.nblk, kDirThreads, 0, st>>>(a);
+        else k_direct_pair<float, false><<<a.nblk, kDirThreads, 0, st>>>(a);
+    } else {
+        if (energy) k_direct_pair<double, true><<<a.nblk, kDirThreads, 0, st>>>(a);
+        else k_direct_pair<double, false><<<a.nblk, kDirThreads, 0, st>>>(a);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace mts

@@ -28,7 +28,8 @@ __global__ void __launch_bounds__(256) k_int(IntArgs a) {
         if (a.kick3_start) vq = vq + a.c3 * a.f3[q];
         a.v[q] = vq;
         if (a.drift) {
-            xn[k] = wrap1(a.x[q] + a.dt * vq + a.cx * a.f2cur[q], d.L[k]);
+            const double xd = a.x[q] + a.dt * vq + a.cx * a.f2cur[q];
+            xn[k] = a.open ? xd : wrap1(xd, d.L[k]);
             a.x[q] = xn[k];
         }
     }

@@ -26,6 +26,8 @@ MTS_ERR_OOM = -7
 MTS_ERR_UNSUPPORTED = -8
 MTS_FP64 = 0
 MTS_FP32 = 1
+MTS_CUTOFF = 0
+MTS_DIRECT = 1
 MTS_NE = 5
 
 EXPORTS = ("mts_init_system", "mts_destroy_system", "mts_build_cells", "mts_compute_pair_forces",
@@ -48,7 +50,7 @@ class mts_params(C.Structure):
                 ("nu", C.c_double), ("rc_triplet", C.c_double), ("mass", C.c_double),
                 ("dt", C.c_double), ("skin", C.c_double), ("k", C.c_int32),
                 ("precision", C.c_int32),
-                ("lj_energy_shift", C.c_int32), ("reserved", C.c_int32)]
+                ("lj_energy_shift", C.c_int32), ("method", C.c_int32)]
 
 
 class mts_tuning(C.Structure):
@@ -127,12 +129,14 @@ class Params:
     precision: str = "fp64"   # "fp64" or "fp32"
     lj_energy_shift: bool = True
     skin: float = 0.0         # pair-list skin; 0 picks the library default
+    method: str = "cutoff"    # "cutoff" (linked cells, periodic) or "direct" (DirectSum)
 
     def to_c(self) -> mts_params:
         prec = {"fp64": MTS_FP64, "fp32": MTS_FP32}[self.precision]
+        meth = {"cutoff": MTS_CUTOFF, "direct": MTS_DIRECT}[self.method]
         return mts_params(self.epsilon, self.sigma, self.rc_pair, self.nu, self.rc_triplet,
                           self.mass, self.dt, float(self.skin), int(self.k), prec,
-                          int(bool(self.lj_energy_shift)), 0)
+                          int(bool(self.lj_energy_shift)), meth)
 
 
 def _ptr(t, what: str, shape: Optional[Tuple[int, ...]] = None, dtype=None):

@@ -243,6 +243,39 @@ def batched(n_replicas: int = 256, n_min: int = 200, n_max: int = 20_000) -> Wor
                     n_iter=1000, precision="fp32")
 
 
+def open_cluster(n_particles: int, length: float, jitter: float, rng: np.random.Generator):
+    """N sites drawn without replacement from the smallest FCC lattice holding N that fills
+    a cube of edge `length`, jittered and not wrapped (open boundaries); returns (x, box)."""
+    n = int(math.ceil((n_particles / 4.0) ** (1.0 / 3.0) - 1e-12))
+    while 4 * n ** 3 < n_particles:
+        n += 1
+    sites = fcc_sites((n, n, n), np.full(3, length / n))
+    keep = np.sort(rng.choice(sites.shape[0], size=n_particles, replace=False))
+    x = sites[keep] + rng.uniform(-jitter, jitter, size=(n_particles, 3))
+    return x, np.full(3, length)
+
+
+def toy(nu: float = 0.073, n_particles: int = 675, length: float = 10.0, temperature: float = 0.7,
+        seed: int = 1006) -> Workload:
+    """Toy scenario of the RVITE study (Sec. 4.2.1): 675 particles in a 10^3 domain,
+    eps = sigma = 1, dt = 0.001, nu varied; DirectSum (open boundaries).  Initial state
+    (the paper gives none): a jittered FCC subset filling the domain, T 0.7."""
+    rng = rng_for(seed)
+    x, box = open_cluster(n_particles, length, 0.05, rng)
+    return _single("toy%d_nu%.3g" % (n_particles, nu), x, box, temperature, rng, nu=nu, k=1,
+                   n_iter=1200)
+
+
+def aluminium(seed: int = 1007) -> Workload:
+    """Aluminium scenario (appendix table): 4,995 particles in a 20^3 domain, nu 0.3095,
+    dt 0.00304, T 1.1 (reduced units); DirectSum (open boundaries).  Initial state: a
+    jittered FCC subset filling the domain."""
+    rng = rng_for(seed)
+    n, length = 4995, 20.0
+    x, box = open_cluster(n, length, 0.05, rng)
+    return _single("al4995", x, box, 1.1, rng, nu=0.3095, dt=0.00304, k=12, n_iter=24000)
+
+
 def perfect_fcc(n_cells: int, density: float = 0.8):
     """Unjittered lattice (x, box): every force vanishes by inversion symmetry."""
     return fcc(n_cells, density, 0.0, None)

@@ -39,7 +39,7 @@ def test_status_strings(lib):
 def _init(lib, **over):
     from paper_2507_11172_amd import mts
     kw = dict(epsilon=1.0, sigma=1.0, rc_pair=2.5, nu=0.073, rc_triplet=2.5, mass=1.0, dt=0.001,
-              skin=0.0, k=10, precision=0, lj_energy_shift=1, reserved=0)
+              skin=0.0, k=10, precision=0, lj_energy_shift=1, method=0)
     n = over.pop("n", [500])
     box = over.pop("box", [[8.55, 8.55, 8.55]])
     kw.update(over)
@@ -54,7 +54,7 @@ def _init(lib, **over):
 
 @pytest.mark.parametrize("bad,code", [
     (dict(k=0), -1), (dict(dt=0.0), -1), (dict(mass=-1.0), -1), (dict(sigma=0.0), -1),
-    (dict(rc_pair=float("nan")), -1), (dict(precision=7), -1), (dict(reserved=1), -1),
+    (dict(rc_pair=float("nan")), -1), (dict(precision=7), -1), (dict(method=2), -1),
     (dict(epsilon=-1.0), -1), (dict(skin=-0.1), -1), (dict(skin=float("inf")), -1),
     (dict(n=[-5]), -1),
     (dict(box=[[4.9, 8.5, 8.5]]), -2), (dict(box=[[8.5, 8.5, 5.0]]), -2),
@@ -74,6 +74,20 @@ def test_null_arguments(lib):
     assert lib.mts_get_tuning(None, None) == -1
     assert lib.mts_set_option(None, 1, 1) == -1
     lib.mts_destroy_system(None)  # ignored
+
+
+def test_params_struct_matches_header(lib):
+    """The binding's mts_params mirrors the header's field order and types."""
+    import re
+    from paper_2507_11172_amd import mts
+    hdr = open(os.path.join(ROOT, "include", "mts.h")).read()
+    start = hdr.index("typedef struct {", hdr.index("Interaction and integration parameters"))
+    body = hdr[start:hdr.index("} mts_params;")]
+    fields = re.findall(r"^\s*(double|int32_t)\s+(\w+);", body, re.M)
+    py = [(n, t) for n, t in mts.mts_params._fields_]
+    assert [f[1] for f in fields] == [n for n, _ in py]
+    for (ctype, _), (_, t) in zip(fields, py):
+        assert (ctype == "double") == (t is C.c_double)
 
 
 def test_tuning_struct_matches_header(lib):

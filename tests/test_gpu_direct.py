@@ -1,0 +1,169 @@
+"""GPU parity of the DirectSum path (every pair and triplet, no cutoff, open boundaries)
+against the FP64 CPU oracle.
+
+The oracle has periodic boxes and cutoffs; with a box far larger than the cluster and a
+cutoff beyond every distance (but below half the box) its minimum image is the plain
+difference and every pair and triplet interacts: that is DirectSum.  Positions are shifted
+to be positive so that the oracle's wrap is the identity.  Bars as for the cutoff path:
+FP64 forces within 1e-12 (max |dF| over RMS |F|), energies within 1e-12 relative; the FP32
+form within 1e-5 on forces and 1e-7 per particle on energy.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2507_11172_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+BIG = np.full(3, 1.0e6)
+RC = 4.0e5
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "no GPU visible"
+    return torch
+
+
+def _dev(a):
+    torch = _torch()
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _system(ns, nu=0.073, dt=0.001, k=1, precision="fp64"):
+    from paper_2507_11172_amd import mts
+    p = mts.Params(nu=nu, dt=dt, k=k, precision=precision, method="direct")
+    return mts.System(p, list(ns), np.full((len(ns), 3), 10.0))
+
+
+def _cluster(n, seed, length=None):
+    rng = W.rng_for(seed)
+    length = length or max(2.0, (n / 0.675) ** (1.0 / 3.0))
+    x, _ = W.open_cluster(n, length, 0.05, rng)
+    v = W.maxwell_boltzmann(n, 0.7, rng)
+    return x + 1.0, v  # positive: the oracle's wrap is the identity
+
+
+def rel_err(got, ref):
+    return np.abs(got - ref).max() / max(np.sqrt(np.mean(np.sum(ref * ref, axis=1))), 1e-300)
+
+
+def _gpu_forces(ns, x, precision="fp64", nu=0.073):
+    torch = _torch()
+    with _system(ns, nu=nu, precision=precision) as s:
+        xd = _dev(x)
+        f2, f3 = torch.empty_like(xd), torch.empty_like(xd)
+        e2 = torch.zeros((len(ns), 2), dtype=torch.float64, device="cuda")
+        e3 = torch.zeros((len(ns), 2), dtype=torch.float64, device="cuda")
+        s.compute_pair_forces(xd, f2, e2)
+        s.compute_triplet_forces(xd, f3, e3)
+        count = s.count_triplets(xd)
+        s.sync()
+    return f2.cpu().numpy(), f3.cpu().numpy(), e2.cpu().numpy(), e3.cpu().numpy(), count
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 5, 64, 65, 130, 200])
+def test_direct_forces_and_energies_match_oracle(n):
+    """Empty, tiny, exact and ragged 64-particle blocks; every pair and triplet."""
+    x, _ = _cluster(max(n, 1), 40 + n)
+    x = x[:n]
+    f2, f3, e2, e3, count = _gpu_forces([n], x)
+    assert count == math.comb(n, 3)
+    if n == 0:
+        return
+    r2 = oracle.pair_forces(x, BIG, rc=RC, shift=False)
+    r3 = oracle.triplet_forces(x, BIG, rc=RC)
+    assert r2.count == math.comb(n, 2) and r3.count == math.comb(n, 3)
+    if n >= 2:
+        assert rel_err(f2, r2.f) <= 1e-12
+        assert abs(e2[0, 0] - r2.energy) <= 1e-12 * abs(r2.energy)
+        assert abs(e2[0, 1] - r2.virial) <= 1e-12 * abs(r2.virial)
+    else:
+        assert np.all(f2 == 0.0) and np.all(e2 == 0.0)
+    if n >= 3:
+        assert rel_err(f3, r3.f) <= 1e-12
+        assert abs(e3[0, 0] - r3.energy) <= 1e-12 * abs(r3.energy)
+        assert abs(e3[0, 1] - r3.virial) <= 1e-12 * abs(r3.virial)
+        assert np.abs(f3.sum(axis=0)).max() <= 1e-10 * np.abs(f3).max()  # Newton's third law
+    else:
+        assert np.all(f3 == 0.0) and np.all(e3 == 0.0)
+
+
+def test_direct_toy_scenario_both_forms():
+    """675 particles in a 10^3 domain (the RVITE study's toy scenario), nu 0.3: FP64 at the
+    1e-12 bar, the FP32 form at 1e-5 on forces and 1e-7 per particle on energy."""
+    w = W.toy(nu=0.3)
+    x = w.x + 1.0
+    n = x.shape[0]
+    r2 = oracle.pair_forces(x, BIG, rc=RC, shift=False)
+    r3 = oracle.triplet_forces(x, BIG, nu=0.3, rc=RC)
+    f2, f3, e2, e3, _ = _gpu_forces([n], x, nu=0.3)
+    assert rel_err(f2, r2.f) <= 1e-12 and rel_err(f3, r3.f) <= 1e-12
+    assert abs(e3[0, 0] - r3.energy) <= 1e-12 * abs(r3.energy)
+    g2, g3, h2, h3, _ = _gpu_forces([n], x, precision="fp32", nu=0.3)
+    assert rel_err(g2, r2.f) <= 1e-5 and rel_err(g3, r3.f) <= 1e-5
+    assert abs((h2[0, 0] + h3[0, 0]) - (r2.energy + r3.energy)) / n <= 1e-7
+
+
+def test_direct_batched_bitwise_and_oracle():
+    """Uneven systems in one handle: each one bit for bit as on its own handle, and at the
+    oracle's bar."""
+    ns = [200, 77, 1, 0, 130]
+    xs = [_cluster(max(m, 1), 60 + i)[0][:m] for i, m in enumerate(ns)]
+    x = np.concatenate(xs)
+    f2, f3, e2, e3, count = _gpu_forces(ns, x)
+    assert count == sum(math.comb(m, 3) for m in ns)
+    off = 0
+    for i, m in enumerate(ns):
+        g2, g3, h2, h3, _ = _gpu_forces([m], xs[i])
+        sl = slice(off, off + m)
+        assert np.array_equal(f2[sl], g2) and np.array_equal(f3[sl], g3), i
+        assert np.array_equal(e2[i], h2[0]) and np.array_equal(e3[i], h3[0]), i
+        if m >= 3:
+            assert rel_err(f3[sl], oracle.triplet_forces(xs[i], BIG, rc=RC).f) <= 1e-12, i
+        off += m
+
+
+def test_direct_respa_matches_oracle_and_graph():
+    """Algorithm 2 on DirectSum forces, k = 3: the trajectory and the energy records
+    follow the oracle's within round-off amplification; graph replay and eager launches
+    agree bit for bit."""
+    torch = _torch()
+    from paper_2507_11172_amd import mts
+    n, k, n_iter = 100, 3, 12
+    x, v = _cluster(n, 77)
+    xo, vo, eo = oracle.respa(x, v, BIG, n_iter=n_iter, k=k, rc_pair=RC, rc3=RC, shift=False)
+    runs = []
+    for graph in (1, 0):
+        with _system([n], k=k) as s:
+            s.set_option(mts.MTS_OPT_CYCLE_GRAPH, graph)
+            xd, vd = _dev(x), _dev(v)
+            e = torch.zeros((n_iter // k + 1, 1, mts.MTS_NE), dtype=torch.float64, device="cuda")
+            s.respa_step(xd, vd, n_iter, e)
+            s.sync()
+            runs.append((xd.cpu().numpy(), vd.cpu().numpy(), e.cpu().numpy()[:, 0, :]))
+    for a, b in zip(runs[0], runs[1]):
+        assert np.array_equal(a, b)
+    xg, vg, eg = runs[0]
+    assert np.abs(xg - xo).max() <= 1e-10
+    assert np.abs(vg - vo).max() <= 1e-9
+    assert np.abs(eg - eo).max() <= 1e-9 * np.abs(eo).max()
+
+
+def test_direct_unsupported_calls():
+    torch = _torch()
+    from paper_2507_11172_amd import mts
+    x, _ = _cluster(10, 5)
+    with _system([10]) as s:
+        xd = _dev(x)
+        with pytest.raises(mts.MTSError) as e:
+            s.build_cells(xd)
+        assert e.value.code == mts.MTS_ERR_UNSUPPORTED
+        with pytest.raises(mts.MTSError) as e:
+            s.list_triplets(xd, 16)
+        assert e.value.code == mts.MTS_ERR_UNSUPPORTED
+        t = s.autotune(xd, torch.zeros_like(xd), 100)
+        assert t["trials"] == 0
