@@ -14,6 +14,10 @@ the FP32 form and the CPU oracle timed beside it.  Other workloads (--workload):
   slab30   the same with rc3 3.0
   batched  256 replicas of 200..20,000 particles in one handle, FP32 form, k = 10, with
            the same replicas run one handle at a time for comparison
+  toy675   DirectSum (every pair and triplet, open boundaries): the RVITE study's toy
+           scenario, 675 particles in a 10^3 domain, nu 0.3, FP64, k = 1
+  al4995   DirectSum: the aluminium scenario, 4,995 particles in a 20^3 domain,
+           nu 0.3095, dt 0.00304, FP64, k = 12
 Prints one JSON line.  For several systems "value" is the aggregate over systems
 (system inner steps per second).
 """
@@ -53,6 +57,8 @@ def _workload(name: str):
         "slab25": lambda: W.inhomogeneous(2.5),
         "slab30": lambda: W.inhomogeneous(3.0),
         "batched": W.batched,
+        "toy675": lambda: W.toy(nu=0.3),
+        "al4995": W.aluminium,
     }
     if name not in table:
         raise SystemExit("unknown workload %s (one of %s)" % (name, ", ".join(table)))
@@ -62,7 +68,8 @@ def _workload(name: str):
 def _params(w, precision: str, k: int):
     from paper_2507_11172_amd import mts
     return mts.Params(epsilon=w.epsilon, sigma=w.sigma, rc_pair=w.rc_pair, nu=w.nu,
-                      rc_triplet=w.rc_triplet, mass=w.mass, dt=w.dt, k=k, precision=precision)
+                      rc_triplet=w.rc_triplet, mass=w.mass, dt=w.dt, k=k, precision=precision,
+                      method=w.method)
 
 
 def _drift_stats(en, n_particles):
@@ -202,6 +209,8 @@ def cpu_baseline(w, k: int):
     evaluation of the whole system, scaled to inner steps/s for step-size factor k."""
     import oracle
     nthreads = oracle.num_threads()
+    if w.method == "direct":
+        return _cpu_baseline_direct(w, k, nthreads)
     box = w.box[0]
     t0 = time.perf_counter()
     oracle.pair_forces(w.x, box, rc=w.rc_pair, nthreads=nthreads)
@@ -216,6 +225,35 @@ def cpu_baseline(w, k: int):
                       "k=%d pair + 1 triplet evaluations per k inner steps"
                       % (t_pair, t_trip, r3.count, w.n_total, k),
             "triplets_per_s": r3.count / t_trip}
+
+
+def _cpu_baseline_direct(w, k: int, nthreads: int):
+    """DirectSum through the oracle: a box far larger than the cluster and a cutoff beyond
+    every distance.  The pair evaluation runs on the whole system; the O(N^3) triplet one on
+    the first M particles, M chosen for a few seconds of work, its rate scaled to C(N, 3)."""
+    import math
+    import numpy as np
+    import oracle
+    big, rc = np.full(3, 1.0e6), 4.0e5
+    x = w.x - w.x.min(axis=0) + 1.0
+    n = x.shape[0]
+    t0 = time.perf_counter()
+    oracle.pair_forces(x, big, rc=rc, shift=False, nthreads=nthreads)
+    t_pair = time.perf_counter() - t0
+    m = min(n, 1200)
+    t0 = time.perf_counter()
+    r3 = oracle.triplet_forces(x[:m], big, nu=w.nu, rc=rc, nthreads=nthreads)
+    t_m = time.perf_counter() - t0
+    rate = r3.count / t_m
+    t_trip = math.comb(n, 3) / rate
+    return {"value": k / (k * t_pair + t_trip), "unit": "MD steps/s", "cores": nthreads,
+            "kind": "oracle",
+            "sample": "DirectSum: one LJ evaluation of all %d particles (%.2f s) and one ATM "
+                      "evaluation of the first %d (%.2f s, %d triplets), its rate scaled to "
+                      "the C(N,3) = %d triplets of the system; k=%d pair + 1 triplet "
+                      "evaluations per k inner steps" % (n, t_pair, m, t_m, r3.count,
+                                                         math.comb(n, 3), k),
+            "triplets_per_s": rate}
 
 
 def traffic_probe(w, precision: str, k: int, tune_ms: int):
@@ -280,6 +318,8 @@ def main(argv=None):
     achieved = FLOPS_PER_TRIPLET * r["triplets_per_eval"] / trip_s / 1e12 if trip_s > 0 else 0.0
     peak = PEAK_TFLOPS[precision]
     kernel = "k_triplet_and_list" if r["tuning"].get("shared_launch") else "k_triplet"
+    if w.method == "direct":
+        kernel = "k_direct_triplet"
     ncls = int(r["tuning"].get("tile_classes", 1))
     if ncls > 1:  # one launch per tile class, timed together
         kernel += " + k_triplet x %d (tile classes)" % (ncls - 1)
@@ -296,7 +336,8 @@ def main(argv=None):
         "vs_baseline": None,
         "dtype": "f64" if precision == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": w.name, "n_particles": w.n_total, "n_systems": w.n_systems,
+        "config": {"workload": w.name, "method": w.method, "n_particles": w.n_total,
+                   "n_systems": w.n_systems,
                    "k": k, "inner_steps": r["inner_steps"], "precision": precision,
                    "rc_pair": w.rc_pair, "rc_triplet": w.rc_triplet, "nu": w.nu, "dt": w.dt,
                    "step": "one r-RESPA outer cycle (k inner steps + 1 triplet evaluation)"},

@@ -478,33 +478,26 @@ void free_direct(DirectState &d) {
     d = DirectState{};
 }
 
-// DirectSum set-up: per system, the block pairs (I <= J) of 64-particle blocks, J
-// ascending (the heaviest tasks first), their K-slot offsets, the lookup table of task
-// indices, and the block tables of the gather and pair kernels.
+// DirectSum set-up: per system, the block triples (I <= J <= K) of 64-particle blocks,
+// the lookup table of task indices, and the block tables of the gather and pair kernels.
 mts_status setup_direct(mts_system *s) {
     DirectState &D = s->dir;
     std::vector<DirectTask> tasks;
     std::vector<int> blk_sys, blk0(s->nsys), pblk_sys, pblk0(s->nsys), task_of;
     std::vector<int64_t> task_of0(s->nsys);
     std::vector<SysDesc> sd = s->base;
-    int64_t koff = 0;
     for (int q = 0; q < s->nsys; ++q) {
         const int n = (int)s->base[q].n;
         const int nb = (n + kDirBlock - 1) / kDirBlock;
         sd[q].cell0 = (int)tasks.size();
         task_of0[q] = (int64_t)task_of.size();
-        task_of.resize(task_of.size() + (size_t)nb * nb, -1);
-        for (int J = 0; J < nb; ++J)
-            for (int I = 0; I <= J; ++I) {
-                task_of[task_of0[q] + (int64_t)I * nb + J] = (int)tasks.size();
-                DirectTask t{};
-                t.sys = q;
-                t.I = I;
-                t.J = J;
-                t.koff = koff;
-                koff += nb - J;
-                tasks.push_back(t);
-            }
+        task_of.resize(task_of.size() + (size_t)nb * nb * nb, -1);
+        for (int I = 0; I < nb; ++I)
+            for (int J = I; J < nb; ++J)
+                for (int K = J; K < nb; ++K) {
+                    task_of[task_of0[q] + ((int64_t)I * nb + J) * nb + K] = (int)tasks.size();
+                    tasks.push_back(DirectTask{q, I, J, K});
+                }
         sd[q].ncell = (int)tasks.size() - sd[q].cell0;
         blk0[q] = (int)blk_sys.size();
         for (int b = 0; b < nb; ++b) blk_sys.push_back(q);
@@ -519,7 +512,7 @@ mts_status setup_direct(mts_system *s) {
     HIP_TRY(s, dalloc(&D.task, tasks.size()));
     HIP_TRY(s, dalloc(&D.pI, tasks.size() * slot));
     HIP_TRY(s, dalloc(&D.pJ, tasks.size() * slot));
-    HIP_TRY(s, dalloc(&D.pK, (size_t)koff * slot));
+    HIP_TRY(s, dalloc(&D.pK, tasks.size() * slot));
     HIP_TRY(s, dalloc(&D.ce, 2 * tasks.size()));
     HIP_TRY(s, dalloc(&D.blk_sys, blk_sys.size()));
     HIP_TRY(s, dalloc(&D.blk0, blk0.size()));

@@ -365,25 +365,22 @@ constexpr int kRedChunks = 64;
 // ---- DirectSum (no cutoff, open boundaries)
 constexpr int kDirBlock = 64;  // particles per block of the all-triplets kernel
 
-// One workgroup of the all-triplets kernel: block pair (I <= J) of system sys, walking the
-// blocks K = J .. nb-1; its F_K partials are pK blocks koff .. koff + nb - 1 - J.
+// One workgroup of the all-triplets kernel: block triple (I <= J <= K) of system sys.
 struct DirectTask {
-    int sys, I, J, pad;
-    int64_t koff;
+    int sys, I, J, K;
 };
 struct DirectArgs {
     int ntask;
-    const DirectTask *task;  // [ntask], systems in order, J ascending (heaviest first)
+    const DirectTask *task;  // [ntask], systems in order
     const SysDesc *sd;       // p0, n of each system
     const double *x;         // [N][3] positions, input order, no wrapping
     double nu;
-    double *pI, *pJ;         // [ntask][3][kDirBlock] partial forces of blocks I and J
-    double *pK;              // [sum of (nb - J)][3][kDirBlock] partial forces of blocks K
+    double *pI, *pJ, *pK;    // [ntask][3][kDirBlock] partial forces of blocks I, J and K
     double *ce;              // [ntask][2] ATM energy and virial, or null
     int nblk;                // 64-particle blocks over all systems (gather workgroups)
     const int *blk_sys;      // [nblk] system of each block
     const int *blk0;         // [nsys] first block of each system
-    const int *task_of;      // per system [nb][nb]: task index of (I, J), I <= J
+    const int *task_of;      // per system [nb][nb][nb]: task index of (I, J, K), I <= J <= K
     const int64_t *task_of0; // [nsys] offset of each system's table
     int *flags;
 };

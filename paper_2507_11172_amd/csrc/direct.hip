@@ -6,17 +6,18 @@
 //
 // k_direct_triplet is the compute-bound kernel: O(N^3) ATM evaluations, Newton's third
 // law across each triplet.  Particles form blocks of 64 (one per lane).  A workgroup of
-// four waves takes a block pair (I <= J) and walks the blocks K >= J:
+// four waves takes a block triple (I <= J <= K) -- equal work per workgroup, and enough
+// workgroups to fill the chip from a few hundred particles on:
 //  * lane l owns particle i = 64 I + l; the waves split the j of block J; for each j the
 //    wave sweeps the 64 k of block K in 64 steps, lane l taking k-slot (l + t) mod 64 at
 //    step t, so that every lane evaluates one triplet per step with no divergence;
 //  * F_i stays in the lane's registers, F_j is summed across the wave once per (j, K),
 //    and F_k is accumulated in the register of lane "k-slot": at step t lane m pulls the
 //    contribution of lane (m - t) mod 64 by a cross-lane permute -- no atomics;
-//  * the partial forces of a task go to its own slots (pI, pJ, one pK block per K) and
-//    k_direct_gather sums, for each particle, every slot that holds a contribution to it
-//    in a fixed order.  Results are bitwise reproducible.
-// Block pairs with I = J, or K = J, mask the triplets that are not i < j < k.  Positions
+//  * the partial forces of a task go to its own slots (pI, pJ, pK) and k_direct_gather
+//    sums, for each particle, every slot that holds a contribution to it in a fixed
+//    order.  Results are bitwise reproducible.
+// Block triples with I = J or J = K mask the triplets that are not i < j < k.  Positions
 // are FP64; T is the precision of the ATM arithmetic; forces accumulate in FP64.
 #include "common.h"
 
@@ -73,11 +74,10 @@ __global__ void __launch_bounds__(kDirThreads) k_direct_triplet(DirectArgs a) {
     const SysDesc &d = a.sd[tk.sys];
     const int n = (int)d.n;
     const int64_t p0 = d.p0;
-    const int nb = (n + kDirBlock - 1) / kDirBlock;
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
-    for (int e = tid; e < 2 * 3 * kDirBlock; e += kDirThreads) {
+    for (int e = tid; e < 3 * 3 * kDirBlock; e += kDirThreads) {
         const int blk = e / (3 * kDirBlock), c = (e / kDirBlock) % 3, slot = e % kDirBlock;
-        const int idx = (blk ? tk.J : tk.I) * kDirBlock + slot;
+        const int idx = (blk == 0 ? tk.I : (blk == 1 ? tk.J : tk.K)) * kDirBlock + slot;
         sx[blk][c][slot] = idx < n ? a.x[3 * (p0 + idx) + c] : 0.0;
     }
     for (int e = tid; e < 3 * kDirBlock; e += kDirThreads) sj[e / kDirBlock][e % kDirBlock] = 0.0;
@@ -87,14 +87,8 @@ __global__ void __launch_bounds__(kDirThreads) k_direct_triplet(DirectArgs a) {
     const bool iv = i < n;
     const double xi = sx[0][0][lane], yi = sx[0][1][lane], zi = sx[0][2][lane];
     double fix = 0.0, fiy = 0.0, fiz = 0.0, U = 0.0, W = 0.0;
-    for (int K = tk.J; K < nb; ++K) {
-        __syncthreads();  // every read of the previous block K is done
-        for (int e = tid; e < 3 * kDirBlock; e += kDirThreads) {
-            const int c = e / kDirBlock, slot = e % kDirBlock;
-            const int idx = K * kDirBlock + slot;
-            sx[2][c][slot] = idx < n ? a.x[3 * (p0 + idx) + c] : 0.0;
-        }
-        __syncthreads();
+    {
+        const int K = tk.K;
         double kx = 0.0, ky = 0.0, kz = 0.0;  // F of k-slot `lane` of block K
         for (int jj = wave; jj < kDirBlock; jj += 4) {
             const int j = tk.J * kDirBlock + jj;
@@ -147,7 +141,7 @@ __global__ void __launch_bounds__(kDirThreads) k_direct_triplet(DirectArgs a) {
         if (tid < 3 * kDirBlock) {
             const int c = tid / kDirBlock, slot = tid % kDirBlock;
             const double r = ((red[0][c][slot] + red[1][c][slot]) + red[2][c][slot]) + red[3][c][slot];
-            a.pK[(tk.koff + (K - tk.J)) * 3 * kDirBlock + tid] = r;
+            a.pK[(int64_t)blockIdx.x * 3 * kDirBlock + tid] = r;
         }
     }
     __syncthreads();
@@ -176,9 +170,9 @@ __global__ void __launch_bounds__(kDirThreads) k_direct_triplet(DirectArgs a) {
 }
 
 // F3 of every particle of block X of system s (one workgroup per block): the slots that
-// hold contributions to it -- tasks (X, J) as I, tasks (I, X) as J, tasks (I, J <= X) as
-// K -- summed in a fixed order: each wave takes every fourth slot, the four wave sums are
-// added in wave order.
+// hold contributions to it -- tasks (X, J, K) as I, (I, X, K) as J, (I, J, X) as K --
+// summed in a fixed order: wave w takes every fourth slot of that sequence, the four wave
+// sums are added in wave order.
 __global__ void __launch_bounds__(kDirThreads) k_direct_gather(DirectArgs a, double *f) {
     __shared__ double red[4][3][kDirBlock];
     const int s = a.blk_sys[blockIdx.x];
@@ -187,29 +181,21 @@ __global__ void __launch_bounds__(kDirThreads) k_direct_gather(DirectArgs a, dou
     const int nb = (n + kDirBlock - 1) / kDirBlock;
     const int X = (int)blockIdx.x - a.blk0[s];
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
-    const int *tid_of = a.task_of + a.task_of0[s];  // [nb][nb], I <= J
+    const int *tof = a.task_of + a.task_of0[s];  // [nb][nb][nb], I <= J <= K
     double acc[3] = {0.0, 0.0, 0.0};
-    // terms: J = X..nb-1 (role I), I = 0..X (role J), then (I, J) with I <= J <= X (role K)
-    const int nI = nb - X, nJ = X + 1, nK = (X + 1) * (X + 2) / 2;
-    for (int q = wave; q < nI + nJ + nK; q += 4) {
-        const double *src;
-        if (q < nI) {
-            src = a.pI + (int64_t)tid_of[X * nb + X + q] * 3 * kDirBlock;
-        } else if (q < nI + nJ) {
-            src = a.pJ + (int64_t)tid_of[(q - nI) * nb + X] * 3 * kDirBlock;
-        } else {
-            // the r-th pair (I, J) with I <= J <= X, in J-major order
-            const int r = q - nI - nJ;
-            int J = (int)((sqrt(8.0 * r + 1.0) - 1.0) * 0.5);
-            while ((J + 1) * (J + 2) / 2 <= r) ++J;
-            while (J * (J + 1) / 2 > r) --J;
-            const int I = r - J * (J + 1) / 2;
-            const DirectTask &t = a.task[tid_of[I * nb + J]];
-            src = a.pK + (t.koff + (X - J)) * 3 * kDirBlock;
-        }
+    int q = 0;
+    auto add = [&](const double *slots, int task) {
+        if ((q++ & 3) != wave) return;  // wave-uniform
+        const double *src = slots + (int64_t)task * 3 * kDirBlock;
 #pragma unroll
         for (int c = 0; c < 3; ++c) acc[c] += src[c * kDirBlock + lane];
-    }
+    };
+    for (int J = X; J < nb; ++J)
+        for (int K = J; K < nb; ++K) add(a.pI, tof[((int64_t)X * nb + J) * nb + K]);
+    for (int I = 0; I <= X; ++I)
+        for (int K = X; K < nb; ++K) add(a.pJ, tof[((int64_t)I * nb + X) * nb + K]);
+    for (int J = 0; J <= X; ++J)
+        for (int I = 0; I <= J; ++I) add(a.pK, tof[((int64_t)I * nb + J) * nb + X]);
 #pragma unroll
     for (int c = 0; c < 3; ++c) red[wave][c][lane] = acc[c];
     __syncthreads();

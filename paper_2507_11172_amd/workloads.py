@@ -172,6 +172,7 @@ class Workload:
     k: int = 1
     n_iter: int = 100
     precision: str = "fp64"
+    method: str = "cutoff"   # "direct": DirectSum, no cutoff, open boundaries
 
     @property
     def n_systems(self) -> int:
@@ -263,7 +264,7 @@ def toy(nu: float = 0.073, n_particles: int = 675, length: float = 10.0, tempera
     rng = rng_for(seed)
     x, box = open_cluster(n_particles, length, 0.05, rng)
     return _single("toy%d_nu%.3g" % (n_particles, nu), x, box, temperature, rng, nu=nu, k=1,
-                   n_iter=1200)
+                   n_iter=1200, method="direct")
 
 
 def aluminium(seed: int = 1007) -> Workload:
@@ -273,7 +274,8 @@ def aluminium(seed: int = 1007) -> Workload:
     rng = rng_for(seed)
     n, length = 4995, 20.0
     x, box = open_cluster(n, length, 0.05, rng)
-    return _single("al4995", x, box, 1.1, rng, nu=0.3095, dt=0.00304, k=12, n_iter=24000)
+    return _single("al4995", x, box, 1.1, rng, nu=0.3095, dt=0.00304, k=12, n_iter=24000,
+                   method="direct")
 
 
 def perfect_fcc(n_cells: int, density: float = 0.8):
