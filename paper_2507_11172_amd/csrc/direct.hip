@@ -94,37 +94,49 @@ __global__ void __launch_bounds__(kDirThreads) k_direct_triplet(DirectArgs a) {
             const int j = tk.J * kDirBlock + jj;
             if (j >= n) break;  // wave-uniform
             const double xj = sx[1][0][jj], yj = sx[1][1][jj], zj = sx[1][2][jj];
-            const T ux = (T)(xj - xi), uy = (T)(yj - yi), uz = (T)(zj - zi);
+            const double dux = xj - xi, duy = yj - yi, duz = zj - zi;
+            const T ux = (T)dux, uy = (T)duy, uz = (T)duz;
             const T aa = fma(uz, uz, fma(uy, uy, ux * ux));
             const bool ij = iv && i < j;
-            double jx = 0.0, jy = 0.0, jz = 0.0;
+            // over the 64 steps: F_i = (sum g_a) u + sum g_b w, F_j = -(sum g_a) u + sum g_c v
+            double sga = 0.0, bwx = 0.0, bwy = 0.0, bwz = 0.0, cvx = 0.0, cvy = 0.0, cvz = 0.0;
             for (int t = 0; t < kDirBlock; ++t) {
                 const int ks = (lane + t) & (kDirBlock - 1);
                 const int k = K * kDirBlock + ks;
                 const bool ok = ij && j < k && k < n;
                 const double xk = sx[2][0][ks], yk = sx[2][1][ks], zk = sx[2][2][ks];
-                const T wx = (T)(xk - xi), wy = (T)(yk - yi), wz = (T)(zk - zi);
-                const T vx = (T)(xk - xj), vy = (T)(yk - yj), vz = (T)(zk - zj);
+                const double dwx = xk - xi, dwy = yk - yi, dwz = zk - zi;
+                const double dvx = xk - xj, dvy = yk - yj, dvz = zk - zj;
+                const T wx = (T)dwx, wy = (T)dwy, wz = (T)dwz;
+                const T vx = (T)dvx, vy = (T)dvy, vz = (T)dvz;
                 const T bb = fma(wz, wz, fma(wy, wy, wx * wx));
                 const T cc = fma(vz, vz, fma(vy, vy, vx * vx));
                 T phi, ga, gb, gc;
                 datm<T>(aa, bb, cc, nu, phi, ga, gb, gc);
-                const T f1x = fma(ga, ux, gb * wx), f1y = fma(ga, uy, gb * wy), f1z = fma(ga, uz, gb * wz);
-                const T f2x = fma(gc, vx, -ga * ux), f2y = fma(gc, vy, -ga * uy), f2z = fma(gc, vz, -ga * uz);
-                // invalid triplets (masked) may be non-finite: select, never multiply
-                const double ax = ok ? (double)f1x : 0.0, ay = ok ? (double)f1y : 0.0, az = ok ? (double)f1z : 0.0;
-                const double bx = ok ? (double)f2x : 0.0, by = ok ? (double)f2y : 0.0, bz = ok ? (double)f2z : 0.0;
-                fix += ax; fiy += ay; fiz += az;
-                jx += bx; jy += by; jz += bz;
+                // masked triplets (i = j, j = k, padding) may be non-finite: select, never
+                // multiply; zero coefficients then zero every force term
+                ga = ok ? ga : T(0);
+                gb = ok ? gb : T(0);
+                gc = ok ? gc : T(0);
+                const double dga = (double)ga, dgb = (double)gb, dgc = (double)gc;
+                sga += dga;
+                bwx = fma(dgb, dwx, bwx); bwy = fma(dgb, dwy, bwy); bwz = fma(dgb, dwz, bwz);
+                cvx = fma(dgc, dvx, cvx); cvy = fma(dgc, dvy, cvy); cvz = fma(dgc, dvz, cvz);
+                // F_k = -g_b w - g_c v, summed in the register of lane k-slot
+                const T fkx = -fma(gb, wx, gc * vx), fky = -fma(gb, wy, gc * vy), fkz = -fma(gb, wz, gc * vz);
                 const int src = (lane - t) & (kDirBlock - 1);
-                kx += __shfl(-(ax + bx), src);
-                ky += __shfl(-(ay + by), src);
-                kz += __shfl(-(az + bz), src);
+                kx += (double)__shfl(fkx, src);
+                ky += (double)__shfl(fky, src);
+                kz += (double)__shfl(fkz, src);
                 if (ENERGY) {
                     U += ok ? (double)phi : 0.0;
-                    W += ok ? -(double)fma(aa, ga, fma(bb, gb, cc * gc)) : 0.0;
+                    W -= (double)fma(aa, ga, fma(bb, gb, cc * gc));
                 }
             }
+            fix = fma(sga, dux, fix + bwx);
+            fiy = fma(sga, duy, fiy + bwy);
+            fiz = fma(sga, duz, fiz + bwz);
+            double jx = fma(-sga, dux, cvx), jy = fma(-sga, duy, cvy), jz = fma(-sga, duz, cvz);
             jx = dwave_sum(jx);
             jy = dwave_sum(jy);
             jz = dwave_sum(jz);
