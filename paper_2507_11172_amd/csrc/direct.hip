@@ -25,7 +25,7 @@ namespace mts {
 
 constexpr int kDirThreads = 4 * kWave;
 
-// ATM terms as in the cutoff kernel (law-of-cosines form): phi and g_a = 2 dphi/da etc.
+// 1/sqrt(x): the hardware estimate, refined by two Newton-Raphson steps in FP64.
 template <typename T>
 __device__ __forceinline__ T drsqrt(T x);
 template <>
@@ -39,23 +39,27 @@ __device__ __forceinline__ double drsqrt<double>(double x) {
 template <>
 __device__ __forceinline__ float drsqrt<float>(float x) { return __builtin_amdgcn_rsqf(x); }
 
+// The same terms as the cutoff kernel's (law-of-cosines form), rearranged for fewer
+// operations: phi and g_a = 2 dphi/da, g_b, g_c with the factor 2 nu folded into the
+// coefficients, the edge products shared, and t_1..t_3 from s = a + b + c.
 template <typename T>
 __device__ __forceinline__ void datm(T a, T b, T c, T nu, T &phi, T &ga, T &gb, T &gc) {
-    const T P = a * b * c;
-    const T rs = drsqrt<T>(P);
-    const T ip = rs * rs;
-    const T p32 = rs * ip;
-    const T p52 = p32 * ip;
-    const T t1 = a + b - c, t2 = a - b + c, t3 = b + c - a;
-    const T tt = t1 * t2 * t3;
-    const T q = T(0.375) * p52;
-    const T K = fma(T(-0.9375) * tt, p52, T(-1.5) * p32);
-    const T Kp = K * ip;
-    const T two_nu = T(2) * nu;
-    ga = two_nu * fma(Kp, b * c, q * fma(T(2) * a, t3, -t1 * t2));
-    gb = two_nu * fma(Kp, a * c, q * fma(T(2) * b, t2, -t1 * t3));
-    gc = two_nu * fma(Kp, a * b, q * fma(T(2) * c, t1, -t2 * t3));
-    phi = nu * fma(q, tt, p32);
+    const T ab = a * b, bc = b * c, ac = a * c;
+    const T P = ab * c;
+    const T rs = drsqrt<T>(P);         // P^-1/2
+    const T ip = rs * rs;              // P^-1
+    const T p32 = rs * ip;             // P^-3/2
+    const T p52 = p32 * ip;            // P^-5/2
+    const T sum = (a + b) + c;
+    const T t1 = fma(T(-2), c, sum), t2 = fma(T(-2), b, sum), t3 = fma(T(-2), a, sum);
+    const T t12 = t1 * t2;
+    const T tt = t12 * t3;
+    const T q2 = (T(0.75) * nu) * p52;                                  // 2 nu (3/8) P^-5/2
+    const T kp = fma((T(-1.875) * nu) * tt, p52, (T(-3) * nu) * p32) * ip;  // 2 nu K / P
+    ga = fma(kp, bc, q2 * fma(a + a, t3, -t12));
+    gb = fma(kp, ac, q2 * fma(b + b, t2, -(t1 * t3)));
+    gc = fma(kp, ab, q2 * fma(c + c, t1, -(t2 * t3)));
+    phi = fma(T(0.5) * q2, tt, nu * p32);
 }
 
 __device__ __forceinline__ double dwave_sum(double v) {
@@ -122,12 +126,12 @@ __global__ void __launch_bounds__(kDirThreads) k_direct_triplet(DirectArgs a) {
                 sga += dga;
                 bwx = fma(dgb, dwx, bwx); bwy = fma(dgb, dwy, bwy); bwz = fma(dgb, dwz, bwz);
                 cvx = fma(dgc, dvx, cvx); cvy = fma(dgc, dvy, cvy); cvz = fma(dgc, dvz, cvz);
-                // F_k = -g_b w - g_c v, summed in the register of lane k-slot
-                const T fkx = -fma(gb, wx, gc * vx), fky = -fma(gb, wy, gc * vy), fkz = -fma(gb, wz, gc * vz);
+                // F_k = -(g_b w + g_c v), summed in the register of lane k-slot
+                const T fkx = fma(gb, wx, gc * vx), fky = fma(gb, wy, gc * vy), fkz = fma(gb, wz, gc * vz);
                 const int src = (lane - t) & (kDirBlock - 1);
-                kx += (double)__shfl(fkx, src);
-                ky += (double)__shfl(fky, src);
-                kz += (double)__shfl(fkz, src);
+                kx -= (double)__shfl(fkx, src);
+                ky -= (double)__shfl(fky, src);
+                kz -= (double)__shfl(fkz, src);
                 if (ENERGY) {
                     U += ok ? (double)phi : 0.0;
                     W -= (double)fma(aa, ga, fma(bb, gb, cc * gc));
