@@ -19,48 +19,12 @@
 //    order.  Results are bitwise reproducible.
 // Block triples with I = J or J = K mask the triplets that are not i < j < k.  Positions
 // are FP64; T is the precision of the ATM arithmetic; forces accumulate in FP64.
+#include "atm.h"
 #include "common.h"
 
 namespace mts {
 
 constexpr int kDirThreads = 4 * kWave;
-
-// 1/sqrt(x): the hardware estimate, refined by two Newton-Raphson steps in FP64.
-template <typename T>
-__device__ __forceinline__ T drsqrt(T x);
-template <>
-__device__ __forceinline__ double drsqrt<double>(double x) {
-    double y = __builtin_amdgcn_rsq(x);
-    const double h = 0.5 * x;
-    y = y * fma(-h * y, y, 1.5);
-    y = y * fma(-h * y, y, 1.5);
-    return y;
-}
-template <>
-__device__ __forceinline__ float drsqrt<float>(float x) { return __builtin_amdgcn_rsqf(x); }
-
-// The same terms as the cutoff kernel's (law-of-cosines form), rearranged for fewer
-// operations: phi and g_a = 2 dphi/da, g_b, g_c with the factor 2 nu folded into the
-// coefficients, the edge products shared, and t_1..t_3 from s = a + b + c.
-template <typename T>
-__device__ __forceinline__ void datm(T a, T b, T c, T nu, T &phi, T &ga, T &gb, T &gc) {
-    const T ab = a * b, bc = b * c, ac = a * c;
-    const T P = ab * c;
-    const T rs = drsqrt<T>(P);         // P^-1/2
-    const T ip = rs * rs;              // P^-1
-    const T p32 = rs * ip;             // P^-3/2
-    const T p52 = p32 * ip;            // P^-5/2
-    const T sum = (a + b) + c;
-    const T t1 = fma(T(-2), c, sum), t2 = fma(T(-2), b, sum), t3 = fma(T(-2), a, sum);
-    const T t12 = t1 * t2;
-    const T tt = t12 * t3;
-    const T q2 = (T(0.75) * nu) * p52;                                  // 2 nu (3/8) P^-5/2
-    const T kp = fma((T(-1.875) * nu) * tt, p52, (T(-3) * nu) * p32) * ip;  // 2 nu K / P
-    ga = fma(kp, bc, q2 * fma(a + a, t3, -t12));
-    gb = fma(kp, ac, q2 * fma(b + b, t2, -(t1 * t3)));
-    gc = fma(kp, ab, q2 * fma(c + c, t1, -(t2 * t3)));
-    phi = fma(T(0.5) * q2, tt, nu * p32);
-}
 
 __device__ __forceinline__ double dwave_sum(double v) {
 #pragma unroll
@@ -116,7 +80,7 @@ __global__ void __launch_bounds__(kDirThreads) k_direct_triplet(DirectArgs a) {
                 const T bb = fma(wz, wz, fma(wy, wy, wx * wx));
                 const T cc = fma(vz, vz, fma(vy, vy, vx * vx));
                 T phi, ga, gb, gc;
-                datm<T>(aa, bb, cc, nu, phi, ga, gb, gc);
+                atm_terms<T>(aa, bb, cc, nu, phi, ga, gb, gc);
                 // masked triplets (i = j, j = k, padding) may be non-finite: select, never
                 // multiply; zero coefficients then zero every force term
                 ga = ok ? ga : T(0);

@@ -42,6 +42,7 @@
 // arrays are structure-of-arrays so that consecutive lanes touch consecutive banks.
 #include <algorithm>
 
+#include "atm.h"
 #include "common.h"
 #include "list_build.h"
 
@@ -153,49 +154,6 @@ __device__ __forceinline__ void carve(unsigned char *raw, int cap, int lc, int w
 // certain misses (above) and the rare ambiguous cases, which are settled by the canonical
 // FP64 test: the triplet set is exactly the FP64 one.
 constexpr float kPrefilterBand = 1e-5f;
-
-// 1/sqrt(x): hardware estimate refined by two Newton-Raphson steps y <- y (3 - x y^2)/2
-// (quadratic convergence from the ~2^-22 estimate to below one FP64 ulp of error).
-__device__ __forceinline__ double rsqrt_nr(double x) {
-    double y = __builtin_amdgcn_rsq(x);
-    const double h = 0.5 * x;
-    y = y * fma(-h * y, y, 1.5);
-    y = y * fma(-h * y, y, 1.5);
-    return y;
-}
-
-template <typename T>
-__device__ __forceinline__ T rsqrt_t(T x);
-template <>
-__device__ __forceinline__ double rsqrt_t<double>(double x) { return rsqrt_nr(x); }
-template <>
-__device__ __forceinline__ float rsqrt_t<float>(float x) { return __builtin_amdgcn_rsqf(x); }
-
-// ATM potential in squared edge lengths a = |u|^2, b = |w|^2, c = |v|^2 (u: anchor->j,
-// w: anchor->k, v: j->k).  By the law of cosines the cosine product of Sec. 2.1 is
-// t1 t2 t3 / (8abc), t1 = a+b-c, t2 = a-b+c, t3 = b+c-a, so
-//   phi = nu [P^-3/2 + 3/8 T P^-5/2],  P = abc,  T = t1 t2 t3.
-// Returns phi and g_a = 2 dphi/da, g_b, g_c; the forces are
-//   F_anchor = g_a u + g_b w,  F_j = -g_a u + g_c v,  F_k = -g_b w - g_c v,
-// and the triplet's virial sum_x x.F = u.F_j + w.F_k = -(a g_a + b g_b + c g_c).
-template <typename T>
-__device__ __forceinline__ void atm_terms(T a, T b, T c, T nu, T &phi, T &ga, T &gb, T &gc) {
-    const T P = a * b * c;
-    const T rs = rsqrt_t<T>(P);       // P^-1/2
-    const T ip = rs * rs;             // P^-1
-    const T p32 = rs * ip;            // P^-3/2
-    const T p52 = p32 * ip;           // P^-5/2
-    const T t1 = a + b - c, t2 = a - b + c, t3 = b + c - a;
-    const T tt = t1 * t2 * t3;
-    const T q = T(0.375) * p52;
-    const T K = fma(T(-0.9375) * tt, p52, T(-1.5) * p32);
-    const T Kp = K * ip;              // K / P;  K/a = Kp * b * c
-    const T two_nu = T(2) * nu;
-    ga = two_nu * fma(Kp, b * c, q * fma(T(2) * a, t3, -t1 * t2));
-    gb = two_nu * fma(Kp, a * c, q * fma(T(2) * b, t2, -t1 * t3));
-    gc = two_nu * fma(Kp, a * b, q * fma(T(2) * c, t1, -t2 * t3));
-    phi = nu * fma(q, tt, p32);
-}
 
 // One queued triplet (anchor, j, k): forces on all three members (j and k as list
 // partials, the anchor's in the caller's registers), energy and virial.
