@@ -256,6 +256,48 @@ def _cpu_baseline_direct(w, k: int, nthreads: int):
             "triplets_per_s": rate}
 
 
+def rvite_sweep(nus, ks, n_iter: int, precision: str):
+    """RVITE (Eq. 4) of the toy scenario (675 particles in a 10^3 domain, DirectSum, the
+    same seeded initial state for every run) for each nu and step-size factor: n_iter inner
+    steps of r-RESPA with energy records at every full step."""
+    import numpy as np
+    import torch
+    from paper_2507_11172_amd import mts, workloads as W
+
+    dev = torch.device("cuda:0")
+    bad = [k for k in ks if n_iter % k]
+    if bad:
+        raise SystemExit("--sweep-iter %d is not a multiple of %s" % (n_iter, bad))
+    table, seconds = {}, 0.0
+    for nu in nus:
+        w = W.toy(nu=nu)
+        row = {}
+        for k in ks:
+            with mts.System(_params(w, precision, k), w.n_particles.tolist(), w.box) as s:
+                x = torch.tensor(w.x, dtype=torch.float64, device=dev)
+                v = torch.tensor(w.v, dtype=torch.float64, device=dev)
+                e = torch.zeros((n_iter // k + 1, 1, mts.MTS_NE), dtype=torch.float64, device=dev)
+                t0 = time.perf_counter()
+                s.respa_step(x, v, n_iter, e)
+                s.sync()
+                seconds += time.perf_counter() - t0
+            en = e.cpu().numpy()
+            _, rv = _drift_stats(en, w.n_particles)
+            row[str(k)] = rv
+        table["%g" % nu] = row
+        print("nu %g: %s" % (nu, " ".join("k%s=%.3e" % kv for kv in row.items())),
+              file=sys.stderr, flush=True)
+    # trend of RVITE with nu for each factor: slope of log(RVITE) against nu
+    trend = {}
+    for k in ks:
+        y = np.log([table["%g" % nu][str(k)] for nu in nus])
+        trend[str(k)] = float(np.polyfit(nus, y, 1)[0]) if len(nus) > 1 else 0.0
+    return {"experiment": "RVITE vs nu and step-size factor, toy scenario (Sec. 4.2.1)",
+            "method": "direct", "n_particles": 675, "box": 10.0, "dt": W.DT,
+            "n_iter": n_iter, "precision": precision, "rvite": table,
+            "dlogRVITE_dnu": trend, "gpu_seconds": seconds, "data": "synthetic"}
+
+
 def traffic_probe(w, precision: str, k: int, tune_ms: int):
     """For HBM counter runs (FETCH_SIZE / WRITE_SIZE): four outer cycles of the tuned
     r-RESPA loop with energy records (the triplet launch of the timed region, once per
@@ -299,12 +341,25 @@ def main(argv=None):
                     help="only run the kernels of the HBM counter runs, print no bench line")
     ap.add_argument("--loop-steps", type=int, default=5,
                     help="cycles of the one-handle-per-replica loop (batched workload)")
+    ap.add_argument("--rvite-sweep", action="store_true",
+                    help="the toy scenario's RVITE study (Sec. 4.2.1) on DirectSum instead of "
+                         "the bench line: one JSON line with RVITE per nu and step-size factor")
+    ap.add_argument("--sweep-nu", default="0.05,0.1,0.2,0.3,0.5,0.7,1.0")
+    ap.add_argument("--sweep-k", default="1,2,3,4,6,8,12")
+    ap.add_argument("--sweep-iter", type=int, default=24000,
+                    help="inner steps per run (a multiple of every factor)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
               "(requested --gpus %d)" % args.gpus, file=sys.stderr)
         return 2
 
+    if args.rvite_sweep:
+        nus = [float(v) for v in args.sweep_nu.split(",")]
+        ks = [int(v) for v in args.sweep_k.split(",")]
+        print(json.dumps(rvite_sweep(nus, ks, args.sweep_iter, args.precision or "fp64")),
+              flush=True)
+        return 0
     w = _workload(args.workload)
     k = args.k or w.k
     precision = args.precision or w.precision

@@ -79,12 +79,11 @@ struct Layout {
 
 // DirectSum mode: the task list of the all-triplets kernel and its partial-force slots.
 struct DirectState {
-    int ntask = 0, nblk = 0, npblk = 0;
+    int ntask = 0, nblk = 0;
     DirectTask *task = nullptr;   // [ntask]
     double *pI = nullptr, *pJ = nullptr, *pK = nullptr;  // partial force slots
     double *ce = nullptr;         // [ntask][2] ATM energy and virial per task
     int *blk_sys = nullptr, *blk0 = nullptr;    // 64-particle blocks (gather)
-    int *pblk_sys = nullptr, *pblk0 = nullptr;  // 256-particle blocks (pairs)
     int *task_of = nullptr;       // per system [nb][nb]
     int64_t *task_of0 = nullptr;
     SysDesc *sd = nullptr;        // p0, n; cell0/ncell = the system's task range
@@ -471,19 +470,18 @@ mts_status set_layout(mts_system *s, const Config &cfg) {
 }
 
 void free_direct(DirectState &d) {
-    void *ptrs[] = {d.task, d.pI, d.pJ, d.pK, d.ce, d.blk_sys, d.blk0, d.pblk_sys, d.pblk0,
-                    d.task_of, d.task_of0, d.sd};
+    void *ptrs[] = {d.task, d.pI, d.pJ, d.pK, d.ce, d.blk_sys, d.blk0, d.task_of, d.task_of0, d.sd};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     d = DirectState{};
 }
 
 // DirectSum set-up: per system, the block triples (I <= J <= K) of 64-particle blocks,
-// the lookup table of task indices, and the block tables of the gather and pair kernels.
+// the lookup table of task indices, and the block table of the gather kernel.
 mts_status setup_direct(mts_system *s) {
     DirectState &D = s->dir;
     std::vector<DirectTask> tasks;
-    std::vector<int> blk_sys, blk0(s->nsys), pblk_sys, pblk0(s->nsys), task_of;
+    std::vector<int> blk_sys, blk0(s->nsys), task_of;
     std::vector<int64_t> task_of0(s->nsys);
     std::vector<SysDesc> sd = s->base;
     for (int q = 0; q < s->nsys; ++q) {
@@ -501,13 +499,10 @@ mts_status setup_direct(mts_system *s) {
         sd[q].ncell = (int)tasks.size() - sd[q].cell0;
         blk0[q] = (int)blk_sys.size();
         for (int b = 0; b < nb; ++b) blk_sys.push_back(q);
-        pblk0[q] = (int)pblk_sys.size();
-        for (int b = 0; b < (n + 255) / 256; ++b) pblk_sys.push_back(q);
     }
     if (tasks.size() >= (size_t)1 << 31) return fail(s, MTS_ERR_UNSUPPORTED, "too many particles for DirectSum");
     D.ntask = (int)tasks.size();
     D.nblk = (int)blk_sys.size();
-    D.npblk = (int)pblk_sys.size();
     const size_t slot = 3 * kDirBlock;
     HIP_TRY(s, dalloc(&D.task, tasks.size()));
     HIP_TRY(s, dalloc(&D.pI, tasks.size() * slot));
@@ -516,8 +511,6 @@ mts_status setup_direct(mts_system *s) {
     HIP_TRY(s, dalloc(&D.ce, 2 * tasks.size()));
     HIP_TRY(s, dalloc(&D.blk_sys, blk_sys.size()));
     HIP_TRY(s, dalloc(&D.blk0, blk0.size()));
-    HIP_TRY(s, dalloc(&D.pblk_sys, pblk_sys.size()));
-    HIP_TRY(s, dalloc(&D.pblk0, pblk0.size()));
     HIP_TRY(s, dalloc(&D.task_of, task_of.size()));
     HIP_TRY(s, dalloc(&D.task_of0, task_of0.size()));
     HIP_TRY(s, dalloc(&D.sd, sd.size()));
@@ -527,8 +520,6 @@ mts_status setup_direct(mts_system *s) {
     HIP_TRY(s, up(D.task, tasks.data(), sizeof(DirectTask) * tasks.size()));
     HIP_TRY(s, up(D.blk_sys, blk_sys.data(), sizeof(int) * blk_sys.size()));
     HIP_TRY(s, up(D.blk0, blk0.data(), sizeof(int) * blk0.size()));
-    HIP_TRY(s, up(D.pblk_sys, pblk_sys.data(), sizeof(int) * pblk_sys.size()));
-    HIP_TRY(s, up(D.pblk0, pblk0.data(), sizeof(int) * pblk0.size()));
     HIP_TRY(s, up(D.task_of, task_of.data(), sizeof(int) * task_of.size()));
     HIP_TRY(s, up(D.task_of0, task_of0.data(), sizeof(int64_t) * task_of0.size()));
     HIP_TRY(s, up(D.sd, sd.data(), sizeof(SysDesc) * sd.size()));
@@ -780,9 +771,8 @@ mts_status enqueue_triplet_and_list(mts_system *s, bool energy) {
 // as kernel class 1.
 mts_status enqueue_direct_pair(mts_system *s, const double *x, double *f2, bool energy) {
     DirectPairArgs a{};
-    a.nblk = s->dir.npblk;
-    a.blk_sys = s->dir.pblk_sys;
-    a.blk0 = s->dir.pblk0;
+    a.n = s->n;
+    a.sys_of = s->sys_of;
     a.sd = s->dir.sd;
     a.x = x;
     a.f = f2;

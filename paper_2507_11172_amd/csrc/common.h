@@ -389,8 +389,8 @@ struct DirectArgs {
 hipError_t launch_direct_triplet(hipStream_t st, const DirectArgs &a, bool fp32, bool energy);
 hipError_t launch_direct_gather(hipStream_t st, const DirectArgs &a, double *f);
 struct DirectPairArgs {
-    int nblk;                // 256-particle blocks over all systems
-    const int *blk_sys, *blk0;
+    int64_t n;               // particles over all systems (one wave each)
+    const int *sys_of;       // [n] system of each particle
     const SysDesc *sd;
     const double *x;
     double *f;               // [N][3]

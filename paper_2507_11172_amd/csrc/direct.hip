@@ -195,47 +195,48 @@ __global__ void __launch_bounds__(kDirThreads) k_direct_gather(DirectArgs a, dou
     }
 }
 
-// LJ forces of every pair (no cutoff, no images): each particle gathers its own force
-// over all others of its system (no scatter, fixed order), 256 particles per workgroup
-// against tiles of 256 staged in LDS.  pe receives half of each pair's energy and virial.
+// LJ forces of every pair (no cutoff, no images): one wave per particle gathers its own
+// force over all others of its system, lane l taking j = l, l + 64, ... (coalesced reads),
+// then a butterfly sum in fixed order -- no scatter, bitwise reproducible, and one wave
+// per particle fills the chip from a few hundred particles on.  pe receives half of each
+// pair's energy and virial.
 template <typename T, bool ENERGY>
 __global__ void __launch_bounds__(kDirThreads) k_direct_pair(DirectPairArgs a) {
-    __shared__ double tx[3][kDirThreads];
-    const int s = a.blk_sys[blockIdx.x];
-    const SysDesc &d = a.sd[s];
+    const int64_t p = ((int64_t)blockIdx.x * kDirThreads + threadIdx.x) / kWave;
+    const int lane = threadIdx.x % kWave;
+    if (p >= a.n) return;  // whole waves
+    const SysDesc &d = a.sd[a.sys_of[p]];
     const int n = (int)d.n;
-    const int i = ((int)blockIdx.x - a.blk0[s]) * kDirThreads + (int)threadIdx.x;
-    const bool iv = i < n;
-    const int64_t p = d.p0 + (iv ? i : 0);
-    const double xi = iv ? a.x[3 * p] : 0.0, yi = iv ? a.x[3 * p + 1] : 0.0,
-                 zi = iv ? a.x[3 * p + 2] : 0.0;
+    const int i = (int)(p - d.p0);
+    const double xi = a.x[3 * p], yi = a.x[3 * p + 1], zi = a.x[3 * p + 2];
     const T sigma2 = (T)a.sigma2, eps24 = (T)(24.0 * a.eps), eps4 = (T)(4.0 * a.eps);
     double fx = 0.0, fy = 0.0, fz = 0.0, u = 0.0, w = 0.0;
-    for (int j0 = 0; j0 < n; j0 += kDirThreads) {
-        __syncthreads();
-        const int jl = j0 + (int)threadIdx.x;
-        for (int c = 0; c < 3; ++c) tx[c][threadIdx.x] = jl < n ? a.x[3 * (d.p0 + jl) + c] : 0.0;
-        __syncthreads();
-        const int m = min(kDirThreads, n - j0);
-        for (int t = 0; t < m; ++t) {
-            const T dx = (T)(tx[0][t] - xi), dy = (T)(tx[1][t] - yi), dz = (T)(tx[2][t] - zi);
-            const T r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-            const T inv = T(1) / r2;
-            const T s2 = sigma2 * inv;
-            const T s6 = s2 * s2 * s2;
-            const T s12 = s6 * s6;
-            const T fr = eps24 * fma(T(2), s12, -s6) * inv;
-            const bool ok = iv && j0 + t != i;
-            fx -= ok ? (double)(fr * dx) : 0.0;
-            fy -= ok ? (double)(fr * dy) : 0.0;
-            fz -= ok ? (double)(fr * dz) : 0.0;
-            if (ENERGY) {
-                u += ok ? (double)(eps4 * (s12 - s6)) : 0.0;
-                w += ok ? (double)(fr * r2) : 0.0;
-            }
+    for (int j = lane; j < n; j += kWave) {
+        const int64_t q = d.p0 + j;
+        const T dx = (T)(a.x[3 * q] - xi), dy = (T)(a.x[3 * q + 1] - yi), dz = (T)(a.x[3 * q + 2] - zi);
+        const T r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+        const T inv = T(1) / r2;
+        const T s2 = sigma2 * inv;
+        const T s6 = s2 * s2 * s2;
+        const T s12 = s6 * s6;
+        const T fr = eps24 * fma(T(2), s12, -s6) * inv;
+        const bool ok = j != i;  // the particle itself (r2 = 0) is selected away
+        fx -= ok ? (double)(fr * dx) : 0.0;
+        fy -= ok ? (double)(fr * dy) : 0.0;
+        fz -= ok ? (double)(fr * dz) : 0.0;
+        if (ENERGY) {
+            u += ok ? (double)(eps4 * (s12 - s6)) : 0.0;
+            w += ok ? (double)(fr * r2) : 0.0;
         }
     }
-    if (!iv) return;
+    fx = dwave_sum(fx);
+    fy = dwave_sum(fy);
+    fz = dwave_sum(fz);
+    if (ENERGY) {
+        u = dwave_sum(u);
+        w = dwave_sum(w);
+    }
+    if (lane != 0) return;
     a.f[3 * p] = fx;
     a.f[3 * p + 1] = fy;
     a.f[3 * p + 2] = fz;
@@ -264,14 +265,15 @@ hipError_t launch_direct_gather(hipStream_t st, const DirectArgs &a, double *f) 
 }
 
 hipError_t launch_direct_pair(hipStream_t st, const DirectPairArgs &a, bool fp32) {
-    if (a.nblk <= 0) return hipSuccess;
+    if (a.n <= 0) return hipSuccess;
+    const unsigned blocks = (unsigned)((a.n * kWave + kDirThreads - 1) / kDirThreads);
     const bool energy = a.pe != nullptr;
     if (fp32) {
-        if (energy) k_direct_pair<float, true><<<a.nblk, kDirThreads, 0, st>>>(a);
-        else k_direct_pair<float, false><<<a.nblk, kDirThreads, 0, st>>>(a);
+        if (energy) k_direct_pair<float, true><<<blocks, kDirThreads, 0, st>>>(a);
+        else k_direct_pair<float, false><<<blocks, kDirThreads, 0, st>>>(a);
     } else {
-        if (energy) k_direct_pair<double, true><<<a.nblk, kDirThreads, 0, st>>>(a);
-        else k_direct_pair<double, false><<<a.nblk, kDirThreads, 0, st>>>(a);
+        if (energy) k_direct_pair<double, true><<<blocks, kDirThreads, 0, st>>>(a);
+        else k_direct_pair<double, false><<<blocks, kDirThreads, 0, st>>>(a);
     }
     return hipGetLastError();
 }
