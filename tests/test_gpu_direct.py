@@ -167,3 +167,15 @@ def test_direct_unsupported_calls():
         assert e.value.code == mts.MTS_ERR_UNSUPPORTED
         t = s.autotune(xd, torch.zeros_like(xd), 100)
         assert t["trials"] == 0
+
+
+def test_rvite_sweep_short():
+    """The RVITE study's runner on a short horizon: finite records, and a large step-size
+    factor worse than velocity Verlet at strong three-body coupling."""
+    import bench
+    r = bench.rvite_sweep([0.1, 1.0], [1, 12], 1200, "fp64")
+    t = r["rvite"]
+    for nu in ("0.1", "1"):
+        for k in ("1", "12"):
+            assert math.isfinite(t[nu][k]) and t[nu][k] > 0.0
+    assert t["1"]["12"] > 2.0 * t["1"]["1"]
