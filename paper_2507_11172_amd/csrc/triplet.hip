@@ -61,10 +61,11 @@ __device__ __forceinline__ int below(uint64_t mask) {
                                           __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
 }
 
-// LDS layout.  The hot scans read 16-byte FP32 copies (ds_read_b128 by consecutive
-// lanes, free of bank conflicts); the FP64 entries (32 bytes) are read only for the
-// anchor's candidates and for the rare ambiguous cutoff tests.  Accumulators updated at
-// scattered addresses are structure-of-arrays.
+// LDS layout.  Every array has a 16-byte (or smaller) element, so that consecutive lanes
+// read consecutive 16-byte words (ds_read_b128 free of bank conflicts; a 32-byte stride
+// puts two of every eight lanes on the same banks): the 32-byte FP64 records are stored
+// as two arrays of 16-byte halves.  Accumulators updated at scattered addresses are
+// structure-of-arrays.
 struct PosEnt {                // a staged particle in registers: wrapped FP64 position
     double x, y, z;            // and the image shift (0 or +-L per component) seen from
     double sx, sy, sz;         // the base cell
@@ -101,15 +102,55 @@ __device__ __forceinline__ PosEnt unpack(const TileEnt &t, double L0, double L1,
 }
 
 struct Tile {                  // staged neighbour cells, CAP entries
-    TileEnt *e;                // FP64 (canonical tests, displacements)
+    double2 *exy;              // TileEnt halves: (x, y) and (z, shift code)
+    double2 *ezc;
     float4 *r;                 // FP64 form only: FP32 position relative to the base cell
                                // (prefilter of the anchor lists)
     double *fx, *fy, *fz;      // force accumulators
 };
 
+__device__ __forceinline__ TileEnt tile_get(const Tile &tl, int t) {
+    const double2 a = tl.exy[t], b = tl.ezc[t];
+    TileEnt e;
+    e.x = a.x;
+    e.y = a.y;
+    e.z = b.x;
+    e.code = (int)__double_as_longlong(b.y);
+    e.pad = 0;
+    return e;
+}
+
+__device__ __forceinline__ void tile_set(const Tile &tl, int t, const TileEnt &e) {
+    tl.exy[t] = make_double2(e.x, e.y);
+    tl.ezc[t] = make_double2(e.z, __longlong_as_double((long long)e.code));
+}
+
+// A wave's list entries in the precision of the arithmetic: FP32 entries are one 16-byte
+// array, FP64 entries two arrays of (ux, uy) and (uz, a) halves.
+template <typename T>
+struct ListStore;
+template <>
+struct ListStore<float> {
+    ListEnt<float> *u;
+    __device__ __forceinline__ ListEnt<float> get(int i) const { return u[i]; }
+    __device__ __forceinline__ void set(int i, const ListEnt<float> &e) const { u[i] = e; }
+};
+template <>
+struct ListStore<double> {
+    double2 *uxy, *uza;
+    __device__ __forceinline__ ListEnt<double> get(int i) const {
+        const double2 a = uxy[i], b = uza[i];
+        return ListEnt<double>{a.x, a.y, b.x, b.y};
+    }
+    __device__ __forceinline__ void set(int i, const ListEnt<double> &e) const {
+        uxy[i] = make_double2(e.ux, e.uy);
+        uza[i] = make_double2(e.uz, e.a);
+    }
+};
+
 template <typename T>
 struct List {                  // one wave's forward-neighbour list, LC entries
-    ListEnt<T> *u;             // displacement from the anchor (ATM arithmetic)
+    ListStore<T> u;            // displacement from the anchor (ATM arithmetic)
     ListEnt<float> *f;         // the same in FP32 (j-k prefilter; == u in the FP32 form)
     double *px, *py, *pz;      // partner force partials of the current anchor
     int *t;                    // tile index
@@ -128,14 +169,20 @@ size_t triplet_lds_bytes(int cap, int lcap, bool fp32) {
 template <typename T>
 __device__ __forceinline__ void carve(unsigned char *raw, int cap, int lc, int wave, Tile &tl,
                                       List<T> &L) {
-    tl.e = (TileEnt *)raw;
-    tl.r = sizeof(T) == sizeof(float) ? nullptr : (float4 *)(tl.e + cap);
-    ListEnt<T> *lu = (ListEnt<T> *)(sizeof(T) == sizeof(float) ? (void *)(tl.e + cap) : (void *)(tl.r + cap));
-    L.u = lu + (size_t)wave * lc;
-    ListEnt<float> *lf = (ListEnt<float> *)(lu + (size_t)kTripWaves * lc);
-    if (sizeof(T) == sizeof(float)) {
-        L.f = (ListEnt<float> *)L.u;
+    tl.exy = (double2 *)raw;
+    tl.ezc = tl.exy + cap;
+    tl.r = sizeof(T) == sizeof(float) ? nullptr : (float4 *)(tl.ezc + cap);
+    // list entries: kTripWaves * lc records of sizeof(ListEnt<T>) bytes
+    unsigned char *lu = sizeof(T) == sizeof(float) ? (unsigned char *)(tl.ezc + cap)
+                                                    : (unsigned char *)(tl.r + cap);
+    ListEnt<float> *lf = (ListEnt<float> *)(lu + (size_t)kTripWaves * lc * sizeof(ListEnt<T>));
+    if constexpr (sizeof(T) == sizeof(float)) {
+        L.u.u = (ListEnt<float> *)lu + (size_t)wave * lc;
+        L.f = L.u.u;
     } else {
+        double2 *h = (double2 *)lu;
+        L.u.uxy = h + (size_t)wave * lc;
+        L.u.uza = h + (size_t)kTripWaves * lc + (size_t)wave * lc;
         L.f = lf + (size_t)wave * lc;
         lf += (size_t)kTripWaves * lc;
     }
@@ -261,7 +308,7 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
         te.z = ps.z;
         te.code = code & 0xff;
         te.pad = 0;
-        tile.e[t] = te;
+        tile_set(tile, t, te);
         if constexpr (sizeof(T) != sizeof(float)) {
             const PosEnt e = unpack(te, L0, L1, L2);
             tile.r[t] = make_float4((float)((e.x + e.sx) - ox), (float)((e.y + e.sy) - oy),
@@ -283,7 +330,7 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
     int ntrip = 0;  // wave-uniform
 
     for (int ia = wave; ia < nself; ia += kTripWaves) {
-        const PosEnt an = unpack(tile.e[ia], L0, L1, L2);  // anchor: base cell, zero shift
+        const PosEnt an = unpack(tile_get(tile, ia), L0, L1, L2);  // anchor: base cell, zero shift
         int m = 0;
         if constexpr (sizeof(T) != sizeof(float)) {
             // ---- A1: FP32 prefilter of the tile entries after the anchor (tile order);
@@ -317,7 +364,7 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
             for (int c0 = 0; c0 < mc; c0 += kWave) {
                 const int c = c0 + lane;
                 const int t = c < mc ? L.t[c] : ia;
-                const PosEnt e = unpack(tile.e[t], L0, L1, L2);
+                const PosEnt e = unpack(tile_get(tile, t), L0, L1, L2);
                 const double dx = disp1(an.x, e.x, e.sx), dy = disp1(an.y, e.y, e.sy),
                              dz = disp1(an.z, e.z, e.sz);
                 const double r2 = norm2(dx, dy, dz);
@@ -326,7 +373,7 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
                 const int pos = m + below(mk);
                 __builtin_amdgcn_wave_barrier();  // all reads of this round before the writes
                 if (in) {
-                    L.u[pos] = ListEnt<T>{(T)dx, (T)dy, (T)dz, (T)r2};
+                    L.u.set(pos, ListEnt<T>{(T)dx, (T)dy, (T)dz, (T)r2});
                     L.f[pos] = ListEnt<float>{(float)dx, (float)dy, (float)dz, (float)r2};
                     L.t[pos] = t;
                     L.px[pos] = 0.0;
@@ -340,8 +387,8 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
             // anchor, two per lane per round; ballot + prefix-count compaction keeps tile order
             for (int t0 = ia + 1; t0 < nst; t0 += 2 * kWave) {
                 const int t1 = t0 + lane, t2 = t0 + kWave + lane;
-                const PosEnt e1 = unpack(tile.e[t1 < nst ? t1 : ia], L0, L1, L2);
-                const PosEnt e2 = unpack(tile.e[t2 < nst ? t2 : ia], L0, L1, L2);
+                const PosEnt e1 = unpack(tile_get(tile, t1 < nst ? t1 : ia), L0, L1, L2);
+                const PosEnt e2 = unpack(tile_get(tile, t2 < nst ? t2 : ia), L0, L1, L2);
                 const double x1 = disp1(an.x, e1.x, e1.sx), y1 = disp1(an.y, e1.y, e1.sy),
                              z1 = disp1(an.z, e1.z, e1.sz);
                 const double x2 = disp1(an.x, e2.x, e2.sx), y2 = disp1(an.y, e2.y, e2.sy),
@@ -353,14 +400,14 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
                 const int n1 = __popcll(m1);
                 const int p1 = m + below(m1), p2 = m + n1 + below(m2);
                 if (in1 && p1 < LC) {
-                    L.u[p1] = ListEnt<T>{(T)x1, (T)y1, (T)z1, (T)q1};
+                    L.u.set(p1, ListEnt<T>{(T)x1, (T)y1, (T)z1, (T)q1});
                     L.t[p1] = t1;
                     L.px[p1] = 0.0;
                     L.py[p1] = 0.0;
                     L.pz[p1] = 0.0;
                 }
                 if (in2 && p2 < LC) {
-                    L.u[p2] = ListEnt<T>{(T)x2, (T)y2, (T)z2, (T)q2};
+                    L.u.set(p2, ListEnt<T>{(T)x2, (T)y2, (T)z2, (T)q2});
                     L.t[p2] = t2;
                     L.px[p2] = 0.0;
                     L.py[p2] = 0.0;
@@ -410,7 +457,7 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
             const int e2 = v2 ? Q[(qh + kWave + lane) & kQueueMask] : e1;
             qh += cnt;
             const int j1 = e1 & 0xff, k1 = e1 >> 8, j2 = e2 & 0xff, k2 = e2 >> 8;
-            const ListEnt<T> uj1 = L.u[j1], uk1 = L.u[k1], uj2 = L.u[j2], uk2 = L.u[k2];
+            const ListEnt<T> uj1 = L.u.get(j1), uk1 = L.u.get(k1), uj2 = L.u.get(j2), uk2 = L.u.get(k2);
             const AtmOut<T> o1 = atm_triplet<T>(uj1, uk1, nu);
             const AtmOut<T> o2 = atm_triplet<T>(uj2, uk2, nu);
             fax += v1 ? (double)o1.fix : 0.0;
@@ -463,8 +510,8 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
                     const bool amb2 = c2 && q2 > jk_lo && q2 <= jk_hi;
                     if (__ballot(amb1 || amb2)) {  // rare: settle with the FP64 test
                         if (amb1 || amb2) {
-                            const PosEnt ej = unpack(tile.e[L.t[j]], L0, L1, L2);
-                            const PosEnt ek = unpack(tile.e[L.t[amb1 ? k1 : k2]], L0, L1, L2);
+                            const PosEnt ej = unpack(tile_get(tile, L.t[j]), L0, L1, L2);
+                            const PosEnt ek = unpack(tile_get(tile, L.t[amb1 ? k1 : k2]), L0, L1, L2);
                             const double vx = disp1(ej.x, ek.x, ek.sx - ej.sx);
                             const double vy = disp1(ej.y, ek.y, ek.sy - ej.sy);
                             const double vz = disp1(ej.z, ek.z, ek.sz - ej.sz);
@@ -472,7 +519,7 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
                             if (amb1) hit1 = h;
                             else hit2 = h;
                             if (amb1 && amb2) {
-                                const PosEnt ek2 = unpack(tile.e[L.t[k2]], L0, L1, L2);
+                                const PosEnt ek2 = unpack(tile_get(tile, L.t[k2]), L0, L1, L2);
                                 const double wx = disp1(ej.x, ek2.x, ek2.sx - ej.sx);
                                 const double wy = disp1(ej.y, ek2.y, ek2.sy - ej.sy);
                                 const double wz = disp1(ej.z, ek2.z, ek2.sz - ej.sz);
