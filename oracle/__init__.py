@@ -53,6 +53,11 @@ def lib():
         L.orc_pair.argtypes = [C.c_int64, _D, _D, C.c_double, C.c_double, C.c_double, C.c_int,
                                _D, _D, _I64, C.c_int]
         L.orc_triplet.argtypes = [C.c_int64, _D, _D, C.c_double, C.c_double, _D, _D, _I64, C.c_int]
+        L.orc_triplet_class.argtypes = [C.c_int64, _D, _D, C.c_double, C.c_double, C.c_double,
+                                        _D, _D, _I64, C.c_int]
+        L.orc_respa_nested.argtypes = [C.c_int64, _D, _D, _D, C.POINTER(_MD), C.c_int64, C.c_int,
+                                       C.c_int, C.c_double, _D]
+        L.orc_respa_alg1.argtypes = [C.c_int64, _D, _D, _D, C.POINTER(_MD), C.c_int64, C.c_int, _D]
         L.orc_triplet_list.argtypes = [C.c_int64, _D, _D, C.c_double, _I32, C.c_int64]
         L.orc_triplet_list.restype = C.c_int64
         L.orc_subset.argtypes = [C.c_int64, _D, _D, C.c_double, C.c_double, C.c_double,
@@ -118,14 +123,16 @@ def pair_forces(x, box, eps=1.0, sigma=1.0, rc=2.5, shift=True, nthreads=0) -> F
     return ForceResult(f, float(uw[0]), float(uw[1]), int(cnt.value))
 
 
-def triplet_forces(x, box, nu=0.073, rc=2.5, nthreads=0) -> ForceResult:
+def triplet_forces(x, box, nu=0.073, rc=2.5, r_lo=0.0, nthreads=0) -> ForceResult:
+    """ATM over the triplets with all three edges <= rc; with r_lo > 0 only those whose
+    longest edge exceeds r_lo (the outer distance class (r_lo, rc])."""
     x = _f64(x).reshape(-1, 3)
     box = _f64(box).reshape(3)
     f = np.empty_like(x)
     uw = np.zeros(2)
     cnt = C.c_int64(0)
-    _check(lib().orc_triplet(x.shape[0], _d(x), _d(box), nu, rc, _d(f), _d(uw), C.byref(cnt),
-                             nthreads), "triplet_forces")
+    _check(lib().orc_triplet_class(x.shape[0], _d(x), _d(box), nu, r_lo, rc, _d(f), _d(uw),
+                                   C.byref(cnt), nthreads), "triplet_forces")
     return ForceResult(f, float(uw[0]), float(uw[1]), int(cnt.value))
 
 
@@ -170,6 +177,36 @@ def respa(x, v, box, n_iter, k, eps=1.0, sigma=1.0, rc_pair=2.5, nu=0.073, rc3=2
     p = _md(eps, sigma, rc_pair, nu, rc3, mass, dt, shift, nthreads)
     _check(lib().orc_respa(x.shape[0], _d(x), _d(v), _d(box), C.byref(p), n_iter, k, _d(e)),
            "respa")
+    return x, v, e
+
+
+def respa_nested(x, v, box, n_iter, k, k_outer, r_a, eps=1.0, sigma=1.0, rc_pair=2.5,
+                 nu=0.073, rc3=2.5, mass=1.0, dt=0.001, shift=True, nthreads=0):
+    """Three-level r-RESPA over the triplet distance classes split at r_a: F2 every step,
+    the inner class every k steps, the outer class every k * k_outer steps.  Returns
+    (x, v, e_full[n_iter / (k k_outer) + 1, 5])."""
+    x = _f64(x).reshape(-1, 3).copy()
+    v = _f64(v).reshape(-1, 3).copy()
+    box = _f64(box).reshape(3)
+    span = k * k_outer
+    e = np.zeros((n_iter // span + 1 if span > 0 else 1, 5))
+    p = _md(eps, sigma, rc_pair, nu, rc3, mass, dt, shift, nthreads)
+    _check(lib().orc_respa_nested(x.shape[0], _d(x), _d(v), _d(box), C.byref(p), n_iter, k,
+                                  k_outer, r_a, _d(e)), "respa_nested")
+    return x, v, e
+
+
+def respa_alg1(x, v, box, n_outer, P, eps=1.0, sigma=1.0, rc_pair=2.5, nu=0.073, rc3=2.5,
+               mass=1.0, delta_t=0.004, shift=True, nthreads=0):
+    """Algorithm 1 as printed: full steps delta_t, F2 over P sub-steps, F3 kicks per full
+    step.  Returns (x, v, e[n_outer + 1, 5])."""
+    x = _f64(x).reshape(-1, 3).copy()
+    v = _f64(v).reshape(-1, 3).copy()
+    box = _f64(box).reshape(3)
+    e = np.zeros((n_outer + 1, 5))
+    p = _md(eps, sigma, rc_pair, nu, rc3, mass, delta_t, shift, nthreads)
+    _check(lib().orc_respa_alg1(x.shape[0], _d(x), _d(v), _d(box), C.byref(p), n_outer, P, _d(e)),
+           "respa_alg1")
     return x, v, e
 
 

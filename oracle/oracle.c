@@ -246,9 +246,13 @@ int orc_pair(int64_t n, const double *x, const double *L, double eps, double sig
 
 /* F3 for all particles by pruned brute force: loop i<j, skip k when (i,j) is out of
  * range, loop k>j.  uw = {U3, W3}; W3 sums x_a . F_a over the three members, written
- * relative to particle i as u . F_j + w . F_k. */
-int orc_triplet(int64_t n, const double *x, const double *L, double nu, double rc, double *f,
-                double *uw, int64_t *ntrip, int nthreads) {
+ * relative to particle i as u . F_j + w . F_k.
+ * Distance class (the intermediate cutoffs of Sec. 5, after the related work of Sec. 3):
+ * with r_lo > 0 a triplet of T(rc) counts only if its longest edge exceeds r_lo, i.e.
+ * unless all three squared edges are <= r_lo^2.  Classes (0, ra] and (ra, rc] thus
+ * split T(rc) into two disjoint parts; r_lo <= 0 keeps all of T(rc). */
+int orc_triplet_class(int64_t n, const double *x, const double *L, double nu, double r_lo,
+                      double rc, double *f, double *uw, int64_t *ntrip, int nthreads) {
     if (n < 0 || rc <= 0.0) return ORC_ERR_INVALID_ARG;
     if (!box_ok(L, rc)) return ORC_ERR_BOX_TOO_SMALL;
     double *xw = wrapped_copy(n, x, L);
@@ -259,6 +263,7 @@ int orc_triplet(int64_t n, const double *x, const double *L, double nu, double r
     int64_t *cnt = (int64_t *)calloc((size_t)nt, sizeof(int64_t));
     if (!fp || !ue || !cnt) { free(xw); free(fp); free(ue); free(cnt); return ORC_ERR_OOM; }
     double rc2 = rc * rc;
+    double lo2 = r_lo > 0.0 ? r_lo * r_lo : -1.0;
 #ifdef _OPENMP
 #pragma omp parallel for schedule(static, 4) num_threads(nt)
 #endif
@@ -274,6 +279,7 @@ int orc_triplet(int64_t n, const double *x, const double *L, double nu, double r
             for (int64_t k = j + 1; k < n; ++k) {
                 double w[3], v[3];
                 if (!triplet_in(xw + 3 * i, xw + 3 * j, xw + 3 * k, L, rc2, u, w, v)) continue;
+                if (dot3(u, u) <= lo2 && dot3(w, w) <= lo2 && dot3(v, v) <= lo2) continue;
                 double fi[3], fj[3], fk[3];
                 atm_forces(u, w, v, nu, fi, fj, fk);
                 for (int c = 0; c < 3; ++c) {
@@ -300,6 +306,11 @@ int orc_triplet(int64_t n, const double *x, const double *L, double nu, double r
     free(xw); free(fp); free(ue); free(cnt);
     if (!all_finite(f, 3 * n) || !all_finite(uw, 2)) return ORC_ERR_NONFINITE;
     return ORC_OK;
+}
+
+int orc_triplet(int64_t n, const double *x, const double *L, double nu, double rc, double *f,
+                double *uw, int64_t *ntrip, int nthreads) {
+    return orc_triplet_class(n, x, L, nu, 0.0, rc, f, uw, ntrip, nthreads);
 }
 
 /* Every interacting triplet as (i, j, k), i<j<k, in lexicographic order.  Returns the
@@ -461,6 +472,145 @@ int orc_respa(int64_t n, double *x, double *v, const double *L, const orc_md *p,
         }
     }
     free(f2); free(f2n); free(f3);
+    return rc;
+}
+
+/* The two distance classes of T(rc3) split at r_a: inner (longest edge <= r_a) into fin,
+ * outer (r_a < longest edge <= rc3) into fout; uw gets {U, W} of both classes summed.
+ * r_a == 0: the inner class is empty; r_a >= rc3: the outer class is empty. */
+static int class_forces(int64_t n, const double *x, const double *L, const orc_md *p, double r_a,
+                        double *fin, double *fout, double uw[2], int want_in, int want_out) {
+    double ui[2] = {0.0, 0.0}, uo[2] = {0.0, 0.0};
+    int rc = ORC_OK;
+    if (want_in) {
+        if (r_a > 0.0)
+            rc = orc_triplet_class(n, x, L, p->nu, 0.0, r_a < p->rc3 ? r_a : p->rc3, fin, ui, NULL,
+                                   p->nthreads);
+        else
+            memset(fin, 0, (size_t)n * 3 * sizeof(double));
+    }
+    if (rc == ORC_OK && want_out) {
+        if (r_a < p->rc3)
+            rc = orc_triplet_class(n, x, L, p->nu, r_a, p->rc3, fout, uo, NULL, p->nthreads);
+        else
+            memset(fout, 0, (size_t)n * 3 * sizeof(double));
+    }
+    uw[0] = ui[0] + uo[0];
+    uw[1] = ui[1] + uo[1];
+    return rc;
+}
+
+/* r-RESPA with three time scales, the nested form of Sec. 2.3.1 (Algorithm 1 extended by
+ * one level, as the text allows for any number of force splittings) applied to the
+ * distance classes of Sec. 5: F2 every inner step dt, the inner triplet class Fin every
+ * k steps, the outer class Fout every k*k_outer steps.  One outer cycle:
+ *   v <- v + (dt k k_outer / 2m) Fout(x)
+ *   repeat k_outer times:
+ *     v <- v + (dt k / 2m) Fin(x)
+ *     k velocity-Verlet steps on F2 (as in Algorithm 2)
+ *     compute Fin(x);  v <- v + (dt k / 2m) Fin(x)
+ *   compute Fout(x);  v <- v + (dt k k_outer / 2m) Fout(x)
+ * e_full holds {K, U2, U3, W2, W3} (U3, W3 over both classes) at x^0 and after every outer
+ * cycle: n_iter / (k k_outer) + 1 rows.  k_outer = 1 is Algorithm 2 with s = k. */
+int orc_respa_nested(int64_t n, double *x, double *v, const double *L, const orc_md *p,
+                     int64_t n_iter, int k, int k_outer, double r_a, double *e_full) {
+    if (n < 0 || n_iter < 0 || k < 1 || k_outer < 1 || r_a < 0.0 || p->dt <= 0.0 ||
+        p->mass <= 0.0)
+        return ORC_ERR_INVALID_ARG;
+    const int64_t span = (int64_t)k * (int64_t)k_outer;
+    if (n_iter % span != 0) return ORC_ERR_NOT_MULTIPLE_OF_K;
+    size_t bytes = (size_t)(n > 0 ? n : 1) * 3 * sizeof(double);
+    double *f2 = (double *)malloc(bytes), *f2n = (double *)malloc(bytes);
+    double *fin = (double *)malloc(bytes), *fout = (double *)malloc(bytes);
+    if (!f2 || !f2n || !fin || !fout) {
+        free(f2); free(f2n); free(fin); free(fout);
+        return ORC_ERR_OOM;
+    }
+    double uw2[2], uw3[2];
+    int rc = orc_pair(n, x, L, p->eps, p->sigma, p->rc_pair, p->shift, f2, uw2, NULL, p->nthreads);
+    if (rc == ORC_OK) rc = class_forces(n, x, L, p, r_a, fin, fout, uw3, 1, 1);
+    if (rc != ORC_OK) { free(f2); free(f2n); free(fin); free(fout); return rc; }
+    if (e_full) record(e_full, kinetic(n, v, p->mass), uw2, uw3);
+    const double c_in = (p->dt * (double)k) / (2.0 * p->mass);
+    const double c_out = (p->dt * (double)span) / (2.0 * p->mass);
+    const double cx = (p->dt * p->dt) / (2.0 * p->mass);
+    const double c2 = p->dt / (2.0 * p->mass);
+    double uin[2];
+    for (int64_t c = 0; c < n_iter / span && rc == ORC_OK; ++c) {
+        for (int64_t q = 0; q < 3 * n; ++q) v[q] = v[q] + c_out * fout[q];
+        for (int j = 0; j < k_outer && rc == ORC_OK; ++j) {
+            for (int64_t q = 0; q < 3 * n; ++q) v[q] = v[q] + c_in * fin[q];
+            for (int s = 0; s < k; ++s) {
+                for (int64_t a = 0; a < n; ++a)
+                    for (int d = 0; d < 3; ++d) {
+                        int64_t q = 3 * a + d;
+                        x[q] = wrap1(x[q] + p->dt * v[q] + cx * f2[q], L[d]);
+                    }
+                rc = orc_pair(n, x, L, p->eps, p->sigma, p->rc_pair, p->shift, f2n, uw2, NULL,
+                              p->nthreads);
+                if (rc != ORC_OK) break;
+                for (int64_t q = 0; q < 3 * n; ++q) v[q] = v[q] + c2 * (f2[q] + f2n[q]);
+                double *t = f2; f2 = f2n; f2n = t;
+            }
+            if (rc != ORC_OK) break;
+            rc = class_forces(n, x, L, p, r_a, fin, fout, uin, 1, 0);
+            if (rc != ORC_OK) break;
+            for (int64_t q = 0; q < 3 * n; ++q) v[q] = v[q] + c_in * fin[q];
+        }
+        if (rc != ORC_OK) break;
+        double uout[2];
+        rc = class_forces(n, x, L, p, r_a, fin, fout, uout, 0, 1);
+        if (rc != ORC_OK) break;
+        uw3[0] = uin[0] + uout[0];  /* uin: the inner class at this same x, just computed */
+        uw3[1] = uin[1] + uout[1];
+        for (int64_t q = 0; q < 3 * n; ++q) v[q] = v[q] + c_out * fout[q];
+        if (e_full) record(e_full + 5 * (c + 1), kinetic(n, v, p->mass), uw2, uw3);
+    }
+    free(f2); free(f2n); free(fin); free(fout);
+    return rc;
+}
+
+/* Algorithm 1 (Sec. 2.3.1) as printed, with the fast force F0 = F2 and the slow force
+ * F1 = F3 and p->dt the full step delta t, split into P sub-steps of h = delta t / P.
+ * Readings of the garbled parts: the sub-step velocity update adds (h / 2m) times the sum
+ * F0(x^{i+(j-1)/P}) + F0(x^{i+j/P}), and the closing kick's Delta t is delta t.  Per full
+ * step: v <- v + (delta t / 2m) F3(x); P velocity-Verlet sub-steps on F2; compute F3(x);
+ * v <- v + (delta t / 2m) F3(x).  e holds {K,U2,U3,W2,W3} at x^0 and after every full
+ * step: n_outer + 1 rows. */
+int orc_respa_alg1(int64_t n, double *x, double *v, const double *L, const orc_md *p,
+                   int64_t n_outer, int P, double *e) {
+    if (n < 0 || n_outer < 0 || P < 1 || p->dt <= 0.0 || p->mass <= 0.0) return ORC_ERR_INVALID_ARG;
+    size_t bytes = (size_t)(n > 0 ? n : 1) * 3 * sizeof(double);
+    double *f0 = (double *)malloc(bytes), *f0n = (double *)malloc(bytes), *f1 = (double *)malloc(bytes);
+    if (!f0 || !f0n || !f1) { free(f0); free(f0n); free(f1); return ORC_ERR_OOM; }
+    double uw2[2], uw3[2];
+    int rc = orc_pair(n, x, L, p->eps, p->sigma, p->rc_pair, p->shift, f0, uw2, NULL, p->nthreads);
+    if (rc == ORC_OK) rc = orc_triplet(n, x, L, p->nu, p->rc3, f1, uw3, NULL, p->nthreads);
+    if (rc != ORC_OK) { free(f0); free(f0n); free(f1); return rc; }
+    if (e) record(e, kinetic(n, v, p->mass), uw2, uw3);
+    const double h = p->dt / (double)P;
+    const double kick1 = p->dt / (2.0 * p->mass);
+    for (int64_t i = 0; i < n_outer; ++i) {
+        for (int64_t q = 0; q < 3 * n; ++q) v[q] = v[q] + kick1 * f1[q];
+        for (int j = 1; j <= P; ++j) {
+            for (int64_t a = 0; a < n; ++a)
+                for (int d = 0; d < 3; ++d) {
+                    int64_t q = 3 * a + d;
+                    x[q] = wrap1(x[q] + h * v[q] + ((h * h) / (2.0 * p->mass)) * f0[q], L[d]);
+                }
+            rc = orc_pair(n, x, L, p->eps, p->sigma, p->rc_pair, p->shift, f0n, uw2, NULL,
+                          p->nthreads);
+            if (rc != ORC_OK) break;
+            for (int64_t q = 0; q < 3 * n; ++q) v[q] = v[q] + (h / (2.0 * p->mass)) * (f0[q] + f0n[q]);
+            double *t = f0; f0 = f0n; f0n = t;
+        }
+        if (rc != ORC_OK) break;
+        rc = orc_triplet(n, x, L, p->nu, p->rc3, f1, uw3, NULL, p->nthreads);
+        if (rc != ORC_OK) break;
+        for (int64_t q = 0; q < 3 * n; ++q) v[q] = v[q] + kick1 * f1[q];
+        if (e) record(e + 5 * (i + 1), kinetic(n, v, p->mass), uw2, uw3);
+    }
+    free(f0); free(f0n); free(f1);
     return rc;
 }
 
