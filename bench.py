@@ -59,6 +59,7 @@ def _workload(name: str):
         "batched": W.batched,
         "toy675": lambda: W.toy(nu=0.3),
         "al4995": W.aluminium,
+        "fcc32k_nested": W.nested_at_scale,
     }
     if name not in table:
         raise SystemExit("unknown workload %s (one of %s)" % (name, ", ".join(table)))
@@ -69,7 +70,7 @@ def _params(w, precision: str, k: int):
     from paper_2507_11172_amd import mts
     return mts.Params(epsilon=w.epsilon, sigma=w.sigma, rc_pair=w.rc_pair, nu=w.nu,
                       rc_triplet=w.rc_triplet, mass=w.mass, dt=w.dt, k=k, precision=precision,
-                      method=w.method)
+                      method=w.method, k_outer=w.k_outer, rc_triplet_inner=w.rc_triplet_inner)
 
 
 def _drift_stats(en, n_particles):
@@ -87,6 +88,7 @@ def run_gpu(w, precision: str, k: int, steps: int, warmup: int, tune_ms: int):
     from paper_2507_11172_amd import mts
 
     dev = torch.device("cuda:0")
+    span = k * w.k_outer  # inner steps per full step
     sysm = mts.System(_params(w, precision, k), w.n_particles.tolist(), w.box)
     x = torch.tensor(w.x, dtype=torch.float64, device=dev)
     v = torch.tensor(w.v, dtype=torch.float64, device=dev)
@@ -95,7 +97,7 @@ def run_gpu(w, precision: str, k: int, steps: int, warmup: int, tune_ms: int):
     x0, v0 = x.clone(), v.clone()
     for attempt in range(3):
         if warmup > 0:
-            sysm.respa_step(x, v, warmup * k)
+            sysm.respa_step(x, v, warmup * span)
         try:
             sysm.sync()
             break
@@ -111,7 +113,7 @@ def run_gpu(w, precision: str, k: int, steps: int, warmup: int, tune_ms: int):
     for attempt in range(3):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        sysm.respa_step(x, v, steps * k, e)
+        sysm.respa_step(x, v, steps * span, e)
         try:
             sysm.sync()
         except mts.MTSError as err:
@@ -130,20 +132,28 @@ def run_gpu(w, precision: str, k: int, steps: int, warmup: int, tune_ms: int):
     # the energy records, as in the timed region: the same kernel variants)
     nt = max(2, min(steps, 20))
     sysm.enable_kernel_timing(True)
-    sysm.respa_step(x, v, nt * k,
+    sysm.respa_step(x, v, nt * span,
                     torch.zeros((nt + 1, w.n_systems, mts.MTS_NE), dtype=torch.float64, device=dev))
     times = sysm.kernel_times()
     sysm.enable_kernel_timing(False)
     n_trip = sysm.count_triplets(x)
     sysm.sync()
     sysm.close()
+    n_inner = 0
+    if w.k_outer > 1:  # size of the inner distance class at the same positions
+        import dataclasses
+        wi = dataclasses.replace(w, rc_triplet=w.rc_triplet_inner, k_outer=1, rc_triplet_inner=0.0)
+        with mts.System(_params(wi, precision, k), w.n_particles.tolist(), w.box) as si:
+            n_inner = si.count_triplets(x)
     drift, rvite = _drift_stats(e.cpu().numpy(), w.n_particles)
     trip_launches, trip_ms = times["triplet"]
     pair_launches, pair_ms = times["pair"]
     return {
         "elapsed_s": elapsed,
-        "inner_steps": steps * k,
+        "inner_steps": steps * span,
         "triplets_per_eval": n_trip,
+        "inner_class_triplets": n_inner,
+        "triplet_ms_per_full_step": trip_ms / nt,
         "triplet_kernel_ms": trip_ms / max(trip_launches, 1),
         "pair_kernel_ms": pair_ms / max(pair_launches, 1),
         "energy_drift_per_particle": drift,
@@ -218,6 +228,22 @@ def cpu_baseline(w, k: int):
     t0 = time.perf_counter()
     r3 = oracle.triplet_forces(w.x, box, rc=w.rc_triplet, nthreads=nthreads)
     t_trip = time.perf_counter() - t0
+    if w.k_outer > 1:
+        # nested: per full step k * k_outer pair evaluations, the inner class k_outer times
+        # and the outer class once (about the cost of the whole set: the same loops)
+        span = k * w.k_outer
+        t0 = time.perf_counter()
+        ri = oracle.triplet_forces(w.x, box, rc=w.rc_triplet_inner, nthreads=nthreads)
+        t_in = time.perf_counter() - t0
+        return {"value": span / (span * t_pair + w.k_outer * t_in + t_trip), "unit": "MD steps/s",
+                "cores": nthreads, "kind": "oracle",
+                "sample": "one LJ evaluation (%.2f s), one evaluation of the inner class "
+                          "(%.2f s, %d triplets) and one of the whole cutoff set (%.2f s, %d "
+                          "triplets) of the %d-particle system, combined as %d pair + %d inner "
+                          "+ 1 whole-set evaluations per full step of %d inner steps"
+                          % (t_pair, t_in, ri.count, t_trip, r3.count, w.n_total, span,
+                             w.k_outer, span),
+                "triplets_per_s": (r3.count + ri.count) / (t_trip + t_in)}
     steps_per_s = k / (k * t_pair + t_trip)
     return {"value": steps_per_s, "unit": "MD steps/s", "cores": nthreads, "kind": "oracle",
             "sample": "one LJ pair evaluation (%.2f s) and one ATM triplet evaluation "
@@ -369,8 +395,11 @@ def main(argv=None):
     r = run_gpu(w, precision, k, args.steps, args.warmup, args.tune_ms)
     steps_per_s = w.n_systems * r["inner_steps"] / r["elapsed_s"]
     ms_per_cycle = 1e3 * r["elapsed_s"] / args.steps
-    trip_s = r["triplet_kernel_ms"] * 1e-3
-    achieved = FLOPS_PER_TRIPLET * r["triplets_per_eval"] / trip_s / 1e12 if trip_s > 0 else 0.0
+    # triplet work and kernel time of one full step (nested: the whole cutoff set once and
+    # the inner class k_outer times)
+    evaluated = r["triplets_per_eval"] + w.k_outer * r["inner_class_triplets"]
+    trip_s = r["triplet_ms_per_full_step"] * 1e-3
+    achieved = FLOPS_PER_TRIPLET * evaluated / trip_s / 1e12 if trip_s > 0 else 0.0
     peak = PEAK_TFLOPS[precision]
     kernel = "k_triplet_and_list" if r["tuning"].get("shared_launch") else "k_triplet"
     if w.method == "direct":
@@ -378,6 +407,8 @@ def main(argv=None):
     ncls = int(r["tuning"].get("tile_classes", 1))
     if ncls > 1:  # one launch per tile class, timed together
         kernel += " + k_triplet x %d (tile classes)" % (ncls - 1)
+    if w.k_outer > 1:
+        kernel += " + inner-class k_triplet passes"
     out = {
         "metric": METRIC,
         "value": steps_per_s,
@@ -396,7 +427,7 @@ def main(argv=None):
                    "k": k, "inner_steps": r["inner_steps"], "precision": precision,
                    "rc_pair": w.rc_pair, "rc_triplet": w.rc_triplet, "nu": w.nu, "dt": w.dt,
                    "step": "one r-RESPA outer cycle (k inner steps + 1 triplet evaluation)"},
-        "triplets_per_s": r["triplets_per_eval"] / trip_s if trip_s > 0 else None,
+        "triplets_per_s": evaluated / trip_s if trip_s > 0 else None,
         "triplets_per_eval": r["triplets_per_eval"],
         "kernel_ms": {"triplet": r["triplet_kernel_ms"], "pair": r["pair_kernel_ms"]},
         "energy_drift_per_particle": r["energy_drift_per_particle"],
@@ -406,6 +437,13 @@ def main(argv=None):
                      "traffic": TRIPLET_TRAFFIC_BYTES.get((w.name, precision, kernel))},
         "tuning": r["tuning"],
     }
+    if w.k_outer > 1:
+        out["config"].update({
+            "k_outer": w.k_outer, "rc_triplet_inner": w.rc_triplet_inner,
+            "step": "one full step of nested r-RESPA: k_outer cycles of k inner steps; the "
+                    "inner triplet class (all edges <= rc_triplet_inner) every k steps, the "
+                    "whole cutoff set every k * k_outer"})
+        out["inner_class_triplets"] = r["inner_class_triplets"]
     if w.n_systems > 1:
         out["per_system_loop"] = {
             "value": run_per_system_loop(w, precision, k, args.loop_steps),
@@ -413,12 +451,13 @@ def main(argv=None):
             "note": "the same replicas, one handle each, stepped one after another"}
     if not args.no_fp32_form and precision == "fp64":
         r32 = run_gpu(w, "fp32", k, args.steps, args.warmup, args.tune_ms)
-        t32 = r32["triplet_kernel_ms"] * 1e-3
+        t32 = r32["triplet_ms_per_full_step"] * 1e-3
+        ev32 = r32["triplets_per_eval"] + w.k_outer * r32["inner_class_triplets"]
         out["fp32_form"] = {
             "value": w.n_systems * r32["inner_steps"] / r32["elapsed_s"], "unit": "MD steps/s",
-            "triplets_per_s": r32["triplets_per_eval"] / t32 if t32 > 0 else None,
+            "triplets_per_s": ev32 / t32 if t32 > 0 else None,
             "kernel_ms": {"triplet": r32["triplet_kernel_ms"], "pair": r32["pair_kernel_ms"]},
-            "roofline_frac_fp32_peak": (FLOPS_PER_TRIPLET * r32["triplets_per_eval"] / t32 / 1e12
+            "roofline_frac_fp32_peak": (FLOPS_PER_TRIPLET * ev32 / t32 / 1e12
                                         / PEAK_TFLOPS["fp32"]) if t32 > 0 else None,
             "energy_drift_per_particle": r32["energy_drift_per_particle"],
             "rvite": r32["rvite"],

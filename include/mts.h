@@ -11,7 +11,10 @@
  *     (Sec. 4.1 and 4.2.2), found through linked cells (Sec. 2.2, 4.1), evaluated
  *     once per outer step;
  *   - r-RESPA as the paper implements it (Sec. 4.1, Algorithm 2): F2 every step,
- *     F3 kicks of dt*s/(2m) every s-th step, s = k here.
+ *     F3 kicks of dt*s/(2m) every s-th step, s = k here.  Algorithm 1 (Sec. 2.3.1: full
+ *     steps delta_t of P sub-steps each) is the same scheme with dt = delta_t / P, k = P;
+ *   - optionally three time scales (mts_params.k_outer): the nested form of Sec. 2.3.1
+ *     over two distance classes of triplets split at an intermediate cutoff (Sec. 5).
  *
  * Conventions shared by every call
  *   - Units: reduced Lennard-Jones units as in the paper's appendix table.
@@ -85,6 +88,13 @@ typedef struct {
     int32_t precision;       /* mts_precision */
     int32_t lj_energy_shift; /* 1: report U2 shifted by -U(rc_pair) per pair (forces unchanged) */
     int32_t method;          /* mts_method */
+    int32_t k_outer;         /* nested r-RESPA over two triplet distance classes (Sec. 2.3.1
+                                nested loops, applied to the intermediate cutoffs of Sec. 5):
+                                0 or 1: off (Algorithm 2 with s = k); > 1: the outer class
+                                (longest edge > rc_triplet_inner) kicks every k * k_outer
+                                steps, the inner class (all edges <= rc_triplet_inner) every
+                                k steps; MTS_CUTOFF only */
+    double rc_triplet_inner; /* class split r_a: 0 < r_a < rc_triplet when k_outer > 1, else 0 */
 } mts_params;
 
 /* Energy record per system: kinetic K, LJ energy U2, ATM energy U3, pair virial W2,
@@ -134,11 +144,16 @@ mts_status mts_compute_triplet_forces(mts_system *sys, const double *x, double *
  * cycle (k inner steps, one F3 evaluation, its half kicks and the energy record) is one
  * captured HIP graph replayed on a library stream that is ordered after, and before, the
  * handle's stream (see MTS_OPT_CYCLE_GRAPH); the caller's x and v are copied in and out.
+ * With k_outer > 1 (nested, three time scales) a full step spans S = k * k_outer inner
+ * steps: the outer triplet class is evaluated and kicked (dt S / 2m) at its ends, the
+ * inner class every k steps (dt k / 2m); at a full step both kicks fall together.
+ * Otherwise S = k.
  *   x       dev [N][3] positions x^0 in, x^n out (wrapped into the box after each drift).
  *   v       dev [N][3] velocities v^0 in, v^n out.
- *   n_iter  number of inner steps, a multiple of k (else MTS_ERR_NOT_MULTIPLE_OF_K).
- *   e_full  dev [n_iter/k + 1][n_systems][MTS_NE] energies at x^0 and after every full
- *           step (only full steps have synchronised velocities), or NULL.
+ *   n_iter  number of inner steps, a multiple of S (else MTS_ERR_NOT_MULTIPLE_OF_K).
+ *   e_full  dev [n_iter/S + 1][n_systems][MTS_NE] energies at x^0 and after every full
+ *           step (only full steps have synchronised velocities; U3 and W3 cover both
+ *           classes), or NULL.
  * Both forces are recomputed at x^0 on entry, as Algorithm 2 does, so two calls of
  * n and m steps equal one call of n + m steps.  Between full steps the pair forces come
  * from a Verlet list of radius rc_pair + skin built at every full step (see

@@ -114,6 +114,8 @@ struct mts_system {
     int *red_done = nullptr;      // [nsys + 1] reduction completion counters (zero at rest)
     double *f2a = nullptr, *f2b = nullptr, *f3 = nullptr;  // [n][3] force caches
     double *pf = nullptr;         // [14][3][n] triplet partial slots
+    int k2 = 1;                   // nested r-RESPA: mid cycles per full step (k_outer, >= 1)
+    double *pf_in = nullptr;      // [14][3][n] slots of the inner distance class (k2 > 1)
     double *pe = nullptr;         // [n][2] per-particle pair energy/virial (pair-grid order)
     long long *cnt_sys = nullptr; // [nsys]
     int *nn = nullptr;            // [n]
@@ -131,7 +133,7 @@ struct mts_system {
     hipStream_t ist = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     bool use_graph = true;
-    hipGraphExec_t gexec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [energies][F2 parity]
+    hipGraphExec_t gexec[2][2][2] = {};  // [energies][F2 parity][ends a full step]
     double *xi = nullptr, *vi = nullptr;  // internal copies of x and v, [n][3]
 
     // optional per-launch HIP-event timing of the two force kernels (0: triplet, 1: pair)
@@ -184,6 +186,20 @@ mts_status validate_params(const mts_params *p, std::string &msg) {
     if (p->k < 1) { msg = "k (step-size factor) must be >= 1"; return MTS_ERR_INVALID_ARG; }
     if (p->precision != MTS_FP64 && p->precision != MTS_FP32) { msg = "unknown precision"; return MTS_ERR_INVALID_ARG; }
     if (p->method != MTS_CUTOFF && p->method != MTS_DIRECT) { msg = "unknown method"; return MTS_ERR_INVALID_ARG; }
+    if (p->k_outer < 0) { msg = "k_outer must be >= 0"; return MTS_ERR_INVALID_ARG; }
+    if (p->k_outer > 1) {
+        if (!(p->rc_triplet_inner > 0.0 && p->rc_triplet_inner < p->rc_triplet)) {
+            msg = "rc_triplet_inner must lie in (0, rc_triplet) when k_outer > 1";
+            return MTS_ERR_INVALID_ARG;
+        }
+        if (p->method == MTS_DIRECT) {
+            msg = "triplet distance classes need the cutoff method";
+            return MTS_ERR_UNSUPPORTED;
+        }
+    } else if (p->rc_triplet_inner != 0.0) {
+        msg = "rc_triplet_inner must be 0 unless k_outer > 1";
+        return MTS_ERR_INVALID_ARG;
+    }
     return MTS_OK;
 }
 
@@ -445,16 +461,21 @@ mts_status alloc_all(mts_system *s) {
     if (n > 0) HIP_TRY(s, hipMemcpy(s->sys_of, so.data(), sizeof(int) * n, hipMemcpyHostToDevice));
     HIP_TRY(s, hipMemset(s->flags, 0, sizeof(int)));
     if (n > 0) HIP_TRY(s, hipMemset(s->pf, 0, sizeof(double) * kNumHalf * 3 * n));
+    if (s->k2 > 1) {
+        HIP_TRY(s, dalloc(&s->pf_in, (size_t)kNumHalf * 3 * n));
+        if (n > 0) HIP_TRY(s, hipMemset(s->pf_in, 0, sizeof(double) * kNumHalf * 3 * n));
+    }
     return MTS_OK;
 }
 
 void drop_graphs(mts_system *s) {
     for (auto &g : s->gexec)
-        for (hipGraphExec_t &e : g)
-            if (e) {
-                (void)hipGraphExecDestroy(e);
-                e = nullptr;
-            }
+        for (auto &h : g)
+            for (hipGraphExec_t &e : h)
+                if (e) {
+                    (void)hipGraphExecDestroy(e);
+                    e = nullptr;
+                }
 }
 
 // Replaces the handle's layout by one built for cfg (the old one stays on failure).
@@ -536,7 +557,7 @@ void free_all(mts_system *s) {
     for (int c = 0; c < 2; ++c)
         for (hipEvent_t e : s->ev_pool[c]) (void)hipEventDestroy(e);
     free_layout(s->lo);
-    void *ptrs[] = {s->sys_of, s->red_part, s->red_done, s->f2a, s->f2b, s->f3, s->pf, s->pe, s->cnt_sys,
+    void *ptrs[] = {s->sys_of, s->red_part, s->red_done, s->f2a, s->f2b, s->f3, s->pf, s->pf_in, s->pe, s->cnt_sys,
                     s->nn, s->stats, s->tile_obs, s->x_ref, s->flags, s->row, s->e_buf, s->list_n,
                     s->xi, s->vi};
     for (void *p : ptrs)
@@ -650,9 +671,21 @@ mts_status enqueue_list_build(mts_system *s) {
 }
 
 // Update steps fused behind the list forces (see PairListArgs).
+// Which triplet slots a full-step evaluation produces.  Without distance classes
+// (k_outer = 1, and every standalone call) T(rc3) into pf.  Nested r-RESPA: at a full
+// step T(rc3) into pf and the inner class into pf_in, gathered as F_in + k_outer F_out
+// (the two kicks that fall together there, both scaled by dt k / 2m); between full steps
+// the inner class alone into pf.
+enum F3Mode { kF3All, kF3Outer, kF3Inner };
+
+F3Mode cycle_mode(const mts_system *s, bool full) {
+    return s->k2 == 1 ? kF3All : (full ? kF3Outer : kF3Inner);
+}
+
 struct Fused {
     bool kick2 = false, kick3_end = false, kick3_start = false, drift = false;
     bool gather3 = false;  // gather F3 from the partial slots (into s->f3) first
+    bool outer3 = false;   // ... combined with the inner class's slots (kF3Outer)
     bool bin = false;      // with drift: first binning pass of both grids
     const double *f2prev = nullptr;
     Pos4 *xs_out = nullptr;
@@ -687,6 +720,8 @@ mts_status enqueue_pair_list(mts_system *s, const Pos4 *xs_in, double *f2, const
     }
     if (u.gather3) {
         a.pf = s->pf;
+        a.pf_in = u.outer3 ? s->pf_in : nullptr;
+        a.w_out = (double)s->k2;
         a.inv_perm3 = s->lo.gt.inv_perm;
         a.f3_out = s->f3;
     }
@@ -713,9 +748,10 @@ mts_status enqueue_pair_list(mts_system *s, const Pos4 *xs_in, double *f2, const
     return MTS_OK;
 }
 
-// Arguments of the launch of tile class cls.
+// Arguments of the launch of tile class cls.  inner: the inner distance class (all edges
+// <= rc_triplet_inner) into the slots pf_out (default pf), without energies or counts.
 TripletArgs triplet_args(const mts_system *s, int cls, int *list_ijk, long long list_rows,
-                         bool energy) {
+                         bool energy, bool inner = false, double *pf_out = nullptr) {
     const Layout &lo = s->lo;
     const Grid &g = lo.gt;
     TripletArgs a{};
@@ -740,29 +776,53 @@ TripletArgs triplet_args(const mts_system *s, int cls, int *list_ijk, long long 
     a.list_rows = list_rows;
     a.stats = s->collect_stats ? s->stats : nullptr;
     a.tile_obs = s->tile_obs;
+    if (pf_out) a.pf = pf_out;
+    if (inner) {
+        a.rc2 = s->p.rc_triplet_inner * s->p.rc_triplet_inner;
+        a.ce = nullptr;
+        a.cc = nullptr;
+        a.stats = nullptr;
+        a.list_ijk = nullptr;
+    }
     return a;
 }
 
-// The triplet partial slots of every cell: one launch per tile class.
-mts_status enqueue_triplet(mts_system *s, double *f3, int *list_ijk, long long list_rows,
-                           bool energy) {
-    const long ts = timer_begin(s, 0);
+// The inner class's slots into pf_out: one launch per tile class.
+mts_status enqueue_triplet_inner(mts_system *s, double *pf_out) {
     for (int c = 0; c < s->lo.ncls; ++c)
-        HIP_TRY(s, launch_triplet(s->st, triplet_args(s, c, list_ijk, list_rows, energy), s->fp32,
-                                  list_ijk != nullptr));
-    timer_end(s, 0, ts);
-    if (f3) HIP_TRY(s, launch_triplet_gather(s->st, s->n, s->pf, s->lo.gt.perm, f3, s->flags));
+        HIP_TRY(s, launch_triplet(s->st, triplet_args(s, c, nullptr, 0, false, true, pf_out),
+                                  s->fp32, false));
     return MTS_OK;
 }
 
-// The triplet partial slots and the new pair list: the list build shares the launch of
-// the first tile class (timed together as kernel class 0).
-mts_status enqueue_triplet_and_list(mts_system *s, bool energy) {
+// The triplet partial slots of every cell for mode (one launch per tile class and
+// class of triplets), then, when f3 is given, their gather into f3.
+mts_status enqueue_triplet(mts_system *s, double *f3, int *list_ijk, long long list_rows,
+                           bool energy, F3Mode mode = kF3All) {
     const long ts = timer_begin(s, 0);
-    HIP_TRY(s, launch_triplet_and_list(s->st, triplet_args(s, 0, nullptr, 0, energy),
+    if (mode != kF3Inner)
+        for (int c = 0; c < s->lo.ncls; ++c)
+            HIP_TRY(s, launch_triplet(s->st, triplet_args(s, c, list_ijk, list_rows, energy), s->fp32,
+                                      list_ijk != nullptr));
+    if (mode != kF3All) MTS_TRY(enqueue_triplet_inner(s, mode == kF3Outer ? s->pf_in : s->pf));
+    timer_end(s, 0, ts);
+    if (f3)
+        HIP_TRY(s, launch_triplet_gather(s->st, s->n, s->pf, mode == kF3Outer ? s->pf_in : nullptr,
+                                         (double)s->k2, s->lo.gt.perm, f3, s->flags));
+    return MTS_OK;
+}
+
+// The triplet partial slots for mode and the new pair list: the list build shares the
+// launch of the first tile class (timed together as kernel class 0).
+mts_status enqueue_triplet_and_list(mts_system *s, bool energy, F3Mode mode) {
+    const long ts = timer_begin(s, 0);
+    const bool in = mode == kF3Inner;
+    HIP_TRY(s, launch_triplet_and_list(s->st, triplet_args(s, 0, nullptr, 0, energy && !in, in),
                                        list_build_args(s), s->fp32));
     for (int c = 1; c < s->lo.ncls; ++c)
-        HIP_TRY(s, launch_triplet(s->st, triplet_args(s, c, nullptr, 0, energy), s->fp32, false));
+        HIP_TRY(s, launch_triplet(s->st, triplet_args(s, c, nullptr, 0, energy && !in, in), s->fp32,
+                                  false));
+    if (mode == kF3Outer) MTS_TRY(enqueue_triplet_inner(s, s->pf_in));
     timer_end(s, 0, ts);
     return MTS_OK;
 }
@@ -876,14 +936,14 @@ bool shared_launch(const mts_system *s) {
 }
 
 // Rebins both grids at the internal positions, rebuilds the pair list and computes the
-// triplet partial slots (list mode); the caller's list force kernel then gathers F3.
-mts_status enqueue_full_step_list(mts_system *s, bool energy, bool counted = false) {
+// triplet partial slots for mode (list mode); the caller's list force kernel then gathers F3.
+mts_status enqueue_full_step_list(mts_system *s, bool energy, bool counted, F3Mode mode) {
     MTS_TRY(enqueue_bin(s, kBinPair | kBinTriplet, s->xi, true, counted));
     if (shared_launch(s)) {
-        MTS_TRY(enqueue_triplet_and_list(s, energy));
+        MTS_TRY(enqueue_triplet_and_list(s, energy, mode));
     } else {
         MTS_TRY(enqueue_list_build(s));
-        MTS_TRY(enqueue_triplet(s, nullptr, nullptr, 0, energy));
+        MTS_TRY(enqueue_triplet(s, nullptr, nullptr, 0, energy, mode));
     }
     return MTS_OK;
 }
@@ -894,14 +954,16 @@ mts_status enqueue_entry_forces(mts_system *s, double *f2, bool energy) {
         MTS_TRY(enqueue_direct_pair(s, s->xi, f2, energy));
         MTS_TRY(enqueue_direct_triplet(s, s->xi, s->f3, energy));
     } else if (s->lo.skin > 0.0) {
-        MTS_TRY(enqueue_full_step_list(s, energy));
+        const F3Mode mode = cycle_mode(s, true);
+        MTS_TRY(enqueue_full_step_list(s, energy, false, mode));
         Fused g;
         g.gather3 = true;
+        g.outer3 = mode == kF3Outer;
         MTS_TRY(enqueue_pair_list(s, s->lo.gp.xs, f2, g, true));
     } else {
         MTS_TRY(enqueue_bin(s, kBinPair | kBinTriplet, s->xi, false));
         MTS_TRY(enqueue_pair(s, f2));
-        MTS_TRY(enqueue_triplet(s, s->f3, nullptr, 0, energy));
+        MTS_TRY(enqueue_triplet(s, s->f3, nullptr, 0, energy, cycle_mode(s, true)));
     }
     return MTS_OK;
 }
@@ -920,8 +982,12 @@ mts_status enqueue_entry_forces(mts_system *s, double *f2, bool energy) {
 // Without a list (skin 0) every step rebins the pair grid and runs the tile kernel.
 // DirectSum: k_int and the all-pairs kernel every step, the all-triplets kernel and its
 // gather at x^k.
-mts_status enqueue_cycle(mts_system *s, double *f2_0, double *f2_1, bool energies) {
+// Nested r-RESPA (k_outer > 1): this is one mid cycle; full says whether x^k ends a full
+// step (outer class evaluated too, its kick merged into the F3 gather); energies only then.
+mts_status enqueue_cycle(mts_system *s, double *f2_0, double *f2_1, bool energies, bool full) {
     const int k = s->p.k;
+    const F3Mode mode = cycle_mode(s, full);
+    if (!full) energies = false;
     double *f2[2] = {f2_0, f2_1};
     if (s->direct) {
         for (int i = 0; i < k; ++i) {
@@ -943,9 +1009,10 @@ mts_status enqueue_cycle(mts_system *s, double *f2_0, double *f2_1, bool energie
             u.bin = i + 1 == k;  // ... whose first pass this kernel does
             MTS_TRY(enqueue_pair_list(s, buf[i & 1], f2[i & 1], u, false));
         }
-        MTS_TRY(enqueue_full_step_list(s, energies, k > 1));
+        MTS_TRY(enqueue_full_step_list(s, energies, k > 1, mode));
         Fused u;
         u.gather3 = true;
+        u.outer3 = mode == kF3Outer;
         u.kick2 = true;
         u.kick3_end = true;
         u.f2prev = f2[(k - 1) & 1];
@@ -957,7 +1024,7 @@ mts_status enqueue_cycle(mts_system *s, double *f2_0, double *f2_1, bool energie
             if (i == k - 1) {
                 MTS_TRY(enqueue_bin(s, kBinPair | kBinTriplet, s->xi, false));
                 MTS_TRY(enqueue_pair(s, next));
-                MTS_TRY(enqueue_triplet(s, s->f3, nullptr, 0, energies));
+                MTS_TRY(enqueue_triplet(s, s->f3, nullptr, 0, energies, mode));
             } else {
                 MTS_TRY(enqueue_bin(s, kBinPair, s->xi, false));
                 MTS_TRY(enqueue_pair(s, next));
@@ -972,10 +1039,10 @@ mts_status enqueue_cycle(mts_system *s, double *f2_0, double *f2_1, bool energie
 }
 
 // Captures one cycle into an executable graph (kernels only: no memset or copy nodes).
-mts_status capture_cycle(mts_system *s, bool energies, int parity) {
+mts_status capture_cycle(mts_system *s, bool energies, int parity, bool full) {
     double *fa = parity ? s->f2b : s->f2a, *fb = parity ? s->f2a : s->f2b;
     HIP_TRY(s, hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal));
-    mts_status r = enqueue_cycle(s, fa, fb, energies);
+    mts_status r = enqueue_cycle(s, fa, fb, energies, full);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(s->st, &g);
     if (r != MTS_OK) {
@@ -983,7 +1050,7 @@ mts_status capture_cycle(mts_system *s, bool energies, int parity) {
         return r;
     }
     if (e != hipSuccess) return hip_fail(s, e, "hipStreamEndCapture");
-    e = hipGraphInstantiate(&s->gexec[energies][parity], g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&s->gexec[energies][parity][full], g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return hip_fail(s, e, "hipGraphInstantiate");
     return MTS_OK;
@@ -991,17 +1058,18 @@ mts_status capture_cycle(mts_system *s, bool energies, int parity) {
 
 mts_status respa_internal(mts_system *s, double *x, double *v, int64_t n_iter, double *e_full) {
     const int k = s->p.k;
-    const int64_t cycles = n_iter / k;
+    const int64_t cycles = n_iter / k;                     // mid cycles of k steps
+    const int64_t full_steps = n_iter / ((int64_t)k * s->k2);
     const bool energies = e_full != nullptr;
     const int64_t bytes = 3 * s->n * (int64_t)sizeof(double);
-    if (energies && s->e_rows < cycles + 1) {
+    if (energies && s->e_rows < full_steps + 1) {
         // grow the energy record buffer; graphs holding the old pointer are dropped
         drop_graphs(s);
         if (s->e_buf) HIP_TRY(s, hipFree(s->e_buf));
         s->e_buf = nullptr;
         s->e_rows = 0;
-        HIP_TRY(s, dalloc(&s->e_buf, (size_t)(cycles + 1) * s->nsys * kNE));
-        s->e_rows = cycles + 1;
+        HIP_TRY(s, dalloc(&s->e_buf, (size_t)(full_steps + 1) * s->nsys * kNE));
+        s->e_rows = full_steps + 1;
     }
     if (bytes > 0) {
         HIP_TRY(s, hipMemcpyAsync(s->xi, x, bytes, hipMemcpyDeviceToDevice, s->st));
@@ -1016,11 +1084,13 @@ mts_status respa_internal(mts_system *s, double *x, double *v, int64_t n_iter, d
     const bool graph = s->use_graph && !s->timing;
     for (int64_t c = 0; c < cycles; ++c) {
         const int parity = (k & 1) ? (int)(c & 1) : 0;
+        const bool full = (c + 1) % s->k2 == 0;
+        const bool e = energies && full;
         if (graph) {
-            if (!s->gexec[energies][parity]) MTS_TRY(capture_cycle(s, energies, parity));
-            HIP_TRY(s, hipGraphLaunch(s->gexec[energies][parity], s->st));
+            if (!s->gexec[e][parity][full]) MTS_TRY(capture_cycle(s, e, parity, full));
+            HIP_TRY(s, hipGraphLaunch(s->gexec[e][parity][full], s->st));
         } else {
-            MTS_TRY(enqueue_cycle(s, parity ? s->f2b : s->f2a, parity ? s->f2a : s->f2b, energies));
+            MTS_TRY(enqueue_cycle(s, parity ? s->f2b : s->f2a, parity ? s->f2a : s->f2b, e, full));
         }
     }
     if (bytes > 0) {
@@ -1028,7 +1098,7 @@ mts_status respa_internal(mts_system *s, double *x, double *v, int64_t n_iter, d
         HIP_TRY(s, hipMemcpyAsync(v, s->vi, bytes, hipMemcpyDeviceToDevice, s->st));
     }
     if (energies)
-        HIP_TRY(s, hipMemcpyAsync(e_full, s->e_buf, sizeof(double) * (size_t)(cycles + 1) * s->nsys * kNE,
+        HIP_TRY(s, hipMemcpyAsync(e_full, s->e_buf, sizeof(double) * (size_t)(full_steps + 1) * s->nsys * kNE,
                                   hipMemcpyDeviceToDevice, s->st));
     return MTS_OK;
 }
@@ -1054,9 +1124,9 @@ std::map<std::string, std::pair<Config, double>> &tune_cache() {
 std::string shape_key(const mts_system *s) {
     std::string k;
     char buf[160];
-    snprintf(buf, sizeof buf, "%.17g|%.17g|%.17g|%.17g|%.17g|%.17g|%.17g|%d|%d|%d", s->p.epsilon,
-             s->p.sigma, s->p.rc_pair, s->p.nu, s->p.rc_triplet, s->p.mass, s->p.dt, s->p.k,
-             s->p.precision, s->nsys);
+    snprintf(buf, sizeof buf, "%.17g|%.17g|%.17g|%.17g|%.17g|%.17g|%.17g|%d|%d|%d|%d|%.17g",
+             s->p.epsilon, s->p.sigma, s->p.rc_pair, s->p.nu, s->p.rc_triplet, s->p.mass, s->p.dt,
+             s->p.k, s->p.precision, s->nsys, s->k2, s->p.rc_triplet_inner);
     k = buf;
     for (const SysDesc &d : s->base) {
         snprintf(buf, sizeof buf, "|%lld:%.17g,%.17g,%.17g", (long long)d.n, d.L[0], d.L[1], d.L[2]);
@@ -1148,6 +1218,7 @@ mts_status mts_init_system(const mts_params *params, int32_t n_systems, const in
     mts_system *s = new mts_system();
     s->p = *params;
     s->direct = params->method == MTS_DIRECT;
+    s->k2 = std::max(1, (int)params->k_outer);
     s->nsys = n_systems;
     s->n = p0;
     s->st = (hipStream_t)stream;
@@ -1238,8 +1309,9 @@ mts_status mts_respa_step(mts_system *sys, double *x, double *v, int64_t n_iter,
     if (!sys) return MTS_ERR_INVALID_ARG;
     if ((!x || !v) && sys->n > 0) return fail(sys, MTS_ERR_INVALID_ARG, "x or v is NULL");
     if (n_iter < 0) return fail(sys, MTS_ERR_INVALID_ARG, "n_iter < 0");
-    if (n_iter % sys->p.k != 0)
-        return fail(sys, MTS_ERR_NOT_MULTIPLE_OF_K, "n_iter must be a multiple of k (Sec. 4.1)");
+    if (n_iter % ((int64_t)sys->p.k * sys->k2) != 0)
+        return fail(sys, MTS_ERR_NOT_MULTIPLE_OF_K,
+                    "n_iter must be a multiple of k (Sec. 4.1), times k_outer when nested");
     // run on the internal stream, ordered after and before the caller's stream
     hipStream_t user = sys->st;
     HIP_TRY(sys, hipEventRecord(sys->ev_in, user));
@@ -1385,7 +1457,7 @@ mts_status mts_list_triplets(mts_system *sys, const double *x, int32_t *ijk, int
 
 static mts_status time_cycles(mts_system *s, const double *x, const double *v, double *tx,
                               double *tv, int cycles, double &ms) {
-    const int k = s->p.k;
+    const int64_t k = (int64_t)s->p.k * s->k2;  // one full step
     const int64_t bytes = 3 * s->n * (int64_t)sizeof(double);
     HIP_TRY(s, hipMemcpyAsync(tx, x, bytes, hipMemcpyDeviceToDevice, s->st));
     HIP_TRY(s, hipMemcpyAsync(tv, v, bytes, hipMemcpyDeviceToDevice, s->st));

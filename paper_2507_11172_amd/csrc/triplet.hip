@@ -595,7 +595,7 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
     if (tid == 0) {
         long long c = 0;
         for (int q = 0; q < kTripWaves; ++q) c += s_cnt[q];
-        a.cc[base] = c;
+        if (a.cc) a.cc[base] = c;
         if (ENERGY) {
             double u = 0.0, w = 0.0;
             for (int q = 0; q < kTripWaves; ++q) {
@@ -608,8 +608,11 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
     }
 }
 
-// Sum of the 14 partial slots of every particle, written in input order.
+// Sum of the 14 partial slots of every particle, written in input order.  With pf_in (the
+// inner distance class's slots) the result is S_in + w (S - S_in): the inner class plus w
+// times the outer class, the combined kick force of a full nested step.
 __global__ void __launch_bounds__(256) k_triplet_gather(int64_t n, const double *__restrict__ pf,
+                                                        const double *__restrict__ pf_in, double w,
                                                         const int *__restrict__ perm,
                                                         double *__restrict__ f, int *flags) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -619,6 +622,16 @@ __global__ void __launch_bounds__(256) k_triplet_gather(int64_t n, const double 
     for (int o = 0; o < kNumHalf; ++o) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) s[k] += pf[(3 * o + k) * n + p];
+    }
+    if (pf_in) {
+        double si[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int o = 0; o < kNumHalf; ++o) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) si[k] += pf_in[(3 * o + k) * n + p];
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) s[k] = si[k] + w * (s[k] - si[k]);
     }
     const int64_t i = perm[p];
     f[3 * i] = s[0];
@@ -719,9 +732,10 @@ int triplet_blocks_per_cu(bool fp32, size_t lds, size_t lds_per_cu) {
     return std::min(nb, (int)(lds_per_cu / per));
 }
 
-hipError_t launch_triplet_gather(hipStream_t st, int64_t n, const double *pf, const int *perm,
-                                 double *f, int *flags) {
-    if (n > 0) k_triplet_gather<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, pf, perm, f, flags);
+hipError_t launch_triplet_gather(hipStream_t st, int64_t n, const double *pf, const double *pf_in,
+                                 double w, const int *perm, double *f, int *flags) {
+    if (n > 0)
+        k_triplet_gather<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, pf, pf_in, w, perm, f, flags);
     return hipGetLastError();
 }
 

@@ -50,7 +50,8 @@ class mts_params(C.Structure):
                 ("nu", C.c_double), ("rc_triplet", C.c_double), ("mass", C.c_double),
                 ("dt", C.c_double), ("skin", C.c_double), ("k", C.c_int32),
                 ("precision", C.c_int32),
-                ("lj_energy_shift", C.c_int32), ("method", C.c_int32)]
+                ("lj_energy_shift", C.c_int32), ("method", C.c_int32), ("k_outer", C.c_int32),
+                ("rc_triplet_inner", C.c_double)]
 
 
 class mts_tuning(C.Structure):
@@ -130,13 +131,21 @@ class Params:
     lj_energy_shift: bool = True
     skin: float = 0.0         # pair-list skin; 0 picks the library default
     method: str = "cutoff"    # "cutoff" (linked cells, periodic) or "direct" (DirectSum)
+    k_outer: int = 1          # > 1: nested r-RESPA, outer triplet class every k * k_outer steps
+    rc_triplet_inner: float = 0.0  # split of the two triplet distance classes (k_outer > 1)
+
+    @property
+    def span(self) -> int:
+        """Inner steps per full step (k, times k_outer when nested)."""
+        return self.k * max(1, self.k_outer)
 
     def to_c(self) -> mts_params:
         prec = {"fp64": MTS_FP64, "fp32": MTS_FP32}[self.precision]
         meth = {"cutoff": MTS_CUTOFF, "direct": MTS_DIRECT}[self.method]
         return mts_params(self.epsilon, self.sigma, self.rc_pair, self.nu, self.rc_triplet,
                           self.mass, self.dt, float(self.skin), int(self.k), prec,
-                          int(bool(self.lj_energy_shift)), meth)
+                          int(bool(self.lj_energy_shift)), meth, int(self.k_outer),
+                          float(self.rc_triplet_inner))
 
 
 def _ptr(t, what: str, shape: Optional[Tuple[int, ...]] = None, dtype=None):
@@ -208,8 +217,8 @@ class System:
 
     def respa_step(self, x, v, n_iter: int, e_full=None):
         import torch
-        k = self.params.k
-        shape = (n_iter // k + 1, self.n_systems, MTS_NE) if k > 0 else None
+        span = self.params.span
+        shape = (n_iter // span + 1, self.n_systems, MTS_NE) if span > 0 else None
         self._check(self._lib.mts_respa_step(
             self._h, self._vec(x, "x"), self._vec(v, "v"), int(n_iter),
             _ptr(e_full, "e_full", shape, torch.float64)), "mts_respa_step")

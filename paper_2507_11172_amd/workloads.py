@@ -173,6 +173,8 @@ class Workload:
     n_iter: int = 100
     precision: str = "fp64"
     method: str = "cutoff"   # "direct": DirectSum, no cutoff, open boundaries
+    k_outer: int = 1         # > 1: nested r-RESPA over two triplet distance classes
+    rc_triplet_inner: float = 0.0
 
     @property
     def n_systems(self) -> int:
@@ -205,6 +207,15 @@ def plain_fp64() -> Workload:
 def fp64_at_scale() -> Workload:
     """32,000 particles (20^3 FCC cells), T 0.7, r-RESPA k=10, 1,000 inner steps."""
     return fcc_workload("fcc32k_fp64_k10", 20, 1002, k=10, n_iter=1000)
+
+
+def nested_at_scale() -> Workload:
+    """The 32,000-particle system under nested r-RESPA: triplets with all edges <= 2.0
+    every 2 steps, the rest of the 2.5 cutoff set every 10 (the same full step as k=10)."""
+    w = fcc_workload("fcc32k_nested_k2x5", 20, 1002, k=2, n_iter=1000)
+    w.k_outer = 5
+    w.rc_triplet_inner = 2.0
+    return w
 
 
 def precision_form(k: int = 10) -> Workload:

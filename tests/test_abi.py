@@ -59,6 +59,10 @@ def _init(lib, **over):
     (dict(n=[-5]), -1),
     (dict(box=[[4.9, 8.5, 8.5]]), -2), (dict(box=[[8.5, 8.5, 5.0]]), -2),
     (dict(rc_triplet=4.3), -2),
+    (dict(k_outer=-1), -1), (dict(k_outer=2), -1), (dict(k_outer=2, rc_triplet_inner=2.5), -1),
+    (dict(k_outer=2, rc_triplet_inner=-1.0), -1), (dict(k_outer=1, rc_triplet_inner=2.0), -1),
+    (dict(k_outer=2, rc_triplet_inner=float("nan")), -1),
+    (dict(k_outer=3, rc_triplet_inner=2.0, method=1), -8),
 ])
 def test_host_validation(lib, bad, code):
     rc, h = _init(lib, **bad)
