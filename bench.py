@@ -25,6 +25,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -324,6 +325,216 @@ def rvite_sweep(nus, ks, n_iter: int, precision: str):
             "dlogRVITE_dnu": trend, "gpu_seconds": seconds, "data": "synthetic"}
 
 
+def nested_study(n_iter: int, nu: float, precision: str, schemes):
+    """Cost and accuracy of nested r-RESPA against plain step-size factors on the
+    32,000-particle cutoff system: for each scheme (k, k_outer, r_a) the MD steps/s of one
+    respa_step call of n_iter inner steps and the relative deviation of its total energy
+    from Stoermer-Verlet's (k = 1) at the common full steps (the metric of Sec. 4.2.2,
+    Fig. 4; both runs share the cutoff's own fluctuations)."""
+    import dataclasses
+    import numpy as np
+    import torch
+    from paper_2507_11172_amd import mts, workloads as W
+
+    dev = torch.device("cuda:0")
+    base = dataclasses.replace(W.fp64_at_scale(), nu=nu)
+    common = 1
+    for k, ko, _ in schemes:
+        common = common * (k * ko) // math.gcd(common, k * ko)
+    if n_iter % common:
+        raise SystemExit("--study-iter %d is not a multiple of %d" % (n_iter, common))
+    runs = []
+    for k, ko, ra in [(1, 1, 0.0)] + list(schemes):
+        w = dataclasses.replace(base, k_outer=ko, rc_triplet_inner=ra)
+        span = k * ko
+        with mts.System(_params(w, precision, k), w.n_particles.tolist(), w.box) as s:
+            x = torch.tensor(w.x, dtype=torch.float64, device=dev)
+            v = torch.tensor(w.v, dtype=torch.float64, device=dev)
+            s.respa_step(x.clone(), v.clone(), span)  # capture the graphs
+            s.sync()
+            e = torch.zeros((n_iter // span + 1, 1, mts.MTS_NE), dtype=torch.float64, device=dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.respa_step(x, v, n_iter, e)
+            s.sync()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        en = e.cpu().numpy()[:, 0, :]
+        tot = en[:, 0] + en[:, 1] + en[:, 2]
+        runs.append({"k": k, "k_outer": ko, "rc_triplet_inner": ra, "steps_per_s": n_iter / dt,
+                     "total": tot[:: common // span], "kinetic": en[:, 0]})
+        print("scheme k=%d k_outer=%d r_a=%g: %.0f steps/s" % (k, ko, ra, n_iter / dt),
+              file=sys.stderr, flush=True)
+    ref = runs[0]["total"]
+    out = []
+    for r in runs:
+        dev_rel = np.abs(r["total"] - ref) / np.abs(ref)
+        out.append({"k": r["k"], "k_outer": r["k_outer"], "rc_triplet_inner": r["rc_triplet_inner"],
+                    "steps_per_s": r["steps_per_s"],
+                    "mean_rel_dev_vs_sv": float(dev_rel.mean()),
+                    "max_rel_dev_vs_sv": float(dev_rel.max()),
+                    "rvite": float(np.mean(np.abs(r["total"] - r["total"].mean()))
+                                   / np.mean(r["kinetic"]))})
+    return {"experiment": "nested r-RESPA over triplet distance classes vs plain step-size "
+                          "factors (cost, and total-energy deviation from Stoermer-Verlet)",
+            "workload": base.name, "n_particles": base.n_total, "nu": nu, "n_iter": n_iter,
+            "precision": precision, "compare_every": common, "schemes": out,
+            "data": "synthetic"}
+
+
+def _run_chunked(s, x, v, n_iter: int, span: int, chunk: int, label: str, on_chunk=None):
+    """respa_step in chunks of `chunk` inner steps (a resumed run equals one call); returns
+    the energy records [n_iter / span + 1][systems][5]; prints one line per chunk."""
+    import numpy as np
+    import torch
+    from paper_2507_11172_amd import mts
+    rows = []
+    done = 0
+    while done < n_iter:
+        m = min(chunk, n_iter - done)
+        e = torch.zeros((m // span + 1, s.n_systems, mts.MTS_NE), dtype=torch.float64,
+                        device=x.device)
+        s.respa_step(x, v, m, e)
+        s.sync()
+        en = e.cpu().numpy()
+        rows.append(en if not rows else en[1:])
+        done += m
+        if on_chunk is not None:
+            on_chunk(x)
+        print("%s: %d / %d inner steps" % (label, done, n_iter), file=sys.stderr, flush=True)
+    return np.concatenate(rows, axis=0)
+
+
+def al_energy_study(n_iter: int, ks, precision: str):
+    """The aluminium scenario's total-energy deviation from Stoermer-Verlet (Sec. 4.2.2,
+    Fig. 4) on DirectSum: one run per step-size factor from the same initial state, total
+    energy at every 12th iteration (a full step of every factor), its relative deviation
+    from the k = 1 run, binned into 50 bins over the range of all factors' deviations."""
+    import numpy as np
+    import torch
+    from paper_2507_11172_amd import mts, workloads as W
+
+    dev = torch.device("cuda:0")
+    w = W.aluminium()
+    common = 12
+    if n_iter % common or any(common % k for k in ks):
+        raise SystemExit("--al-iter must be a multiple of 12 and every factor divide 12")
+    ks = [1] + [k for k in ks if k != 1]
+    tot, seconds = {}, 0.0
+    for k in ks:
+        with mts.System(_params(w, precision, k), w.n_particles.tolist(), w.box) as s:
+            x = torch.tensor(w.x, dtype=torch.float64, device=dev)
+            v = torch.tensor(w.v, dtype=torch.float64, device=dev)
+            t0 = time.perf_counter()
+            en = _run_chunked(s, x, v, n_iter, k, 240, "aluminium DirectSum k=%d" % k)
+            seconds += time.perf_counter() - t0
+        t = en[:, 0, 0] + en[:, 0, 1] + en[:, 0, 2]
+        tot[k] = t[:: common // k]
+    ref = tot[1]
+    rel = {k: (tot[k] - ref) / np.abs(ref) for k in ks}
+    lo = min(float(rel[k].min()) for k in ks if k != 1)
+    hi = max(float(rel[k].max()) for k in ks if k != 1)
+    edges = np.linspace(lo, hi, 51) if hi > lo else np.linspace(lo - 1e-12, hi + 1e-12, 51)
+    out = {}
+    for k in ks:
+        mean = float(tot[k].mean())
+        h, _ = np.histogram(rel[k], bins=edges)
+        out[str(k)] = {"mean_total_energy": mean,
+                       "max_dev_from_mean_pct": float(100 * np.abs(tot[k] - mean).max() / abs(mean)),
+                       "mean_rel_dev_vs_sv": float(rel[k].mean()),
+                       "hist": (h / max(len(rel[k]), 1)).tolist()}
+    return {"experiment": "aluminium total energy vs Stoermer-Verlet, DirectSum (Sec. 4.2.2, "
+                          "Fig. 4)", "n_particles": w.n_total, "n_iter": n_iter, "dt": w.dt,
+            "nu": w.nu, "precision": precision, "every": common,
+            "bin_edges_rel_dev": edges.tolist(), "factors": out, "gpu_seconds": seconds,
+            "data": "synthetic"}
+
+
+def _rdf(x, box, r_max: float, nbins: int):
+    """Pair counts of one frame in nbins shells up to r_max (minimum image)."""
+    import numpy as np
+    n = x.shape[0]
+    counts = np.zeros(nbins)
+    for i0 in range(0, n, 512):
+        d = x[i0:i0 + 512, None, :] - x[None, :, :]
+        d -= box * np.rint(d / box)
+        r = np.sqrt(np.sum(d * d, axis=-1))
+        ii = np.arange(i0, min(n, i0 + 512))[:, None]
+        jj = np.arange(n)[None, :]
+        counts += np.histogram(r[jj > ii], bins=nbins, range=(0.0, r_max))[0]
+    return counts
+
+
+def al_pbc_study(n_iter: int, n_eq: int, ks, precision: str):
+    """The aluminium parameters on the cutoff path with periodic boundaries (Sec. 4.2.2,
+    Figs. 6 and 7): after n_eq Stoermer-Verlet steps, one run of n_iter steps per
+    step-size factor and one pure two-body run (nu = 0), all from the equilibrated state.
+    Pressure (2K + W2 + W3) / 3V at every full step, binned into 20 bins over the range of
+    all runs; radial distribution function from ten frames per run (host-side analysis of
+    positions copied back)."""
+    import dataclasses
+    import math as m
+    import numpy as np
+    import torch
+    from paper_2507_11172_amd import mts, workloads as W
+
+    dev = torch.device("cuda:0")
+    w = W.aluminium_periodic()
+    box = w.box[0]
+    vol = float(np.prod(box))
+    x = torch.tensor(w.x, dtype=torch.float64, device=dev)
+    v = torch.tensor(w.v, dtype=torch.float64, device=dev)
+    with mts.System(_params(w, precision, 1), w.n_particles.tolist(), w.box) as s:
+        _run_chunked(s, x, v, n_eq, 1, max(n_eq // 4, 12), "aluminium PBC equilibration")
+    x_eq, v_eq = x.clone(), v.clone()
+    r_max, nbins = 5.0, 100
+    runs = [("two-body", 1, 0.0)] + [("k=%d" % k, k, w.nu) for k in ks]
+    chunk = n_iter // 10
+    if n_iter % 10 or any(chunk % k for _, k, _ in runs):
+        raise SystemExit("--al-pbc-iter / 10 must be a multiple of every factor")
+    res = {}
+    for label, k, nu in runs:
+        wk = dataclasses.replace(w, nu=nu)
+        x, v = x_eq.clone(), v_eq.clone()
+        acc = np.zeros(nbins)
+        frames = [0]
+
+        def frame(xd):
+            acc[:] += _rdf(xd.cpu().numpy(), box, r_max, nbins)
+            frames[0] += 1
+
+        with mts.System(_params(wk, precision, k), w.n_particles.tolist(), w.box) as s:
+            en = _run_chunked(s, x, v, n_iter, k, chunk, "aluminium PBC %s" % label, frame)
+        p = (2.0 * en[1:, 0, 0] + en[1:, 0, 3] + en[1:, 0, 4]) / (3.0 * vol)
+        shell = 4.0 / 3.0 * m.pi * np.diff(np.linspace(0.0, r_max, nbins + 1) ** 3)
+        rho = w.n_total / vol
+        g = 2.0 * acc / (frames[0] * w.n_total * rho * shell)
+        res[label] = {"k": k, "nu": nu, "pressure": p, "rdf": g}
+    lo = min(float(r["pressure"].min()) for r in res.values())
+    hi = max(float(r["pressure"].max()) for r in res.values())
+    edges = np.linspace(lo, hi, 21)
+    ref = res["k=1"]["rdf"] if "k=1" in res else None
+    out = {}
+    centers = 0.5 * (np.linspace(0.0, r_max, nbins + 1)[1:] + np.linspace(0.0, r_max, nbins + 1)[:-1])
+    for label, r in res.items():
+        g = r["rdf"]
+        ipk = int(np.argmax(g))
+        out[label] = {"k": r["k"], "nu": r["nu"], "pressure_mean": float(r["pressure"].mean()),
+                      "pressure_std": float(r["pressure"].std()), "samples": int(len(r["pressure"])),
+                      "pressure_hist": (np.histogram(r["pressure"], bins=edges)[0]
+                                        / len(r["pressure"])).tolist(),
+                      "rdf_first_peak": [float(centers[ipk]), float(g[ipk])],
+                      "rdf_l1_vs_sv": (float(np.abs(g - ref).sum() * (r_max / nbins))
+                                       if ref is not None else None),
+                      "rdf": g.tolist()}
+    return {"experiment": "aluminium parameters, cutoff + PBC: pressure and RDF per step-size "
+                          "factor and pure two-body (Sec. 4.2.2, Figs. 6, 7)",
+            "n_particles": w.n_total, "box": box.tolist(), "rc_pair": w.rc_pair,
+            "rc_triplet": w.rc_triplet, "dt": w.dt, "n_eq": n_eq, "n_iter": n_iter,
+            "precision": precision, "pressure_bin_edges": edges.tolist(),
+            "rdf_r": centers.tolist(), "runs": out, "data": "synthetic"}
+
+
 def traffic_probe(w, precision: str, k: int, tune_ms: int):
     """For HBM counter runs (FETCH_SIZE / WRITE_SIZE): four outer cycles of the tuned
     r-RESPA loop with energy records (the triplet launch of the timed region, once per
@@ -374,6 +585,18 @@ def main(argv=None):
     ap.add_argument("--sweep-k", default="1,2,3,4,6,8,12")
     ap.add_argument("--sweep-iter", type=int, default=24000,
                     help="inner steps per run (a multiple of every factor)")
+    ap.add_argument("--nested-study", action="store_true",
+                    help="cost and energy deviation of nested r-RESPA vs plain factors on the "
+                         "32,000-particle system instead of the bench line")
+    ap.add_argument("--study-iter", type=int, default=10000)
+    ap.add_argument("--study-nu", type=float, default=0.073)
+    ap.add_argument("--al-energy-study", action="store_true",
+                    help="aluminium DirectSum total energy vs Stoermer-Verlet (Fig. 4)")
+    ap.add_argument("--al-iter", type=int, default=2400)
+    ap.add_argument("--al-pbc-study", action="store_true",
+                    help="aluminium cutoff + PBC pressure and RDF per factor (Figs. 6, 7)")
+    ap.add_argument("--al-pbc-iter", type=int, default=24000)
+    ap.add_argument("--al-pbc-eq", type=int, default=2400)
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -385,6 +608,19 @@ def main(argv=None):
         ks = [int(v) for v in args.sweep_k.split(",")]
         print(json.dumps(rvite_sweep(nus, ks, args.sweep_iter, args.precision or "fp64")),
               flush=True)
+        return 0
+    if args.al_energy_study:
+        print(json.dumps(al_energy_study(args.al_iter, [2, 3, 4, 6, 12],
+                                         args.precision or "fp64")), flush=True)
+        return 0
+    if args.al_pbc_study:
+        print(json.dumps(al_pbc_study(args.al_pbc_iter, args.al_pbc_eq, [1, 2, 3, 4, 6, 12],
+                                      args.precision or "fp64")), flush=True)
+        return 0
+    if args.nested_study:
+        schemes = [(2, 1, 0.0), (10, 1, 0.0), (2, 5, 2.0), (2, 5, 2.2), (5, 2, 2.0)]
+        print(json.dumps(nested_study(args.study_iter, args.study_nu, args.precision or "fp64",
+                                      schemes)), flush=True)
         return 0
     w = _workload(args.workload)
     k = args.k or w.k

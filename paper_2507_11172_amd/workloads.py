@@ -289,6 +289,16 @@ def aluminium(seed: int = 1007) -> Workload:
                    method="direct")
 
 
+def aluminium_periodic(seed: int = 1008) -> Workload:
+    """The aluminium parameters (appendix table) on the cutoff path: 4,995 particles in a
+    periodic 20^3 box, cutoffs 2.5 sigma for pairs and triplets.  Initial state: a jittered
+    FCC subset of the box."""
+    rng = rng_for(seed)
+    n, length = 4995, 20.0
+    x, box = fcc_subset(n, n / length ** 3, 0.05, rng)
+    return _single("al4995_pbc", x, box, 1.1, rng, nu=0.3095, dt=0.00304, k=1, n_iter=24000)
+
+
 def perfect_fcc(n_cells: int, density: float = 0.8):
     """Unjittered lattice (x, box): every force vanishes by inversion symmetry."""
     return fcc(n_cells, density, 0.0, None)

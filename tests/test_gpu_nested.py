@@ -149,3 +149,16 @@ def test_nested_step_count_must_span_full_steps():
         s.respa_step(x, v, 6)
         s.sync()
         assert bool(torch.isfinite(x).all())
+
+
+def test_nested_study_short():
+    """The nested study's runner on a short horizon: Stoermer-Verlet deviates from itself by
+    zero, every scheme's records are finite."""
+    import math
+    import bench
+    r = bench.nested_study(100, 0.073, "fp64", [(2, 1, 0.0), (2, 5, 2.0)])
+    s = r["schemes"]
+    assert [(q["k"], q["k_outer"]) for q in s] == [(1, 1), (2, 1), (2, 5)]
+    assert s[0]["mean_rel_dev_vs_sv"] == 0.0
+    for q in s:
+        assert math.isfinite(q["mean_rel_dev_vs_sv"]) and q["steps_per_s"] > 0
