@@ -7,9 +7,12 @@
 //   * the pair grid, cell edge >= rc_pair + skin, used to build a Verlet pair list.
 // Between two full steps of r-RESPA the particles move far less than half the skin, so
 // the pair list built at a full step holds every pair within rc_pair for the next k
-// inner steps; each inner step then costs two launches (fused update, list pair forces)
-// instead of a full rebinning.  A particle that moves more than half the skin raises a
-// device flag that mts_sync reports (the list is rebuilt at every full step anyway).
+// inner steps; each inner step is then one launch of the list force kernel with the
+// update fused behind it, instead of a full rebinning.  A particle that moves more than
+// half the skin raises a device flag that mts_sync reports (the list is rebuilt at every
+// full step anyway).  Nested r-RESPA (k_outer > 1) runs cycles of k steps the same way; at
+// the end of every cycle the inner triplet class is evaluated, at the end of every k_outer
+// cycles the whole cutoff set as well (see F3Mode).
 #include <algorithm>
 #include <chrono>
 #include <cmath>
