@@ -162,3 +162,45 @@ def test_nested_study_short():
     assert s[0]["mean_rel_dev_vs_sv"] == 0.0
     for q in s:
         assert math.isfinite(q["mean_rel_dev_vs_sv"]) and q["steps_per_s"] > 0
+
+
+def _class_batch():
+    """Systems whose triplet tiles fall into different tile classes (liquid density with
+    five cells per edge, a small dense box with two large cells per edge, one between)."""
+    specs = [(2048, 0.8, 71), (365, 0.9, 72), (1200, 0.7, 73)]
+    xs, vs, boxes = [], [], []
+    for n, rho, seed in specs:
+        rng = W.rng_for(seed)
+        x, box = W.fcc_subset(n, rho, 0.05, rng)
+        xs.append(x)
+        vs.append(W.maxwell_boltzmann(n, 0.8, rng))
+        boxes.append(box)
+    return W.Workload("classes", np.concatenate(xs), np.concatenate(vs), np.stack(boxes),
+                      np.array([n for n, _, _ in specs]), np.full(len(specs), 0.8))
+
+
+def test_nested_tile_classes_after_autotune():
+    """Nested r-RESPA on a batch split into tile classes, after the autotuner has picked its
+    configuration: every system follows the oracle's nested trajectory."""
+    torch = _torch()
+    from paper_2507_11172_amd import mts
+    w = _class_batch()
+    k, k_outer, r_a, n_iter = 2, 2, 2.0, 8
+    p = _params(w, k=k, k_outer=k_outer, rc_triplet_inner=r_a, skin=0.3)
+    with mts.System(p, w.n_particles.tolist(), w.box) as s:
+        assert s.tuning()["tile_classes"] >= 2
+        x, v = _dev(w.x), _dev(w.v)
+        s.autotune(x, v, 300)
+        e = torch.zeros((n_iter // (k * k_outer) + 1, w.n_systems, mts.MTS_NE),
+                        dtype=torch.float64, device="cuda")
+        s.respa_step(x, v, n_iter, e)
+        s.sync()
+        xb, vb, eb = x.cpu().numpy(), v.cpu().numpy(), e.cpu().numpy()
+    off = 0
+    for r in range(w.n_systems):
+        n = int(w.n_particles[r])
+        sl = slice(off, off + n)
+        ref = oracle.respa_nested(w.x[sl], w.v[sl], w.box[r], n_iter=n_iter, k=k,
+                                  k_outer=k_outer, r_a=r_a)
+        _assert_trajectory((xb[sl], vb[sl], eb[:, r, :]), ref, w.box[r])
+        off += n
