@@ -204,3 +204,31 @@ def test_nested_tile_classes_after_autotune():
                                   k_outer=k_outer, r_a=r_a)
         _assert_trajectory((xb[sl], vb[sl], eb[:, r, :]), ref, w.box[r])
         off += n
+
+
+def test_nested_without_inner_triplets_is_algorithm2_at_32k():
+    """32,000 particles in the bench's nested launch configuration, with the split below
+    every distance (empty inner class): the run equals Algorithm 2 with s = k * k_outer up
+    to summation order (pair lists are rebuilt on different schedules)."""
+    w = W.nested_at_scale()
+    box = w.box[0]
+    a = _run(w, 20, k=2, k_outer=5, rc_triplet_inner=0.5)
+    b = _run(w, 20, k=10)
+    d = a[0] - b[0]
+    d -= box * np.rint(d / box)
+    assert np.abs(d).max() <= 1e-10
+    assert np.abs(a[1] - b[1]).max() <= 1e-10 * np.abs(b[1]).max()
+    assert np.abs(a[2] - b[2]).max() <= 1e-10 * np.abs(b[2]).max()
+
+
+@pytest.mark.slow
+def test_nested_at_scale_32k_vs_oracle():
+    """32,000 particles, split at 2.0, k = 2, k_outer = 2: one full step against the
+    oracle's nested loop on the whole system (five class evaluations of 32,000 particles
+    on the host, about a minute)."""
+    w = W.nested_at_scale()
+    box = w.box[0]
+    print("oracle nested run, 32,000 particles", flush=True)
+    ref = oracle.respa_nested(w.x, w.v, box, n_iter=4, k=2, k_outer=2, r_a=2.0)
+    got = _run(w, 4, k=2, k_outer=2, rc_triplet_inner=2.0)
+    _assert_trajectory((got[0], got[1], got[2][:, 0, :]), ref, box)
