@@ -225,7 +225,8 @@ typedef struct {
     int32_t shared_launch;/* 1: the pair list is built in the triplet kernel's launch */
     int32_t tile_classes; /* triplet launches per force evaluation: systems are grouped by
                              the workgroups per CU their tile size allows, one launch each */
-    double cycle_ms;      /* measured ms per outer r-RESPA cycle (0: untuned) */
+    double cycle_ms;      /* measured ms per full step (k inner steps, k * k_outer when
+                             nested; 0: untuned) */
 } mts_tuning;
 
 /* (MTS_DIRECT handles have nothing to tune: the call returns their configuration.)
