@@ -118,7 +118,6 @@ struct mts_system {
     double *f2a = nullptr, *f2b = nullptr, *f3 = nullptr;  // [n][3] force caches
     double *pf = nullptr;         // [14][3][n] triplet partial slots
     int k2 = 1;                   // nested r-RESPA: mid cycles per full step (k_outer, >= 1)
-    double *pf_in = nullptr;      // [14][3][n] slots of the inner distance class (k2 > 1)
     double *pe = nullptr;         // [n][2] per-particle pair energy/virial (pair-grid order)
     long long *cnt_sys = nullptr; // [nsys]
     int *nn = nullptr;            // [n]
@@ -464,10 +463,6 @@ mts_status alloc_all(mts_system *s) {
     if (n > 0) HIP_TRY(s, hipMemcpy(s->sys_of, so.data(), sizeof(int) * n, hipMemcpyHostToDevice));
     HIP_TRY(s, hipMemset(s->flags, 0, sizeof(int)));
     if (n > 0) HIP_TRY(s, hipMemset(s->pf, 0, sizeof(double) * kNumHalf * 3 * n));
-    if (s->k2 > 1) {
-        HIP_TRY(s, dalloc(&s->pf_in, (size_t)kNumHalf * 3 * n));
-        if (n > 0) HIP_TRY(s, hipMemset(s->pf_in, 0, sizeof(double) * kNumHalf * 3 * n));
-    }
     return MTS_OK;
 }
 
@@ -560,7 +555,7 @@ void free_all(mts_system *s) {
     for (int c = 0; c < 2; ++c)
         for (hipEvent_t e : s->ev_pool[c]) (void)hipEventDestroy(e);
     free_layout(s->lo);
-    void *ptrs[] = {s->sys_of, s->red_part, s->red_done, s->f2a, s->f2b, s->f3, s->pf, s->pf_in, s->pe, s->cnt_sys,
+    void *ptrs[] = {s->sys_of, s->red_part, s->red_done, s->f2a, s->f2b, s->f3, s->pf, s->pe, s->cnt_sys,
                     s->nn, s->stats, s->tile_obs, s->x_ref, s->flags, s->row, s->e_buf, s->list_n,
                     s->xi, s->vi};
     for (void *p : ptrs)
@@ -674,11 +669,10 @@ mts_status enqueue_list_build(mts_system *s) {
 }
 
 // Update steps fused behind the list forces (see PairListArgs).
-// Which triplet slots a full-step evaluation produces.  Without distance classes
-// (k_outer = 1, and every standalone call) T(rc3) into pf.  Nested r-RESPA: at a full
-// step T(rc3) into pf and the inner class into pf_in, gathered as F_in + k_outer F_out
-// (the two kicks that fall together there, both scaled by dt k / 2m); between full steps
-// the inner class alone into pf.
+// Which triplet forces an evaluation leaves in the slots pf.  Without distance classes
+// (k_outer = 1, and every standalone call) those of T(rc3).  Nested r-RESPA: at a full step
+// the weighted pass over T(rc3), F_in + k_outer F_out (the two kicks that fall together
+// there, both applied with dt k / 2m); between full steps the inner class alone.
 enum F3Mode { kF3All, kF3Outer, kF3Inner };
 
 F3Mode cycle_mode(const mts_system *s, bool full) {
@@ -688,7 +682,6 @@ F3Mode cycle_mode(const mts_system *s, bool full) {
 struct Fused {
     bool kick2 = false, kick3_end = false, kick3_start = false, drift = false;
     bool gather3 = false;  // gather F3 from the partial slots (into s->f3) first
-    bool outer3 = false;   // ... combined with the inner class's slots (kF3Outer)
     bool bin = false;      // with drift: first binning pass of both grids
     const double *f2prev = nullptr;
     Pos4 *xs_out = nullptr;
@@ -723,8 +716,6 @@ mts_status enqueue_pair_list(mts_system *s, const Pos4 *xs_in, double *f2, const
     }
     if (u.gather3) {
         a.pf = s->pf;
-        a.pf_in = u.outer3 ? s->pf_in : nullptr;
-        a.w_out = (double)s->k2;
         a.inv_perm3 = s->lo.gt.inv_perm;
         a.f3_out = s->f3;
     }
@@ -751,10 +742,11 @@ mts_status enqueue_pair_list(mts_system *s, const Pos4 *xs_in, double *f2, const
     return MTS_OK;
 }
 
-// Arguments of the launch of tile class cls.  inner: the inner distance class (all edges
-// <= rc_triplet_inner) into the slots pf_out (default pf), without energies or counts.
+// Arguments of the launch of tile class cls for mode: kF3Inner evaluates the inner
+// distance class (all edges <= rc_triplet_inner), without energies or counts; kF3Outer
+// weights the outer class's forces by k_outer.
 TripletArgs triplet_args(const mts_system *s, int cls, int *list_ijk, long long list_rows,
-                         bool energy, bool inner = false, double *pf_out = nullptr) {
+                         bool energy, F3Mode mode = kF3All) {
     const Layout &lo = s->lo;
     const Grid &g = lo.gt;
     TripletArgs a{};
@@ -779,23 +771,18 @@ TripletArgs triplet_args(const mts_system *s, int cls, int *list_ijk, long long 
     a.list_rows = list_rows;
     a.stats = s->collect_stats ? s->stats : nullptr;
     a.tile_obs = s->tile_obs;
-    if (pf_out) a.pf = pf_out;
-    if (inner) {
+    if (mode == kF3Inner) {
         a.rc2 = s->p.rc_triplet_inner * s->p.rc_triplet_inner;
         a.ce = nullptr;
         a.cc = nullptr;
         a.stats = nullptr;
         a.list_ijk = nullptr;
+    } else if (mode == kF3Outer) {
+        a.ra2 = s->p.rc_triplet_inner * s->p.rc_triplet_inner;
+        a.w_out = (double)s->k2;
+        a.list_ijk = nullptr;
     }
     return a;
-}
-
-// The inner class's slots into pf_out: one launch per tile class.
-mts_status enqueue_triplet_inner(mts_system *s, double *pf_out) {
-    for (int c = 0; c < s->lo.ncls; ++c)
-        HIP_TRY(s, launch_triplet(s->st, triplet_args(s, c, nullptr, 0, false, true, pf_out),
-                                  s->fp32, false));
-    return MTS_OK;
 }
 
 // The triplet partial slots of every cell for mode (one launch per tile class and
@@ -803,15 +790,11 @@ mts_status enqueue_triplet_inner(mts_system *s, double *pf_out) {
 mts_status enqueue_triplet(mts_system *s, double *f3, int *list_ijk, long long list_rows,
                            bool energy, F3Mode mode = kF3All) {
     const long ts = timer_begin(s, 0);
-    if (mode != kF3Inner)
-        for (int c = 0; c < s->lo.ncls; ++c)
-            HIP_TRY(s, launch_triplet(s->st, triplet_args(s, c, list_ijk, list_rows, energy), s->fp32,
-                                      list_ijk != nullptr));
-    if (mode != kF3All) MTS_TRY(enqueue_triplet_inner(s, mode == kF3Outer ? s->pf_in : s->pf));
+    for (int c = 0; c < s->lo.ncls; ++c)
+        HIP_TRY(s, launch_triplet(s->st, triplet_args(s, c, list_ijk, list_rows, energy, mode),
+                                  s->fp32, list_ijk != nullptr));
     timer_end(s, 0, ts);
-    if (f3)
-        HIP_TRY(s, launch_triplet_gather(s->st, s->n, s->pf, mode == kF3Outer ? s->pf_in : nullptr,
-                                         (double)s->k2, s->lo.gt.perm, f3, s->flags));
+    if (f3) HIP_TRY(s, launch_triplet_gather(s->st, s->n, s->pf, s->lo.gt.perm, f3, s->flags));
     return MTS_OK;
 }
 
@@ -819,13 +802,11 @@ mts_status enqueue_triplet(mts_system *s, double *f3, int *list_ijk, long long l
 // launch of the first tile class (timed together as kernel class 0).
 mts_status enqueue_triplet_and_list(mts_system *s, bool energy, F3Mode mode) {
     const long ts = timer_begin(s, 0);
-    const bool in = mode == kF3Inner;
-    HIP_TRY(s, launch_triplet_and_list(s->st, triplet_args(s, 0, nullptr, 0, energy && !in, in),
+    HIP_TRY(s, launch_triplet_and_list(s->st, triplet_args(s, 0, nullptr, 0, energy, mode),
                                        list_build_args(s), s->fp32));
     for (int c = 1; c < s->lo.ncls; ++c)
-        HIP_TRY(s, launch_triplet(s->st, triplet_args(s, c, nullptr, 0, energy && !in, in), s->fp32,
+        HIP_TRY(s, launch_triplet(s->st, triplet_args(s, c, nullptr, 0, energy, mode), s->fp32,
                                   false));
-    if (mode == kF3Outer) MTS_TRY(enqueue_triplet_inner(s, s->pf_in));
     timer_end(s, 0, ts);
     return MTS_OK;
 }
@@ -961,7 +942,6 @@ mts_status enqueue_entry_forces(mts_system *s, double *f2, bool energy) {
         MTS_TRY(enqueue_full_step_list(s, energy, false, mode));
         Fused g;
         g.gather3 = true;
-        g.outer3 = mode == kF3Outer;
         MTS_TRY(enqueue_pair_list(s, s->lo.gp.xs, f2, g, true));
     } else {
         MTS_TRY(enqueue_bin(s, kBinPair | kBinTriplet, s->xi, false));
@@ -1015,7 +995,6 @@ mts_status enqueue_cycle(mts_system *s, double *f2_0, double *f2_1, bool energie
         MTS_TRY(enqueue_full_step_list(s, energies, k > 1, mode));
         Fused u;
         u.gather3 = true;
-        u.outer3 = mode == kF3Outer;
         u.kick2 = true;
         u.kick3_end = true;
         u.f2prev = f2[(k - 1) & 1];

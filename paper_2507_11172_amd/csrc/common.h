@@ -269,9 +269,6 @@ struct PairListArgs {
     // optional: F3 gathered here from the triplet kernel's partial slots (fixed slot
     // order, as k_triplet_gather), written to f3_out and used by the kicks instead of f3
     const double *pf;       // [14][3][n] partial slots, or null
-    const double *pf_in;    // [14][3][n] slots of the inner distance class, or null: then
-                            // F3 = S_in + w_out (S - S_in) (nested r-RESPA, full step)
-    double w_out;
     const int *inv_perm3;   // input -> sorted index of the triplet grid
     double *f3_out;         // [n][3]
     // optional (with drift): first binning pass of the drifted positions into nbin grids
@@ -309,6 +306,9 @@ struct TripletArgs {
                             // list length before capping
     int *tile_obs;          // [nsys] atomic max of the tile size per system, recorded on
                             // overflow and whenever stats is set
+    // nested r-RESPA full step (w_out > 1): forces of triplets whose longest edge exceeds
+    // sqrt(ra2) are scaled by w_out (energies and virials are not)
+    double ra2, w_out;
 };
 hipError_t launch_triplet(hipStream_t st, const TripletArgs &a, bool fp32, bool listing);
 // One launch: the triplet forces of every triplet-grid cell, then (remaining workgroups)
@@ -319,9 +319,8 @@ size_t triplet_lds_bytes(int stage_cap, int list_cap, bool fp32);
 // Triplet workgroups that fit on one CU (registers, and lds bytes of dynamic LDS each out
 // of lds_per_cu); -1: unknown.
 int triplet_blocks_per_cu(bool fp32, size_t lds, size_t lds_per_cu);
-// f = sum of the slots pf; with pf_in: S_in + w (S - S_in), S_in the sum of pf_in.
-hipError_t launch_triplet_gather(hipStream_t st, int64_t n, const double *pf, const double *pf_in,
-                                 double w, const int *perm, double *f, int *flags);
+hipError_t launch_triplet_gather(hipStream_t st, int64_t n, const double *pf, const int *perm,
+                                 double *f, int *flags);
 
 // Fused r-RESPA update (input particle order, FP64), in Algorithm 2's order:
 //   kick2:  v <- v + dt/(2m) (F2(x^{i-1}) + F2(x^i))     (previous step's F2 kick)

@@ -252,12 +252,6 @@ __global__ void __launch_bounds__(256) k_pair_list(PairListArgs a) {
         double s3 = 0.0;
 #pragma unroll
         for (int o = 0; o < kNumHalf; ++o) s3 += a.pf[(3 * o + r) * n + pt];
-        if (a.pf_in) {
-            double si = 0.0;
-#pragma unroll
-            for (int o = 0; o < kNumHalf; ++o) si += a.pf_in[(3 * o + r) * n + pt];
-            s3 = si + a.w_out * (s3 - si);
-        }
         f3q = s3;
         a.f3_out[q] = s3;
         if (!isfinite(s3)) atomicOr(a.flags, kFlagNonFinite);

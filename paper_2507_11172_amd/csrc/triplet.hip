@@ -265,8 +265,17 @@ __device__ __forceinline__ int tile_slot(const StencilTable<kNumHalf> &tab, int 
     return tab.begin[o] + (t - tab.off[o]);
 }
 
-// The triplet work of one base cell (one workgroup of kTripThreads threads).
-template <typename T, bool LIST, bool ENERGY>
+// Forward-list entries keep their tile index in the low bits of L.t; the weighted pass
+// of a nested full step marks entries within the class split of the anchor with this bit.
+constexpr int kInnerBit = 1 << 30;
+constexpr int kTileMask = kInnerBit - 1;
+
+// The triplet work of one base cell (one workgroup of kTripThreads threads).  WEIGHT: the
+// full-step pass of nested r-RESPA -- each triplet's forces are scaled by 1 if its longest
+// edge is within the split (a.ra2: all three squared edges <= ra2, decided exactly as the
+// cutoff is) and by a.w_out otherwise, so that the slots sum to F_in + w_out F_out;
+// energies and virials stay unscaled.
+template <typename T, bool LIST, bool ENERGY, bool WEIGHT>
 __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
                                               unsigned char *smem_raw) {
     __shared__ int s_turn;
@@ -328,6 +337,11 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
     unsigned short *Q = L.q;
     double U = 0.0, W = 0.0;
     int ntrip = 0;  // wave-uniform
+    auto tix = [](int v) {
+        if constexpr (WEIGHT) return v & kTileMask;
+        else return v;
+    };
+    const double ra2 = a.ra2;
 
     for (int ia = wave; ia < nself; ia += kTripWaves) {
         const PosEnt an = unpack(tile_get(tile, ia), L0, L1, L2);  // anchor: base cell, zero shift
@@ -375,7 +389,7 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
                 if (in) {
                     L.u.set(pos, ListEnt<T>{(T)dx, (T)dy, (T)dz, (T)r2});
                     L.f[pos] = ListEnt<float>{(float)dx, (float)dy, (float)dz, (float)r2};
-                    L.t[pos] = t;
+                    L.t[pos] = WEIGHT && r2 <= ra2 ? (t | kInnerBit) : t;
                     L.px[pos] = 0.0;
                     L.py[pos] = 0.0;
                     L.pz[pos] = 0.0;
@@ -401,14 +415,14 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
                 const int p1 = m + below(m1), p2 = m + n1 + below(m2);
                 if (in1 && p1 < LC) {
                     L.u.set(p1, ListEnt<T>{(T)x1, (T)y1, (T)z1, (T)q1});
-                    L.t[p1] = t1;
+                    L.t[p1] = WEIGHT && q1 <= ra2 ? (t1 | kInnerBit) : t1;
                     L.px[p1] = 0.0;
                     L.py[p1] = 0.0;
                     L.pz[p1] = 0.0;
                 }
                 if (in2 && p2 < LC) {
                     L.u.set(p2, ListEnt<T>{(T)x2, (T)y2, (T)z2, (T)q2});
-                    L.t[p2] = t2;
+                    L.t[p2] = WEIGHT && q2 <= ra2 ? (t2 | kInnerBit) : t2;
                     L.px[p2] = 0.0;
                     L.py[p2] = 0.0;
                     L.pz[p2] = 0.0;
@@ -437,14 +451,40 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
                 const long long sidx = (long long)atomicAdd(a.list_n, 1ull);
                 if (sidx < a.list_rows) {
                     const int p0 = a.perm[tile_slot(tab, ia)];
-                    const int p1 = a.perm[tile_slot(tab, L.t[j])];
-                    const int p2 = a.perm[tile_slot(tab, L.t[k])];
+                    const int p1 = a.perm[tile_slot(tab, tix(L.t[j]))];
+                    const int p2 = a.perm[tile_slot(tab, tix(L.t[k]))];
                     const int lo = min(p0, min(p1, p2)), hi = max(p0, max(p1, p2));
                     a.list_ijk[3 * sidx] = lo;
                     a.list_ijk[3 * sidx + 1] = p0 + p1 + p2 - lo - hi;
                     a.list_ijk[3 * sidx + 2] = hi;
                 }
             }
+        };
+        // Class of a hit (WEIGHT): inner iff both anchor edges were within the split at the
+        // list build (exact FP64 test, kInnerBit) and so is the j-k edge: from the list
+        // displacements, settled by the canonical FP64 displacement within a band around
+        // the split that covers their rounding (rare).
+        const T nu_out = (T)(a.nu * a.w_out);
+        const double inv_w = 1.0 / a.w_out;
+        const double band = (sizeof(T) == sizeof(float) ? 1e-5 : 1e-12) * rc2;
+        auto inner_class = [&](int j, int k, const ListEnt<T> &uj, const ListEnt<T> &uk) {
+            const int tj = L.t[j], tk = L.t[k];
+            bool in = (tj & tk & kInnerBit) != 0;
+            const T vx = uk.ux - uj.ux, vy = uk.uy - uj.uy, vz = uk.uz - uj.uz;
+            const double c = (double)((vx * vx + vy * vy) + vz * vz);
+            const bool amb = in && c > ra2 - band && c <= ra2 + band;
+            in = in && c <= ra2 - band;
+            if (__ballot(amb)) {
+                if (amb) {
+                    const PosEnt ej = unpack(tile_get(tile, tj & kTileMask), L0, L1, L2);
+                    const PosEnt ek = unpack(tile_get(tile, tk & kTileMask), L0, L1, L2);
+                    const double wx = disp1(ej.x, ek.x, ek.sx - ej.sx);
+                    const double wy = disp1(ej.y, ek.y, ek.sy - ej.sy);
+                    const double wz = disp1(ej.z, ek.z, ek.sz - ej.sz);
+                    in = norm2(wx, wy, wz) <= ra2;
+                }
+            }
+            return in;
         };
         // Two queued hits per lane, computed as two independent straight-line chains
         // (lanes without a second hit recompute their first, lanes without any hit
@@ -458,8 +498,17 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
             qh += cnt;
             const int j1 = e1 & 0xff, k1 = e1 >> 8, j2 = e2 & 0xff, k2 = e2 >> 8;
             const ListEnt<T> uj1 = L.u.get(j1), uk1 = L.u.get(k1), uj2 = L.u.get(j2), uk2 = L.u.get(k2);
-            const AtmOut<T> o1 = atm_triplet<T>(uj1, uk1, nu);
-            const AtmOut<T> o2 = atm_triplet<T>(uj2, uk2, nu);
+            T nu1 = nu, nu2 = nu;
+            double iw1 = 1.0, iw2 = 1.0;  // unscale the energy terms of weighted triplets
+            if constexpr (WEIGHT) {
+                const bool in1 = inner_class(j1, k1, uj1, uk1), in2 = inner_class(j2, k2, uj2, uk2);
+                nu1 = in1 ? nu : nu_out;
+                nu2 = in2 ? nu : nu_out;
+                iw1 = in1 ? 1.0 : inv_w;
+                iw2 = in2 ? 1.0 : inv_w;
+            }
+            const AtmOut<T> o1 = atm_triplet<T>(uj1, uk1, nu1);
+            const AtmOut<T> o2 = atm_triplet<T>(uj2, uk2, nu2);
             fax += v1 ? (double)o1.fix : 0.0;
             fay += v1 ? (double)o1.fiy : 0.0;
             faz += v1 ? (double)o1.fiz : 0.0;
@@ -467,10 +516,17 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
             fay += v2 ? (double)o2.fiy : 0.0;
             faz += v2 ? (double)o2.fiz : 0.0;
             if (ENERGY) {
-                U += v1 ? (double)o1.phi : 0.0;
-                W += v1 ? (double)o1.vir : 0.0;
-                U += v2 ? (double)o2.phi : 0.0;
-                W += v2 ? (double)o2.vir : 0.0;
+                if constexpr (WEIGHT) {
+                    U += v1 ? (double)o1.phi * iw1 : 0.0;
+                    W += v1 ? (double)o1.vir * iw1 : 0.0;
+                    U += v2 ? (double)o2.phi * iw2 : 0.0;
+                    W += v2 ? (double)o2.vir * iw2 : 0.0;
+                } else {
+                    U += v1 ? (double)o1.phi : 0.0;
+                    W += v1 ? (double)o1.vir : 0.0;
+                    U += v2 ? (double)o2.phi : 0.0;
+                    W += v2 ? (double)o2.vir : 0.0;
+                }
             }
             if (v1) scatter(o1, j1, k1);
             if (v2) scatter(o2, j2, k2);
@@ -510,8 +566,8 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
                     const bool amb2 = c2 && q2 > jk_lo && q2 <= jk_hi;
                     if (__ballot(amb1 || amb2)) {  // rare: settle with the FP64 test
                         if (amb1 || amb2) {
-                            const PosEnt ej = unpack(tile_get(tile, L.t[j]), L0, L1, L2);
-                            const PosEnt ek = unpack(tile_get(tile, L.t[amb1 ? k1 : k2]), L0, L1, L2);
+                            const PosEnt ej = unpack(tile_get(tile, tix(L.t[j])), L0, L1, L2);
+                            const PosEnt ek = unpack(tile_get(tile, tix(L.t[amb1 ? k1 : k2])), L0, L1, L2);
                             const double vx = disp1(ej.x, ek.x, ek.sx - ej.sx);
                             const double vy = disp1(ej.y, ek.y, ek.sy - ej.sy);
                             const double vz = disp1(ej.z, ek.z, ek.sz - ej.sz);
@@ -519,7 +575,7 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
                             if (amb1) hit1 = h;
                             else hit2 = h;
                             if (amb1 && amb2) {
-                                const PosEnt ek2 = unpack(tile_get(tile, L.t[k2]), L0, L1, L2);
+                                const PosEnt ek2 = unpack(tile_get(tile, tix(L.t[k2])), L0, L1, L2);
                                 const double wx = disp1(ej.x, ek2.x, ek2.sx - ej.sx);
                                 const double wy = disp1(ej.y, ek2.y, ek2.sy - ej.sy);
                                 const double wz = disp1(ej.z, ek2.z, ek2.sz - ej.sz);
@@ -560,7 +616,7 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         for (int t = lane; t < m; t += kWave) {
-            const int te = L.t[t];
+            const int te = tix(L.t[t]);
             tile.fx[te] += L.px[t];
             tile.fy[te] += L.py[t];
             tile.fz[te] += L.pz[t];
@@ -608,11 +664,8 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
     }
 }
 
-// Sum of the 14 partial slots of every particle, written in input order.  With pf_in (the
-// inner distance class's slots) the result is S_in + w (S - S_in): the inner class plus w
-// times the outer class, the combined kick force of a full nested step.
+// Sum of the 14 partial slots of every particle, written in input order.
 __global__ void __launch_bounds__(256) k_triplet_gather(int64_t n, const double *__restrict__ pf,
-                                                        const double *__restrict__ pf_in, double w,
                                                         const int *__restrict__ perm,
                                                         double *__restrict__ f, int *flags) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -623,16 +676,6 @@ __global__ void __launch_bounds__(256) k_triplet_gather(int64_t n, const double 
 #pragma unroll
         for (int k = 0; k < 3; ++k) s[k] += pf[(3 * o + k) * n + p];
     }
-    if (pf_in) {
-        double si[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-        for (int o = 0; o < kNumHalf; ++o) {
-#pragma unroll
-            for (int k = 0; k < 3; ++k) si[k] += pf_in[(3 * o + k) * n + p];
-        }
-#pragma unroll
-        for (int k = 0; k < 3; ++k) s[k] = si[k] + w * (s[k] - si[k]);
-    }
     const int64_t i = perm[p];
     f[3 * i] = s[0];
     f[3 * i + 1] = s[1];
@@ -640,56 +683,67 @@ __global__ void __launch_bounds__(256) k_triplet_gather(int64_t n, const double 
     if (!isfinite(s[0]) || !isfinite(s[1]) || !isfinite(s[2])) atomicOr(flags, kFlagNonFinite);
 }
 
-template <typename T, bool LIST, bool ENERGY>
+template <typename T, bool LIST, bool ENERGY, bool WEIGHT>
 __global__ void __launch_bounds__(kTripThreads) k_triplet(TripletArgs a) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
-    triplet_block<T, LIST, ENERGY>(a, a.cell_map ? a.cell_map[blockIdx.x] : (int)blockIdx.x, smem_raw);
+    triplet_block<T, LIST, ENERGY, WEIGHT>(a, a.cell_map ? a.cell_map[blockIdx.x] : (int)blockIdx.x,
+                                           smem_raw);
 }
 
 // The triplet forces of every triplet-grid cell and, in the same launch, the Verlet list
 // rows of every pair-grid cell (workgroups past the triplet cells): the list build fills
 // the compute units that the triplet workgroups leave idle as they drain.
-template <typename T, bool ENERGY>
+template <typename T, bool ENERGY, bool WEIGHT>
 __global__ void __launch_bounds__(kTripThreads) k_triplet_and_list(TripletArgs a, ListBuildArgs b) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     if ((int)blockIdx.x < a.ncell)
-        triplet_block<T, false, ENERGY>(a, a.cell_map ? a.cell_map[blockIdx.x] : (int)blockIdx.x,
-                                        smem_raw);
+        triplet_block<T, false, ENERGY, WEIGHT>(a, a.cell_map ? a.cell_map[blockIdx.x] : (int)blockIdx.x,
+                                                smem_raw);
     else
         list_build_block(b, (int)blockIdx.x - a.ncell, smem_raw);
 }
 
-template <typename T, bool ENERGY>
+template <typename T, bool ENERGY, bool WEIGHT>
 static hipError_t launch_triplet_and_list_t(hipStream_t st, const TripletArgs &a,
                                             const ListBuildArgs &b) {
     const size_t lds = std::max(triplet_lds_bytes(a.stage_cap, a.list_cap, sizeof(T) == 4),
                                 list_build_bytes(b.stage_cap));
-    k_triplet_and_list<T, ENERGY><<<a.ncell + b.ncell, kTripThreads, lds, st>>>(a, b);
+    k_triplet_and_list<T, ENERGY, WEIGHT><<<a.ncell + b.ncell, kTripThreads, lds, st>>>(a, b);
     return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_triplet_and_list_p(hipStream_t st, const TripletArgs &a,
+                                            const ListBuildArgs &b) {
+    if (a.w_out > 1.0)
+        return a.ce ? launch_triplet_and_list_t<T, true, true>(st, a, b)
+                    : launch_triplet_and_list_t<T, false, true>(st, a, b);
+    return a.ce ? launch_triplet_and_list_t<T, true, false>(st, a, b)
+                : launch_triplet_and_list_t<T, false, false>(st, a, b);
 }
 
 hipError_t launch_triplet_and_list(hipStream_t st, const TripletArgs &a, const ListBuildArgs &b,
                                    bool fp32) {
     if (a.ncell + b.ncell <= 0) return hipSuccess;
-    if (fp32)
-        return a.ce ? launch_triplet_and_list_t<float, true>(st, a, b)
-                    : launch_triplet_and_list_t<float, false>(st, a, b);
-    return a.ce ? launch_triplet_and_list_t<double, true>(st, a, b)
-                : launch_triplet_and_list_t<double, false>(st, a, b);
+    return fp32 ? launch_triplet_and_list_p<float>(st, a, b)
+                : launch_triplet_and_list_p<double>(st, a, b);
 }
 
-template <typename T, bool LIST, bool ENERGY>
+template <typename T, bool LIST, bool ENERGY, bool WEIGHT>
 static hipError_t launch_triplet_t(hipStream_t st, const TripletArgs &a) {
     const size_t lds = triplet_lds_bytes(a.stage_cap, a.list_cap, sizeof(T) == 4);
-    k_triplet<T, LIST, ENERGY><<<a.ncell, kTripThreads, lds, st>>>(a);
+    k_triplet<T, LIST, ENERGY, WEIGHT><<<a.ncell, kTripThreads, lds, st>>>(a);
     return hipGetLastError();
 }
 
 template <typename T>
 static hipError_t launch_triplet_p(hipStream_t st, const TripletArgs &a, bool listing) {
-    if (listing) return launch_triplet_t<T, true, false>(st, a);
-    if (a.ce) return launch_triplet_t<T, false, true>(st, a);
-    return launch_triplet_t<T, false, false>(st, a);
+    if (listing) return launch_triplet_t<T, true, false, false>(st, a);
+    if (a.w_out > 1.0)
+        return a.ce ? launch_triplet_t<T, false, true, true>(st, a)
+                    : launch_triplet_t<T, false, false, true>(st, a);
+    if (a.ce) return launch_triplet_t<T, false, true, false>(st, a);
+    return launch_triplet_t<T, false, false, false>(st, a);
 }
 
 hipError_t launch_triplet(hipStream_t st, const TripletArgs &a, bool fp32, bool listing) {
@@ -698,16 +752,24 @@ hipError_t launch_triplet(hipStream_t st, const TripletArgs &a, bool fp32, bool 
 }
 
 hipError_t configure_triplet_lds(size_t max_bytes) {
-    const void *fns[] = {(const void *)k_triplet<double, false, false>,
-                         (const void *)k_triplet<double, false, true>,
-                         (const void *)k_triplet<double, true, false>,
-                         (const void *)k_triplet<float, false, false>,
-                         (const void *)k_triplet<float, false, true>,
-                         (const void *)k_triplet<float, true, false>,
-                         (const void *)k_triplet_and_list<double, false>,
-                         (const void *)k_triplet_and_list<double, true>,
-                         (const void *)k_triplet_and_list<float, false>,
-                         (const void *)k_triplet_and_list<float, true>};
+    const void *fns[] = {(const void *)k_triplet<double, false, false, false>,
+                         (const void *)k_triplet<double, false, true, false>,
+                         (const void *)k_triplet<double, true, false, false>,
+                         (const void *)k_triplet<double, false, false, true>,
+                         (const void *)k_triplet<double, false, true, true>,
+                         (const void *)k_triplet<float, false, false, false>,
+                         (const void *)k_triplet<float, false, true, false>,
+                         (const void *)k_triplet<float, true, false, false>,
+                         (const void *)k_triplet<float, false, false, true>,
+                         (const void *)k_triplet<float, false, true, true>,
+                         (const void *)k_triplet_and_list<double, false, false>,
+                         (const void *)k_triplet_and_list<double, true, false>,
+                         (const void *)k_triplet_and_list<double, false, true>,
+                         (const void *)k_triplet_and_list<double, true, true>,
+                         (const void *)k_triplet_and_list<float, false, false>,
+                         (const void *)k_triplet_and_list<float, true, false>,
+                         (const void *)k_triplet_and_list<float, false, true>,
+                         (const void *)k_triplet_and_list<float, true, true>};
     for (const void *f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_bytes);
         if (e != hipSuccess) return e;
@@ -717,8 +779,8 @@ hipError_t configure_triplet_lds(size_t max_bytes) {
 
 int triplet_blocks_per_cu(bool fp32, size_t lds, size_t lds_per_cu) {
     // the variant with the most registers of each precision
-    const void *f = fp32 ? (const void *)k_triplet_and_list<float, true>
-                         : (const void *)k_triplet_and_list<double, true>;
+    const void *f = fp32 ? (const void *)k_triplet_and_list<float, true, false>
+                         : (const void *)k_triplet_and_list<double, true, false>;
     int nb = 0;
     hipFuncAttributes fa{};
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kTripThreads, 0) != hipSuccess ||
@@ -732,10 +794,9 @@ int triplet_blocks_per_cu(bool fp32, size_t lds, size_t lds_per_cu) {
     return std::min(nb, (int)(lds_per_cu / per));
 }
 
-hipError_t launch_triplet_gather(hipStream_t st, int64_t n, const double *pf, const double *pf_in,
-                                 double w, const int *perm, double *f, int *flags) {
-    if (n > 0)
-        k_triplet_gather<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, pf, pf_in, w, perm, f, flags);
+hipError_t launch_triplet_gather(hipStream_t st, int64_t n, const double *pf, const int *perm,
+                                 double *f, int *flags) {
+    if (n > 0) k_triplet_gather<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, pf, perm, f, flags);
     return hipGetLastError();
 }
 
