@@ -232,3 +232,38 @@ def test_nested_at_scale_32k_vs_oracle():
     ref = oracle.respa_nested(w.x, w.v, box, n_iter=4, k=2, k_outer=2, r_a=2.0)
     got = _run(w, 4, k=2, k_outer=2, rc_triplet_inner=2.0)
     _assert_trajectory((got[0], got[1], got[2][:, 0, :]), ref, box)
+
+
+def _triangle(order, eps):
+    tri = np.array([[10.0, 10.0, 10.0], [11.5 + eps, 10.0, 10.0], [10.75, 10.75, 10.0]])
+    x = tri[list(order)]
+    return W.Workload("triangle", x, np.zeros_like(x), np.full((1, 3), 40.0), np.array([3]),
+                      np.array([0.0]))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("order", [(0, 1, 2), (2, 0, 1)])
+@pytest.mark.parametrize("offset", [0.0, 1.0])
+def test_nested_class_split_is_exact(precision, order, offset):
+    """One triangle whose longest edge lies exactly at the split r_a = 1.5 (squared 2.25,
+    exact in binary: inner class) or just beyond it, inside the band where the kernel
+    settles the class with the canonical FP64 displacement (outer class).  The input order
+    makes that edge an anchor edge (0, 1, 2) or the j-k edge (2, 0, 1).  The edge grows past
+    1.5 during the first step, so the class taken at x^0 decides whether the triplet's
+    first kick pairs with later ones: the other class changes the velocities at first
+    order (checked on the oracle), far beyond the bar."""
+    eps = (2.0 ** -42 if precision == "fp64" else 2.0 ** -20) * offset
+    w = _triangle(order, eps)
+    box = w.box[0]
+    assert oracle.triplet_forces(w.x, box, rc=1.5).count == (1 if offset == 0.0 else 0)
+    ref = oracle.respa_nested(w.x, w.v, box, n_iter=3, k=1, k_outer=3, r_a=1.5)
+    if offset == 0.0:   # outer at x^0, as later: a split just below the edge
+        other = oracle.respa_nested(w.x, w.v, box, n_iter=3, k=1, k_outer=3, r_a=1.4999)
+    else:               # inner at x^0, outer later: the triangle without the offset
+        w0 = _triangle(order, 0.0)
+        other = oracle.respa_nested(w0.x, w0.v, box, n_iter=3, k=1, k_outer=3, r_a=1.5)
+    tol = 1e-10 if precision == "fp64" else 1e-4
+    scale = np.abs(ref[1]).max()
+    assert np.abs(other[1] - ref[1]).max() > 10 * tol * scale
+    xg, vg, eg = _run(w, 3, k=1, k_outer=3, rc_triplet_inner=1.5, precision=precision)
+    assert np.abs(vg - ref[1]).max() <= tol * scale
