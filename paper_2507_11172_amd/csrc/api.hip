@@ -11,8 +11,8 @@
 // update fused behind it, instead of a full rebinning.  A particle that moves more than
 // half the skin raises a device flag that mts_sync reports (the list is rebuilt at every
 // full step anyway).  Nested r-RESPA (k_outer > 1) runs cycles of k steps the same way; at
-// the end of every cycle the inner triplet class is evaluated, at the end of every k_outer
-// cycles the whole cutoff set as well (see F3Mode).
+// the end of a cycle the inner triplet class is evaluated, at the end of every k_outer-th
+// cycle instead the whole cutoff set with per-class weights (see F3Mode).
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -966,7 +966,8 @@ mts_status enqueue_entry_forces(mts_system *s, double *f2, bool energy) {
 // DirectSum: k_int and the all-pairs kernel every step, the all-triplets kernel and its
 // gather at x^k.
 // Nested r-RESPA (k_outer > 1): this is one mid cycle; full says whether x^k ends a full
-// step (outer class evaluated too, its kick merged into the F3 gather); energies only then.
+// step (then the class-weighted pass over the whole cutoff set, whose slots hold
+// F_in + k_outer F_out; otherwise the inner class alone); energies only at full steps.
 mts_status enqueue_cycle(mts_system *s, double *f2_0, double *f2_1, bool energies, bool full) {
     const int k = s->p.k;
     const F3Mode mode = cycle_mode(s, full);
