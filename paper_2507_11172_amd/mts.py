@@ -134,6 +134,15 @@ class Params:
     k_outer: int = 1          # > 1: nested r-RESPA, outer triplet class every k * k_outer steps
     rc_triplet_inner: float = 0.0  # split of the two triplet distance classes (k_outer > 1)
 
+    @classmethod
+    def algorithm1(cls, delta_t: float, P: int, **kw) -> "Params":
+        """Parameters running Algorithm 1 (Sec. 2.3.1): full steps delta_t of P sub-steps,
+        F2 in the sub-steps and F3 kicks per full step -- the same scheme as Algorithm 2
+        with dt = delta_t / P and step-size factor P."""
+        if P < 1:
+            raise ValueError("P must be >= 1")
+        return cls(dt=delta_t / P, k=int(P), **kw)
+
     @property
     def span(self) -> int:
         """Inner steps per full step (k, times k_outer when nested)."""

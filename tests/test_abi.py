@@ -105,3 +105,14 @@ def test_tuning_struct_matches_header(lib):
     assert [f[1] for f in fields] == [n for n, _ in py]
     for (ctype, _), (_, t) in zip(fields, py):
         assert (ctype == "double") == (t is C.c_double)
+
+
+def test_algorithm1_parameters():
+    """Algorithm 1's full step delta_t of P sub-steps maps to dt = delta_t / P, k = P; a
+    nested handle's full step spans k * k_outer inner steps."""
+    from paper_2507_11172_amd import mts
+    p = mts.Params.algorithm1(0.004, 4, nu=0.3)
+    assert p.dt == 0.004 / 4 and p.k == 4 and p.nu == 0.3 and p.span == 4
+    assert mts.Params(k=2, k_outer=5, rc_triplet_inner=2.0).span == 10
+    with pytest.raises(ValueError):
+        mts.Params.algorithm1(0.004, 0)
