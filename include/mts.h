@@ -109,8 +109,9 @@ enum { MTS_NE = 5 };
  *   box          host [n_systems][3], edge lengths (> 0; unused with MTS_DIRECT).
  *   stream       hipStream_t to enqueue on (NULL = default stream).
  *   out          host, receives the handle; release it with mts_destroy_system.
- * Fails with MTS_ERR_BOX_TOO_SMALL, MTS_ERR_INVALID_ARG or MTS_ERR_OOM; on failure
- * *out is NULL. */
+ * Fails with MTS_ERR_BOX_TOO_SMALL, MTS_ERR_INVALID_ARG, MTS_ERR_OOM, or
+ * MTS_ERR_UNSUPPORTED (k_outer > 1 with MTS_DIRECT, or 2^30 particles or more); on
+ * failure *out is NULL. */
 mts_status mts_init_system(const mts_params *params, int32_t n_systems, const int64_t *n_particles,
                            const double *box, void *stream, mts_system **out);
 
