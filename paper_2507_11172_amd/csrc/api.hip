@@ -87,8 +87,8 @@ struct DirectState {
     double *pI = nullptr, *pJ = nullptr, *pK = nullptr;  // partial force slots
     double *ce = nullptr;         // [ntask][2] ATM energy and virial per task
     int *blk_sys = nullptr, *blk0 = nullptr;    // 64-particle blocks (gather)
-    int *task_of = nullptr;       // per system [nb][nb]
-    int64_t *task_of0 = nullptr;
+    int *gslot = nullptr;         // gather sequences of every block (see DirectArgs)
+    int64_t *gslot0 = nullptr;    // [nblk + 1]
     SysDesc *sd = nullptr;        // p0, n; cell0/ncell = the system's task range
 };
 
@@ -489,23 +489,30 @@ mts_status set_layout(mts_system *s, const Config &cfg) {
 }
 
 void free_direct(DirectState &d) {
-    void *ptrs[] = {d.task, d.pI, d.pJ, d.pK, d.ce, d.blk_sys, d.blk0, d.task_of, d.task_of0, d.sd};
+    void *ptrs[] = {d.task, d.pI, d.pJ, d.pK, d.ce, d.blk_sys, d.blk0, d.gslot, d.gslot0, d.sd};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     d = DirectState{};
 }
 
-// DirectSum set-up: per system, the block triples (I <= J <= K) of 64-particle blocks,
-// the lookup table of task indices, and the block table of the gather kernel.
+// DirectSum set-up: per system, the block triples (I <= J <= K) of 64-particle blocks
+// (split along j into up to kDirMaxSplit tasks for small systems), and for the gather
+// kernel the block table and each block's sequence of slots.
 mts_status setup_direct(mts_system *s) {
     DirectState &D = s->dir;
     std::vector<DirectTask> tasks;
     std::vector<int> blk_sys, blk0(s->nsys), task_of;
-    std::vector<int64_t> task_of0(s->nsys);
+    std::vector<int64_t> task_of0(s->nsys), gslot0;
+    std::vector<int> gslot;
     std::vector<SysDesc> sd = s->base;
     for (int q = 0; q < s->nsys; ++q) {
         const int n = (int)s->base[q].n;
         const int nb = (n + kDirBlock - 1) / kDirBlock;
+        // split the j range of each triple so that the system alone makes ~kDirTaskTarget
+        // tasks (a power of two, at most kDirMaxSplit, so that 64 / split >= 8 j per task)
+        const int64_t triples = (int64_t)nb * (nb + 1) * (nb + 2) / 6;
+        int sp = 1;
+        while (sp < kDirMaxSplit && triples > 0 && triples * sp < kDirTaskTarget) sp *= 2;
         sd[q].cell0 = (int)tasks.size();
         task_of0[q] = (int64_t)task_of.size();
         task_of.resize(task_of.size() + (size_t)nb * nb * nb, -1);
@@ -513,13 +520,33 @@ mts_status setup_direct(mts_system *s) {
             for (int J = I; J < nb; ++J)
                 for (int K = J; K < nb; ++K) {
                     task_of[task_of0[q] + ((int64_t)I * nb + J) * nb + K] = (int)tasks.size();
-                    tasks.push_back(DirectTask{q, I, J, K});
+                    for (int u = 0; u < sp; ++u)
+                        tasks.push_back(DirectTask{q, I, J, K, u * (kDirBlock / sp),
+                                                   (u + 1) * (kDirBlock / sp)});
                 }
         sd[q].ncell = (int)tasks.size() - sd[q].cell0;
         blk0[q] = (int)blk_sys.size();
         for (int b = 0; b < nb; ++b) blk_sys.push_back(q);
+        // gather sequence of block X: its slots as I, then as J, then as K
+        auto tof = [&](int I, int J, int K) {
+            return task_of[task_of0[q] + ((int64_t)I * nb + J) * nb + K];
+        };
+        for (int X = 0; X < nb; ++X) {
+            gslot0.push_back((int64_t)gslot.size());
+            auto push = [&](int role, int first) {
+                for (int u = 0; u < sp; ++u) gslot.push_back((role << 30) | (first + u));
+            };
+            for (int J = X; J < nb; ++J)
+                for (int K = J; K < nb; ++K) push(0, tof(X, J, K));
+            for (int I = 0; I <= X; ++I)
+                for (int K = X; K < nb; ++K) push(1, tof(I, X, K));
+            for (int J = 0; J <= X; ++J)
+                for (int I = 0; I <= J; ++I) push(2, tof(I, J, X));
+        }
     }
-    if (tasks.size() >= (size_t)1 << 31) return fail(s, MTS_ERR_UNSUPPORTED, "too many particles for DirectSum");
+    gslot0.push_back((int64_t)gslot.size());
+    if (tasks.size() >= (size_t)1 << 30)  // task indices carry a 2-bit role in gslot
+        return fail(s, MTS_ERR_UNSUPPORTED, "too many particles for DirectSum");
     D.ntask = (int)tasks.size();
     D.nblk = (int)blk_sys.size();
     const size_t slot = 3 * kDirBlock;
@@ -530,8 +557,8 @@ mts_status setup_direct(mts_system *s) {
     HIP_TRY(s, dalloc(&D.ce, 2 * tasks.size()));
     HIP_TRY(s, dalloc(&D.blk_sys, blk_sys.size()));
     HIP_TRY(s, dalloc(&D.blk0, blk0.size()));
-    HIP_TRY(s, dalloc(&D.task_of, task_of.size()));
-    HIP_TRY(s, dalloc(&D.task_of0, task_of0.size()));
+    HIP_TRY(s, dalloc(&D.gslot, gslot.size()));
+    HIP_TRY(s, dalloc(&D.gslot0, gslot0.size()));
     HIP_TRY(s, dalloc(&D.sd, sd.size()));
     auto up = [&](void *dst, const void *src, size_t bytes) {
         return bytes ? hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) : hipSuccess;
@@ -539,8 +566,8 @@ mts_status setup_direct(mts_system *s) {
     HIP_TRY(s, up(D.task, tasks.data(), sizeof(DirectTask) * tasks.size()));
     HIP_TRY(s, up(D.blk_sys, blk_sys.data(), sizeof(int) * blk_sys.size()));
     HIP_TRY(s, up(D.blk0, blk0.data(), sizeof(int) * blk0.size()));
-    HIP_TRY(s, up(D.task_of, task_of.data(), sizeof(int) * task_of.size()));
-    HIP_TRY(s, up(D.task_of0, task_of0.data(), sizeof(int64_t) * task_of0.size()));
+    HIP_TRY(s, up(D.gslot, gslot.data(), sizeof(int) * gslot.size()));
+    HIP_TRY(s, up(D.gslot0, gslot0.data(), sizeof(int64_t) * gslot0.size()));
     HIP_TRY(s, up(D.sd, sd.data(), sizeof(SysDesc) * sd.size()));
     if (!tasks.empty()) HIP_TRY(s, hipMemset(D.ce, 0, sizeof(double) * 2 * tasks.size()));
     return MTS_OK;
@@ -847,8 +874,8 @@ mts_status enqueue_direct_triplet(mts_system *s, const double *x, double *f3, bo
     a.nblk = D.nblk;
     a.blk_sys = D.blk_sys;
     a.blk0 = D.blk0;
-    a.task_of = D.task_of;
-    a.task_of0 = D.task_of0;
+    a.gslot = D.gslot;
+    a.gslot0 = D.gslot0;
     a.flags = s->flags;
     const long ts = timer_begin(s, 0);
     HIP_TRY(s, launch_direct_triplet(s->st, a, s->fp32, energy));

@@ -371,7 +371,13 @@ constexpr int kDirBlock = 64;  // particles per block of the all-triplets kernel
 // One workgroup of the all-triplets kernel: block triple (I <= J <= K) of system sys.
 struct DirectTask {
     int sys, I, J, K;
+    int j0, j1;              // the task's range of j slots in block J (a split triple)
 };
+// A system's block triples are split along j into this many tasks when it has too few
+// triples to fill the chip (about 2,048 tasks); the split depends on the system alone, so
+// batched and single handles sum the same partial slots.
+constexpr int kDirTaskTarget = 2048;
+constexpr int kDirMaxSplit = 8;
 struct DirectArgs {
     int ntask;
     const DirectTask *task;  // [ntask], systems in order
@@ -383,8 +389,9 @@ struct DirectArgs {
     int nblk;                // 64-particle blocks over all systems (gather workgroups)
     const int *blk_sys;      // [nblk] system of each block
     const int *blk0;         // [nsys] first block of each system
-    const int *task_of;      // per system [nb][nb][nb]: task index of (I, J, K), I <= J <= K
-    const int64_t *task_of0; // [nsys] offset of each system's table
+    const int *gslot;        // per block, in summation order, the slots holding
+                             // contributions to it: role (0: I, 1: J, 2: K) << 30 | task
+    const int64_t *gslot0;   // [nblk + 1] offset of each block's sequence
     int *flags;
 };
 // All-triplets forces of every system: the triplet kernel fills the partial slots, the

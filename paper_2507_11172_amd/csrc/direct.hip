@@ -8,7 +8,8 @@
 // law across each triplet.  Particles form blocks of 64 (one per lane).  A workgroup of
 // four waves takes a block triple (I <= J <= K) -- equal work per workgroup, and enough
 // workgroups to fill the chip from a few hundred particles on:
-//  * lane l owns particle i = 64 I + l; the waves split the j of block J; for each j the
+//  * lane l owns particle i = 64 I + l; the waves split the j of block J (or of the task's
+//    part of it, when a small system's triples are split to fill the chip); for each j the
 //    wave sweeps the 64 k of block K in 64 steps, lane l taking k-slot (l + t) mod 64 at
 //    step t, so that every lane evaluates one triplet per step with no divergence;
 //  * F_i stays in the lane's registers, F_j is summed across the wave once per (j, K),
@@ -58,7 +59,7 @@ __global__ void __launch_bounds__(kDirThreads) k_direct_triplet(DirectArgs a) {
     {
         const int K = tk.K;
         double kx = 0.0, ky = 0.0, kz = 0.0;  // F of k-slot `lane` of block K
-        for (int jj = wave; jj < kDirBlock; jj += 4) {
+        for (int jj = tk.j0 + wave; jj < tk.j1; jj += 4) {
             const int j = tk.J * kDirBlock + jj;
             if (j >= n) break;  // wave-uniform
             const double xj = sx[1][0][jj], yj = sx[1][1][jj], zj = sx[1][2][jj];
@@ -149,33 +150,31 @@ __global__ void __launch_bounds__(kDirThreads) k_direct_triplet(DirectArgs a) {
     }
 }
 
-// F3 of every particle of block X of system s (one workgroup per block): the slots that
-// hold contributions to it -- tasks (X, J, K) as I, (I, X, K) as J, (I, J, X) as K --
-// summed in a fixed order: wave w takes every fourth slot of that sequence, the four wave
-// sums are added in wave order.
-__global__ void __launch_bounds__(kDirThreads) k_direct_gather(DirectArgs a, double *f) {
-    __shared__ double red[4][3][kDirBlock];
+// F3 of every particle of one 64-particle block (one workgroup per block): the slots that
+// hold contributions to it -- tasks (X, J, K) as I, (I, X, K) as J, (I, J, X) as K, each
+// triple's split tasks in order, listed in gslot at set-up -- summed in a fixed order:
+// wave w takes every kGatherWaves-th slot of that sequence, and the wave sums are added in
+// wave order.
+constexpr int kGatherWaves = 16;
+
+__global__ void __launch_bounds__(kGatherWaves * kWave) k_direct_gather(DirectArgs a, double *f) {
+    __shared__ double red[kGatherWaves][3][kDirBlock];
     const int s = a.blk_sys[blockIdx.x];
     const SysDesc &d = a.sd[s];
     const int n = (int)d.n;
-    const int nb = (n + kDirBlock - 1) / kDirBlock;
     const int X = (int)blockIdx.x - a.blk0[s];
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
-    const int *tof = a.task_of + a.task_of0[s];  // [nb][nb][nb], I <= J <= K
+    const int64_t beg = a.gslot0[blockIdx.x], end = a.gslot0[blockIdx.x + 1];
     double acc[3] = {0.0, 0.0, 0.0};
-    int q = 0;
-    auto add = [&](const double *slots, int task) {
-        if ((q++ & 3) != wave) return;  // wave-uniform
-        const double *src = slots + (int64_t)task * 3 * kDirBlock;
+#pragma unroll 4
+    for (int64_t q = beg + wave; q < end; q += kGatherWaves) {
+        const int e = a.gslot[q];
+        const int role = e >> 30;
+        const double *slots = role == 0 ? a.pI : (role == 1 ? a.pJ : a.pK);
+        const double *src = slots + (int64_t)(e & 0x3fffffff) * 3 * kDirBlock;
 #pragma unroll
         for (int c = 0; c < 3; ++c) acc[c] += src[c * kDirBlock + lane];
-    };
-    for (int J = X; J < nb; ++J)
-        for (int K = J; K < nb; ++K) add(a.pI, tof[((int64_t)X * nb + J) * nb + K]);
-    for (int I = 0; I <= X; ++I)
-        for (int K = X; K < nb; ++K) add(a.pJ, tof[((int64_t)I * nb + X) * nb + K]);
-    for (int J = 0; J <= X; ++J)
-        for (int I = 0; I <= J; ++I) add(a.pK, tof[((int64_t)I * nb + J) * nb + X]);
+    }
 #pragma unroll
     for (int c = 0; c < 3; ++c) red[wave][c][lane] = acc[c];
     __syncthreads();
@@ -184,8 +183,11 @@ __global__ void __launch_bounds__(kDirThreads) k_direct_gather(DirectArgs a, dou
         if (i < n) {
             double o[3];
 #pragma unroll
-            for (int c = 0; c < 3; ++c)
-                o[c] = ((red[0][c][tid] + red[1][c][tid]) + red[2][c][tid]) + red[3][c][tid];
+            for (int c = 0; c < 3; ++c) {
+                double t = 0.0;
+                for (int w = 0; w < kGatherWaves; ++w) t += red[w][c][tid];
+                o[c] = t;
+            }
             const int64_t p = d.p0 + i;
             f[3 * p] = o[0];
             f[3 * p + 1] = o[1];
@@ -260,7 +262,7 @@ hipError_t launch_direct_triplet(hipStream_t st, const DirectArgs &a, bool fp32,
 }
 
 hipError_t launch_direct_gather(hipStream_t st, const DirectArgs &a, double *f) {
-    if (a.nblk > 0) k_direct_gather<<<a.nblk, kDirThreads, 0, st>>>(a, f);
+    if (a.nblk > 0) k_direct_gather<<<a.nblk, kGatherWaves * kWave, 0, st>>>(a, f);
     return hipGetLastError();
 }
 

@@ -67,7 +67,8 @@ def _gpu_forces(ns, x, precision="fp64", nu=0.073):
 
 @pytest.mark.parametrize("n", [0, 1, 2, 3, 5, 64, 65, 130, 200])
 def test_direct_forces_and_energies_match_oracle(n):
-    """Empty, tiny, exact and ragged 64-particle blocks; every pair and triplet."""
+    """Empty, tiny, exact and ragged 64-particle blocks; every pair and triplet (these
+    small systems split each block triple along j into 8 tasks)."""
     x, _ = _cluster(max(n, 1), 40 + n)
     x = x[:n]
     f2, f3, e2, e3, count = _gpu_forces([n], x)
@@ -90,6 +91,24 @@ def test_direct_forces_and_energies_match_oracle(n):
         assert np.abs(f3.sum(axis=0)).max() <= 1e-10 * np.abs(f3).max()  # Newton's third law
     else:
         assert np.all(f3 == 0.0) and np.all(e3 == 0.0)
+
+
+@pytest.mark.parametrize("n,split", [(1400, 2), (1500, 1)])
+def test_direct_task_split_sizes(n, split):
+    """1,400 particles (22 blocks, 2,024 block triples) split each triple into 2 tasks;
+    1,500 (2,600 triples) keep one task per triple.  Forces on 64 sampled particles against
+    the oracle's exact subset mode (every pair and triplet holding the particle), the
+    triplet count against C(N, 3)."""
+    x, _ = _cluster(n, 90 + n)
+    idx = np.sort(W.rng_for(91).choice(n, size=64, replace=False))
+    r2, r3 = oracle.subset_forces(x, BIG, idx, rc_pair=RC, rc3=RC)
+    f2, f3, e2, e3, count = _gpu_forces([n], x)
+    assert count == math.comb(n, 3)
+    rms2 = np.sqrt(np.mean(np.sum(f2 * f2, axis=1)))
+    rms3 = np.sqrt(np.mean(np.sum(f3 * f3, axis=1)))
+    assert np.abs(f2[idx] - r2).max() <= 1e-12 * rms2
+    assert np.abs(f3[idx] - r3).max() <= 1e-12 * rms3
+    assert np.abs(f3.sum(axis=0)).max() <= 1e-10 * np.abs(f3).sum()
 
 
 def test_direct_toy_scenario_both_forms():
