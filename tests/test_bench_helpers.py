@@ -27,3 +27,23 @@ def test_rdf_counts_each_pair_once_with_minimum_image():
     x = np.array([[0.5, 0.5, 0.5], [9.5, 0.5, 0.5], [5.0, 5.0, 5.0]])  # 1.0 apart through the face
     c = bench._rdf(x, box, 2.0, 4)
     assert c.tolist() == [0.0, 0.0, 1.0, 0.0]
+
+
+def test_bench_rvite_matches_the_oracle_definition():
+    """The bench's per-system RVITE (and drift) from energy records equal Eq. 4 as the
+    oracle states it, on synthetic records of two systems."""
+    import bench
+    import oracle
+    rng = np.random.default_rng(3)
+    rows, nsys = 21, 2
+    en = np.zeros((rows, nsys, 5))
+    en[:, :, 0] = 50.0 + rng.normal(0.0, 1.0, (rows, nsys))      # K
+    en[:, :, 1] = -200.0 + rng.normal(0.0, 1.0, (rows, nsys))    # U2
+    en[:, :, 2] = 3.0 + rng.normal(0.0, 0.1, (rows, nsys))       # U3
+    n_particles = np.array([100, 300])
+    drift, rvite = bench._drift_stats(en, n_particles)
+    tot = en[:, :, 0] + en[:, :, 1] + en[:, :, 2]
+    ref = [oracle.rvite(tot[:, q], en[:, q, 0]) for q in range(nsys)]
+    assert abs(rvite - np.mean(ref)) <= 1e-15 * abs(np.mean(ref))
+    ref_drift = np.mean(np.abs(tot[-1] - tot[0]) / n_particles)
+    assert abs(drift - ref_drift) <= 1e-15 * abs(ref_drift)
