@@ -325,19 +325,22 @@ def rvite_sweep(nus, ks, n_iter: int, precision: str):
             "dlogRVITE_dnu": trend, "gpu_seconds": seconds, "data": "synthetic"}
 
 
-def nested_study(n_iter: int, nu: float, precision: str, schemes):
-    """Cost and accuracy of nested r-RESPA against plain step-size factors on the
-    32,000-particle cutoff system: for each scheme (k, k_outer, r_a) the MD steps/s of one
-    respa_step call of n_iter inner steps and the relative deviation of its total energy
-    from Stoermer-Verlet's (k = 1) at the common full steps (the metric of Sec. 4.2.2,
-    Fig. 4; both runs share the cutoff's own fluctuations)."""
+def nested_study(n_iter: int, nu: float, precision: str, schemes, workload: str = "fcc32k"):
+    """Cost and accuracy of nested r-RESPA against plain step-size factors on a cutoff
+    system (the 32,000-particle one, or the aluminium parameters in a periodic box with
+    workload "al4995_pbc"; nu <= 0 keeps the workload's own): for each scheme (k, k_outer,
+    r_a) the MD steps/s of one respa_step call of n_iter inner steps and the relative
+    deviation of its total energy from Stoermer-Verlet's (k = 1) at the common full steps
+    (the metric of Sec. 4.2.2, Fig. 4; both runs share the cutoff's own fluctuations)."""
     import dataclasses
     import numpy as np
     import torch
     from paper_2507_11172_amd import mts, workloads as W
 
     dev = torch.device("cuda:0")
-    base = dataclasses.replace(W.fp64_at_scale(), nu=nu)
+    base = W.aluminium_periodic() if workload == "al4995_pbc" else W.fp64_at_scale()
+    if nu > 0.0:
+        base = dataclasses.replace(base, nu=nu)
     common = 1
     for k, ko, _ in schemes:
         common = common * (k * ko) // math.gcd(common, k * ko)
@@ -377,7 +380,7 @@ def nested_study(n_iter: int, nu: float, precision: str, schemes):
                                    / np.mean(r["kinetic"]))})
     return {"experiment": "nested r-RESPA over triplet distance classes vs plain step-size "
                           "factors (cost, and total-energy deviation from Stoermer-Verlet)",
-            "workload": base.name, "n_particles": base.n_total, "nu": nu, "n_iter": n_iter,
+            "workload": base.name, "n_particles": base.n_total, "nu": base.nu, "n_iter": n_iter,
             "precision": precision, "compare_every": common, "schemes": out,
             "data": "synthetic"}
 
@@ -589,7 +592,9 @@ def main(argv=None):
                     help="cost and energy deviation of nested r-RESPA vs plain factors on the "
                          "32,000-particle system instead of the bench line")
     ap.add_argument("--study-iter", type=int, default=10000)
-    ap.add_argument("--study-nu", type=float, default=0.073)
+    ap.add_argument("--study-nu", type=float, default=0.073,
+                    help="nu of the nested study (<= 0: the workload's own)")
+    ap.add_argument("--study-workload", default="fcc32k", choices=["fcc32k", "al4995_pbc"])
     ap.add_argument("--al-energy-study", action="store_true",
                     help="aluminium DirectSum total energy vs Stoermer-Verlet (Fig. 4)")
     ap.add_argument("--al-iter", type=int, default=2400)
@@ -620,7 +625,7 @@ def main(argv=None):
     if args.nested_study:
         schemes = [(2, 1, 0.0), (10, 1, 0.0), (2, 5, 2.0), (2, 5, 2.2), (5, 2, 2.0)]
         print(json.dumps(nested_study(args.study_iter, args.study_nu, args.precision or "fp64",
-                                      schemes)), flush=True)
+                                      schemes, args.study_workload)), flush=True)
         return 0
     w = _workload(args.workload)
     k = args.k or w.k
