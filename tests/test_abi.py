@@ -116,3 +116,41 @@ def test_algorithm1_parameters():
     assert mts.Params(k=2, k_outer=5, rc_triplet_inner=2.0).span == 10
     with pytest.raises(ValueError):
         mts.Params.algorithm1(0.004, 0)
+
+
+C_PROGRAM = r"""
+#include <stdio.h>
+#include <string.h>
+#include "mts.h"
+int main(void) {
+    mts_params p;
+    memset(&p, 0, sizeof p);
+    p.epsilon = 1.0; p.sigma = 1.0; p.rc_pair = 2.5; p.nu = 0.073; p.rc_triplet = 2.5;
+    p.mass = 1.0; p.dt = 0.001; p.k = 0;  /* invalid: k < 1 */
+    int64_t n = 10;
+    double box[3] = {10.0, 10.0, 10.0};
+    mts_system *s = (mts_system *)&p;
+    mts_status r = mts_init_system(&p, 1, &n, box, NULL, &s);
+    printf("%s %s\n", mts_status_string(r), mts_status_string(MTS_ERR_NOT_MULTIPLE_OF_K));
+    return (r == MTS_ERR_INVALID_ARG && s == NULL) ? 0 : 1;
+}
+"""
+
+
+def test_header_is_c99_and_library_links_from_c(lib, tmp_path):
+    """The boundary is a C ABI: the header compiles as strict C99 without warnings, and a
+    plain C program linked against libmts.so gets host-side validation through it."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "abi.c"
+    src.write_text(C_PROGRAM)
+    exe = tmp_path / "abi"
+    libdir = os.path.join(ROOT, "paper_2507_11172_amd")
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror",
+                    "-I", os.path.join(ROOT, "include"), str(src), "-L", libdir, "-lmts",
+                    "-Wl,-rpath," + libdir, "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert out.stdout.split() == ["MTS_ERR_INVALID_ARG", "MTS_ERR_NOT_MULTIPLE_OF_K"]
