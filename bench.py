@@ -215,6 +215,17 @@ def run_per_system_loop(w, precision: str, k: int, steps: int):
     return w.n_systems * steps * k / elapsed
 
 
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
+
+
 def cpu_baseline(w, k: int):
     """The FP64 oracle as it stands, timed on this host: one pair and one triplet force
     evaluation of the whole system, scaled to inner steps/s for step-size factor k."""
@@ -237,7 +248,7 @@ def cpu_baseline(w, k: int):
         ri = oracle.triplet_forces(w.x, box, rc=w.rc_triplet_inner, nthreads=nthreads)
         t_in = time.perf_counter() - t0
         return {"value": span / (span * t_pair + w.k_outer * t_in + t_trip), "unit": "MD steps/s",
-                "cores": nthreads, "kind": "oracle",
+                "cores": nthreads, "kind": "oracle", "cpu": _cpu_model(),
                 "sample": "one LJ evaluation (%.2f s), one evaluation of the inner class "
                           "(%.2f s, %d triplets) and one of the whole cutoff set (%.2f s, %d "
                           "triplets) of the %d-particle system, combined as %d pair + %d inner "
@@ -247,6 +258,7 @@ def cpu_baseline(w, k: int):
                 "triplets_per_s": (r3.count + ri.count) / (t_trip + t_in)}
     steps_per_s = k / (k * t_pair + t_trip)
     return {"value": steps_per_s, "unit": "MD steps/s", "cores": nthreads, "kind": "oracle",
+            "cpu": _cpu_model(),
             "sample": "one LJ pair evaluation (%.2f s) and one ATM triplet evaluation "
                       "(%.2f s, %d triplets) of the full %d-particle system, combined as "
                       "k=%d pair + 1 triplet evaluations per k inner steps"
@@ -274,7 +286,7 @@ def _cpu_baseline_direct(w, k: int, nthreads: int):
     rate = r3.count / t_m
     t_trip = math.comb(n, 3) / rate
     return {"value": k / (k * t_pair + t_trip), "unit": "MD steps/s", "cores": nthreads,
-            "kind": "oracle",
+            "kind": "oracle", "cpu": _cpu_model(),
             "sample": "DirectSum: one LJ evaluation of all %d particles (%.2f s) and one ATM "
                       "evaluation of the first %d (%.2f s, %d triplets), its rate scaled to "
                       "the C(N,3) = %d triplets of the system; k=%d pair + 1 triplet "
