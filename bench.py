@@ -163,6 +163,45 @@ def run_gpu(w, precision: str, k: int, steps: int, warmup: int, tune_ms: int):
     }
 
 
+def fp32_force_error(w, k: int):
+    """The FP32 form's force and energy error against the FP64 path on the GPU, at the
+    workload's initial state, each the largest over the systems: max |dF| / RMS |F| of a
+    system for F2 and F3, and |dE| / N of a system's total potential energy."""
+    import numpy as np
+    import torch
+    from paper_2507_11172_amd import mts
+
+    dev = torch.device("cuda:0")
+    out = {}
+    for prec in ("fp64", "fp32"):
+        with mts.System(_params(w, prec, k), w.n_particles.tolist(), w.box) as s:
+            x = torch.tensor(w.x, dtype=torch.float64, device=dev)
+            f2, f3 = torch.empty_like(x), torch.empty_like(x)
+            e2 = torch.zeros((w.n_systems, 2), dtype=torch.float64, device=dev)
+            e3 = torch.zeros((w.n_systems, 2), dtype=torch.float64, device=dev)
+            s.compute_pair_forces(x, f2, e2)
+            s.compute_triplet_forces(x, f3, e3)
+            s.sync()
+            out[prec] = (f2.cpu().numpy(), f3.cpu().numpy(),
+                         (e2[:, 0] + e3[:, 0]).cpu().numpy())
+
+    starts = np.concatenate([[0], np.cumsum(w.n_particles)])
+
+    def rel(a, r):  # the largest per-system max |dF| / RMS |F|
+        worst = 0.0
+        for lo, hi in zip(starts[:-1], starts[1:]):
+            ref = r[lo:hi]
+            rms = np.sqrt(np.mean(np.sum(ref * ref, axis=1))) if hi > lo else 0.0
+            if rms > 0:
+                worst = max(worst, float(np.abs(a[lo:hi] - ref).max() / rms))
+        return worst
+
+    (a2, a3, ae), (b2, b3, be) = out["fp32"], out["fp64"]
+    return {"f2": rel(a2, b2), "f3": rel(a3, b3),
+            "energy_per_particle": float(np.max(np.abs(ae - be) / np.maximum(w.n_particles, 1))),
+            "bars": "1e-5 on forces, 1e-7 per particle on energy"}
+
+
 def run_per_system_loop(w, precision: str, k: int, steps: int):
     """The same replicas, one handle each, stepped one after another: aggregate system
     inner steps per second of that launch loop."""
@@ -714,7 +753,10 @@ def main(argv=None):
                                         / PEAK_TFLOPS["fp32"]) if t32 > 0 else None,
             "energy_drift_per_particle": r32["energy_drift_per_particle"],
             "rvite": r32["rvite"],
+            "error_vs_fp64": fp32_force_error(w, k),
         }
+    if precision == "fp32":  # an FP32-form line states its error against the FP64 path
+        out["error_vs_fp64"] = fp32_force_error(w, k)
     if not args.no_cpu_baseline:
         if w.n_systems == 1 and w.n_total <= 40_000:
             out["cpu_baseline"] = cpu_baseline(w, k)

@@ -59,7 +59,7 @@ typedef enum {
 
 typedef enum {
     MTS_FP64 = 0, /* all force arithmetic in FP64 */
-    MTS_FP32 = 1  /* LJ and ATM arithmetic in FP32; cutoff geometry, accumulation,
+    MTS_FP32 = 1  /* ATM arithmetic in FP32; LJ arithmetic, cutoff geometry, accumulation,
                      integration and energy reductions in FP64 */
 } mts_precision;
 

@@ -664,7 +664,7 @@ mts_status enqueue_pair(mts_system *s, double *f2) {
     a.ushift = s->ushift;
     a.flags = s->flags;
     const long ts = timer_begin(s, 1);
-    HIP_TRY(s, launch_pair(s->st, a, s->fp32));
+    HIP_TRY(s, launch_pair(s->st, a));
     timer_end(s, 1, ts);
     return MTS_OK;
 }
@@ -764,7 +764,7 @@ mts_status enqueue_pair_list(mts_system *s, const Pos4 *xs_in, double *f2, const
         a.half_skin2 = 0.25 * s->lo.skin * s->lo.skin;
     }
     const long ts = timer_begin(s, 1);
-    HIP_TRY(s, launch_pair_list(s->st, a, s->fp32));
+    HIP_TRY(s, launch_pair_list(s->st, a));
     timer_end(s, 1, ts);
     return MTS_OK;
 }
@@ -852,7 +852,7 @@ mts_status enqueue_direct_pair(mts_system *s, const double *x, double *f2, bool 
     a.sigma2 = s->p.sigma * s->p.sigma;
     a.flags = s->flags;
     const long ts = timer_begin(s, 1);
-    HIP_TRY(s, launch_direct_pair(s->st, a, s->fp32));
+    HIP_TRY(s, launch_direct_pair(s->st, a));
     timer_end(s, 1, ts);
     return MTS_OK;
 }

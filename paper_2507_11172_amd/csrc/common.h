@@ -207,7 +207,7 @@ struct PairArgs {
     double eps, sigma2, rc2, ushift;
     int *flags;
 };
-hipError_t launch_pair(hipStream_t st, const PairArgs &a, bool fp32);
+hipError_t launch_pair(hipStream_t st, const PairArgs &a);  // LJ in FP64 in both forms
 
 // Verlet pair list of the pair grid: for every sorted particle p, the sorted indices of
 // all particles within sqrt(rv2) (tile order), nbr[p * nl_cap + s], and their number
@@ -276,7 +276,7 @@ struct PairListArgs {
     int nbin;
     BinGrid bin[2];
 };
-hipError_t launch_pair_list(hipStream_t st, const PairListArgs &a, bool fp32);
+hipError_t launch_pair_list(hipStream_t st, const PairListArgs &a);  // LJ in FP64
 size_t pair_lds_bytes(int stage_cap);
 
 // Lets every LDS-tiled kernel use up to max_bytes of dynamic LDS per workgroup.
@@ -408,7 +408,7 @@ struct DirectPairArgs {
     double eps, sigma2;
     int *flags;
 };
-hipError_t launch_direct_pair(hipStream_t st, const DirectPairArgs &a, bool fp32);
+hipError_t launch_direct_pair(hipStream_t st, const DirectPairArgs &a);  // LJ in FP64
 hipError_t launch_reduce(hipStream_t st, const ReduceArgs &a);
 hipError_t launch_set_int(hipStream_t st, int *p, int v);  // a kernel, so it may be captured
 

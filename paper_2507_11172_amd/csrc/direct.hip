@@ -266,17 +266,11 @@ hipError_t launch_direct_gather(hipStream_t st, const DirectArgs &a, double *f) 
     return hipGetLastError();
 }
 
-hipError_t launch_direct_pair(hipStream_t st, const DirectPairArgs &a, bool fp32) {
+hipError_t launch_direct_pair(hipStream_t st, const DirectPairArgs &a) {
     if (a.n <= 0) return hipSuccess;
     const unsigned blocks = (unsigned)((a.n * kWave + kDirThreads - 1) / kDirThreads);
-    const bool energy = a.pe != nullptr;
-    if (fp32) {
-        if (energy) k_direct_pair<float, true><<<blocks, kDirThreads, 0, st>>>(a);
-        else k_direct_pair<float, false><<<blocks, kDirThreads, 0, st>>>(a);
-    } else {
-        if (energy) k_direct_pair<double, true><<<blocks, kDirThreads, 0, st>>>(a);
-        else k_direct_pair<double, false><<<blocks, kDirThreads, 0, st>>>(a);
-    }
+    if (a.pe != nullptr) k_direct_pair<double, true><<<blocks, kDirThreads, 0, st>>>(a);
+    else k_direct_pair<double, false><<<blocks, kDirThreads, 0, st>>>(a);
     return hipGetLastError();
 }
 

@@ -22,7 +22,10 @@
 //    the particle's r-RESPA update is fused behind the force (one launch per inner
 //    step).  Energies and virials are summed only when asked for (full steps).
 // Cutoff geometry is always FP64 and canonical (bit-identical pair set in both
-// precisions); T is the precision of the LJ arithmetic.  Forces accumulate in FP64.
+// precisions).  The LJ arithmetic is FP64 in both forms of the library: FP32 issues at the
+// FP64 rate here (no packed FP32), and FP32 LJ misses a 1e-5 relative force error for the
+// close pairs of hot, dense systems.  The kernels keep the arithmetic type T as a template
+// parameter.  Forces accumulate in FP64.
 #include "common.h"
 #include "list_build.h"
 
@@ -364,32 +367,25 @@ __global__ void __launch_bounds__(256) k_pair_list(PairListArgs a) {
 }
 
 template <int G>
-static hipError_t launch_pair_list_g(hipStream_t st, const PairListArgs &a, bool fp32) {
+static hipError_t launch_pair_list_g(hipStream_t st, const PairListArgs &a) {
     const int64_t threads = a.n * G;
     const unsigned blocks = (unsigned)((threads + 255) / 256);
     if (blocks == 0) return hipSuccess;
-    const bool energy = a.pe != nullptr;
-    if (fp32) {
-        if (energy) k_pair_list<float, true, G><<<blocks, 256, 0, st>>>(a);
-        else k_pair_list<float, false, G><<<blocks, 256, 0, st>>>(a);
-    } else {
-        if (energy) k_pair_list<double, true, G><<<blocks, 256, 0, st>>>(a);
-        else k_pair_list<double, false, G><<<blocks, 256, 0, st>>>(a);
-    }
+    if (a.pe != nullptr) k_pair_list<double, true, G><<<blocks, 256, 0, st>>>(a);
+    else k_pair_list<double, false, G><<<blocks, 256, 0, st>>>(a);
     return hipGetLastError();
 }
 
-hipError_t launch_pair_list(hipStream_t st, const PairListArgs &a, bool fp32) {
-    if (a.lanes == 8) return launch_pair_list_g<8>(st, a, fp32);
-    if (a.lanes == 16) return launch_pair_list_g<16>(st, a, fp32);
+hipError_t launch_pair_list(hipStream_t st, const PairListArgs &a) {
+    if (a.lanes == 8) return launch_pair_list_g<8>(st, a);
+    if (a.lanes == 16) return launch_pair_list_g<16>(st, a);
     return hipErrorInvalidValue;
 }
 
 hipError_t configure_triplet_lds(size_t max_bytes);
 
 hipError_t configure_kernel_lds(size_t max_bytes) {
-    const void *fns[] = {(const void *)k_pair<double>, (const void *)k_pair<float>,
-                         (const void *)k_list_build};
+    const void *fns[] = {(const void *)k_pair<double>, (const void *)k_list_build};
     for (const void *f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_bytes);
         if (e != hipSuccess) return e;
@@ -397,13 +393,10 @@ hipError_t configure_kernel_lds(size_t max_bytes) {
     return configure_triplet_lds(max_bytes);
 }
 
-hipError_t launch_pair(hipStream_t st, const PairArgs &a, bool fp32) {
+hipError_t launch_pair(hipStream_t st, const PairArgs &a) {
     if (a.ncell <= 0) return hipSuccess;
     const size_t lds = pair_lds_bytes(a.stage_cap);
-    if (fp32)
-        k_pair<float><<<a.ncell, kPairThreads, lds, st>>>(a);
-    else
-        k_pair<double><<<a.ncell, kPairThreads, lds, st>>>(a);
+    k_pair<double><<<a.ncell, kPairThreads, lds, st>>>(a);
     return hipGetLastError();
 }
 

@@ -388,6 +388,44 @@ def test_batched_replicas_forces_vs_oracle():
         off += n
 
 
+
+def test_fp32_form_dense_replicas_within_bars():
+    """FP32 form on three of the 256 replicas of the batched workload (rho 0.87, 0.81 and
+    0.88): per-replica forces within 1e-5 and energies within 1e-7 per particle of the
+    oracle.  With FP32 LJ arithmetic the first two missed the energy bar (about 1.7e-7 and
+    1.2e-7 per particle, from the cancellation in s^12 - s^6 of the many pairs near r =
+    sigma), which is why the FP32 form computes LJ in FP64."""
+    torch = _torch()
+    full = W.batched()
+    starts = np.concatenate([[0], np.cumsum(full.n_particles)])
+    pick = [77, 89, 189]
+    sl = [slice(int(starts[r]), int(starts[r + 1])) for r in pick]
+    w = W.Workload("dense3", np.concatenate([full.x[s] for s in sl]),
+                   np.concatenate([full.v[s] for s in sl]), full.box[pick],
+                   full.n_particles[pick], full.temperature[pick])
+    with _system(w, precision="fp32") as s:
+        x = _dev(w.x)
+        f2, f3 = torch.empty_like(x), torch.empty_like(x)
+        e2 = torch.zeros((w.n_systems, 2), dtype=torch.float64, device="cuda")
+        e3 = torch.zeros((w.n_systems, 2), dtype=torch.float64, device="cuda")
+        s.compute_pair_forces(x, f2, e2)
+        s.compute_triplet_forces(x, f3, e3)
+        s.sync()
+    f2, f3 = f2.cpu().numpy(), f3.cpu().numpy()
+    e = (e2[:, 0] + e3[:, 0]).cpu().numpy()
+    off = 0
+    for r in range(w.n_systems):
+        n = int(w.n_particles[r])
+        rs = slice(off, off + n)
+        r2 = oracle.pair_forces(w.x[rs], w.box[r], rc=w.rc_pair)
+        r3 = oracle.triplet_forces(w.x[rs], w.box[r], rc=w.rc_triplet)
+        err2, err3 = rel_err(f2[rs], r2.f), rel_err(f3[rs], r3.f)
+        de = abs(e[r] - r2.energy - r3.energy) / n
+        print("replica %d (N %d): F2 %.2e  F3 %.2e  dE/N %.2e" % (pick[r], n, err2, err3, de))
+        assert err2 <= 1e-5 and err3 <= 1e-5, pick[r]
+        assert de <= 1e-7, pick[r]
+        off += n
+
 def _class_batch():
     """A liquid-density box with five cells per edge, one too small for three cells per
     edge (two large cells: its triplet tile holds ~1.75 N entries) and one in between."""
