@@ -23,9 +23,9 @@
 //    step).  Energies and virials are summed only when asked for (full steps).
 // Cutoff geometry is always FP64 and canonical (bit-identical pair set in both
 // precisions).  The LJ arithmetic is FP64 in both forms of the library: FP32 issues at the
-// FP64 rate here (no packed FP32), and FP32 LJ misses a 1e-5 relative force error for the
-// close pairs of hot, dense systems.  The kernels keep the arithmetic type T as a template
-// parameter.  Forces accumulate in FP64.
+// FP64 rate here (no packed FP32), and in dense systems FP32 LJ exceeds an energy error of
+// 1e-7 per particle (s^12 - s^6 cancels for the many pairs near r = sigma).  The kernels
+// keep the arithmetic type T as a template parameter.  Forces accumulate in FP64.
 #include "common.h"
 #include "list_build.h"
 
