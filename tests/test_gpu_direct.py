@@ -111,6 +111,28 @@ def test_direct_task_split_sizes(n, split):
     assert np.abs(f3.sum(axis=0)).max() <= 1e-10 * np.abs(f3).sum()
 
 
+@pytest.mark.slow
+def test_direct_aluminium_full_size():
+    """The aluminium scenario at full size (4,995 particles, nu 0.3095; 79 blocks, split
+    into one task per block triple), both forms: forces on 16 seeded particles against the
+    oracle's exact subset mode, the FP32 form against the FP64 path on every particle, the
+    triplet count against C(N, 3)."""
+    w = W.aluminium()
+    x = w.x - w.x.min(axis=0) + 1.0  # positive: the oracle's wrap is the identity
+    n = w.n_total
+    idx = np.sort(W.rng_for(92).choice(n, size=16, replace=False))
+    r2, r3 = oracle.subset_forces(x, BIG, idx, nu=w.nu, rc_pair=RC, rc3=RC)
+    a2, a3, ae2, ae3, count = _gpu_forces([n], x, nu=w.nu)
+    b2, b3, be2, be3, _ = _gpu_forces([n], x, precision="fp32", nu=w.nu)
+    assert count == math.comb(n, 3)
+    for f, ref, bar in ((a2, r2, 1e-12), (a3, r3, 1e-12), (b2, r2, 1e-5), (b3, r3, 1e-5)):
+        rms = np.sqrt(np.mean(np.sum(f * f, axis=1)))
+        assert np.abs(f[idx] - ref).max() <= bar * rms
+    assert rel_err(b2, a2) <= 1e-5 and rel_err(b3, a3) <= 1e-5
+    assert abs((be2[0, 0] + be3[0, 0]) - (ae2[0, 0] + ae3[0, 0])) / n <= 1e-7
+    assert np.abs(a3.sum(axis=0)).max() <= 1e-10 * np.abs(a3).sum()
+
+
 def test_direct_toy_scenario_both_forms():
     """675 particles in a 10^3 domain (the RVITE study's toy scenario), nu 0.3: FP64 at the
     1e-12 bar, the FP32 form at 1e-5 on forces and 1e-7 per particle on energy."""

@@ -426,6 +426,53 @@ def test_fp32_form_dense_replicas_within_bars():
         assert de <= 1e-7, pick[r]
         off += n
 
+
+def _batched_forces(w, precision, tune_ms):
+    torch = _torch()
+    with _system(w, precision=precision) as s:
+        x, v = _dev(w.x), _dev(w.v)
+        s.autotune(x, v, tune_ms)
+        f2, f3 = torch.empty_like(x), torch.empty_like(x)
+        e2 = torch.zeros((w.n_systems, 2), dtype=torch.float64, device="cuda")
+        e3 = torch.zeros((w.n_systems, 2), dtype=torch.float64, device="cuda")
+        s.compute_pair_forces(x, f2, e2)
+        s.compute_triplet_forces(x, f3, e3)
+        s.sync()
+        tuning = s.tuning()
+    return f2.cpu().numpy(), f3.cpu().numpy(), (e2[:, 0] + e3[:, 0]).cpu().numpy(), tuning
+
+
+@pytest.mark.slow
+def test_batched_256_replicas_full_size():
+    """The batched workload at full size (256 replicas, 1.13 M particles), autotuned as the
+    bench runs it: both forms on seeded sampled particles of twelve replicas (the three
+    largest, densest and smallest, three seeded others) against the oracle's exact subset
+    mode; the FP32 form against the FP64 path on every replica (forces 1e-5, energy 1e-7
+    per particle)."""
+    w = W.batched()
+    starts = np.concatenate([[0], np.cumsum(w.n_particles)])
+    a2, a3, ua, ta = _batched_forces(w, "fp64", 1500)
+    b2, b3, ub, tb = _batched_forces(w, "fp32", 1500)
+    print("tuning fp64", ta, "fp32", tb)
+    rho = w.n_particles / np.prod(w.box, axis=1)
+    order = np.argsort(w.n_particles)
+    pick = set(order[-3:]) | set(np.argsort(rho)[-3:]) | set(order[:3])
+    pick |= set(W.rng_for(79).choice(w.n_systems, size=3, replace=False))
+    for r in sorted(int(p) for p in pick):
+        lo, hi = int(starts[r]), int(starts[r + 1])
+        n = hi - lo
+        idx = np.sort(W.rng_for(800 + r).choice(n, size=min(n, 60), replace=False))
+        r2, r3 = oracle.subset_forces(w.x[lo:hi], w.box[r], idx)
+        e = [_subset_bar(f[lo:hi][idx], ref) for f, ref in ((a2, r2), (a3, r3), (b2, r2), (b3, r3))]
+        print("replica %d (N %d, rho %.3f): fp64 %.1e %.1e  fp32 %.1e %.1e" % ((r, n, rho[r]) + tuple(e)))
+        assert e[0] <= 1e-12 and e[1] <= 1e-12, r
+        assert e[2] <= 1e-5 and e[3] <= 1e-5, r
+    for r in range(w.n_systems):
+        lo, hi = int(starts[r]), int(starts[r + 1])
+        assert rel_err(b2[lo:hi], a2[lo:hi]) <= 1e-5, r
+        assert rel_err(b3[lo:hi], a3[lo:hi]) <= 1e-5, r
+        assert abs(ub[r] - ua[r]) / (hi - lo) <= 1e-7, r
+
 def _class_batch():
     """A liquid-density box with five cells per edge, one too small for three cells per
     edge (two large cells: its triplet tile holds ~1.75 N entries) and one in between."""
