@@ -46,7 +46,7 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
 # scaled by the counts of a 256 MiB copy (FETCH_SIZE reads half the copied bytes: factor
 # 2.0; WRITE_SIZE factor 1.0).  Valid for this kernel version only; other workloads,
 # precisions and kernels report null.
-TRIPLET_TRAFFIC_BYTES = {("fcc32k_fp64_k10", "fp64", "k_triplet_and_list"): 37205758}
+TRIPLET_TRAFFIC_BYTES = {("fcc32k_fp64_k10", "fp64", "k_triplet_and_list"): 34036457}
 
 
 def _workload(name: str):
