@@ -203,7 +203,11 @@ enum {
     /* 1 (default): mts_respa_step replays each outer cycle from a captured HIP graph on
      * an internal stream; 0: launches every kernel one by one (same kernels, same order,
      * bitwise-identical results). */
-    MTS_OPT_CYCLE_GRAPH = 1
+    MTS_OPT_CYCLE_GRAPH = 1,
+    /* Lanes per particle of the list force kernel: 4, 8 or 16 (else MTS_ERR_INVALID_ARG).
+     * mts_autotune searches this knob and sets it; results differ between lane counts
+     * only by the order of the per-particle sums.  Takes effect from the next call. */
+    MTS_OPT_LIST_LANES = 2
 };
 
 /* Sets an option (see the MTS_OPT_ constants).  MTS_ERR_INVALID_ARG for unknown options. */
@@ -216,7 +220,7 @@ typedef struct {
     double skin;          /* Verlet pair-list skin in use (0: no list; the pair grid is
                              rebinned every inner step) */
     double cell_factor;   /* triplet cells have edges >= cell_factor * rc_triplet (>= 1) */
-    int32_t list_lanes;   /* lanes per particle of the list force kernel (8 or 16) */
+    int32_t list_lanes;   /* lanes per particle of the list force kernel (4, 8 or 16) */
     int32_t stage_cap;    /* largest triplet tile capacity (particles staged per workgroup)
                              over the tile classes */
     int32_t list_cap;     /* forward-neighbour list capacity per anchor particle */
@@ -237,7 +241,7 @@ typedef struct {
  * (none, 0.15, 0.3, 0.5 sigma; only skins that a particle 1.5 times faster than the
  * fastest one in v would not outrun in one outer cycle), triplet cell factor (1, 1.12,
  * 1.25) and list-kernel
- * lanes (16, 8), searched one knob at a time from the current configuration; each
+ * lanes (16, 8, 4), searched one knob at a time from the current configuration; each
  * candidate gets tile and list capacities sized from the maxima observed on x, a warm-up
  * cycle and the faster of two timed runs of about 4 ms (at least 3 cycles each), and
  * replaces the best so far only if at least 2% faster.  The search stops once budget_ms

@@ -1340,6 +1340,14 @@ mts_status mts_set_option(mts_system *sys, int32_t option, int64_t value) {
         case MTS_OPT_CYCLE_GRAPH:
             sys->use_graph = value != 0;
             return MTS_OK;
+        case MTS_OPT_LIST_LANES:
+            if (value != 4 && value != 8 && value != 16)
+                return fail(sys, MTS_ERR_INVALID_ARG, "list lanes must be 4, 8 or 16");
+            HIP_TRY(sys, hipStreamSynchronize(sys->ist));
+            HIP_TRY(sys, hipStreamSynchronize(sys->st));
+            drop_graphs(sys);  // captured list launches carry the old lane count
+            sys->lo.cfg.lanes = (int)value;
+            return MTS_OK;
         default:
             return fail(sys, MTS_ERR_INVALID_ARG, "unknown option");
     }
@@ -1617,7 +1625,7 @@ mts_status mts_autotune(mts_system *sys, const double *x, const double *v, int32
         auto r = trial(c);
         if (r.first < 0.98 * best.first) best = r;
     }
-    for (int g : {16, 8}) {
+    for (int g : {16, 8, 4}) {
         if (over_budget() || best.second.skin == 0.0) break;
         Config c = best.second;
         if (c.lanes == g) continue;

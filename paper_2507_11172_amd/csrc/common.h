@@ -247,7 +247,7 @@ struct PairListArgs {
     int64_t n;
     const Pos4 *xs;         // current wrapped positions in the list's sorted order
     const int *perm;        // sorted -> input index
-    int lanes;              // lanes per particle: 8 or 16
+    int lanes;              // lanes per particle: 4, 8 or 16
     const int *nbr;         // [n][nl_cap]
     const int *nn;          // [n]
     int nl_cap;

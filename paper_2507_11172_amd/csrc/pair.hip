@@ -16,7 +16,7 @@
 //    wavefront per particle, FP32 distance test, ballot compaction of every neighbour
 //    within rc + skin into the particle's row of the Verlet list.  Runs once per outer
 //    r-RESPA cycle.
-//  * k_pair_list: 8 or 16 lanes per particle (a tuning choice) walk its list row (four
+//  * k_pair_list: 4, 8 or 16 lanes per particle (a tuning choice) walk its list row (four
 //    gathers in flight per lane), a DPP butterfly inside the group combines them in
 //    fixed order, and
 //    the particle's r-RESPA update is fused behind the force (one launch per inner
@@ -181,14 +181,14 @@ __device__ __forceinline__ double dpp_row(double v) {
     return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Sum over G = 8 or 16 consecutive lanes (inside one DPP row); every lane of the group
+// Sum over G = 4, 8 or 16 consecutive lanes (inside one DPP row); every lane of the group
 // ends with the same value.
 template <int G>
 __device__ __forceinline__ double group_sum(double v) {
-    static_assert(G == 8 || G == 16, "groups of 8 or 16 lanes");
+    static_assert(G == 4 || G == 8 || G == 16, "groups of 4, 8 or 16 lanes");
     v += dpp_row<0xB1>(v);   // quad_perm [1,0,3,2]
     v += dpp_row<0x4E>(v);   // quad_perm [2,3,0,1]
-    v += dpp_row<0x141>(v);  // row_half_mirror
+    if (G >= 8) v += dpp_row<0x141>(v);  // row_half_mirror
     if (G == 16) v += dpp_row<0x140>(v);  // row_mirror
     return v;
 }
@@ -377,6 +377,7 @@ static hipError_t launch_pair_list_g(hipStream_t st, const PairListArgs &a) {
 }
 
 hipError_t launch_pair_list(hipStream_t st, const PairListArgs &a) {
+    if (a.lanes == 4) return launch_pair_list_g<4>(st, a);
     if (a.lanes == 8) return launch_pair_list_g<8>(st, a);
     if (a.lanes == 16) return launch_pair_list_g<16>(st, a);
     return hipErrorInvalidValue;

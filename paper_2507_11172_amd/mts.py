@@ -36,6 +36,7 @@ EXPORTS = ("mts_init_system", "mts_destroy_system", "mts_build_cells", "mts_comp
            "mts_list_triplets", "mts_enable_kernel_timing", "mts_kernel_times", "mts_set_option",
            "mts_autotune", "mts_get_tuning")
 MTS_OPT_CYCLE_GRAPH = 1
+MTS_OPT_LIST_LANES = 2
 
 
 class MTSError(RuntimeError):

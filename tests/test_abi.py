@@ -107,6 +107,18 @@ def test_tuning_struct_matches_header(lib):
         assert (ctype == "double") == (t is C.c_double)
 
 
+
+def test_enum_constants_match_header():
+    """Every MTS_ constant the binding defines has the header's value."""
+    from paper_2507_11172_amd import mts
+    hdr = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "mts.h")).read(), flags=re.S)
+    values = {n: int(v) for n, v in re.findall(r"\b(MTS_[A-Z0-9_]+)\s*=\s*(-?\d+)", hdr)}
+    ours = {n: getattr(mts, n) for n in dir(mts) if n.startswith("MTS_OPT_")}
+    assert ours and set(ours) <= set(values)
+    for n, v in ours.items():
+        assert values[n] == v, n
+    assert values["MTS_OPT_LIST_LANES"] == 2
+
 def test_algorithm1_parameters():
     """Algorithm 1's full step delta_t of P sub-steps maps to dt = delta_t / P, k = P; a
     nested handle's full step spans k * k_outer inner steps."""

@@ -234,6 +234,34 @@ def test_respa_pair_list_variants(case, skin):
     assert np.abs(e.cpu().numpy()[:, 0, :] - eo).max() <= 1e-10 * np.abs(eo).max()
 
 
+def test_list_lanes_option():
+    """The list force kernel with 4, 8 and 16 lanes per particle (set through
+    MTS_OPT_LIST_LANES, also between calls on one handle, graphs recaptured): each follows
+    the oracle's trajectory; other lane counts are rejected."""
+    torch = _torch()
+    from paper_2507_11172_amd import mts
+    w = CASES["fcc500"]()
+    box = w.box[0]
+    k, n_iter = 5, 20
+    xo, vo, eo = oracle.respa(w.x, w.v, box, n_iter=n_iter, k=k)
+    with _system(w, k=k, skin=0.3) as s:
+        for g in (4, 16, 8, 4):
+            s.set_option(mts.MTS_OPT_LIST_LANES, g)
+            assert s.tuning()["list_lanes"] == g
+            x, v = _dev(w.x), _dev(w.v)
+            e = torch.zeros((n_iter // k + 1, 1, 5), dtype=torch.float64, device="cuda")
+            s.respa_step(x, v, n_iter, e)
+            s.sync()
+            dx = x.cpu().numpy() - xo
+            dx -= box * np.rint(dx / box)
+            assert np.abs(dx).max() <= 1e-10, g
+            assert np.abs(v.cpu().numpy() - vo).max() <= 1e-10 * np.abs(vo).max(), g
+            assert np.abs(e.cpu().numpy()[:, 0, :] - eo).max() <= 1e-10 * np.abs(eo).max(), g
+        for bad in (0, 2, 12, 32):
+            with pytest.raises(mts.MTSError):
+                s.set_option(mts.MTS_OPT_LIST_LANES, bad)
+
+
 def test_pair_list_skin_violation_is_reported():
     """Particles that outrun half the skin between full steps raise an error at sync."""
     torch = _torch()
