@@ -37,7 +37,7 @@ if ROOT not in sys.path:
 METRIC = "3-body triplets/s + r-RESPA MD steps/s, FP32 vs FP64 GPU at stated force error"
 # Algorithmic work per in-cutoff ATM triplet (edge, ATM arithmetic, three forces and their
 # accumulation; FMA = 2), and the published MI355X vector peaks (the FP32 figure assumes
-# packed FP32 instructions, which this build does not emit: its FP32 arithmetic runs at
+# packed FP32 instructions, which this library does not emit: its FP32 arithmetic runs at
 # the unpacked rate, equal to the FP64 one).
 FLOPS_PER_TRIPLET = 100.0
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
@@ -655,7 +655,7 @@ def main(argv=None):
     ap.add_argument("--al-pbc-eq", type=int, default=2400)
     args = ap.parse_args(argv)
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+        print("bench.py runs on exactly one GPU: this library has no multi-GPU path "
               "(requested --gpus %d)" % args.gpus, file=sys.stderr)
         return 2
 

@@ -54,7 +54,7 @@ typedef enum {
     MTS_ERR_NONFINITE = -5,         /* a force or energy became NaN or infinite */
     MTS_ERR_HIP = -6,               /* a HIP runtime call failed */
     MTS_ERR_OOM = -7,               /* device allocation failed */
-    MTS_ERR_UNSUPPORTED = -8        /* valid input this build does not handle */
+    MTS_ERR_UNSUPPORTED = -8        /* valid input this library does not handle */
 } mts_status;
 
 typedef enum {
