@@ -29,30 +29,40 @@ __global__ void __launch_bounds__(256) k_bin_count(BinArgs a) {
 }
 
 // Exclusive scan of count[0..ncell) into start[0..ncell], start[ncell] = n.  One
-// workgroup of 1024 threads per grid; each thread owns a contiguous chunk of cells.
+// workgroup of 1024 threads per grid walks the cells in tiles of 4,096: each thread loads
+// four consecutive counts (consecutive threads, consecutive 16-byte runs), the workgroup
+// scans the 1,024 thread sums in LDS, and a running carry links the tiles.  The counts
+// are cleared for the next binning.  Integer sums: the result does not depend on the order.
 __global__ void __launch_bounds__(1024) k_scan(BinArgs a) {
     __shared__ int part[1024];
     const BinGrid &g = a.g[blockIdx.x];
     const int ncell = g.ncell;
     const int t = threadIdx.x;
-    const int chunk = (ncell + 1023) / 1024;
-    const int b = t * chunk;
-    const int e = min(ncell, b + chunk);
-    int s = 0;
-    for (int c = b; c < e; ++c) s += g.count[c];
-    part[t] = s;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const int v = t >= off ? part[t - off] : 0;
+    int carry = 0;
+    for (int base = 0; base < ncell; base += 4 * 1024) {
+        const int c0 = base + 4 * t;
+        int v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = c0 + k < ncell ? g.count[c0 + k] : 0;
+        const int s = (v[0] + v[1]) + (v[2] + v[3]);
+        part[t] = s;
         __syncthreads();
-        part[t] += v;
-        __syncthreads();
-    }
-    int run = part[t] - s;  // exclusive prefix of this chunk
-    for (int c = b; c < e; ++c) {
-        g.start[c] = run;
-        run += g.count[c];
-        g.count[c] = 0;  // ready for the next binning
+        for (int off = 1; off < 1024; off <<= 1) {
+            const int u = t >= off ? part[t - off] : 0;
+            __syncthreads();
+            part[t] += u;
+            __syncthreads();
+        }
+        int run = carry + part[t] - s;  // exclusive prefix of this thread's four cells
+        carry += part[1023];
+        __syncthreads();  // every thread has read part[] before the next tile writes it
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (c0 + k < ncell) {
+                g.start[c0 + k] = run;
+                run += v[k];
+                g.count[c0 + k] = 0;
+            }
     }
     if (t == 0) g.start[ncell] = (int)a.n;
 }
