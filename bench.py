@@ -5,11 +5,12 @@ Lennard-Jones forces and the velocity-Verlet updates, plus one Axilrod-Teller-Mu
 evaluation with its kicks and the energy reductions of that full step.  The timed region
 is a single respa_step call of steps * k inner steps on inputs already resident in HBM.
 
-Default workload: 32,000 particles (20^3 FCC cells, rho 0.8, T 0.7, jitter 0.05), LJ
+Default workload: 1,048,576 particles (64^3 FCC cells, rho 0.8, T 0.7, jitter 0.05), LJ
 eps = sigma = 1 with rc 2.5, ATM nu = 0.073 with rc3 2.5, dt 0.001, k = 10, FP64, with
-the FP32 form and the CPU oracle timed beside it.  Other workloads (--workload):
+the FP32 form and the CPU oracle (its exact subset mode on 4,000 seeded particles, scaled
+to the whole system) timed beside it.  Other workloads (--workload):
+  fcc32k   32,000 particles (20^3 FCC cells), k = 10, FP64 (--k to sweep)
   fcc500   500 particles, k = 1 (velocity Verlet), FP64
-  fcc1m    1,048,576 particles (64^3 FCC cells), FP32 form (--k to sweep 1, 5, 10, 20)
   slab25   500,000-particle liquid slab + vapour, 1:1:3 box, rc3 2.5, FP32 form, k = 10
   slab30   the same with rc3 3.0
   batched  256 replicas of 200..20,000 particles in one handle, FP32 form, k = 10, with
@@ -41,12 +42,44 @@ METRIC = "3-body triplets/s + r-RESPA MD steps/s, FP32 vs FP64 GPU at stated for
 # the unpacked rate, equal to the FP64 one).
 FLOPS_PER_TRIPLET = 100.0
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
-# HBM bytes per launch of the FP64 triplet launch with energy records on the default
-# workload, from FETCH_SIZE and WRITE_SIZE counter runs of `bench.py --traffic-probe`
-# scaled by the counts of a 256 MiB copy (FETCH_SIZE reads half the copied bytes: factor
-# 2.0; WRITE_SIZE factor 1.0).  Valid for this kernel version only; other workloads,
-# precisions and kernels report null.
-TRIPLET_TRAFFIC_BYTES = {("fcc32k_fp64_k10", "fp64", "k_triplet_and_list"): 34036457}
+# HBM bytes per launch of the triplet launch, measured by FETCH_SIZE and WRITE_SIZE
+# counter runs of `bench.py --traffic-probe` and scaled by the counts of a 256 MiB copy;
+# stored in profiles/hbm_traffic.json with a hash of the kernel's sources, so that a
+# changed kernel reports null until its counters are taken again.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+TRIPLET_SOURCES = ("triplet.hip", "atm.h", "common.h", "list_build.h")
+# Algorithmic bytes per particle of one list force launch (k_pair_list) besides its list
+# row: own sorted position 32, perm and system index 8, row length 4, F2 written 24, and
+# the fused update of a plain inner step: v read and written 48, previous F2 read 24, x
+# read and written 48, skin reference read 24, drifted sorted position written 24.
+PAIR_BYTES_FIXED = 256
+PAIR_BYTES_PER_ENTRY = 4  # one int32 neighbour index per list entry
+HBM_PEAK_GBS = 8000.0
+
+
+def kernel_sources_sha(names=TRIPLET_SOURCES) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in names:
+        with open(os.path.join(ROOT, "paper_2507_11172_amd", "csrc", name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(workload: str, precision: str, kernel: str):
+    """HBM bytes per launch from the committed counter summary, or None when no counter
+    run covers this workload, precision and kernel at the current sources."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rows = json.load(f)
+    except (OSError, ValueError):
+        return None
+    sha = kernel_sources_sha()
+    for r in rows:
+        if (r.get("workload"), r.get("precision"), r.get("kernel_reported"),
+                r.get("sources_sha")) == (workload, precision, kernel, sha):
+            return r.get("bytes_per_launch")
+    return None
 
 
 def _workload(name: str):
@@ -55,6 +88,7 @@ def _workload(name: str):
         "fcc32k": W.fp64_at_scale,
         "fcc500": W.plain_fp64,
         "fcc1m": lambda: W.precision_form(10),
+        "fcc1m_fp32": lambda: W.precision_form(10, "fp32"),
         "slab25": lambda: W.inhomogeneous(2.5),
         "slab30": lambda: W.inhomogeneous(3.0),
         "batched": W.batched,
@@ -85,6 +119,7 @@ def _drift_stats(en, n_particles):
 
 
 def run_gpu(w, precision: str, k: int, steps: int, warmup: int, tune_ms: int):
+    import numpy as np
     import torch
     from paper_2507_11172_amd import mts
 
@@ -130,13 +165,22 @@ def run_gpu(w, precision: str, k: int, steps: int, warmup: int, tune_ms: int):
         break
 
     # live per-launch HIP-event timing of the force kernels, on the handle's stream (with
-    # the energy records, as in the timed region: the same kernel variants)
-    nt = max(2, min(steps, 20))
+    # the energy records, as in the timed region: the same kernel variants).  Every
+    # respa_step call opens with one evaluation of the entry forces, so two calls of nt1
+    # and nt2 cycles are timed and differenced: what remains is exactly nt2 - nt1 full
+    # steps of the r-RESPA cycle.
+    nt1 = 2
+    nt2 = nt1 + max(2, min(steps, 20))
     sysm.enable_kernel_timing(True)
-    sysm.respa_step(x, v, nt * span,
-                    torch.zeros((nt + 1, w.n_systems, mts.MTS_NE), dtype=torch.float64, device=dev))
-    times = sysm.kernel_times()
+    passes = []
+    for nt in (nt1, nt2):
+        sysm.respa_step(x, v, nt * span, torch.zeros((nt + 1, w.n_systems, mts.MTS_NE),
+                                                     dtype=torch.float64, device=dev))
+        passes.append(sysm.kernel_times())
     sysm.enable_kernel_timing(False)
+    nt = nt2 - nt1
+    times = {c: (passes[1][c][0] - passes[0][c][0], passes[1][c][1] - passes[0][c][1])
+             for c in ("triplet", "pair")}
     n_trip = sysm.count_triplets(x)
     sysm.sync()
     sysm.close()
@@ -149,12 +193,18 @@ def run_gpu(w, precision: str, k: int, steps: int, warmup: int, tune_ms: int):
     drift, rvite = _drift_stats(e.cpu().numpy(), w.n_particles)
     trip_launches, trip_ms = times["triplet"]
     pair_launches, pair_ms = times["pair"]
+    skin = float(tuning.get("skin", 0.0))
+    rv3 = (w.rc_pair + skin) ** 3
+    list_entries = sum(float(n) * (float(n) / float(np.prod(b))) * 4.0 / 3.0 * math.pi * rv3
+                       for n, b in zip(w.n_particles, w.box))
     return {
         "elapsed_s": elapsed,
+        "list_entries_est": list_entries,
         "inner_steps": steps * span,
         "triplets_per_eval": n_trip,
         "inner_class_triplets": n_inner,
         "triplet_ms_per_full_step": trip_ms / nt,
+        "triplet_launches_per_full_step": trip_launches / nt,
         "triplet_kernel_ms": trip_ms / max(trip_launches, 1),
         "pair_kernel_ms": pair_ms / max(pair_launches, 1),
         "energy_drift_per_particle": drift,
@@ -303,6 +353,50 @@ def cpu_baseline(w, k: int):
                       "k=%d pair + 1 triplet evaluations per k inner steps"
                       % (t_pair, t_trip, r3.count, w.n_total, k),
             "triplets_per_s": r3.count / t_trip}
+
+
+SUBSET_SAMPLE = 4000  # particles of the oracle's exact subset mode on large systems
+SUBSET_SAMPLE_SINGLE = 1000  # the same on one thread (a bounded run)
+
+
+def cpu_baseline_subset(w, k: int):
+    """The oracle's exact subset mode on seeded particles of a large system (every pair
+    and triplet holding each sampled particle, found by a scan over all N): 4,000
+    particles on all host cores, 1,000 on one.  Scaled to the whole system: one
+    evaluation of both forces costs N / sample times the sample's.  A cycle of k inner
+    steps needs k pair evaluations and one triplet evaluation; each pair evaluation costs
+    the same O(N) scan per particle as the combined one (the triplet loop adds little),
+    so a cycle is scaled as k combined evaluations.  Triplets/s: the sample's triplet
+    visits / 3 (each triplet is visited from its three members) per second."""
+    import numpy as np
+    import oracle
+    from paper_2507_11172_amd import workloads as W
+    box = w.box[0]
+    n = w.n_total
+    out = {}
+    for label, nthreads, m in (("all", oracle.num_threads(), SUBSET_SAMPLE),
+                               ("single", 1, SUBSET_SAMPLE_SINGLE)):
+        idx = np.sort(W.rng_for(78).choice(n, size=min(m, n), replace=False))
+        t0 = time.perf_counter()
+        _, _, (_, ntrip) = oracle.subset_forces(w.x, box, idx, rc_pair=w.rc_pair, nu=w.nu,
+                                                rc3=w.rc_triplet, nthreads=nthreads, counts=True)
+        t = time.perf_counter() - t0
+        full = t * n / idx.shape[0]  # one whole-system evaluation of F2 and F3
+        out[label] = {"value": k / (k * full), "triplets_per_s": ntrip / 3.0 / t,
+                      "cores": nthreads, "sample_particles": int(idx.shape[0]),
+                      "sample_s": t, "triplet_visits": ntrip}
+    a, one = out["all"], out["single"]
+    return {"value": a["value"], "unit": "MD steps/s", "cores": a["cores"], "kind": "oracle",
+            "cpu": _cpu_model(), "scaled": True,
+            "sample": "exact subset mode (scan of all N per particle, every pair and triplet "
+                      "holding it) on %d seeded particles of the %d-particle system: %.2f s "
+                      "on %d threads, %d triplet visits; scaled by N / %d to a whole-system "
+                      "evaluation, and a cycle of k = %d inner steps as k such evaluations"
+                      % (a["sample_particles"], n, a["sample_s"], a["cores"],
+                         a["triplet_visits"], a["sample_particles"], k),
+            "triplets_per_s": a["triplets_per_s"],
+            "single_thread": {k2: one[k2] for k2 in ("value", "triplets_per_s", "cores",
+                                                     "sample_particles", "sample_s")}}
 
 
 def _cpu_baseline_direct(w, k: int, nthreads: int):
@@ -614,15 +708,52 @@ def traffic_probe(w, precision: str, k: int, tune_ms: int):
           % (w.n_total, b.numel() * 4), flush=True)
 
 
+def _counter_rows(path: str):
+    """(kernel name, dispatch id, counter value) of a rocprofv3 counter-collection CSV;
+    values of one dispatch (one per XCD or instance) are summed."""
+    import csv
+    acc = {}
+    with open(path, newline="") as f:
+        for row in csv.DictReader(f):
+            key = (row["Kernel_Name"], row.get("Dispatch_Id", row.get("Correlation_Id")))
+            acc[key] = acc.get(key, 0.0) + float(row["Counter_Value"])
+    return acc
+
+
+def traffic_summary(fetch_csv: str, write_csv: str, kernel: str, workload: str,
+                    precision: str, copy_kib: float = 262144.0):
+    """HBM bytes per launch of `kernel` (exact demangled name) from a FETCH_SIZE and a
+    WRITE_SIZE counter run of the traffic probe.  Each counter is scaled by what it reads
+    for the probe's plain copy of copy_kib KiB (the largest copy dispatch), so that the
+    result is in the same bytes the copy moves; returns the row for profiles/hbm_traffic.json."""
+    out = {"workload": workload, "precision": precision, "kernel": kernel,
+           "sources_sha": kernel_sources_sha()}
+    total = 0.0
+    for name, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        rows = _counter_rows(path)
+        copy = max((v for (k, _), v in rows.items() if "copyBuffer" in k), default=0.0)
+        vals = [v for (k, _), v in rows.items() if k.startswith(kernel)]
+        if not vals or copy <= 0:
+            raise SystemExit("no %s dispatches of %s or of the calibration copy in %s"
+                             % (name, kernel, path))
+        factor = copy_kib / copy
+        per = sum(vals) / len(vals)
+        out[name] = {"calibration_copy_kib": copy, "factor": factor, "dispatches": len(vals),
+                     "kib_per_dispatch": per, "scaled_kib": per * factor}
+        total += per * factor * 1024.0
+    out["bytes_per_launch"] = int(round(total))
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__,
                                  formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100, help="timed r-RESPA outer cycles")
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="fcc32k")
+    ap.add_argument("--workload", default="fcc1m")
     ap.add_argument("--precision", default="", choices=["", "fp64", "fp32"],
-                    help="default: fp64 for fcc32k and fcc500, the FP32 form otherwise")
+                    help="default: fp64 for fcc1m, fcc32k and fcc500, the FP32 form otherwise")
     ap.add_argument("--k", type=int, default=0, help="override the step-size factor")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32-form", action="store_true")
@@ -630,6 +761,10 @@ def main(argv=None):
                     help="autotuning budget before the timed region (0: default configuration)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only run the kernels of the HBM counter runs, print no bench line")
+    ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="scale the two counter runs of --traffic-probe into HBM bytes per "
+                         "launch of --traffic-kernel and print the JSON row")
+    ap.add_argument("--traffic-kernel", default="k_triplet_and_list<double, true, false>")
     ap.add_argument("--loop-steps", type=int, default=5,
                     help="cycles of the one-handle-per-replica loop (batched workload)")
     ap.add_argument("--rvite-sweep", action="store_true",
@@ -681,6 +816,13 @@ def main(argv=None):
     w = _workload(args.workload)
     k = args.k or w.k
     precision = args.precision or w.precision
+    if args.traffic_summary:
+        kern = args.traffic_kernel.split("<")[0]
+        row = traffic_summary(args.traffic_summary[0], args.traffic_summary[1],
+                              args.traffic_kernel, w.name, precision)
+        row["kernel_reported"] = kern
+        print(json.dumps(row), flush=True)
+        return 0
     if args.traffic_probe:
         traffic_probe(w, precision, k, args.tune_ms)
         return 0
@@ -693,6 +835,9 @@ def main(argv=None):
     trip_s = r["triplet_ms_per_full_step"] * 1e-3
     achieved = FLOPS_PER_TRIPLET * evaluated / trip_s / 1e12 if trip_s > 0 else 0.0
     peak = PEAK_TFLOPS[precision]
+    # list force kernel: algorithmic HBM bytes of one launch over its average duration
+    pair_bytes = (PAIR_BYTES_FIXED * w.n_total + PAIR_BYTES_PER_ENTRY * r["list_entries_est"])
+    pair_s = r["pair_kernel_ms"] * 1e-3
     kernel = "k_triplet_and_list" if r["tuning"].get("shared_launch") else "k_triplet"
     if w.method == "direct":
         kernel = "k_direct_triplet"
@@ -726,7 +871,19 @@ def main(argv=None):
         "rvite": r["rvite"],
         "roofline": {"bound": "alu", "kernel": kernel, "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": TRIPLET_TRAFFIC_BYTES.get((w.name, precision, kernel))},
+                     "traffic": stored_traffic(w.name, precision, kernel),
+                     "flops_per_triplet": FLOPS_PER_TRIPLET,
+                     "triplets_per_launch": evaluated / max(r["triplet_launches_per_full_step"], 1),
+                     "launch_ms": r["triplet_kernel_ms"]},
+        "pair_roofline": {"bound": "hbm", "kernel": "k_pair_list",
+                          "achieved": pair_bytes / pair_s / 1e9 if pair_s > 0 else None,
+                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": pair_bytes / pair_s / 1e9 / HBM_PEAK_GBS if pair_s > 0 else None,
+                          "algorithmic_bytes_per_launch": pair_bytes,
+                          "bytes": "%d B per particle + %d B per list entry (list length "
+                                   "estimated as rho 4/3 pi (rc + skin)^3)"
+                                   % (PAIR_BYTES_FIXED, PAIR_BYTES_PER_ENTRY),
+                          "launch_ms": r["pair_kernel_ms"]},
         "tuning": r["tuning"],
     }
     if w.k_outer > 1:
@@ -751,6 +908,11 @@ def main(argv=None):
             "kernel_ms": {"triplet": r32["triplet_kernel_ms"], "pair": r32["pair_kernel_ms"]},
             "roofline_frac_fp32_peak": (FLOPS_PER_TRIPLET * ev32 / t32 / 1e12
                                         / PEAK_TFLOPS["fp32"]) if t32 > 0 else None,
+            # this library emits no packed FP32: its FP32 arithmetic issues at the FP64
+            # vector rate, the reachable ceiling
+            "roofline_frac_unpacked_fp32": (FLOPS_PER_TRIPLET * ev32 / t32 / 1e12
+                                            / PEAK_TFLOPS["fp64"]) if t32 > 0 else None,
+            "speedup_vs_fp64": (w.n_systems * r32["inner_steps"] / r32["elapsed_s"]) / steps_per_s,
             "energy_drift_per_particle": r32["energy_drift_per_particle"],
             "rvite": r32["rvite"],
             "error_vs_fp64": fp32_force_error(w, k),
@@ -760,6 +922,8 @@ def main(argv=None):
     if not args.no_cpu_baseline:
         if w.n_systems == 1 and w.n_total <= 40_000:
             out["cpu_baseline"] = cpu_baseline(w, k)
+        elif w.n_systems == 1 and w.method != "direct" and w.k_outer == 1:
+            out["cpu_baseline"] = cpu_baseline_subset(w, k)
         else:
             out["cpu_baseline"] = None  # the brute-force oracle is O(N^2) or worse here
     print(json.dumps(out), flush=True)

@@ -61,7 +61,7 @@ def lib():
         L.orc_triplet_list.argtypes = [C.c_int64, _D, _D, C.c_double, _I32, C.c_int64]
         L.orc_triplet_list.restype = C.c_int64
         L.orc_subset.argtypes = [C.c_int64, _D, _D, C.c_double, C.c_double, C.c_double,
-                                 C.c_double, C.c_double, C.c_int64, _I64, _D, _D, C.c_int]
+                                 C.c_double, C.c_double, C.c_int64, _I64, _D, _D, _I64, C.c_int]
         L.orc_respa.argtypes = [C.c_int64, _D, _D, _D, C.POINTER(_MD), C.c_int64, C.c_int, _D]
         L.orc_vv.argtypes = [C.c_int64, _D, _D, _D, C.POINTER(_MD), C.c_int64, _D]
         L.orc_atm_energy.argtypes = [_D, _D, C.c_double]
@@ -150,16 +150,22 @@ def triplet_list(x, box, rc=2.5) -> np.ndarray:
 
 
 def subset_forces(x, box, idx, eps=1.0, sigma=1.0, rc_pair=2.5, nu=0.073, rc3=2.5,
-                  nthreads=0) -> Tuple[np.ndarray, np.ndarray]:
-    """Exact (F2, F3) on the chosen particles of an arbitrarily large system."""
+                  nthreads=0, counts=False):
+    """Exact (F2, F3) on the chosen particles of an arbitrarily large system; with
+    counts=True also (pairs, triplets) summed over the chosen particles (each pair or
+    triplet once per chosen member)."""
     x = _f64(x).reshape(-1, 3)
     box = _f64(box).reshape(3)
     idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int64))
     f2 = np.empty((idx.shape[0], 3))
     f3 = np.empty((idx.shape[0], 3))
+    cnt = np.zeros(2, dtype=np.int64)
     _check(lib().orc_subset(x.shape[0], _d(x), _d(box), eps, sigma, rc_pair, nu, rc3,
-                            idx.shape[0], idx.ctypes.data_as(_I64), _d(f2), _d(f3), nthreads),
+                            idx.shape[0], idx.ctypes.data_as(_I64), _d(f2), _d(f3),
+                            cnt.ctypes.data_as(_I64), nthreads),
            "subset_forces")
+    if counts:
+        return f2, f3, (int(cnt[0]), int(cnt[1]))
     return f2, f3
 
 

@@ -344,10 +344,12 @@ int64_t orc_triplet_list(int64_t n, const double *x, const double *L, double rc,
 
 /* Exact F2 and F3 on a subset of particles of an arbitrarily large system: for each
  * chosen particle p, scan all N particles for its neighbours and sum every pair and
- * every triplet that contains p (p plays the role of i in the formulas above). */
+ * every triplet that contains p (p plays the role of i in the formulas above).
+ * counts (nullable) receives {pairs, triplets} summed over the chosen particles: a pair
+ * or triplet holding two or three of them is counted once per chosen member. */
 int orc_subset(int64_t n, const double *x, const double *L, double eps, double sigma,
                double rc_pair, double nu, double rc3, int64_t ns, const int64_t *idx,
-               double *f2, double *f3, int nthreads) {
+               double *f2, double *f3, int64_t *counts, int nthreads) {
     if (n < 0 || ns < 0 || rc_pair <= 0.0 || rc3 <= 0.0) return ORC_ERR_INVALID_ARG;
     if (!box_ok(L, rc_pair) || !box_ok(L, rc3)) return ORC_ERR_BOX_TOO_SMALL;
     for (int64_t s = 0; s < ns; ++s)
@@ -357,8 +359,9 @@ int orc_subset(int64_t n, const double *x, const double *L, double eps, double s
     double rcp2 = rc_pair * rc_pair, rc32 = rc3 * rc3;
     int nt = nthreads_of(nthreads);
     int failed = 0;
+    int64_t npair = 0, ntrip = 0;
 #ifdef _OPENMP
-#pragma omp parallel for schedule(dynamic, 1) num_threads(nt)
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nt) reduction(+ : npair, ntrip)
 #endif
     for (int64_t s = 0; s < ns; ++s) {
         int64_t p = idx[s];
@@ -374,6 +377,7 @@ int orc_subset(int64_t n, const double *x, const double *L, double eps, double s
                 double fr;
                 (void)lj(r2, eps, sigma, &fr);
                 for (int c = 0; c < 3; ++c) fp2[c] -= fr * d[c];
+                ++npair;
             }
             if (r2 <= rc32) {
                 if (m == cap) {
@@ -392,6 +396,7 @@ int orc_subset(int64_t n, const double *x, const double *L, double eps, double s
                     continue;
                 atm_forces(u, w, v, nu, fi, fj, fk);
                 for (int c = 0; c < 3; ++c) fp3[c] += fi[c];
+                ++ntrip;
             }
         for (int c = 0; c < 3; ++c) {
             f2[3 * s + c] = fp2[c];
@@ -401,6 +406,10 @@ int orc_subset(int64_t n, const double *x, const double *L, double eps, double s
     }
     free(xw);
     if (failed) return ORC_ERR_OOM;
+    if (counts) {
+        counts[0] = npair;
+        counts[1] = ntrip;
+    }
     if (!all_finite(f2, 3 * ns) || !all_finite(f3, 3 * ns)) return ORC_ERR_NONFINITE;
     return ORC_OK;
 }

@@ -218,9 +218,10 @@ def nested_at_scale() -> Workload:
     return w
 
 
-def precision_form(k: int = 10) -> Workload:
-    """1,048,576 particles (64^3 FCC cells), FP32 force form, r-RESPA k in {1,5,10,20}."""
-    return fcc_workload("fcc1m_fp32_k%d" % k, 64, 1003, k=k, n_iter=1000, precision="fp32")
+def precision_form(k: int = 10, precision: str = "fp64") -> Workload:
+    """1,048,576 particles (64^3 FCC cells), r-RESPA k in {1,5,10,20}: the FP64 path and
+    the FP32 form compared on it."""
+    return fcc_workload("fcc1m_k%d" % k, 64, 1003, k=k, n_iter=1000, precision=precision)
 
 
 def fcc4000(seed: int = 1003) -> Workload:

@@ -193,6 +193,17 @@ def test_subset_mode_equals_full_forces(orc):
     assert np.abs(f3 - t.f[idx]).max() <= 1e-12 * np.abs(t.f).max()
 
 
+def test_subset_counts_every_member(orc):
+    """Subset mode over every particle visits each pair from both members and each
+    triplet from all three: twice the pair count and three times the triplet count of
+    the whole-system loops."""
+    x, box = _jittered(seed=13)
+    idx = np.arange(x.shape[0])
+    _, _, (npair, ntrip) = orc.subset_forces(x, box, idx, counts=True)
+    assert npair == 2 * orc.pair_forces(x, box).count
+    assert ntrip == 3 * orc.triplet_forces(x, box).count
+
+
 def test_triplet_list_matches_count_and_order(orc):
     x, box = _jittered(n_cells=3, density=0.8, jitter=0.1, seed=21)
     lst = orc.triplet_list(x, box)
