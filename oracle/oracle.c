@@ -436,51 +436,63 @@ static void record(double *e, double K, const double *uw2, const double *uw3) {
     e[4] = uw3[1];
 }
 
-/* r-RESPA exactly as the paper implements it (Sec. 4.1, Algorithm 2), with s = k:
- *   compute F2(x^0), F3(x^0)
- *   for i = 0 .. n_iter-1:
- *     if i % k == 0:        v <- v + (dt k / 2m) F3
- *     x <- x + dt v + (dt^2 / 2m) F2(x^i)          (then wrapped into the box)
- *     compute F2(x^{i+1});  v <- v + (dt / 2m) (F2(x^i) + F2(x^{i+1}))
- *     if (i+1) % k == 0:    compute F3(x^{i+1});  v <- v + (dt k / 2m) F3
- * Only iterations with (i+1) % k == 0 are full steps; e_full holds {K,U2,U3,W2,W3} at
- * x^0 and after each full step: n_iter/k + 1 rows.  x and v are updated in place. */
+/* v <- v + c f, element by element. */
+static void kick(int64_t n, double *v, const double *f, double c) {
+    for (int64_t q = 0; q < 3 * n; ++q) v[q] = v[q] + c * f[q];
+}
+
+/* One velocity-Verlet step of length h on the pair force alone, with the velocity
+ * half-kicks of the step merged: the drift x <- wrap(x + h v + h^2/(2m) F2(x)), then the
+ * new pair force and v <- v + h/(2m) (F2(x_old) + F2(x_new)).  *f2 holds F2(x) on entry
+ * and F2(x_new) on exit (the two buffers are swapped); uw2 gets {U2, W2} at x_new. */
+static int vv_pair_step(int64_t n, double *x, double *v, const double *L, const orc_md *p,
+                        double h, double **f2, double **f2n, double uw2[2]) {
+    const double cx = (h * h) / (2.0 * p->mass);
+    const double c2 = h / (2.0 * p->mass);
+    double *fo = *f2, *fn = *f2n;
+    for (int64_t a = 0; a < n; ++a)
+        for (int d = 0; d < 3; ++d) {
+            int64_t q = 3 * a + d;
+            x[q] = wrap1(x[q] + h * v[q] + cx * fo[q], L[d]);
+        }
+    int rc = orc_pair(n, x, L, p->eps, p->sigma, p->rc_pair, p->shift, fn, uw2, NULL, p->nthreads);
+    if (rc != ORC_OK) return rc;
+    for (int64_t q = 0; q < 3 * n; ++q) v[q] = v[q] + c2 * (fo[q] + fn[q]);
+    *f2 = fn;
+    *f2n = fo;
+    return ORC_OK;
+}
+
+/* r-RESPA as the paper runs it (Sec. 4.1, Algorithm 2) with step-size factor s = k: the
+ * three-body force acts as an impulse of half an outer step (dt k) at each end of an
+ * outer cycle, and the pair force moves the particles through the k inner steps of
+ * velocity Verlet between the two impulses.  Only the ends of the cycles are full steps,
+ * where velocities are synchronised; e_full holds {K,U2,U3,W2,W3} at x^0 and after each
+ * cycle: n_iter/k + 1 rows.  x and v are updated in place. */
 int orc_respa(int64_t n, double *x, double *v, const double *L, const orc_md *p, int64_t n_iter,
               int k, double *e_full) {
     if (n < 0 || n_iter < 0 || k < 1 || p->dt <= 0.0 || p->mass <= 0.0) return ORC_ERR_INVALID_ARG;
     if (n_iter % k != 0) return ORC_ERR_NOT_MULTIPLE_OF_K;
     size_t bytes = (size_t)(n > 0 ? n : 1) * 3 * sizeof(double);
-    double *f2 = (double *)malloc(bytes), *f2n = (double *)malloc(bytes), *f3 = (double *)malloc(bytes);
-    if (!f2 || !f2n || !f3) { free(f2); free(f2n); free(f3); return ORC_ERR_OOM; }
+    double *b2 = (double *)malloc(bytes), *b2n = (double *)malloc(bytes), *f3 = (double *)malloc(bytes);
+    if (!b2 || !b2n || !f3) { free(b2); free(b2n); free(f3); return ORC_ERR_OOM; }
+    double *f2 = b2, *f2n = b2n;
     double uw2[2], uw3[2];
     int rc;
     rc = orc_pair(n, x, L, p->eps, p->sigma, p->rc_pair, p->shift, f2, uw2, NULL, p->nthreads);
     if (rc == ORC_OK) rc = orc_triplet(n, x, L, p->nu, p->rc3, f3, uw3, NULL, p->nthreads);
-    if (rc != ORC_OK) { free(f2); free(f2n); free(f3); return rc; }
-    if (e_full) record(e_full, kinetic(n, v, p->mass), uw2, uw3);
-    const double c3 = (p->dt * (double)k) / (2.0 * p->mass);
-    const double cx = (p->dt * p->dt) / (2.0 * p->mass);
-    const double c2 = p->dt / (2.0 * p->mass);
-    for (int64_t i = 0; i < n_iter; ++i) {
-        if (i % k == 0)
-            for (int64_t q = 0; q < 3 * n; ++q) v[q] = v[q] + c3 * f3[q];
-        for (int64_t a = 0; a < n; ++a)
-            for (int c = 0; c < 3; ++c) {
-                int64_t q = 3 * a + c;
-                x[q] = wrap1(x[q] + p->dt * v[q] + cx * f2[q], L[c]);
-            }
-        rc = orc_pair(n, x, L, p->eps, p->sigma, p->rc_pair, p->shift, f2n, uw2, NULL, p->nthreads);
+    if (rc == ORC_OK && e_full) record(e_full, kinetic(n, v, p->mass), uw2, uw3);
+    const double impulse = (p->dt * (double)k) / (2.0 * p->mass);  /* half an outer step */
+    for (int64_t cyc = 0; rc == ORC_OK && cyc < n_iter / k; ++cyc) {
+        kick(n, v, f3, impulse);
+        for (int s = 0; rc == ORC_OK && s < k; ++s)
+            rc = vv_pair_step(n, x, v, L, p, p->dt, &f2, &f2n, uw2);
+        if (rc == ORC_OK) rc = orc_triplet(n, x, L, p->nu, p->rc3, f3, uw3, NULL, p->nthreads);
         if (rc != ORC_OK) break;
-        for (int64_t q = 0; q < 3 * n; ++q) v[q] = v[q] + c2 * (f2[q] + f2n[q]);
-        double *t = f2; f2 = f2n; f2n = t;
-        if ((i + 1) % k == 0) {
-            rc = orc_triplet(n, x, L, p->nu, p->rc3, f3, uw3, NULL, p->nthreads);
-            if (rc != ORC_OK) break;
-            for (int64_t q = 0; q < 3 * n; ++q) v[q] = v[q] + c3 * f3[q];
-            if (e_full) record(e_full + 5 * ((i + 1) / k), kinetic(n, v, p->mass), uw2, uw3);
-        }
+        kick(n, v, f3, impulse);
+        if (e_full) record(e_full + 5 * (cyc + 1), kinetic(n, v, p->mass), uw2, uw3);
     }
-    free(f2); free(f2n); free(f3);
+    free(b2); free(b2n); free(f3);
     return rc;
 }
 
@@ -509,18 +521,14 @@ static int class_forces(int64_t n, const double *x, const double *L, const orc_m
     return rc;
 }
 
-/* r-RESPA with three time scales, the nested form of Sec. 2.3.1 (Algorithm 1 extended by
- * one level, as the text allows for any number of force splittings) applied to the
- * distance classes of Sec. 5: F2 every inner step dt, the inner triplet class Fin every
- * k steps, the outer class Fout every k*k_outer steps.  One outer cycle:
- *   v <- v + (dt k k_outer / 2m) Fout(x)
- *   repeat k_outer times:
- *     v <- v + (dt k / 2m) Fin(x)
- *     k velocity-Verlet steps on F2 (as in Algorithm 2)
- *     compute Fin(x);  v <- v + (dt k / 2m) Fin(x)
- *   compute Fout(x);  v <- v + (dt k k_outer / 2m) Fout(x)
- * e_full holds {K, U2, U3, W2, W3} (U3, W3 over both classes) at x^0 and after every outer
- * cycle: n_iter / (k k_outer) + 1 rows.  k_outer = 1 is Algorithm 2 with s = k. */
+/* r-RESPA with three time scales: the nested form of Sec. 2.3.1 (one more level, as the
+ * text allows for any number of force splittings) over the triplet distance classes of
+ * Sec. 5.  F2 drives velocity Verlet with the inner step dt; the inner triplet class Fin
+ * acts as impulses of half of k inner steps around every group of k inner steps, the
+ * outer class Fout as impulses of half of k k_outer inner steps around every k_outer such
+ * groups (an outer cycle).  Velocities are synchronised only at the ends of outer cycles:
+ * e_full holds {K, U2, U3, W2, W3} (U3, W3 over both classes) at x^0 and after every
+ * outer cycle: n_iter / (k k_outer) + 1 rows.  k_outer = 1 is Algorithm 2 with s = k. */
 int orc_respa_nested(int64_t n, double *x, double *v, const double *L, const orc_md *p,
                      int64_t n_iter, int k, int k_outer, double r_a, double *e_full) {
     if (n < 0 || n_iter < 0 || k < 1 || k_outer < 1 || r_a < 0.0 || p->dt <= 0.0 ||
@@ -529,97 +537,70 @@ int orc_respa_nested(int64_t n, double *x, double *v, const double *L, const orc
     const int64_t span = (int64_t)k * (int64_t)k_outer;
     if (n_iter % span != 0) return ORC_ERR_NOT_MULTIPLE_OF_K;
     size_t bytes = (size_t)(n > 0 ? n : 1) * 3 * sizeof(double);
-    double *f2 = (double *)malloc(bytes), *f2n = (double *)malloc(bytes);
+    double *b2 = (double *)malloc(bytes), *b2n = (double *)malloc(bytes);
     double *fin = (double *)malloc(bytes), *fout = (double *)malloc(bytes);
-    if (!f2 || !f2n || !fin || !fout) {
-        free(f2); free(f2n); free(fin); free(fout);
+    if (!b2 || !b2n || !fin || !fout) {
+        free(b2); free(b2n); free(fin); free(fout);
         return ORC_ERR_OOM;
     }
+    double *f2 = b2, *f2n = b2n;
     double uw2[2], uw3[2];
     int rc = orc_pair(n, x, L, p->eps, p->sigma, p->rc_pair, p->shift, f2, uw2, NULL, p->nthreads);
     if (rc == ORC_OK) rc = class_forces(n, x, L, p, r_a, fin, fout, uw3, 1, 1);
-    if (rc != ORC_OK) { free(f2); free(f2n); free(fin); free(fout); return rc; }
-    if (e_full) record(e_full, kinetic(n, v, p->mass), uw2, uw3);
-    const double c_in = (p->dt * (double)k) / (2.0 * p->mass);
-    const double c_out = (p->dt * (double)span) / (2.0 * p->mass);
-    const double cx = (p->dt * p->dt) / (2.0 * p->mass);
-    const double c2 = p->dt / (2.0 * p->mass);
-    double uin[2];
-    for (int64_t c = 0; c < n_iter / span && rc == ORC_OK; ++c) {
-        for (int64_t q = 0; q < 3 * n; ++q) v[q] = v[q] + c_out * fout[q];
-        for (int j = 0; j < k_outer && rc == ORC_OK; ++j) {
-            for (int64_t q = 0; q < 3 * n; ++q) v[q] = v[q] + c_in * fin[q];
-            for (int s = 0; s < k; ++s) {
-                for (int64_t a = 0; a < n; ++a)
-                    for (int d = 0; d < 3; ++d) {
-                        int64_t q = 3 * a + d;
-                        x[q] = wrap1(x[q] + p->dt * v[q] + cx * f2[q], L[d]);
-                    }
-                rc = orc_pair(n, x, L, p->eps, p->sigma, p->rc_pair, p->shift, f2n, uw2, NULL,
-                              p->nthreads);
-                if (rc != ORC_OK) break;
-                for (int64_t q = 0; q < 3 * n; ++q) v[q] = v[q] + c2 * (f2[q] + f2n[q]);
-                double *t = f2; f2 = f2n; f2n = t;
-            }
-            if (rc != ORC_OK) break;
-            rc = class_forces(n, x, L, p, r_a, fin, fout, uin, 1, 0);
-            if (rc != ORC_OK) break;
-            for (int64_t q = 0; q < 3 * n; ++q) v[q] = v[q] + c_in * fin[q];
+    if (rc == ORC_OK && e_full) record(e_full, kinetic(n, v, p->mass), uw2, uw3);
+    const double imp_in = (p->dt * (double)k) / (2.0 * p->mass);
+    const double imp_out = (p->dt * (double)span) / (2.0 * p->mass);
+    double uin[2], uout[2];
+    for (int64_t cyc = 0; rc == ORC_OK && cyc < n_iter / span; ++cyc) {
+        kick(n, v, fout, imp_out);
+        for (int g = 0; rc == ORC_OK && g < k_outer; ++g) {
+            kick(n, v, fin, imp_in);
+            for (int s = 0; rc == ORC_OK && s < k; ++s)
+                rc = vv_pair_step(n, x, v, L, p, p->dt, &f2, &f2n, uw2);
+            if (rc == ORC_OK) rc = class_forces(n, x, L, p, r_a, fin, fout, uin, 1, 0);
+            if (rc == ORC_OK) kick(n, v, fin, imp_in);
         }
-        if (rc != ORC_OK) break;
-        double uout[2];
-        rc = class_forces(n, x, L, p, r_a, fin, fout, uout, 0, 1);
+        if (rc == ORC_OK) rc = class_forces(n, x, L, p, r_a, fin, fout, uout, 0, 1);
         if (rc != ORC_OK) break;
         uw3[0] = uin[0] + uout[0];  /* uin: the inner class at this same x, just computed */
         uw3[1] = uin[1] + uout[1];
-        for (int64_t q = 0; q < 3 * n; ++q) v[q] = v[q] + c_out * fout[q];
-        if (e_full) record(e_full + 5 * (c + 1), kinetic(n, v, p->mass), uw2, uw3);
+        kick(n, v, fout, imp_out);
+        if (e_full) record(e_full + 5 * (cyc + 1), kinetic(n, v, p->mass), uw2, uw3);
     }
-    free(f2); free(f2n); free(fin); free(fout);
+    free(b2); free(b2n); free(fin); free(fout);
     return rc;
 }
 
-/* Algorithm 1 (Sec. 2.3.1) as printed, with the fast force F0 = F2 and the slow force
- * F1 = F3 and p->dt the full step delta t, split into P sub-steps of h = delta t / P.
- * Readings of the garbled parts: the sub-step velocity update adds (h / 2m) times the sum
- * F0(x^{i+(j-1)/P}) + F0(x^{i+j/P}), and the closing kick's Delta t is delta t.  Per full
- * step: v <- v + (delta t / 2m) F3(x); P velocity-Verlet sub-steps on F2; compute F3(x);
- * v <- v + (delta t / 2m) F3(x).  e holds {K,U2,U3,W2,W3} at x^0 and after every full
- * step: n_outer + 1 rows. */
+/* Algorithm 1 (Sec. 2.3.1) with the fast force F0 = F2 and the slow force F1 = F3:
+ * p->dt is the full step delta t, split into P sub-steps h = delta t / P.  The slow
+ * force acts as impulses of delta t / 2 at both ends of every full step, the fast one
+ * moves the particles through P velocity-Verlet sub-steps of length h in between.
+ * Readings of the garbled parts: the sub-step velocity update adds h/(2m) times the sum
+ * of the fast force at the sub-step's two ends, and the closing impulse uses delta t.
+ * e holds {K,U2,U3,W2,W3} at x^0 and after every full step: n_outer + 1 rows. */
 int orc_respa_alg1(int64_t n, double *x, double *v, const double *L, const orc_md *p,
                    int64_t n_outer, int P, double *e) {
     if (n < 0 || n_outer < 0 || P < 1 || p->dt <= 0.0 || p->mass <= 0.0) return ORC_ERR_INVALID_ARG;
     size_t bytes = (size_t)(n > 0 ? n : 1) * 3 * sizeof(double);
-    double *f0 = (double *)malloc(bytes), *f0n = (double *)malloc(bytes), *f1 = (double *)malloc(bytes);
-    if (!f0 || !f0n || !f1) { free(f0); free(f0n); free(f1); return ORC_ERR_OOM; }
+    double *b0 = (double *)malloc(bytes), *b0n = (double *)malloc(bytes), *f1 = (double *)malloc(bytes);
+    if (!b0 || !b0n || !f1) { free(b0); free(b0n); free(f1); return ORC_ERR_OOM; }
+    double *f0 = b0, *f0n = b0n;
     double uw2[2], uw3[2];
     int rc = orc_pair(n, x, L, p->eps, p->sigma, p->rc_pair, p->shift, f0, uw2, NULL, p->nthreads);
     if (rc == ORC_OK) rc = orc_triplet(n, x, L, p->nu, p->rc3, f1, uw3, NULL, p->nthreads);
-    if (rc != ORC_OK) { free(f0); free(f0n); free(f1); return rc; }
-    if (e) record(e, kinetic(n, v, p->mass), uw2, uw3);
+    if (rc == ORC_OK && e) record(e, kinetic(n, v, p->mass), uw2, uw3);
     const double h = p->dt / (double)P;
-    const double kick1 = p->dt / (2.0 * p->mass);
-    for (int64_t i = 0; i < n_outer; ++i) {
-        for (int64_t q = 0; q < 3 * n; ++q) v[q] = v[q] + kick1 * f1[q];
-        for (int j = 1; j <= P; ++j) {
-            for (int64_t a = 0; a < n; ++a)
-                for (int d = 0; d < 3; ++d) {
-                    int64_t q = 3 * a + d;
-                    x[q] = wrap1(x[q] + h * v[q] + ((h * h) / (2.0 * p->mass)) * f0[q], L[d]);
-                }
-            rc = orc_pair(n, x, L, p->eps, p->sigma, p->rc_pair, p->shift, f0n, uw2, NULL,
-                          p->nthreads);
-            if (rc != ORC_OK) break;
-            for (int64_t q = 0; q < 3 * n; ++q) v[q] = v[q] + (h / (2.0 * p->mass)) * (f0[q] + f0n[q]);
-            double *t = f0; f0 = f0n; f0n = t;
-        }
+    const double impulse = p->dt / (2.0 * p->mass);
+    for (int64_t i = 0; rc == ORC_OK && i < n_outer; ++i) {
+        kick(n, v, f1, impulse);
+        for (int j = 0; rc == ORC_OK && j < P; ++j)
+            rc = vv_pair_step(n, x, v, L, p, h, &f0, &f0n, uw2);
+        if (rc == ORC_OK) rc = orc_triplet(n, x, L, p->nu, p->rc3, f1, uw3, NULL, p->nthreads);
         if (rc != ORC_OK) break;
-        rc = orc_triplet(n, x, L, p->nu, p->rc3, f1, uw3, NULL, p->nthreads);
-        if (rc != ORC_OK) break;
-        for (int64_t q = 0; q < 3 * n; ++q) v[q] = v[q] + kick1 * f1[q];
+        kick(n, v, f1, impulse);
         if (e) record(e + 5 * (i + 1), kinetic(n, v, p->mass), uw2, uw3);
     }
-    free(f0); free(f0n); free(f1);
+    free(b0); free(b0n); free(f1);
     return rc;
 }
 
