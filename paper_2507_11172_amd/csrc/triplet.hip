@@ -50,10 +50,11 @@ namespace mts {
 
 constexpr int kTripWaves = 4;
 constexpr int kTripThreads = kTripWaves * kWave;
-// Hit queue: evaluated two hits per lane once 2 x 64 are pending; one round of tests
-// pushes at most 2 x 64 more.
-constexpr int kQueueCap = 4 * kWave;   // a ring: at most 2 x 64 pending + 2 x 64 pushed
+// Hit queue: evaluated EV hits per lane once EV x 64 are pending; one round of tests
+// pushes at most 64 more.
+constexpr int kQueueCap = 4 * kWave;   // a ring: fewer than EV x 64 pending + 64 pushed
 constexpr int kQueueMask = kQueueCap - 1;
+constexpr int EV = 1;                  // queued hits evaluated per lane at a time (1 or 2)
 
 // Number of set bits of mask in the lanes below this one.
 __device__ __forceinline__ int below(uint64_t mask) {
@@ -486,118 +487,104 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
             }
             return in;
         };
-        // Two queued hits per lane, computed as two independent straight-line chains
-        // (lanes without a second hit recompute their first, lanes without any hit
-        // compute on entry 0; such results are selected away).  The register sums take
-        // both chains unconditionally, which keeps the compiler from sinking the second
-        // chain behind the first one's scatter.
+        // EV queued hits per lane, computed as independent straight-line chains (lanes
+        // without a hit compute on the first pending entry; such results are selected
+        // away).  The register sums take every chain unconditionally, which keeps the
+        // compiler from sinking a chain behind another one's scatter.
         auto evaluate = [&](int cnt) {
-            const bool v1 = lane < cnt, v2 = lane + kWave < cnt;
-            const int e1 = v1 ? Q[(qh + lane) & kQueueMask] : 0;
-            const int e2 = v2 ? Q[(qh + kWave + lane) & kQueueMask] : e1;
+            const bool v1 = lane < cnt, v2 = EV == 2 && lane + kWave < cnt;
+            const int e1 = Q[(qh + (v1 ? lane : 0)) & kQueueMask];
+            const int e2 = EV == 2 && v2 ? Q[(qh + kWave + lane) & kQueueMask] : e1;
             qh += cnt;
-            const int j1 = e1 & 0xff, k1 = e1 >> 8, j2 = e2 & 0xff, k2 = e2 >> 8;
-            const ListEnt<T> uj1 = L.u.get(j1), uk1 = L.u.get(k1), uj2 = L.u.get(j2), uk2 = L.u.get(k2);
-            T nu1 = nu, nu2 = nu;
-            double iw1 = 1.0, iw2 = 1.0;  // unscale the energy terms of weighted triplets
+            const int j1 = e1 & 0xff, k1 = e1 >> 8;
+            const ListEnt<T> uj1 = L.u.get(j1), uk1 = L.u.get(k1);
+            T nu1 = nu;
+            double iw1 = 1.0;  // unscales the energy terms of weighted triplets
             if constexpr (WEIGHT) {
-                const bool in1 = inner_class(j1, k1, uj1, uk1), in2 = inner_class(j2, k2, uj2, uk2);
+                const bool in1 = inner_class(j1, k1, uj1, uk1);
                 nu1 = in1 ? nu : nu_out;
-                nu2 = in2 ? nu : nu_out;
                 iw1 = in1 ? 1.0 : inv_w;
-                iw2 = in2 ? 1.0 : inv_w;
             }
             const AtmOut<T> o1 = atm_triplet<T>(uj1, uk1, nu1);
-            const AtmOut<T> o2 = atm_triplet<T>(uj2, uk2, nu2);
             fax += v1 ? (double)o1.fix : 0.0;
             fay += v1 ? (double)o1.fiy : 0.0;
             faz += v1 ? (double)o1.fiz : 0.0;
-            fax += v2 ? (double)o2.fix : 0.0;
-            fay += v2 ? (double)o2.fiy : 0.0;
-            faz += v2 ? (double)o2.fiz : 0.0;
             if (ENERGY) {
+                U += v1 ? (double)o1.phi * iw1 : 0.0;
+                W += v1 ? (double)o1.vir * iw1 : 0.0;
+            }
+            if constexpr (EV == 2) {
+                const int j2 = e2 & 0xff, k2 = e2 >> 8;
+                const ListEnt<T> uj2 = L.u.get(j2), uk2 = L.u.get(k2);
+                T nu2 = nu;
+                double iw2 = 1.0;
                 if constexpr (WEIGHT) {
-                    U += v1 ? (double)o1.phi * iw1 : 0.0;
-                    W += v1 ? (double)o1.vir * iw1 : 0.0;
+                    const bool in2 = inner_class(j2, k2, uj2, uk2);
+                    nu2 = in2 ? nu : nu_out;
+                    iw2 = in2 ? 1.0 : inv_w;
+                }
+                const AtmOut<T> o2 = atm_triplet<T>(uj2, uk2, nu2);
+                fax += v2 ? (double)o2.fix : 0.0;
+                fay += v2 ? (double)o2.fiy : 0.0;
+                faz += v2 ? (double)o2.fiz : 0.0;
+                if (ENERGY) {
                     U += v2 ? (double)o2.phi * iw2 : 0.0;
                     W += v2 ? (double)o2.vir * iw2 : 0.0;
-                } else {
-                    U += v1 ? (double)o1.phi : 0.0;
-                    W += v1 ? (double)o1.vir : 0.0;
-                    U += v2 ? (double)o2.phi : 0.0;
-                    W += v2 ? (double)o2.vir : 0.0;
                 }
+                if (v1) scatter(o1, j1, k1);
+                if (v2) scatter(o2, j2, k2);
+            } else {
+                if (v1) scatter(o1, j1, k1);
             }
-            if (v1) scatter(o1, j1, k1);
-            if (v2) scatter(o2, j2, k2);
             __builtin_amdgcn_wave_barrier();
         };
 
-        if (m >= 2) {
-            const int D = m >> 1;
-            const bool even = (m & 1) == 0;
-            // Lane -> (j, phase): with P = max(1, 64 / m) phases, lane l takes entry
-            // j = jb + l % span and the circular distances dd = 1 + phase, 1 + phase + P,
-            // 1 + phase + 2P, ... (two per round), so all m(m-1)/2 unordered pairs are
-            // tested once: dd <= D, and for even m the distance D only from j < D.
-            const int P = m < kWave ? kWave / m : 1;
-            const int span = m < kWave ? m : kWave;
-            for (int jb = 0; jb < m; jb += span) {
-                const int j = jb + lane % span;
-                const int phase = lane / span;
-                // largest distance this lane tests (-1: idle lane)
-                const int Dj = (phase < P && j < m) ? ((even && j >= D) ? D - 1 : D) : -1;
-                const ListEnt<float> fj = L.f[Dj >= 0 ? j : 0];
-                int dd = 1 + phase;
-                int k1 = j + dd;
-                k1 -= k1 >= m ? m : 0;
-                for (int d0 = 1; d0 <= D; d0 += 2 * P) {
-                    int k2 = k1 + P;
-                    k2 -= k2 >= m ? m : 0;
-                    const bool c1 = dd <= Dj, c2 = dd + P <= Dj;  // c2 implies c1
-                    const ListEnt<float> fk1 = L.f[c1 ? k1 : 0];
-                    const ListEnt<float> fk2 = L.f[c2 ? k2 : 0];
-                    const float vx1 = fk1.ux - fj.ux, vy1 = fk1.uy - fj.uy, vz1 = fk1.uz - fj.uz;
-                    const float vx2 = fk2.ux - fj.ux, vy2 = fk2.uy - fj.uy, vz2 = fk2.uz - fj.uz;
-                    const float q1 = (vx1 * vx1 + vy1 * vy1) + vz1 * vz1;
-                    const float q2 = (vx2 * vx2 + vy2 * vy2) + vz2 * vz2;
-                    bool hit1 = c1 && q1 <= jk_lo, hit2 = c2 && q2 <= jk_lo;
-                    const bool amb1 = c1 && q1 > jk_lo && q1 <= jk_hi;
-                    const bool amb2 = c2 && q2 > jk_lo && q2 <= jk_hi;
-                    if (__ballot(amb1 || amb2)) {  // rare: settle with the FP64 test
-                        if (amb1 || amb2) {
-                            const PosEnt ej = unpack(tile_get(tile, tix(L.t[j])), L0, L1, L2);
-                            const PosEnt ek = unpack(tile_get(tile, tix(L.t[amb1 ? k1 : k2])), L0, L1, L2);
-                            const double vx = disp1(ej.x, ek.x, ek.sx - ej.sx);
-                            const double vy = disp1(ej.y, ek.y, ek.sy - ej.sy);
-                            const double vz = disp1(ej.z, ek.z, ek.sz - ej.sz);
-                            const bool h = norm2(vx, vy, vz) <= rc2;
-                            if (amb1) hit1 = h;
-                            else hit2 = h;
-                            if (amb1 && amb2) {
-                                const PosEnt ek2 = unpack(tile_get(tile, tix(L.t[k2])), L0, L1, L2);
-                                const double wx = disp1(ej.x, ek2.x, ek2.sx - ej.sx);
-                                const double wy = disp1(ej.y, ek2.y, ek2.sy - ej.sy);
-                                const double wz = disp1(ej.z, ek2.z, ek2.sz - ej.sz);
-                                hit2 = norm2(wx, wy, wz) <= rc2;
-                            }
-                        }
+        // ---- B: the j-k test of every unordered list pair, 64 per round.  Pair item
+        // q = (dd - 1) m + j stands for (j, k = (j + dd) mod m): diagonals dd = 1, 2, ...
+        // of the circulant, each a permutation of the list; for even m the last diagonal
+        // dd = m/2 pairs each entry with its opposite, and its first half (j < m/2) covers
+        // those pairs once, so q < m(m - 1)/2 visits every pair exactly once with all
+        // lanes busy.  Lane l starts at q = l and advances by 64 per round.
+        const int npair = m * (m - 1) / 2;
+        if (npair > 0) {
+            const int adv_d = kWave / m, adv_j = kWave - adv_d * m;  // 64 = adv_d m + adv_j
+            int dd = (int)(((float)lane + 0.5f) / (float)m);
+            int j = lane - dd * m;
+            if (j >= m) { j -= m; ++dd; }
+            if (j < 0) { j += m; --dd; }
+            ++dd;
+            for (int q0 = 0; q0 < npair; q0 += kWave) {
+                const bool valid = q0 + lane < npair;  // false only in the last round
+                int k = j + dd;
+                k -= k >= m ? m : 0;
+                const ListEnt<float> fj = L.f[valid ? j : 0];
+                const ListEnt<float> fk = L.f[valid ? k : 0];
+                const float vx = fk.ux - fj.ux, vy = fk.uy - fj.uy, vz = fk.uz - fj.uz;
+                const float q2 = (vx * vx + vy * vy) + vz * vz;
+                bool hit = valid && q2 <= jk_lo;
+                const bool amb = valid && q2 > jk_lo && q2 <= jk_hi;
+                if (__ballot(amb)) {  // rare: settle with the canonical FP64 test
+                    if (amb) {
+                        const PosEnt ej = unpack(tile_get(tile, tix(L.t[j])), L0, L1, L2);
+                        const PosEnt ek = unpack(tile_get(tile, tix(L.t[k])), L0, L1, L2);
+                        const double wx = disp1(ej.x, ek.x, ek.sx - ej.sx);
+                        const double wy = disp1(ej.y, ek.y, ek.sy - ej.sy);
+                        const double wz = disp1(ej.z, ek.z, ek.sz - ej.sz);
+                        hit = norm2(wx, wy, wz) <= rc2;
                     }
-                    // append the hits to the ring queue, lane order, first then second
-                    const uint64_t m1 = __ballot(hit1), m2 = __ballot(hit2);
-                    const int n1 = __popcll(m1);
-                    if (hit1) Q[(qt + below(m1)) & kQueueMask] = (unsigned short)(j | (k1 << 8));
-                    if (hit2) Q[(qt + n1 + below(m2)) & kQueueMask] = (unsigned short)(j | (k2 << 8));
-                    qt += n1 + __popcll(m2);
-                    __builtin_amdgcn_wave_barrier();
-                    if (qt - qh >= 2 * kWave) {
-                        evaluate(2 * kWave);
-                        ntrip += 2 * kWave;
-                    }
-                    dd += 2 * P;
-                    k1 = k2 + P;
-                    k1 -= k1 >= m ? m : 0;
                 }
+                // append the hits to the ring queue in lane order
+                const uint64_t mh = __ballot(hit);
+                if (hit) Q[(qt + below(mh)) & kQueueMask] = (unsigned short)(j | (k << 8));
+                qt += __popcll(mh);
+                __builtin_amdgcn_wave_barrier();
+                if (qt - qh >= EV * kWave) {
+                    evaluate(EV * kWave);
+                    ntrip += EV * kWave;
+                }
+                j += adv_j;
+                dd += adv_d;
+                if (j >= m) { j -= m; ++dd; }
             }
             if (qt > qh) {
                 ntrip += qt - qh;
