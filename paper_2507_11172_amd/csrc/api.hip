@@ -40,6 +40,8 @@ struct Grid {
     int *rank = nullptr;          // [n] atomic arrival rank in the cell
     int *count = nullptr;         // [ncell] histogram (kept zero between binnings)
     int *start = nullptr;         // [ncell + 1]
+    int *start_loc = nullptr;     // [ncell] tile-local prefix of the scan
+    int *tile_sum = nullptr;      // [2 ntile + 1] scan tile totals, offsets and counter
     int *perm_tmp = nullptr;      // [n] unordered scatter
     int *perm = nullptr;          // [n] sorted -> input
     int *inv_perm = nullptr;      // [n] input -> sorted
@@ -277,6 +279,10 @@ mts_status alloc_grid(mts_system *s, Grid &g) {
     HIP_TRY(s, dalloc(&g.rank, n));
     HIP_TRY(s, dalloc(&g.count, g.ncell));
     HIP_TRY(s, dalloc(&g.start, (size_t)g.ncell + 1));
+    const size_t ntile = ((size_t)g.ncell + kScanTile - 1) / kScanTile;
+    HIP_TRY(s, dalloc(&g.start_loc, (size_t)g.ncell));
+    HIP_TRY(s, dalloc(&g.tile_sum, 2 * ntile + 1));
+    HIP_TRY(s, hipMemset(g.tile_sum, 0, sizeof(int) * (2 * ntile + 1)));
     HIP_TRY(s, dalloc(&g.perm_tmp, n));
     HIP_TRY(s, dalloc(&g.perm, n));
     HIP_TRY(s, dalloc(&g.inv_perm, n));
@@ -294,7 +300,7 @@ mts_status alloc_grid(mts_system *s, Grid &g) {
 }
 
 void free_grid(Grid &g) {
-    void *ptrs[] = {g.sd, g.sys_of_cell, g.cell_of, g.rank, g.count, g.start, g.perm_tmp,
+    void *ptrs[] = {g.sd, g.sys_of_cell, g.cell_of, g.rank, g.count, g.start, g.start_loc, g.tile_sum, g.perm_tmp,
                     g.perm, g.inv_perm, g.xs, g.xs2};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -325,10 +331,13 @@ double effective_skin(const mts_system *s, double skin) {
 // Largest tile capacity (a multiple of 32) whose triplet workgroup fits `limit` bytes of
 // LDS with lists of lc entries.
 int cap_for_lds(const mts_system *s, int lc, size_t limit) {
-    const size_t fixed = triplet_lds_bytes(0, lc, s->fp32);
-    const size_t per = triplet_lds_bytes(1, lc, s->fp32) - fixed;
-    if (limit < fixed) return 0;
-    return (int)std::min<size_t>(4096, (limit - fixed) / per) / 32 * 32;
+    int lo = 0, hi = 4096 / 32;  // in units of 32 entries
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (triplet_lds_bytes(32 * mid, lc, s->fp32) <= limit) lo = mid;
+        else hi = mid - 1;
+    }
+    return 32 * lo;
 }
 
 // Groups the systems into tile classes.  A system's tile need fixes how many triplet
@@ -620,6 +629,8 @@ void fill_bin_grid(BinGrid &b, Grid &g, double *x_ref) {
     b.rank = g.rank;
     b.count = g.count;
     b.start = g.start;
+    b.start_loc = g.start_loc;
+    b.tile_sum = g.tile_sum;
     b.tmp = g.perm_tmp;
     b.perm = g.perm;
     b.inv_perm = g.inv_perm;

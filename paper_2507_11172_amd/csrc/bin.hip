@@ -5,6 +5,8 @@
 // deterministic, which fixes every later summation order.  All passes are HBM/L2-bound
 // streaming kernels.  One launch per pass serves both cell grids (blockIdx.y selects
 // the grid), so a rebinning of the pair-list and triplet grids costs four launches.
+#include <algorithm>
+
 #include "common.h"
 
 namespace mts {
@@ -28,50 +30,78 @@ __global__ void __launch_bounds__(256) k_bin_count(BinArgs a) {
     g.rank[i] = atomicAdd(&g.count[cell], 1);
 }
 
-// Exclusive scan of count[0..ncell) into start[0..ncell], start[ncell] = n.  One
-// workgroup of 1024 threads per grid walks the cells in tiles of 4,096: each thread loads
-// four consecutive counts (consecutive threads, consecutive 16-byte runs), the workgroup
-// scans the 1,024 thread sums in LDS, and a running carry links the tiles.  The counts
-// are cleared for the next binning.  Integer sums: the result does not depend on the order.
-__global__ void __launch_bounds__(1024) k_scan(BinArgs a) {
+// Exclusive scan of count[0..ncell) into start[0..ncell], start[ncell] = n, over many
+// workgroups that never wait for one another:
+//  * k_scan_tiles: one workgroup of 1024 threads per tile of kScanTile cells (each thread
+//    four consecutive counts) writes the tile-local exclusive prefix to start_loc and the
+//    tile total to tile_sum, and clears the counts for the next binning.  The workgroup
+//    that finishes last (a device-scope counter, reset by it) scans the tile totals into
+//    tile_off and writes start[ncell].
+//  * k_bin_scatter adds the tile offsets back: start = start_loc + tile_off[tile], both
+//    for its own scatter and, grid-stride, into start[] for every later kernel.
+// Integer sums: the result does not depend on the order.
+__global__ void __launch_bounds__(1024) k_scan_tiles(BinArgs a) {
     __shared__ int part[1024];
-    const BinGrid &g = a.g[blockIdx.x];
+    __shared__ bool last;
+    const BinGrid &g = a.g[blockIdx.y];
     const int ncell = g.ncell;
+    const int ntile = (ncell + kScanTile - 1) / kScanTile;
+    const int tile = blockIdx.x;
+    if (tile >= ntile) return;  // grids of fewer tiles (uniform per workgroup)
     const int t = threadIdx.x;
-    int carry = 0;
-    for (int base = 0; base < ncell; base += 4 * 1024) {
-        const int c0 = base + 4 * t;
-        int v[4];
+    const int c0 = tile * kScanTile + 4 * t;
+    int v[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) v[k] = c0 + k < ncell ? g.count[c0 + k] : 0;
-        const int s = (v[0] + v[1]) + (v[2] + v[3]);
-        part[t] = s;
+    for (int k = 0; k < 4; ++k) v[k] = c0 + k < ncell ? g.count[c0 + k] : 0;
+    const int s = (v[0] + v[1]) + (v[2] + v[3]);
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int u = t >= off ? part[t - off] : 0;
         __syncthreads();
-        for (int off = 1; off < 1024; off <<= 1) {
-            const int u = t >= off ? part[t - off] : 0;
-            __syncthreads();
-            part[t] += u;
-            __syncthreads();
-        }
-        int run = carry + part[t] - s;  // exclusive prefix of this thread's four cells
-        carry += part[1023];
-        __syncthreads();  // every thread has read part[] before the next tile writes it
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-            if (c0 + k < ncell) {
-                g.start[c0 + k] = run;
-                run += v[k];
-                g.count[c0 + k] = 0;
-            }
+        part[t] += u;
+        __syncthreads();
     }
-    if (t == 0) g.start[ncell] = (int)a.n;
+    int run = part[t] - s;  // exclusive prefix of this thread's four cells in the tile
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (c0 + k < ncell) {
+            g.start_loc[c0 + k] = run;
+            run += v[k];
+            g.count[c0 + k] = 0;
+        }
+    if (t == 1023) g.tile_sum[tile] = part[1023];
+    __threadfence();
+    __syncthreads();
+    if (t == 0) last = atomicAdd(&g.tile_sum[2 * ntile], 1) == ntile - 1;
+    __syncthreads();
+    if (!last) return;
+    // the last tile: exclusive scan of the ntile totals (a few dozen) by thread 0
+    __threadfence();
+    if (t == 0) {
+        int acc = 0;
+        for (int q = 0; q < ntile; ++q) {
+            const int x = __hip_atomic_load(&g.tile_sum[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            g.tile_sum[ntile + q] = acc;
+            acc += x;
+        }
+        g.start[ncell] = (int)a.n;
+        g.tile_sum[2 * ntile] = 0;  // counter at rest for the next binning
+    }
 }
 
+// Scatter of every particle to its cell (arrival rank inside the cell), and the final
+// cell starts: start = start_loc + the offset of the cell's tile.
 __global__ void __launch_bounds__(256) k_bin_scatter(BinArgs a) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.n) return;
     const BinGrid &g = a.g[blockIdx.y];
-    g.tmp[g.start[g.cell_of[i]] + g.rank[i]] = (int)i;
+    const int *off = g.tile_sum + (g.ncell + kScanTile - 1) / kScanTile;
+    if (i < a.n) {
+        const int c = g.cell_of[i];
+        g.tmp[g.start_loc[c] + off[c / kScanTile] + g.rank[i]] = (int)i;
+    }
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t c = i; c < g.ncell; c += stride) g.start[c] = g.start_loc[c] + off[c / kScanTile];
 }
 
 // Final, deterministic order inside each cell: the particle that the atomic scatter put
@@ -117,12 +147,16 @@ static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b -
 hipError_t launch_bin(hipStream_t st, const BinArgs &a) {
     if (a.ng < 1 || a.ng > 2) return hipErrorInvalidValue;
     const dim3 grid(blocks_for(a.n, 256), (unsigned)a.ng);
-    if (a.n > 0 && !a.counted) k_bin_count<<<grid, 256, 0, st>>>(a);
-    k_scan<<<(unsigned)a.ng, 1024, 0, st>>>(a);  // also for n = 0: start[] must be valid
-    if (a.n > 0) {
-        k_bin_scatter<<<grid, 256, 0, st>>>(a);
-        k_rank_gather<<<grid, 256, 0, st>>>(a);
+    int ntile = 0;
+    for (int q = 0; q < a.ng; ++q) {
+        if (a.g[q].ncell <= 0) return hipErrorInvalidValue;
+        ntile = std::max(ntile, (a.g[q].ncell + kScanTile - 1) / kScanTile);
     }
+    if (a.n > 0 && !a.counted) k_bin_count<<<grid, 256, 0, st>>>(a);
+    k_scan_tiles<<<dim3((unsigned)ntile, (unsigned)a.ng), 1024, 0, st>>>(a);
+    // also for n = 0: the scatter writes the final cell starts
+    k_bin_scatter<<<dim3(std::max(1u, grid.x), (unsigned)a.ng), 256, 0, st>>>(a);
+    if (a.n > 0) k_rank_gather<<<grid, 256, 0, st>>>(a);
     return hipGetLastError();
 }
 

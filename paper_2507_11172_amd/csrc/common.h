@@ -162,6 +162,9 @@ __device__ __forceinline__ int stencil_cell_of(const StencilTable<NC> &tab, int 
 // ---------------------------------------------------------------- launchers
 // All launchers enqueue on `st` and return hipGetLastError().
 
+// Cells per tile of the multi-workgroup scan.
+constexpr int kScanTile = 4096;
+
 // Binning (counting sort by cell) of one set of positions into one or two cell grids
 // (the pair-list grid and the triplet grid) with one launch per pass.
 struct BinGrid {
@@ -171,6 +174,9 @@ struct BinGrid {
     int *rank;              // [n] arrival rank inside the cell (scratch)
     int *count;             // [ncell] histogram; zero on entry, left zero by the scan
     int *start;             // [ncell + 1] first sorted slot of each cell
+    int *start_loc;         // [ncell] exclusive prefix of the counts inside each scan tile
+    int *tile_sum;          // [2 ntile + 1], ntile = ceil(ncell / kScanTile): tile totals,
+                            // tile offsets, and the scan's completion counter (zero at rest)
     int *tmp;               // [n] unordered scatter (scratch)
     int *perm;              // [n] sorted -> input index
     int *inv_perm;          // [n] input -> sorted index

@@ -761,3 +761,51 @@ def test_long_three_body_cutoff_big_lists():
     g = got.cpu().numpy().astype(np.int64)
     assert np.array_equal(g[np.lexsort((g[:, 2], g[:, 1], g[:, 0]))], ref.astype(np.int64))
     assert rel_err(f3.cpu().numpy(), r3.f) <= 1e-12
+
+
+def test_scan_over_several_tiles_ragged():
+    """A dilute gas with small clusters in a 53 x 58 x 63 box: 21 x 23 x 25 = 12,075
+    triplet cells (three scan tiles of 4,096 cells, the last one ragged, ncell % 4 = 3),
+    mostly empty.  Cell assignment, the triplet set, forces and a few r-RESPA steps
+    against the oracle: every cell start comes from the multi-workgroup scan."""
+    torch = _torch()
+    rng = W.rng_for(31)
+    box = np.array([53.0, 58.0, 63.0])
+    centres = rng.uniform(0.0, 1.0, size=(150, 3)) * box
+    cluster = W.fcc_sites((2, 2, 2), np.full(3, 1.6))  # 32 sites, neighbours 1.13 apart
+    x = (centres[:, None, :] + cluster[None, :, :] + rng.uniform(-0.05, 0.05, (150, 32, 3)))
+    x = x.reshape(-1, 3) % box
+    # drop particles that came closer than 0.8 to an earlier one (overlapping clusters)
+    keep = np.ones(x.shape[0], bool)
+    for i in range(x.shape[0]):
+        if keep[i]:
+            d = x[i + 1:] - x[i]
+            d -= box * np.rint(d / box)
+            keep[i + 1:] &= np.sum(d * d, axis=1) >= 0.64
+    x = x[keep]
+    n = x.shape[0]
+    v = W.maxwell_boltzmann(n, 0.7, rng)
+    w = W.Workload("tiles", x, v, box[None, :], np.array([n]), np.array([0.7]), k=2)
+    ref = oracle.triplet_list(x, box)
+    assert ref.shape[0] > 1000
+    r3 = oracle.triplet_forces(x, box)
+    with _system(w) as s:
+        assert s.get_grid(0) == (21, 23, 25)
+        xd = _dev(x)
+        s.build_cells(xd)
+        cell = torch.empty(n, dtype=torch.int32, device="cuda")
+        s.get_cell_index(cell)
+        got, total = s.list_triplets(xd, ref.shape[0] + 16)
+        f3 = torch.empty_like(xd)
+        s.compute_triplet_forces(xd, f3)
+        vd = _dev(v)
+        s.respa_step(xd, vd, 4)
+        s.sync()
+        assert np.array_equal(cell.cpu().numpy(), oracle.cell_index(x, box, (21, 23, 25)))
+    assert total == ref.shape[0]
+    g = got.cpu().numpy().astype(np.int64)
+    assert np.array_equal(g[np.lexsort((g[:, 2], g[:, 1], g[:, 0]))], ref.astype(np.int64))
+    assert rel_err(f3.cpu().numpy(), r3.f) <= 1e-12
+    xo, vo, _ = oracle.respa(x, v, box, n_iter=4, k=2)
+    d = xd.cpu().numpy() - xo
+    assert np.abs(d - box * np.rint(d / box)).max() <= 1e-10
