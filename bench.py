@@ -722,7 +722,7 @@ def _counter_rows(path: str):
 
 def traffic_summary(fetch_csv: str, write_csv: str, kernel: str, workload: str,
                     precision: str, copy_kib: float = 262144.0):
-    """HBM bytes per launch of `kernel` (exact demangled name) from a FETCH_SIZE and a
+    """HBM bytes per launch of `kernel` (a part of its demangled name) from a FETCH_SIZE and a
     WRITE_SIZE counter run of the traffic probe.  Each counter is scaled by what it reads
     for the probe's plain copy of copy_kib KiB (the largest copy dispatch), so that the
     result is in the same bytes the copy moves; returns the row for profiles/hbm_traffic.json."""
@@ -732,7 +732,7 @@ def traffic_summary(fetch_csv: str, write_csv: str, kernel: str, workload: str,
     for name, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
         rows = _counter_rows(path)
         copy = max((v for (k, _), v in rows.items() if "copyBuffer" in k), default=0.0)
-        vals = [v for (k, _), v in rows.items() if k.startswith(kernel)]
+        vals = [v for (k, _), v in rows.items() if kernel in k]
         if not vals or copy <= 0:
             raise SystemExit("no %s dispatches of %s or of the calibration copy in %s"
                              % (name, kernel, path))
@@ -764,7 +764,7 @@ def main(argv=None):
     ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="scale the two counter runs of --traffic-probe into HBM bytes per "
                          "launch of --traffic-kernel and print the JSON row")
-    ap.add_argument("--traffic-kernel", default="k_triplet_and_list<double, true, false>")
+    ap.add_argument("--traffic-kernel", default="mts::k_triplet_and_list<double, true, false>(")
     ap.add_argument("--loop-steps", type=int, default=5,
                     help="cycles of the one-handle-per-replica loop (batched workload)")
     ap.add_argument("--rvite-sweep", action="store_true",
@@ -817,7 +817,7 @@ def main(argv=None):
     k = args.k or w.k
     precision = args.precision or w.precision
     if args.traffic_summary:
-        kern = args.traffic_kernel.split("<")[0]
+        kern = args.traffic_kernel.split("<")[0].split("::")[-1]
         row = traffic_summary(args.traffic_summary[0], args.traffic_summary[1],
                               args.traffic_kernel, w.name, precision)
         row["kernel_reported"] = kern
