@@ -764,7 +764,7 @@ def main(argv=None):
     ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="scale the two counter runs of --traffic-probe into HBM bytes per "
                          "launch of --traffic-kernel and print the JSON row")
-    ap.add_argument("--traffic-kernel", default="mts::k_triplet_and_list<double, true, false>(")
+    ap.add_argument("--traffic-kernel", default="mts::k_triplet_items<double, false, true, false>(")
     ap.add_argument("--loop-steps", type=int, default=5,
                     help="cycles of the one-handle-per-replica loop (batched workload)")
     ap.add_argument("--rvite-sweep", action="store_true",
@@ -838,14 +838,12 @@ def main(argv=None):
     # list force kernel: algorithmic HBM bytes of one launch over its average duration
     pair_bytes = (PAIR_BYTES_FIXED * w.n_total + PAIR_BYTES_PER_ENTRY * r["list_entries_est"])
     pair_s = r["pair_kernel_ms"] * 1e-3
-    kernel = "k_triplet_and_list" if r["tuning"].get("shared_launch") else "k_triplet"
+    kernel = "k_triplet_items"  # one persistent launch per evaluation (with the pair-list
+    # build as its last items when tuning["shared_launch"] is 1)
     if w.method == "direct":
         kernel = "k_direct_triplet"
-    ncls = int(r["tuning"].get("tile_classes", 1))
-    if ncls > 1:  # one launch per tile class, timed together
-        kernel += " + k_triplet x %d (tile classes)" % (ncls - 1)
     if w.k_outer > 1:
-        kernel += " + inner-class k_triplet passes"
+        kernel += " + inner-class passes"
     out = {
         "metric": METRIC,
         "value": steps_per_s,

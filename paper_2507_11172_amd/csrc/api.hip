@@ -73,6 +73,7 @@ struct Layout {
     int ncls = 0;
     int cls_cap[kMaxTileClasses] = {};
     int cls_off[kMaxTileClasses + 1] = {};
+    bool any_whole = false;       // some system's triplet tile is the whole system
     std::vector<int> cls_order;   // host copy of the cell order (all classes)
     int *cls_cells = nullptr;     // [ncell_t] device; nullptr with one class (identity)
     double *ce = nullptr;         // [ncell_t][2] per-cell triplet energy/virial
@@ -211,7 +212,7 @@ int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
 // Grid with cell edges of at least hmin (margin against rounding so that any pair within
 // the cutoff lies in adjacent cells), at least 2 cells per edge.
-mts_status make_grid(Grid &g, const std::vector<SysDesc> &base, double hmin) {
+mts_status make_grid(Grid &g, const std::vector<SysDesc> &base, double hmin, bool triplet) {
     g.hsd = base;
     int64_t cell0 = 0;
     for (SysDesc &d : g.hsd) {
@@ -221,6 +222,7 @@ mts_status make_grid(Grid &g, const std::vector<SysDesc> &base, double hmin) {
             d.q[k] = (double)d.nc[k] / d.L[k];
         }
         d.ncell = d.nc[0] * d.nc[1] * d.nc[2];
+        d.whole = triplet && d.ncell < kNumHalf ? 1 : 0;
         d.cell0 = (int)cell0;
         cell0 += d.ncell;
     }
@@ -264,7 +266,8 @@ void size_tiles(const mts_system *s, Layout &lo) {
         const SysDesc &d = lo.gt.hsd[q];
         const double rho = std::max(0.9, 1.2 * (double)d.n / (d.L[0] * d.L[1] * d.L[2]));
         const double v = rho * (d.L[0] / d.nc[0]) * (d.L[1] / d.nc[1]) * (d.L[2] / d.nc[2]);
-        lo.cfg.tile_need[q] = (int)std::ceil(kNumHalf * v * 1.1) + 16;
+        // a whole-system tile holds exactly the system's particles
+        lo.cfg.tile_need[q] = d.whole ? (int)d.n : (int)std::ceil(kNumHalf * v * 1.1) + 16;
     }
     lo.pair_cap = std::min(2048, round_up((int)std::ceil(kNumFull * vp * 1.1) + 16, 32));
     lo.list_cap = std::min(kMaxListCap, round_up((int)std::ceil(1.25 * rho_t * (4.0 / 3.0) * M_PI * rc3 * rc3 * rc3) + 8, 16));
@@ -340,59 +343,59 @@ int cap_for_lds(const mts_system *s, int lc, size_t limit) {
     return 32 * lo;
 }
 
-// Groups the systems into tile classes.  A system's tile need fixes how many triplet
-// workgroups fit on one CU (LDS and registers); systems with the same count share a
-// class, which gets the largest capacity with that count -- headroom against overflow at
-// no cost in occupancy.  A batch of boxes too small for three cells per edge (large cells,
-// tiles up to ~1.75 N) thus no longer drags every other system's workgroups down to its
-// own occupancy.  Classes run in order of decreasing occupancy, each as one launch; the
-// cell order lists each class's cells in system order.
+// The one triplet launch of a force evaluation (a single tile class): its tile capacity
+// is the largest need of any system, raised to the largest capacity that keeps the same
+// number of workgroups per CU (headroom against overflow at no cost in occupancy).  With
+// several systems the base cells are ordered by decreasing estimated work per cell
+// (anchors per cell x tile entries), so that the dispatcher starts the costly items
+// first and the launch ends on cheap ones.  Whole-system tiles (boxes of fewer
+// than 14 cells) hold N entries instead of 14 cells' worth, which keeps tiny boxes from
+// setting the capacity of the whole batch.
 mts_status classify(const mts_system *s, Layout &lo) {
     const int lc = lo.list_cap;
+    lo.any_whole = false;
+    for (const SysDesc &d : lo.gt.hsd) lo.any_whole = lo.any_whole || d.whole;
     const int cmax = cap_for_lds(s, lc, s->max_lds);
     auto occ = [&](int cap) {
         const size_t b = triplet_lds_bytes(cap, lc, s->fp32);
-        const int r = triplet_blocks_per_cu(s->fp32, b, s->lds_per_cu);
+        const int r = triplet_blocks_per_cu(s->fp32, lo.any_whole, b, s->lds_per_cu);
         return r > 0 ? r : std::max(1, std::min(2, (int)(s->lds_per_cu / (b + 2048))));
     };
-    std::vector<int> occ_of(s->nsys), level;
-    for (int q = 0; q < s->nsys; ++q) {
-        const int c = round_up(std::max(32, lo.cfg.tile_need[q]), 32);
-        if (c > cmax) return MTS_ERR_UNSUPPORTED;
-        occ_of[q] = occ(c);
-        if (std::find(level.begin(), level.end(), occ_of[q]) == level.end()) level.push_back(occ_of[q]);
+    int need = 32;
+    for (int q = 0; q < s->nsys; ++q) need = std::max(need, round_up(std::max(32, lo.cfg.tile_need[q]), 32));
+    if (need > cmax) return MTS_ERR_UNSUPPORTED;
+    const int level = occ(need);
+    int lo_i = need / 32, hi_i = cmax / 32;
+    while (lo_i < hi_i) {  // largest capacity with at least this occupancy
+        const int mid = (lo_i + hi_i + 1) / 2;
+        if (occ(32 * mid) >= level) lo_i = mid;
+        else hi_i = mid - 1;
     }
-    if ((int)level.size() > kMaxTileClasses) return MTS_ERR_UNSUPPORTED;
-    std::sort(level.begin(), level.end(), [](int a, int b) { return a > b; });
-    lo.ncls = (int)level.size();
-    lo.stage_cap = 0;
+    lo.ncls = 1;
+    lo.cls_cap[0] = 32 * lo_i;
+    lo.stage_cap = lo.cls_cap[0];
+    lo.cls_off[0] = 0;
+    lo.cls_off[1] = lo.gt.ncell;
     lo.cls_order.clear();
-    for (int c = 0; c < lo.ncls; ++c) {
-        int lo_i = 1;
-        for (int q = 0; q < s->nsys; ++q)
-            if (occ_of[q] == level[c]) lo_i = std::max(lo_i, round_up(std::max(32, lo.cfg.tile_need[q]), 32) / 32);
-        int hi_i = cmax / 32;
-        while (lo_i < hi_i) {  // largest capacity with at least this occupancy
-            const int mid = (lo_i + hi_i + 1) / 2;
-            if (occ(32 * mid) >= level[c]) lo_i = mid;
-            else hi_i = mid - 1;
+    if (s->nsys > 1) {
+        std::vector<std::pair<double, int>> work(s->nsys);
+        for (int q = 0; q < s->nsys; ++q) {
+            const SysDesc &d = lo.gt.hsd[q];
+            const double per_cell = (double)d.n / std::max(1, d.ncell);
+            work[q] = {-per_cell * (d.whole ? (double)d.n : kNumHalf * per_cell), q};
         }
-        lo.cls_cap[c] = 32 * lo_i;
-        lo.stage_cap = std::max(lo.stage_cap, lo.cls_cap[c]);
-        lo.cls_off[c] = (int)lo.cls_order.size();
-        for (int q = 0; q < s->nsys; ++q)
-            if (occ_of[q] == level[c]) {
-                const SysDesc &d = lo.gt.hsd[q];
-                for (int k = 0; k < d.ncell; ++k) lo.cls_order.push_back(d.cell0 + k);
-            }
+        std::stable_sort(work.begin(), work.end());
+        for (const auto &w : work) {
+            const SysDesc &d = lo.gt.hsd[w.second];
+            for (int k = 0; k < d.ncell; ++k) lo.cls_order.push_back(d.cell0 + k);
+        }
     }
-    lo.cls_off[lo.ncls] = (int)lo.cls_order.size();
     return MTS_OK;
 }
 
-// The class cell order on the device (none with a single class: identity order).
+// The cell order on the device (none for a single system: identity order).
 mts_status upload_classes(mts_system *s, Layout &lo) {
-    if (lo.ncls <= 1) return MTS_OK;
+    if (lo.cls_order.empty()) return MTS_OK;
     if (!lo.cls_cells) HIP_TRY(s, dalloc(&lo.cls_cells, lo.gt.ncell));
     HIP_TRY(s, hipMemcpy(lo.cls_cells, lo.cls_order.data(), sizeof(int) * lo.cls_order.size(),
                          hipMemcpyHostToDevice));
@@ -404,8 +407,8 @@ mts_status build_layout(mts_system *s, const Config &cfg, Layout &out) {
     out = Layout{};
     out.cfg = cfg;
     out.skin = cfg.skin;
-    mts_status r = make_grid(out.gt, s->base, cfg.cell_factor * s->p.rc_triplet * kCellMargin);
-    if (r == MTS_OK) r = make_grid(out.gp, s->base, (s->p.rc_pair + cfg.skin) * kCellMargin);
+    mts_status r = make_grid(out.gt, s->base, cfg.cell_factor * s->p.rc_triplet * kCellMargin, true);
+    if (r == MTS_OK) r = make_grid(out.gp, s->base, (s->p.rc_pair + cfg.skin) * kCellMargin, false);
     if (r != MTS_OK) {
         out = Layout{};
         return r;
@@ -790,6 +793,7 @@ TripletArgs triplet_args(const mts_system *s, int cls, int *list_ijk, long long 
     TripletArgs a{};
     a.ncell = lo.cls_off[cls + 1] - lo.cls_off[cls];
     a.cell_map = lo.cls_cells ? lo.cls_cells + lo.cls_off[cls] : nullptr;
+    a.any_whole = lo.any_whole ? 1 : 0;
     a.xs = g.xs;
     a.start = g.start;
     a.sd = g.sd;

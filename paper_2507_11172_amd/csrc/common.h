@@ -27,7 +27,9 @@ struct SysDesc {
     int nc[3];      // cells per edge (>= 2); cell edge L/nc exceeds the largest cutoff
     int cell0;      // first global cell id of this system
     int ncell;      // nc[0] * nc[1] * nc[2]
-    int pad;
+    int whole;      // triplet grid only, 1 when ncell < 14: the half stencil would stage
+                    // particles of the system more than once, so the triplet kernel stages
+                    // the whole system instead, and cell c stands for anchor chunk c
     int64_t p0;     // first particle (global index); particles are concatenated by system
     int64_t n;      // particles in this system
 };
@@ -288,11 +290,14 @@ size_t pair_lds_bytes(int stage_cap);
 // Lets every LDS-tiled kernel use up to max_bytes of dynamic LDS per workgroup.
 hipError_t configure_kernel_lds(size_t max_bytes);
 
-// Triplet forces: one workgroup per base cell, forward half stencil in LDS.
+// Triplet forces: one launch whose workgroups take one base cell (item) each, in the order
+// of cell_map, staging its forward half stencil (or a tiny system whole) in LDS; the
+// pair-list build's cells follow as further items of the same launch.
 struct TripletArgs {
-    int ncell;              // base cells of this launch (one workgroup each)
-    const int *cell_map;    // [ncell] triplet-grid cell of each workgroup, or nullptr:
-                            // workgroup b takes cell b
+    int ncell;              // base cells of this launch (items)
+    const int *cell_map;    // [ncell] triplet-grid cell of each item, or nullptr: item b
+                            // is cell b
+    int any_whole;          // 1 if some system of the launch is staged whole (SysDesc.whole)
     const Pos4 *xs;
     const int *start;
     const SysDesc *sd;
@@ -324,7 +329,7 @@ hipError_t launch_triplet_and_list(hipStream_t st, const TripletArgs &a, const L
 size_t triplet_lds_bytes(int stage_cap, int list_cap, bool fp32);
 // Triplet workgroups that fit on one CU (registers, and lds bytes of dynamic LDS each out
 // of lds_per_cu); -1: unknown.
-int triplet_blocks_per_cu(bool fp32, size_t lds, size_t lds_per_cu);
+int triplet_blocks_per_cu(bool fp32, bool whole, size_t lds, size_t lds_per_cu);
 hipError_t launch_triplet_gather(hipStream_t st, int64_t n, const double *pf, const int *perm,
                                  double *f, int *flags);
 

@@ -50,11 +50,14 @@ namespace mts {
 
 constexpr int kTripWaves = 4;
 constexpr int kTripThreads = kTripWaves * kWave;
-// Hit queue: evaluated EV hits per lane once EV x 64 are pending; one round of tests
-// pushes at most 64 more.
-constexpr int kQueueCap = 4 * kWave;   // a ring: fewer than EV x 64 pending + 64 pushed
+// Hit queue: evaluated one hit per lane whenever 64 are pending; one round of tests
+// pushes at most 2 x 64 more.
+constexpr int kQueueCap = 4 * kWave;   // a ring: fewer than 64 pending + 128 pushed
 constexpr int kQueueMask = kQueueCap - 1;
-constexpr int EV = 1;                  // queued hits evaluated per lane at a time (1 or 2)
+// List pairs tested per lane and round of the j-k sweep (1 or 2): two give each lane two
+// independent chains, one keeps the register count (and so the occupancy) lower.
+template <typename T>
+constexpr int kPairsPerLane = sizeof(T) == sizeof(float) ? 1 : 2;
 
 // Number of set bits of mask in the lanes below this one.
 __device__ __forceinline__ int below(uint64_t mask) {
@@ -100,6 +103,15 @@ __device__ __forceinline__ PosEnt unpack(const TileEnt &t, double L0, double L1,
     e.sy = (double)(((t.code >> 2) & 3) - 1) * L1;
     e.sz = (double)(((t.code >> 4) & 3) - 1) * L2;
     return e;
+}
+
+// A whole-system tile carries no image shifts: the shift of entry e as seen from the
+// anchor is that of the minimum image, S = -L rint((x_e - x_a) / L), so that
+// disp1(x_a, x_e, S) = fl(fl(x_e - x_a) + S) is the canonical displacement.
+__device__ __forceinline__ void mic_from(PosEnt &e, const PosEnt &an, const SysDesc &d) {
+    e.sx = -d.L[0] * rint((e.x - an.x) * d.iL[0]);
+    e.sy = -d.L[1] * rint((e.y - an.y) * d.iL[1]);
+    e.sz = -d.L[2] * rint((e.z - an.z) * d.iL[2]);
 }
 
 struct Tile {                  // staged neighbour cells, CAP entries
@@ -203,11 +215,11 @@ __device__ __forceinline__ void carve(unsigned char *raw, int cap, int lc, int w
 // FP64 test: the triplet set is exactly the FP64 one.
 constexpr float kPrefilterBand = 1e-5f;
 
-// One queued triplet (anchor, j, k): forces on all three members (j and k as list
-// partials, the anchor's in the caller's registers), energy and virial.
+// One queued triplet (anchor, j, k): the forces on the partners j and k (the anchor's is
+// minus their sum), energy and virial.
 template <typename T>
 struct AtmOut {
-    T fix, fiy, fiz, fjx, fjy, fjz, fkx, fky, fkz, phi, vir;
+    T fjx, fjy, fjz, fkx, fky, fkz, phi, vir;
 };
 
 template <typename T>
@@ -222,15 +234,12 @@ __device__ __forceinline__ AtmOut<T> atm_triplet(const ListEnt<T> &lj, const Lis
     T phi, ga, gb, gc;
     atm_terms<T>(aa, bb, cc, nu, phi, ga, gb, gc);
     AtmOut<T> o;
-    o.fix = fma(ga, ux, gb * wx);
-    o.fiy = fma(ga, uy, gb * wy);
-    o.fiz = fma(ga, uz, gb * wz);
     o.fjx = fma(gc, vx, -ga * ux);
     o.fjy = fma(gc, vy, -ga * uy);
     o.fjz = fma(gc, vz, -ga * uz);
-    o.fkx = -(o.fix + o.fjx);
-    o.fky = -(o.fiy + o.fjy);
-    o.fkz = -(o.fiz + o.fjz);
+    o.fkx = -fma(gb, wx, gc * vx);
+    o.fky = -fma(gb, wy, gc * vy);
+    o.fkz = -fma(gb, wz, gc * vz);
     o.phi = phi;
     o.vir = -fma(aa, ga, fma(bb, gb, cc * gc));
     return o;
@@ -271,15 +280,19 @@ __device__ __forceinline__ int tile_slot(const StencilTable<kNumHalf> &tab, int 
 constexpr int kInnerBit = 1 << 30;
 constexpr int kTileMask = kInnerBit - 1;
 
-// The triplet work of one base cell (one workgroup of kTripThreads threads).  WEIGHT: the
+// The triplet work of one base cell (one workgroup of kTripThreads threads).  A system with
+// fewer than 14 cells (SysDesc.whole) is staged whole instead, with minimum-image
+// displacements; its cell c then stands for the c-th of ncell chunks of anchors, each
+// chunk writing partial slot c of every particle of the system.  WEIGHT: the
 // full-step pass of nested r-RESPA -- each triplet's forces are scaled by 1 if its longest
 // edge is within the split (a.ra2: all three squared edges <= ra2, decided exactly as the
 // cutoff is) and by a.w_out otherwise, so that the slots sum to F_in + w_out F_out;
 // energies and virials stay unscaled.
-template <typename T, bool LIST, bool ENERGY, bool WEIGHT>
+template <typename T, bool LIST, bool ENERGY, bool WEIGHT, bool WHOLE>
 __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
                                               unsigned char *smem_raw) {
     __shared__ int s_turn;
+    __shared__ double s_anc[kTripWaves][3];  // each wave's current anchor force
     __shared__ double s_red[kTripWaves][2];
     __shared__ int s_cnt[kTripWaves];
     __shared__ StencilTable<kNumHalf> tab;
@@ -289,6 +302,7 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
     const int64_t n = a.n;
     const int sysq = a.sys_of_cell[base];
     const SysDesc &d = a.sd[sysq];
+    constexpr bool whole = WHOLE;  // d.whole != 0: the caller dispatches on it
     const int loc = base - d.cell0;
     const int cx = loc % d.nc[0], cy = (loc / d.nc[0]) % d.nc[1], cz = loc / (d.nc[0] * d.nc[1]);
     const double L0 = d.L[0], L1 = d.L[1], L2 = d.L[2];
@@ -297,20 +311,36 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
     List<T> L;
     carve<T>(smem_raw, CAP, LC, wave, tile, L);
 
-    // ---- stage the base cell and its 13 forward cells (shared by the workgroup)
-    int nst = stencil_table<kNumHalf, true>(tab, d, cx, cy, cz, a.start);
-    int nself = tab.off[1];
+    // ---- stage the base cell and its 13 forward cells (shared by the workgroup), or the
+    // whole system; anchors are the tile entries [a_lo, a_hi)
+    int nst, a_lo, a_hi, p0s = 0;
+    if (whole) {
+        p0s = a.start[d.cell0];
+        nst = a.start[d.cell0 + d.ncell] - p0s;
+        a_lo = (int)((int64_t)loc * nst / d.ncell);
+        a_hi = (int)((int64_t)(loc + 1) * nst / d.ncell);
+    } else {
+        nst = stencil_table<kNumHalf, true>(tab, d, cx, cy, cz, a.start);
+        a_lo = 0;
+        a_hi = tab.off[1];
+    }
     if (a.stats && tid == 0) atomicMax(&a.stats[0], nst);
     if ((a.stats || nst > CAP) && tid == 0) atomicMax(&a.tile_obs[sysq], nst);
     if (nst > CAP) {
         if (tid == 0) atomicOr(a.flags, kFlagStageOverflow);
         nst = CAP;
     }
-    nself = min(nself, nst);
+    a_hi = min(a_hi, nst);
     for (int t = tid; t < nst; t += kTripThreads) {
-        const int o = stencil_cell_of<kNumHalf>(tab, t);
-        const int src = tab.begin[o] + (t - tab.off[o]);
-        const int code = tab.code[o];
+        int src, code;
+        if (whole) {
+            src = p0s + t;
+            code = 0x15;  // zero shift code: images follow the anchor (mic_from)
+        } else {
+            const int o = stencil_cell_of<kNumHalf>(tab, t);
+            src = tab.begin[o] + (t - tab.off[o]);
+            code = tab.code[o];
+        }
         const Pos4 ps = a.xs[src];
         TileEnt te;
         te.x = ps.x;
@@ -319,7 +349,7 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
         te.code = code & 0xff;
         te.pad = 0;
         tile_set(tile, t, te);
-        if constexpr (sizeof(T) != sizeof(float)) {
+        if (sizeof(T) != sizeof(float) && !whole) {
             const PosEnt e = unpack(te, L0, L1, L2);
             tile.r[t] = make_float4((float)((e.x + e.sx) - ox), (float)((e.y + e.sy) - oy),
                                    (float)((e.z + e.sz) - oz), 0.0f);
@@ -328,7 +358,7 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
         tile.fy[t] = 0.0;
         tile.fz[t] = 0.0;
     }
-    if (tid == 0) s_turn = 0;
+    if (tid == 0) s_turn = a_lo;
     __syncthreads();
 
     const T nu = (T)a.nu;
@@ -344,10 +374,17 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
     };
     const double ra2 = a.ra2;
 
-    for (int ia = wave; ia < nself; ia += kTripWaves) {
+    // sorted particle index of tile entry t (debug listing only)
+    auto slot_of = [&](int t) { return whole ? p0s + t : tile_slot(tab, t); };
+    for (int ia = a_lo + wave; ia < a_hi; ia += kTripWaves) {
         const PosEnt an = unpack(tile_get(tile, ia), L0, L1, L2);  // anchor: base cell, zero shift
+        auto entry = [&](int t) {  // tile entry t with its image shift seen from the anchor
+            PosEnt e = unpack(tile_get(tile, t), L0, L1, L2);
+            if (whole) mic_from(e, an, d);
+            return e;
+        };
         int m = 0;
-        if constexpr (sizeof(T) != sizeof(float)) {
+        if (sizeof(T) != sizeof(float) && !whole) {
             // ---- A1: FP32 prefilter of the tile entries after the anchor (tile order);
             // certain and ambiguous candidates are compacted into L.t, in tile order
             const float4 ar = tile.r[ia];
@@ -402,8 +439,8 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
             // anchor, two per lane per round; ballot + prefix-count compaction keeps tile order
             for (int t0 = ia + 1; t0 < nst; t0 += 2 * kWave) {
                 const int t1 = t0 + lane, t2 = t0 + kWave + lane;
-                const PosEnt e1 = unpack(tile_get(tile, t1 < nst ? t1 : ia), L0, L1, L2);
-                const PosEnt e2 = unpack(tile_get(tile, t2 < nst ? t2 : ia), L0, L1, L2);
+                const PosEnt e1 = entry(t1 < nst ? t1 : ia);
+                const PosEnt e2 = entry(t2 < nst ? t2 : ia);
                 const double x1 = disp1(an.x, e1.x, e1.sx), y1 = disp1(an.y, e1.y, e1.sy),
                              z1 = disp1(an.z, e1.z, e1.sz);
                 const double x2 = disp1(an.x, e2.x, e2.sx), y2 = disp1(an.y, e2.y, e2.sy),
@@ -416,6 +453,8 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
                 const int p1 = m + below(m1), p2 = m + n1 + below(m2);
                 if (in1 && p1 < LC) {
                     L.u.set(p1, ListEnt<T>{(T)x1, (T)y1, (T)z1, (T)q1});
+                    if constexpr (sizeof(T) != sizeof(float))  // whole-system tiles
+                        L.f[p1] = ListEnt<float>{(float)x1, (float)y1, (float)z1, (float)q1};
                     L.t[p1] = WEIGHT && q1 <= ra2 ? (t1 | kInnerBit) : t1;
                     L.px[p1] = 0.0;
                     L.py[p1] = 0.0;
@@ -423,6 +462,8 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
                 }
                 if (in2 && p2 < LC) {
                     L.u.set(p2, ListEnt<T>{(T)x2, (T)y2, (T)z2, (T)q2});
+                    if constexpr (sizeof(T) != sizeof(float))
+                        L.f[p2] = ListEnt<float>{(float)x2, (float)y2, (float)z2, (float)q2};
                     L.t[p2] = WEIGHT && q2 <= ra2 ? (t2 | kInnerBit) : t2;
                     L.px[p2] = 0.0;
                     L.py[p2] = 0.0;
@@ -439,7 +480,6 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
         __builtin_amdgcn_wave_barrier();
 
         // ---- B + C: j-k tests, queued hits evaluated two per lane
-        double fax = 0.0, fay = 0.0, faz = 0.0;
         int qh = 0, qt = 0;  // ring queue head and tail (wave-uniform)
         auto scatter = [&](const AtmOut<T> &o, int j, int k) {
             atomicAdd(&L.px[j], (double)o.fjx);
@@ -451,9 +491,9 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
             if (LIST) {
                 const long long sidx = (long long)atomicAdd(a.list_n, 1ull);
                 if (sidx < a.list_rows) {
-                    const int p0 = a.perm[tile_slot(tab, ia)];
-                    const int p1 = a.perm[tile_slot(tab, tix(L.t[j]))];
-                    const int p2 = a.perm[tile_slot(tab, tix(L.t[k]))];
+                    const int p0 = a.perm[slot_of(ia)];
+                    const int p1 = a.perm[slot_of(tix(L.t[j]))];
+                    const int p2 = a.perm[slot_of(tix(L.t[k]))];
                     const int lo = min(p0, min(p1, p2)), hi = max(p0, max(p1, p2));
                     a.list_ijk[3 * sidx] = lo;
                     a.list_ijk[3 * sidx + 1] = p0 + p1 + p2 - lo - hi;
@@ -477,8 +517,8 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
             in = in && c <= ra2 - band;
             if (__ballot(amb)) {
                 if (amb) {
-                    const PosEnt ej = unpack(tile_get(tile, tj & kTileMask), L0, L1, L2);
-                    const PosEnt ek = unpack(tile_get(tile, tk & kTileMask), L0, L1, L2);
+                    const PosEnt ej = entry(tj & kTileMask);
+                    const PosEnt ek = entry(tk & kTileMask);
                     const double wx = disp1(ej.x, ek.x, ek.sx - ej.sx);
                     const double wy = disp1(ej.y, ek.y, ek.sy - ej.sy);
                     const double wz = disp1(ej.z, ek.z, ek.sz - ej.sz);
@@ -487,14 +527,13 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
             }
             return in;
         };
-        // EV queued hits per lane, computed as independent straight-line chains (lanes
-        // without a hit compute on the first pending entry; such results are selected
-        // away).  The register sums take every chain unconditionally, which keeps the
-        // compiler from sinking a chain behind another one's scatter.
+        // One queued hit per lane (lanes without one compute on the first pending entry and
+        // are masked): the forces on j and k go to the list partials; the anchor's force is
+        // not formed here -- by Newton's third law within the triplet it is minus the sum
+        // of the partner forces, and the merge takes it from the partials.
         auto evaluate = [&](int cnt) {
-            const bool v1 = lane < cnt, v2 = EV == 2 && lane + kWave < cnt;
+            const bool v1 = lane < cnt;
             const int e1 = Q[(qh + (v1 ? lane : 0)) & kQueueMask];
-            const int e2 = EV == 2 && v2 ? Q[(qh + kWave + lane) & kQueueMask] : e1;
             qh += cnt;
             const int j1 = e1 & 0xff, k1 = e1 >> 8;
             const ListEnt<T> uj1 = L.u.get(j1), uk1 = L.u.get(k1);
@@ -506,95 +545,110 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
                 iw1 = in1 ? 1.0 : inv_w;
             }
             const AtmOut<T> o1 = atm_triplet<T>(uj1, uk1, nu1);
-            fax += v1 ? (double)o1.fix : 0.0;
-            fay += v1 ? (double)o1.fiy : 0.0;
-            faz += v1 ? (double)o1.fiz : 0.0;
             if (ENERGY) {
                 U += v1 ? (double)o1.phi * iw1 : 0.0;
                 W += v1 ? (double)o1.vir * iw1 : 0.0;
             }
-            if constexpr (EV == 2) {
-                const int j2 = e2 & 0xff, k2 = e2 >> 8;
-                const ListEnt<T> uj2 = L.u.get(j2), uk2 = L.u.get(k2);
-                T nu2 = nu;
-                double iw2 = 1.0;
-                if constexpr (WEIGHT) {
-                    const bool in2 = inner_class(j2, k2, uj2, uk2);
-                    nu2 = in2 ? nu : nu_out;
-                    iw2 = in2 ? 1.0 : inv_w;
-                }
-                const AtmOut<T> o2 = atm_triplet<T>(uj2, uk2, nu2);
-                fax += v2 ? (double)o2.fix : 0.0;
-                fay += v2 ? (double)o2.fiy : 0.0;
-                faz += v2 ? (double)o2.fiz : 0.0;
-                if (ENERGY) {
-                    U += v2 ? (double)o2.phi * iw2 : 0.0;
-                    W += v2 ? (double)o2.vir * iw2 : 0.0;
-                }
-                if (v1) scatter(o1, j1, k1);
-                if (v2) scatter(o2, j2, k2);
-            } else {
-                if (v1) scatter(o1, j1, k1);
-            }
+            if (v1) scatter(o1, j1, k1);
             __builtin_amdgcn_wave_barrier();
         };
 
-        // ---- B: the j-k test of every unordered list pair, 64 per round.  Pair item
-        // q = (dd - 1) m + j stands for (j, k = (j + dd) mod m): diagonals dd = 1, 2, ...
-        // of the circulant, each a permutation of the list; for even m the last diagonal
-        // dd = m/2 pairs each entry with its opposite, and its first half (j < m/2) covers
-        // those pairs once, so q < m(m - 1)/2 visits every pair exactly once with all
-        // lanes busy.  Lane l starts at q = l and advances by 64 per round.
+        // ---- B: the j-k test of every unordered list pair, P x 64 per round (P per lane).
+        // Pair item q = (dd - 1) m + j stands for (j, k = (j + dd) mod m): diagonals
+        // dd = 1, 2, ... of the circulant, each a permutation of the list; for even m the
+        // last diagonal dd = m/2 pairs each entry with its opposite, and its first half
+        // (j < m/2) covers those pairs once, so q < m(m - 1)/2 visits every pair exactly
+        // once with all lanes busy.  Lane l takes q = l + 64 p (p < P) and advances by 64 P.
+        constexpr int P = kPairsPerLane<T>;
         const int npair = m * (m - 1) / 2;
         if (npair > 0) {
-            const int adv_d = kWave / m, adv_j = kWave - adv_d * m;  // 64 = adv_d m + adv_j
-            int dd = (int)(((float)lane + 0.5f) / (float)m);
-            int j = lane - dd * m;
-            if (j >= m) { j -= m; ++dd; }
-            if (j < 0) { j += m; --dd; }
-            ++dd;
-            for (int q0 = 0; q0 < npair; q0 += kWave) {
-                const bool valid = q0 + lane < npair;  // false only in the last round
-                int k = j + dd;
-                k -= k >= m ? m : 0;
-                const ListEnt<float> fj = L.f[valid ? j : 0];
-                const ListEnt<float> fk = L.f[valid ? k : 0];
-                const float vx = fk.ux - fj.ux, vy = fk.uy - fj.uy, vz = fk.uz - fj.uz;
-                const float q2 = (vx * vx + vy * vy) + vz * vz;
-                bool hit = valid && q2 <= jk_lo;
-                const bool amb = valid && q2 > jk_lo && q2 <= jk_hi;
-                if (__ballot(amb)) {  // rare: settle with the canonical FP64 test
-                    if (amb) {
-                        const PosEnt ej = unpack(tile_get(tile, tix(L.t[j])), L0, L1, L2);
-                        const PosEnt ek = unpack(tile_get(tile, tix(L.t[k])), L0, L1, L2);
-                        const double wx = disp1(ej.x, ek.x, ek.sx - ej.sx);
-                        const double wy = disp1(ej.y, ek.y, ek.sy - ej.sy);
-                        const double wz = disp1(ej.z, ek.z, ek.sz - ej.sz);
-                        hit = norm2(wx, wy, wz) <= rc2;
-                    }
+            const int adv_d = (P * kWave) / m, adv_j = P * kWave - adv_d * m;  // 64 P = adv_d m + adv_j
+            int jj[P], dq[P];
+#pragma unroll
+            for (int p = 0; p < P; ++p) {  // (j, dd) of item lane + 64 p
+                const int q = lane + p * kWave;
+                int d0 = (int)(((float)q + 0.5f) / (float)m);
+                int j0 = q - d0 * m;
+                if (j0 >= m) { j0 -= m; ++d0; }
+                if (j0 < 0) { j0 += m; --d0; }
+                jj[p] = j0;
+                dq[p] = d0 + 1;
+            }
+            // the canonical FP64 test of a j-k edge within rounding of the cutoff (rare)
+            auto settle = [&](int j, int k) {
+                const PosEnt ej = entry(tix(L.t[j]));
+                const PosEnt ek = entry(tix(L.t[k]));
+                const double wx = disp1(ej.x, ek.x, ek.sx - ej.sx);
+                const double wy = disp1(ej.y, ek.y, ek.sy - ej.sy);
+                const double wz = disp1(ej.z, ek.z, ek.sz - ej.sz);
+                return norm2(wx, wy, wz) <= rc2;
+            };
+            for (int q0 = 0; q0 < npair; q0 += P * kWave) {
+                bool hit[P], amb[P];
+                int kk[P];
+                bool any_amb = false;
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    const bool ok = q0 + p * kWave + lane < npair;
+                    int k = jj[p] + dq[p];
+                    k -= k >= m ? m : 0;
+                    kk[p] = k;
+                    const ListEnt<float> fj = L.f[ok ? jj[p] : 0], fk = L.f[ok ? k : 0];
+                    const float x = fk.ux - fj.ux, y = fk.uy - fj.uy, z = fk.uz - fj.uz;
+                    const float c = (x * x + y * y) + z * z;
+                    hit[p] = ok && c <= jk_lo;
+                    amb[p] = ok && c > jk_lo && c <= jk_hi;
+                    any_amb = any_amb || amb[p];
                 }
-                // append the hits to the ring queue in lane order
-                const uint64_t mh = __ballot(hit);
-                if (hit) Q[(qt + below(mh)) & kQueueMask] = (unsigned short)(j | (k << 8));
-                qt += __popcll(mh);
+                if (__ballot(any_amb)) {  // rare: settle with the canonical FP64 test
+#pragma unroll
+                    for (int p = 0; p < P; ++p)
+                        if (amb[p]) hit[p] = settle(jj[p], kk[p]);
+                }
+                // append the hits to the ring queue: lane order, item by item
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    const uint64_t mh = __ballot(hit[p]);
+                    if (hit[p]) Q[(qt + below(mh)) & kQueueMask] = (unsigned short)(jj[p] | (kk[p] << 8));
+                    qt += __popcll(mh);
+                }
                 __builtin_amdgcn_wave_barrier();
-                if (qt - qh >= EV * kWave) {
-                    evaluate(EV * kWave);
-                    ntrip += EV * kWave;
+                while (qt - qh >= kWave) {
+                    evaluate(kWave);
+                    ntrip += kWave;
                 }
-                j += adv_j;
-                dd += adv_d;
-                if (j >= m) { j -= m; ++dd; }
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    jj[p] += adv_j;
+                    dq[p] += adv_d;
+                    if (jj[p] >= m) { jj[p] -= m; ++dq[p]; }
+                }
             }
             if (qt > qh) {
                 ntrip += qt - qh;
                 evaluate(qt - qh);
             }
         }
-        fax = wave_sum(fax);
-        fay = wave_sum(fay);
-        faz = wave_sum(faz);
 
+        // ---- the anchor's force: minus the sum of its partners' partials (a fixed-order
+        // wave sum)
+        double *anc = s_anc[wave];
+        {
+            double sx = 0.0, sy = 0.0, sz = 0.0;
+            for (int t = lane; t < m; t += kWave) {
+                sx -= L.px[t];
+                sy -= L.py[t];
+                sz -= L.pz[t];
+            }
+            sx = wave_sum(sx);
+            sy = wave_sum(sy);
+            sz = wave_sum(sz);
+            if (lane == 0) {
+                anc[0] = sx;
+                anc[1] = sy;
+                anc[2] = sz;
+            }
+        }
         // ---- merge this anchor's forces into the tile, in anchor order
         if (lane == 0) {
             while (__hip_atomic_load(&s_turn, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) != ia)
@@ -608,10 +662,9 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
             tile.fy[te] += L.py[t];
             tile.fz[te] += L.pz[t];
         }
-        if (lane == 0) {
-            tile.fx[ia] += fax;
-            tile.fy[ia] += fay;
-            tile.fz[ia] += faz;
+        if (lane < 3) {
+            double *f = lane == 0 ? tile.fx : (lane == 1 ? tile.fy : tile.fz);
+            f[ia] += anc[lane];
         }
         __builtin_amdgcn_wave_barrier();
         if (lane == 0) __hip_atomic_store(&s_turn, ia + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -627,13 +680,28 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
     }
     __syncthreads();
 
-    // ---- flush the tile's forces: slot (offset, particle) has exactly one writer
-    for (int t = tid; t < nst; t += kTripThreads) {
-        const int o = stencil_cell_of<kNumHalf>(tab, t);
-        const int64_t p = tab.begin[o] + (t - tab.off[o]);
-        a.pf[(3 * o) * n + p] = tile.fx[t];
-        a.pf[(3 * o + 1) * n + p] = tile.fy[t];
-        a.pf[(3 * o + 2) * n + p] = tile.fz[t];
+    // ---- flush the tile's forces: slot (offset, particle) has exactly one writer; a
+    // whole-system chunk c writes slot c of every particle of the system, chunk 0 also
+    // clears the slots no chunk uses
+    if (whole) {
+        for (int t = tid; t < nst; t += kTripThreads) {
+            const int64_t p = p0s + t;
+            a.pf[(3 * loc) * n + p] = tile.fx[t];
+            a.pf[(3 * loc + 1) * n + p] = tile.fy[t];
+            a.pf[(3 * loc + 2) * n + p] = tile.fz[t];
+        }
+        if (loc == 0)
+            for (int o = d.ncell; o < kNumHalf; ++o)
+                for (int t = tid; t < nst; t += kTripThreads)
+                    for (int k = 0; k < 3; ++k) a.pf[(3 * o + k) * n + p0s + t] = 0.0;
+    } else {
+        for (int t = tid; t < nst; t += kTripThreads) {
+            const int o = stencil_cell_of<kNumHalf>(tab, t);
+            const int64_t p = tab.begin[o] + (t - tab.off[o]);
+            a.pf[(3 * o) * n + p] = tile.fx[t];
+            a.pf[(3 * o + 1) * n + p] = tile.fy[t];
+            a.pf[(3 * o + 2) * n + p] = tile.fz[t];
+        }
     }
     if (tid == 0) {
         long long c = 0;
@@ -670,93 +738,86 @@ __global__ void __launch_bounds__(256) k_triplet_gather(int64_t n, const double 
     if (!isfinite(s[0]) || !isfinite(s[1]) || !isfinite(s[2])) atomicOr(flags, kFlagNonFinite);
 }
 
+// One launch per force evaluation over the items of every system: workgroup b takes the
+// triplet base cell a.cell_map[b] (the host orders the cells by decreasing estimated
+// work, so the dispatcher starts the costly ones first), and the workgroups past the
+// a.ncell triplet items build the pair list of one pair-grid cell each, filling the
+// compute units that the triplet items leave idle as they drain.  (A persistent form
+// that pops items from a device counter was measured 20-25 % slower: the dispatcher
+// overlaps the start of one workgroup with the tail of another on a compute unit.)
+//   LB: the launch also builds the pair list; WH: some system is staged whole (the whole-
+//   system code path costs registers, so launches without such systems leave it out).
+template <typename T, bool LIST, bool ENERGY, bool WEIGHT, bool LB, bool WH>
+__global__ void __launch_bounds__(kTripThreads) k_triplet_items(TripletArgs a, ListBuildArgs b) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    const int it = (int)blockIdx.x;
+    if (it < a.ncell) {
+        const int base = a.cell_map ? a.cell_map[it] : it;
+        if (WH && a.sd[a.sys_of_cell[base]].whole)
+            triplet_block<T, LIST, ENERGY, WEIGHT, WH>(a, base, smem_raw);
+        else
+            triplet_block<T, LIST, ENERGY, WEIGHT, false>(a, base, smem_raw);
+    } else if constexpr (LB) {
+        list_build_block(b, it - a.ncell, smem_raw);
+    }
+}
+
 template <typename T, bool LIST, bool ENERGY, bool WEIGHT>
-__global__ void __launch_bounds__(kTripThreads) k_triplet(TripletArgs a) {
-    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
-    triplet_block<T, LIST, ENERGY, WEIGHT>(a, a.cell_map ? a.cell_map[blockIdx.x] : (int)blockIdx.x,
-                                           smem_raw);
-}
-
-// The triplet forces of every triplet-grid cell and, in the same launch, the Verlet list
-// rows of every pair-grid cell (workgroups past the triplet cells): the list build fills
-// the compute units that the triplet workgroups leave idle as they drain.
-template <typename T, bool ENERGY, bool WEIGHT>
-__global__ void __launch_bounds__(kTripThreads) k_triplet_and_list(TripletArgs a, ListBuildArgs b) {
-    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
-    if ((int)blockIdx.x < a.ncell)
-        triplet_block<T, false, ENERGY, WEIGHT>(a, a.cell_map ? a.cell_map[blockIdx.x] : (int)blockIdx.x,
-                                                smem_raw);
-    else
-        list_build_block(b, (int)blockIdx.x - a.ncell, smem_raw);
-}
-
-template <typename T, bool ENERGY, bool WEIGHT>
-static hipError_t launch_triplet_and_list_t(hipStream_t st, const TripletArgs &a,
-                                            const ListBuildArgs &b) {
-    const size_t lds = std::max(triplet_lds_bytes(a.stage_cap, a.list_cap, sizeof(T) == 4),
-                                list_build_bytes(b.stage_cap));
-    k_triplet_and_list<T, ENERGY, WEIGHT><<<a.ncell + b.ncell, kTripThreads, lds, st>>>(a, b);
+static hipError_t launch_items_t(hipStream_t st, const TripletArgs &a, const ListBuildArgs &b) {
+    size_t lds = a.ncell > 0 ? triplet_lds_bytes(a.stage_cap, a.list_cap, sizeof(T) == 4) : 0;
+    if (b.ncell > 0) lds = std::max(lds, list_build_bytes(b.stage_cap));
+    const int grid = a.ncell + b.ncell;
+    if (b.ncell > 0) {
+        if constexpr (!LIST) {
+            if (a.any_whole) k_triplet_items<T, LIST, ENERGY, WEIGHT, true, true><<<grid, kTripThreads, lds, st>>>(a, b);
+            else k_triplet_items<T, LIST, ENERGY, WEIGHT, true, false><<<grid, kTripThreads, lds, st>>>(a, b);
+        }
+    } else {
+        if (a.any_whole) k_triplet_items<T, LIST, ENERGY, WEIGHT, false, true><<<grid, kTripThreads, lds, st>>>(a, b);
+        else k_triplet_items<T, LIST, ENERGY, WEIGHT, false, false><<<grid, kTripThreads, lds, st>>>(a, b);
+    }
     return hipGetLastError();
 }
 
 template <typename T>
-static hipError_t launch_triplet_and_list_p(hipStream_t st, const TripletArgs &a,
-                                            const ListBuildArgs &b) {
+static hipError_t launch_items_p(hipStream_t st, const TripletArgs &a, const ListBuildArgs &b,
+                                 bool listing) {
+    if (listing) return launch_items_t<T, true, false, false>(st, a, b);
     if (a.w_out > 1.0)
-        return a.ce ? launch_triplet_and_list_t<T, true, true>(st, a, b)
-                    : launch_triplet_and_list_t<T, false, true>(st, a, b);
-    return a.ce ? launch_triplet_and_list_t<T, true, false>(st, a, b)
-                : launch_triplet_and_list_t<T, false, false>(st, a, b);
+        return a.ce ? launch_items_t<T, false, true, true>(st, a, b)
+                    : launch_items_t<T, false, false, true>(st, a, b);
+    return a.ce ? launch_items_t<T, false, true, false>(st, a, b)
+                : launch_items_t<T, false, false, false>(st, a, b);
 }
 
 hipError_t launch_triplet_and_list(hipStream_t st, const TripletArgs &a, const ListBuildArgs &b,
                                    bool fp32) {
     if (a.ncell + b.ncell <= 0) return hipSuccess;
-    return fp32 ? launch_triplet_and_list_p<float>(st, a, b)
-                : launch_triplet_and_list_p<double>(st, a, b);
-}
-
-template <typename T, bool LIST, bool ENERGY, bool WEIGHT>
-static hipError_t launch_triplet_t(hipStream_t st, const TripletArgs &a) {
-    const size_t lds = triplet_lds_bytes(a.stage_cap, a.list_cap, sizeof(T) == 4);
-    k_triplet<T, LIST, ENERGY, WEIGHT><<<a.ncell, kTripThreads, lds, st>>>(a);
-    return hipGetLastError();
-}
-
-template <typename T>
-static hipError_t launch_triplet_p(hipStream_t st, const TripletArgs &a, bool listing) {
-    if (listing) return launch_triplet_t<T, true, false, false>(st, a);
-    if (a.w_out > 1.0)
-        return a.ce ? launch_triplet_t<T, false, true, true>(st, a)
-                    : launch_triplet_t<T, false, false, true>(st, a);
-    if (a.ce) return launch_triplet_t<T, false, true, false>(st, a);
-    return launch_triplet_t<T, false, false, false>(st, a);
+    return fp32 ? launch_items_p<float>(st, a, b, false) : launch_items_p<double>(st, a, b, false);
 }
 
 hipError_t launch_triplet(hipStream_t st, const TripletArgs &a, bool fp32, bool listing) {
     if (a.ncell <= 0) return hipSuccess;
-    return fp32 ? launch_triplet_p<float>(st, a, listing) : launch_triplet_p<double>(st, a, listing);
+    const ListBuildArgs none{};
+    return fp32 ? launch_items_p<float>(st, a, none, listing)
+                : launch_items_p<double>(st, a, none, listing);
 }
 
 hipError_t configure_triplet_lds(size_t max_bytes) {
-    const void *fns[] = {(const void *)k_triplet<double, false, false, false>,
-                         (const void *)k_triplet<double, false, true, false>,
-                         (const void *)k_triplet<double, true, false, false>,
-                         (const void *)k_triplet<double, false, false, true>,
-                         (const void *)k_triplet<double, false, true, true>,
-                         (const void *)k_triplet<float, false, false, false>,
-                         (const void *)k_triplet<float, false, true, false>,
-                         (const void *)k_triplet<float, true, false, false>,
-                         (const void *)k_triplet<float, false, false, true>,
-                         (const void *)k_triplet<float, false, true, true>,
-                         (const void *)k_triplet_and_list<double, false, false>,
-                         (const void *)k_triplet_and_list<double, true, false>,
-                         (const void *)k_triplet_and_list<double, false, true>,
-                         (const void *)k_triplet_and_list<double, true, true>,
-                         (const void *)k_triplet_and_list<float, false, false>,
-                         (const void *)k_triplet_and_list<float, true, false>,
-                         (const void *)k_triplet_and_list<float, false, true>,
-                         (const void *)k_triplet_and_list<float, true, true>};
+#define MTS_ITEMS(T, LB, WH)                                                 \
+    (const void *)k_triplet_items<T, false, false, false, LB, WH>,           \
+        (const void *)k_triplet_items<T, false, true, false, LB, WH>,        \
+        (const void *)k_triplet_items<T, false, false, true, LB, WH>,        \
+        (const void *)k_triplet_items<T, false, true, true, LB, WH>
+    const void *fns[] = {(const void *)k_triplet_items<double, true, false, false, false, false>,
+                         (const void *)k_triplet_items<double, true, false, false, false, true>,
+                         (const void *)k_triplet_items<float, true, false, false, false, false>,
+                         (const void *)k_triplet_items<float, true, false, false, false, true>,
+                         MTS_ITEMS(double, false, false), MTS_ITEMS(double, true, false),
+                         MTS_ITEMS(double, false, true), MTS_ITEMS(double, true, true),
+                         MTS_ITEMS(float, false, false), MTS_ITEMS(float, true, false),
+                         MTS_ITEMS(float, false, true), MTS_ITEMS(float, true, true)};
+#undef MTS_ITEMS
     for (const void *f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_bytes);
         if (e != hipSuccess) return e;
@@ -764,10 +825,13 @@ hipError_t configure_triplet_lds(size_t max_bytes) {
     return hipSuccess;
 }
 
-int triplet_blocks_per_cu(bool fp32, size_t lds, size_t lds_per_cu) {
-    // the variant with the most registers of each precision
-    const void *f = fp32 ? (const void *)k_triplet_and_list<float, true, false>
-                         : (const void *)k_triplet_and_list<double, true, false>;
+int triplet_blocks_per_cu(bool fp32, bool whole, size_t lds, size_t lds_per_cu) {
+    // the variant with the most registers of each precision and kind of launch
+    const void *f =
+        fp32 ? (whole ? (const void *)k_triplet_items<float, false, true, true, true, true>
+                      : (const void *)k_triplet_items<float, false, true, true, true, false>)
+             : (whole ? (const void *)k_triplet_items<double, false, true, true, true, true>
+                      : (const void *)k_triplet_items<double, false, true, true, true, false>);
     int nb = 0;
     hipFuncAttributes fa{};
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kTripThreads, 0) != hipSuccess ||
