@@ -271,6 +271,33 @@ mts_status mts_enable_kernel_timing(mts_system *sys, int32_t enable);
  * duration in milliseconds (host arrays of 2).  Resets the counters. */
 mts_status mts_kernel_times(mts_system *sys, int64_t launches[2], double ms[2]);
 
+/* ---- without a handle, without allocating ---- */
+
+/* Device memory this entry point works in: one static array per GPU (16 MiB). */
+#define MTS_STATIC_SCRATCH_BYTES (16u << 20)
+
+/* For callers that cannot allocate device memory -- code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc: the triplet forces F3 (and, with ew,
+ * {U3, W3}) of one periodic system, as mts_compute_triplet_forces computes them on a
+ * one-system handle with the same params, but with no handle and no allocation.  The
+ * cell grid, partial-force slots and counters live in a static device array of
+ * MTS_STATIC_SCRATCH_BYTES that each GPU holds until the process ends (about 390 bytes
+ * per particle plus 32 per cell: roughly 40,000 particles at liquid density).
+ *   params  only epsilon/sigma/rc_pair (box check), nu, rc_triplet and precision are
+ *           used; method must be MTS_CUTOFF and k_outer <= 1 (else MTS_ERR_UNSUPPORTED)
+ *   n       particles (>= 0); box: host [3] edges, each > 2 max(rc_pair, rc_triplet)
+ *   x       dev [n][3] FP64 positions, any image; f3: dev [n][3] out; ew: dev [2] out or NULL
+ *   stream  HIP stream (NULL: the default stream) the work is enqueued on
+ * Synchronising: waits for the stream and returns MTS_OK, MTS_ERR_CAPACITY (the system
+ * needs more than MTS_STATIC_SCRATCH_BYTES, or a cell neighbourhood or forward list
+ * outgrew the capacities sized from the mean density: f3 is then invalid),
+ * MTS_ERR_NONFINITE, MTS_ERR_BOX_TOO_SMALL, MTS_ERR_INVALID_ARG or MTS_ERR_HIP.
+ * Every call on one GPU works in that GPU's one array: calls that overlap on a GPU
+ * (other threads, other streams) race and must be serialised by the caller. */
+mts_status mts_compute_triplet_forces_static(const mts_params *params, int64_t n,
+                                             const double box[3], const double *x,
+                                             double *f3, double *ew, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

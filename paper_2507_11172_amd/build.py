@@ -16,7 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmts.so")
-SOURCES = ["api.hip", "bin.hip", "pair.hip", "triplet.hip", "integrate.hip", "direct.hip"]
+SOURCES = ["api.hip", "bin.hip", "pair.hip", "triplet.hip", "integrate.hip", "direct.hip",
+           "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

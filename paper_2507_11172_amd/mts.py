@@ -34,7 +34,8 @@ EXPORTS = ("mts_init_system", "mts_destroy_system", "mts_build_cells", "mts_comp
            "mts_compute_triplet_forces", "mts_respa_step", "mts_sync", "mts_last_error",
            "mts_status_string", "mts_get_grid", "mts_get_cell_index", "mts_count_triplets",
            "mts_list_triplets", "mts_enable_kernel_timing", "mts_kernel_times", "mts_set_option",
-           "mts_autotune", "mts_get_tuning")
+           "mts_autotune", "mts_get_tuning", "mts_compute_triplet_forces_static")
+MTS_STATIC_SCRATCH_BYTES = 16 << 20
 MTS_OPT_CYCLE_GRAPH = 1
 MTS_OPT_LIST_LANES = 2
 
@@ -102,10 +103,13 @@ def load_library(path: str = LIB_PATH):
     L.mts_kernel_times.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
     L.mts_autotune.argtypes = [vp, vp, vp, C.c_int32, C.POINTER(mts_tuning)]
     L.mts_get_tuning.argtypes = [vp, C.POINTER(mts_tuning)]
+    L.mts_compute_triplet_forces_static.argtypes = [C.POINTER(mts_params), C.c_int64,
+                                                    C.POINTER(C.c_double), vp, vp, vp, vp]
     for name in ("mts_enable_kernel_timing", "mts_kernel_times", "mts_init_system",
                  "mts_build_cells", "mts_compute_pair_forces", "mts_compute_triplet_forces",
                  "mts_respa_step", "mts_sync", "mts_get_grid", "mts_get_cell_index",
-                 "mts_count_triplets", "mts_list_triplets", "mts_autotune", "mts_get_tuning"):
+                 "mts_count_triplets", "mts_list_triplets", "mts_autotune", "mts_get_tuning",
+                 "mts_compute_triplet_forces_static"):
         getattr(L, name).restype = C.c_int32
     _LIB = L
     return L
@@ -171,6 +175,25 @@ def _ptr(t, what: str, shape: Optional[Tuple[int, ...]] = None, dtype=None):
     if shape is not None and tuple(t.shape) != tuple(shape):
         raise ValueError("%s must have shape %s, got %s" % (what, shape, tuple(t.shape)))
     return C.c_void_p(t.data_ptr())
+
+
+def compute_triplet_forces_static(params: Params, box, x, f3, ew=None, stream=None):
+    """mts_compute_triplet_forces_static: F3 (and {U3, W3} into ew) of one periodic system
+    without a handle and without device allocation (synchronising)."""
+    import numpy as np
+    import torch
+    lib = load_library()
+    n = int(x.shape[0]) if x is not None else 0
+    b = np.ascontiguousarray(np.asarray(box, dtype=np.float64).reshape(3))
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    cp = params.to_c()
+    rc = lib.mts_compute_triplet_forces_static(
+        C.byref(cp), n, b.ctypes.data_as(C.POINTER(C.c_double)),
+        _ptr(x, "x", (n, 3), torch.float64), _ptr(f3, "f3", (n, 3), torch.float64),
+        _ptr(ew, "ew", (2,), torch.float64), C.c_void_p(stream.cuda_stream))
+    if rc != MTS_OK:
+        raise MTSError(rc, "mts_compute_triplet_forces_static")
 
 
 class System:
