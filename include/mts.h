@@ -165,7 +165,10 @@ mts_status mts_respa_step(mts_system *sys, double *x, double *v, int64_t n_iter,
 
 /* Waits for the stream and reports device flags raised since the last mts_sync:
  * MTS_ERR_CAPACITY (the affected forces are wrong; the tile or list capacities, or the
- * pair-list skin when a particle outran half of it, are enlarged for the next call) or
+ * pair-list skin when a particle outran half of it, are enlarged for the next call),
+ * MTS_ERR_UNSUPPORTED (an overflow that no enlargement can cure: a forward-neighbour list
+ * beyond its 256-entry limit, or a triplet tile and lists beyond a workgroup's LDS; the
+ * input is too dense for this library -- repeating the call fails the same way) or
  * MTS_ERR_NONFINITE.  Clears the flags. */
 mts_status mts_sync(mts_system *sys);
 
@@ -207,7 +210,11 @@ enum {
     /* Lanes per particle of the list force kernel: 4, 8 or 16 (else MTS_ERR_INVALID_ARG).
      * mts_autotune searches this knob and sets it; results differ between lane counts
      * only by the order of the per-particle sums.  Takes effect from the next call. */
-    MTS_OPT_LIST_LANES = 2
+    MTS_OPT_LIST_LANES = 2,
+    /* Triplet launches of a batch: 0 (default) one launch over every system; 1 one launch
+     * per tile class (systems grouped by the workgroups per CU their tiles allow).
+     * mts_autotune tries both for batches.  Results are bitwise the same either way. */
+    MTS_OPT_TILE_CLASSES = 3
 };
 
 /* Sets an option (see the MTS_OPT_ constants).  MTS_ERR_INVALID_ARG for unknown options. */
@@ -228,8 +235,10 @@ typedef struct {
     int32_t nl_cap;       /* pair-list row capacity */
     int32_t trials;       /* configurations the last mts_autotune timed (0: cached/untuned) */
     int32_t shared_launch;/* 1: the pair list is built in the triplet kernel's launch */
-    int32_t tile_classes; /* triplet launches per force evaluation: systems are grouped by
-                             the workgroups per CU their tile size allows, one launch each */
+    int32_t tile_classes; /* triplet launches per force evaluation: 1 by default (every
+                             system in one launch); mts_autotune may group the systems of a
+                             batch by the workgroups per CU their tile size allows, one
+                             launch per group, when that measures faster */
     double cycle_ms;      /* measured ms per full step (k inner steps, k * k_outer when
                              nested; 0: untuned) */
 } mts_tuning;

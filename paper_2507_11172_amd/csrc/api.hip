@@ -56,6 +56,9 @@ struct Config {
     int lanes = 16;               // lanes per particle in the list force kernel
     int list_cap = 0, pair_cap = 0, nl_cap = 0;  // 0: sized by heuristics
     std::vector<int> tile_need;   // triplet tile entries each system needs (empty: heuristic)
+    bool split = false;           // several systems: one triplet launch per tile class
+                                  // (systems allowing the same workgroups per CU) instead
+                                  // of a single launch at the occupancy of the largest tile
 };
 
 constexpr int kMaxTileClasses = 8;
@@ -343,14 +346,16 @@ int cap_for_lds(const mts_system *s, int lc, size_t limit) {
     return 32 * lo;
 }
 
-// The one triplet launch of a force evaluation (a single tile class): its tile capacity
-// is the largest need of any system, raised to the largest capacity that keeps the same
-// number of workgroups per CU (headroom against overflow at no cost in occupancy).  With
-// several systems the base cells are ordered by decreasing estimated work per cell
-// (anchors per cell x tile entries), so that the dispatcher starts the costly items
-// first and the launch ends on cheap ones.  Whole-system tiles (boxes of fewer
-// than 14 cells) hold N entries instead of 14 cells' worth, which keeps tiny boxes from
-// setting the capacity of the whole batch.
+// The triplet launches of a force evaluation.  By default one launch (a single tile
+// class): its tile capacity is the largest need of any system, raised to the largest
+// capacity that keeps the same number of workgroups per CU (headroom against overflow at
+// no cost in occupancy).  With cfg.split (a tuning choice for batches) the systems are
+// grouped into tile classes by the workgroups per CU their tiles allow, one launch per
+// class, so that a few large tiles do not set the occupancy of the whole batch.  Within a
+// launch the base cells of several systems are ordered by decreasing estimated work per
+// cell (anchors per cell x tile entries), so that the dispatcher starts the costly items
+// first.  Whole-system tiles (boxes of fewer than 14 cells) hold N entries instead of 14
+// cells' worth.
 mts_status classify(const mts_system *s, Layout &lo) {
     const int lc = lo.list_cap;
     lo.any_whole = false;
@@ -361,35 +366,52 @@ mts_status classify(const mts_system *s, Layout &lo) {
         const int r = triplet_blocks_per_cu(s->fp32, lo.any_whole, b, s->lds_per_cu);
         return r > 0 ? r : std::max(1, std::min(2, (int)(s->lds_per_cu / (b + 2048))));
     };
-    int need = 32;
-    for (int q = 0; q < s->nsys; ++q) need = std::max(need, round_up(std::max(32, lo.cfg.tile_need[q]), 32));
-    if (need > cmax) return MTS_ERR_UNSUPPORTED;
-    const int level = occ(need);
-    int lo_i = need / 32, hi_i = cmax / 32;
-    while (lo_i < hi_i) {  // largest capacity with at least this occupancy
-        const int mid = (lo_i + hi_i + 1) / 2;
-        if (occ(32 * mid) >= level) lo_i = mid;
-        else hi_i = mid - 1;
+    std::vector<int> occ_of(s->nsys), level;
+    int need_max = 32;
+    for (int q = 0; q < s->nsys; ++q) {
+        const int c = round_up(std::max(32, lo.cfg.tile_need[q]), 32);
+        if (c > cmax) return MTS_ERR_UNSUPPORTED;
+        need_max = std::max(need_max, c);
+        occ_of[q] = lo.cfg.split ? occ(c) : 0;
+        if (std::find(level.begin(), level.end(), occ_of[q]) == level.end()) level.push_back(occ_of[q]);
     }
-    lo.ncls = 1;
-    lo.cls_cap[0] = 32 * lo_i;
-    lo.stage_cap = lo.cls_cap[0];
-    lo.cls_off[0] = 0;
-    lo.cls_off[1] = lo.gt.ncell;
+    if (!lo.cfg.split) level.assign(1, occ(need_max));
+    if ((int)level.size() > kMaxTileClasses) return MTS_ERR_UNSUPPORTED;
+    std::sort(level.begin(), level.end(), [](int a, int b) { return a > b; });
+    // estimated work per cell of each system, for the order of the cells
+    std::vector<std::pair<double, int>> work(s->nsys);
+    for (int q = 0; q < s->nsys; ++q) {
+        const SysDesc &d = lo.gt.hsd[q];
+        const double per_cell = (double)d.n / std::max(1, d.ncell);
+        work[q] = {-per_cell * (d.whole ? (double)d.n : kNumHalf * per_cell), q};
+    }
+    std::stable_sort(work.begin(), work.end());
+    lo.ncls = (int)level.size();
+    lo.stage_cap = 0;
     lo.cls_order.clear();
-    if (s->nsys > 1) {
-        std::vector<std::pair<double, int>> work(s->nsys);
-        for (int q = 0; q < s->nsys; ++q) {
-            const SysDesc &d = lo.gt.hsd[q];
-            const double per_cell = (double)d.n / std::max(1, d.ncell);
-            work[q] = {-per_cell * (d.whole ? (double)d.n : kNumHalf * per_cell), q};
+    for (int c = 0; c < lo.ncls; ++c) {
+        const bool in_class_all = !lo.cfg.split;
+        int lo_i = 1;
+        for (int q = 0; q < s->nsys; ++q)
+            if (in_class_all || occ_of[q] == level[c])
+                lo_i = std::max(lo_i, round_up(std::max(32, lo.cfg.tile_need[q]), 32) / 32);
+        int hi_i = cmax / 32;
+        while (lo_i < hi_i) {  // largest capacity with at least this occupancy
+            const int mid = (lo_i + hi_i + 1) / 2;
+            if (occ(32 * mid) >= level[c]) lo_i = mid;
+            else hi_i = mid - 1;
         }
-        std::stable_sort(work.begin(), work.end());
-        for (const auto &w : work) {
-            const SysDesc &d = lo.gt.hsd[w.second];
-            for (int k = 0; k < d.ncell; ++k) lo.cls_order.push_back(d.cell0 + k);
-        }
+        lo.cls_cap[c] = 32 * lo_i;
+        lo.stage_cap = std::max(lo.stage_cap, lo.cls_cap[c]);
+        lo.cls_off[c] = (int)lo.cls_order.size();
+        for (const auto &w : work)
+            if (in_class_all || occ_of[w.second] == level[c]) {
+                const SysDesc &d = lo.gt.hsd[w.second];
+                for (int k = 0; k < d.ncell; ++k) lo.cls_order.push_back(d.cell0 + k);
+            }
     }
+    lo.cls_off[lo.ncls] = (int)lo.cls_order.size();
+    if (s->nsys == 1) lo.cls_order.clear();  // identity order, no cell map
     return MTS_OK;
 }
 
@@ -1363,6 +1385,14 @@ mts_status mts_set_option(mts_system *sys, int32_t option, int64_t value) {
             drop_graphs(sys);  // captured list launches carry the old lane count
             sys->lo.cfg.lanes = (int)value;
             return MTS_OK;
+        case MTS_OPT_TILE_CLASSES: {
+            if (value != 0 && value != 1)
+                return fail(sys, MTS_ERR_INVALID_ARG, "tile classes option must be 0 or 1");
+            if (sys->direct) return MTS_OK;  // no triplet tiles
+            Config c = sys->lo.cfg;
+            c.split = value != 0;
+            return set_layout(sys, c);
+        }
         default:
             return fail(sys, MTS_ERR_INVALID_ARG, "unknown option");
     }
@@ -1389,11 +1419,15 @@ mts_status mts_sync(mts_system *sys) {
                     lo.cfg.tile_need[q] = std::max(lo.cfg.tile_need[q], (int)std::ceil(1.15 * obs[q]) + 16);
             lo.pair_cap = std::min(4096, 2 * lo.pair_cap);
         }
+        // what cannot grow any further: forward lists at their 256-entry limit (list
+        // positions are packed in 8 bits), or a tile and lists beyond a workgroup's LDS
+        bool stuck = (flags & kFlagListOverflow) && old_l >= kMaxListCap;
         if (flags & kFlagListOverflow) lo.list_cap = std::min(kMaxListCap, 2 * lo.list_cap);
         if (classify(sys, lo) != MTS_OK) {  // beyond the LDS of a workgroup: keep the old sizes
             lo.cfg.tile_need = old_need;
             lo.list_cap = old_l;
             (void)classify(sys, lo);
+            stuck = true;
         }
         MTS_TRY(upload_classes(sys, lo));
         if (pair_lds_bytes(lo.pair_cap) > sys->max_lds) lo.pair_cap = old_p;
@@ -1410,14 +1444,17 @@ mts_status mts_sync(mts_system *sys) {
         sys->lo.cfg.pair_cap = sys->lo.pair_cap;
         sys->lo.cfg.nl_cap = sys->lo.nl_cap;
         drop_graphs(sys);  // captured launches carry the old sizes and pointers
-        char buf[240];
+        char buf[320];
         snprintf(buf, sizeof buf,
                  "capacity overflow (flags %d): triplet tile %d -> %d, pair tile %d -> %d, "
                  "neighbour list %d -> %d, pair list %d -> %d; results since the last sync "
-                 "are invalid",
+                 "are invalid%s",
                  flags, old_s, sys->lo.stage_cap, old_p, sys->lo.pair_cap, old_l, sys->lo.list_cap, old_n,
-                 sys->lo.nl_cap);
-        return fail(sys, MTS_ERR_CAPACITY, buf);
+                 sys->lo.nl_cap,
+                 stuck ? "; the triplet tile or forward lists cannot grow further (lists "
+                         "are limited to 256 entries, tile and lists to a workgroup's LDS)"
+                       : "");
+        return fail(sys, stuck ? MTS_ERR_UNSUPPORTED : MTS_ERR_CAPACITY, buf);
     }
     if (flags & kFlagSkin) {
         // the next call runs with a doubled skin (as far as the boxes allow)
@@ -1621,8 +1658,8 @@ mts_status mts_autotune(mts_system *sys, const double *x, const double *v, int32
         return el > budget;
     };
     std::pair<double, Config> best = trial(start);
-    // coordinate descent over the pair-list skin, the triplet cell size and the lanes
-    // per particle of the list force kernel
+    // coordinate descent over the pair-list skin, the triplet cell size, the lanes per
+    // particle of the list force kernel and, for batches, the triplet launch grouping
     std::vector<double> skins = {0.0, 0.15 * sys->p.sigma, 0.3 * sys->p.sigma, 0.5 * sys->p.sigma};
     for (double sk : skins) {
         if (over_budget()) break;
@@ -1645,6 +1682,14 @@ mts_status mts_autotune(mts_system *sys, const double *x, const double *v, int32
         Config c = best.second;
         if (c.lanes == g) continue;
         c.lanes = g;
+        auto r = trial(c);
+        if (r.first < 0.98 * best.first) best = r;
+    }
+    // batches: one triplet launch at the occupancy of the largest tile, or one launch per
+    // tile class
+    if (sys->nsys > 1 && !over_budget()) {
+        Config c = best.second;
+        c.split = !c.split;
         auto r = trial(c);
         if (r.first < 0.98 * best.first) best = r;
     }

@@ -38,6 +38,7 @@ EXPORTS = ("mts_init_system", "mts_destroy_system", "mts_build_cells", "mts_comp
 MTS_STATIC_SCRATCH_BYTES = 16 << 20
 MTS_OPT_CYCLE_GRAPH = 1
 MTS_OPT_LIST_LANES = 2
+MTS_OPT_TILE_CLASSES = 3
 
 
 class MTSError(RuntimeError):

@@ -194,6 +194,37 @@ def test_fp64_at_scale_32k():
     assert rel_err(f3, full.f) <= 1e-12
 
 
+@pytest.mark.slow
+def test_algorithm2_at_32k_both_forms():
+    """32,000 particles, k = 10, two full steps of Algorithm 2 in the bench's tuned launch
+    configuration, against the oracle's whole-system r-RESPA: the FP64 path within
+    round-off amplification, the FP32 form within its force bar's effect on a 20-step
+    trajectory and 1e-7 per particle on every energy record."""
+    torch = _torch()
+    w = W.fp64_at_scale()
+    box = w.box[0]
+    k, n_iter = 10, 20
+    xo, vo, eo = oracle.respa(w.x, w.v, box, n_iter=n_iter, k=k)
+    for precision in ("fp64", "fp32"):
+        with _system(w, k=k, precision=precision) as s:
+            x, v = _dev(w.x), _dev(w.v)
+            s.autotune(x, v, 1500)
+            e = torch.zeros((n_iter // k + 1, 1, 5), dtype=torch.float64, device="cuda")
+            s.respa_step(x, v, n_iter, e)
+            s.sync()
+        dx = x.cpu().numpy() - xo
+        dx -= box * np.rint(dx / box)
+        de = np.abs(e.cpu().numpy()[:, 0, :] - eo)
+        if precision == "fp64":
+            assert np.abs(dx).max() <= 1e-10
+            assert np.abs(v.cpu().numpy() - vo).max() <= 1e-10 * np.abs(vo).max()
+            assert de.max() <= 1e-10 * np.abs(eo).max()
+        else:
+            assert np.abs(dx).max() <= 1e-9
+            assert np.abs(v.cpu().numpy() - vo).max() <= 1e-6 * np.abs(vo).max()
+            assert de[:, 1:3].sum(axis=1).max() / w.n_total <= 1e-7
+
+
 @pytest.mark.parametrize("k,n_iter", [(1, 100), (2, 20), (5, 40)])
 def test_respa_matches_oracle(k, n_iter):
     torch = _torch()
@@ -317,22 +348,61 @@ def test_error_paths():
 
 
 def test_capacity_overflow_is_reported_then_recovers():
-    """A dense clump overflows the LDS tile: the kernel clamps, flags, and the next call
-    runs with a doubled tile."""
+    """A compressed block at density 2.3 filling 40 % of a 12^3 box (mean density 0.93):
+    its triplet tiles and forward lists outgrow the capacities sized from the mean
+    density.  The first call reports MTS_ERR_CAPACITY; the library enlarges what
+    overflowed, and the repeated call matches the oracle."""
     torch = _torch()
     from paper_2507_11172_amd import mts
     rng = W.rng_for(9)
-    n = 700
-    x = 1.0 + rng.uniform(0.0, 2.4, size=(n, 3)) * np.array([1.0, 1.0, 1.0])
-    w = W.Workload("clump", x, np.zeros_like(x), np.full((1, 3), 20.0), np.array([n]),
-                   np.array([0.0]), nu=0.0)
+    cells = W.fcc_sites((10, 10, 4), np.full(3, 12.0 / 10))  # 1,600 sites, density 2.3
+    x = (cells + rng.uniform(-0.05, 0.05, cells.shape)) % 12.0
+    n = x.shape[0]
+    box = np.full(3, 12.0)
+    w = W.Workload("block", x, np.zeros_like(x), box[None, :], np.array([n]), np.array([0.0]))
+    ref = oracle.triplet_forces(x, box)
     with _system(w) as s:
+        cap0 = s.tuning()["stage_cap"]
         xd = _dev(x)
         f = torch.empty_like(xd)
         s.compute_triplet_forces(xd, f)
         with pytest.raises(mts.MTSError) as e:
             s.sync()
         assert e.value.code == mts.MTS_ERR_CAPACITY
+        assert s.tuning()["stage_cap"] > cap0
+        s.compute_triplet_forces(xd, f)
+        s.sync()
+    assert rel_err(f.cpu().numpy(), ref.f) <= 1e-12
+
+
+def test_capacity_that_cannot_grow_is_unsupported():
+    """700 particles packed into a 2.4^3 clump: every anchor has about 700 forward
+    neighbours, beyond the 256 that lists can hold.  The library enlarges what it can
+    and, once the lists are at their limit, reports MTS_ERR_UNSUPPORTED instead of a
+    capacity error that a retry could cure."""
+    torch = _torch()
+    from paper_2507_11172_amd import mts
+    rng = W.rng_for(9)
+    n = 700
+    x = 1.0 + rng.uniform(0.0, 2.4, size=(n, 3))
+    w = W.Workload("clump", x, np.zeros_like(x), np.full((1, 3), 20.0), np.array([n]),
+                   np.array([0.0]), nu=0.0)
+    codes = []
+    with _system(w) as s:
+        xd = _dev(x)
+        f = torch.empty_like(xd)
+        for _ in range(6):
+            s.compute_triplet_forces(xd, f)
+            try:
+                s.sync()
+                codes.append(mts.MTS_OK)
+            except mts.MTSError as e:
+                codes.append(e.code)
+            if codes[-1] == mts.MTS_ERR_UNSUPPORTED:
+                break
+    assert codes[0] == mts.MTS_ERR_CAPACITY
+    assert codes[-1] == mts.MTS_ERR_UNSUPPORTED, codes
+    assert mts.MTS_OK not in codes
 
 
 @pytest.mark.parametrize("k", [3, 10])
@@ -501,11 +571,11 @@ def test_batched_256_replicas_full_size():
         assert rel_err(b3[lo:hi], a3[lo:hi]) <= 1e-5, r
         assert abs(ub[r] - ua[r]) / (hi - lo) <= 1e-7, r
 
-def _class_batch():
+def _class_batch(extra=()):
     """A liquid-density box with five cells per edge, one too small for three cells per
     edge (two large cells: a half-stencil tile would hold ~1.75 N entries, so the system
-    is staged whole) and one in between."""
-    specs = [(2048, 0.8, 71), (365, 0.9, 72), (1200, 0.7, 73)]
+    is staged whole) and one in between; `extra` adds (n, density, seed) systems."""
+    specs = [(2048, 0.8, 71), (365, 0.9, 72), (1200, 0.7, 73)] + list(extra)
     xs, vs, boxes = [], [], []
     for n, rho, seed in specs:
         rng = W.rng_for(seed)
@@ -574,6 +644,48 @@ def test_tile_classes_match_oracle_and_single_systems():
         s.compute_triplet_forces(x, f3)
         s.sync()
     assert rel_err(f3.cpu().numpy(), fb3.numpy()) <= 1e-5
+
+
+def test_batch_launch_grouping_option_and_autotune():
+    """A batch of very different tiles (with a box of cells barely above the cutoff, whose
+    small tiles allow more workgroups per CU than the others) in one triplet launch and
+    split into tile classes (MTS_OPT_TILE_CLASSES): bitwise the same forces and trajectory;
+    the autotuner, which tries both groupings for batches, keeps the oracle bars."""
+    torch = _torch()
+    from paper_2507_11172_amd import mts
+    w = _class_batch(extra=[(812, 0.8, 74)])
+    k, n_iter = 5, 20
+    for precision in ("fp32", "fp64"):
+        out = []
+        for split in (0, 1):
+            with _system(w, k=k, skin=0.3, precision=precision) as s:
+                s.set_option(mts.MTS_OPT_TILE_CLASSES, split)
+                classes = s.tuning()["tile_classes"]
+                assert classes == 1 if not split else classes >= 1
+                if precision == "fp32" and split:  # 16-byte list entries: the tiles differ
+                    assert classes >= 2
+                x, v = _dev(w.x), _dev(w.v)
+                f3 = torch.empty_like(x)
+                s.compute_triplet_forces(x, f3)
+                s.respa_step(x, v, n_iter)
+                s.sync()
+                out.append((f3.cpu(), x.cpu(), v.cpu()))
+        for a, b in zip(out[0], out[1]):
+            assert torch.equal(a, b)
+    with _system(w, k=k) as s:
+        x, v = _dev(w.x), _dev(w.v)
+        t = s.autotune(x, v, budget_ms=3000)
+        assert t["trials"] >= 2
+        f3 = torch.empty_like(x)
+        s.compute_triplet_forces(x, f3)
+        s.sync()
+    off = 0
+    for r in range(w.n_systems):
+        n = int(w.n_particles[r])
+        sl = slice(off, off + n)
+        ref = oracle.triplet_forces(w.x[sl], w.box[r]).f
+        assert rel_err(f3.cpu().numpy()[sl], ref) <= 1e-12, r
+        off += n
 
 
 def _forces_and_energies(w, precision):
