@@ -745,6 +745,43 @@ def traffic_summary(fetch_csv: str, write_csv: str, kernel: str, workload: str,
     return out
 
 
+def traffic_table(fetch_csv: str, write_csv: str, stats_csv: str = "", copy_kib: float = 262144.0):
+    """Markdown table of HBM bytes per dispatch of every kernel in a FETCH_SIZE and a
+    WRITE_SIZE counter run, each counter scaled by the plain copy as in traffic_summary;
+    with a rocprofv3 kernel-stats CSV, the average duration and the rate they imply."""
+    import csv
+    per = {}
+    for col, path in ((0, fetch_csv), (1, write_csv)):
+        rows = _counter_rows(path)
+        copy = max((v for (k, _), v in rows.items() if "copyBuffer" in k), default=0.0)
+        if copy <= 0:
+            raise SystemExit("no calibration copy in %s" % path)
+        acc = {}
+        for (k, _), v in rows.items():
+            acc.setdefault(k, []).append(v * copy_kib / copy)
+        for k, vals in acc.items():
+            per.setdefault(k, [None, None, 0])
+            per[k][col] = sum(vals) / len(vals)
+            per[k][2] = max(per[k][2], len(vals))
+    avg_us = {}
+    if stats_csv:
+        with open(stats_csv, newline="") as f:
+            for row in csv.DictReader(f):
+                avg_us[row["Name"]] = float(row["AverageNs"]) / 1e3
+    lines = ["| kernel | dispatches | FETCH MiB | WRITE MiB | total MiB | avg us | GB/s |",
+             "|---|---:|---:|---:|---:|---:|---:|"]
+    for k in sorted(per, key=lambda k: -((per[k][0] or 0) + (per[k][1] or 0))):
+        fe, wr, nd = per[k]
+        tot = (fe or 0) + (wr or 0)
+        us = avg_us.get(k)
+        rate = "%.0f" % (tot * 1024 / (us * 1e3)) if us and fe is not None and wr is not None else "-"
+        lines.append("| `%s` | %d | %s | %s | %.1f | %s | %s |" % (
+            k.split("(")[0].replace("void ", ""), nd,
+            "-" if fe is None else "%.1f" % (fe / 1024), "-" if wr is None else "%.1f" % (wr / 1024),
+            tot / 1024, "-" if us is None else "%.1f" % us, rate))
+    return "\n".join(lines)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__,
                                  formatter_class=argparse.RawDescriptionHelpFormatter)
@@ -764,7 +801,10 @@ def main(argv=None):
     ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="scale the two counter runs of --traffic-probe into HBM bytes per "
                          "launch of --traffic-kernel and print the JSON row")
-    ap.add_argument("--traffic-kernel", default="mts::k_triplet_items<double, false, true, false>(")
+    ap.add_argument("--traffic-table", nargs="+", metavar="CSV",
+                    help="FETCH_CSV WRITE_CSV [KERNEL_STATS_CSV]: print the HBM bytes of every "
+                         "kernel of the two counter runs as a markdown table")
+    ap.add_argument("--traffic-kernel", default="mts::k_triplet_items<double, false, true, false, true, false>(")
     ap.add_argument("--loop-steps", type=int, default=5,
                     help="cycles of the one-handle-per-replica loop (batched workload)")
     ap.add_argument("--rvite-sweep", action="store_true",
@@ -816,6 +856,11 @@ def main(argv=None):
     w = _workload(args.workload)
     k = args.k or w.k
     precision = args.precision or w.precision
+    if args.traffic_table:
+        if len(args.traffic_table) not in (2, 3):
+            raise SystemExit("--traffic-table takes FETCH_CSV WRITE_CSV [KERNEL_STATS_CSV]")
+        print(traffic_table(*args.traffic_table), flush=True)
+        return 0
     if args.traffic_summary:
         kern = args.traffic_kernel.split("<")[0].split("::")[-1]
         row = traffic_summary(args.traffic_summary[0], args.traffic_summary[1],
