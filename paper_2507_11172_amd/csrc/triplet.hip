@@ -16,26 +16,31 @@
 //    LDS-staged neighbour-cell tile shared by the workgroup.  Waves take anchors
 //    round-robin.
 //  * Per anchor (one wave):
-//      A. the canonical FP64 displacement of every tile entry after the anchor and its
-//         exact cutoff test, two entries per lane per round -- ballot + prefix-count
-//         compaction into the wave's list (the displacement u from the anchor and
-//         |u|^2, the tile index), in tile order;
-//      B. each lane owns one list entry j (kept in registers) and walks its partners
-//         k = j + 1 .. j + m/2 around the list, two per round, so all m(m-1)/2 pairs
-//         are visited once with balanced lanes; the third edge j-k is prefiltered in
-//         FP32 and settled, when within rounding of the cutoff, with the canonical FP64
-//         displacement; hits are compacted into a queue;
-//      C. evaluate ATM two queued hits per lane (two independent chains in flight)
-//         once 128 are pending, and on the rest at the end of the anchor.
-//  * Accumulation.  The anchor's force stays in registers and is summed across the wave
-//    with DPP row operations; partner forces go to the wave's per-list-slot FP64
-//    partials (LDS atomics inside one wave: a fixed order).  When the anchor is done,
-//    the wave merges its partials into the shared tile accumulator in anchor order,
-//    serialised by a turn counter in LDS -- so the result is bitwise reproducible
-//    without float atomics across waves.  At the end the tile is flushed to
+//      A. the tile entries after the anchor are tested against the cutoff -- in the FP64
+//         form an FP32 prefilter over an FP32 copy of the tile first, then the canonical
+//         FP64 displacement and exact test of the candidates -- and ballot + prefix-count
+//         compaction keeps the hits in tile order as the wave's list (displacement u
+//         from the anchor and |u|^2, tile index);
+//      B. every unordered pair of list entries is tested once along the flattened
+//         diagonals of the circulant (item q = (dd - 1) m + j stands for j and
+//         k = (j + dd) mod m), so all lanes are busy whatever m is; the third edge j-k is
+//         prefiltered in FP32 and settled, when within rounding of the cutoff, with the
+//         canonical FP64 displacement; hits are compacted into a ring queue;
+//      C. ATM is evaluated one queued hit per lane whenever 64 are pending, and on the
+//         rest at the end of the anchor.
+//  * Accumulation.  The partner forces of each hit go to the wave's per-list-slot FP64
+//    partials by LDS atomics issued from one wave.  The order is taken to be fixed: the
+//    wave's instructions reach the LDS in program order, and the lanes of one
+//    instruction that hit the same address are assumed to be applied in a fixed
+//    (hardware) order -- an assumption that bitwise repeat runs at 32,000 particles
+//    guard.  By Newton's third law within the triplet, the anchor's force is minus the
+//    sum of the partials, formed by a fixed-order wave sum.  When the anchor is done, the wave
+//    merges its partials into the shared tile accumulator in anchor order, serialised by
+//    a turn counter in LDS -- so the result is bitwise reproducible without float
+//    atomics across waves.  At the end the tile is flushed to
 //    pf[offset][component][particle]; every (offset, particle) slot has exactly one
-//    writer, and k_triplet_gather sums the 14 slots in fixed order.  Nothing is
-//    accumulated with global float atomics.
+//    writer, and the gather sums the 14 slots in fixed order.  Nothing is accumulated
+//    with global float atomics.
 //
 // Cutoff geometry is FP64 and canonical, so the triplet set is bit-identical to the
 // FP64 oracle's in both precisions; T is the precision of the ATM arithmetic.  LDS
@@ -229,7 +234,7 @@ __device__ __forceinline__ AtmOut<T> atm_triplet(const ListEnt<T> &lj, const Lis
     const T ux = lj.ux, uy = lj.uy, uz = lj.uz;
     const T wx = lk.ux, wy = lk.uy, wz = lk.uz;
     const T vx = wx - ux, vy = wy - uy, vz = wz - uz;
-    const T cc = (vx * vx + vy * vy) + vz * vz;
+    const T cc = fma(vz, vz, fma(vy, vy, vx * vx));
     const T aa = lj.a, bb = lk.a;
     T phi, ga, gb, gc;
     atm_terms<T>(aa, bb, cc, nu, phi, ga, gb, gc);
@@ -396,8 +401,8 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
                 const float4 r2 = tile.r[t2 < nst ? t2 : ia];
                 const float x1 = r1.x - ar.x, y1 = r1.y - ar.y, z1 = r1.z - ar.z;
                 const float x2 = r2.x - ar.x, y2 = r2.y - ar.y, z2 = r2.z - ar.z;
-                const bool in1 = t1 < nst && (x1 * x1 + y1 * y1) + z1 * z1 <= pf_hi;
-                const bool in2 = t2 < nst && (x2 * x2 + y2 * y2) + z2 * z2 <= pf_hi;
+                const bool in1 = t1 < nst && fmaf(z1, z1, fmaf(y1, y1, x1 * x1)) <= pf_hi;
+                const bool in2 = t2 < nst && fmaf(z2, z2, fmaf(y2, y2, x2 * x2)) <= pf_hi;
                 const uint64_t m1 = __ballot(in1), m2 = __ballot(in2);
                 const int n1 = __popcll(m1);
                 const int p1 = mc + below(m1), p2 = mc + n1 + below(m2);
@@ -595,7 +600,7 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
                     kk[p] = k;
                     const ListEnt<float> fj = L.f[ok ? jj[p] : 0], fk = L.f[ok ? k : 0];
                     const float x = fk.ux - fj.ux, y = fk.uy - fj.uy, z = fk.uz - fj.uz;
-                    const float c = (x * x + y * y) + z * z;
+                    const float c = fmaf(z, z, fmaf(y, y, x * x));
                     hit[p] = ok && c <= jk_lo;
                     amb[p] = ok && c > jk_lo && c <= jk_hi;
                     any_amb = any_amb || amb[p];

@@ -327,6 +327,30 @@ def test_determinism_and_resume():
         assert torch.equal(x1, x2) and torch.equal(v1, v2)
 
 
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_triplet_forces_bitwise_repeatable_at_scale(precision):
+    """Partner forces are summed by FP64 LDS atomics issued from one wave, and lanes of one
+    instruction can hit the same list slot; the kernel relies on the hardware applying
+    them in a fixed order.  Five evaluations (with energies) of the 32,000-particle system,
+    about 6.4 million triplets, must agree bit for bit, and with a second handle."""
+    torch = _torch()
+    w = W.fp64_at_scale()
+    outs = []
+    for _ in range(2):
+        with _system(w, precision=precision) as s:
+            x = _dev(w.x)
+            for _ in range(5 if not outs else 1):
+                f3 = torch.empty_like(x)
+                ew = torch.zeros((1, 2), dtype=torch.float64, device="cuda")
+                s.compute_triplet_forces(x, f3, ew)
+                outs.append((f3, ew))
+            s.sync()
+    f_ref, e_ref = outs[0]
+    assert float(e_ref[0, 0]) != 0.0
+    for f, e in outs[1:]:
+        assert torch.equal(f, f_ref) and torch.equal(e, e_ref)
+
 def test_error_paths():
     torch = _torch()
     from paper_2507_11172_amd import mts
