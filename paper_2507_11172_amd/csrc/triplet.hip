@@ -242,9 +242,9 @@ __device__ __forceinline__ AtmOut<T> atm_triplet(const ListEnt<T> &lj, const Lis
     o.fjx = fma(gc, vx, -ga * ux);
     o.fjy = fma(gc, vy, -ga * uy);
     o.fjz = fma(gc, vz, -ga * uz);
-    o.fkx = -fma(gb, wx, gc * vx);
-    o.fky = -fma(gb, wy, gc * vy);
-    o.fkz = -fma(gb, wz, gc * vz);
+    o.fkx = fma(-gb, wx, -(gc * vx));  // -(gb w + gc v), rounded once as before
+    o.fky = fma(-gb, wy, -(gc * vy));
+    o.fkz = fma(-gb, wz, -(gc * vz));
     o.phi = phi;
     o.vir = -fma(aa, ga, fma(bb, gb, cc * gc));
     return o;
@@ -252,7 +252,7 @@ __device__ __forceinline__ AtmOut<T> atm_triplet(const ListEnt<T> &lj, const Lis
 
 // Wave-wide sum landing in lane 63, by DPP: quad swaps, half-row and row mirrors, then
 // row broadcasts 15 and 31 (fixed order, so bitwise reproducible).  Returned to every
-// lane through a read of lane 63.
+// lane through a read of lane 63.  Called with every lane active.
 template <int CTRL, int ROWMASK>
 __device__ __forceinline__ double dpp_d(double v) {
     const long long b = __builtin_bit_cast(long long, v);
@@ -261,17 +261,45 @@ __device__ __forceinline__ double dpp_d(double v) {
     return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
 
+// The same move for a permutation within each row: every lane is written from a lane of
+// its own row, so the destination's previous content is not needed (no zero fill).
+template <int CTRL>
+__device__ __forceinline__ double dpp_row(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ double lane_value(double v, int l) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum of each row of 16 lanes, in every lane of the row.
+__device__ __forceinline__ double row_sum(double v) {
+    v += dpp_row<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_row<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_row<0x141>(v);  // row_half_mirror
+    v += dpp_row<0x140>(v);  // row_mirror
+    return v;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
-    v += dpp_d<0xB1, 0xf>(v);   // quad_perm [1,0,3,2]
-    v += dpp_d<0x4E, 0xf>(v);   // quad_perm [2,3,0,1]
-    v += dpp_d<0x141, 0xf>(v);  // row_half_mirror
-    v += dpp_d<0x140, 0xf>(v);  // row_mirror
+    v = row_sum(v);
     v += dpp_d<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
     v += dpp_d<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
-    const long long b = __builtin_bit_cast(long long, v);
-    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), 63);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
-    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+    return lane_value(v, 63);
+}
+
+// wave_sum when lanes 32..63 hold +0.0: lane 31 holds rows 0 and 1 summed in the same
+// order, and adding the zero rows 2 and 3 would not change a bit.
+__device__ __forceinline__ double wave_sum_lo(double v) {
+    v = row_sum(v);
+    v += dpp_d<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+    return lane_value(v, 31);
 }
 
 // Sorted particle index of tile entry t (debug listing only).
@@ -565,14 +593,22 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
         // (j < m/2) covers those pairs once, so q < m(m - 1)/2 visits every pair exactly
         // once with all lanes busy.  Lane l takes q = l + 64 p (p < P) and advances by 64 P.
         constexpr int P = kPairsPerLane<T>;
+        m = __builtin_amdgcn_readfirstlane(m);  // wave-uniform: keeps m and what follows scalar
         const int npair = m * (m - 1) / 2;
         if (npair > 0) {
-            const int adv_d = (P * kWave) / m, adv_j = P * kWave - adv_d * m;  // 64 P = adv_d m + adv_j
+            // 64 P = adv_d m + adv_j, and item q = (dd - 1) m + j: quotients from the
+            // hardware reciprocal of m, corrected by one step where it rounded across
+            const float rm = __builtin_amdgcn_rcpf((float)m);
+            int adv_d = (int)((float)(P * kWave) * rm), adv_j = P * kWave - adv_d * m;
+            if (adv_j >= m) { adv_j -= m; ++adv_d; }
+            if (adv_j < 0) { adv_j += m; --adv_d; }
+            adv_d = __builtin_amdgcn_readfirstlane(adv_d);
+            adv_j = __builtin_amdgcn_readfirstlane(adv_j);
             int jj[P], dq[P];
 #pragma unroll
             for (int p = 0; p < P; ++p) {  // (j, dd) of item lane + 64 p
                 const int q = lane + p * kWave;
-                int d0 = (int)(((float)q + 0.5f) / (float)m);
+                int d0 = (int)(((float)q + 0.5f) * rm);
                 int j0 = q - d0 * m;
                 if (j0 >= m) { j0 -= m; ++d0; }
                 if (j0 < 0) { j0 += m; --d0; }
@@ -589,11 +625,16 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
                 return norm2(wx, wy, wz) <= rc2;
             };
             for (int q0 = 0; q0 < npair; q0 += P * kWave) {
+                // a last round of at most 64 items leaves out its second half
+                const bool full = q0 + kWave < npair;  // wave-uniform
                 bool hit[P], amb[P];
                 int kk[P];
                 bool any_amb = false;
 #pragma unroll
                 for (int p = 0; p < P; ++p) {
+                    hit[p] = amb[p] = false;
+                    kk[p] = 0;
+                    if (p > 0 && !full) continue;
                     const bool ok = q0 + p * kWave + lane < npair;
                     int k = jj[p] + dq[p];
                     k -= k >= m ? m : 0;
@@ -613,6 +654,7 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
                 // append the hits to the ring queue: lane order, item by item
 #pragma unroll
                 for (int p = 0; p < P; ++p) {
+                    if (p > 0 && !full) break;
                     const uint64_t mh = __ballot(hit[p]);
                     if (hit[p]) Q[(qt + below(mh)) & kQueueMask] = (unsigned short)(jj[p] | (kk[p] << 8));
                     qt += __popcll(mh);
@@ -645,9 +687,15 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
                 sy -= L.py[t];
                 sz -= L.pz[t];
             }
-            sx = wave_sum(sx);
-            sy = wave_sum(sy);
-            sz = wave_sum(sz);
+            if (m <= 32) {  // lanes from m on hold +0.0 and none holds -0.0: rows 2, 3 add nothing
+                sx = wave_sum_lo(sx);
+                sy = wave_sum_lo(sy);
+                sz = wave_sum_lo(sz);
+            } else {
+                sx = wave_sum(sx);
+                sy = wave_sum(sy);
+                sz = wave_sum(sz);
+            }
             if (lane == 0) {
                 anc[0] = sx;
                 anc[1] = sy;
