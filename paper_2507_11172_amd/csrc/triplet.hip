@@ -16,18 +16,19 @@
 //    LDS-staged neighbour-cell tile shared by the workgroup.  Waves take anchors
 //    round-robin.
 //  * Per anchor (one wave):
-//      A. the tile entries after the anchor are tested against the cutoff -- in the FP64
-//         form an FP32 prefilter over an FP32 copy of the tile first, then the canonical
-//         FP64 displacement and exact test of the candidates -- and ballot + prefix-count
-//         compaction keeps the hits in tile order as the wave's list (displacement u
-//         from the anchor and |u|^2, tile index);
+//      A. the canonical FP64 displacement of every tile entry after the anchor and its
+//         exact cutoff test, two entries per lane per round; ballot + prefix-count
+//         compaction keeps the hits in tile order as the wave's list (tile index, and the
+//         displacement u from the anchor with |u|^2 in FP32);
 //      B. every unordered pair of list entries is tested once along the flattened
 //         diagonals of the circulant (item q = (dd - 1) m + j stands for j and
 //         k = (j + dd) mod m), so all lanes are busy whatever m is; the third edge j-k is
 //         prefiltered in FP32 and settled, when within rounding of the cutoff, with the
 //         canonical FP64 displacement; hits are compacted into a ring queue;
 //      C. ATM is evaluated one queued hit per lane whenever 64 are pending, and on the
-//         rest at the end of the anchor.
+//         rest at the end of the anchor.  The FP32 form takes u from the list; the FP64
+//         form recomputes it from the staged positions (the same canonical displacement,
+//         so the same bits), which keeps a workgroup's LDS small enough for four per CU.
 //  * Accumulation.  The partner forces of each hit go to the wave's per-list-slot FP64
 //    partials by LDS atomics issued from one wave.  The order is taken to be fixed: the
 //    wave's instructions reach the LDS in program order, and the lanes of one
@@ -87,17 +88,17 @@ struct alignas(16) TileEnt {   // its LDS form: the shift as a 2-bit code per co
 };
 
 // Forward neighbour j of the current anchor: the canonical displacement anchor -> j and
-// its square |u|^2, rounded to the precision T of the ATM arithmetic (16 bytes in FP32,
-// 32 in FP64).  The j-k sweep reads FP32 entries: the FP32 form's own, or an FP32 copy
-// beside the FP64 form's (at the FP64 rate of CDNA4 the FP64 test costs the same ALU
-// time, but twice the LDS bytes).
+// its square |u|^2 in the precision T of the ATM arithmetic.  The list keeps them in FP32
+// (16 bytes): the j-k sweep tests in FP32, and the FP32 form evaluates from them; the
+// FP64 form recomputes its FP64 entries from the tile when it evaluates a hit (32 bytes
+// per entry and wave would cost the fourth workgroup per CU, which is worth more than
+// the recomputation).
 template <typename T>
 struct alignas(16) ListEnt {
     T ux, uy, uz, a;
 };
 
-static_assert(sizeof(TileEnt) == 32 && sizeof(ListEnt<double>) == 32 &&
-              sizeof(ListEnt<float>) == 16, "LDS entry sizes");
+static_assert(sizeof(TileEnt) == 32 && sizeof(ListEnt<float>) == 16, "LDS entry sizes");
 
 __device__ __forceinline__ PosEnt unpack(const TileEnt &t, double L0, double L1, double L2) {
     PosEnt e;
@@ -122,8 +123,6 @@ __device__ __forceinline__ void mic_from(PosEnt &e, const PosEnt &an, const SysD
 struct Tile {                  // staged neighbour cells, CAP entries
     double2 *exy;              // TileEnt halves: (x, y) and (z, shift code)
     double2 *ezc;
-    float4 *r;                 // FP64 form only: FP32 position relative to the base cell
-                               // (prefilter of the anchor lists)
     double *fx, *fy, *fz;      // force accumulators
 };
 
@@ -143,67 +142,29 @@ __device__ __forceinline__ void tile_set(const Tile &tl, int t, const TileEnt &e
     tl.ezc[t] = make_double2(e.z, __longlong_as_double((long long)e.code));
 }
 
-// A wave's list entries in the precision of the arithmetic: FP32 entries are one 16-byte
-// array, FP64 entries two arrays of (ux, uy) and (uz, a) halves.
-template <typename T>
-struct ListStore;
-template <>
-struct ListStore<float> {
-    ListEnt<float> *u;
-    __device__ __forceinline__ ListEnt<float> get(int i) const { return u[i]; }
-    __device__ __forceinline__ void set(int i, const ListEnt<float> &e) const { u[i] = e; }
-};
-template <>
-struct ListStore<double> {
-    double2 *uxy, *uza;
-    __device__ __forceinline__ ListEnt<double> get(int i) const {
-        const double2 a = uxy[i], b = uza[i];
-        return ListEnt<double>{a.x, a.y, b.x, b.y};
-    }
-    __device__ __forceinline__ void set(int i, const ListEnt<double> &e) const {
-        uxy[i] = make_double2(e.ux, e.uy);
-        uza[i] = make_double2(e.uz, e.a);
-    }
-};
-
-template <typename T>
 struct List {                  // one wave's forward-neighbour list, LC entries
-    ListStore<T> u;            // displacement from the anchor (ATM arithmetic)
-    ListEnt<float> *f;         // the same in FP32 (j-k prefilter; == u in the FP32 form)
+    ListEnt<float> *f;         // displacement from the anchor and its square, FP32
     double *px, *py, *pz;      // partner force partials of the current anchor
     int *t;                    // tile index
     unsigned short *q;         // hit queue, kQueueCap entries: j | k << 8 (lists <= 256)
 };
 
-size_t triplet_lds_bytes(int cap, int lcap, bool fp32) {
-    const size_t ent = fp32 ? sizeof(ListEnt<float>) : sizeof(ListEnt<double>) + sizeof(ListEnt<float>);
-    return (size_t)cap * (sizeof(TileEnt) + (fp32 ? 0 : sizeof(float4)) + 3 * sizeof(double)) +
-           (size_t)kTripWaves * lcap * (ent + 3 * sizeof(double) + sizeof(int)) +
+// The same layout in both precisions (the argument is kept for the callers).
+size_t triplet_lds_bytes(int cap, int lcap, bool /*fp32*/) {
+    return (size_t)cap * (sizeof(TileEnt) + 3 * sizeof(double)) +
+           (size_t)kTripWaves * lcap * (sizeof(ListEnt<float>) + 3 * sizeof(double) + sizeof(int)) +
            (size_t)kTripWaves * kQueueCap * sizeof(unsigned short);
 }
 
 // Carves the dynamic LDS block (cap is a multiple of 32 and lc of 16, so every array
-// starts 16-byte aligned): 32- and 16-byte entries, then doubles, ints and the queue.
-template <typename T>
+// starts 16-byte aligned): 16-byte entries, then doubles, ints and the queue.
 __device__ __forceinline__ void carve(unsigned char *raw, int cap, int lc, int wave, Tile &tl,
-                                      List<T> &L) {
+                                      List &L) {
     tl.exy = (double2 *)raw;
     tl.ezc = tl.exy + cap;
-    tl.r = sizeof(T) == sizeof(float) ? nullptr : (float4 *)(tl.ezc + cap);
-    // list entries: kTripWaves * lc records of sizeof(ListEnt<T>) bytes
-    unsigned char *lu = sizeof(T) == sizeof(float) ? (unsigned char *)(tl.ezc + cap)
-                                                    : (unsigned char *)(tl.r + cap);
-    ListEnt<float> *lf = (ListEnt<float> *)(lu + (size_t)kTripWaves * lc * sizeof(ListEnt<T>));
-    if constexpr (sizeof(T) == sizeof(float)) {
-        L.u.u = (ListEnt<float> *)lu + (size_t)wave * lc;
-        L.f = L.u.u;
-    } else {
-        double2 *h = (double2 *)lu;
-        L.u.uxy = h + (size_t)wave * lc;
-        L.u.uza = h + (size_t)kTripWaves * lc + (size_t)wave * lc;
-        L.f = lf + (size_t)wave * lc;
-        lf += (size_t)kTripWaves * lc;
-    }
+    ListEnt<float> *lf = (ListEnt<float> *)(tl.ezc + cap);
+    L.f = lf + (size_t)wave * lc;
+    lf += (size_t)kTripWaves * lc;
     double *dp = (double *)lf;
     tl.fx = dp; tl.fy = dp + cap; tl.fz = dp + 2 * cap;
     double *pw = dp + 3 * (size_t)cap + (size_t)wave * 3 * lc;
@@ -339,10 +300,9 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
     const int loc = base - d.cell0;
     const int cx = loc % d.nc[0], cy = (loc / d.nc[0]) % d.nc[1], cz = loc / (d.nc[0] * d.nc[1]);
     const double L0 = d.L[0], L1 = d.L[1], L2 = d.L[2];
-    const double ox = cx * (L0 / d.nc[0]), oy = cy * (L1 / d.nc[1]), oz = cz * (L2 / d.nc[2]);
     Tile tile;
-    List<T> L;
-    carve<T>(smem_raw, CAP, LC, wave, tile, L);
+    List L;
+    carve(smem_raw, CAP, LC, wave, tile, L);
 
     // ---- stage the base cell and its 13 forward cells (shared by the workgroup), or the
     // whole system; anchors are the tile entries [a_lo, a_hi)
@@ -382,11 +342,6 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
         te.code = code & 0xff;
         te.pad = 0;
         tile_set(tile, t, te);
-        if (sizeof(T) != sizeof(float) && !whole) {
-            const PosEnt e = unpack(te, L0, L1, L2);
-            tile.r[t] = make_float4((float)((e.x + e.sx) - ox), (float)((e.y + e.sy) - oy),
-                                   (float)((e.z + e.sz) - oz), 0.0f);
-        }
         tile.fx[t] = 0.0;
         tile.fy[t] = 0.0;
         tile.fz[t] = 0.0;
@@ -416,60 +371,22 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
             if (whole) mic_from(e, an, d);
             return e;
         };
-        int m = 0;
-        if (sizeof(T) != sizeof(float) && !whole) {
-            // ---- A1: FP32 prefilter of the tile entries after the anchor (tile order);
-            // certain and ambiguous candidates are compacted into L.t, in tile order
-            const float4 ar = tile.r[ia];
-            const float pf_hi = (float)rc2 * (1.0f + kPrefilterBand);
-            int mc = 0;
-            for (int t0 = ia + 1; t0 < nst; t0 += 2 * kWave) {
-                const int t1 = t0 + lane, t2 = t0 + kWave + lane;
-                const float4 r1 = tile.r[t1 < nst ? t1 : ia];
-                const float4 r2 = tile.r[t2 < nst ? t2 : ia];
-                const float x1 = r1.x - ar.x, y1 = r1.y - ar.y, z1 = r1.z - ar.z;
-                const float x2 = r2.x - ar.x, y2 = r2.y - ar.y, z2 = r2.z - ar.z;
-                const bool in1 = t1 < nst && fmaf(z1, z1, fmaf(y1, y1, x1 * x1)) <= pf_hi;
-                const bool in2 = t2 < nst && fmaf(z2, z2, fmaf(y2, y2, x2 * x2)) <= pf_hi;
-                const uint64_t m1 = __ballot(in1), m2 = __ballot(in2);
-                const int n1 = __popcll(m1);
-                const int p1 = mc + below(m1), p2 = mc + n1 + below(m2);
-                if (in1 && p1 < LC) L.t[p1] = t1;
-                if (in2 && p2 < LC) L.t[p2] = t2;
-                mc += n1 + __popcll(m2);
-            }
-            if (a.stats && lane == 0) atomicMax(&a.stats[1], mc);
-            if (mc > LC) {
-                if (lane == 0) atomicOr(a.flags, kFlagListOverflow);
-                mc = LC;
-            }
-            __builtin_amdgcn_wave_barrier();
-            // ---- A2: canonical FP64 displacement and exact test of every candidate; the
-            // list keeps the candidates' (tile) order
-            for (int c0 = 0; c0 < mc; c0 += kWave) {
-                const int c = c0 + lane;
-                const int t = c < mc ? L.t[c] : ia;
-                const PosEnt e = unpack(tile_get(tile, t), L0, L1, L2);
+        // list entry j in the precision of the ATM arithmetic: FP32 from the list, FP64
+        // recomputed from the tile (the canonical displacement of step A, bit for bit)
+        auto list_entry = [&](int j) {
+            if constexpr (sizeof(T) == sizeof(float)) {
+                return L.f[j];
+            } else {
+                const PosEnt e = entry(tix(L.t[j]));
                 const double dx = disp1(an.x, e.x, e.sx), dy = disp1(an.y, e.y, e.sy),
                              dz = disp1(an.z, e.z, e.sz);
-                const double r2 = norm2(dx, dy, dz);
-                const bool in = c < mc && r2 <= rc2;
-                const uint64_t mk = __ballot(in);
-                const int pos = m + below(mk);
-                __builtin_amdgcn_wave_barrier();  // all reads of this round before the writes
-                if (in) {
-                    L.u.set(pos, ListEnt<T>{(T)dx, (T)dy, (T)dz, (T)r2});
-                    L.f[pos] = ListEnt<float>{(float)dx, (float)dy, (float)dz, (float)r2};
-                    L.t[pos] = WEIGHT && r2 <= ra2 ? (t | kInnerBit) : t;
-                    L.px[pos] = 0.0;
-                    L.py[pos] = 0.0;
-                    L.pz[pos] = 0.0;
-                }
-                m += __popcll(mk);
+                return ListEnt<T>{dx, dy, dz, norm2(dx, dy, dz)};
             }
-        } else {
-            // ---- A: canonical FP64 displacement and exact test of the tile entries after the
-            // anchor, two per lane per round; ballot + prefix-count compaction keeps tile order
+        };
+        // ---- A: canonical FP64 displacement and exact test of the tile entries after the
+        // anchor, two per lane per round; ballot + prefix-count compaction keeps tile order
+        int m = 0;
+        {
             for (int t0 = ia + 1; t0 < nst; t0 += 2 * kWave) {
                 const int t1 = t0 + lane, t2 = t0 + kWave + lane;
                 const PosEnt e1 = entry(t1 < nst ? t1 : ia);
@@ -485,18 +402,14 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
                 const int n1 = __popcll(m1);
                 const int p1 = m + below(m1), p2 = m + n1 + below(m2);
                 if (in1 && p1 < LC) {
-                    L.u.set(p1, ListEnt<T>{(T)x1, (T)y1, (T)z1, (T)q1});
-                    if constexpr (sizeof(T) != sizeof(float))  // whole-system tiles
-                        L.f[p1] = ListEnt<float>{(float)x1, (float)y1, (float)z1, (float)q1};
+                    L.f[p1] = ListEnt<float>{(float)x1, (float)y1, (float)z1, (float)q1};
                     L.t[p1] = WEIGHT && q1 <= ra2 ? (t1 | kInnerBit) : t1;
                     L.px[p1] = 0.0;
                     L.py[p1] = 0.0;
                     L.pz[p1] = 0.0;
                 }
                 if (in2 && p2 < LC) {
-                    L.u.set(p2, ListEnt<T>{(T)x2, (T)y2, (T)z2, (T)q2});
-                    if constexpr (sizeof(T) != sizeof(float))
-                        L.f[p2] = ListEnt<float>{(float)x2, (float)y2, (float)z2, (float)q2};
+                    L.f[p2] = ListEnt<float>{(float)x2, (float)y2, (float)z2, (float)q2};
                     L.t[p2] = WEIGHT && q2 <= ra2 ? (t2 | kInnerBit) : t2;
                     L.px[p2] = 0.0;
                     L.py[p2] = 0.0;
@@ -569,7 +482,7 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
             const int e1 = Q[(qh + (v1 ? lane : 0)) & kQueueMask];
             qh += cnt;
             const int j1 = e1 & 0xff, k1 = e1 >> 8;
-            const ListEnt<T> uj1 = L.u.get(j1), uk1 = L.u.get(k1);
+            const ListEnt<T> uj1 = list_entry(j1), uk1 = list_entry(k1);
             T nu1 = nu;
             double iw1 = 1.0;  // unscales the energy terms of weighted triplets
             if constexpr (WEIGHT) {
