@@ -241,6 +241,11 @@ typedef struct {
                              launch per group, when that measures faster */
     double cycle_ms;      /* measured ms per full step (k inner steps, k * k_outer when
                              nested; 0: untuned) */
+    int32_t tight_caps;   /* 1: capacities sized from the observed maxima with thin margins
+                             (mts_autotune keeps it when the smaller tiles and lists let
+                             more triplet workgroups share a CU and that measures faster) */
+    int32_t triplet_workgroups_per_cu; /* triplet workgroups one CU holds in the (first)
+                             triplet launch at the current capacities (0: DirectSum) */
 } mts_tuning;
 
 /* (MTS_DIRECT handles have nothing to tune: the call returns their configuration.)

@@ -59,6 +59,8 @@ struct Config {
     bool split = false;           // several systems: one triplet launch per tile class
                                   // (systems allowing the same workgroups per CU) instead
                                   // of a single launch at the occupancy of the largest tile
+    bool tight = false;           // capacities from observed maxima with thin margins, so
+                                  // that the triplet tiles may fit one more workgroup per CU
 };
 
 constexpr int kMaxTileClasses = 8;
@@ -75,6 +77,7 @@ struct Layout {
     // entries and covers the cells cls_cells[cls_off[c] .. cls_off[c + 1]).
     int ncls = 0;
     int cls_cap[kMaxTileClasses] = {};
+    int cls_occ[kMaxTileClasses] = {};  // triplet workgroups per CU of each class
     int cls_off[kMaxTileClasses + 1] = {};
     bool any_whole = false;       // some system's triplet tile is the whole system
     std::vector<int> cls_order;   // host copy of the cell order (all classes)
@@ -402,6 +405,7 @@ mts_status classify(const mts_system *s, Layout &lo) {
             else hi_i = mid - 1;
         }
         lo.cls_cap[c] = 32 * lo_i;
+        lo.cls_occ[c] = occ(lo.cls_cap[c]);
         lo.stage_cap = std::max(lo.stage_cap, lo.cls_cap[c]);
         lo.cls_off[c] = (int)lo.cls_order.size();
         for (const auto &w : work)
@@ -1205,9 +1209,14 @@ mts_status observe(mts_system *s, const double *x, int obs[4], std::vector<int> 
 
 // Capacities for the observed maxima, with room for the fluctuations of a run.
 void caps_from_observed(Config &c, const int obs[4], const std::vector<int> &tile) {
+    // margins against growth during the run: generous by default; thin with c.tight
+    // (a tuning choice: smaller tiles and lists can buy a workgroup per CU, and an overflow
+    // is reported and enlarged like any other)
+    const double ft = c.tight ? 1.04 : 1.15, fl = c.tight ? 1.05 : 1.2;
+    const int at = c.tight ? 8 : 16, al = c.tight ? 4 : 8;
     c.tile_need.resize(tile.size());
-    for (size_t q = 0; q < tile.size(); ++q) c.tile_need[q] = (int)std::ceil(1.15 * tile[q]) + 16;
-    c.list_cap = std::min(kMaxListCap, round_up((int)std::ceil(1.2 * obs[1]) + 8, 16));
+    for (size_t q = 0; q < tile.size(); ++q) c.tile_need[q] = (int)std::ceil(ft * tile[q]) + at;
+    c.list_cap = std::min(kMaxListCap, round_up((int)std::ceil(fl * obs[1]) + al, 16));
     c.pair_cap = std::min(2048, round_up((int)std::ceil(1.15 * obs[2]) + 16, 32));
     if (c.skin > 0.0) c.nl_cap = std::min(2048, round_up((int)std::ceil(1.2 * obs[3]) + 16, 32));
 }
@@ -1566,6 +1575,8 @@ static void fill_tuning(const mts_system *s, mts_tuning *out) {
     out->trials = s->tuned_trials;
     out->shared_launch = shared_launch(s) ? 1 : 0;
     out->tile_classes = s->lo.ncls;
+    out->tight_caps = c.tight ? 1 : 0;
+    out->triplet_workgroups_per_cu = s->direct || s->lo.ncls == 0 ? 0 : s->lo.cls_occ[0];
 }
 
 mts_status mts_get_tuning(const mts_system *sys, mts_tuning *out) {
@@ -1658,14 +1669,22 @@ mts_status mts_autotune(mts_system *sys, const double *x, const double *v, int32
         return el > budget;
     };
     std::pair<double, Config> best = trial(start);
-    // coordinate descent over the pair-list skin, the triplet cell size, the lanes per
-    // particle of the list force kernel and, for batches, the triplet launch grouping
+    // coordinate descent over the pair-list skin, the capacity margins, the triplet cell
+    // size, the lanes per particle of the list force kernel and, for batches, the triplet
+    // launch grouping
     std::vector<double> skins = {0.0, 0.15 * sys->p.sigma, 0.3 * sys->p.sigma, 0.5 * sys->p.sigma};
     for (double sk : skins) {
         if (over_budget()) break;
         Config c = best.second;
         c.skin = effective_skin(sys, sk);
         if (c.skin == best.second.skin || (c.skin > 0.0 && c.skin < min_skin)) continue;
+        auto r = trial(c);
+        if (r.first < 0.98 * best.first) best = r;
+    }
+    // capacities with thin margins (more triplet workgroups per CU where they then fit)
+    if (!over_budget()) {
+        Config c = best.second;
+        c.tight = !c.tight;
         auto r = trial(c);
         if (r.first < 0.98 * best.first) best = r;
     }

@@ -57,13 +57,15 @@ namespace mts {
 constexpr int kTripWaves = 4;
 constexpr int kTripThreads = kTripWaves * kWave;
 // Hit queue: evaluated one hit per lane whenever 64 are pending; one round of tests
-// pushes at most 2 x 64 more.
-constexpr int kQueueCap = 4 * kWave;   // a ring: fewer than 64 pending + 128 pushed
+// pushes at most kPairsPerLane x 64 more.
+constexpr int kQueueCap = 2 * kWave;   // a ring: fewer than 64 pending + 64 pushed
 constexpr int kQueueMask = kQueueCap - 1;
 // List pairs tested per lane and round of the j-k sweep (1 or 2): two give each lane two
-// independent chains, one keeps the register count (and so the occupancy) lower.
+// independent chains, one keeps the registers and the queue small, which is worth more
+// (five waves per SIMD need at most 96 VGPRs).
 template <typename T>
-constexpr int kPairsPerLane = sizeof(T) == sizeof(float) ? 1 : 2;
+constexpr int kPairsPerLane = 1;
+static_assert(kQueueCap >= kWave + kPairsPerLane<double> * kWave, "hit queue too small");
 
 // Number of set bits of mask in the lanes below this one.
 __device__ __forceinline__ int below(uint64_t mask) {
@@ -713,8 +715,12 @@ __global__ void __launch_bounds__(256) k_triplet_gather(int64_t n, const double 
 // overlaps the start of one workgroup with the tail of another on a compute unit.)
 //   LB: the launch also builds the pair list; WH: some system is staged whole (the whole-
 //   system code path costs registers, so launches without such systems leave it out).
+// Registers are held to 96 per lane (five waves per SIMD): with tiles and lists that fit
+// 32 KB of LDS, five workgroups then share a CU (1M particles, FP64: 3.0 -> 2.7 ms); the
+// weighted variants of nested r-RESPA spill a few registers for it.
 template <typename T, bool LIST, bool ENERGY, bool WEIGHT, bool LB, bool WH>
-__global__ void __launch_bounds__(kTripThreads) k_triplet_items(TripletArgs a, ListBuildArgs b) {
+__global__ void __launch_bounds__(kTripThreads) __attribute__((amdgpu_waves_per_eu(5)))
+k_triplet_items(TripletArgs a, ListBuildArgs b) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     const int it = (int)blockIdx.x;
     if (it < a.ncell) {

@@ -61,7 +61,8 @@ class mts_tuning(C.Structure):
     _fields_ = [("skin", C.c_double), ("cell_factor", C.c_double), ("list_lanes", C.c_int32),
                 ("stage_cap", C.c_int32), ("list_cap", C.c_int32), ("pair_cap", C.c_int32),
                 ("nl_cap", C.c_int32), ("trials", C.c_int32), ("shared_launch", C.c_int32),
-                ("tile_classes", C.c_int32), ("cycle_ms", C.c_double)]
+                ("tile_classes", C.c_int32), ("cycle_ms", C.c_double),
+                ("tight_caps", C.c_int32), ("triplet_workgroups_per_cu", C.c_int32)]
 
 
 _LIB = None

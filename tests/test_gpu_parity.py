@@ -785,6 +785,7 @@ def test_autotune_keeps_parity_and_caches(case):
     with _system(w, k=k) as s:
         t = s.autotune(x, v, budget_ms=1500)
         assert t["trials"] >= 1 and t["cycle_ms"] > 0.0
+        assert t["tight_caps"] in (0, 1) and t["triplet_workgroups_per_cu"] >= 1
         assert torch.equal(x, _dev(w.x)) and torch.equal(v, _dev(w.v))  # inputs untouched
         f2, f3 = torch.empty_like(x), torch.empty_like(x)
         s.compute_pair_forces(x, f2)
@@ -806,7 +807,8 @@ def test_autotune_keeps_parity_and_caches(case):
     with _system(w, k=k) as s2:
         t2 = s2.autotune(x, v, budget_ms=1500)
         assert t2["trials"] == 0
-        for key in ("skin", "cell_factor", "list_lanes", "stage_cap", "list_cap", "nl_cap"):
+        for key in ("skin", "cell_factor", "list_lanes", "stage_cap", "list_cap", "nl_cap",
+                    "tight_caps", "triplet_workgroups_per_cu"):
             assert t2[key] == t[key], key
         assert s2.tuning()["list_lanes"] == t["list_lanes"]
 
