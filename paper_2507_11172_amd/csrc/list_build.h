@@ -60,7 +60,8 @@ __device__ __forceinline__ void list_build_block(const ListBuildArgs &a, int bas
     __syncthreads();
 
     // the relative margin (1e-5) dwarfs the FP32 rounding of staged positions and of
-    // the squared distance, so every pair within the list radius is kept
+    // the squared distance (summed with fused multiply-adds), so every pair within the
+    // list radius is kept
     const float rv2 = (float)(a.rv2 * (1.0 + 1e-5));
     const int wave = lane / kWave, wl = lane % kWave;
     const uint64_t below = wl == 0 ? 0ull : (~0ull >> (kWave - wl));
@@ -78,7 +79,7 @@ __device__ __forceinline__ void list_build_block(const ListBuildArgs &a, int bas
             if (t < nst && t != self) {
                 const BuildEnt e = tile[t];
                 const float dx = e.x - pi.x, dy = e.y - pi.y, dz = e.z - pi.z;
-                near = (dx * dx + dy * dy) + dz * dz <= rv2;
+                near = fmaf(dz, dz, fmaf(dy, dy, dx * dx)) <= rv2;
                 slot = e.slot;
             }
             const uint64_t mask = __ballot(near);
