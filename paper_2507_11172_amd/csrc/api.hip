@@ -1296,8 +1296,8 @@ mts_status mts_init_system(const mts_params *params, int32_t n_systems, const in
         else
             s->lds_per_cu = s->max_lds;
         // keep room for the kernels' static LDS
-        s->max_lds = s->max_lds > 1024 ? s->max_lds - 1024 : s->max_lds;
-        if (configure_kernel_lds(s->max_lds) != hipSuccess) s->max_lds = 64 * 1024 - 1024;
+        s->max_lds = s->max_lds > kStaticLdsReserve ? s->max_lds - kStaticLdsReserve : s->max_lds;
+        if (configure_kernel_lds(s->max_lds) != hipSuccess) s->max_lds = 64 * 1024 - kStaticLdsReserve;
         (void)hipGetLastError();  // do not leave a failed attribute call as a sticky error
     }
     // Default configuration.  Pair-list skin: the requested one, by default

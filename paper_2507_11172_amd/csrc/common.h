@@ -288,6 +288,9 @@ hipError_t launch_pair_list(hipStream_t st, const PairListArgs &a);  // LJ in FP
 size_t pair_lds_bytes(int stage_cap);
 
 // Lets every LDS-tiled kernel use up to max_bytes of dynamic LDS per workgroup.
+// LDS left to the kernels' static arrays when the dynamic limit is set (the triplet
+// kernels' static LDS is at most 1.5 KB).
+constexpr size_t kStaticLdsReserve = 2048;
 hipError_t configure_kernel_lds(size_t max_bytes);
 
 // Triplet forces: one launch whose workgroups take one base cell (item) each, in the order

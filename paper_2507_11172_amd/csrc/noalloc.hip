@@ -67,8 +67,8 @@ mts_status device_setup(int dev, unsigned char **ptr, size_t *max_lds) {
         if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
             lds > 0)
             m = (size_t)lds;
-        m = m > 1024 ? m - 1024 : m;  // room for the kernels' static LDS
-        if (configure_kernel_lds(m) != hipSuccess) m = 64 * 1024 - 1024;
+        m = m > kStaticLdsReserve ? m - kStaticLdsReserve : m;  // room for the static LDS
+        if (configure_kernel_lds(m) != hipSuccess) m = 64 * 1024 - kStaticLdsReserve;
         (void)hipGetLastError();
         g_scratch[dev] = (unsigned char *)p;
         g_max_lds[dev] = m;

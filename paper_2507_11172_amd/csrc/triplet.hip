@@ -83,8 +83,8 @@ struct PosEnt {                // a staged particle in registers: wrapped FP64 p
     double sx, sy, sz;         // the base cell
 };
 
-struct alignas(16) TileEnt {   // its LDS form: the shift as a 2-bit code per component
-    double x, y, z;
+struct alignas(16) TileEnt {   // its LDS form: the stencil code of the entry's cell (a
+    double x, y, z;            // 2-bit shift code per component, the cell in bits 8..)
     int code;
     int pad;
 };
@@ -101,19 +101,6 @@ struct alignas(16) ListEnt {
 };
 
 static_assert(sizeof(TileEnt) == 32 && sizeof(ListEnt<float>) == 16, "LDS entry sizes");
-
-__device__ __forceinline__ PosEnt unpack(const TileEnt &t, double L0, double L1, double L2) {
-    PosEnt e;
-    e.x = t.x;
-    e.y = t.y;
-    e.z = t.z;
-    // (c - 1) L for the 2-bit code c: c L - L is exact for c in {0, 1, 2}, one rounding-
-    // free fma instead of a subtraction, a conversion and a product
-    e.sx = fma((double)(unsigned)(t.code & 3), L0, -L0);
-    e.sy = fma((double)(unsigned)((t.code >> 2) & 3), L1, -L1);
-    e.sz = fma((double)(unsigned)((t.code >> 4) & 3), L2, -L2);
-    return e;
-}
 
 // A whole-system tile carries no image shifts: the shift of entry e as seen from the
 // anchor is that of the minimum image, S = -L rint((x_e - x_a) / L), so that
@@ -294,6 +281,8 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
     __shared__ double s_red[kTripWaves][2];
     __shared__ int s_cnt[kTripWaves];
     __shared__ StencilTable<kNumHalf> tab;
+    __shared__ double2 s_sxy[kNumHalf];  // image shift of each stencil cell
+    __shared__ double s_sz[kNumHalf];
     const int CAP = a.stage_cap, LC = a.list_cap;
     const int tid = threadIdx.x;
     const int wave = tid / kWave, lane = tid % kWave;
@@ -343,15 +332,36 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
         te.x = ps.x;
         te.y = ps.y;
         te.z = ps.z;
-        te.code = code & 0xff;
+        te.code = code;
         te.pad = 0;
         tile_set(tile, t, te);
         tile.fx[t] = 0.0;
         tile.fy[t] = 0.0;
         tile.fz[t] = 0.0;
     }
+    // image shift (c - 1) L of each stencil cell from its 2-bit codes c (c L - L is exact
+    // for c in {0, 1, 2}); a tile entry carries its cell in code >> 8.  Whole-system
+    // tiles: no shift (the minimum image is taken per pair)
+    if (tid < kNumHalf) {
+        const int c = whole ? 0x15 : tab.code[tid];
+        s_sxy[tid] = make_double2(fma((double)(unsigned)(c & 3), L0, -L0),
+                                  fma((double)(unsigned)((c >> 2) & 3), L1, -L1));
+        s_sz[tid] = fma((double)(unsigned)((c >> 4) & 3), L2, -L2);
+    }
     if (tid == 0) s_turn = a_lo;
     __syncthreads();
+    auto unpack_s = [&](const TileEnt &t) {
+        PosEnt e;
+        e.x = t.x;
+        e.y = t.y;
+        e.z = t.z;
+        const int o = t.code >> 8;
+        const double2 sxy = s_sxy[o];
+        e.sx = sxy.x;
+        e.sy = sxy.y;
+        e.sz = s_sz[o];
+        return e;
+    };
 
     const T nu = (T)a.nu;
     const double rc2 = a.rc2;
@@ -369,9 +379,9 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
     // sorted particle index of tile entry t (debug listing only)
     auto slot_of = [&](int t) { return whole ? p0s + t : tile_slot(tab, t); };
     for (int ia = a_lo + wave; ia < a_hi; ia += kTripWaves) {
-        const PosEnt an = unpack(tile_get(tile, ia), L0, L1, L2);  // anchor: base cell, zero shift
+        const PosEnt an = unpack_s(tile_get(tile, ia));  // anchor: base cell, zero shift
         auto entry = [&](int t) {  // tile entry t with its image shift seen from the anchor
-            PosEnt e = unpack(tile_get(tile, t), L0, L1, L2);
+            PosEnt e = unpack_s(tile_get(tile, t));
             if (whole) mic_from(e, an, d);
             return e;
         };
