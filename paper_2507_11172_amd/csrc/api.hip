@@ -832,6 +832,7 @@ TripletArgs triplet_args(const mts_system *s, int cls, int *list_ijk, long long 
     a.nu = s->p.nu;
     a.rc2 = s->p.rc_triplet * s->p.rc_triplet;
     a.stage_cap = lo.cls_cap[cls];
+    a.occ6 = lo.cls_occ[cls] >= 6 ? 1 : 0;
     a.list_cap = lo.list_cap;
     a.flags = s->flags;
     a.list_ijk = list_ijk;

@@ -301,6 +301,8 @@ struct TripletArgs {
     const int *cell_map;    // [ncell] triplet-grid cell of each item, or nullptr: item b
                             // is cell b
     int any_whole;          // 1 if some system of the launch is staged whole (SysDesc.whole)
+    int occ6;               // 1: six workgroups per CU fit this launch's LDS; its plain
+                            // (unweighted) passes use the variants held to 80 VGPRs
     const Pos4 *xs;
     const int *start;
     const SysDesc *sd;

@@ -727,11 +727,13 @@ __global__ void __launch_bounds__(256) k_triplet_gather(int64_t n, const double 
 // overlaps the start of one workgroup with the tail of another on a compute unit.)
 //   LB: the launch also builds the pair list; WH: some system is staged whole (the whole-
 //   system code path costs registers, so launches without such systems leave it out).
-// Registers are held to 96 per lane (five waves per SIMD): with tiles and lists that fit
-// 32 KB of LDS, five workgroups then share a CU (1M particles, FP64: 3.0 -> 2.7 ms); the
-// weighted variants of nested r-RESPA spill a few registers for it.
-template <typename T, bool LIST, bool ENERGY, bool WEIGHT, bool LB, bool WH>
-__global__ void __launch_bounds__(kTripThreads) __attribute__((amdgpu_waves_per_eu(5)))
+// OCC: waves per SIMD the registers are held to.  Five (96 VGPRs) let five workgroups
+// share a CU when tiles and lists fit 32 KB of LDS (1M particles, FP64: 3.0 -> 2.7 ms;
+// the weighted variants of nested r-RESPA spill a few registers for it); six (80 VGPRs,
+// with some spilling in FP64) pay only when the LDS also admits six workgroups, so the
+// launcher takes them exactly then (TripletArgs.occ6).
+template <typename T, bool LIST, bool ENERGY, bool WEIGHT, bool LB, bool WH, int OCC>
+__global__ void __launch_bounds__(kTripThreads) __attribute__((amdgpu_waves_per_eu(OCC)))
 k_triplet_items(TripletArgs a, ListBuildArgs b) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     const int it = (int)blockIdx.x;
@@ -746,20 +748,32 @@ k_triplet_items(TripletArgs a, ListBuildArgs b) {
     }
 }
 
+template <typename T, bool LIST, bool ENERGY, bool WEIGHT, int OCC>
+static void launch_items_o(hipStream_t st, const TripletArgs &a, const ListBuildArgs &b,
+                           size_t lds, int grid) {
+    if (b.ncell > 0) {
+        if constexpr (!LIST) {
+            if (a.any_whole) k_triplet_items<T, LIST, ENERGY, WEIGHT, true, true, OCC><<<grid, kTripThreads, lds, st>>>(a, b);
+            else k_triplet_items<T, LIST, ENERGY, WEIGHT, true, false, OCC><<<grid, kTripThreads, lds, st>>>(a, b);
+        }
+    } else {
+        if (a.any_whole) k_triplet_items<T, LIST, ENERGY, WEIGHT, false, true, OCC><<<grid, kTripThreads, lds, st>>>(a, b);
+        else k_triplet_items<T, LIST, ENERGY, WEIGHT, false, false, OCC><<<grid, kTripThreads, lds, st>>>(a, b);
+    }
+}
+
 template <typename T, bool LIST, bool ENERGY, bool WEIGHT>
 static hipError_t launch_items_t(hipStream_t st, const TripletArgs &a, const ListBuildArgs &b) {
     size_t lds = a.ncell > 0 ? triplet_lds_bytes(a.stage_cap, a.list_cap, sizeof(T) == 4) : 0;
     if (b.ncell > 0) lds = std::max(lds, list_build_bytes(b.stage_cap));
     const int grid = a.ncell + b.ncell;
-    if (b.ncell > 0) {
-        if constexpr (!LIST) {
-            if (a.any_whole) k_triplet_items<T, LIST, ENERGY, WEIGHT, true, true><<<grid, kTripThreads, lds, st>>>(a, b);
-            else k_triplet_items<T, LIST, ENERGY, WEIGHT, true, false><<<grid, kTripThreads, lds, st>>>(a, b);
+    if constexpr (!LIST && !WEIGHT) {  // the plain passes come in both register budgets
+        if (a.occ6) {
+            launch_items_o<T, LIST, ENERGY, WEIGHT, 6>(st, a, b, lds, grid);
+            return hipGetLastError();
         }
-    } else {
-        if (a.any_whole) k_triplet_items<T, LIST, ENERGY, WEIGHT, false, true><<<grid, kTripThreads, lds, st>>>(a, b);
-        else k_triplet_items<T, LIST, ENERGY, WEIGHT, false, false><<<grid, kTripThreads, lds, st>>>(a, b);
     }
+    launch_items_o<T, LIST, ENERGY, WEIGHT, 5>(st, a, b, lds, grid);
     return hipGetLastError();
 }
 
@@ -789,14 +803,16 @@ hipError_t launch_triplet(hipStream_t st, const TripletArgs &a, bool fp32, bool 
 
 hipError_t configure_triplet_lds(size_t max_bytes) {
 #define MTS_ITEMS(T, LB, WH)                                                 \
-    (const void *)k_triplet_items<T, false, false, false, LB, WH>,           \
-        (const void *)k_triplet_items<T, false, true, false, LB, WH>,        \
-        (const void *)k_triplet_items<T, false, false, true, LB, WH>,        \
-        (const void *)k_triplet_items<T, false, true, true, LB, WH>
-    const void *fns[] = {(const void *)k_triplet_items<double, true, false, false, false, false>,
-                         (const void *)k_triplet_items<double, true, false, false, false, true>,
-                         (const void *)k_triplet_items<float, true, false, false, false, false>,
-                         (const void *)k_triplet_items<float, true, false, false, false, true>,
+    (const void *)k_triplet_items<T, false, false, false, LB, WH, 5>,        \
+        (const void *)k_triplet_items<T, false, true, false, LB, WH, 5>,     \
+        (const void *)k_triplet_items<T, false, false, true, LB, WH, 5>,     \
+        (const void *)k_triplet_items<T, false, true, true, LB, WH, 5>,      \
+        (const void *)k_triplet_items<T, false, false, false, LB, WH, 6>,    \
+        (const void *)k_triplet_items<T, false, true, false, LB, WH, 6>
+    const void *fns[] = {(const void *)k_triplet_items<double, true, false, false, false, false, 5>,
+                         (const void *)k_triplet_items<double, true, false, false, false, true, 5>,
+                         (const void *)k_triplet_items<float, true, false, false, false, false, 5>,
+                         (const void *)k_triplet_items<float, true, false, false, false, true, 5>,
                          MTS_ITEMS(double, false, false), MTS_ITEMS(double, true, false),
                          MTS_ITEMS(double, false, true), MTS_ITEMS(double, true, true),
                          MTS_ITEMS(float, false, false), MTS_ITEMS(float, true, false),
@@ -810,23 +826,34 @@ hipError_t configure_triplet_lds(size_t max_bytes) {
 }
 
 int triplet_blocks_per_cu(bool fp32, bool whole, size_t lds, size_t lds_per_cu) {
-    // the variant with the most registers of each precision and kind of launch
-    const void *f =
-        fp32 ? (whole ? (const void *)k_triplet_items<float, false, true, true, true, true>
-                      : (const void *)k_triplet_items<float, false, true, true, true, false>)
-             : (whole ? (const void *)k_triplet_items<double, false, true, true, true, true>
-                      : (const void *)k_triplet_items<double, false, true, true, true, false>);
-    int nb = 0;
-    hipFuncAttributes fa{};
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kTripThreads, 0) != hipSuccess ||
-        hipFuncGetAttributes(&fa, f) != hipSuccess) {
-        (void)hipGetLastError();  // leave no sticky error for the next launch check
-        return -1;
-    }
-    // LDS goes out in granules: static + dynamic bytes rounded up to 512, plus 512 of
-    // margin for a coarser granule
-    const size_t per = (fa.sharedSizeBytes + lds + 511) / 512 * 512 + 512;
-    return std::min(nb, (int)(lds_per_cu / per));
+    auto blocks = [&](const void *f) {
+        int nb = 0;
+        hipFuncAttributes fa{};
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kTripThreads, 0) != hipSuccess ||
+            hipFuncGetAttributes(&fa, f) != hipSuccess) {
+            (void)hipGetLastError();  // leave no sticky error for the next launch check
+            return -1;
+        }
+        // LDS goes out in granules: static + dynamic bytes rounded up to 512, plus 512 of
+        // margin for a coarser granule
+        const size_t per = (fa.sharedSizeBytes + lds + 511) / 512 * 512 + 512;
+        return std::min(nb, (int)(lds_per_cu / per));
+    };
+    // the variant with the most registers of each precision and kind of launch in each
+    // register budget; six per CU only where the six-wave budget reaches it
+    const void *f5 =
+        fp32 ? (whole ? (const void *)k_triplet_items<float, false, true, true, true, true, 5>
+                      : (const void *)k_triplet_items<float, false, true, true, true, false, 5>)
+             : (whole ? (const void *)k_triplet_items<double, false, true, true, true, true, 5>
+                      : (const void *)k_triplet_items<double, false, true, true, true, false, 5>);
+    const void *f6 =
+        fp32 ? (whole ? (const void *)k_triplet_items<float, false, true, false, true, true, 6>
+                      : (const void *)k_triplet_items<float, false, true, false, true, false, 6>)
+             : (whole ? (const void *)k_triplet_items<double, false, true, false, true, true, 6>
+                      : (const void *)k_triplet_items<double, false, true, false, true, false, 6>);
+    const int n5 = blocks(f5), n6 = blocks(f6);
+    if (n5 < 0) return n5;
+    return n6 >= 6 ? n6 : n5;
 }
 
 hipError_t launch_triplet_gather(hipStream_t st, int64_t n, const double *pf, const int *perm,
