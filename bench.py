@@ -804,7 +804,9 @@ def main(argv=None):
     ap.add_argument("--traffic-table", nargs="+", metavar="CSV",
                     help="FETCH_CSV WRITE_CSV [KERNEL_STATS_CSV]: print the HBM bytes of every "
                          "kernel of the two counter runs as a markdown table")
-    ap.add_argument("--traffic-kernel", default="mts::k_triplet_items<double, false, true, false, true, false>(")
+    ap.add_argument("--traffic-kernel", default="mts::k_triplet_items<double, false, true, false, true, false, ",
+                    help="a part of the demangled name (the register budget, the last template "
+                         "argument, is left open)")
     ap.add_argument("--loop-steps", type=int, default=5,
                     help="cycles of the one-handle-per-replica loop (batched workload)")
     ap.add_argument("--rvite-sweep", action="store_true",
