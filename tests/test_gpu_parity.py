@@ -712,10 +712,12 @@ def test_batch_launch_grouping_option_and_autotune():
         off += n
 
 
-def _forces_and_energies(w, precision):
+def _forces_and_energies(w, precision, tune_ms=0):
     torch = _torch()
     with _system(w, precision=precision) as s:
         x = _dev(w.x)
+        if tune_ms > 0:  # the bench's configuration: autotuned on the input
+            s.autotune(x, _dev(w.v), tune_ms)
         f2, f3 = torch.empty_like(x), torch.empty_like(x)
         e2 = torch.zeros((1, 2), dtype=torch.float64, device="cuda")
         e3 = torch.zeros((1, 2), dtype=torch.float64, device="cuda")
@@ -730,13 +732,16 @@ def _subset_bar(f, ref):
 
 
 @pytest.mark.slow
-def test_precision_form_1m_particles():
+@pytest.mark.parametrize("tune_ms", [0, 3000])
+def test_precision_form_1m_particles(tune_ms):
     """1,048,576 particles: the FP32 form against the FP64 GPU run on every particle, and
-    both against the oracle's exact subset mode on 4,000 seeded particles."""
+    both against the oracle's exact subset mode on 4,000 seeded particles -- in the default
+    configuration and in the bench's (autotuned: thin capacity margins, five or six triplet
+    workgroups per CU and the register budget that goes with them)."""
     w = W.precision_form(10)
     n = w.n_total
-    a2, a3, u2, u3 = _forces_and_energies(w, "fp64")
-    b2, b3, v2, v3 = _forces_and_energies(w, "fp32")
+    a2, a3, u2, u3 = _forces_and_energies(w, "fp64", tune_ms)
+    b2, b3, v2, v3 = _forces_and_energies(w, "fp32", tune_ms)
     assert rel_err(b2, a2) <= 1e-5 and rel_err(b3, a3) <= 1e-5
     assert abs((v2 + v3) - (u2 + u3)) / n <= 1e-7
     idx = np.sort(W.rng_for(78).choice(n, size=4000, replace=False))
