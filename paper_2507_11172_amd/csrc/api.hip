@@ -1670,22 +1670,23 @@ mts_status mts_autotune(mts_system *sys, const double *x, const double *v, int32
         return el > budget;
     };
     std::pair<double, Config> best = trial(start);
-    // coordinate descent over the pair-list skin, the capacity margins, the triplet cell
+    // coordinate descent over the capacity margins, the pair-list skin, the triplet cell
     // size, the lanes per particle of the list force kernel and, for batches, the triplet
-    // launch grouping
-    std::vector<double> skins = {0.0, 0.15 * sys->p.sigma, 0.3 * sys->p.sigma, 0.5 * sys->p.sigma};
-    for (double sk : skins) {
-        if (over_budget()) break;
-        Config c = best.second;
-        c.skin = effective_skin(sys, sk);
-        if (c.skin == best.second.skin || (c.skin > 0.0 && c.skin < min_skin)) continue;
-        auto r = trial(c);
-        if (r.first < 0.98 * best.first) best = r;
-    }
+    // launch grouping (the knobs that moved the cycle most come first, so that a short
+    // budget still reaches them)
     // capacities with thin margins (more triplet workgroups per CU where they then fit)
     if (!over_budget()) {
         Config c = best.second;
         c.tight = !c.tight;
+        auto r = trial(c);
+        if (r.first < 0.98 * best.first) best = r;
+    }
+    const double sg = sys->p.sigma;
+    for (double sk : {0.15 * sg, 0.1 * sg, 0.2 * sg, 0.3 * sg, 0.5 * sg, 0.0}) {
+        if (over_budget()) break;
+        Config c = best.second;
+        c.skin = effective_skin(sys, sk);
+        if (c.skin == best.second.skin || (c.skin > 0.0 && c.skin < min_skin)) continue;
         auto r = trial(c);
         if (r.first < 0.98 * best.first) best = r;
     }
