@@ -669,10 +669,8 @@ void fill_bin_grid(BinGrid &b, Grid &g, double *x_ref) {
 
 // Counting sort of x into the pair grid and/or the triplet grid (one launch per pass);
 // with_ref also records the wrapped positions as the reference of the next skin check.
-mts_status enqueue_bin(mts_system *s, int which, const double *x, bool with_ref,
-                       bool counted = false) {
+mts_status enqueue_bin(mts_system *s, int which, const double *x, bool with_ref) {
     BinArgs a{};
-    a.counted = counted;
     a.n = s->n;
     a.x = x;
     a.sys_of = s->sys_of;
@@ -749,7 +747,6 @@ F3Mode cycle_mode(const mts_system *s, bool full) {
 struct Fused {
     bool kick2 = false, kick3_end = false, kick3_start = false, drift = false;
     bool gather3 = false;  // gather F3 from the partial slots (into s->f3) first
-    bool bin = false;      // with drift: first binning pass of both grids
     const double *f2prev = nullptr;
     Pos4 *xs_out = nullptr;
 };
@@ -776,11 +773,6 @@ mts_status enqueue_pair_list(mts_system *s, const Pos4 *xs_in, double *f2, const
     a.rc2 = s->p.rc_pair * s->p.rc_pair;
     a.ushift = s->ushift;
     a.flags = s->flags;
-    if (u.bin) {
-        a.nbin = 2;
-        fill_bin_grid(a.bin[0], s->lo.gp, nullptr);
-        fill_bin_grid(a.bin[1], s->lo.gt, nullptr);
-    }
     if (u.gather3) {
         a.pf = s->pf;
         a.inv_perm3 = s->lo.gt.inv_perm;
@@ -990,8 +982,8 @@ bool shared_launch(const mts_system *s) {
 
 // Rebins both grids at the internal positions, rebuilds the pair list and computes the
 // triplet partial slots for mode (list mode); the caller's list force kernel then gathers F3.
-mts_status enqueue_full_step_list(mts_system *s, bool energy, bool counted, F3Mode mode) {
-    MTS_TRY(enqueue_bin(s, kBinPair | kBinTriplet, s->xi, true, counted));
+mts_status enqueue_full_step_list(mts_system *s, bool energy, F3Mode mode) {
+    MTS_TRY(enqueue_bin(s, kBinPair | kBinTriplet, s->xi, true));
     if (shared_launch(s)) {
         MTS_TRY(enqueue_triplet_and_list(s, energy, mode));
     } else {
@@ -1008,7 +1000,7 @@ mts_status enqueue_entry_forces(mts_system *s, double *f2, bool energy) {
         MTS_TRY(enqueue_direct_triplet(s, s->xi, s->f3, energy));
     } else if (s->lo.skin > 0.0) {
         const F3Mode mode = cycle_mode(s, true);
-        MTS_TRY(enqueue_full_step_list(s, energy, false, mode));
+        MTS_TRY(enqueue_full_step_list(s, energy, mode));
         Fused g;
         g.gather3 = true;
         MTS_TRY(enqueue_pair_list(s, s->lo.gp.xs, f2, g, true));
@@ -1023,12 +1015,13 @@ mts_status enqueue_entry_forces(mts_system *s, double *f2, bool energy) {
 // One outer cycle of Algorithm 2 on the internal copies xi, vi.  On entry F2 of the
 // cycle's first position x^0 is in f2[0] and F3(x^0) in s->f3; on exit F2(x^k) is in
 // f2[k % 2] and F3(x^k) in s->f3, with the closing F3 half kick applied.
-// With a pair list (launches per cycle: k + 5 for k > 1, plus 1 with energies):
+// With a pair list (launches per cycle: k + 6, plus 1 with energies):
 //   step 0:          k_int: opening F3 kick, drift to x^1 (also into sorted buffer B)
 //   x^i, 0 < i < k:  k_pair_list at x^i: F2(x^i), then kick2 of step i-1 and the drift
 //                    of step i, positions ping-ponging between sorted buffers A and B
-//   x^k:             rebin both grids (3 launches: the last k_pair_list did the first
-//                    pass); one launch for the triplet partial
+//   x^k:             rebin both grids (4 launches; a first binning pass fused into the
+//                    last k_pair_list measured slower: its atomics with return stall
+//                    the force kernel's few waves); one launch for the triplet partial
 //                    slots of x^k and the new pair list; k_pair_list at x^k: F2(x^k),
 //                    F3(x^k) gathered from the slots, last kick2 and the closing F3 kick
 // Without a list (skin 0) every step rebins the pair grid and runs the tile kernel.
@@ -1059,10 +1052,9 @@ mts_status enqueue_cycle(mts_system *s, double *f2_0, double *f2_1, bool energie
             u.drift = true;
             u.f2prev = f2[(i - 1) & 1];
             u.xs_out = i + 1 < k ? buf[(i + 1) & 1] : nullptr;  // x^k: a rebinning follows
-            u.bin = i + 1 == k;  // ... whose first pass this kernel does
             MTS_TRY(enqueue_pair_list(s, buf[i & 1], f2[i & 1], u, false));
         }
-        MTS_TRY(enqueue_full_step_list(s, energies, k > 1, mode));
+        MTS_TRY(enqueue_full_step_list(s, energies, mode));
         Fused u;
         u.gather3 = true;
         u.kick2 = true;

@@ -152,7 +152,7 @@ hipError_t launch_bin(hipStream_t st, const BinArgs &a) {
         if (a.g[q].ncell <= 0) return hipErrorInvalidValue;
         ntile = std::max(ntile, (a.g[q].ncell + kScanTile - 1) / kScanTile);
     }
-    if (a.n > 0 && !a.counted) k_bin_count<<<grid, 256, 0, st>>>(a);
+    if (a.n > 0) k_bin_count<<<grid, 256, 0, st>>>(a);
     k_scan_tiles<<<dim3((unsigned)ntile, (unsigned)a.ng), 1024, 0, st>>>(a);
     // also for n = 0: the scatter writes the final cell starts
     k_bin_scatter<<<dim3(std::max(1u, grid.x), (unsigned)a.ng), 256, 0, st>>>(a);

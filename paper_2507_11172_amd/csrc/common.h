@@ -191,8 +191,6 @@ struct BinArgs {
     const int *sys_of;      // [n]
     int *flags;
     int ng;                 // 1 or 2 grids
-    int counted;            // 1: cell_of, rank and the histograms were filled by the kernel
-                            // that produced x (the first pass is skipped)
     BinGrid g[2];
 };
 hipError_t launch_bin(hipStream_t st, const BinArgs &a);
@@ -279,10 +277,6 @@ struct PairListArgs {
     const double *pf;       // [14][3][n] partial slots, or null
     const int *inv_perm3;   // input -> sorted index of the triplet grid
     double *f3_out;         // [n][3]
-    // optional (with drift): first binning pass of the drifted positions into nbin grids
-    // (cell index, arrival rank, histogram), as the binning's count kernel does
-    int nbin;
-    BinGrid bin[2];
 };
 hipError_t launch_pair_list(hipStream_t st, const PairListArgs &a);  // LJ in FP64
 size_t pair_lds_bytes(int stage_cap);

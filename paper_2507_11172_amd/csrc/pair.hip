@@ -308,7 +308,7 @@ __global__ void __launch_bounds__(256) k_pair_list(PairListArgs a) {
     }
 
     // ---- fused update of component r, in Algorithm 2's order
-    double dd2 = 0.0, xnew = 0.0;
+    double dd2 = 0.0;
     if (act && r < 3) {
         const double F = r == 0 ? fx : (r == 1 ? fy : fz);
         a.f[q] = F;
@@ -320,7 +320,6 @@ __global__ void __launch_bounds__(256) k_pair_list(PairListArgs a) {
             if (a.drift) {
                 const double Lr = L[r];
                 const double xn = wrap1(xq + a.dt * vq + a.cx * F, Lr);
-                xnew = xn;
                 a.x[q] = xn;
                 if (a.xs_out) reinterpret_cast<double *>(a.xs_out + p)[r] = xn;
                 if (a.x_ref) {
@@ -335,25 +334,6 @@ __global__ void __launch_bounds__(256) k_pair_list(PairListArgs a) {
     // displacement since the list build: (dx^2 + dy^2) + dz^2 in lane r = 0
     const double d1 = __shfl_down(dd2, 1, G);
     const double d2 = __shfl_down(dd2, 2, G);
-    if (a.nbin > 0) {  // first binning pass of the new position (wave-uniform branch)
-        const double yb = __shfl_down(xnew, 1, G), zb = __shfl_down(xnew, 2, G);
-        if (act && r == 0 && upd && a.drift) {
-            const int64_t i = a.perm[pp];
-            const double xs3[3] = {xnew, yb, zb};
-            const bool finite = isfinite(xnew) && isfinite(yb) && isfinite(zb);
-            if (!finite) atomicOr(a.flags, kFlagNonFinite);
-            for (int g = 0; g < a.nbin; ++g) {
-                const BinGrid &bg = a.bin[g];
-                const SysDesc &dg = bg.sd[a.sys_of[i]];
-                int c[3];
-#pragma unroll
-                for (int k = 0; k < 3; ++k) c[k] = cell_coord(wrap1(xs3[k], dg.L[k]), dg.q[k], dg.nc[k]);
-                const int cell = dg.cell0 + (c[2] * dg.nc[1] + c[1]) * dg.nc[0] + c[0];
-                bg.cell_of[i] = cell;
-                bg.rank[i] = atomicAdd(&bg.count[cell], 1);
-            }
-        }
-    }
     if (act && r == 0) {
         if (ENERGY) {
             a.pe[2 * p] = 0.5 * u;
