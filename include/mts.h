@@ -214,7 +214,12 @@ enum {
     /* Triplet launches of a batch: 0 (default) one launch over every system; 1 one launch
      * per tile class (systems grouped by the workgroups per CU their tiles allow).
      * mts_autotune tries both for batches.  Results are bitwise the same either way. */
-    MTS_OPT_TILE_CLASSES = 3
+    MTS_OPT_TILE_CLASSES = 3,
+    /* Where F3 is summed from the triplet partial slots at each full step: 1 by a kernel of
+     * its own, 0 inside the list force kernel (default: 1 for 128 Ki particles and more).
+     * mts_autotune tries both.  Results are bitwise the same either way (the same slot
+     * order). */
+    MTS_OPT_F3_GATHER_APART = 4
 };
 
 /* Sets an option (see the MTS_OPT_ constants).  MTS_ERR_INVALID_ARG for unknown options. */
@@ -246,6 +251,10 @@ typedef struct {
                              more triplet workgroups share a CU and that measures faster) */
     int32_t triplet_workgroups_per_cu; /* triplet workgroups one CU holds in the (first)
                              triplet launch at the current capacities (0: DirectSum) */
+    int32_t f3_gather_apart; /* 1: F3 is summed from the triplet partial slots by a kernel
+                             of its own at each full step (coalesced reads; by default for
+                             128 Ki particles and more); 0: inside the list force kernel */
+    int32_t pad_;         /* keeps the struct a multiple of 8 bytes */
 } mts_tuning;
 
 /* (MTS_DIRECT handles have nothing to tune: the call returns their configuration.)

@@ -39,6 +39,7 @@ MTS_STATIC_SCRATCH_BYTES = 16 << 20
 MTS_OPT_CYCLE_GRAPH = 1
 MTS_OPT_LIST_LANES = 2
 MTS_OPT_TILE_CLASSES = 3
+MTS_OPT_F3_GATHER_APART = 4
 
 
 class MTSError(RuntimeError):
@@ -62,7 +63,8 @@ class mts_tuning(C.Structure):
                 ("stage_cap", C.c_int32), ("list_cap", C.c_int32), ("pair_cap", C.c_int32),
                 ("nl_cap", C.c_int32), ("trials", C.c_int32), ("shared_launch", C.c_int32),
                 ("tile_classes", C.c_int32), ("cycle_ms", C.c_double),
-                ("tight_caps", C.c_int32), ("triplet_workgroups_per_cu", C.c_int32)]
+                ("tight_caps", C.c_int32), ("triplet_workgroups_per_cu", C.c_int32),
+                ("f3_gather_apart", C.c_int32), ("pad_", C.c_int32)]
 
 
 _LIB = None
@@ -289,7 +291,7 @@ class System:
 
     @staticmethod
     def _tuning_dict(t: "mts_tuning") -> dict:
-        return {name: getattr(t, name) for name, _ in mts_tuning._fields_}
+        return {name: getattr(t, name) for name, _ in mts_tuning._fields_ if name != "pad_"}
 
     def autotune(self, x, v, budget_ms: int = 2000) -> dict:
         """Times candidate configurations on (x, v) (not modified) and keeps the fastest;

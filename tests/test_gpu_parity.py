@@ -450,6 +450,31 @@ def test_cycle_graph_matches_eager_bitwise(k):
         assert torch.equal(a, b)
 
 
+
+def test_f3_gather_placement_option():
+    """F3 summed from the partial slots by its own kernel or inside the list force kernel:
+    the same slot order, so trajectories and energy records agree bit for bit (and the
+    fused form is the one the oracle tests above check at this size)."""
+    torch = _torch()
+    from paper_2507_11172_amd import mts
+    w = W.plain_fp64()
+    k = 5
+    out = []
+    for apart in (0, 1):
+        with _system(w, k=k) as s:
+            s.set_option(mts.MTS_OPT_F3_GATHER_APART, apart)
+            assert s.tuning()["f3_gather_apart"] == apart
+            x, v = _dev(w.x), _dev(w.v)
+            e = torch.zeros((5, 1, 5), dtype=torch.float64, device="cuda")
+            s.respa_step(x, v, 4 * k, e)
+            s.sync()
+            out.append((x.cpu(), v.cpu(), e.cpu()))
+    for a, b in zip(out[0], out[1]):
+        assert torch.equal(a, b)
+    with _system(w, k=k) as s:
+        with pytest.raises(mts.MTSError):
+            s.set_option(mts.MTS_OPT_F3_GATHER_APART, 2)
+
 def test_batched_replicas_match_single_systems():
     """One batched handle over uneven replicas gives, bit for bit, the forces, trajectories
     and per-system energies of each replica run on its own (same explicit skin)."""
@@ -791,6 +816,7 @@ def test_autotune_keeps_parity_and_caches(case):
         t = s.autotune(x, v, budget_ms=1500)
         assert t["trials"] >= 1 and t["cycle_ms"] > 0.0
         assert t["tight_caps"] in (0, 1) and t["triplet_workgroups_per_cu"] >= 1
+        assert t["f3_gather_apart"] in (0, 1)
         assert torch.equal(x, _dev(w.x)) and torch.equal(v, _dev(w.v))  # inputs untouched
         f2, f3 = torch.empty_like(x), torch.empty_like(x)
         s.compute_pair_forces(x, f2)
@@ -813,7 +839,7 @@ def test_autotune_keeps_parity_and_caches(case):
         t2 = s2.autotune(x, v, budget_ms=1500)
         assert t2["trials"] == 0
         for key in ("skin", "cell_factor", "list_lanes", "stage_cap", "list_cap", "nl_cap",
-                    "tight_caps", "triplet_workgroups_per_cu"):
+                    "tight_caps", "triplet_workgroups_per_cu", "f3_gather_apart"):
             assert t2[key] == t[key], key
         assert s2.tuning()["list_lanes"] == t["list_lanes"]
 
