@@ -125,7 +125,8 @@ struct mts_system {
 
     // device buffers (library-owned)
     int *sys_of = nullptr;        // [n]
-    double *red_part = nullptr;   // [nsys][kRedChunks][6] reduction partials
+    int red_chunks = kRedChunks;  // reduction workgroups per system (largest system's count)
+    double *red_part = nullptr;   // [nsys][red_chunks][6] reduction partials
     int *red_done = nullptr;      // [nsys + 1] reduction completion counters (zero at rest)
     double *f2a = nullptr, *f2b = nullptr, *f3 = nullptr;  // [n][3] force caches
     double *pf = nullptr;         // [14][3][n] triplet partial slots
@@ -473,7 +474,9 @@ mts_status build_layout(mts_system *s, const Config &cfg, Layout &out) {
 mts_status alloc_all(mts_system *s) {
     const int64_t n = s->n;
     HIP_TRY(s, dalloc(&s->sys_of, n));
-    HIP_TRY(s, dalloc(&s->red_part, (size_t)s->nsys * kRedChunks * 6));
+    s->red_chunks = kRedChunks;
+    for (const SysDesc &d : s->base) s->red_chunks = std::max(s->red_chunks, red_chunks(d.n));
+    HIP_TRY(s, dalloc(&s->red_part, (size_t)s->nsys * s->red_chunks * 6));
     HIP_TRY(s, dalloc(&s->red_done, (size_t)s->nsys + 1));
     HIP_TRY(s, hipMemset(s->red_done, 0, sizeof(int) * (s->nsys + 1)));
     HIP_TRY(s, dalloc(&s->f2a, 3 * n));
@@ -939,6 +942,7 @@ mts_status enqueue_reduce(mts_system *s, const double *v, bool pair, bool trip, 
     a.row = row;
     a.part = s->red_part;
     a.done = s->red_done;
+    a.chunks = s->red_chunks;
     HIP_TRY(s, launch_reduce(s->st, a));
     return MTS_OK;
 }

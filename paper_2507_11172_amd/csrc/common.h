@@ -370,10 +370,19 @@ struct ReduceArgs {
     int *flags;
     int *row;               // optional device row counter: row[0] is the row to write
                             // (out += row * nsys * stride) and is advanced by one
-    double *part;           // scratch [nsys][kRedChunks][6]
+    double *part;           // scratch [nsys][chunks][6]
     int *done;              // [nsys + 1] completion counters, zero between launches
+    int chunks;             // workgroups per system in the grid, >= red_chunks(n) of each
 };
+// Chunks of one system's reduction: 64 per 64 Ki particles, from 64 up to 1024, so that a
+// large system spreads over the whole chip while the summation order of a system depends
+// on its own particle count only (a system gives the same bits alone and in a batch).
 constexpr int kRedChunks = 64;
+constexpr int kRedChunksMax = 16 * kRedChunks;
+__host__ __device__ inline int red_chunks(int64_t n) {
+    const int64_t m = (n + 65535) >> 16;
+    return (int)(m < 1 ? 1 : (m > 16 ? 16 : m)) * kRedChunks;
+}
 
 // ---- DirectSum (no cutoff, open boundaries)
 constexpr int kDirBlock = 64;  // particles per block of the all-triplets kernel

@@ -67,19 +67,23 @@ __device__ __forceinline__ double wave_sum_xor(double v) {
 // One launch per reduction.  Block (system s, chunk c) sums a fixed contiguous chunk of the
 // system's particles (kinetic, pair energy/virial) and cells (triplet energy/virial/count)
 // and stores the six partials; the block that finishes a system's chunks last (a
-// device-scope counter per system) then sums that system's partials in a fixed order (one
-// lane per chunk, butterfly) and writes its record.  The last system to finish advances the record row and every counter
-// is left at zero for the next launch, so the kernel can be replayed from a graph.
+// device-scope counter per system) then sums that system's partials in a fixed order (lane
+// l adds chunks l, l + 64, ... in turn, then a butterfly) and writes its record.  A system
+// has red_chunks(n) chunks; blocks beyond them (a batch of unequal systems) exit at once.
+// The last system to finish advances the record row and every counter is left at zero for
+// the next launch, so the kernel can be replayed from a graph.
 __global__ void __launch_bounds__(kRed) k_reduce(ReduceArgs a) {
     __shared__ double red[kRed / kWave][6];
     __shared__ int s_last;
-    const int s = blockIdx.x / kRedChunks, c = blockIdx.x % kRedChunks;
+    const int s = blockIdx.x / a.chunks, c = blockIdx.x % a.chunks;
     const int t = threadIdx.x;
     const SysDesc &d = a.sd[s];
-    const int64_t lp = (d.n + kRedChunks - 1) / kRedChunks;
-    const int64_t pb = d.p0 + c * lp, pe = d.p0 + min(d.n, (c + 1) * lp);
-    const int lc = (d.ncell + kRedChunks - 1) / kRedChunks;
-    const int cb = d.cell0 + c * lc, ce = d.cell0 + min(d.ncell, (c + 1) * lc);
+    const int nch = red_chunks(d.n);
+    if (c >= nch) return;
+    const int64_t lp = (d.n + nch - 1) / nch;
+    const int64_t pb = d.p0 + min(d.n, c * lp), pe = d.p0 + min(d.n, (c + 1) * lp);
+    const int lc = (d.ncell + nch - 1) / nch;
+    const int cb = d.cell0 + min(d.ncell, c * lc), ce = d.cell0 + min(d.ncell, (c + 1) * lc);
     double v6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // K, U2, U3, W2, W3, count
     if (a.v)
         for (int64_t i = pb + t; i < pe; i += kRed) {
@@ -105,24 +109,26 @@ __global__ void __launch_bounds__(kRed) k_reduce(ReduceArgs a) {
         for (int k = 0; k < 6; ++k) red[t / kWave][k] = v6[k];
     __syncthreads();
     if (t == 0) {
-        double *o = a.part + 6 * (size_t)blockIdx.x;
+        double *o = a.part + 6 * ((size_t)s * a.chunks + c);
         for (int k = 0; k < 6; ++k) {
             double r = 0.0;
             for (int w = 0; w < kRed / kWave; ++w) r += red[w][k];
             o[k] = r;
         }
         __threadfence();  // the partials before the count (release)
-        s_last = atomicAdd(&a.done[s], 1) == kRedChunks - 1;
+        s_last = atomicAdd(&a.done[s], 1) == nch - 1;
     }
     __syncthreads();
     if (!s_last || t >= kWave) return;
     __threadfence();  // acquire: every chunk's partials of system s are visible
-    // lane q holds chunk q's partials; butterfly sums in a fixed order
-    static_assert(kRedChunks == kWave, "one lane per chunk");
-    const double *part = a.part + 6 * ((size_t)s * kRedChunks + t);
-    double r[6];
+    static_assert(kRedChunks == kWave, "chunk counts are whole waves");
+    const double *part = a.part + 6 * ((size_t)s * a.chunks + t);
+    double r[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int q = 0; q < nch; q += kWave)
 #pragma unroll
-    for (int k = 0; k < 6; ++k) r[k] = wave_sum_xor(part[k]);
+        for (int k = 0; k < 6; ++k) r[k] += part[6 * q + k];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) r[k] = wave_sum_xor(r[k]);
     if (t != 0) return;
     a.done[s] = 0;
     const double kin = r[0] * a.half_mass;
@@ -160,7 +166,9 @@ hipError_t launch_int(hipStream_t st, const IntArgs &a) {
 
 hipError_t launch_reduce(hipStream_t st, const ReduceArgs &a) {
     if (a.nsys <= 0) return hipSuccess;
-    k_reduce<<<a.nsys * kRedChunks, kRed, 0, st>>>(a);
+    if (a.chunks < kRedChunks || a.chunks > kRedChunksMax || a.chunks % kRedChunks)
+        return hipErrorInvalidValue;
+    k_reduce<<<a.nsys * a.chunks, kRed, 0, st>>>(a);
     return hipGetLastError();
 }
 

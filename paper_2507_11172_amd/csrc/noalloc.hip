@@ -151,7 +151,7 @@ extern "C" mts_status mts_compute_triplet_forces_static(const mts_params *params
     Pos4 *xs = cv.take<Pos4>(n);
     double *pf = cv.take<double>((size_t)kNumHalf * 3 * n);
     double *ce = cv.take<double>(2 * (size_t)ncell);
-    double *part = cv.take<double>((size_t)kRedChunks * 6);
+    double *part = cv.take<double>((size_t)red_chunks(n) * 6);
     if (cv.used > (size_t)MTS_STATIC_SCRATCH_BYTES) return MTS_ERR_CAPACITY;
 
     hipStream_t st = (hipStream_t)stream;
@@ -227,6 +227,7 @@ extern "C" mts_status mts_compute_triplet_forces_static(const mts_params *params
         ra.flags = flags;
         ra.part = part;
         ra.done = red_done;
+        ra.chunks = red_chunks(n);
         NA_TRY(launch_reduce(st, ra));
     }
     int hflags = 0;
