@@ -15,6 +15,11 @@
 namespace mts {
 
 constexpr int kWave = 64;        // CDNA wavefront width
+
+// Lanes of the wavefront where p holds, as a 64-bit mask.  Taken from the bool itself, so
+// the compare's lane mask is used directly (through an int, the predicate would first be
+// materialised in a vector register and compared again).
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 constexpr int kNumHalf = 14;     // self cell + 13 forward cells of the half stencil
 constexpr int kNumFull = 27;     // full 3x3x3 stencil
 constexpr int kNE = 5;           // K, U2, U3, W2, W3

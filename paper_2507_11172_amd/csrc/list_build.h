@@ -82,7 +82,7 @@ __device__ __forceinline__ void list_build_block(const ListBuildArgs &a, int bas
                 near = fmaf(dz, dz, fmaf(dy, dy, dx * dx)) <= rv2;
                 slot = e.slot;
             }
-            const uint64_t mask = __ballot(near);
+            const uint64_t mask = ballot(near);
             const int pos = cnt + __popcll(mask & below);
             if (near && pos < a.nl_cap) a.nbr[p * a.nl_cap + pos] = slot;
             cnt += __popcll(mask);

@@ -47,6 +47,7 @@
 // FP64 oracle's in both precisions; T is the precision of the ATM arithmetic.  LDS
 // arrays are structure-of-arrays so that consecutive lanes touch consecutive banks.
 #include <algorithm>
+#include <type_traits>
 
 #include "atm.h"
 #include "common.h"
@@ -57,15 +58,10 @@ namespace mts {
 constexpr int kTripWaves = 4;
 constexpr int kTripThreads = kTripWaves * kWave;
 // Hit queue: evaluated one hit per lane whenever 64 are pending; one round of tests
-// pushes at most kPairsPerLane x 64 more.
+// (one list pair per lane: two per lane would give each lane two independent chains, but
+// one keeps the registers and the queue small, which is worth more) pushes at most 64 more.
 constexpr int kQueueCap = 2 * kWave;   // a ring: fewer than 64 pending + 64 pushed
 constexpr int kQueueMask = kQueueCap - 1;
-// List pairs tested per lane and round of the j-k sweep (1 or 2): two give each lane two
-// independent chains, one keeps the registers and the queue small, which is worth more
-// (five waves per SIMD need at most 96 VGPRs).
-template <typename T>
-constexpr int kPairsPerLane = 1;
-static_assert(kQueueCap >= kWave + kPairsPerLane<double> * kWave, "hit queue too small");
 
 // Number of set bits of mask in the lanes below this one.
 __device__ __forceinline__ int below(uint64_t mask) {
@@ -285,7 +281,7 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
     __shared__ double s_sz[kNumHalf];
     const int CAP = a.stage_cap, LC = a.list_cap;
     const int tid = threadIdx.x;
-    const int wave = tid / kWave, lane = tid % kWave;
+    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave), lane = tid % kWave;
     const int64_t n = a.n;
     const int sysq = a.sys_of_cell[base];
     const SysDesc &d = a.sd[sysq];
@@ -317,6 +313,10 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
         nst = CAP;
     }
     a_hi = min(a_hi, nst);
+    // workgroup-uniform: the loops over tile entries and anchors stay scalar
+    nst = __builtin_amdgcn_readfirstlane(nst);
+    a_lo = __builtin_amdgcn_readfirstlane(a_lo);
+    a_hi = __builtin_amdgcn_readfirstlane(a_hi);
     for (int t = tid; t < nst; t += kTripThreads) {
         int src, code;
         if (whole) {
@@ -412,7 +412,10 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
                 const double q1 = norm2(x1, y1, z1), q2 = norm2(x2, y2, z2);
                 const bool in1 = t1 < nst && q1 <= rc2;
                 const bool in2 = t2 < nst && q2 <= rc2;
-                const uint64_t m1 = __ballot(in1), m2 = __ballot(in2);
+                // the masks from the compares themselves (a ballot of their conjunction
+                // would first be materialised in a vector register)
+                const uint64_t m1 = ballot(t1 < nst) & ballot(q1 <= rc2);
+                const uint64_t m2 = ballot(t2 < nst) & ballot(q2 <= rc2);
                 const int n1 = __popcll(m1);
                 const int p1 = m + below(m1), p2 = m + n1 + below(m2);
                 if (in1 && p1 < LC) {
@@ -475,7 +478,7 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
             const double c = (double)((vx * vx + vy * vy) + vz * vz);
             const bool amb = in && c > ra2 - band && c <= ra2 + band;
             in = in && c <= ra2 - band;
-            if (__ballot(amb)) {
+            if (ballot(amb)) {
                 if (amb) {
                     const PosEnt ej = entry(tj & kTileMask);
                     const PosEnt ek = entry(tk & kTileMask);
@@ -513,34 +516,42 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
             __builtin_amdgcn_wave_barrier();
         };
 
-        // ---- B: the j-k test of every unordered list pair, P x 64 per round (P per lane).
+        // ---- B: the j-k test of every unordered list pair, one per lane and round.
         // Pair item q = (dd - 1) m + j stands for (j, k = (j + dd) mod m): diagonals
         // dd = 1, 2, ... of the circulant, each a permutation of the list; for even m the
         // last diagonal dd = m/2 pairs each entry with its opposite, and its first half
         // (j < m/2) covers those pairs once, so q < m(m - 1)/2 visits every pair exactly
-        // once with all lanes busy.  Lane l takes q = l + 64 p (p < P) and advances by 64 P.
-        constexpr int P = kPairsPerLane<T>;
+        // once with all lanes busy.  Lane l takes q = l and advances by 64.
         m = __builtin_amdgcn_readfirstlane(m);  // wave-uniform: keeps m and what follows scalar
         const int npair = m * (m - 1) / 2;
         if (npair > 0) {
-            // 64 P = adv_d m + adv_j, and item q = (dd - 1) m + j: quotients from the
-            // hardware reciprocal of m, corrected by one step where it rounded across
+            // 64 = adv_d m + adv_j, and item q = (dd - 1) m + j: quotients from the
+            // hardware reciprocal of m, corrected by one step where it rounded across.
+            // An advance by 64 items moves j by adv_j mod m, and dd by adv_d plus the carry
+            // of j's wrap, so k = (j + dd) mod m moves by (adv_j + adv_d) mod m plus that
+            // carry; with more than one round m >= 12 and adv_d <= 5 < m, so each sum is
+            // below 2m and one conditional subtraction reduces it: (j + a) mod m for
+            // j + a < 2m is min(j + a, j + a - m) in unsigned arithmetic (the second
+            // wraps when j + a < m).
             const float rm = __builtin_amdgcn_rcpf((float)m);
-            int adv_d = (int)((float)(P * kWave) * rm), adv_j = P * kWave - adv_d * m;
+            int adv_d = (int)((float)kWave * rm), adv_j = kWave - adv_d * m;
             if (adv_j >= m) { adv_j -= m; ++adv_d; }
             if (adv_j < 0) { adv_j += m; --adv_d; }
-            adv_d = __builtin_amdgcn_readfirstlane(adv_d);
-            adv_j = __builtin_amdgcn_readfirstlane(adv_j);
-            int jj[P], dq[P];
-#pragma unroll
-            for (int p = 0; p < P; ++p) {  // (j, dd) of item lane + 64 p
-                const int q = lane + p * kWave;
-                int d0 = (int)(((float)q + 0.5f) * rm);
-                int j0 = q - d0 * m;
+            int adv_k = adv_j + adv_d;
+            if (adv_k >= m) adv_k -= m;
+            const unsigned aj = (unsigned)__builtin_amdgcn_readfirstlane(adv_j);
+            const unsigned ak = (unsigned)__builtin_amdgcn_readfirstlane(adv_k);
+            const unsigned um = (unsigned)m;
+            unsigned jj, kk;
+            {  // (j, k) of item lane
+                int d0 = (int)(((float)lane + 0.5f) * rm);
+                int j0 = lane - d0 * m;
                 if (j0 >= m) { j0 -= m; ++d0; }
                 if (j0 < 0) { j0 += m; --d0; }
-                jj[p] = j0;
-                dq[p] = d0 + 1;
+                int k0 = j0 + d0 + 1;   // dd <= m/2 for a valid item: one step
+                k0 -= k0 >= m ? m : 0;
+                jj = (unsigned)j0;
+                kk = (unsigned)k0;
             }
             // the canonical FP64 test of a j-k edge within rounding of the cutoff (rare)
             auto settle = [&](int j, int k) {
@@ -551,52 +562,40 @@ __device__ __forceinline__ void triplet_block(const TripletArgs &a, int base,
                 const double wz = disp1(ej.z, ek.z, ek.sz - ej.sz);
                 return norm2(wx, wy, wz) <= rc2;
             };
-            for (int q0 = 0; q0 < npair; q0 += P * kWave) {
-                // a last round of at most 64 items leaves out its second half
-                const bool full = q0 + kWave < npair;  // wave-uniform
-                bool hit[P], amb[P];
-                int kk[P];
-                bool any_amb = false;
-#pragma unroll
-                for (int p = 0; p < P; ++p) {
-                    hit[p] = amb[p] = false;
-                    kk[p] = 0;
-                    if (p > 0 && !full) continue;
-                    const bool ok = q0 + p * kWave + lane < npair;
-                    int k = jj[p] + dq[p];
-                    k -= k >= m ? m : 0;
-                    kk[p] = k;
-                    const ListEnt<float> fj = L.f[ok ? jj[p] : 0], fk = L.f[ok ? k : 0];
+            for (int q0 = 0; q0 < npair; q0 += kWave) {
+                // FP32 |u_k - u_j|^2 of this lane's item; the round that runs past the
+                // last item (CHECK) gives its idle lanes +inf and reads entry 0 for them
+                auto jk2 = [&](auto check) {
+                    constexpr bool CHECK = decltype(check)::value;
+                    const bool ok = !CHECK || q0 + lane < npair;
+                    const ListEnt<float> fj = L.f[CHECK && !ok ? 0u : jj];
+                    const ListEnt<float> fk = L.f[CHECK && !ok ? 0u : kk];
                     const float x = fk.ux - fj.ux, y = fk.uy - fj.uy, z = fk.uz - fj.uz;
                     const float c = fmaf(z, z, fmaf(y, y, x * x));
-                    hit[p] = ok && c <= jk_lo;
-                    amb[p] = ok && c > jk_lo && c <= jk_hi;
-                    any_amb = any_amb || amb[p];
+                    return CHECK && !ok ? __builtin_inff() : c;
+                };
+                float c;
+                if (q0 + kWave <= npair) c = jk2(std::false_type{});
+                else c = jk2(std::true_type{});
+                bool hit = c <= jk_lo;
+                uint64_t mh = ballot(hit);
+                if (ballot(c <= jk_hi) & ~mh) {  // rare: settle with the canonical FP64 test
+                    bool s = false;
+                    if (c > jk_lo && c <= jk_hi) s = settle((int)jj, (int)kk);
+                    hit = hit || s;
+                    mh |= ballot(s);
                 }
-                if (__ballot(any_amb)) {  // rare: settle with the canonical FP64 test
-#pragma unroll
-                    for (int p = 0; p < P; ++p)
-                        if (amb[p]) hit[p] = settle(jj[p], kk[p]);
-                }
-                // append the hits to the ring queue: lane order, item by item
-#pragma unroll
-                for (int p = 0; p < P; ++p) {
-                    if (p > 0 && !full) break;
-                    const uint64_t mh = __ballot(hit[p]);
-                    if (hit[p]) Q[(qt + below(mh)) & kQueueMask] = (unsigned short)(jj[p] | (kk[p] << 8));
-                    qt += __popcll(mh);
-                }
+                // append the hits to the ring queue in lane order
+                if (hit) Q[(qt + below(mh)) & kQueueMask] = (unsigned short)(jj | (kk << 8));
+                qt += __popcll(mh);
                 __builtin_amdgcn_wave_barrier();
                 while (qt - qh >= kWave) {
                     evaluate(kWave);
                     ntrip += kWave;
                 }
-#pragma unroll
-                for (int p = 0; p < P; ++p) {
-                    jj[p] += adv_j;
-                    dq[p] += adv_d;
-                    if (jj[p] >= m) { jj[p] -= m; ++dq[p]; }
-                }
+                const unsigned j1 = jj + aj, k1 = kk + ak + (j1 >= um ? 1u : 0u);
+                jj = min(j1, j1 - um);
+                kk = min(k1, k1 - um);
             }
             if (qt > qh) {
                 ntrip += qt - qh;
