@@ -37,7 +37,7 @@ __device__ __forceinline__ void list_build_block(const ListBuildArgs &a, int bas
 
     __shared__ StencilTable<kNumFull> tab;
     int nst = stencil_table<kNumFull, false>(tab, d, cx, cy, cz, a.start);
-    const int s13 = tab.off[13];
+    int s13 = tab.off[13];
     int nself = tab.off[14] - s13;
     if (a.stats && lane == 0) atomicMax(&a.stats[0], nst);
     if (nst > CAP) {
@@ -45,6 +45,10 @@ __device__ __forceinline__ void list_build_block(const ListBuildArgs &a, int bas
         nst = CAP;
         nself = max(0, min(nself, CAP - s13));
     }
+    // workgroup-uniform: the loops below stay scalar
+    nst = __builtin_amdgcn_readfirstlane(nst);
+    s13 = __builtin_amdgcn_readfirstlane(s13);
+    nself = __builtin_amdgcn_readfirstlane(nself);
     for (int t = lane; t < nst; t += kListBuildThreads) {
         const int o = stencil_cell_of<kNumFull>(tab, t);
         const int src = tab.begin[o] + (t - tab.off[o]);
@@ -63,28 +67,29 @@ __device__ __forceinline__ void list_build_block(const ListBuildArgs &a, int bas
     // the squared distance (summed with fused multiply-adds), so every pair within the
     // list radius is kept
     const float rv2 = (float)(a.rv2 * (1.0 + 1e-5));
-    const int wave = lane / kWave, wl = lane % kWave;
-    const uint64_t below = wl == 0 ? 0ull : (~0ull >> (kWave - wl));
+    const int wave = __builtin_amdgcn_readfirstlane(lane / kWave), wl = lane % kWave;
     const int pbase = a.start[base];
     // one wavefront per base-cell particle, all 64 lanes sweeping the tile
     for (int i = wave; i < nself; i += kListBuildThreads / kWave) {
         const int self = s13 + i;
         const BuildEnt pi = tile[self];
         const int64_t p = pbase + i;
+        int *row = a.nbr + p * a.nl_cap;
         int cnt = 0;
         for (int t0 = 0; t0 < nst; t0 += kWave) {
             const int t = t0 + wl;
-            bool near = false;
-            int slot = 0;
-            if (t < nst && t != self) {
-                const BuildEnt e = tile[t];
-                const float dx = e.x - pi.x, dy = e.y - pi.y, dz = e.z - pi.z;
-                near = fmaf(dz, dz, fmaf(dy, dy, dx * dx)) <= rv2;
-                slot = e.slot;
-            }
-            const uint64_t mask = ballot(near);
-            const int pos = cnt + __popcll(mask & below);
-            if (near && pos < a.nl_cap) a.nbr[p * a.nl_cap + pos] = slot;
+            const bool in = t < nst;
+            const BuildEnt e = tile[in ? t : self];
+            const float dx = e.x - pi.x, dy = e.y - pi.y, dz = e.z - pi.z;
+            const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+            const bool near = in && t != self && d2 <= rv2;
+            // the lane mask from the compares themselves (a ballot of their conjunction
+            // would first be materialised in a vector register)
+            const uint64_t mask = ballot(in) & ballot(t != self) & ballot(d2 <= rv2);
+            const int pos = cnt + (int)__builtin_amdgcn_mbcnt_hi(
+                                      (unsigned)(mask >> 32),
+                                      __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+            if (near && pos < a.nl_cap) row[pos] = e.slot;
             cnt += __popcll(mask);
         }
         if (wl == 0) {
