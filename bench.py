@@ -118,6 +118,11 @@ def _drift_stats(en, n_particles):
     return float(drift.mean()), float(rvite.mean())
 
 
+# Runs repeated after a capacity overflow: every overflow enlarges what overflowed (tile,
+# lists), so the sizes grow monotonically; a batch of many systems can reveal a few in turn.
+CAPACITY_ATTEMPTS = 8
+
+
 def run_gpu(w, precision: str, k: int, steps: int, warmup: int, tune_ms: int):
     import numpy as np
     import torch
@@ -131,7 +136,7 @@ def run_gpu(w, precision: str, k: int, steps: int, warmup: int, tune_ms: int):
     # one-time set-up outside the timed region, like the graph capture of the warm-up
     tuning = sysm.autotune(x, v, tune_ms) if tune_ms > 0 else sysm.tuning()
     x0, v0 = x.clone(), v.clone()
-    for attempt in range(3):
+    for attempt in range(CAPACITY_ATTEMPTS):
         if warmup > 0:
             sysm.respa_step(x, v, warmup * span)
         try:
@@ -140,13 +145,14 @@ def run_gpu(w, precision: str, k: int, steps: int, warmup: int, tune_ms: int):
         except mts.MTSError as err:
             # a tile or list outgrew its initial size: the library has enlarged it, and
             # the warm-up is repeated from the initial state
-            if err.code != mts.MTS_ERR_CAPACITY or attempt == 2:
+            if err.code != mts.MTS_ERR_CAPACITY or attempt == CAPACITY_ATTEMPTS - 1:
                 raise
+            print(f"warm-up repeated: {err}", file=sys.stderr, flush=True)
             x.copy_(x0)
             v.copy_(v0)
     e = torch.zeros((steps + 1, w.n_systems, mts.MTS_NE), dtype=torch.float64, device=dev)
     x1, v1 = x.clone(), v.clone()
-    for attempt in range(3):
+    for attempt in range(CAPACITY_ATTEMPTS):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         sysm.respa_step(x, v, steps * span, e)
@@ -155,8 +161,9 @@ def run_gpu(w, precision: str, k: int, steps: int, warmup: int, tune_ms: int):
         except mts.MTSError as err:
             # a list outgrew its size or a particle outran the skin: the library has
             # enlarged it; the timed run is repeated from the same state
-            if err.code != mts.MTS_ERR_CAPACITY or attempt == 2:
+            if err.code != mts.MTS_ERR_CAPACITY or attempt == CAPACITY_ATTEMPTS - 1:
                 raise
+            print(f"timed run repeated: {err}", file=sys.stderr, flush=True)
             x.copy_(x1)
             v.copy_(v1)
             continue

@@ -1434,14 +1434,17 @@ mts_status mts_sync(mts_system *sys) {
         Layout &lo = sys->lo;
         const int old_s = lo.stage_cap, old_l = lo.list_cap, old_p = lo.pair_cap, old_n = lo.nl_cap;
         const std::vector<int> old_need = lo.cfg.tile_need;
+        bool triplet_tile = false;  // a triplet tile overflowed (else a pair tile did)
         if (flags & kFlagStageOverflow) {
             // triplet tiles: every overflowing system recorded its size; pair tiles double
             std::vector<int> obs(sys->nsys, 0);
             HIP_TRY(sys, hipMemcpy(obs.data(), sys->tile_obs, sizeof(int) * sys->nsys, hipMemcpyDeviceToHost));
             HIP_TRY(sys, hipMemset(sys->tile_obs, 0, sizeof(int) * sys->nsys));
             for (int q = 0; q < sys->nsys; ++q)
-                if (obs[q] > 0)
+                if (obs[q] > 0) {
                     lo.cfg.tile_need[q] = std::max(lo.cfg.tile_need[q], (int)std::ceil(1.15 * obs[q]) + 16);
+                    triplet_tile = true;
+                }
             lo.pair_cap = std::min(4096, 2 * lo.pair_cap);
         }
         // what cannot grow any further: forward lists at their 256-entry limit (list
@@ -1455,7 +1458,11 @@ mts_status mts_sync(mts_system *sys) {
             stuck = true;
         }
         MTS_TRY(upload_classes(sys, lo));
-        if (pair_lds_bytes(lo.pair_cap) > sys->max_lds) lo.pair_cap = old_p;
+        // a pair tile as large as a workgroup's LDS allows where doubling does not fit; an
+        // overflowing pair tile that cannot grow is as stuck as a full list
+        if (pair_lds_bytes(lo.pair_cap) > sys->max_lds)
+            lo.pair_cap = std::max(old_p, (int)(sys->max_lds / pair_lds_bytes(1)) / 32 * 32);
+        if ((flags & kFlagStageOverflow) && !triplet_tile && lo.pair_cap == old_p) stuck = true;
         if (flags & kFlagPairList) {
             const int cap = std::min(4096, 2 * sys->lo.nl_cap);
             int *nb = nullptr;
@@ -1469,15 +1476,15 @@ mts_status mts_sync(mts_system *sys) {
         sys->lo.cfg.pair_cap = sys->lo.pair_cap;
         sys->lo.cfg.nl_cap = sys->lo.nl_cap;
         drop_graphs(sys);  // captured launches carry the old sizes and pointers
-        char buf[320];
+        char buf[400];
         snprintf(buf, sizeof buf,
                  "capacity overflow (flags %d): triplet tile %d -> %d, pair tile %d -> %d, "
                  "neighbour list %d -> %d, pair list %d -> %d; results since the last sync "
                  "are invalid%s",
                  flags, old_s, sys->lo.stage_cap, old_p, sys->lo.pair_cap, old_l, sys->lo.list_cap, old_n,
                  sys->lo.nl_cap,
-                 stuck ? "; the triplet tile or forward lists cannot grow further (lists "
-                         "are limited to 256 entries, tile and lists to a workgroup's LDS)"
+                 stuck ? "; a tile or the forward lists cannot grow further (lists are "
+                         "limited to 256 entries, tiles and lists to a workgroup's LDS)"
                        : "");
         return fail(sys, stuck ? MTS_ERR_UNSUPPORTED : MTS_ERR_CAPACITY, buf);
     }
@@ -1486,7 +1493,14 @@ mts_status mts_sync(mts_system *sys) {
         const double old_skin = sys->lo.skin;
         Config c = sys->lo.cfg;
         c.skin = effective_skin(sys, 2.0 * old_skin);
-        if (c.skin > old_skin) (void)set_layout(sys, c);
+        if (c.skin > old_skin) {
+            // the pair grid's cells and the list radius grow with the skin: pair tiles and
+            // list rows observed on the old grid (autotuned capacities) may no longer fit,
+            // so both are sized again for the new one
+            c.pair_cap = 0;
+            c.nl_cap = 0;
+            (void)set_layout(sys, c);
+        }
         char buf[240];
         snprintf(buf, sizeof buf,
                  "a particle moved more than half the pair-list skin (%.3g) between full steps; "
