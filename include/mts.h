@@ -160,15 +160,17 @@ mts_status mts_compute_triplet_forces(mts_system *sys, const double *x, double *
  * from a Verlet list of radius rc_pair + skin built at every full step (see
  * mts_params.skin and mts_autotune); a particle that moves more than half the skin from
  * its position at the build is reported by the next mts_sync as MTS_ERR_CAPACITY (the
- * forces since may miss pairs; the skin is enlarged for the next call). */
+ * forces since may miss pairs; the skin is enlarged for the next call, and the pair tile
+ * and list-row capacities are sized again for the coarser pair grid). */
 mts_status mts_respa_step(mts_system *sys, double *x, double *v, int64_t n_iter, double *e_full);
 
 /* Waits for the stream and reports device flags raised since the last mts_sync:
  * MTS_ERR_CAPACITY (the affected forces are wrong; the tile or list capacities, or the
  * pair-list skin when a particle outran half of it, are enlarged for the next call),
  * MTS_ERR_UNSUPPORTED (an overflow that no enlargement can cure: a forward-neighbour list
- * beyond its 256-entry limit, or a triplet tile and lists beyond a workgroup's LDS; the
- * input is too dense for this library -- repeating the call fails the same way) or
+ * beyond its 256-entry limit, a triplet tile and lists or a pair tile beyond a
+ * workgroup's LDS; the input is too dense for this library -- repeating the call fails
+ * the same way) or
  * MTS_ERR_NONFINITE.  Clears the flags. */
 mts_status mts_sync(mts_system *sys);
 

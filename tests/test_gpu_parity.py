@@ -307,6 +307,36 @@ def test_pair_list_skin_violation_is_reported():
         assert "skin" in str(e.value)
 
 
+def test_skin_doubling_resizes_pair_capacities():
+    """A skin doubled after a violation sizes the pair tile and the list rows for the new
+    pair grid.  In a 9-sigma box the pair grid has three cells per edge at skin 0.3 (a pair
+    tile is the whole box) and two at 0.6 (a tile stages 27/8 of the box), so a pair tile
+    autotuned on the old grid would overflow on every repeat; resized, the next call runs."""
+    _torch()
+    from paper_2507_11172_amd import mts
+    n, length = 437, 9.0
+    rng = W.rng_for(23)
+    x0, box = W.fcc_subset(n, n / length ** 3, 0.05, rng)
+    v0 = W.maxwell_boltzmann(n, 0.7, rng)
+    w = W.Workload("box9", x0, v0, box[None, :], np.array([n]), np.array([0.7]))
+    with _system(w, k=10, skin=0.3) as s:
+        s.autotune(_dev(w.x), _dev(w.v), 1)  # first trial only: capacities seen at skin 0.3
+        t0 = s.tuning()
+        assert t0["skin"] == pytest.approx(0.3) and t0["pair_cap"] < 27 * n // 8, t0
+        fast = w.v.copy()
+        fast[0] = (40.0, 0.0, 0.0)  # outruns half the skin within one cycle
+        s.respa_step(_dev(w.x), _dev(fast), 10)
+        with pytest.raises(mts.MTSError) as e:
+            s.sync()
+        assert e.value.code == mts.MTS_ERR_CAPACITY and "skin now 0.6" in str(e.value)
+        t1 = s.tuning()
+        assert t1["skin"] == pytest.approx(0.6) and t1["pair_cap"] >= 27 * n // 8, t1
+        x, v = _dev(w.x), _dev(w.v)
+        s.respa_step(x, v, 10)
+        s.sync()
+        assert np.isfinite(x.cpu().numpy()).all()
+
+
 def test_determinism_and_resume():
     torch = _torch()
     w = W.plain_fp64()
