@@ -27,7 +27,26 @@ __global__ void __launch_bounds__(256) k_bin_count(BinArgs a) {
     if (!finite) atomicOr(a.flags, kFlagNonFinite);
     const int cell = d.cell0 + (c[2] * d.nc[1] + c[1]) * d.nc[0] + c[0];
     g.cell_of[i] = cell;
-    g.rank[i] = atomicAdd(&g.count[cell], 1);
+    // Arrival slot inside the cell, one device atomic per distinct cell of the wavefront
+    // (particles in input order are mostly clustered in space, and these atomics are
+    // resolved far from the CU): group the lanes by cell, the lowest lane of each group
+    // adds the group's size, the others take consecutive slots after it.  Any unique slot
+    // will do -- the rank pass orders every cell by input index.
+    uint64_t todo = __builtin_amdgcn_read_exec(), group = 0;
+    while (todo) {
+        const int l = __builtin_ctzll(todo);
+        const int lc = __builtin_amdgcn_readlane(cell, l);
+        const uint64_t m = ballot(cell == lc) & todo;
+        if (cell == lc) group = m;
+        todo &= ~m;
+    }
+    const int leader = __builtin_ctzll(group);
+    const int lane = (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&g.count[cell], __popcll(group));
+    base = __shfl(base, leader);
+    g.rank[i] = base + (int)__builtin_amdgcn_mbcnt_hi(
+                           (unsigned)(group >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)group, 0u));
 }
 
 // Exclusive scan of count[0..ncell) into start[0..ncell], start[ncell] = n, over many
