@@ -379,14 +379,15 @@ struct ReduceArgs {
     int *done;              // [nsys + 1] completion counters, zero between launches
     int chunks;             // workgroups per system in the grid, >= red_chunks(n) of each
 };
-// Chunks of one system's reduction: 64 per 64 Ki particles, from 64 up to 1024, so that a
-// large system spreads over the whole chip while the summation order of a system depends
-// on its own particle count only (a system gives the same bits alone and in a batch).
+// Chunks of one system's reduction: 64 per 256 Ki particles, from 64 up to 256 (each
+// chunk's last block to finish takes a device atomic on one counter, so more chunks cost
+// more than their shorter loops save), and a function of the system's own particle count,
+// so that a system sums in the same order alone and in a batch.
 constexpr int kRedChunks = 64;
-constexpr int kRedChunksMax = 16 * kRedChunks;
+constexpr int kRedChunksMax = 4 * kRedChunks;
 __host__ __device__ inline int red_chunks(int64_t n) {
-    const int64_t m = (n + 65535) >> 16;
-    return (int)(m < 1 ? 1 : (m > 16 ? 16 : m)) * kRedChunks;
+    const int64_t m = (n + 262143) >> 18;
+    return (int)(m < 1 ? 1 : (m > 4 ? 4 : m)) * kRedChunks;
 }
 
 // ---- DirectSum (no cutoff, open boundaries)

@@ -56,6 +56,7 @@ __global__ void __launch_bounds__(256) k_int(IntArgs a) {
 }
 
 constexpr int kRed = 256;
+constexpr int kRedBatch = 4;  // strides of particles whose loads are in flight together
 
 // Wave-wide sum by butterfly shuffles (fixed order: bitwise reproducible), in every lane.
 __device__ __forceinline__ double wave_sum_xor(double v) {
@@ -85,15 +86,38 @@ __global__ void __launch_bounds__(kRed) k_reduce(ReduceArgs a) {
     const int lc = (d.ncell + nch - 1) / nch;
     const int cb = d.cell0 + min(d.ncell, c * lc), ce = d.cell0 + min(d.ncell, (c + 1) * lc);
     double v6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // K, U2, U3, W2, W3, count
+    // particles in batches of kRedBatch strides: the batch's loads are all issued before
+    // its values are added (in the same order as one stride at a time)
     if (a.v)
-        for (int64_t i = pb + t; i < pe; i += kRed) {
-            const double vx = a.v[3 * i], vy = a.v[3 * i + 1], vz = a.v[3 * i + 2];
-            v6[0] += (vx * vx + vy * vy) + vz * vz;
+        for (int64_t i0 = pb + t; i0 < pe; i0 += kRedBatch * kRed) {
+            double sq[kRedBatch];
+#pragma unroll
+            for (int u = 0; u < kRedBatch; ++u) {
+                const int64_t i = i0 + (int64_t)u * kRed;
+                sq[u] = 0.0;
+                if (i < pe) {
+                    const double vx = a.v[3 * i], vy = a.v[3 * i + 1], vz = a.v[3 * i + 2];
+                    sq[u] = (vx * vx + vy * vy) + vz * vz;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kRedBatch; ++u)
+                if (i0 + (int64_t)u * kRed < pe) v6[0] += sq[u];
         }
     if (a.pe)
-        for (int64_t p = pb + t; p < pe; p += kRed) {
-            v6[1] += a.pe[2 * p];
-            v6[3] += a.pe[2 * p + 1];
+        for (int64_t p0 = pb + t; p0 < pe; p0 += kRedBatch * kRed) {
+            double2 e[kRedBatch];
+#pragma unroll
+            for (int u = 0; u < kRedBatch; ++u) {
+                const int64_t p = p0 + (int64_t)u * kRed;
+                e[u] = p < pe ? reinterpret_cast<const double2 *>(a.pe)[p] : make_double2(0.0, 0.0);
+            }
+#pragma unroll
+            for (int u = 0; u < kRedBatch; ++u)
+                if (p0 + (int64_t)u * kRed < pe) {
+                    v6[1] += e[u].x;
+                    v6[3] += e[u].y;
+                }
         }
     if (a.ce)
         for (int q = cb + t; q < ce; q += kRed) {
