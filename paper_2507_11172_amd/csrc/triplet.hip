@@ -28,7 +28,7 @@
 //      C. ATM is evaluated one queued hit per lane whenever 64 are pending, and on the
 //         rest at the end of the anchor.  The FP32 form takes u from the list; the FP64
 //         form recomputes it from the staged positions (the same canonical displacement,
-//         so the same bits), which keeps a workgroup's LDS small enough for four per CU.
+//         so the same bits), which keeps a workgroup's LDS small enough for six per CU.
 //  * Accumulation.  The partner forces of each hit go to the wave's per-list-slot FP64
 //    partials by LDS atomics issued from one wave.  The order is taken to be fixed: the
 //    wave's instructions reach the LDS in program order, and the lanes of one
@@ -728,9 +728,9 @@ __global__ void __launch_bounds__(256) k_triplet_gather(int64_t n, const double 
 //   system code path costs registers, so launches without such systems leave it out).
 // OCC: waves per SIMD the registers are held to.  Five (96 VGPRs) let five workgroups
 // share a CU when tiles and lists fit 32 KB of LDS (1M particles, FP64: 3.0 -> 2.7 ms;
-// the weighted variants of nested r-RESPA spill a few registers for it); six (80 VGPRs,
-// with some spilling in FP64) pay only when the LDS also admits six workgroups, so the
-// launcher takes them exactly then (TripletArgs.occ6).
+// the whole-system weighted variant spills a few registers for it); six (80 VGPRs; the
+// variants with whole-system tiles spill a few) pay only when the LDS also admits six
+// workgroups, so the launcher takes them exactly then (TripletArgs.occ6).
 template <typename T, bool LIST, bool ENERGY, bool WEIGHT, bool LB, bool WH, int OCC>
 __global__ void __launch_bounds__(kTripThreads) __attribute__((amdgpu_waves_per_eu(OCC)))
 k_triplet_items(TripletArgs a, ListBuildArgs b) {
