@@ -137,7 +137,7 @@ struct mts_system {
     int *stats = nullptr;         // [4] observed maxima (tile and list sizes), tuning only
     int *tile_obs = nullptr;      // [nsys] largest triplet tile seen per system (overflow,
                                   // tuning), zeroed after reading
-    double *x_ref = nullptr;      // [n][3] wrapped positions at the last list build
+    double *x_ref = nullptr;      // [n][3] wrapped positions at the last list build (pair grid order)
     int *flags = nullptr;
     int *row = nullptr;
     double *e_buf = nullptr;      // [e_rows][nsys][5] energy records of one respa_step

@@ -146,10 +146,10 @@ __global__ void __launch_bounds__(256) k_rank_gather(BinArgs a) {
     w.z = wrap1(a.x[3 * (int64_t)key + 2], d.L[2]);
     w.w = 0.0;
     g.xs[dst] = w;
-    if (g.x_ref) {
-        g.x_ref[3 * (int64_t)key] = w.x;
-        g.x_ref[3 * (int64_t)key + 1] = w.y;
-        g.x_ref[3 * (int64_t)key + 2] = w.z;
+    if (g.x_ref) {  // in the grid's sorted order, like xs
+        g.x_ref[3 * dst] = w.x;
+        g.x_ref[3 * dst + 1] = w.y;
+        g.x_ref[3 * dst + 2] = w.z;
     }
 }
 

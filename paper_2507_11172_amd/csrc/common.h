@@ -188,7 +188,7 @@ struct BinGrid {
     int *perm;              // [n] sorted -> input index
     int *inv_perm;          // [n] input -> sorted index
     Pos4 *xs;               // [n] sorted wrapped positions
-    double *x_ref;          // [n][3] wrapped positions in input order, or null
+    double *x_ref;          // [n][3] wrapped positions in this grid's sorted order, or null
 };
 struct BinArgs {
     int64_t n;
@@ -275,7 +275,7 @@ struct PairListArgs {
     const double *f3;       // F3 (kick3)
     double c2, c3, dt, cx;
     Pos4 *xs_out;           // [n] sorted positions after the drift
-    const double *x_ref;    // positions at the last list build (input order)
+    const double *x_ref;    // positions at the last list build (sorted order)
     double half_skin2;
     // optional: F3 gathered here from the triplet kernel's partial slots (fixed slot
     // order, as k_triplet_gather), written to f3_out and used by the kicks instead of f3
@@ -354,7 +354,7 @@ struct IntArgs {
     const int *sys_of;
     const int *inv_perm;    // input -> sorted index of the pair grid, or null
     Pos4 *xs;               // sorted positions of the pair grid, or null
-    const double *x_ref;    // positions at the last list build, or null
+    const double *x_ref;    // positions at the last list build (pair grid order), or null
     double half_skin2;      // (skin / 2)^2
     int *flags;
 };

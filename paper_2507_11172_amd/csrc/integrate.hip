@@ -43,10 +43,11 @@ __global__ void __launch_bounds__(256) k_int(IntArgs a) {
         a.xs[a.inv_perm[i]] = w;
     }
     if (a.x_ref) {
+        const int64_t ir = 3 * (int64_t)a.inv_perm[i];  // x_ref is in the pair grid's order
         double dd[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            double t = xn[k] - a.x_ref[3 * i + k];
+            double t = xn[k] - a.x_ref[ir + k];
             const double h = 0.5 * d.L[k];
             t = t > h ? t - d.L[k] : (t < -h ? t + d.L[k] : t);
             dd[k] = t;

@@ -265,7 +265,7 @@ __global__ void __launch_bounds__(256) k_pair_list(PairListArgs a) {
         if (!a.pf && (a.kick3_end || a.kick3_start)) f3q = a.f3[q];
         if (a.drift) {
             xq = a.x[q];
-            if (a.x_ref) xr = a.x_ref[q];
+            if (a.x_ref) xr = a.x_ref[3 * pp + r];  // sorted order
         }
     }
 
