@@ -150,6 +150,9 @@ struct mts_system {
     bool use_graph = true;
     hipGraphExec_t gexec[2][2][2] = {};  // [energies][F2 parity][ends a full step]
     double *xi = nullptr, *vi = nullptr;  // internal copies of x and v, [n][3]
+    // v and two F2 caches in the pair grid's sorted order, for the inner steps between
+    // the first and the last of a cycle with a pair list
+    double *vs = nullptr, *f2s[2] = {nullptr, nullptr};
 
     // optional per-launch HIP-event timing of the two force kernels (0: triplet, 1: pair)
     bool timing = false;
@@ -495,6 +498,11 @@ mts_status alloc_all(mts_system *s) {
     HIP_TRY(s, dalloc(&s->list_n, 1));
     HIP_TRY(s, dalloc(&s->xi, 3 * n));
     HIP_TRY(s, dalloc(&s->vi, 3 * n));
+    if (!s->direct) {
+        HIP_TRY(s, dalloc(&s->vs, 3 * n));
+        HIP_TRY(s, dalloc(&s->f2s[0], 3 * n));
+        HIP_TRY(s, dalloc(&s->f2s[1], 3 * n));
+    }
     HIP_TRY(s, hipStreamCreateWithFlags(&s->ist, hipStreamNonBlocking));
     HIP_TRY(s, hipEventCreateWithFlags(&s->ev_in, hipEventDisableTiming));
     HIP_TRY(s, hipEventCreateWithFlags(&s->ev_out, hipEventDisableTiming));
@@ -628,7 +636,7 @@ void free_all(mts_system *s) {
     free_layout(s->lo);
     void *ptrs[] = {s->sys_of, s->red_part, s->red_done, s->f2a, s->f2b, s->f3, s->pf, s->pe, s->cnt_sys,
                     s->nn, s->stats, s->tile_obs, s->x_ref, s->flags, s->row, s->e_buf, s->list_n,
-                    s->xi, s->vi};
+                    s->xi, s->vi, s->vs, s->f2s[0], s->f2s[1]};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -753,6 +761,9 @@ F3Mode cycle_mode(const mts_system *s, bool full) {
 struct Fused {
     bool kick2 = false, kick3_end = false, kick3_start = false, drift = false;
     bool gather3 = false;  // gather F3 from the partial slots (into s->f3) first
+    // v and the previous F2 read in the pair grid's sorted order (s->vs), F2 and v
+    // written in it (and x not written); see PairListArgs
+    bool in_sorted = false, out_sorted = false;
     const double *f2prev = nullptr;
     Pos4 *xs_out = nullptr;
 };
@@ -789,8 +800,11 @@ mts_status enqueue_pair_list(mts_system *s, const Pos4 *xs_in, double *f2, const
         a.kick3_end = u.kick3_end;
         a.kick3_start = u.kick3_start;
         a.drift = u.drift;
-        a.x = s->xi;
-        a.v = s->vi;
+        a.in_sorted = u.in_sorted;
+        a.out_sorted = u.out_sorted;
+        a.x = u.out_sorted ? nullptr : s->xi;
+        a.v_in = u.in_sorted ? s->vs : s->vi;
+        a.v_out = u.out_sorted ? s->vs : s->vi;
         a.f2prev = u.f2prev;
         a.f3 = s->f3;
         a.c2 = dt / (2.0 * m);
@@ -1057,12 +1071,17 @@ mts_status enqueue_cycle(mts_system *s, double *f2_0, double *f2_1, bool energie
         Pos4 *buf[2] = {s->lo.gp.xs, s->lo.gp.xs2};  // x^i lives in buf[i & 1] for 0 < i < k
         MTS_TRY(enqueue_int(s, nullptr, f2[0], false, false, true, true, k > 1 ? buf[1] : nullptr));
         for (int i = 1; i < k; ++i) {
+            // steps 2 .. k-2 keep v and F2 in the pair grid's sorted order (the order
+            // holds until the rebinning at x^k): step 1 reads them in input order, step
+            // k - 1 writes them (and x) back in input order
             Fused u;
             u.kick2 = true;
             u.drift = true;
-            u.f2prev = f2[(i - 1) & 1];
+            u.in_sorted = i >= 2;
+            u.out_sorted = i <= k - 2;
+            u.f2prev = u.in_sorted ? s->f2s[(i - 1) & 1] : f2[(i - 1) & 1];
             u.xs_out = i + 1 < k ? buf[(i + 1) & 1] : nullptr;  // x^k: a rebinning follows
-            MTS_TRY(enqueue_pair_list(s, buf[i & 1], f2[i & 1], u, false));
+            MTS_TRY(enqueue_pair_list(s, buf[i & 1], u.out_sorted ? s->f2s[i & 1] : f2[i & 1], u, false));
         }
         MTS_TRY(enqueue_full_step_list(s, energies, mode));
         Fused u;

@@ -213,7 +213,7 @@ struct PairArgs {
     const int *start;       // cell starts [ncell_total + 1]
     const SysDesc *sd;
     const int *sys_of;      // per particle (same in input and sorted order)
-    double *f;              // out [n][3], input order
+    double *f;              // out [n][3], input order (sorted with out_sorted)
     double *pe;             // out [n][2] per-particle {U2/2-sums, W2/2-sums}, sorted order
     double eps, sigma2, rc2, ushift;
     int *flags;
@@ -270,7 +270,14 @@ struct PairListArgs {
     int *flags;
     // fused update (all optional)
     int kick2, kick3_end, kick3_start, drift;
-    double *x, *v;          // [n][3] input order
+    // The inner steps between the first and the last of a cycle keep v and F2 in the
+    // pair grid's sorted order (coalesced): in_sorted reads v_in and f2prev at the sorted
+    // index, out_sorted writes f and v_out there.  The drift takes x^i from xs (the same
+    // bits as the input-order copy) and writes x (input order) only when x is non-null.
+    int in_sorted, out_sorted;
+    double *x;              // [n][3] input order, or null
+    const double *v_in;     // [n][3]
+    double *v_out;          // [n][3] (may be v_in)
     const double *f2prev;   // F2 of the previous inner position (kick2)
     const double *f3;       // F3 (kick3)
     double c2, c3, dt, cx;

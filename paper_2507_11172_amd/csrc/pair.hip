@@ -242,11 +242,13 @@ __global__ void __launch_bounds__(256) k_pair_list(PairListArgs a) {
     for (int k = 0; k < U; ++k) qn[k] = row[min(r + k * G, a.nl_cap - 1)];
     const int cnt = act ? a.nn[pp] : 0;
     const Pos4 pi = a.xs[pp];
-    const int64_t q = 3 * (int64_t)a.perm[pp] + (r < 3 ? r : 0);
+    const int64_t q = 3 * (int64_t)a.perm[pp] + (r < 3 ? r : 0);  // input order
+    const int64_t qs = 3 * pp + (r < 3 ? r : 0);                    // sorted order
+    const int64_t qi = a.in_sorted ? qs : q, qo = a.out_sorted ? qs : q;
     const SysDesc &d = a.sd[a.sys_of[pp]];
     const double L[3] = {d.L[0], d.L[1], d.L[2]};
     const double iL[3] = {d.iL[0], d.iL[1], d.iL[2]};
-    const bool upd = act && r < 3 && a.v != nullptr;
+    const bool upd = act && r < 3 && a.v_in != nullptr;
     double vq = 0.0, f2p = 0.0, f3q = 0.0, xq = 0.0, xr = 0.0;
     if (act && r < 3 && a.pf) {
         // F3 of this particle from the 14 partial slots, in slot order
@@ -260,12 +262,12 @@ __global__ void __launch_bounds__(256) k_pair_list(PairListArgs a) {
         if (!isfinite(s3)) atomicOr(a.flags, kFlagNonFinite);
     }
     if (upd) {
-        vq = a.v[q];
-        if (a.kick2) f2p = a.f2prev[q];
+        vq = a.v_in[qi];
+        if (a.kick2) f2p = a.f2prev[qi];
         if (!a.pf && (a.kick3_end || a.kick3_start)) f3q = a.f3[q];
         if (a.drift) {
-            xq = a.x[q];
-            if (a.x_ref) xr = a.x_ref[3 * pp + r];  // sorted order
+            xq = r == 0 ? pi.x : (r == 1 ? pi.y : pi.z);  // x^i
+            if (a.x_ref) xr = a.x_ref[qs];
         }
     }
 
@@ -311,16 +313,16 @@ __global__ void __launch_bounds__(256) k_pair_list(PairListArgs a) {
     double dd2 = 0.0;
     if (act && r < 3) {
         const double F = r == 0 ? fx : (r == 1 ? fy : fz);
-        a.f[q] = F;
+        a.f[qo] = F;
         if (upd) {
             if (a.kick2) vq = vq + a.c2 * (f2p + F);
             if (a.kick3_end) vq = vq + a.c3 * f3q;
             if (a.kick3_start) vq = vq + a.c3 * f3q;
-            a.v[q] = vq;
+            a.v_out[qo] = vq;
             if (a.drift) {
                 const double Lr = L[r];
                 const double xn = wrap1(xq + a.dt * vq + a.cx * F, Lr);
-                a.x[q] = xn;
+                if (a.x) a.x[q] = xn;
                 if (a.xs_out) reinterpret_cast<double *>(a.xs_out + p)[r] = xn;
                 if (a.x_ref) {
                     double t = xn - xr;
