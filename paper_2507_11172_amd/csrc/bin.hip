@@ -60,28 +60,41 @@ __global__ void __launch_bounds__(256) k_bin_count(BinArgs a) {
 //    for its own scatter and, grid-stride, into start[] for every later kernel.
 // Integer sums: the result does not depend on the order.
 __global__ void __launch_bounds__(1024) k_scan_tiles(BinArgs a) {
-    __shared__ int part[1024];
+    constexpr int kWaves = 1024 / kWave;
+    __shared__ int wsum[kWaves];
     __shared__ bool last;
     const BinGrid &g = a.g[blockIdx.y];
     const int ncell = g.ncell;
     const int ntile = (ncell + kScanTile - 1) / kScanTile;
     const int tile = blockIdx.x;
     if (tile >= ntile) return;  // grids of fewer tiles (uniform per workgroup)
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, lane = t % kWave, wave = t / kWave;
     const int c0 = tile * kScanTile + 4 * t;
     int v[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) v[k] = c0 + k < ncell ? g.count[c0 + k] : 0;
     const int s = (v[0] + v[1]) + (v[2] + v[3]);
-    part[t] = s;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const int u = t >= off ? part[t - off] : 0;
-        __syncthreads();
-        part[t] += u;
-        __syncthreads();
+    // inclusive scan across the lanes of each wavefront, then of the wavefront totals
+    int incl = s;
+#pragma unroll
+    for (int m = 1; m < kWave; m <<= 1) {
+        const int y = __shfl_up(incl, m);
+        if (lane >= m) incl += y;
     }
-    int run = part[t] - s;  // exclusive prefix of this thread's four cells in the tile
+    if (lane == kWave - 1) wsum[wave] = incl;
+    __syncthreads();
+    if (wave == 0) {
+        const int w = lane < kWaves ? wsum[lane] : 0;
+        int wi = w;
+#pragma unroll
+        for (int m = 1; m < kWaves; m <<= 1) {
+            const int y = __shfl_up(wi, m);
+            if (lane >= m) wi += y;
+        }
+        if (lane < kWaves) wsum[lane] = wi - w;  // exclusive prefix of each wavefront
+    }
+    __syncthreads();
+    int run = wsum[wave] + incl - s;  // exclusive prefix of this thread's four cells in the tile
 #pragma unroll
     for (int k = 0; k < 4; ++k)
         if (c0 + k < ncell) {
@@ -89,7 +102,7 @@ __global__ void __launch_bounds__(1024) k_scan_tiles(BinArgs a) {
             run += v[k];
             g.count[c0 + k] = 0;
         }
-    if (t == 1023) g.tile_sum[tile] = part[1023];
+    if (t == 1023) g.tile_sum[tile] = wsum[kWaves - 1] + incl;
     __threadfence();
     __syncthreads();
     if (t == 0) last = atomicAdd(&g.tile_sum[2 * ntile], 1) == ntile - 1;
