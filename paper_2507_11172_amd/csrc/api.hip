@@ -148,7 +148,8 @@ struct mts_system {
     hipStream_t ist = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     bool use_graph = true;
-    hipGraphExec_t gexec[2][2][2] = {};  // [energies][F2 parity][ends a full step]
+    // [energies][F2 parity][ends a full step][continues a call: opening done by the last]
+    hipGraphExec_t gexec[2][2][2][2] = {};
     double *xi = nullptr, *vi = nullptr;  // internal copies of x and v, [n][3]
     // v and two F2 caches in the pair grid's sorted order, for the inner steps between
     // the first and the last of a cycle with a pair list
@@ -521,11 +522,12 @@ mts_status alloc_all(mts_system *s) {
 void drop_graphs(mts_system *s) {
     for (auto &g : s->gexec)
         for (auto &h : g)
-            for (hipGraphExec_t &e : h)
-                if (e) {
-                    (void)hipGraphExecDestroy(e);
-                    e = nullptr;
-                }
+            for (auto &i : h)
+                for (hipGraphExec_t &e : i)
+                    if (e) {
+                        (void)hipGraphExecDestroy(e);
+                        e = nullptr;
+                    }
 }
 
 // Replaces the handle's layout by one built for cfg (the old one stays on failure).
@@ -764,6 +766,9 @@ struct Fused {
     // v and the previous F2 read in the pair grid's sorted order (s->vs), F2 and v
     // written in it (and x not written); see PairListArgs
     bool in_sorted = false, out_sorted = false;
+    // also the next cycle's opening (F3 half kick, first drift) into s->vs, s->f2s[0] and
+    // the pair grid's second position buffer; see PairListArgs
+    bool open_next = false;
     const double *f2prev = nullptr;
     Pos4 *xs_out = nullptr;
 };
@@ -812,7 +817,13 @@ mts_status enqueue_pair_list(mts_system *s, const Pos4 *xs_in, double *f2, const
         a.dt = dt;
         a.cx = (dt * dt) / (2.0 * m);
         a.xs_out = u.xs_out;
-        a.x_ref = u.drift && u.xs_out ? s->x_ref : nullptr;
+        a.x_ref = (u.drift && u.xs_out) || u.open_next ? s->x_ref : nullptr;
+        if (u.open_next) {
+            a.open_next = 1;
+            a.v_next = s->vs;
+            a.f2_next = s->f2s[0];
+            a.xs_next = s->lo.gp.xs2;
+        }
         a.half_skin2 = 0.25 * s->lo.skin * s->lo.skin;
     }
     const long ts = timer_begin(s, 1);
@@ -1054,7 +1065,8 @@ mts_status enqueue_entry_forces(mts_system *s, double *f2, bool energy) {
 // Nested r-RESPA (k_outer > 1): this is one mid cycle; full says whether x^k ends a full
 // step (then the class-weighted pass over the whole cutoff set, whose slots hold
 // F_in + k_outer F_out; otherwise the inner class alone); energies only at full steps.
-mts_status enqueue_cycle(mts_system *s, double *f2_0, double *f2_1, bool energies, bool full) {
+mts_status enqueue_cycle(mts_system *s, double *f2_0, double *f2_1, bool energies, bool full,
+                         bool cont) {
     const int k = s->p.k;
     const F3Mode mode = cycle_mode(s, full);
     if (!full) energies = false;
@@ -1069,15 +1081,21 @@ mts_status enqueue_cycle(mts_system *s, double *f2_0, double *f2_1, bool energie
         MTS_TRY(enqueue_int(s, f2[(k - 1) & 1], f2[k & 1], true, true, false, false, nullptr));
     } else if (s->lo.skin > 0.0) {
         Pos4 *buf[2] = {s->lo.gp.xs, s->lo.gp.xs2};  // x^i lives in buf[i & 1] for 0 < i < k
-        MTS_TRY(enqueue_int(s, nullptr, f2[0], false, false, true, true, k > 1 ? buf[1] : nullptr));
+        // with k >= 2 the closing launch also opens the next cycle (its F3 half kick and
+        // first drift, into the sorted-order v, F2(x^0) and buf[1]), so a cycle that
+        // continues a call starts at step 1 without k_int
+        const bool fuse = k >= 2;
+        if (!(fuse && cont))
+            MTS_TRY(enqueue_int(s, nullptr, f2[0], false, false, true, true, k > 1 ? buf[1] : nullptr));
         for (int i = 1; i < k; ++i) {
             // steps 2 .. k-2 keep v and F2 in the pair grid's sorted order (the order
-            // holds until the rebinning at x^k): step 1 reads them in input order, step
-            // k - 1 writes them (and x) back in input order
+            // holds until the rebinning at x^k): step 1 reads them in input order (in
+            // sorted order after a fused opening), step k - 1 writes them (and x) back in
+            // input order
             Fused u;
             u.kick2 = true;
             u.drift = true;
-            u.in_sorted = i >= 2;
+            u.in_sorted = i >= 2 || (fuse && cont);
             u.out_sorted = i <= k - 2;
             u.f2prev = u.in_sorted ? s->f2s[(i - 1) & 1] : f2[(i - 1) & 1];
             u.xs_out = i + 1 < k ? buf[(i + 1) & 1] : nullptr;  // x^k: a rebinning follows
@@ -1091,6 +1109,7 @@ mts_status enqueue_cycle(mts_system *s, double *f2_0, double *f2_1, bool energie
             u.gather3 = true;
         u.kick2 = true;
         u.kick3_end = true;
+        u.open_next = fuse;
         u.f2prev = f2[(k - 1) & 1];
         MTS_TRY(enqueue_pair_list(s, s->lo.gp.xs, f2[k & 1], u, energies));
     } else {
@@ -1115,10 +1134,10 @@ mts_status enqueue_cycle(mts_system *s, double *f2_0, double *f2_1, bool energie
 }
 
 // Captures one cycle into an executable graph (kernels only: no memset or copy nodes).
-mts_status capture_cycle(mts_system *s, bool energies, int parity, bool full) {
+mts_status capture_cycle(mts_system *s, bool energies, int parity, bool full, bool cont) {
     double *fa = parity ? s->f2b : s->f2a, *fb = parity ? s->f2a : s->f2b;
     HIP_TRY(s, hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal));
-    mts_status r = enqueue_cycle(s, fa, fb, energies, full);
+    mts_status r = enqueue_cycle(s, fa, fb, energies, full, cont);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(s->st, &g);
     if (r != MTS_OK) {
@@ -1126,7 +1145,7 @@ mts_status capture_cycle(mts_system *s, bool energies, int parity, bool full) {
         return r;
     }
     if (e != hipSuccess) return hip_fail(s, e, "hipStreamEndCapture");
-    e = hipGraphInstantiate(&s->gexec[energies][parity][full], g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&s->gexec[energies][parity][full][cont], g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return hip_fail(s, e, "hipGraphInstantiate");
     return MTS_OK;
@@ -1162,11 +1181,12 @@ mts_status respa_internal(mts_system *s, double *x, double *v, int64_t n_iter, d
         const int parity = (k & 1) ? (int)(c & 1) : 0;
         const bool full = (c + 1) % s->k2 == 0;
         const bool e = energies && full;
+        const bool cont = c > 0;  // the previous cycle of this call opened this one
         if (graph) {
-            if (!s->gexec[e][parity][full]) MTS_TRY(capture_cycle(s, e, parity, full));
-            HIP_TRY(s, hipGraphLaunch(s->gexec[e][parity][full], s->st));
+            if (!s->gexec[e][parity][full][cont]) MTS_TRY(capture_cycle(s, e, parity, full, cont));
+            HIP_TRY(s, hipGraphLaunch(s->gexec[e][parity][full][cont], s->st));
         } else {
-            MTS_TRY(enqueue_cycle(s, parity ? s->f2b : s->f2a, parity ? s->f2a : s->f2b, e, full));
+            MTS_TRY(enqueue_cycle(s, parity ? s->f2b : s->f2a, parity ? s->f2a : s->f2b, e, full, cont));
         }
     }
     if (bytes > 0) {

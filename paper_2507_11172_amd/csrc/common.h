@@ -282,6 +282,13 @@ struct PairListArgs {
     const double *f3;       // F3 (kick3)
     double c2, c3, dt, cx;
     Pos4 *xs_out;           // [n] sorted positions after the drift
+    // The next cycle's opening fused into a cycle's closing launch (optional): its F3 half
+    // kick on the closed v and its first drift with this launch's F2, from x (input
+    // order), into v_next, f2_next (sorted order) and xs_next, with the skin check; the
+    // closed v, F2 and x stay as they are (the caller's output and the energy record)
+    int open_next;
+    double *v_next, *f2_next;
+    Pos4 *xs_next;
     const double *x_ref;    // positions at the last list build (sorted order)
     double half_skin2;
     // optional: F3 gathered here from the triplet kernel's partial slots (fixed slot

@@ -269,6 +269,10 @@ __global__ void __launch_bounds__(256) k_pair_list(PairListArgs a) {
             xq = r == 0 ? pi.x : (r == 1 ? pi.y : pi.z);  // x^i
             if (a.x_ref) xr = a.x_ref[qs];
         }
+        if (a.open_next) {
+            xq = a.x[q];  // x^k as the caller keeps it
+            xr = a.x_ref[qs];
+        }
     }
 
     double fx = 0.0, fy = 0.0, fz = 0.0, u = 0.0, w = 0.0;
@@ -331,6 +335,18 @@ __global__ void __launch_bounds__(256) k_pair_list(PairListArgs a) {
                     dd2 = t * t;
                 }
             }
+            if (a.open_next) {  // the next cycle's F3 half kick and first drift
+                const double vn = vq + a.c3 * f3q;
+                a.v_next[qs] = vn;
+                a.f2_next[qs] = F;
+                const double Lr = L[r];
+                const double xn = wrap1(xq + a.dt * vn + a.cx * F, Lr);
+                reinterpret_cast<double *>(a.xs_next + p)[r] = xn;
+                double t = xn - xr;
+                const double h = 0.5 * Lr;
+                t = t > h ? t - Lr : (t < -h ? t + Lr : t);
+                dd2 = t * t;
+            }
         }
     }
     // displacement since the list build: (dx^2 + dy^2) + dz^2 in lane r = 0
@@ -343,7 +359,7 @@ __global__ void __launch_bounds__(256) k_pair_list(PairListArgs a) {
         }
         if (!isfinite(fx) || !isfinite(fy) || !isfinite(fz) || (ENERGY && !isfinite(u)))
             atomicOr(a.flags, kFlagNonFinite);
-        if (upd && a.drift && a.x_ref && !((dd2 + d1) + d2 <= a.half_skin2))
+        if (upd && ((a.drift && a.x_ref) || a.open_next) && !((dd2 + d1) + d2 <= a.half_skin2))
             atomicOr(a.flags, kFlagSkin);
     }
 }
