@@ -1050,8 +1050,11 @@ mts_status enqueue_entry_forces(mts_system *s, double *f2, bool energy) {
 // One outer cycle of Algorithm 2 on the internal copies xi, vi.  On entry F2 of the
 // cycle's first position x^0 is in f2[0] and F3(x^0) in s->f3; on exit F2(x^k) is in
 // f2[k % 2] and F3(x^k) in s->f3, with the closing F3 half kick applied.
-// With a pair list (launches per cycle: k + 6, plus 1 with energies):
-//   step 0:          k_int: opening F3 kick, drift to x^1 (also into sorted buffer B)
+// With a pair list (launches per cycle: k + 6, plus 1 with energies; k + 5 for a cycle that
+// continues a call when k >= 2):
+//   step 0:          k_int: opening F3 kick, drift to x^1 (also into sorted buffer B) --
+//                    for a cycle that continues a call (k >= 2), done by the previous
+//                    cycle's closing launch instead
 //   x^i, 0 < i < k:  k_pair_list at x^i: F2(x^i), then kick2 of step i-1 and the drift
 //                    of step i, positions ping-ponging between sorted buffers A and B
 //   x^k:             rebin both grids (4 launches; a first binning pass fused into the
@@ -1059,6 +1062,7 @@ mts_status enqueue_entry_forces(mts_system *s, double *f2, bool energy) {
 //                    the force kernel's few waves); one launch for the triplet partial
 //                    slots of x^k and the new pair list; k_pair_list at x^k: F2(x^k),
 //                    F3(x^k) gathered from the slots, last kick2 and the closing F3 kick
+//                    (and, k >= 2, the next cycle's opening kick and first drift)
 // Without a list (skin 0) every step rebins the pair grid and runs the tile kernel.
 // DirectSum: k_int and the all-pairs kernel every step, the all-triplets kernel and its
 // gather at x^k.
